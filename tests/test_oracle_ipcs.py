@@ -1,0 +1,132 @@
+"""Pins of the oracle's IPCS step (eq. (9), Section 2.2.1).
+
+* exact fixed point: for the polynomial steady solutions every integrand of the
+  step is a polynomial of degree <= 5, so the interpolated exact state is
+  reproduced to rounding, in 2D and 3D, explicit and semi-implicit;
+* one step equals the same step done with dense direct solves;
+* the sign of the pressure-increment right-hand side: with the sign adopted,
+  the correction removes most of the discrete divergence of u*; the printed
+  sign increases it (the test plants the printed sign in the oracle);
+* convergence orders of the Taylor-Green problem: velocity -> 3, pressure -> 2
+  (the theoretical Taylor-Hood orders, also observed by the paper's table
+  "convergence_ipcs"), with a guard that the time error is negligible;
+* Taylor-Green kinetic-energy decay rate e^{-4 nu k^2 t}.
+"""
+import numpy as np
+import pytest
+
+from oracle import errors, fem, ipcs, krylov, mesh, problems
+
+
+@pytest.mark.parametrize("dim,semi", [(2, False), (2, True), (3, False), (3, True)])
+def test_polynomial_steady_state_is_a_fixed_point(dim, semi):
+    if dim == 2:
+        S, pb = fem.Space(*mesh.unit_square(5, 4)), problems.PolySteady2D(0.07)
+    else:
+        S, pb = fem.Space(*mesh.unit_cube(2, 2, 2)), problems.PolySteady3D(0.07)
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=pb.nu, dt=0.05, semi_implicit=semi,
+                                      tol_mom=1e-14, tol_p=1e-14, tol_corr=1e-14))
+    U0, P0 = st.U.copy(), st.P.copy()
+    np.testing.assert_allclose(P0, pb.p(S.X, 0.0), atol=1e-14)   # zero mean already
+    for _ in range(2):
+        st.step()
+    assert np.abs(st.U - U0).max() < 1e-12
+    assert np.abs(st.P - P0).max() < 1e-12
+
+
+def test_step_equals_dense_direct_solves():
+    S = fem.Space(*mesh.unit_square(4, 4))
+    pb = problems.TaylorGreen2D(np.pi, 0.05)
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=0.05, dt=0.02, tol_mom=1e-14, tol_p=1e-14,
+                                      tol_corr=1e-14))
+    U, P, t = st.U.copy(), st.P.copy(), st.t + 0.02
+    st.step()
+    # the same step, every solve dense
+    d, B = S.dim, S.boundary2
+    g = pb.u(S.x2, t).T
+    C = fem.convection(S, U)
+    A = (st.M / 0.02 + 0.05 * st.K).tocsr()
+    Us = np.zeros_like(U)
+    for c in range(d):
+        b = st.M @ U[c] / 0.02 - C @ U[c] - st.G[c] @ P
+        Us[c] = np.linalg.solve(fem.eliminate(A, B).toarray(), fem.lift(A, b, B, g[c]))
+    r = -(1 / 0.02) * sum(st.D[c] @ Us[c] for c in range(d))
+    Kp = st.Kp.toarray()
+    n1 = S.N1
+    Bd = np.zeros((n1 + 1, n1 + 1))
+    Bd[:n1, :n1], Bd[:n1, n1], Bd[n1, :n1] = Kp, st.w, st.w
+    dP = np.linalg.solve(Bd, np.r_[r - r.mean(), 0.0])[:n1]
+    Un = np.zeros_like(U)
+    for c in range(d):
+        b = st.M @ Us[c] - 0.02 * (st.G[c] @ dP)
+        Un[c] = np.linalg.solve(fem.eliminate(st.M, B).toarray(), fem.lift(st.M, b, B, g[c]))
+    assert np.linalg.norm(st.U - Un) <= 1e-11 * np.linalg.norm(Un)
+    assert np.linalg.norm(st.P - (P + dP)) <= 1e-11 * np.linalg.norm(P + dP)
+
+
+def _divergence_after_correction(sign):
+    S = fem.Space(*mesh.unit_square(16, 16))
+    pb = problems.TaylorGreen2D(np.pi, 0.01)
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=0.01, dt=0.01))
+    X = S.x2
+    Us = np.stack([np.sin(np.pi * X[:, 0]) ** 2 * np.sin(np.pi * X[:, 1]) ** 2,
+                   np.zeros(S.N2)])
+    g = np.zeros((2, S.N2))
+    dP, _ = st.pressure(Us)
+    dP = sign * dP                       # dP is linear in r: sign -1 plants the printed sign
+    Un, _ = st.correction(Us, dP, g)
+    div = lambda V: np.linalg.norm(sum(st.D[c] @ V[c] for c in range(2)))
+    return div(Us), div(Un)
+
+
+def test_pressure_sign_removes_divergence():
+    before, after = _divergence_after_correction(+1)
+    assert after <= 0.5 * before
+    before, after_printed = _divergence_after_correction(-1)
+    assert after_printed > before
+
+
+def _tg_errors(n, dt, T=0.005):
+    pb = problems.TaylorGreen2D(np.pi, 0.01)
+    S = fem.Space(*mesh.unit_square(n, n))
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=0.01, dt=dt))
+    st.run(int(round(T / dt)))
+    return (errors.l2_velocity(S, st.U, pb.u, st.t), errors.l2_pressure(S, st.P, pb.p, st.t))
+
+
+@pytest.mark.slow
+def test_taylor_green_convergence_orders():
+    e = {n: _tg_errors(n, 1e-3) for n in (8, 16, 32)}
+    # time-error guard: halving dt moves the finest errors by < 5 %
+    eh = _tg_errors(32, 5e-4)
+    assert abs(eh[0] / e[32][0] - 1) < 0.05 and abs(eh[1] / e[32][1] - 1) < 0.05
+    ou = np.log2(e[16][0] / e[32][0])
+    op = np.log2(e[16][1] / e[32][1])
+    assert abs(ou - 3.0) <= 0.15, ou
+    assert abs(op - 2.0) <= 0.2, op
+    assert np.log2(e[8][0] / e[16][0]) > 2.4 and np.log2(e[8][1] / e[16][1]) > 1.8
+
+
+def test_taylor_green_energy_decay():
+    k, nu = np.pi, 0.01
+    pb = problems.TaylorGreen2D(k, nu)
+    S = fem.Space(*mesh.unit_square(16, 16))
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=nu, dt=0.01))
+    E = lambda: sum(st.U[c] @ (st.M @ st.U[c]) for c in range(2))
+    E0 = E()
+    st.run(10)
+    ratio = E() / E0
+    exact = np.exp(-4 * nu * k * k * 0.1)
+    assert abs(ratio / exact - 1) < 2e-3
+
+
+def test_golden_ipcs_table_orders_are_the_theoretical_ones():
+    """The paper's own IPCS table: its last orders approach 3 and 2."""
+    import os
+    rows = [list(map(float, l.split())) for l in
+            open(os.path.join(os.path.dirname(__file__), "golden", "convergence_ipcs.txt"))
+            if l.strip() and not l.startswith("#")]
+    eu = [r[1] for r in rows]
+    ep = [r[2] for r in rows]
+    assert abs(np.log2(eu[-2] / eu[-1]) - 3) < 0.05
+    assert abs(np.log2(ep[-2] / ep[-1]) - 2) < 0.1
