@@ -1,0 +1,232 @@
+/*
+ * ipcs.h -- C ABI of the MI355X (gfx950) incremental pressure-correction
+ * (IPCS) solver for the incompressible Navier-Stokes equations with
+ * Taylor-Hood P2-P1 elements on triangles and tetrahedra.
+ *
+ * What is computed (arXiv 2605.25403, FEALPy.CFD):
+ *   PDE      : Section 2.1, eq. (3): du/dt - nu Lap u + (u.grad)u + grad p = f,
+ *              div u = 0, density rho = 1 unless set.
+ *   Spaces   : Section 2.2.1, eqs. (4)-(5): V_h = continuous P2 per velocity
+ *              component with Dirichlet data, Q_h = continuous P1 pressure.
+ *   Scheme   : Section 2.2.1, eq. (9) (IPCS): momentum with explicit convection
+ *              ((u^n.grad)u^n, v) and pressure p^n, pressure-increment Poisson,
+ *              velocity correction. The Poisson right-hand side is taken as
+ *              -(rho/dt)(div u*, q), the sign for which the correction makes
+ *              u^{n+1} discretely divergence-free; the pressure is fixed by zero
+ *              integral mean.
+ *   Workflow : Section 4.2 (create mesh, choose spaces, choose method, run,
+ *              read back) and the step decomposition of Section 3.2.3 (matrix,
+ *              right-hand side and coefficient-update interfaces per step).
+ *
+ * Conventions
+ *   - Every call returns IPCS_OK (0) or a negative status; nothing throws.
+ *     ipcs_last_error() returns a thread-local message for the last failure on
+ *     the calling thread (valid until the next call on that thread).
+ *   - Handles are opaque and owned by the library; destroy calls accept NULL.
+ *   - Host arrays passed in are copied; output buffers are caller-allocated and
+ *     come with a capacity in elements; a buffer that is too small gives
+ *     IPCS_E_INVALID and writes nothing.
+ *   - Device memory: a run lives entirely inside one caller-provided device
+ *     workspace (dev_ws, ws_bytes >= ipcs_run_workspace_bytes); the library
+ *     never frees it and allocates no other device memory except small pinned
+ *     host staging buffers. All device work of a run is issued on the HIP
+ *     stream given at creation (or to ipcs_batch_step).
+ *   - Layout: velocity is component-major [dim][N2]. P2 DOFs are the mesh
+ *     vertices (input order) followed by the edges sorted by (min vertex, max
+ *     vertex); P1 DOFs are the vertices. All host-side fields are FP64,
+ *     whatever the internal precision.
+ *   - Threading: a run is not thread-safe; distinct runs may be driven from
+ *     distinct threads.
+ */
+#ifndef IPCS_H
+#define IPCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+  IPCS_OK = 0,
+  IPCS_E_INVALID = -1,        /* bad argument, handle or buffer size          */
+  IPCS_E_NOMEM = -2,          /* workspace too small / host allocation failed */
+  IPCS_E_DEVICE = -3,         /* HIP runtime error                            */
+  IPCS_E_NOT_CONVERGED = -4,  /* a Krylov solve hit maxit                     */
+  IPCS_E_BREAKDOWN = -5,      /* unrecoverable Krylov breakdown               */
+  IPCS_E_NONFINITE = -6,      /* NaN/Inf met in a solve                       */
+  IPCS_E_STATE = -7,          /* call not valid in the run's current state    */
+  IPCS_E_CAPACITY = -8        /* admission refused (workspace budget)         */
+};
+
+const char* ipcs_last_error(void);
+
+/* ---------------------------------------------------------------- mesh */
+typedef struct ipcs_mesh_s* ipcs_mesh;
+
+enum { IPCS_SPACE_P1 = 1, IPCS_SPACE_P2 = 2 };
+enum {                         /* sparsity patterns of the step's matrices      */
+  IPCS_PATTERN_P2P2 = 0,       /* M, K, C, A (velocity x velocity)             */
+  IPCS_PATTERN_P1P1 = 1,       /* Kp (pressure x pressure)                     */
+  IPCS_PATTERN_P1P2 = 2,       /* D_c, divergence (pressure rows, velocity cols) */
+  IPCS_PATTERN_P2P1 = 3        /* G_c, gradient (velocity rows, pressure cols) */
+};
+
+typedef struct {
+  int32_t dim;                 /* 2 or 3                                       */
+  int64_t nv, nc;              /* vertices, cells                              */
+  int64_t n1, n2;              /* P1 and P2 DOFs per component                 */
+  int64_t nnz[4];              /* nnz of IPCS_PATTERN_* patterns               */
+  int64_t nb2;                 /* boundary P2 nodes                            */
+} ipcs_counts;
+
+/* Unit square, nx x ny squares, each split by its SW-NE diagonal into two
+ * counter-clockwise triangles; vertex (i,j) = (i/nx, j/ny) has index
+ * j*(nx+1)+i (Section 2.2.1: conforming simplicial mesh T_h). */
+int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out);
+/* Unit cube, nx*ny*nz cubes, each split into the 6 Kuhn tetrahedra around its
+ * main diagonal; vertex (i,j,k) has index (k(ny+1)+j)(nx+1)+i. */
+int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out);
+/* Any conforming simplicial mesh: x[nv*dim] coordinates, cells[nc*(dim+1)]
+ * vertex indices (0-based). Cells of negative orientation are accepted. */
+int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
+                          const int32_t* cells, ipcs_mesh* out);
+int ipcs_mesh_counts(ipcs_mesh m, ipcs_counts* out);
+/* Coordinates of the DOFs of a space, [n*dim]. cap in doubles. */
+int ipcs_mesh_dof_coords(ipcs_mesh m, int32_t space, double* out, int64_t cap);
+/* Cell -> DOF table of a space, [nc * nloc] (P2 local order: vertices, then
+ * edges v1v2, v2v0, v0v1 (2D) or 01,02,03,12,13,23 (3D)). cap in int32s. */
+int ipcs_mesh_cell_dofs(ipcs_mesh m, int32_t space, int32_t* out, int64_t cap);
+/* Boundary flags of the P2 nodes (1 = on the boundary), [n2]. */
+int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap);
+/* CSR pattern (row pointer [rows+1], sorted column indices [nnz]). */
+int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
+                      int32_t* col, int64_t cap_nnz);
+/* The degree-5 cell quadrature rule the kernels use, in barycentric
+ * coordinates lam[nq*(dim+1)] with weights w[nq] summing to 1/dim!.
+ * *nq receives the number of points; pass NULL buffers to query it. */
+int ipcs_quadrature_rule(int32_t dim, int32_t* nq, double* lam, double* w, int64_t cap);
+void ipcs_mesh_destroy(ipcs_mesh m);
+
+/* ---------------------------------------------------------------- runs */
+typedef struct ipcs_run_s* ipcs_run;
+
+enum { IPCS_FP64 = 0, IPCS_MIXED = 1 };
+enum { IPCS_CONV_EXPLICIT = 0, IPCS_CONV_SEMI_IMPLICIT = 1 };
+
+typedef struct {
+  double nu;            /* kinematic viscosity                                 */
+  double rho;           /* density in the pressure steps (default 1)          */
+  double dt;            /* time step                                           */
+  double t0;            /* initial time                                        */
+  int32_t precision;    /* IPCS_FP64 or IPCS_MIXED                             */
+  int32_t convection;   /* IPCS_CONV_EXPLICIT (eq. (9)) or SEMI_IMPLICIT       */
+  double tol_mom;       /* relative residual tolerance, momentum BiCGStab      */
+  double tol_p;         /* pressure Poisson PCG (FP64 form)                    */
+  double tol_corr;      /* velocity-correction PCG                             */
+  double tol_ir;        /* mixed form: FP64 iterative-refinement tolerance     */
+  int32_t maxit;        /* iteration cap per solve                             */
+  int32_t check_every;  /* host convergence poll interval (iterations)         */
+  int32_t callbacks;    /* 1: reserve staging for host-callback forcing        */
+  int32_t reserved;
+} ipcs_params;
+
+/* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12
+ * (tol_ir 1e-10), maxit 20000, check_every 16, callbacks 0. */
+void ipcs_params_default(ipcs_params* p);
+
+/* Device workspace a run of this mesh needs (its whole HBM footprint). */
+int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes);
+/* Uploads the mesh data, assembles the constant matrices (M, K, Kp, D_c, G_c,
+ * A = M/dt + nu K with Dirichlet rows/columns eliminated) on the device.
+ * The initial state is zero until ipcs_set_state / ipcs_set_builtin_solution.
+ * hip_stream is a hipStream_t (NULL = default stream). The mesh may be
+ * destroyed afterwards. */
+int ipcs_run_create(ipcs_mesh m, const ipcs_params* p, void* dev_ws, int64_t ws_bytes,
+                    void* hip_stream, ipcs_run* out);
+int ipcs_set_viscosity(ipcs_run r, double nu);    /* re-forms A before next step */
+int ipcs_set_time_step(ipcs_run r, double dt);    /* re-forms A before next step */
+
+/* Host callback evaluating a vector field at npts points x[npts*dim] at time
+ * t into out[npts*dim]. */
+typedef void (*ipcs_field_fn)(void* ctx, int32_t dim, int64_t npts, const double* x,
+                              double t, double* out);
+/* Body force f (eq. (3)); NULL means f = 0. Evaluated on the host at the
+ * quadrature points every step (slow path, for tests); needs a run created
+ * with params.callbacks = 1 (else IPCS_E_STATE). */
+int ipcs_set_forcing(ipcs_run r, ipcs_field_fn f, void* ctx);
+/* Dirichlet data g (the velocity on the boundary, H^1_0 lifting of V_h);
+ * evaluated on the host at the boundary P2 nodes every step. */
+int ipcs_set_dirichlet(ipcs_run r, ipcs_field_fn g, void* ctx);
+
+enum {
+  IPCS_SOL_TAYLOR_GREEN_2D = 1, /* prm = {k}; f = 0                               */
+  IPCS_SOL_JOHN_2D = 2,         /* Section 5.1 benchmark; prm unused             */
+  IPCS_SOL_BELTRAMI_3D = 3,     /* Ethier-Steinman, prm = {a, d}; f = 0           */
+  IPCS_SOL_POLY_STEADY_2D = 4,  /* u=(y^2,x^2), p=x+y-1                           */
+  IPCS_SOL_POLY_STEADY_3D = 5   /* u=(y^2+z^2,z^2+x^2,x^2+y^2), p=x+y+z-3/2      */
+};
+/* Closed-form manufactured solution evaluated on the device: Dirichlet data,
+ * forcing and the initial state U = I_h u(t), P = I_h p(t) shifted to zero
+ * integral mean, at the run's current time. */
+int ipcs_set_builtin_solution(ipcs_run r, int32_t kind, const double* prm, int32_t nprm);
+/* Initial state / resume: u[dim*N2], p[N1] used as given, time t. */
+int ipcs_set_state(ipcs_run r, const double* u, const double* p, double t);
+
+typedef struct {
+  int32_t status;           /* IPCS_OK or the failing status                    */
+  int32_t it_mom[3];        /* BiCGStab iterations per component                */
+  int32_t it_p;             /* Poisson PCG iterations (inner total, mixed form) */
+  int32_t it_corr[3];       /* correction PCG iterations per component          */
+  int32_t ir_outer;         /* mixed form: refinement sweeps of the Poisson     */
+  int32_t failed_solve;     /* 0 none, 1 momentum, 2 pressure, 3 correction     */
+  double res_mom[3], res_p, res_corr[3];   /* final relative residuals         */
+  double t;                 /* time reached                                     */
+  float ms_asm, ms_mom, ms_p, ms_corr;     /* phase times (stream events)      */
+} ipcs_step_stats;
+
+/* Advance nsteps IPCS steps. stats may be NULL or hold nsteps entries. On a
+ * failure the state stays at the last completed step and the status of the
+ * failing solve is returned. */
+int ipcs_advance(ipcs_run r, int32_t nsteps, ipcs_step_stats* stats);
+
+enum { IPCS_PHASE_ASM = 0, IPCS_PHASE_MOMENTUM = 1, IPCS_PHASE_PRESSURE = 2,
+       IPCS_PHASE_CORRECTION = 3 };
+/* One sub-step of eq. (9) at a time (ASM: Dirichlet data, forcing, C(U^n) and
+ * the momentum right-hand side; MOMENTUM: u*; PRESSURE: dP and its right-hand
+ * side; CORRECTION: u^{n+1}, P^{n+1}, time advance). Phases must be called in
+ * order; ipcs_advance is equivalent to the four in sequence. */
+int ipcs_step_phase(ipcs_run r, int32_t phase, ipcs_step_stats* stats);
+
+int ipcs_get_velocity(ipcs_run r, double* u, int64_t cap);   /* [dim*N2] */
+int ipcs_get_pressure(ipcs_run r, double* p, int64_t cap);   /* [N1]     */
+int ipcs_get_time(ipcs_run r, double* t);
+
+enum { IPCS_FIELD_U = 0, IPCS_FIELD_P = 1, IPCS_FIELD_USTAR = 2, IPCS_FIELD_DP = 3,
+       IPCS_FIELD_RHS_MOM = 4, IPCS_FIELD_RHS_P = 5 };
+/* Intermediate vectors of the current step (after the phase that makes them). */
+int ipcs_get_field(ipcs_run r, int32_t which, double* out, int64_t cap);
+
+enum { IPCS_MAT_M = 0, IPCS_MAT_K = 1, IPCS_MAT_KP = 2, IPCS_MAT_A = 3,
+       IPCS_MAT_E = 4,          /* M/dt - C(U^n), the explicit momentum operator */
+       IPCS_MAT_D0 = 8,         /* D_c = IPCS_MAT_D0 + c                          */
+       IPCS_MAT_G0 = 12,        /* G_c = IPCS_MAT_G0 + c                          */
+       IPCS_MAT_A_ELIM = 16, IPCS_MAT_M_ELIM = 17 };
+/* Copy a device matrix to the host as CSR (values in FP64). rowptr/col may be
+ * NULL to fetch values only. */
+int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_rows,
+                       int32_t* col, double* val, int64_t cap_nnz);
+
+/* One IPCS step for every run in runs[0..nruns) with shared kernel launches
+ * on one stream (serving form): the runs' Krylov iterations advance together
+ * with per-run scalars and convergence. Each run's result is the same as when
+ * it is stepped alone. stats may be NULL or hold nruns entries. */
+int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats);
+
+void ipcs_run_destroy(ipcs_run r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPCS_H */

@@ -1,0 +1,395 @@
+// extern "C" entry points declared in include/ipcs.h. Every call converts
+// exceptions into status codes and records a thread-local message.
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+#include "ipcs.h"
+#include "mesh.hpp"
+#include "rules.hpp"
+#include "run.hpp"
+
+struct ipcs_mesh_s {
+  std::shared_ptr<ipcs::Mesh> m;
+};
+struct ipcs_run_s {
+  ipcs::Run r;
+};
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+int guard(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const ipcs::Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return IPCS_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return IPCS_E_INVALID;
+  } catch (...) {
+    g_err = "unknown error";
+    return IPCS_E_INVALID;
+  }
+}
+
+void need(bool c, const char* msg) {
+  if (!c) ipcs::fail(IPCS_E_INVALID, msg);
+}
+
+const ipcs::Mesh& M(ipcs_mesh m) {
+  need(m && m->m, "null mesh handle");
+  return *m->m;
+}
+
+ipcs::Run& R(ipcs_run r) {
+  need(r != nullptr, "null run handle");
+  return r->r;
+}
+
+int wrap_mesh(ipcs::Mesh* raw, ipcs_mesh* out) {
+  std::unique_ptr<ipcs::Mesh> own(raw);
+  auto* h = new ipcs_mesh_s;
+  h->m.reset(own.release());
+  *out = h;
+  return IPCS_OK;
+}
+
+void check_params(const ipcs_params* p) {
+  need(p != nullptr, "null params");
+  need(p->nu >= 0 && p->dt > 0 && p->rho > 0, "need nu >= 0, dt > 0, rho > 0");
+  need(p->tol_mom > 0 && p->tol_p > 0 && p->tol_corr > 0, "tolerances must be positive");
+  need(p->maxit > 0, "maxit must be positive");
+  need(p->precision == IPCS_FP64 || p->precision == IPCS_MIXED, "unknown precision");
+  need(p->convection == IPCS_CONV_EXPLICIT, "only explicit convection is available");
+  need(p->precision == IPCS_FP64, "the mixed-precision form is not available in this build");
+}
+}  // namespace
+
+extern "C" {
+
+const char* ipcs_last_error(void) { return g_err.c_str(); }
+
+int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_unit_square(nx, ny), out);
+  });
+}
+
+int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_unit_cube(nx, ny, nz), out);
+  });
+}
+
+int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
+                          const int32_t* cells, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_from_arrays(dim, nv, x, nc, cells), out);
+  });
+}
+
+int ipcs_mesh_counts(ipcs_mesh m, ipcs_counts* out) {
+  return guard([&]() -> int {
+    const ipcs::Mesh& mm = M(m);
+    need(out != nullptr, "null output");
+    std::memset(out, 0, sizeof(*out));
+    out->dim = mm.dim;
+    out->nv = mm.nv;
+    out->nc = mm.nc;
+    out->n1 = mm.n1;
+    out->n2 = mm.n2;
+    for (int k = 0; k < 4; ++k) out->nnz[k] = mm.pattern(k).nnz();
+    out->nb2 = (int64_t)mm.bidx.size();
+    return IPCS_OK;
+  });
+}
+
+int ipcs_mesh_dof_coords(ipcs_mesh m, int32_t space, double* out, int64_t cap) {
+  return guard([&]() -> int {
+    const ipcs::Mesh& mm = M(m);
+    need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
+    const int64_t n = (space == IPCS_SPACE_P1 ? mm.n1 : mm.n2) * mm.dim;
+    need(out != nullptr && cap >= n, "output buffer too small");
+    std::memcpy(out, mm.x2.data(), sizeof(double) * n);   // P1 nodes are the first n1
+    return IPCS_OK;
+  });
+}
+
+int ipcs_mesh_cell_dofs(ipcs_mesh m, int32_t space, int32_t* out, int64_t cap) {
+  return guard([&]() -> int {
+    const ipcs::Mesh& mm = M(m);
+    need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
+    const int nl = space == IPCS_SPACE_P1 ? mm.nloc1 : mm.nloc2;
+    need(out != nullptr && cap >= mm.nc * nl, "output buffer too small");
+    for (int64_t c = 0; c < mm.nc; ++c)
+      for (int j = 0; j < nl; ++j) out[c * nl + j] = mm.c2d[c * mm.nloc2 + j];
+    return IPCS_OK;
+  });
+}
+
+int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap) {
+  return guard([&]() -> int {
+    const ipcs::Mesh& mm = M(m);
+    need(out != nullptr && cap >= mm.n2, "output buffer too small");
+    std::memcpy(out, mm.bmask.data(), mm.n2);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
+                      int32_t* col, int64_t cap_nnz) {
+  return guard([&]() -> int {
+    const ipcs::Pattern& P = M(m).pattern(which);
+    need(rowptr != nullptr && cap_rows >= P.nrows + 1, "rowptr buffer too small");
+    need(col != nullptr && cap_nnz >= P.nnz(), "col buffer too small");
+    std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
+    std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
+    return IPCS_OK;
+  });
+}
+
+int ipcs_quadrature_rule(int32_t dim, int32_t* nq, double* lam, double* w, int64_t cap) {
+  return guard([&]() -> int {
+    need(dim == 2 || dim == 3, "dim must be 2 or 3");
+    const int n = dim == 2 ? ipcs::Rule<2>::NQ : ipcs::Rule<3>::NQ;
+    if (nq) *nq = n;
+    if (!lam && !w) return IPCS_OK;
+    need(lam && w && cap >= (int64_t)n * (dim + 1), "output buffer too small");
+    for (int q = 0; q < n; ++q) {
+      w[q] = dim == 2 ? ipcs::Rule<2>::w(q) : ipcs::Rule<3>::w(q);
+      for (int k = 0; k <= dim; ++k)
+        lam[q * (dim + 1) + k] = dim == 2 ? ipcs::Rule<2>::lam(q, k) : ipcs::Rule<3>::lam(q, k);
+    }
+    return IPCS_OK;
+  });
+}
+
+void ipcs_mesh_destroy(ipcs_mesh m) { delete m; }
+
+void ipcs_params_default(ipcs_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nu = 0.01;
+  p->rho = 1.0;
+  p->dt = 1e-3;
+  p->t0 = 0.0;
+  p->precision = IPCS_FP64;
+  p->convection = IPCS_CONV_EXPLICIT;
+  p->tol_mom = p->tol_p = p->tol_corr = 1e-12;
+  p->tol_ir = 1e-10;
+  p->maxit = 20000;
+  p->check_every = 16;
+  p->callbacks = 0;
+}
+
+int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes) {
+  return guard([&]() -> int {
+    check_params(p);
+    need(bytes != nullptr, "null output");
+    ipcs::Run tmp;
+    tmp.mesh = m ? m->m : nullptr;
+    const ipcs::Mesh& mm = M(m);
+    tmp.prm = *p;
+    tmp.dim = mm.dim;
+    tmp.n1 = mm.n1;
+    tmp.n2 = mm.n2;
+    tmp.nc = mm.nc;
+    tmp.nv = mm.nv;
+    tmp.nb = (int64_t)mm.bidx.size();
+    tmp.nlift = (int64_t)mm.lift_slot.size();
+    tmp.G22 = ipcs::lanes_for(double(mm.p22.nnz()) / mm.n2);
+    tmp.G11 = ipcs::lanes_for(double(mm.p11.nnz()) / mm.n1);
+    ipcs::Carver c;
+    tmp.layout(c);
+    *bytes = c.off;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_run_create(ipcs_mesh m, const ipcs_params* p, void* dev_ws, int64_t ws_bytes,
+                    void* hip_stream, ipcs_run* out) {
+  return guard([&]() -> int {
+    check_params(p);
+    need(out != nullptr, "null output handle");
+    (void)M(m);
+    std::unique_ptr<ipcs_run_s> h(new ipcs_run_s);
+    h->r.create(m->m, *p, dev_ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+    *out = h.release();
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_viscosity(ipcs_run r, double nu) {
+  return guard([&]() -> int {
+    need(nu >= 0, "nu must be >= 0");
+    R(r).prm.nu = nu;
+    R(r).A_dirty = true;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_time_step(ipcs_run r, double dt) {
+  return guard([&]() -> int {
+    need(dt > 0, "dt must be > 0");
+    R(r).prm.dt = dt;
+    R(r).A_dirty = true;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_forcing(ipcs_run r, ipcs_field_fn f, void* ctx) {
+  return guard([&]() -> int {
+    ipcs::Run& rr = R(r);
+    if (f && !rr.prm.callbacks)
+      ipcs::fail(IPCS_E_STATE, "forcing callbacks need a run created with params.callbacks = 1");
+    rr.f_cb = f;
+    rr.f_ctx = ctx;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_dirichlet(ipcs_run r, ipcs_field_fn g, void* ctx) {
+  return guard([&]() -> int {
+    R(r).g_cb = g;
+    R(r).g_ctx = ctx;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_builtin_solution(ipcs_run r, int32_t kind, const double* prm, int32_t nprm) {
+  return guard([&]() -> int {
+    need(nprm >= 0 && (nprm == 0 || prm != nullptr), "bad parameter array");
+    R(r).set_builtin(kind, prm, nprm);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_set_state(ipcs_run r, const double* u, const double* p, double t) {
+  return guard([&]() -> int {
+    need(u != nullptr && p != nullptr, "null state arrays");
+    R(r).set_state(u, p, t);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_advance(ipcs_run r, int32_t nsteps, ipcs_step_stats* stats) {
+  return guard([&]() -> int {
+    need(nsteps >= 0, "nsteps must be >= 0");
+    ipcs::Run& rr = R(r);
+    for (int32_t k = 0; k < nsteps; ++k) {
+      const int rc = rr.step(stats ? stats + k : nullptr);
+      if (rc != IPCS_OK) {
+        g_err = "step " + std::to_string(k) + " failed in solve " +
+                std::to_string(stats ? stats[k].failed_solve : 0);
+        return rc;
+      }
+    }
+    return IPCS_OK;
+  });
+}
+
+int ipcs_step_phase(ipcs_run r, int32_t phase, ipcs_step_stats* stats) {
+  return guard([&]() -> int { return R(r).phase(phase, stats); });
+}
+
+static int copy_out(ipcs::Run& rr, const double* src, int64_t n, double* out, int64_t cap) {
+  need(out != nullptr && cap >= n, "output buffer too small");
+  HIP_OK(hipMemcpyAsync(out, src, sizeof(double) * n, hipMemcpyDeviceToHost, rr.stream));
+  HIP_OK(hipStreamSynchronize(rr.stream));
+  return IPCS_OK;
+}
+
+int ipcs_get_velocity(ipcs_run r, double* u, int64_t cap) {
+  return guard([&]() -> int { ipcs::Run& rr = R(r); return copy_out(rr, rr.U, rr.dim * rr.n2, u, cap); });
+}
+
+int ipcs_get_pressure(ipcs_run r, double* p, int64_t cap) {
+  return guard([&]() -> int { ipcs::Run& rr = R(r); return copy_out(rr, rr.P, rr.n1, p, cap); });
+}
+
+int ipcs_get_time(ipcs_run r, double* t) {
+  return guard([&]() -> int {
+    need(t != nullptr, "null output");
+    *t = R(r).t;
+    return IPCS_OK;
+  });
+}
+
+int ipcs_get_field(ipcs_run r, int32_t which, double* out, int64_t cap) {
+  return guard([&]() -> int {
+    ipcs::Run& rr = R(r);
+    switch (which) {
+      case IPCS_FIELD_U: return copy_out(rr, rr.U, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_P: return copy_out(rr, rr.P, rr.n1, out, cap);
+      case IPCS_FIELD_USTAR: return copy_out(rr, rr.Ustar, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_DP: return copy_out(rr, rr.dP, rr.n1, out, cap);
+      case IPCS_FIELD_RHS_MOM: return copy_out(rr, rr.bU, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_RHS_P: return copy_out(rr, rr.rP, rr.n1, out, cap);
+    }
+    ipcs::fail(IPCS_E_INVALID, "unknown field id");
+  });
+}
+
+int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_rows,
+                       int32_t* col, double* val, int64_t cap_nnz) {
+  return guard([&]() -> int {
+    ipcs::Run& rr = R(r);
+    const ipcs::Mesh& mm = *rr.mesh;
+    const double* src = nullptr;
+    int pat = IPCS_PATTERN_P2P2;
+    if (which == IPCS_MAT_M) src = rr.M;
+    else if (which == IPCS_MAT_K) src = rr.K;
+    else if (which == IPCS_MAT_E) src = rr.E;
+    else if (which == IPCS_MAT_A_ELIM) src = rr.Ael;
+    else if (which == IPCS_MAT_M_ELIM) src = rr.Mel;
+    else if (which == IPCS_MAT_KP) {
+      src = rr.Kp;
+      pat = IPCS_PATTERN_P1P1;
+    } else if (which >= IPCS_MAT_D0 && which < IPCS_MAT_D0 + rr.dim) {
+      src = rr.Dc[which - IPCS_MAT_D0];
+      pat = IPCS_PATTERN_P1P2;
+    } else if (which >= IPCS_MAT_G0 && which < IPCS_MAT_G0 + rr.dim) {
+      src = rr.Gc[which - IPCS_MAT_G0];
+      pat = IPCS_PATTERN_P2P1;
+    } else if (which == IPCS_MAT_A) {
+      ipcs::fail(IPCS_E_INVALID, "A is stored Dirichlet-eliminated: use IPCS_MAT_A_ELIM");
+    } else {
+      ipcs::fail(IPCS_E_INVALID, "unknown matrix id");
+    }
+    const ipcs::Pattern& P = mm.pattern(pat);
+    if (rowptr) {
+      need(cap_rows >= P.nrows + 1, "rowptr buffer too small");
+      std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
+    }
+    need(cap_nnz >= P.nnz(), "value buffer too small");
+    if (col) std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
+    if (rr.A_dirty) rr.reform_A();
+    return copy_out(rr, src, P.nnz(), val, cap_nnz);
+  });
+}
+
+int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats) {
+  return guard([&]() -> int {
+    (void)runs;
+    (void)nruns;
+    (void)hip_stream;
+    (void)stats;
+    ipcs::fail(IPCS_E_STATE, "batched stepping is not available in this build");
+  });
+}
+
+void ipcs_run_destroy(ipcs_run r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,479 @@
+// Cell-quadrature assembly kernels for gfx950 (row-owner, conflict-free).
+//
+// Each thread owns one CSR row (a P2 or P1 DOF). It walks the cells incident to
+// its DOF, evaluates that cell's local matrix row by the degree-5 rule
+// (reference basis values are compile-time constants folded into the code) and
+// adds it into the row's slots, which live in LDS in the same packed layout as
+// the CSR value array. After a barrier the block writes its rows back with
+// coalesced stores. No value is written by two threads, so there are no
+// atomics and the result is deterministic.
+//
+// Local matrices (Section 2.2.1, weak forms of eq. (9)), on a cell K with affine
+// map x = x0 + J xi, gradients grad phi = J^{-T} grad_ref phi:
+//   M_ij = sum_q w_q |J| phi_i phi_j              K_ij = sum_q w_q |J| grad phi_i . grad phi_j
+//   C_ij = sum_q w_q |J| phi_i (u_h . grad phi_j) with u_h = sum_m U_m phi_m
+//   (G_c)_ik = sum_q w_q |J| phi_i d_c psi_k      (D_c)_kj = sum_q w_q |J| psi_k d_c phi_j
+//   Kp_kl = |K| grad psi_k . grad psi_l           w_k = int_K psi_k = |K|/(d+1)
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "dev_util.hpp"
+#include "device.hpp"
+#include "builtin.hpp"
+#include "rules.hpp"
+
+namespace ipcs {
+
+template <int D>
+struct Geo {
+  double Ji[D][D];   // J^{-1}
+  double det;        // |det J|
+};
+
+template <int D>
+__device__ __forceinline__ Geo<D> cell_geo(const double* X, const int32_t* dofs) {
+  double x0[D], J[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r) x0[r] = X[(size_t)dofs[0] * D + r];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int r = 0; r < D; ++r) J[r][k] = X[(size_t)dofs[k + 1] * D + r] - x0[r];
+  Geo<D> g;
+  if constexpr (D == 2) {
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double id = 1.0 / det;
+    g.Ji[0][0] = J[1][1] * id;
+    g.Ji[0][1] = -J[0][1] * id;
+    g.Ji[1][0] = -J[1][0] * id;
+    g.Ji[1][1] = J[0][0] * id;
+    g.det = fabs(det);
+  } else {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    g.Ji[0][0] = c00 * id;
+    g.Ji[1][0] = c01 * id;
+    g.Ji[2][0] = c02 * id;
+    g.Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    g.Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    g.Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    g.Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    g.Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    g.Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    g.det = fabs(det);
+  }
+  return g;
+}
+
+// Reference-element tables at the quadrature points, built at compile time
+// and kept in constant memory: indices that are uniform across a wavefront
+// (q, j) are served by the scalar cache, the row-dependent entries (the row's
+// local index li) by ordinary cached loads.
+template <int D>
+struct Tab {
+  static constexpr int NQ = Rule<D>::NQ, NL = P2<D>::NLOC;
+  double w[NQ];
+  double lam[NQ][D + 1];
+  double phi[NQ][NL];
+  double dphi[NQ][NL][D];
+  constexpr Tab() : w(), lam(), phi(), dphi() {
+    for (int q = 0; q < NQ; ++q) {
+      double l[D + 1] = {};
+      for (int k = 0; k <= D; ++k) l[k] = Rule<D>::lam(q, k);
+      w[q] = Rule<D>::w(q);
+      for (int k = 0; k <= D; ++k) lam[q][k] = l[k];
+      for (int j = 0; j < NL; ++j) {
+        phi[q][j] = P2<D>::phi(j, l);
+        for (int r = 0; r < D; ++r) dphi[q][j][r] = P2<D>::dphi(j, r, l);
+      }
+    }
+  }
+};
+
+__constant__ Tab<2> c_tab2 = Tab<2>();
+__constant__ Tab<3> c_tab3 = Tab<3>();
+
+template <int D>
+__device__ __forceinline__ const Tab<D>& tab();
+template <>
+__device__ __forceinline__ const Tab<2>& tab<2>() { return c_tab2; }
+template <>
+__device__ __forceinline__ const Tab<3>& tab<3>() { return c_tab3; }
+
+// physical gradient components of reference gradient gr: g_b = sum_a Ji[a][b] gr_a
+template <int D>
+__device__ __forceinline__ void phys(const Geo<D>& g, const double* gr, double* out) {
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) s += g.Ji[a][b] * gr[a];
+    out[b] = s;
+  }
+}
+
+// ------------------------------------------------------------------ ops
+// Each op fills v[NOUT][NCOL] = the local row li of NOUT matrices.
+template <int D>
+struct OpMassStiff {   // P2 x P2: M and K
+  static constexpr int NOUT = 2, NCOL = P2<D>::NLOC;
+  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
+                             double (&v)[NOUT][NCOL]) const {
+    const Tab<D>& T = tab<D>();
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) {
+      const double wq = T.w[q] * g.det;
+      const double phi_i = T.phi[q][li];
+      double gi[D];
+      phys<D>(g, T.dphi[q][li], gi);
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) {
+        double gj[D];
+        phys<D>(g, T.dphi[q][j], gj);
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) s += gi[b] * gj[b];
+        v[0][j] += wq * phi_i * T.phi[q][j];
+        v[1][j] += wq * s;
+      }
+    }
+  }
+};
+
+template <int D>
+struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
+  const double* U;        // [D][n2]
+  int64_t n2;
+  double inv_dt;
+  __device__ void operator()(const Geo<D>& g, const int32_t* dofs, int li,
+                             double (&v)[NOUT][NCOL]) const {
+    const Tab<D>& T = tab<D>();
+    double Uc[D][NCOL];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int m = 0; m < NCOL; ++m) Uc[c][m] = U[(size_t)c * n2 + dofs[m]];
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) {
+      double uq[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m) s += Uc[c][m] * T.phi[q][m];
+        uq[c] = s;
+      }
+      double beta[D];   // J^{-1} u_h: reference-frame velocity
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) s += g.Ji[a][c] * uq[c];
+        beta[a] = s;
+      }
+      const double ci = T.w[q] * g.det * T.phi[q][li];
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) {
+        double adv = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) adv += beta[a] * T.dphi[q][j][a];
+        v[0][j] += ci * (T.phi[q][j] * inv_dt - adv);
+      }
+    }
+  }
+};
+
+template <int D>
+struct OpGrad {   // P2 rows x P1 cols: G_c, c < D
+  static constexpr int NOUT = D, NCOL = D + 1;
+  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
+                             double (&v)[NOUT][NCOL]) const {
+    const Tab<D>& T = tab<D>();
+    double int_phi = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) int_phi += T.w[q] * T.phi[q][li];
+    int_phi *= g.det;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+      double gr[D], gp[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) gr[a] = P2<D>::template dlam<double>(k, a);
+      phys<D>(g, gr, gp);
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c][k] += int_phi * gp[c];
+    }
+  }
+};
+
+template <int D>
+struct OpDiv {   // P1 rows x P2 cols: D_c, c < D
+  static constexpr int NOUT = D, NCOL = P2<D>::NLOC;
+  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
+                             double (&v)[NOUT][NCOL]) const {
+    const Tab<D>& T = tab<D>();
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) {
+      const double ci = T.w[q] * g.det * T.lam[q][li];
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) {
+        double gp[D];
+        phys<D>(g, T.dphi[q][j], gp);
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c][j] += ci * gp[c];
+      }
+    }
+  }
+};
+
+template <int D>
+struct OpKp {   // P1 x P1 stiffness
+  static constexpr int NOUT = 1, NCOL = D + 1;
+  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
+                             double (&v)[NOUT][NCOL]) const {
+    double gl[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+      double gr[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) gr[a] = P2<D>::template dlam<double>(k, a);
+      phys<D>(g, gr, gl[k]);
+    }
+    double gi[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      double s = gl[0][b];
+#pragma unroll
+      for (int m = 1; m <= D; ++m) s = (li == m) ? gl[m][b] : s;
+      gi[b] = s;
+    }
+    const double vol = g.det * ref_measure<D>();
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) s += gi[b] * gl[k][b];
+      v[0][k] += vol * s;
+    }
+  }
+};
+
+// ------------------------------------------------------------------ kernel
+template <int D, class Op>
+__global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
+  extern __shared__ double lds[];
+  constexpr int NOUT = Op::NOUT, NCOL = Op::NCOL;
+  const int r0 = blockIdx.x * blockDim.x;
+  const int rend = min(r0 + (int)blockDim.x, a.nrows);
+  const int base = a.rowptr[r0];
+  const int bnnz = a.rowptr[rend] - base;
+  for (int k = threadIdx.x; k < NOUT * bnnz; k += blockDim.x) lds[k] = 0.0;
+  __syncthreads();
+  const int row = r0 + threadIdx.x;
+  if (row < a.nrows) {
+    const int off = a.rowptr[row] - base;
+    for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+      const int code = a.inc[p];
+      const int cell = code >> 4, li = code & 15;
+      const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
+      int32_t dl[P2<D>::NLOC];
+#pragma unroll
+      for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = dofs[m];
+      const Geo<D> g = cell_geo<D>(a.X, dl);
+      double v[NOUT][NCOL];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int j = 0; j < NCOL; ++j) v[o][j] = 0.0;
+      op(g, dl, li, v);
+      const uint8_t* sl = a.slot + (size_t)p * a.stride;
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) {
+        const int s = off + sl[j];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) lds[o * bnnz + s] += v[o][j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < bnnz; k += blockDim.x)
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) a.out[o][base + k] = lds[o * bnnz + k];
+}
+
+template <int D, class Op>
+static void launch_rows(hipStream_t s, const RowAsm& a, const Op& op, int bs, size_t lds) {
+  if (a.nrows <= 0) return;
+  const int nb = (int)div_up(a.nrows, bs);
+  hipLaunchKernelGGL((k_asm_rows<D, Op>), dim3(nb), dim3(bs), lds, s, a, op);
+  HIP_LAUNCH_OK();
+}
+
+void asm_mass_stiff(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  if (dim == 2) launch_rows<2>(s, a, OpMassStiff<2>{}, bs, lds);
+  else launch_rows<3>(s, a, OpMassStiff<3>{}, bs, lds);
+}
+void asm_conv_explicit(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+                       const double* U, int64_t n2, double inv_dt) {
+  if (dim == 2) launch_rows<2>(s, a, OpConvExplicit<2>{U, n2, inv_dt}, bs, lds);
+  else launch_rows<3>(s, a, OpConvExplicit<3>{U, n2, inv_dt}, bs, lds);
+}
+void asm_grad(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  if (dim == 2) launch_rows<2>(s, a, OpGrad<2>{}, bs, lds);
+  else launch_rows<3>(s, a, OpGrad<3>{}, bs, lds);
+}
+void asm_div(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  if (dim == 2) launch_rows<2>(s, a, OpDiv<2>{}, bs, lds);
+  else launch_rows<3>(s, a, OpDiv<3>{}, bs, lds);
+}
+void asm_kp(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  if (dim == 2) launch_rows<2>(s, a, OpKp<2>{}, bs, lds);
+  else launch_rows<3>(s, a, OpKp<3>{}, bs, lds);
+}
+
+// ------------------------------------------------------------------ vectors
+// Lumped P1 mass w_k = sum over incident cells of |K|/(d+1).
+template <int D>
+__global__ void __launch_bounds__(256) k_lumped_p1(RowAsm a, double* w) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  double s = 0.0;
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int cell = a.inc[p] >> 4;
+    int32_t dl[D + 1];
+#pragma unroll
+    for (int m = 0; m <= D; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    s += cell_geo<D>(a.X, dl).det * (ref_measure<D>() / (D + 1));
+  }
+  w[row] = s;
+}
+
+void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w) {
+  const int nb = (int)div_up(a.nrows, 256);
+  if (dim == 2) hipLaunchKernelGGL((k_lumped_p1<2>), dim3(nb), dim3(256), 0, s, a, w);
+  else hipLaunchKernelGGL((k_lumped_p1<3>), dim3(nb), dim3(256), 0, s, a, w);
+  HIP_LAUNCH_OK();
+}
+
+// Forcing vector F_{c,i} = sum_q w_q |J| f_c(x_q, t) phi_i(x_q); f from a
+// built-in closed form or from values fq[c][cell][q] supplied by the host.
+template <int D>
+__global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const double* fq,
+                                                 int64_t nc, double t, double* F, int64_t n2) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int code = a.inc[p];
+    const int cell = code >> 4, li = code & 15;
+    int32_t dl[P2<D>::NLOC];
+#pragma unroll
+    for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    const Geo<D> g = cell_geo<D>(a.X, dl);
+    const Tab<D>& T = tab<D>();
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) {
+      const double ci = T.w[q] * g.det * T.phi[q][li];
+      double f[D];
+      if (fq) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          f[c] = fq[((size_t)c * nc + cell) * Rule<D>::NQ + q];
+      } else {
+        double x[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k <= D; ++k) s += T.lam[q][k] * a.X[(size_t)dl[k] * D + r];
+          x[r] = s;
+        }
+        builtin_force<D>(bi, x, t, f);
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += ci * f[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) F[(size_t)c * n2 + row] = acc[c];
+}
+
+void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, const double* fq,
+                 int64_t nc, double t, double* F, int64_t n2) {
+  const int nb = (int)div_up(a.nrows, 256);
+  if (dim == 2)
+    hipLaunchKernelGGL((k_forcing<2>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
+  else
+    hipLaunchKernelGGL((k_forcing<3>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
+  HIP_LAUNCH_OK();
+}
+
+// ------------------------------------------------------------------ elimination
+// out = cm*M + ck*K with Dirichlet rows and columns eliminated (zero, unit
+// diagonal on boundary rows); dinv = 1/diag(out). One thread per row.
+__global__ void __launch_bounds__(256) k_form_elim(int64_t n, const int32_t* rowptr,
+                                                   const int32_t* col, const uint8_t* bmask,
+                                                   const double* M, const double* K, double cm,
+                                                   double ck, double* out, double* dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool bi = bmask[i];
+  double diag = 1.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const int j = col[k];
+    double v;
+    if (bi || bmask[j]) v = (j == i) ? 1.0 : 0.0;
+    else v = cm * M[k] + (K ? ck * K[k] : 0.0);
+    out[k] = v;
+    if (j == i) diag = v;
+  }
+  dinv[i] = 1.0 / diag;
+}
+
+void form_eliminated(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
+                     const uint8_t* bmask, const double* M, const double* K, double cm,
+                     double ck, double* out, double* dinv) {
+  hipLaunchKernelGGL(k_form_elim, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, rowptr,
+                     col, bmask, M, K, cm, ck, out, dinv);
+  HIP_LAUNCH_OK();
+}
+
+__global__ void k_inv_diag(int64_t n, const int32_t* rowptr, const int32_t* col,
+                           const double* val, double* dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+    if (col[k] == i) d = val[k];
+  dinv[i] = 1.0 / d;
+}
+
+void inv_diagonal(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
+                  const double* val, double* dinv) {
+  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, rowptr, col,
+                     val, dinv);
+  HIP_LAUNCH_OK();
+}
+
+__global__ void k_lift_vals(int64_t n, const int32_t* slot, const double* M, const double* K,
+                            double cm, double ck, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int k = slot[e];
+  out[e] = cm * M[k] + (K ? ck * K[k] : 0.0);
+}
+
+void lift_values(hipStream_t s, int64_t nlift, const int32_t* slot, const double* M,
+                 const double* K, double cm, double ck, double* out) {
+  if (nlift <= 0) return;
+  hipLaunchKernelGGL(k_lift_vals, dim3((unsigned)div_up(nlift, 256)), dim3(256), 0, s, nlift,
+                     slot, M, K, cm, ck, out);
+  HIP_LAUNCH_OK();
+}
+
+}  // namespace ipcs

@@ -1,0 +1,352 @@
+// Mesh generators, P1/P2 DOF maps, CSR patterns and row-owner assembly maps.
+// Integer work done once per mesh on the host (Section 2.2.1: conforming
+// simplicial mesh, continuous Lagrange P2 velocity and P1 pressure spaces).
+#include "mesh.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <string>
+
+#include "common.hpp"
+#include "rules.hpp"
+
+namespace ipcs {
+
+const Pattern& Mesh::pattern(int which) const {
+  switch (which) {
+    case IPCS_PATTERN_P2P2: return p22;
+    case IPCS_PATTERN_P1P1: return p11;
+    case IPCS_PATTERN_P1P2: return p12;
+    case IPCS_PATTERN_P2P1: return p21;
+  }
+  fail(IPCS_E_INVALID, "unknown pattern id " + std::to_string(which));
+}
+
+namespace {
+
+inline int edge_a(int dim, int e) { return dim == 2 ? Edges<2>::a(e) : Edges<3>::a(e); }
+inline int edge_b(int dim, int e) { return dim == 2 ? Edges<2>::b(e) : Edges<3>::b(e); }
+
+inline uint64_t edge_key(int32_t u, int32_t v) {
+  if (u > v) std::swap(u, v);
+  return (uint64_t(uint32_t(u)) << 32) | uint32_t(v);
+}
+
+// Row-wise union of the column DOFs of the cells incident to each row.
+void build_pattern(const Incidence& inc, const std::vector<int32_t>& c2d, int nloc,
+                   int ncolloc, int64_t nrows, int64_t ncols, Pattern& P, int& maxrow) {
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.rowptr.assign(nrows + 1, 0);
+  std::vector<int32_t> len(nrows);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < nrows; ++i) {
+    int32_t buf[1024];
+    int n = 0;
+    for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
+      int64_t c = inc.code[p] >> 4;
+      for (int j = 0; j < ncolloc; ++j) {
+        if (n < 1024) buf[n++] = c2d[c * nloc + j];
+      }
+    }
+    std::sort(buf, buf + n);
+    len[i] = int32_t(std::unique(buf, buf + n) - buf);
+  }
+  int64_t tot = 0;
+  maxrow = 0;
+  for (int64_t i = 0; i < nrows; ++i) {
+    P.rowptr[i] = int32_t(tot);
+    tot += len[i];
+    maxrow = std::max(maxrow, len[i]);
+  }
+  if (tot >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "pattern exceeds 2^31 entries");
+  P.rowptr[nrows] = int32_t(tot);
+  P.col.resize(tot);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < nrows; ++i) {
+    int32_t buf[1024];
+    int n = 0;
+    for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
+      int64_t c = inc.code[p] >> 4;
+      for (int j = 0; j < ncolloc; ++j) {
+        if (n < 1024) buf[n++] = c2d[c * nloc + j];
+      }
+    }
+    std::sort(buf, buf + n);
+    int m = int(std::unique(buf, buf + n) - buf);
+    std::copy(buf, buf + m, P.col.begin() + P.rowptr[i]);
+  }
+  if (maxrow > 255) fail(IPCS_E_INVALID, "a matrix row has more than 255 entries");
+}
+
+void build_slots(const Incidence& inc, const std::vector<int32_t>& c2d, int nloc, int ncolloc,
+                 const Pattern& P, SlotMap& S) {
+  S.stride = int((ncolloc + 3) / 4 * 4);
+  const int64_t npairs = (int64_t)inc.code.size();
+  S.slot.assign(npairs * S.stride, 0);
+  const int64_t nrows = P.nrows;
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < nrows; ++i) {
+    const int32_t* b = P.col.data() + P.rowptr[i];
+    const int32_t* e = P.col.data() + P.rowptr[i + 1];
+    for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
+      int64_t c = inc.code[p] >> 4;
+      for (int j = 0; j < ncolloc; ++j) {
+        const int32_t* f = std::lower_bound(b, e, c2d[c * nloc + j]);
+        S.slot[(int64_t)p * S.stride + j] = uint8_t(f - b);
+      }
+    }
+  }
+}
+
+void build_incidence(const std::vector<int32_t>& c2d, int64_t nc, int nloc, int nrowloc,
+                     int64_t nrows, Incidence& I) {
+  I.ptr.assign(nrows + 1, 0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int j = 0; j < nrowloc; ++j) I.ptr[c2d[c * nloc + j] + 1]++;
+  for (int64_t i = 0; i < nrows; ++i) I.ptr[i + 1] += I.ptr[i];
+  I.code.resize(I.ptr[nrows]);
+  std::vector<int32_t> fill(I.ptr.begin(), I.ptr.end() - 1);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int j = 0; j < nrowloc; ++j) I.code[fill[c2d[c * nloc + j]]++] = int32_t((c << 4) | j);
+}
+
+void finalize(Mesh& m) {
+  const int d = m.dim;
+  const int64_t nc = m.nc, nv = m.nv;
+  const int ne_loc = d == 2 ? 3 : 6;
+  m.nloc1 = d + 1;
+  m.nloc2 = d + 1 + ne_loc;
+  if (nc >= (int64_t(1) << 27)) fail(IPCS_E_INVALID, "too many cells");
+  if (nv >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "too many vertices");
+  // --- edges: unique vertex pairs, sorted lexicographically
+  std::vector<uint64_t> keys(nc * ne_loc);
+#pragma omp parallel for
+  for (int64_t c = 0; c < nc; ++c)
+    for (int e = 0; e < ne_loc; ++e)
+      keys[c * ne_loc + e] = edge_key(m.c2d[c * (d + 1) + edge_a(d, e)],
+                                      m.c2d[c * (d + 1) + edge_b(d, e)]);
+  std::vector<uint64_t> uk(keys);
+  std::sort(uk.begin(), uk.end());
+  uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+  m.ne = (int64_t)uk.size();
+  m.n1 = nv;
+  m.n2 = nv + m.ne;
+  if (m.n2 >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "too many DOFs");
+  m.edges.resize(2 * m.ne);
+  for (int64_t e = 0; e < m.ne; ++e) {
+    m.edges[2 * e] = int32_t(uk[e] >> 32);
+    m.edges[2 * e + 1] = int32_t(uk[e] & 0xffffffffu);
+  }
+  // --- cell -> P2 dofs (c2d currently holds the vertices, stride d+1)
+  std::vector<int32_t> c2d(nc * m.nloc2);
+#pragma omp parallel for
+  for (int64_t c = 0; c < nc; ++c) {
+    for (int k = 0; k <= d; ++k) c2d[c * m.nloc2 + k] = m.c2d[c * (d + 1) + k];
+    for (int e = 0; e < ne_loc; ++e) {
+      uint64_t k = keys[c * ne_loc + e];
+      c2d[c * m.nloc2 + d + 1 + e] =
+          int32_t(nv + (std::lower_bound(uk.begin(), uk.end(), k) - uk.begin()));
+    }
+  }
+  m.c2d.swap(c2d);
+  // --- P2 node coordinates
+  m.x2.resize(m.n2 * d);
+  for (int64_t i = 0; i < nv * d; ++i) m.x2[i] = m.X[i];
+  for (int64_t e = 0; e < m.ne; ++e)
+    for (int k = 0; k < d; ++k)
+      m.x2[(nv + e) * d + k] =
+          0.5 * (m.X[(int64_t)m.edges[2 * e] * d + k] + m.X[(int64_t)m.edges[2 * e + 1] * d + k]);
+  // --- boundary: facets owned by exactly one cell; their vertices and edges
+  m.bmask.assign(m.n2, 0);
+  if (d == 2) {
+    std::vector<int32_t> cnt(m.ne, 0);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int e = 0; e < 3; ++e) cnt[m.c2d[c * m.nloc2 + 3 + e] - nv]++;
+    for (int64_t e = 0; e < m.ne; ++e)
+      if (cnt[e] == 1) {
+        m.bmask[m.edges[2 * e]] = 1;
+        m.bmask[m.edges[2 * e + 1]] = 1;
+        m.bmask[nv + e] = 1;
+      }
+  } else {
+    std::vector<std::array<int32_t, 3>> faces(nc * 4);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int k = 0; k < 4; ++k) {
+        std::array<int32_t, 3> f;
+        int n = 0;
+        for (int j = 0; j < 4; ++j)
+          if (j != k) f[n++] = m.c2d[c * m.nloc2 + j];
+        std::sort(f.begin(), f.end());
+        faces[c * 4 + k] = f;
+      }
+    std::sort(faces.begin(), faces.end());
+    for (size_t i = 0; i < faces.size();) {
+      size_t j = i + 1;
+      while (j < faces.size() && faces[j] == faces[i]) ++j;
+      if (j - i == 1) {
+        const auto& f = faces[i];
+        for (int a = 0; a < 3; ++a) {
+          m.bmask[f[a]] = 1;
+          for (int b = a + 1; b < 3; ++b) {
+            uint64_t k = edge_key(f[a], f[b]);
+            m.bmask[nv + (std::lower_bound(uk.begin(), uk.end(), k) - uk.begin())] = 1;
+          }
+        }
+      }
+      i = j;
+    }
+  }
+  m.bidx.clear();
+  for (int64_t i = 0; i < m.n2; ++i)
+    if (m.bmask[i]) m.bidx.push_back(int32_t(i));
+  // --- incidence, patterns, slot maps
+  build_incidence(m.c2d, nc, m.nloc2, m.nloc2, m.n2, m.inc2);
+  build_incidence(m.c2d, nc, m.nloc2, m.nloc1, m.n1, m.inc1);
+  build_pattern(m.inc2, m.c2d, m.nloc2, m.nloc2, m.n2, m.n2, m.p22, m.max_row22);
+  build_pattern(m.inc2, m.c2d, m.nloc2, m.nloc1, m.n2, m.n1, m.p21, m.max_row21);
+  build_pattern(m.inc1, m.c2d, m.nloc2, m.nloc1, m.n1, m.n1, m.p11, m.max_row11);
+  build_pattern(m.inc1, m.c2d, m.nloc2, m.nloc2, m.n1, m.n2, m.p12, m.max_row12);
+  build_slots(m.inc2, m.c2d, m.nloc2, m.nloc2, m.p22, m.s22);
+  build_slots(m.inc2, m.c2d, m.nloc2, m.nloc1, m.p21, m.s21);
+  build_slots(m.inc1, m.c2d, m.nloc2, m.nloc1, m.p11, m.s11);
+  build_slots(m.inc1, m.c2d, m.nloc2, m.nloc2, m.p12, m.s12);
+  // --- Dirichlet lifting entries (interior rows, boundary columns)
+  m.lift_ptr.assign(m.n2 + 1, 0);
+  m.lift_slot.clear();
+  m.lift_col.clear();
+  for (int64_t i = 0; i < m.n2; ++i) {
+    if (!m.bmask[i])
+      for (int32_t s = m.p22.rowptr[i]; s < m.p22.rowptr[i + 1]; ++s)
+        if (m.bmask[m.p22.col[s]]) {
+          m.lift_slot.push_back(s);
+          m.lift_col.push_back(m.p22.col[s]);
+        }
+    m.lift_ptr[i + 1] = int32_t(m.lift_slot.size());
+  }
+}
+
+}  // namespace
+
+Mesh* build_unit_square(int nx, int ny) {
+  if (nx < 1 || ny < 1) fail(IPCS_E_INVALID, "unit square needs nx, ny >= 1");
+  if (int64_t(nx) * ny > (int64_t(1) << 26)) fail(IPCS_E_INVALID, "mesh too large");
+  Mesh* m = new Mesh;
+  m->dim = 2;
+  m->nv = int64_t(nx + 1) * (ny + 1);
+  m->nc = 2 * int64_t(nx) * ny;
+  m->X.resize(m->nv * 2);
+  for (int j = 0; j <= ny; ++j)
+    for (int i = 0; i <= nx; ++i) {
+      int64_t v = int64_t(j) * (nx + 1) + i;
+      m->X[2 * v] = double(i) / nx;
+      m->X[2 * v + 1] = double(j) / ny;
+    }
+  m->c2d.resize(m->nc * 3);
+  int64_t c = 0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int32_t a = int32_t(int64_t(j) * (nx + 1) + i), b = a + 1, cc = a + (nx + 1) + 1,
+              e = a + (nx + 1);
+      int32_t t0[3] = {a, b, cc}, t1[3] = {a, cc, e};
+      for (int k = 0; k < 3; ++k) m->c2d[3 * c + k] = t0[k];
+      ++c;
+      for (int k = 0; k < 3; ++k) m->c2d[3 * c + k] = t1[k];
+      ++c;
+    }
+  try {
+    finalize(*m);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
+Mesh* build_unit_cube(int nx, int ny, int nz) {
+  if (nx < 1 || ny < 1 || nz < 1) fail(IPCS_E_INVALID, "unit cube needs nx, ny, nz >= 1");
+  if (int64_t(nx) * ny * nz > (int64_t(1) << 23)) fail(IPCS_E_INVALID, "mesh too large");
+  Mesh* m = new Mesh;
+  m->dim = 3;
+  m->nv = int64_t(nx + 1) * (ny + 1) * (nz + 1);
+  m->nc = 6 * int64_t(nx) * ny * nz;
+  m->X.resize(m->nv * 3);
+  auto vid = [&](int i, int j, int k) {
+    return int32_t((int64_t(k) * (ny + 1) + j) * (nx + 1) + i);
+  };
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i <= nx; ++i) {
+        int64_t v = vid(i, j, k);
+        m->X[3 * v] = double(i) / nx;
+        m->X[3 * v + 1] = double(j) / ny;
+        m->X[3 * v + 2] = double(k) / nz;
+      }
+  m->c2d.resize(m->nc * 4);
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                  {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int64_t c = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        for (int p = 0; p < 6; ++p) {
+          int q[3] = {i, j, k};
+          m->c2d[4 * c] = vid(q[0], q[1], q[2]);
+          for (int s = 0; s < 3; ++s) {
+            q[perms[p][s]] += 1;
+            m->c2d[4 * c + 1 + s] = vid(q[0], q[1], q[2]);
+          }
+          // positive orientation: the path e_a, e_b, e_c has det = sign of the
+          // permutation (a,b,c); odd permutations swap the last two vertices
+          if (p == 1 || p == 2 || p == 5) std::swap(m->c2d[4 * c + 2], m->c2d[4 * c + 3]);
+          ++c;
+        }
+  try {
+    finalize(*m);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
+Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells) {
+  if (dim != 2 && dim != 3) fail(IPCS_E_INVALID, "dim must be 2 or 3");
+  if (nv < dim + 1 || nc < 1 || !x || !cells) fail(IPCS_E_INVALID, "empty mesh");
+  Mesh* m = new Mesh;
+  m->dim = dim;
+  m->nv = nv;
+  m->nc = nc;
+  m->X.assign(x, x + nv * dim);
+  m->c2d.assign(cells, cells + nc * (dim + 1));
+  for (int64_t i = 0; i < nc * (dim + 1); ++i)
+    if (m->c2d[i] < 0 || m->c2d[i] >= nv) {
+      delete m;
+      fail(IPCS_E_INVALID, "cell vertex index out of range");
+    }
+  for (int64_t c = 0; c < nc; ++c) {
+    double J[3][3] = {};
+    for (int k = 0; k < dim; ++k)
+      for (int r = 0; r < dim; ++r)
+        J[r][k] = x[(int64_t)cells[c * (dim + 1) + k + 1] * dim + r] -
+                  x[(int64_t)cells[c * (dim + 1)] * dim + r];
+    double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                          : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 0)) {
+      delete m;
+      fail(IPCS_E_INVALID, "degenerate cell " + std::to_string(c));
+    }
+  }
+  try {
+    finalize(*m);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
+}  // namespace ipcs

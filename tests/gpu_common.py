@@ -1,0 +1,70 @@
+"""Helpers shared by the GPU tests: build matching oracle / library runs and
+compare them. Nothing here computes any part of the method."""
+import numpy as np
+import pytest
+
+from oracle import fem, ipcs, mesh, problems
+
+
+def require_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_25403_amd import ipcs as I
+    return torch, I
+
+
+def oracle_problem(kind, dim, nu, k=np.pi):
+    if kind == "tg":
+        return problems.TaylorGreen2D(k, nu)
+    if kind == "john":
+        return problems.John2D(nu)
+    if kind == "beltrami":
+        return problems.Beltrami3D(nu=nu)
+    if kind == "poly":
+        return problems.PolySteady2D(nu) if dim == 2 else problems.PolySteady3D(nu)
+    raise KeyError(kind)
+
+
+def builtin_kind(I, kind, dim):
+    return {"tg": I.IPCS_SOL_TAYLOR_GREEN_2D, "john": I.IPCS_SOL_JOHN_2D,
+            "beltrami": I.IPCS_SOL_BELTRAMI_3D,
+            "poly": I.IPCS_SOL_POLY_STEADY_2D if dim == 2 else I.IPCS_SOL_POLY_STEADY_3D}[kind]
+
+
+def oracle_space(dim, n):
+    return fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)))
+
+
+def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=True, **kw):
+    """Oracle IPCS object and library run for the same problem. With
+    same_state the library starts from the oracle's initial arrays."""
+    S = oracle_space(dim, n)
+    pb = oracle_problem(kind, dim, nu, k)
+    o = ipcs.IPCS(S, pb, ipcs.Params(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol,
+                                     tol_corr=tol))
+    m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
+    p = I.ipcs_params_default(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol, tol_corr=tol, **kw)
+    r = I.Run(m, p)
+    prm = (k,) if kind == "tg" else ()
+    r.set_builtin(builtin_kind(I, kind, dim), prm)
+    if same_state:
+        r.set_state(o.U, o.P, o.t)
+    return S, o, r
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def field_errors(o, r):
+    U, P = r.velocity(), r.pressure()
+    return [rel(U[c], o.U[c]) for c in range(o.S.dim)] + [rel(P, o.P)]
+
+
+def mat_rel(Agpu, Aor):
+    """max |dA| / max |A| on identical patterns (patterns compared exactly)."""
+    np.testing.assert_array_equal(Agpu.indptr, Aor.indptr)
+    np.testing.assert_array_equal(Agpu.indices, Aor.indices)
+    return np.abs(Agpu.data - Aor.data).max() / np.abs(Aor.data).max()

@@ -1,0 +1,130 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: assembled matrices max|dA|/max|A| <= 1e-12; fields ||dx||/||x|| <=
+1e-10 per component and for the pressure, per step. Both sides drive their
+Krylov solves to 1e-13 (each side's distance to the exact discrete solution
+is at most kappa * tol, and kappa(Kp) ~ 1e2 on these meshes)."""
+import numpy as np
+import pytest
+
+from oracle import fem
+from tests.gpu_common import field_errors, make_pair, mat_rel, oracle_space, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+MAT_TOL = 1e-12
+FIELD_TOL = 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(2, 5), (2, 16), (2, 23), (3, 2), (3, 3)])
+def test_constant_matrices(dim, n):
+    torch, I = require_gpu()
+    print(f"constant matrices dim={dim} n={n}", flush=True)
+    nu, dt = 0.013, 0.007
+    kind = "tg" if dim == 2 else "beltrami"
+    S, o, r = make_pair(I, dim, n, kind, nu, dt)
+    assert mat_rel(r.matrix(I.IPCS_MAT_M), o.M) <= MAT_TOL
+    assert mat_rel(r.matrix(I.IPCS_MAT_K), o.K) <= MAT_TOL
+    assert mat_rel(r.matrix(I.IPCS_MAT_KP), o.Kp) <= MAT_TOL
+    assert mat_rel(r.matrix(I.IPCS_MAT_A_ELIM), o.A_el) <= MAT_TOL
+    assert mat_rel(r.matrix(I.IPCS_MAT_M_ELIM), o.M_el) <= MAT_TOL
+    for c in range(dim):
+        assert mat_rel(r.matrix(I.IPCS_MAT_D0 + c), o.D[c]) <= MAT_TOL
+        assert mat_rel(r.matrix(I.IPCS_MAT_G0 + c), o.G[c]) <= MAT_TOL
+
+
+@pytest.mark.parametrize("dim,n,kind", [(2, 16, "tg"), (2, 7, "john"), (3, 3, "beltrami")])
+def test_convection_operator_and_momentum_rhs(dim, n, kind):
+    torch, I = require_gpu()
+    print(f"convection/rhs dim={dim} n={n} {kind}", flush=True)
+    nu, dt = 0.02, 0.01
+    S, o, r = make_pair(I, dim, n, kind, nu, dt)
+    r.phase(I.IPCS_PHASE_ASM)
+    C = fem.convection(S, o.U)
+    E = (o.M / dt - C).tocsr()
+    E.sort_indices()
+    assert mat_rel(r.matrix(I.IPCS_MAT_E), E) <= MAT_TOL
+    t1 = o.t + dt
+    g = o.dirichlet(t1)
+    F = o.forcing(t1)
+    b = r.field(I.IPCS_FIELD_RHS_MOM)
+    for c in range(dim):
+        ref = o.M @ o.U[c] / dt - o.G[c] @ o.P + F[c] - C @ o.U[c]
+        ref = fem.lift(o.A, ref, o.bmask, g[c])
+        assert rel(b[c], ref) <= MAT_TOL
+
+
+@pytest.mark.parametrize("dim,n,kind", [(2, 16, "tg"), (2, 9, "john"), (3, 3, "beltrami")])
+def test_each_substep_from_identical_state(dim, n, kind):
+    torch, I = require_gpu()
+    print(f"substeps dim={dim} n={n} {kind}", flush=True)
+    nu, dt = 0.01, 0.01
+    S, o, r = make_pair(I, dim, n, kind, nu, dt)
+    t1 = o.t + dt
+    g = o.dirichlet(t1)
+    r.phase(I.IPCS_PHASE_ASM)
+    st = r.phase(I.IPCS_PHASE_MOMENTUM)
+    Us_o, _, _ = o.momentum(t1, g)
+    Us = r.field(I.IPCS_FIELD_USTAR)
+    for c in range(dim):
+        assert rel(Us[c], Us_o[c]) <= FIELD_TOL, (c, st)
+    st = r.phase(I.IPCS_PHASE_PRESSURE)
+    dP_o, _ = o.pressure(Us_o)
+    assert rel(r.field(I.IPCS_FIELD_DP), dP_o) <= FIELD_TOL, st
+    r.phase(I.IPCS_PHASE_CORRECTION)
+    Un_o, _ = o.correction(Us_o, dP_o, g)
+    U = r.velocity()
+    for c in range(dim):
+        assert rel(U[c], Un_o[c]) <= FIELD_TOL
+    assert rel(r.pressure(), o.P + dP_o) <= FIELD_TOL
+    assert abs(r.time() - t1) < 1e-15
+
+
+def test_c1_taylor_green_ten_steps():
+    """16 x 16 squares (512 triangles), TG k = pi, nu = 0.01, dt = 0.01,
+    10 steps; the library starts from its own device-evaluated state."""
+    torch, I = require_gpu()
+    print("C1 ten steps", flush=True)
+    S, o, r = make_pair(I, 2, 16, "tg", 0.01, 0.01, same_state=False)
+    errs = field_errors(o, r)
+    assert max(errs) <= 1e-13, errs            # initial interpolation
+    for step in range(10):
+        st = r.advance(1)[0]
+        o.step()
+        errs = field_errors(o, r)
+        assert max(errs) <= FIELD_TOL, (step, errs, st)
+        assert st["status"] == 0 and st["it_p"] > 0
+
+
+@pytest.mark.parametrize("dim,n,semi", [(2, 6, False), (3, 2, False)])
+def test_polynomial_fixed_point(dim, n, semi):
+    torch, I = require_gpu()
+    print(f"fixed point dim={dim}", flush=True)
+    S, o, r = make_pair(I, dim, n, "poly", 0.07, 0.05, tol=1e-14, same_state=False)
+    U0, P0 = r.velocity().copy(), r.pressure().copy()
+    np.testing.assert_allclose(U0, o.U, atol=1e-14)
+    r.advance(2)
+    assert np.abs(r.velocity() - U0).max() < 1e-12
+    assert np.abs(r.pressure() - P0).max() < 1e-12
+
+
+def test_john_forced_steps_and_larger_mesh():
+    torch, I = require_gpu()
+    print("John 3 steps n=40", flush=True)
+    S, o, r = make_pair(I, 2, 40, "john", 1.0, 0.002)
+    for step in range(3):
+        r.advance(1)
+        o.step()
+        errs = field_errors(o, r)
+        assert max(errs) <= FIELD_TOL, (step, errs)
+
+
+def test_beltrami_3d_steps():
+    torch, I = require_gpu()
+    print("Beltrami 3D 3 steps n=4", flush=True)
+    S, o, r = make_pair(I, 3, 4, "beltrami", 0.01, 0.01)
+    for step in range(3):
+        r.advance(1)
+        o.step()
+        errs = field_errors(o, r)
+        assert max(errs) <= FIELD_TOL, (step, errs)

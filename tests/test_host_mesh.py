@@ -1,0 +1,119 @@
+"""Host-side logic of the C-ABI library (no GPU needed): the library loads,
+exports every symbol declared in include/ipcs.h, and its mesh, DOF maps,
+boundary flags and CSR patterns equal the oracle's bit for bit. The
+library's own quadrature table is checked against the closed-form simplex
+moments."""
+import itertools
+import os
+import re
+from math import factorial
+
+import numpy as np
+import pytest
+
+from oracle import fem, mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+I = pytest.importorskip("paper_2605_25403_amd.ipcs",
+                        reason="libipcs.so not built (run __graft_entry__.build())")
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "ipcs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ipcs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    syms = header_symbols()
+    assert len(syms) >= 25
+    for s in syms:
+        assert hasattr(I.lib, s), s
+    assert set(syms) == set(I.EXPORTED)
+
+
+def oracle_space(dim, n):
+    return fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)))
+
+
+def lib_mesh(dim, n):
+    return I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
+
+
+def compare(S, m):
+    c = m.counts
+    assert (c.dim, c.nv, c.nc, c.n1, c.n2) == (S.dim, S.Nv, S.Nc, S.N1, S.N2)
+    np.testing.assert_array_equal(I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2), S.x2)
+    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P2), S.c2d2)
+    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P1), S.c2d1)
+    np.testing.assert_array_equal(I.ipcs_mesh_boundary(m.h).astype(bool), S.boundary2)
+    assert c.nb2 == S.boundary2.sum()
+    ones = lambda rows, cols: fem.assemble(np.ones((S.Nc, rows.shape[1], cols.shape[1])),
+                                           rows, cols, (rows.max() + 1, cols.max() + 1))
+    for which, (r, cc) in {I.IPCS_PATTERN_P2P2: (S.c2d2, S.c2d2),
+                           I.IPCS_PATTERN_P1P1: (S.c2d1, S.c2d1),
+                           I.IPCS_PATTERN_P1P2: (S.c2d1, S.c2d2),
+                           I.IPCS_PATTERN_P2P1: (S.c2d2, S.c2d1)}.items():
+        A = ones(r, cc)
+        rp, col = I.ipcs_mesh_pattern(m.h, which)
+        np.testing.assert_array_equal(rp, A.indptr)
+        np.testing.assert_array_equal(col, A.indices)
+        assert c.nnz[which] == A.nnz
+
+
+@pytest.mark.parametrize("dim,n", [(2, 1), (2, 2), (2, 5), (2, 16), (3, 1), (3, 2), (3, 3)])
+def test_structured_meshes_match_oracle_exactly(dim, n):
+    compare(oracle_space(dim, n), lib_mesh(dim, n))
+
+
+def test_unstructured_mesh_from_arrays_matches_oracle():
+    rng = np.random.default_rng(11)
+    X, cells = mesh.unit_square(6, 5)
+    X = X.copy()
+    interior = (X[:, 0] > 0) & (X[:, 0] < 1) & (X[:, 1] > 0) & (X[:, 1] < 1)
+    X[interior] += 0.04 * rng.standard_normal((interior.sum(), 2))
+    cells = cells[rng.permutation(len(cells))]
+    flip = rng.random(len(cells)) < 0.5
+    cells[flip] = cells[flip][:, [0, 2, 1]]          # clockwise cells are allowed
+    compare(fem.Space(X, cells), I.Mesh.from_arrays(X, cells))
+
+
+def test_library_quadrature_rules_are_degree_5_exact():
+    for dim, nq in ((2, 7), (3, 14)):
+        lam, w = I.ipcs_quadrature_rule(dim)
+        assert lam.shape == (nq, dim + 1)
+        np.testing.assert_allclose(lam.sum(axis=1), 1.0, atol=1e-15)
+        assert abs(w.sum() - 1.0 / factorial(dim)) < 1e-16
+        for alpha in itertools.product(range(6), repeat=dim + 1):
+            if sum(alpha) <= 5:
+                ex = np.prod([factorial(a) for a in alpha]) / factorial(sum(alpha) + dim)
+                got = np.sum(w * np.prod(lam ** np.array(alpha), axis=1))
+                assert abs(got - ex) < 5e-17, (dim, alpha)
+
+
+def test_invalid_arguments_are_reported():
+    with pytest.raises(I.IpcsError) as e:
+        I.ipcs_mesh_unit_square(0, 4)
+    assert e.value.code == I.IPCS_E_INVALID and "nx" in I.ipcs_last_error()
+    m = I.Mesh.unit_square(2)
+    out = np.empty(3, dtype=np.float64)
+    rc = I.lib.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2, out.ctypes.data_as(I.C.c_void_p), 3)
+    assert rc == I.IPCS_E_INVALID
+    with pytest.raises(I.IpcsError):
+        I.ipcs_mesh_from_arrays(np.zeros((3, 2)), np.array([[0, 1, 2]]))   # degenerate
+    with pytest.raises(I.IpcsError):
+        I.ipcs_mesh_from_arrays(np.eye(3, 2), np.array([[0, 1, 5]]))       # bad index
+    p = I.ipcs_params_default(dt=-1.0)
+    with pytest.raises(I.IpcsError):
+        I.ipcs_run_workspace_bytes(m.h, p)
+
+
+def test_workspace_size_grows_with_the_mesh_and_covers_the_values():
+    p = I.ipcs_params_default()
+    ms = I.Mesh.unit_square(8)
+    small = I.ipcs_run_workspace_bytes(ms.h, p)
+    m = I.Mesh.unit_square(32)
+    big = I.ipcs_run_workspace_bytes(m.h, p)
+    assert big > 4 * small          # fixed-size scratch dominates tiny meshes
+    # at least the five P2P2 value arrays and the velocity vectors
+    assert big > 5 * 8 * m.counts.nnz[0] + 6 * 8 * 2 * m.counts.n2
