@@ -224,6 +224,21 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
  * it is stepped alone. stats may be NULL or hold nruns entries. */
 int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats);
 
+enum {                          /* kernels of the step, for ipcs_profile_kernel   */
+  IPCS_KERNEL_PCG_SPMV_P = 0,   /* Poisson PCG: p = z + beta p, q = Kp p, p.q     */
+  IPCS_KERNEL_PCG_UPDATE_P = 1, /* Poisson PCG: x, r, z updates and r.z, r.r      */
+  IPCS_KERNEL_ASM_CONV = 2,     /* convection assembly E = M/dt - C(U^n)           */
+  IPCS_KERNEL_BICG_SPMV = 3,    /* momentum BiCGStab v = A phat, rhat.v (all comps) */
+  IPCS_KERNEL_PCG_SPMV_M = 4    /* correction PCG q = M p, p.q (all components)   */
+};
+/* Measurement hook (not part of the method): launches one of the step's
+ * kernels nlaunch times back to back on the run's stream with the run's own
+ * data and returns the mean duration per launch in microseconds, timed with
+ * HIP events on that stream. Leaves the run's Krylov scratch vectors and
+ * states undefined (the next solve re-initializes them); the state U, P and t
+ * are not touched. Call between steps only. */
+int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_per_launch);
+
 void ipcs_run_destroy(ipcs_run r);
 
 #ifdef __cplusplus

@@ -198,19 +198,11 @@ int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes) 
   return guard([&]() -> int {
     check_params(p);
     need(bytes != nullptr, "null output");
+    (void)M(m);
     ipcs::Run tmp;
-    tmp.mesh = m ? m->m : nullptr;
-    const ipcs::Mesh& mm = M(m);
+    tmp.mesh = m->m;
     tmp.prm = *p;
-    tmp.dim = mm.dim;
-    tmp.n1 = mm.n1;
-    tmp.n2 = mm.n2;
-    tmp.nc = mm.nc;
-    tmp.nv = mm.nv;
-    tmp.nb = (int64_t)mm.bidx.size();
-    tmp.nlift = (int64_t)mm.lift_slot.size();
-    tmp.G22 = ipcs::lanes_for(double(mm.p22.nnz()) / mm.n2);
-    tmp.G11 = ipcs::lanes_for(double(mm.p11.nnz()) / mm.n1);
+    tmp.sizes_from_mesh();
     ipcs::Carver c;
     tmp.layout(c);
     *bytes = c.off;
@@ -373,10 +365,11 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
       need(cap_rows >= P.nrows + 1, "rowptr buffer too small");
       std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
     }
-    need(cap_nnz >= P.nnz(), "value buffer too small");
+    need(val != nullptr && cap_nnz >= P.nnz(), "value buffer too small");
     if (col) std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
     if (rr.A_dirty) rr.reform_A();
-    return copy_out(rr, src, P.nnz(), val, cap_nnz);
+    rr.export_values(pat, src, val);
+    return IPCS_OK;
   });
 }
 
@@ -387,6 +380,14 @@ int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_s
     (void)hip_stream;
     (void)stats;
     ipcs::fail(IPCS_E_STATE, "batched stepping is not available in this build");
+  });
+}
+
+int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_per_launch) {
+  return guard([&]() -> int {
+    need(nlaunch > 0 && us_per_launch != nullptr, "need nlaunch > 0 and an output");
+    *us_per_launch = R(r).profile_kernel(kernel, nlaunch);
+    return IPCS_OK;
   });
 }
 

@@ -1,5 +1,11 @@
-// Device helpers: lane-group and block reductions, and the deterministic
-// "last block finishes the reduction" pattern used for dot products.
+// Device helpers: lane-group and block reductions, and the fence-free
+// two-stage reduction used for dot products.
+//
+// Cross-block reductions never synchronize blocks inside a kernel: a producer
+// kernel writes one partial sum per block, and every block of the next kernel
+// (after the kernel boundary has made the partials visible) sums all of them in
+// block order with a fixed tree. The result is deterministic, identical in
+// every consumer block, and independent of which other systems share a launch.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -18,52 +24,93 @@ __device__ __forceinline__ double group_sum(double v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
-// Sum over the block (blockDim.x == BLOCK); result valid in every thread.
-// The order of additions is fixed, so the result is deterministic.
+// Sum over the block (blockDim.x a multiple of 64, at most 1024); result valid
+// in every thread; fixed order of additions. sh needs blockDim.x/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   v = wave_sum(v);
   __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < BLOCK / 64; ++w) s += sh[w];
+  for (int w = 0; w < nw; ++w) s += sh[w];
   return s;
 }
 
-// Each block contributes K partial sums; the last block to arrive reduces all
-// blocks' partials in block order and returns true (in all its threads) with
-// the totals in tot[]. Other blocks return false. The reduction order depends
-// only on nblk, never on arrival order, so results are bitwise reproducible.
-template <int K>
-__device__ __forceinline__ bool reduce_last(const double (&v)[K], double* part, uint32_t* cnt,
-                                            int nblk, int lb, double (&tot)[K]) {
-  __shared__ double sh[BLOCK / 64];
-  __shared__ int last;
-  double bs[K];
+// Sums N values over the block at once (one barrier pair): out[n] valid in
+// every thread, fixed order of additions. sh needs 16*N doubles.
+template <int N>
+__device__ __forceinline__ void block_sum_n(const double (&v)[N], double (&out)[N], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double w[N];
 #pragma unroll
-  for (int k = 0; k < K; ++k) bs[k] = block_sum(v[k], sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) part[(size_t)lb * KPART + k] = bs[k];
-    __threadfence();
-    uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == uint32_t(nblk - 1));
-  }
+  for (int n = 0; n < N; ++n) w[n] = wave_sum(v[n]);
   __syncthreads();
-  if (!last) return false;
-  __threadfence();
+  if (lane == 0)
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += BLOCK)
-      a += __hip_atomic_load(&part[(size_t)i * KPART + k], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    tot[k] = block_sum(a, sh);
+    for (int n = 0; n < N; ++n) sh[wid * N + n] = w[n];
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += sh[q * N + n];
+    out[n] = s;
   }
-  if (threadIdx.x == 0) *cnt = 0u;
-  return true;
+}
+
+// Partial sums of a producer kernel, loaded in two phases so the loads can
+// be issued early and overlap other memory traffic: load() only fetches this
+// thread's entries (producer blocks tid, tid + blockDim, ...), reduce() sums
+// them over the block in a fixed order. tot[j][k] = sum over b < nb of
+// part[(b*GMAX + j)*KP + k] for j < ns, k < K; valid in every thread.
+template <int K>
+struct Partials {
+  double v[GMAX][K];
+  __device__ __forceinline__ void load(const double* part, int nb, int ns) {
+#pragma unroll
+    for (int j = 0; j < GMAX; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[j][k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const double* p = part + (size_t)b * GMAX * KP;
+#pragma unroll
+      for (int j = 0; j < GMAX; ++j)
+        if (j < ns)
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[j][k] += p[j * KP + k];
+    }
+  }
+  __device__ __forceinline__ void reduce(int ns, double (&tot)[GMAX][K], double* sh) const {
+    double flat[GMAX * K], out[GMAX * K];
+#pragma unroll
+    for (int j = 0; j < GMAX; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) flat[j * K + k] = j < ns ? v[j][k] : 0.0;
+    block_sum_n<GMAX * K>(flat, out, sh);
+#pragma unroll
+    for (int j = 0; j < GMAX; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) tot[j][k] = out[j * K + k];
+  }
+};
+
+// Block-reduce acc[j][k] and store them as this block's partials.
+template <int K>
+__device__ __forceinline__ void store_partials(const double (&acc)[GMAX][K], int ns, double* part,
+                                               int lb, double* sh) {
+  double flat[GMAX * K], out[GMAX * K];
+#pragma unroll
+  for (int j = 0; j < GMAX; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) flat[j * K + k] = acc[j][k];
+  block_sum_n<GMAX * K>(flat, out, sh);
+  if (threadIdx.x < GMAX * K) {
+    const int j = threadIdx.x / K, k = threadIdx.x % K;
+    double val = 0.0;
+#pragma unroll
+    for (int q = 0; q < GMAX * K; ++q) val = (q == (int)threadIdx.x) ? out[q] : val;
+    if (j < ns) part[((size_t)lb * GMAX + j) * KP + k] = val;
+  }
 }
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }

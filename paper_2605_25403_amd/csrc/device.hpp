@@ -7,10 +7,12 @@
 
 namespace ipcs {
 
-constexpr int BLOCK = 256;        // threads per block of the Krylov/vector kernels
-constexpr int KPART = 4;          // partial sums per block per Krylov system
+constexpr int BLOCK = 256;        // threads per block of small utility kernels
+constexpr int KBLOCK_MAX = 1024;  // largest Krylov block (threads = rows / vector entries)
+constexpr int KP = 4;             // partial sums per system per block
+constexpr int GMAX = 3;           // systems per group (velocity components)
 
-// Krylov system status (device-resident, read by the host every few iterations)
+// Krylov system status (device-resident, polled by the host every few iterations)
 enum KStatus : int32_t {
   KS_RUN = 0,        // iterating
   KS_PENDING = 1,    // recursive residual converged (or maxit): confirm with b - A x
@@ -22,43 +24,55 @@ enum KStatus : int32_t {
   KS_NONFINITE = -6
 };
 
+// Scalars of one Krylov system. Between kernels of one iteration they are
+// passed through these fields; a field is only written by block 0 of a kernel
+// in which no other block reads it (rho is double-buffered by iteration parity).
 struct KState {
-  double bb, rr;              // ||b||^2, ||r||^2 (recursive, or true after a check)
-  double rho, rho_old;        // PCG: r.z; BiCGStab: rhat.r (new) and previous
-  double alpha, beta, omega;
+  double bb, rr;              // ||b||^2, last ||r||^2
+  double rho[2];              // PCG r.z / BiCGStab rhat.r, by iteration parity
+  double alpha, omega;
   double tol2;                // tol^2
-  int32_t status, it, maxit, pc;   // pc: current PCG direction buffer (0/1)
-  int32_t tt_zero, nchecks, pad0, pad1;
+  int32_t status, it, it0, maxit;   // it0: iteration of the last (re)start
+  int32_t par, tt_zero, nchecks, pad;
 };
 
-// One linear system A x = b with its Krylov work vectors. A is CSR with
-// int32 indices and FP64 values; vectors are FP64.
-struct KSys {
-  const int32_t* rowptr;
-  const int32_t* col;
-  const double* val;
-  const double* dinv;         // Jacobi: 1 / diag(A)
+// Vectors of one system (FP64). PCG: r, z, p[0..1] (by parity), q = A p.
+// BiCGStab: r, z = rhat, p[0] = p, q = v, s, t, phat, shat.
+struct KVecs {
   const double* b;
   double* x;
   double* r;
-  double* z;                  // PCG z; BiCGStab rhat
-  double* p[2];               // PCG direction (double buffered); BiCGStab p = p[0]
-  double* q;                  // PCG A p; BiCGStab v
-  double* s;                  // BiCGStab
+  double* z;
+  double* p[2];
+  double* q;
+  double* s;
   double* t;
   double* phat;
   double* shat;
   KState* st;
-  double* part;               // [nblk][KPART]
-  uint32_t* cnt;              // last-block arrival counter (left at 0)
-  int32_t n;
+};
+
+// Up to GMAX systems that share one matrix (SELL-64 layout, FP64 values), so
+// the matrix is read once per row for all of them. Every Krylov kernel of a
+// group runs nblk = ceil(n / bs) blocks of the launch's block size bs, one
+// row or vector entry per thread.
+struct KGroup {
+  int32_t nsys, n;
+  const int32_t* sptr;        // SELL slice offsets
+  const int32_t* col;
+  const double* val;
+  const double* dinv;         // Jacobi: 1 / diag(A)
   int32_t nblk;
+  int32_t pad;
+  double* part_m;             // [nblk][GMAX][KP] partials of matrix kernels
+  double* part_v;             // [nblk][GMAX][KP] partials of vector kernels
+  KVecs v[GMAX];
 };
 
 // Row-owner assembly inputs (see mesh.hpp)
 struct RowAsm {
   int32_t nrows;
-  const int32_t* rowptr;      // CSR pattern of the output matrices
+  const int32_t* sptr;        // SELL-64 slice offsets of the output matrices
   const int32_t* inc_ptr;
   const int32_t* inc;         // cell << 4 | local row index
   const uint8_t* slot;
@@ -87,22 +101,33 @@ void asm_kp(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w);
 void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, const double* fq,
                  int64_t nc, double t, double* F, int64_t n2);
-void form_eliminated(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
-                     const uint8_t* bmask, const double* M, const double* K, double cm,
-                     double ck, double* out, double* dinv);
-void inv_diagonal(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
-                  const double* val, double* dinv);
+// SELL-64 matrices: sptr/col layout, rowptr gives the true row lengths
+void form_eliminated(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
+                     const int32_t* col, const uint8_t* bmask, const double* M, const double* K,
+                     double cm, double ck, double* out, double* dinv);
+void inv_diagonal(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
+                  const int32_t* col, const double* val, double* dinv);
 void lift_values(hipStream_t s, int64_t nlift, const int32_t* slot, const double* M,
                  const double* K, double cm, double ck, double* out);
 
-// Krylov (kernels_krylov.hip). G = lanes per CSR row.
-void pcg_init(hipStream_t s, int G, const KSys* sys, const int2* bmap, int nblocks, int mode);
-void pcg_iter(hipStream_t s, int G, const KSys* sys, const int2* bmap, int nblocks);
-void bicg_init(hipStream_t s, int G, const KSys* sys, const int2* bmap, int nblocks, int mode);
-void bicg_iter(hipStream_t s, int G, const KSys* sys, const int2* bmap, int nblocks);
-void ksys_zero(hipStream_t s, const KSys* sys, const int2* bmap, int nblocks);
-// out[i] = *sys[i].st for i < n (one contiguous copy the host can fetch at once)
-void gather_states(hipStream_t s, const KSys* sys, int n, KState* out);
+// Krylov (kernels_krylov.hip): ngroups groups, bmap[nblocks] = (group, block)
+struct KLaunch {
+  const KGroup* groups;
+  int ngroups;
+  const int2* bmap;
+  int nblocks;
+  int bs;            // threads per block: 256, 512 or 1024
+};
+void pcg_start(hipStream_t s, const KLaunch& L, int mode);    // mode 0 start, 1 confirm
+void pcg_iter(hipStream_t s, const KLaunch& L);
+void bicg_start(hipStream_t s, const KLaunch& L, int mode);
+void bicg_iter(hipStream_t s, const KLaunch& L);
+void ksys_finish(hipStream_t s, const KLaunch& L);            // b == 0 systems: x := 0
+void gather_states(hipStream_t s, const KLaunch& L, KState* out);   // out[g*GMAX + j]
+// single kernels of an iteration, for timing
+void pcg_spmv_only(hipStream_t s, const KLaunch& L);
+void pcg_update_only(hipStream_t s, const KLaunch& L);
+void bicg_spmv_only(hipStream_t s, const KLaunch& L);
 
 // Fields and right-hand sides (kernels_fields.hip)
 void eval_velocity(hipStream_t s, int dim, const Builtin& bi, const double* x, int64_t n,
@@ -115,23 +140,25 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
-void rhs_momentum(hipStream_t s, int dim, int G, int64_t n2, const int32_t* rp22,
-                  const int32_t* col22, const double* E, const double* U, const int32_t* rp21,
+void rhs_momentum(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
+                  const int32_t* col22, const double* E, const double* U, const int32_t* sp21,
                   const int32_t* col21, double* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b);
-void rhs_pressure(hipStream_t s, int dim, int G, int64_t n1, const int32_t* rp12,
+// r = scale * sum_c D_c Us_c, then r -= mean(r) (mean_out receives it)
+void rhs_pressure(hipStream_t s, int dim, int64_t n1, const int32_t* sp12,
                   const int32_t* col12, double* const* Dc, const double* Us, int64_t n2,
                   double scale, double* r, double* part, uint32_t* cnt, double* mean_out);
 void sub_scalar(hipStream_t s, int64_t n, const double* scal, double* v);
-void rhs_correction(hipStream_t s, int dim, int G, int64_t n2, const int32_t* rp22,
+void rhs_correction(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
                     const int32_t* col22, const double* M, const double* Us,
-                    const int32_t* rp21, const int32_t* col21, double* const* Gc,
+                    const int32_t* sp21, const int32_t* col21, double* const* Gc,
                     const double* dP, double scale, const int32_t* lift_ptr,
                     const int32_t* lift_col, const double* liftM, const uint8_t* bmask,
                     const double* gfull, double* b);
-void weighted_mean(hipStream_t s, int64_t n, const double* w, const double* v, double* part,
-                   uint32_t* cnt, double* out);   // out = (w.v)/(sum w)
+// v -= (w.v)/(sum w); out receives the subtracted mean
+void sub_weighted_mean(hipStream_t s, int64_t n, const double* w, double* v, double* part,
+                       double* out);
 void axpy_inplace(hipStream_t s, int64_t n, double a, const double* x, double* y);
 
 }  // namespace ipcs

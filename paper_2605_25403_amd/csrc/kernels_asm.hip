@@ -1,12 +1,12 @@
 // Cell-quadrature assembly kernels for gfx950 (row-owner, conflict-free).
 //
-// Each thread owns one CSR row (a P2 or P1 DOF). It walks the cells incident to
-// its DOF, evaluates that cell's local matrix row by the degree-5 rule
-// (reference basis values are compile-time constants folded into the code) and
-// adds it into the row's slots, which live in LDS in the same packed layout as
-// the CSR value array. After a barrier the block writes its rows back with
-// coalesced stores. No value is written by two threads, so there are no
-// atomics and the result is deterministic.
+// Each thread owns one matrix row (a P2 or P1 DOF). It walks the cells incident
+// to its DOF, evaluates that cell's local matrix row by the degree-5 rule
+// (reference tables in constant memory) and adds it into the row's slots,
+// which live in LDS in the same SELL-64 layout as the value array. After a
+// barrier the block writes its slices back with coalesced stores. No value is
+// written by two threads, so there are no atomics and the result is
+// deterministic.
 //
 // Local matrices (Section 2.2.1, weak forms of eq. (9)), on a cell K with affine
 // map x = x0 + J xi, gradients grad phi = J^{-T} grad_ref phi:
@@ -117,27 +117,31 @@ __device__ __forceinline__ void phys(const Geo<D>& g, const double* gr, double* 
 
 // ------------------------------------------------------------------ ops
 // Each op fills v[NOUT][NCOL] = the local row li of NOUT matrices.
-template <int D>
-struct OpMassStiff {   // P2 x P2: M and K
-  static constexpr int NOUT = 2, NCOL = P2<D>::NLOC;
+template <int D, int WHICH>
+struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
   __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
                              double (&v)[NOUT][NCOL]) const {
     const Tab<D>& T = tab<D>();
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
       const double wq = T.w[q] * g.det;
-      const double phi_i = T.phi[q][li];
-      double gi[D];
-      phys<D>(g, T.dphi[q][li], gi);
+      if (WHICH == 0) {
+        const double ci = wq * T.phi[q][li];
 #pragma unroll
-      for (int j = 0; j < NCOL; ++j) {
-        double gj[D];
-        phys<D>(g, T.dphi[q][j], gj);
-        double s = 0.0;
+        for (int j = 0; j < NCOL; ++j) v[0][j] += ci * T.phi[q][j];
+      } else {
+        double gi[D];
+        phys<D>(g, T.dphi[q][li], gi);
 #pragma unroll
-        for (int b = 0; b < D; ++b) s += gi[b] * gj[b];
-        v[0][j] += wq * phi_i * T.phi[q][j];
-        v[1][j] += wq * s;
+        for (int j = 0; j < NCOL; ++j) {
+          double gj[D];
+          phys<D>(g, T.dphi[q][j], gj);
+          double s = 0.0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) s += gi[b] * gj[b];
+          v[0][j] += wq * s;
+        }
       }
     }
   }
@@ -188,8 +192,9 @@ struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
 };
 
 template <int D>
-struct OpGrad {   // P2 rows x P1 cols: G_c, c < D
-  static constexpr int NOUT = D, NCOL = D + 1;
+struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
+  static constexpr int NOUT = 1, NCOL = D + 1;
+  int c;
   __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
                              double (&v)[NOUT][NCOL]) const {
     const Tab<D>& T = tab<D>();
@@ -203,15 +208,18 @@ struct OpGrad {   // P2 rows x P1 cols: G_c, c < D
 #pragma unroll
       for (int a = 0; a < D; ++a) gr[a] = P2<D>::template dlam<double>(k, a);
       phys<D>(g, gr, gp);
+      double gc = gp[0];
 #pragma unroll
-      for (int c = 0; c < D; ++c) v[c][k] += int_phi * gp[c];
+      for (int cc = 1; cc < D; ++cc) gc = (c == cc) ? gp[cc] : gc;
+      v[0][k] += int_phi * gc;
     }
   }
 };
 
 template <int D>
-struct OpDiv {   // P1 rows x P2 cols: D_c, c < D
-  static constexpr int NOUT = D, NCOL = P2<D>::NLOC;
+struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
+  int c;
   __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
                              double (&v)[NOUT][NCOL]) const {
     const Tab<D>& T = tab<D>();
@@ -222,8 +230,10 @@ struct OpDiv {   // P1 rows x P2 cols: D_c, c < D
       for (int j = 0; j < NCOL; ++j) {
         double gp[D];
         phys<D>(g, T.dphi[q][j], gp);
+        double gc = gp[0];
 #pragma unroll
-        for (int c = 0; c < D; ++c) v[c][j] += ci * gp[c];
+        for (int cc = 1; cc < D; ++cc) gc = (c == cc) ? gp[cc] : gc;
+        v[0][j] += ci * gc;
       }
     }
   }
@@ -262,19 +272,23 @@ struct OpKp {   // P1 x P1 stiffness
 };
 
 // ------------------------------------------------------------------ kernel
+// One thread per output row; the block owns whole SELL-64 slices (blockDim a
+// multiple of 64), accumulates their values in LDS in the SELL layout and
+// writes them back as one contiguous, coalesced range.
 template <int D, class Op>
 __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
   extern __shared__ double lds[];
   constexpr int NOUT = Op::NOUT, NCOL = Op::NCOL;
   const int r0 = blockIdx.x * blockDim.x;
-  const int rend = min(r0 + (int)blockDim.x, a.nrows);
-  const int base = a.rowptr[r0];
-  const int bnnz = a.rowptr[rend] - base;
-  for (int k = threadIdx.x; k < NOUT * bnnz; k += blockDim.x) lds[k] = 0.0;
+  const int s0 = r0 >> 6;
+  const int s1 = min((r0 + (int)blockDim.x + 63) >> 6, (a.nrows + 63) >> 6);
+  const int base = a.sptr[s0];
+  const int bent = a.sptr[s1] - base;
+  for (int k = threadIdx.x; k < NOUT * bent; k += blockDim.x) lds[k] = 0.0;
   __syncthreads();
   const int row = r0 + threadIdx.x;
   if (row < a.nrows) {
-    const int off = a.rowptr[row] - base;
+    const int off = a.sptr[row >> 6] - base + (row & 63);
     for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
       const int code = a.inc[p];
       const int cell = code >> 4, li = code & 15;
@@ -292,16 +306,16 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
       const uint8_t* sl = a.slot + (size_t)p * a.stride;
 #pragma unroll
       for (int j = 0; j < NCOL; ++j) {
-        const int s = off + sl[j];
+        const int s = off + 64 * sl[j];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) lds[o * bnnz + s] += v[o][j];
+        for (int o = 0; o < NOUT; ++o) lds[o * bent + s] += v[o][j];
       }
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < bnnz; k += blockDim.x)
+  for (int k = threadIdx.x; k < bent; k += blockDim.x)
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) a.out[o][base + k] = lds[o * bnnz + k];
+    for (int o = 0; o < NOUT; ++o) a.out[o][base + k] = lds[o * bent + k];
 }
 
 template <int D, class Op>
@@ -312,22 +326,40 @@ static void launch_rows(hipStream_t s, const RowAsm& a, const Op& op, int bs, si
   HIP_LAUNCH_OK();
 }
 
+// a.out[0] <- M, a.out[1] <- K
 void asm_mass_stiff(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
-  if (dim == 2) launch_rows<2>(s, a, OpMassStiff<2>{}, bs, lds);
-  else launch_rows<3>(s, a, OpMassStiff<3>{}, bs, lds);
+  RowAsm am = a, ak = a;
+  ak.out[0] = a.out[1];
+  if (dim == 2) {
+    launch_rows<2>(s, am, OpMassStiff<2, 0>{}, bs, lds);
+    launch_rows<2>(s, ak, OpMassStiff<2, 1>{}, bs, lds);
+  } else {
+    launch_rows<3>(s, am, OpMassStiff<3, 0>{}, bs, lds);
+    launch_rows<3>(s, ak, OpMassStiff<3, 1>{}, bs, lds);
+  }
 }
 void asm_conv_explicit(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                        const double* U, int64_t n2, double inv_dt) {
   if (dim == 2) launch_rows<2>(s, a, OpConvExplicit<2>{U, n2, inv_dt}, bs, lds);
   else launch_rows<3>(s, a, OpConvExplicit<3>{U, n2, inv_dt}, bs, lds);
 }
+// a.out[c] <- G_c (one launch per component)
 void asm_grad(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
-  if (dim == 2) launch_rows<2>(s, a, OpGrad<2>{}, bs, lds);
-  else launch_rows<3>(s, a, OpGrad<3>{}, bs, lds);
+  for (int c = 0; c < dim; ++c) {
+    RowAsm ac = a;
+    ac.out[0] = a.out[c];
+    if (dim == 2) launch_rows<2>(s, ac, OpGrad<2>{c}, bs, lds);
+    else launch_rows<3>(s, ac, OpGrad<3>{c}, bs, lds);
+  }
 }
+// a.out[c] <- D_c
 void asm_div(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
-  if (dim == 2) launch_rows<2>(s, a, OpDiv<2>{}, bs, lds);
-  else launch_rows<3>(s, a, OpDiv<3>{}, bs, lds);
+  for (int c = 0; c < dim; ++c) {
+    RowAsm ac = a;
+    ac.out[0] = a.out[c];
+    if (dim == 2) launch_rows<2>(s, ac, OpDiv<2>{c}, bs, lds);
+    else launch_rows<3>(s, ac, OpDiv<3>{c}, bs, lds);
+  }
 }
 void asm_kp(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   if (dim == 2) launch_rows<2>(s, a, OpKp<2>{}, bs, lds);
@@ -415,48 +447,55 @@ void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, con
 
 // ------------------------------------------------------------------ elimination
 // out = cm*M + ck*K with Dirichlet rows and columns eliminated (zero, unit
-// diagonal on boundary rows); dinv = 1/diag(out). One thread per row.
-__global__ void __launch_bounds__(256) k_form_elim(int64_t n, const int32_t* rowptr,
-                                                   const int32_t* col, const uint8_t* bmask,
-                                                   const double* M, const double* K, double cm,
-                                                   double ck, double* out, double* dinv) {
+// diagonal on boundary rows); dinv = 1/diag(out). One thread per row, SELL-64
+// layout; padding entries are left untouched (zero).
+__global__ void __launch_bounds__(256) k_form_elim(int64_t n, const int32_t* sptr,
+                                                   const int32_t* rowptr, const int32_t* col,
+                                                   const uint8_t* bmask, const double* M,
+                                                   const double* K, double cm, double ck,
+                                                   double* out, double* dinv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const bool bi = bmask[i];
+  const int len = rowptr[i + 1] - rowptr[i];
+  const int base = sptr[i >> 6] + (int)(i & 63);
   double diag = 1.0;
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const int j = col[k];
+  for (int k = 0; k < len; ++k) {
+    const int idx = base + 64 * k;
+    const int j = col[idx];
     double v;
     if (bi || bmask[j]) v = (j == i) ? 1.0 : 0.0;
-    else v = cm * M[k] + (K ? ck * K[k] : 0.0);
-    out[k] = v;
+    else v = cm * M[idx] + (K ? ck * K[idx] : 0.0);
+    out[idx] = v;
     if (j == i) diag = v;
   }
   dinv[i] = 1.0 / diag;
 }
 
-void form_eliminated(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
-                     const uint8_t* bmask, const double* M, const double* K, double cm,
-                     double ck, double* out, double* dinv) {
-  hipLaunchKernelGGL(k_form_elim, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, rowptr,
-                     col, bmask, M, K, cm, ck, out, dinv);
+void form_eliminated(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
+                     const int32_t* col, const uint8_t* bmask, const double* M, const double* K,
+                     double cm, double ck, double* out, double* dinv) {
+  hipLaunchKernelGGL(k_form_elim, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, sptr,
+                     rowptr, col, bmask, M, K, cm, ck, out, dinv);
   HIP_LAUNCH_OK();
 }
 
-__global__ void k_inv_diag(int64_t n, const int32_t* rowptr, const int32_t* col,
-                           const double* val, double* dinv) {
+__global__ void k_inv_diag(int64_t n, const int32_t* sptr, const int32_t* rowptr,
+                           const int32_t* col, const double* val, double* dinv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int len = rowptr[i + 1] - rowptr[i];
+  const int base = sptr[i >> 6] + (int)(i & 63);
   double d = 0.0;
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
-    if (col[k] == i) d = val[k];
+  for (int k = 0; k < len; ++k)
+    if (col[base + 64 * k] == i) d = val[base + 64 * k];
   dinv[i] = 1.0 / d;
 }
 
-void inv_diagonal(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col,
-                  const double* val, double* dinv) {
-  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, rowptr, col,
-                     val, dinv);
+void inv_diagonal(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
+                  const int32_t* col, const double* val, double* dinv) {
+  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, sptr,
+                     rowptr, col, val, dinv);
   HIP_LAUNCH_OK();
 }
 

@@ -120,163 +120,144 @@ struct Ptrs3 {
 };
 
 // b_c[i] = sum_j A[ij] X_c[j] - sc * sum_k Gc[ik] Y[k] + F_c[i] - sum lift[i] g_c
-// on interior rows; g_c[i] on boundary rows. One lane group per row.
-template <int D, int G>
-__global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* rp22,
+// on interior rows; g_c[i] on boundary rows. One thread per row, both matrices
+// in SELL-64 layout (coalesced value and column loads across the wavefront).
+template <int D>
+__global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
                                                 const int32_t* col22, const double* A,
-                                                const double* X, const int32_t* rp21,
+                                                const double* X, const int32_t* sp21,
                                                 const int32_t* col21, Ptrs3 Gc, const double* Y,
                                                 double sc, const double* F,
                                                 const int32_t* lift_ptr, const int32_t* lift_col,
                                                 const double* lift, const uint8_t* bmask,
                                                 const double* g, double* b) {
-  const int lane = threadIdx.x % G;
-  const int64_t grp0 = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
-  const int64_t ngrp = (int64_t)gridDim.x * (256 / G);
-  for (int64_t i = grp0; i < n2; i += ngrp) {
-    if (bmask[i]) {
-      if (lane == 0)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  if (bmask[i]) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) b[c * n2 + i] = g[c * n2 + i];
-      continue;
-    }
-    double s[D];
+    for (int c = 0; c < D; ++c) b[c * n2 + i] = g[c * n2 + i];
+    return;
+  }
+  double s[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) s[c] = 0.0;
-    for (int k = rp22[i] + lane; k < rp22[i + 1]; k += G) {
-      const double a = A[k];
-      const int j = col22[k];
+  for (int c = 0; c < D; ++c) s[c] = 0.0;
+  {
+    const int sl = (int)(i >> 6), b0 = sp22[sl], w = (sp22[sl + 1] - b0) >> 6;
+    const int base = b0 + (int)(i & 63);
+    for (int k = 0; k < w; ++k) {
+      const double a = A[base + 64 * k];
+      const int j = col22[base + 64 * k];
 #pragma unroll
       for (int c = 0; c < D; ++c) s[c] += a * X[c * n2 + j];
     }
-    for (int k = rp21[i] + lane; k < rp21[i + 1]; k += G) {
-      const double y = Y[col21[k]];
+  }
+  {
+    const int sl = (int)(i >> 6), b0 = sp21[sl], w = (sp21[sl + 1] - b0) >> 6;
+    const int base = b0 + (int)(i & 63);
+    for (int k = 0; k < w; ++k) {
+      const double y = Y[col21[base + 64 * k]];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s[c] -= sc * (Gc.p[c][k] * y);
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c) s[c] = group_sum<G>(s[c]);
-    if (lane == 0) {
-      for (int e = lift_ptr[i]; e < lift_ptr[i + 1]; ++e) {
-        const double l = lift[e];
-        const int j = lift_col[e];
-#pragma unroll
-        for (int c = 0; c < D; ++c) s[c] -= l * g[c * n2 + j];
-      }
-#pragma unroll
-      for (int c = 0; c < D; ++c) b[c * n2 + i] = s[c] + (F ? F[c * n2 + i] : 0.0);
+      for (int c = 0; c < D; ++c) s[c] -= sc * (Gc.p[c][base + 64 * k] * y);
     }
   }
-}
-
-template <int D>
-static void launch_rhs_p2(hipStream_t s, int G, int64_t n2, const int32_t* rp22,
-                          const int32_t* col22, const double* A, const double* X,
-                          const int32_t* rp21, const int32_t* col21, Ptrs3 Gc, const double* Y,
-                          double sc, const double* F, const int32_t* lp, const int32_t* lc,
-                          const double* lv, const uint8_t* bm, const double* g, double* b) {
-  const int nb = grid_for(n2, 256 / G);
-#define RHS_CASE(GG)                                                                            \
-  case GG:                                                                                      \
-    hipLaunchKernelGGL((k_rhs_p2<D, GG>), dim3(nb), dim3(256), 0, s, n2, rp22, col22, A, X, rp21, \
-                       col21, Gc, Y, sc, F, lp, lc, lv, bm, g, b);                              \
-    break;
-  switch (G) {
-    RHS_CASE(4)
-    RHS_CASE(8)
-    RHS_CASE(16)
-    RHS_CASE(32)
-    RHS_CASE(64)
-    default: fail(IPCS_E_INVALID, "unsupported lane group");
+  for (int e = lift_ptr[i]; e < lift_ptr[i + 1]; ++e) {
+    const double l = lift[e];
+    const int j = lift_col[e];
+#pragma unroll
+    for (int c = 0; c < D; ++c) s[c] -= l * g[c * n2 + j];
   }
-#undef RHS_CASE
-  HIP_LAUNCH_OK();
+#pragma unroll
+  for (int c = 0; c < D; ++c) b[c * n2 + i] = s[c] + (F ? F[c * n2 + i] : 0.0);
 }
 
-void rhs_momentum(hipStream_t s, int dim, int G, int64_t n2, const int32_t* rp22,
-                  const int32_t* col22, const double* E, const double* U, const int32_t* rp21,
+void rhs_momentum(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
+                  const int32_t* col22, const double* E, const double* U, const int32_t* sp21,
                   const int32_t* col21, double* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b) {
   Ptrs3 gp{{Gc[0], Gc[1], dim == 3 ? Gc[2] : nullptr}};
+  const unsigned nb = (unsigned)div_up(n2, 256);
   if (dim == 2)
-    launch_rhs_p2<2>(s, G, n2, rp22, col22, E, U, rp21, col21, gp, P, 1.0, F, lift_ptr, lift_col,
-                     liftA, bmask, gfull, b);
+    hipLaunchKernelGGL(k_rhs_p2<2>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, E, U, sp21, col21,
+                       gp, P, 1.0, F, lift_ptr, lift_col, liftA, bmask, gfull, b);
   else
-    launch_rhs_p2<3>(s, G, n2, rp22, col22, E, U, rp21, col21, gp, P, 1.0, F, lift_ptr, lift_col,
-                     liftA, bmask, gfull, b);
+    hipLaunchKernelGGL(k_rhs_p2<3>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, E, U, sp21, col21,
+                       gp, P, 1.0, F, lift_ptr, lift_col, liftA, bmask, gfull, b);
+  HIP_LAUNCH_OK();
 }
 
-void rhs_correction(hipStream_t s, int dim, int G, int64_t n2, const int32_t* rp22,
+void rhs_correction(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
                     const int32_t* col22, const double* M, const double* Us,
-                    const int32_t* rp21, const int32_t* col21, double* const* Gc,
+                    const int32_t* sp21, const int32_t* col21, double* const* Gc,
                     const double* dP, double scale, const int32_t* lift_ptr,
                     const int32_t* lift_col, const double* liftM, const uint8_t* bmask,
                     const double* gfull, double* b) {
   Ptrs3 gp{{Gc[0], Gc[1], dim == 3 ? Gc[2] : nullptr}};
+  const unsigned nb = (unsigned)div_up(n2, 256);
   if (dim == 2)
-    launch_rhs_p2<2>(s, G, n2, rp22, col22, M, Us, rp21, col21, gp, dP, scale, nullptr, lift_ptr,
-                     lift_col, liftM, bmask, gfull, b);
+    hipLaunchKernelGGL(k_rhs_p2<2>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, M, Us, sp21,
+                       col21, gp, dP, scale, nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
   else
-    launch_rhs_p2<3>(s, G, n2, rp22, col22, M, Us, rp21, col21, gp, dP, scale, nullptr, lift_ptr,
-                     lift_col, liftM, bmask, gfull, b);
+    hipLaunchKernelGGL(k_rhs_p2<3>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, M, Us, sp21,
+                       col21, gp, dP, scale, nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
+  HIP_LAUNCH_OK();
 }
 
-// r[k] = scale * sum_c sum_j D_c[kj] Us_c[j]; mean_out = sum(r)/n1 (deterministic)
-template <int D, int G>
-__global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t* rp,
+// r[k] = scale * sum_c sum_j D_c[kj] Us_c[j] (SELL-64, one thread per row) and
+// per-block partial sums of r; k_sub_mean finishes the mean and subtracts it.
+template <int D>
+__global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t* sp,
                                                       const int32_t* col, Ptrs3 Dc,
                                                       const double* Us, int64_t n2, double scale,
-                                                      double* r, double* part, uint32_t* cnt,
-                                                      double* mean_out) {
-  const int lane = threadIdx.x % G;
-  const int64_t grp0 = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
-  const int64_t ngrp = (int64_t)gridDim.x * (256 / G);
-  double acc = 0.0;
-  for (int64_t k = grp0; k < n1; k += ngrp) {
+                                                      double* r, double* part) {
+  __shared__ double sh[16];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (k < n1) {
+    const int sl = (int)(k >> 6), b0 = sp[sl], w = (sp[sl + 1] - b0) >> 6;
+    const int base = b0 + (int)(k & 63);
     double s = 0.0;
-    for (int e = rp[k] + lane; e < rp[k + 1]; e += G) {
-      const int j = col[e];
+    for (int e = 0; e < w; ++e) {
+      const int j = col[base + 64 * e];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s += Dc.p[c][e] * Us[c * n2 + j];
+      for (int c = 0; c < D; ++c) s += Dc.p[c][base + 64 * e] * Us[c * n2 + j];
     }
-    s = group_sum<G>(s);
-    if (lane == 0) {
-      const double v = scale * s;
-      r[k] = v;
-      acc += v;
-    }
+    v = scale * s;
+    r[k] = v;
   }
-  const double v[1] = {acc};
-  double tot[1];
-  if (reduce_last<1>(v, part, cnt, gridDim.x, blockIdx.x, tot) && threadIdx.x == 0)
-    *mean_out = tot[0] / (double)n1;
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-void rhs_pressure(hipStream_t s, int dim, int G, int64_t n1, const int32_t* rp12,
+// v -= (sum of nb partials) / n, every block reducing the partials itself
+__global__ void __launch_bounds__(256) k_sub_mean(int64_t n, int nb, const double* part,
+                                                  double* v, double* mean_out) {
+  __shared__ double sh[16];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) a += part[b];
+  const double mean = block_sum(a, sh) / (double)n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mean_out = mean;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] -= mean;
+}
+
+void rhs_pressure(hipStream_t s, int dim, int64_t n1, const int32_t* sp12,
                   const int32_t* col12, double* const* Dc, const double* Us, int64_t n2,
                   double scale, double* r, double* part, uint32_t* cnt, double* mean_out) {
+  (void)cnt;
   Ptrs3 dp{{Dc[0], Dc[1], dim == 3 ? Dc[2] : nullptr}};
-  const int nb = (int)std::min<int64_t>(div_up(n1, 256 / G), 1024);
-#define RP_CASE(DD, GG)                                                                      \
-  hipLaunchKernelGGL((k_rhs_pressure<DD, GG>), dim3(nb), dim3(256), 0, s, n1, rp12, col12, dp, \
-                     Us, n2, scale, r, part, cnt, mean_out)
-  if (dim == 2) {
-    switch (G) {
-      case 8: RP_CASE(2, 8); break;
-      case 16: RP_CASE(2, 16); break;
-      case 32: RP_CASE(2, 32); break;
-      default: RP_CASE(2, 64); break;
-    }
-  } else {
-    switch (G) {
-      case 8: RP_CASE(3, 8); break;
-      case 16: RP_CASE(3, 16); break;
-      case 32: RP_CASE(3, 32); break;
-      default: RP_CASE(3, 64); break;
-    }
-  }
-#undef RP_CASE
+  const int nb = (int)div_up(n1, 256);
+  if (nb > 8192) fail(IPCS_E_INVALID, "pressure space too large for the partial buffer");
+  if (dim == 2)
+    hipLaunchKernelGGL(k_rhs_pressure<2>, dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp, Us, n2,
+                       scale, r, part);
+  else
+    hipLaunchKernelGGL(k_rhs_pressure<3>, dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp, Us, n2,
+                       scale, r, part);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n1, 256)), dim3(256), 0, s, n1, nb, part, r,
+                     mean_out);
   HIP_LAUNCH_OK();
 }
 
@@ -292,26 +273,46 @@ void sub_scalar(hipStream_t s, int64_t n, const double* scal, double* v) {
   HIP_LAUNCH_OK();
 }
 
-// out = (w . v) / (sum w), deterministic
-__global__ void __launch_bounds__(256) k_weighted_mean(int64_t n, const double* w,
-                                                       const double* v, double* part,
-                                                       uint32_t* cnt, double* out) {
+// (w . v) / (sum w): per-block partials, then every block of the consumer
+// re-reduces them; the consumer subtracts the mean from v.
+__global__ void __launch_bounds__(256) k_wdot_part(int64_t n, const double* w, const double* v,
+                                                   double* part) {
+  __shared__ double sh[16];
   double a = 0.0, b = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     a += w[i] * v[i];
     b += w[i];
   }
-  const double x[2] = {a, b};
-  double tot[2];
-  if (reduce_last<2>(x, part, cnt, gridDim.x, blockIdx.x, tot) && threadIdx.x == 0)
-    *out = tot[0] / tot[1];
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
 }
 
-void weighted_mean(hipStream_t s, int64_t n, const double* w, const double* v, double* part,
-                   uint32_t* cnt, double* out) {
+__global__ void __launch_bounds__(256) k_sub_wmean(int64_t n, int nb, const double* part,
+                                                   double* v, double* out) {
+  __shared__ double sh[16];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  const double mean = block_sum(a, sh) / block_sum(b, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = mean;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] -= mean;
+}
+
+void sub_weighted_mean(hipStream_t s, int64_t n, const double* w, double* v, double* part,
+                       double* out) {
   const int nb = (int)std::min<int64_t>(div_up(n, 256), 1024);
-  hipLaunchKernelGGL(k_weighted_mean, dim3(nb), dim3(256), 0, s, n, w, v, part, cnt, out);
+  hipLaunchKernelGGL(k_wdot_part, dim3(nb), dim3(256), 0, s, n, w, v, part);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sub_wmean, dim3(grid_for(n, 256)), dim3(256), 0, s, n, nb, part, v, out);
   HIP_LAUNCH_OK();
 }
 

@@ -23,7 +23,46 @@ const Pattern& Mesh::pattern(int which) const {
   fail(IPCS_E_INVALID, "unknown pattern id " + std::to_string(which));
 }
 
+const Sell& Mesh::sell(int which) const {
+  switch (which) {
+    case IPCS_PATTERN_P2P2: return e22;
+    case IPCS_PATTERN_P1P1: return e11;
+    case IPCS_PATTERN_P1P2: return e12;
+    case IPCS_PATTERN_P2P1: return e21;
+  }
+  fail(IPCS_E_INVALID, "unknown pattern id " + std::to_string(which));
+}
+
 namespace {
+
+void build_sell(const Pattern& P, Sell& S) {
+  S.nrows = P.nrows;
+  S.nslices = (P.nrows + 63) / 64;
+  S.sptr.assign(S.nslices + 1, 0);
+  S.maxw = 0;
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    int w = 0;
+    for (int64_t r = 64 * s; r < std::min<int64_t>(P.nrows, 64 * s + 64); ++r)
+      w = std::max(w, P.rowptr[r + 1] - P.rowptr[r]);
+    S.maxw = std::max(S.maxw, w);
+    const int64_t next = (int64_t)S.sptr[s] + 64ll * w;
+    if (next >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "SELL layout exceeds 2^31 entries");
+    S.sptr[s + 1] = int32_t(next);
+  }
+  S.nent = S.sptr[S.nslices];
+  S.col.assign(S.nent, 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    const int w = (S.sptr[s + 1] - S.sptr[s]) / 64;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int64_t r = 64 * s + lane;
+      const int len = r < P.nrows ? P.rowptr[r + 1] - P.rowptr[r] : 0;
+      const int32_t pad = len > 0 ? P.col[P.rowptr[r] + len - 1] : 0;
+      for (int k = 0; k < w; ++k)
+        S.col[S.sptr[s] + 64ll * k + lane] = k < len ? P.col[P.rowptr[r] + k] : pad;
+    }
+  }
+}
 
 inline int edge_a(int dim, int e) { return dim == 2 ? Edges<2>::a(e) : Edges<3>::a(e); }
 inline int edge_b(int dim, int e) { return dim == 2 ? Edges<2>::b(e) : Edges<3>::b(e); }
@@ -212,6 +251,10 @@ void finalize(Mesh& m) {
   build_slots(m.inc2, m.c2d, m.nloc2, m.nloc1, m.p21, m.s21);
   build_slots(m.inc1, m.c2d, m.nloc2, m.nloc1, m.p11, m.s11);
   build_slots(m.inc1, m.c2d, m.nloc2, m.nloc2, m.p12, m.s12);
+  build_sell(m.p22, m.e22);
+  build_sell(m.p21, m.e21);
+  build_sell(m.p11, m.e11);
+  build_sell(m.p12, m.e12);
   // --- Dirichlet lifting entries (interior rows, boundary columns)
   m.lift_ptr.assign(m.n2 + 1, 0);
   m.lift_slot.clear();
@@ -220,7 +263,7 @@ void finalize(Mesh& m) {
     if (!m.bmask[i])
       for (int32_t s = m.p22.rowptr[i]; s < m.p22.rowptr[i + 1]; ++s)
         if (m.bmask[m.p22.col[s]]) {
-          m.lift_slot.push_back(s);
+          m.lift_slot.push_back(int32_t(m.e22.index(i, s - m.p22.rowptr[i])));
           m.lift_col.push_back(m.p22.col[s]);
         }
     m.lift_ptr[i + 1] = int32_t(m.lift_slot.size());

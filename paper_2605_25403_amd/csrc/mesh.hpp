@@ -25,6 +25,19 @@ struct Incidence {
   std::vector<int32_t> code;  // cell << 4 | local index of the row's DOF
 };
 
+// SELL-64 layout of a pattern (sliced ELLPACK): rows are grouped in slices of
+// 64 consecutive rows (one wavefront, one row per lane); slice s holds
+// width(s) = max row length in the slice columns of 64 entries, stored
+// column-major, so entry k of row r sits at sptr[r/64] + 64 k + r%64. Padding
+// entries carry value 0 and repeat the row's last column index.
+struct Sell {
+  int64_t nrows = 0, nslices = 0, nent = 0;
+  int maxw = 0;
+  std::vector<int32_t> sptr;   // [nslices+1], entry offsets
+  std::vector<int32_t> col;    // [nent]
+  int64_t index(int64_t row, int k) const { return sptr[row >> 6] + 64ll * k + (row & 63); }
+};
+
 // Per incidence pair, the slots of the cell's local columns in the row
 // (stride bytes per pair, stride = local columns rounded up to 4).
 struct SlotMap {
@@ -44,15 +57,17 @@ struct Mesh {
   std::vector<uint8_t> bmask;     // [n2]
   std::vector<int32_t> bidx;      // boundary P2 nodes, ascending
   Pattern p22, p11, p12, p21;
+  Sell e22, e11, e12, e21;        // SELL-64 layouts of the four patterns
   Incidence inc2, inc1;
   SlotMap s22, s21, s11, s12;
   // Dirichlet lifting: for interior P2 rows, the entries of the P2P2 pattern
-  // in boundary columns: (slot into p22 values, boundary column).
+  // in boundary columns: (SELL index into P2P2 values, boundary column).
   std::vector<int32_t> lift_ptr;  // [n2+1]
   std::vector<int32_t> lift_slot, lift_col;
   int max_row22 = 0, max_row11 = 0, max_row12 = 0, max_row21 = 0;
 
   const Pattern& pattern(int which) const;
+  const Sell& sell(int which) const;
 };
 
 // Builders. All throw ipcs::Error on invalid input.

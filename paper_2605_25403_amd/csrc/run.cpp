@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -13,35 +15,36 @@
 
 namespace ipcs {
 
-constexpr int NBLK_MAX = 1024;
+int nblk_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, div_up(n, bs)); }
 
-int lanes_for(double avg_row) {
-  int g = 4;
-  while (g < 64 && g < avg_row) g *= 2;
-  return g;
-}
-
-int nblk_for(int64_t n, int G) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(div_up(n, BLOCK / G), NBLK_MAX));
+// Krylov block size of a group: IPCS_KBLOCK_P / IPCS_KBLOCK_V override the
+// defaults (pressure / velocity systems) for tuning sweeps.
+int kblock_for(bool pressure) {
+  const char* e = std::getenv(pressure ? "IPCS_KBLOCK_P" : "IPCS_KBLOCK_V");
+  int bs = pressure ? 512 : 1024;
+  if (e) bs = std::atoi(e);
+  if (bs != 256 && bs != 512 && bs != 1024) fail(IPCS_E_INVALID, "Krylov block size must be 256, 512 or 1024");
+  return bs;
 }
 
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap) {
   bmap.clear();
   int mx = 0;
   for (int b : nblk) mx = std::max(mx, b);
-  // interleave systems block by block so that systems sharing a matrix read it
-  // at nearly the same time (cache reuse across velocity components)
   for (int b = 0; b < mx; ++b)
-    for (size_t s = 0; s < nblk.size(); ++s)
-      if (b < nblk[s]) bmap.push_back(make_int2((int)s, b));
+    for (size_t g = 0; g < nblk.size(); ++g)
+      if (b < nblk[g]) bmap.push_back(make_int2((int)g, b));
 }
 
-static AsmCfg asm_cfg(const Pattern& P, int nout) {
-  for (int bs : {256, 128, 64, 32}) {
+// LDS needed by the assembly kernel with bs rows per block: NOUT * the largest
+// number of SELL entries of the bs/64 slices a block owns.
+static AsmCfg asm_cfg(const Sell& S, int nout) {
+  for (int bs : {256, 128, 64}) {
     int64_t mx = 0;
-    for (int64_t r0 = 0; r0 < P.nrows; r0 += bs) {
-      const int64_t r1 = std::min<int64_t>(r0 + bs, P.nrows);
-      mx = std::max<int64_t>(mx, P.rowptr[r1] - P.rowptr[r0]);
+    const int per = bs / 64;
+    for (int64_t s0 = 0; s0 < S.nslices; s0 += per) {
+      const int64_t s1 = std::min<int64_t>(s0 + per, S.nslices);
+      mx = std::max<int64_t>(mx, S.sptr[s1] - S.sptr[s0]);
     }
     const size_t lds = (size_t)nout * mx * sizeof(double);
     if (lds <= 65536) return AsmCfg{bs, std::max<size_t>(lds, 8)};
@@ -58,48 +61,69 @@ static int status_to_code(int s) {
   return IPCS_OK;
 }
 
-int krylov_solve(hipStream_t s, const SolveSet& S, KMethod m, int check_every,
+int krylov_solve(hipStream_t s, const KSet& S, KMethod m, int check_every,
                  std::vector<KState>& hs, KState* pinned) {
-  const int n = S.nsys;
-  hs.resize(n);
+  const int nslot = S.L.ngroups * GMAX;
+  hs.assign(nslot, KState{});
   auto fetch = [&]() {
-    gather_states(s, S.d_sys, n, S.d_poll);
-    HIP_OK(hipMemcpyAsync(pinned, S.d_poll, sizeof(KState) * n, hipMemcpyDeviceToHost, s));
+    gather_states(s, S.L, S.d_poll);
+    HIP_OK(hipMemcpyAsync(pinned, S.d_poll, sizeof(KState) * nslot, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    std::memcpy(hs.data(), pinned, sizeof(KState) * n);
+    for (int g = 0; g < S.L.ngroups; ++g)
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) hs[g * GMAX + j] = pinned[g * GMAX + j];
   };
-  auto init = [&](int mode) {
-    if (m == KMethod::PCG) pcg_init(s, S.G, S.d_sys, S.d_bmap, S.nblocks, mode);
-    else bicg_init(s, S.G, S.d_sys, S.d_bmap, S.nblocks, mode);
+  auto each = [&](auto f) {
+    for (int g = 0; g < S.L.ngroups; ++g)
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) f(hs[g * GMAX + j]);
   };
-  init(0);
+  auto start = [&](int mode) {
+    if (m == KMethod::PCG) pcg_start(s, S.L, mode);
+    else bicg_start(s, S.L, mode);
+  };
+  start(0);
   int chunk = 2;
   const int cap = std::max(1, check_every);
   for (;;) {
     fetch();
     bool pend = false, run = false;
-    for (const auto& k : hs) pend |= (k.status == KS_PENDING || k.status == KS_RESTART);
+    each([&](const KState& k) { pend |= (k.status == KS_PENDING || k.status == KS_RESTART); });
     if (pend) {
-      init(1);
+      start(1);
       fetch();
     }
-    for (const auto& k : hs) run |= (k.status == KS_RUN);
+    each([&](const KState& k) { run |= (k.status == KS_RUN); });
     if (!run) break;
     for (int k = 0; k < chunk; ++k) {
-      if (m == KMethod::PCG) pcg_iter(s, S.G, S.d_sys, S.d_bmap, S.nblocks);
-      else bicg_iter(s, S.G, S.d_sys, S.d_bmap, S.nblocks);
+      if (m == KMethod::PCG) pcg_iter(s, S.L);
+      else bicg_iter(s, S.L);
     }
     chunk = std::min(chunk * 2, cap);
   }
-  ksys_zero(s, S.d_sys, S.d_bmap, S.nblocks);
-  for (const auto& k : hs) {
+  ksys_finish(s, S.L);
+  int rc = IPCS_OK;
+  each([&](const KState& k) {
     const int c = status_to_code(k.status);
-    if (c != IPCS_OK) return c;
-  }
-  return IPCS_OK;
+    if (rc == IPCS_OK && c != IPCS_OK) rc = c;
+  });
+  return rc;
 }
 
 // ------------------------------------------------------------------ layout
+void Run::sizes_from_mesh() {
+  const Mesh& m = *mesh;
+  dim = m.dim;
+  n1 = m.n1;
+  n2 = m.n2;
+  nc = m.nc;
+  nv = m.nv;
+  nb = (int64_t)m.bidx.size();
+  nlift = (int64_t)m.lift_slot.size();
+  ne22 = m.e22.nent;
+  ne21 = m.e21.nent;
+  ne11 = m.e11.nent;
+  ne12 = m.e12.nent;
+}
+
 void Run::layout(Carver& c) {
   const Mesh& m = *mesh;
   const int nsys = 2 * dim + 1;
@@ -108,14 +132,18 @@ void Run::layout(Carver& c) {
   x2 = c.take<double>(n2 * dim);
   bmask = c.take<uint8_t>(n2);
   bidx = c.take<int32_t>(std::max<int64_t>(nb, 1));
+  sp22 = c.take<int32_t>(m.e22.nslices + 1);
+  col22 = c.take<int32_t>(ne22);
   rp22 = c.take<int32_t>(n2 + 1);
-  col22 = c.take<int32_t>(m.p22.nnz());
+  sp21 = c.take<int32_t>(m.e21.nslices + 1);
+  col21 = c.take<int32_t>(ne21);
   rp21 = c.take<int32_t>(n2 + 1);
-  col21 = c.take<int32_t>(m.p21.nnz());
+  sp11 = c.take<int32_t>(m.e11.nslices + 1);
+  col11 = c.take<int32_t>(ne11);
   rp11 = c.take<int32_t>(n1 + 1);
-  col11 = c.take<int32_t>(m.p11.nnz());
+  sp12 = c.take<int32_t>(m.e12.nslices + 1);
+  col12 = c.take<int32_t>(ne12);
   rp12 = c.take<int32_t>(n1 + 1);
-  col12 = c.take<int32_t>(m.p12.nnz());
   inc2p = c.take<int32_t>(n2 + 1);
   inc2 = c.take<int32_t>((int64_t)m.inc2.code.size());
   inc1p = c.take<int32_t>(n1 + 1);
@@ -127,17 +155,15 @@ void Run::layout(Carver& c) {
   lift_ptr = c.take<int32_t>(n2 + 1);
   lift_slot = c.take<int32_t>(std::max<int64_t>(nlift, 1));
   lift_col = c.take<int32_t>(std::max<int64_t>(nlift, 1));
-  const int64_t nnz22 = m.p22.nnz(), nnz11 = m.p11.nnz(), nnz12 = m.p12.nnz(),
-                nnz21 = m.p21.nnz();
-  M = c.take<double>(nnz22);
-  K = c.take<double>(nnz22);
-  E = c.take<double>(nnz22);
-  Ael = c.take<double>(nnz22);
-  Mel = c.take<double>(nnz22);
-  Kp = c.take<double>(nnz11);
+  M = c.take<double>(ne22);
+  K = c.take<double>(ne22);
+  E = c.take<double>(ne22);
+  Ael = c.take<double>(ne22);
+  Mel = c.take<double>(ne22);
+  Kp = c.take<double>(ne11);
   for (int k = 0; k < 3; ++k) {
-    Dc[k] = k < dim ? c.take<double>(nnz12) : nullptr;
-    Gc[k] = k < dim ? c.take<double>(nnz21) : nullptr;
+    Dc[k] = k < dim ? c.take<double>(ne12) : nullptr;
+    Gc[k] = k < dim ? c.take<double>(ne21) : nullptr;
   }
   liftA = c.take<double>(std::max<int64_t>(nlift, 1));
   liftM = c.take<double>(std::max<int64_t>(nlift, 1));
@@ -157,17 +183,22 @@ void Run::layout(Carver& c) {
   kv2 = c.take<double>(9 * dim * n2);
   kv1 = c.take<double>(5 * n1);
   kst = c.take<KState>(nsys);
-  kcnt = c.take<uint32_t>(nsys);
-  ksys = c.take<KSys>(nsys);
-  kpart = c.take<double>((int64_t)nsys * NBLK_MAX * KPART);
-  const int nb2 = nblk_for(n2, G22), nb1 = nblk_for(n1, G11);
-  bmap_mom = c.take<int2>((int64_t)dim * nb2);
-  bmap_p = c.take<int2>(nb1);
-  bmap_corr = c.take<int2>((int64_t)dim * nb2);
-  spart = c.take<double>(8192 * KPART);
+  kgroups = c.take<KGroup>(3);
+  // partial buffers and block maps are sized for the smallest block size
+  const int b2 = nblk_for(n2, 256), b1 = nblk_for(n1, 256);
+  pm_mom = c.take<double>((int64_t)b2 * GMAX * KP);
+  pv_mom = c.take<double>((int64_t)b2 * GMAX * KP);
+  pm_p = c.take<double>((int64_t)b1 * GMAX * KP);
+  pv_p = c.take<double>((int64_t)b1 * GMAX * KP);
+  pm_corr = c.take<double>((int64_t)b2 * GMAX * KP);
+  pv_corr = c.take<double>((int64_t)b2 * GMAX * KP);
+  bm_mom = c.take<int2>(b2);
+  bm_p = c.take<int2>(b1);
+  bm_corr = c.take<int2>(b2);
+  poll = c.take<KState>(3 * GMAX);
+  spart = c.take<double>(8192 * 2);
   scnt = c.take<uint32_t>(4);
   scal = c.take<double>(8);
-  poll = c.take<KState>(nsys);
   gb = c.take<double>(std::max<int64_t>(nb, 1) * dim);
   const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
   fq = c.take<double>(prm.callbacks ? (int64_t)dim * nc * nq : 1);
@@ -192,14 +223,18 @@ void Run::upload_mesh() {
   up(stream, x2, m.x2);
   up(stream, bmask, m.bmask);
   up(stream, bidx, m.bidx);
+  up(stream, sp22, m.e22.sptr);
+  up(stream, col22, m.e22.col);
   up(stream, rp22, m.p22.rowptr);
-  up(stream, col22, m.p22.col);
+  up(stream, sp21, m.e21.sptr);
+  up(stream, col21, m.e21.col);
   up(stream, rp21, m.p21.rowptr);
-  up(stream, col21, m.p21.col);
+  up(stream, sp11, m.e11.sptr);
+  up(stream, col11, m.e11.col);
   up(stream, rp11, m.p11.rowptr);
-  up(stream, col11, m.p11.col);
+  up(stream, sp12, m.e12.sptr);
+  up(stream, col12, m.e12.col);
   up(stream, rp12, m.p12.rowptr);
-  up(stream, col12, m.p12.col);
   up(stream, inc2p, m.inc2.ptr);
   up(stream, inc2, m.inc2.code);
   up(stream, inc1p, m.inc1.ptr);
@@ -215,25 +250,25 @@ void Run::upload_mesh() {
 
 void Run::assemble_constant() {
   const Mesh& m = *mesh;
-  RowAsm a22{(int32_t)n2, rp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr}};
+  RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr}};
   asm_mass_stiff(dim, stream, a22, cfg_mk.bs, cfg_mk.lds);
-  RowAsm a21{(int32_t)n2, rp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
+  RowAsm a21{(int32_t)n2, sp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
              {Gc[0], Gc[1], Gc[2]}};
   asm_grad(dim, stream, a21, cfg_g.bs, cfg_g.lds);
-  RowAsm a12{(int32_t)n1, rp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
+  RowAsm a12{(int32_t)n1, sp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
              {Dc[0], Dc[1], Dc[2]}};
   asm_div(dim, stream, a12, cfg_d.bs, cfg_d.lds);
-  RowAsm a11{(int32_t)n1, rp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
+  RowAsm a11{(int32_t)n1, sp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
              {Kp, nullptr, nullptr}};
   asm_kp(dim, stream, a11, cfg_kp.bs, cfg_kp.lds);
   asm_lumped_p1(dim, stream, a11, w);
-  inv_diagonal(stream, n1, rp11, col11, Kp, dinvKp);
-  form_eliminated(stream, n2, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
+  inv_diagonal(stream, n1, sp11, rp11, col11, Kp, dinvKp);
+  form_eliminated(stream, n2, sp22, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
   lift_values(stream, nlift, lift_slot, M, nullptr, 1.0, 0.0, liftM);
 }
 
 void Run::reform_A() {
-  form_eliminated(stream, n2, rp22, col22, bmask, M, K, 1.0 / prm.dt, prm.nu, Ael, dinvA);
+  form_eliminated(stream, n2, sp22, rp22, col22, bmask, M, K, 1.0 / prm.dt, prm.nu, Ael, dinvA);
   lift_values(stream, nlift, lift_slot, M, K, 1.0 / prm.dt, prm.nu, liftA);
   bi.nu = prm.nu;
   A_dirty = false;
@@ -250,80 +285,79 @@ static KState fresh_state(double tol, int maxit) {
 
 void Run::setup_solvers() {
   const int nsys = 2 * dim + 1;
-  const int nb2 = nblk_for(n2, G22), nb1 = nblk_for(n1, G11);
-  std::vector<KSys> hs(nsys);
   std::vector<KState> st(nsys);
-  for (int s = 0; s < nsys; ++s) {
-    KSys& k = hs[s];
-    std::memset(&k, 0, sizeof(k));
-    k.st = kst + s;
-    k.part = kpart + (size_t)s * NBLK_MAX * KPART;
-    k.cnt = kcnt + s;
-    const bool vel = s != dim;
-    const int c = s < dim ? s : s - dim - 1;
-    if (vel) {
+  std::vector<KGroup> grp(3);
+  const int bsv = kblock_for(false), bsp = kblock_for(true);
+  const int b2 = nblk_for(n2, bsv), b1 = nblk_for(n1, bsp);
+  for (int gi = 0; gi < 3; ++gi) {
+    KGroup& g = grp[gi];
+    std::memset(&g, 0, sizeof(g));
+    if (gi == 1) {   // pressure Poisson
+      g.nsys = 1;
+      g.n = (int32_t)n1;
+      g.sptr = sp11;
+      g.col = col11;
+      g.val = Kp;
+      g.dinv = dinvKp;
+      g.nblk = b1;
+      g.part_m = pm_p;
+      g.part_v = pv_p;
+      KVecs& V = g.v[0];
+      V.b = rP;
+      V.x = dP;
+      V.r = kv1;
+      V.z = kv1 + n1;
+      V.p[0] = kv1 + 2 * n1;
+      V.p[1] = kv1 + 3 * n1;
+      V.q = kv1 + 4 * n1;
+      V.st = kst + dim;
+      st[dim] = fresh_state(prm.tol_p, prm.maxit);
+      continue;
+    }
+    const bool mom = gi == 0;
+    g.nsys = dim;
+    g.n = (int32_t)n2;
+    g.sptr = sp22;
+    g.col = col22;
+    g.val = mom ? Ael : Mel;
+    g.dinv = mom ? dinvA : dinvM;
+    g.nblk = b2;
+    g.part_m = mom ? pm_mom : pm_corr;
+    g.part_v = mom ? pv_mom : pv_corr;
+    for (int c = 0; c < dim; ++c) {
       double* base = kv2 + (size_t)c * 9 * n2;
-      k.rowptr = rp22;
-      k.col = col22;
-      k.n = (int32_t)n2;
-      k.nblk = nb2;
-      k.r = base;
-      k.z = base + n2;
-      k.p[0] = base + 2 * n2;
-      k.p[1] = base + 3 * n2;
-      k.q = base + 4 * n2;
-      k.s = base + 5 * n2;
-      k.t = base + 6 * n2;
-      k.phat = base + 7 * n2;
-      k.shat = base + 8 * n2;
-      k.b = bU + (size_t)c * n2;
-      if (s < dim) {   // momentum
-        k.val = Ael;
-        k.dinv = dinvA;
-        k.x = Ustar + (size_t)c * n2;
-        st[s] = fresh_state(prm.tol_mom, prm.maxit);
-      } else {         // correction
-        k.val = Mel;
-        k.dinv = dinvM;
-        k.x = Unew + (size_t)c * n2;
-        st[s] = fresh_state(prm.tol_corr, prm.maxit);
-      }
-    } else {           // pressure Poisson
-      k.rowptr = rp11;
-      k.col = col11;
-      k.val = Kp;
-      k.dinv = dinvKp;
-      k.n = (int32_t)n1;
-      k.nblk = nb1;
-      k.r = kv1;
-      k.z = kv1 + n1;
-      k.p[0] = kv1 + 2 * n1;
-      k.p[1] = kv1 + 3 * n1;
-      k.q = kv1 + 4 * n1;
-      k.b = rP;
-      k.x = dP;
-      st[s] = fresh_state(prm.tol_p, prm.maxit);
+      KVecs& V = g.v[c];
+      V.b = bU + (size_t)c * n2;
+      V.x = (mom ? Ustar : Unew) + (size_t)c * n2;
+      V.r = base;
+      V.z = base + n2;
+      V.p[0] = base + 2 * n2;
+      V.p[1] = base + 3 * n2;
+      V.q = base + 4 * n2;
+      V.s = base + 5 * n2;
+      V.t = base + 6 * n2;
+      V.phat = base + 7 * n2;
+      V.shat = base + 8 * n2;
+      const int sidx = mom ? c : dim + 1 + c;
+      V.st = kst + sidx;
+      st[sidx] = fresh_state(mom ? prm.tol_mom : prm.tol_corr, prm.maxit);
     }
   }
-  HIP_OK(hipMemcpyAsync(ksys, hs.data(), sizeof(KSys) * nsys, hipMemcpyHostToDevice, stream));
+  HIP_OK(hipMemcpyAsync(kgroups, grp.data(), sizeof(KGroup) * 3, hipMemcpyHostToDevice, stream));
   HIP_OK(hipMemcpyAsync(kst, st.data(), sizeof(KState) * nsys, hipMemcpyHostToDevice, stream));
-  HIP_OK(hipMemsetAsync(kcnt, 0, sizeof(uint32_t) * nsys, stream));
-  auto mk = [&](SolveSet& S, int first, int count, int G, int nblk, int2* dmap) {
-    S.nsys = count;
-    S.G = G;
-    S.h_sys.assign(hs.begin() + first, hs.begin() + first + count);
-    std::vector<int> nb(count, nblk);
-    build_bmap(nb, S.h_bmap);
-    S.nblocks = (int)S.h_bmap.size();
-    S.d_sys = ksys + first;
-    S.d_bmap = dmap;
-    S.d_poll = poll + first;
-    HIP_OK(hipMemcpyAsync(dmap, S.h_bmap.data(), sizeof(int2) * S.h_bmap.size(),
+  std::vector<std::vector<int2>> maps(3);
+  auto mk = [&](KSet& S, int gi, int2* bm) {
+    S.h_groups = {grp[gi]};
+    build_bmap({grp[gi].nblk}, maps[gi]);
+    HIP_OK(hipMemcpyAsync(bm, maps[gi].data(), sizeof(int2) * maps[gi].size(),
                           hipMemcpyHostToDevice, stream));
+    S.L = KLaunch{kgroups + gi, 1, bm, (int)maps[gi].size(), gi == 1 ? bsp : bsv};
+    S.d_poll = poll + gi * GMAX;
   };
-  mk(set_mom, 0, dim, G22, nb2, bmap_mom);
-  mk(set_p, dim, 1, G11, nb1, bmap_p);
-  mk(set_corr, dim + 1, dim, G22, nb2, bmap_corr);
+  mk(set_mom, 0, bm_mom);
+  mk(set_p, 1, bm_p);
+  mk(set_corr, 2, bm_corr);
+  HIP_OK(hipStreamSynchronize(stream));
 }
 
 void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, int64_t bytes,
@@ -331,22 +365,13 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   mesh = std::move(m);
   prm = p;
   stream = s;
+  sizes_from_mesh();
   const Mesh& mm = *mesh;
-  dim = mm.dim;
-  n1 = mm.n1;
-  n2 = mm.n2;
-  nc = mm.nc;
-  nv = mm.nv;
-  nb = (int64_t)mm.bidx.size();
-  nlift = (int64_t)mm.lift_slot.size();
-  G22 = lanes_for(double(mm.p22.nnz()) / n2);
-  G11 = lanes_for(double(mm.p11.nnz()) / n1);
-  G12 = lanes_for(double(mm.p12.nnz()) / n1);
-  cfg_mk = asm_cfg(mm.p22, 2);
-  cfg_e = asm_cfg(mm.p22, 1);
-  cfg_g = asm_cfg(mm.p21, dim);
-  cfg_d = asm_cfg(mm.p12, dim);
-  cfg_kp = asm_cfg(mm.p11, 1);
+  cfg_mk = asm_cfg(mm.e22, 1);
+  cfg_e = asm_cfg(mm.e22, 1);
+  cfg_g = asm_cfg(mm.e21, 1);
+  cfg_d = asm_cfg(mm.e12, 1);
+  cfg_kp = asm_cfg(mm.e11, 1);
   Carver meas;
   layout(meas);
   if (!ws || bytes < meas.off)
@@ -355,21 +380,28 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   c.base = static_cast<char*>(ws);
   layout(c);
   ws_bytes = bytes;
-  HIP_OK(hipHostMalloc((void**)&pinned, sizeof(KState) * (2 * dim + 1), hipHostMallocDefault));
+  HIP_OK(hipHostMalloc((void**)&pinned, sizeof(KState) * 3 * GMAX, hipHostMallocDefault));
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   upload_mesh();
+  // value arrays: SELL padding entries must read as zero
+  for (double* v : {M, K, E, Ael, Mel}) HIP_OK(hipMemsetAsync(v, 0, sizeof(double) * ne22, stream));
+  HIP_OK(hipMemsetAsync(Kp, 0, sizeof(double) * ne11, stream));
+  for (int k = 0; k < dim; ++k) {
+    HIP_OK(hipMemsetAsync(Dc[k], 0, sizeof(double) * ne12, stream));
+    HIP_OK(hipMemsetAsync(Gc[k], 0, sizeof(double) * ne21, stream));
+  }
   const size_t vbytes = sizeof(double) * dim * n2;
   for (double* v : {U, Unew, Ustar, bU, F, gfull}) HIP_OK(hipMemsetAsync(v, 0, vbytes, stream));
   for (double* v : {P, dP, rP}) HIP_OK(hipMemsetAsync(v, 0, sizeof(double) * n1, stream));
-  HIP_OK(hipMemsetAsync(scnt, 0, sizeof(uint32_t) * 4, stream));
+  // Krylov vectors start finite (gathers of padding columns read them)
+  HIP_OK(hipMemsetAsync(kv2, 0, sizeof(double) * 9 * dim * n2, stream));
+  HIP_OK(hipMemsetAsync(kv1, 0, sizeof(double) * 5 * n1, stream));
   HIP_OK(hipMemsetAsync(scal, 0, sizeof(double) * 8, stream));
   assemble_constant();
   reform_A();
   setup_solvers();
   t = prm.t0;
-  if (!prm.callbacks) {
-    // keep host memory small when no callbacks are used
-  } else {
+  if (prm.callbacks) {
     const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
     h_xq.resize((size_t)nc * nq * dim);
     for (int64_t cc = 0; cc < nc; ++cc)
@@ -387,11 +419,6 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   for (int64_t k = 0; k < nb; ++k)
     for (int r = 0; r < dim; ++r) h_xb[k * dim + r] = mm.x2[(size_t)mm.bidx[k] * dim + r];
   HIP_OK(hipStreamSynchronize(stream));
-}
-
-void Run::normalize_pressure(double* Pdev) {
-  weighted_mean(stream, n1, w, Pdev, spart, scnt, scal + 2);
-  sub_scalar(stream, n1, scal + 2, Pdev);
 }
 
 void Run::set_builtin(int kind, const double* p, int np) {
@@ -413,7 +440,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
   f_cb = g_cb = nullptr;
   eval_velocity(stream, dim, bi, x2, n2, t, U, n2);
   eval_pressure(stream, dim, bi, X, nv, t, P);
-  normalize_pressure(P);
+  sub_weighted_mean(stream, n1, w, P, spart, scal + 2);
   phase_next = IPCS_PHASE_ASM;
   HIP_OK(hipStreamSynchronize(stream));
 }
@@ -426,18 +453,19 @@ void Run::set_state(const double* u, const double* p, double tt) {
   phase_next = IPCS_PHASE_ASM;
 }
 
-void fill_stats_solve(const std::vector<KState>& hs, int which, ipcs_step_stats* st) {
+void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_step_stats* st) {
   if (!st) return;
-  for (size_t c = 0; c < hs.size(); ++c) {
-    const double res = hs[c].bb > 0 ? std::sqrt(hs[c].rr / hs[c].bb) : 0.0;
+  for (int c = 0; c < nsys; ++c) {
+    const KState& k = hs[c];
+    const double res = k.bb > 0 ? std::sqrt(k.rr / k.bb) : 0.0;
     if (which == 1) {
-      st->it_mom[c] = hs[c].it;
+      st->it_mom[c] = k.it;
       st->res_mom[c] = res;
     } else if (which == 2) {
-      st->it_p = hs[c].it;
+      st->it_p = k.it;
       st->res_p = res;
     } else {
-      st->it_corr[c] = hs[c].it;
+      st->it_corr[c] = k.it;
       st->res_corr[c] = res;
     }
   }
@@ -465,7 +493,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
         dirichlet_builtin(stream, dim, bi, x2, bidx, nb, t1, gfull, n2);
       }
       const Mesh& m = *mesh;
-      RowAsm a22{(int32_t)n2, rp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
+      RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
                  {E, nullptr, nullptr}};
       has_F = false;
       if (f_cb) {
@@ -484,8 +512,8 @@ int Run::phase(int which, ipcs_step_stats* st) {
         has_F = true;
       }
       asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
-      rhs_momentum(stream, dim, G22, n2, rp22, col22, E, U, rp21, col21, Gc, P,
-                   has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask, gfull, bU);
+      rhs_momentum(stream, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, has_F ? F : nullptr,
+                   lift_ptr, lift_col, liftA, bmask, gfull, bU);
       copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
       HIP_OK(hipEventRecord(ev[1], stream));
       phase_next = IPCS_PHASE_MOMENTUM;
@@ -493,7 +521,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
     }
     case IPCS_PHASE_MOMENTUM: {
       rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, hs, pinned);
-      fill_stats_solve(hs, 1, st);
+      fill_stats_solve(hs, dim, 1, st);
       HIP_OK(hipEventRecord(ev[2], stream));
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 1;
@@ -504,30 +532,28 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     }
     case IPCS_PHASE_PRESSURE: {
-      rhs_pressure(stream, dim, G12, n1, rp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
-                   scnt, scal + 0);
-      sub_scalar(stream, n1, scal + 0, rP);
+      rhs_pressure(stream, dim, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart, scnt,
+                   scal + 0);
       HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
       rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned);
-      fill_stats_solve(hs, 2, st);
+      fill_stats_solve(hs, 1, 2, st);
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 2;
         phase_next = IPCS_PHASE_ASM;
         return rc;
       }
-      weighted_mean(stream, n1, w, dP, spart, scnt, scal + 1);
-      sub_scalar(stream, n1, scal + 1, dP);
+      sub_weighted_mean(stream, n1, w, dP, spart, scal + 1);
       HIP_OK(hipEventRecord(ev[3], stream));
       phase_next = IPCS_PHASE_CORRECTION;
       return IPCS_OK;
     }
     case IPCS_PHASE_CORRECTION: {
-      rhs_correction(stream, dim, G22, n2, rp22, col22, M, Ustar, rp21, col21, Gc, dP,
+      rhs_correction(stream, dim, n2, sp22, col22, M, Ustar, sp21, col21, Gc, dP,
                      prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
       HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
                             stream));
       rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, hs, pinned);
-      fill_stats_solve(hs, 3, st);
+      fill_stats_solve(hs, dim, 3, st);
       phase_next = IPCS_PHASE_ASM;
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 3;
@@ -565,6 +591,95 @@ int Run::step(ipcs_step_stats* st) {
     }
   }
   return IPCS_OK;
+}
+
+// Times nlaunch back-to-back launches of one kernel of the step on this run's
+// data. The solver states are forced to "iterating" first and checked after:
+// every timed launch must have done its full work.
+double Run::profile_kernel(int kernel, int nlaunch) {
+  if (phase_next != IPCS_PHASE_ASM) fail(IPCS_E_STATE, "profile only between steps");
+  const KSet* S = kernel == IPCS_KERNEL_BICG_SPMV     ? &set_mom
+                  : kernel == IPCS_KERNEL_PCG_SPMV_M  ? &set_corr
+                  : kernel == IPCS_KERNEL_ASM_CONV    ? nullptr
+                                                      : &set_p;
+  if (S) {
+    const KGroup& g = S->h_groups[0];
+    for (int j = 0; j < g.nsys; ++j) {
+      KState& k = pinned[j];
+      std::memset(&k, 0, sizeof(k));
+      k.status = KS_RUN;
+      k.rho[0] = k.rho[1] = 1.0;
+      k.alpha = k.omega = 1.0;
+      k.bb = 1.0;
+      k.tol2 = 0.0;
+      k.maxit = 1 << 30;
+      k.it = 1;       // not a (re)start: the full iteration path runs
+      k.it0 = 0;
+      HIP_OK(hipMemcpyAsync(g.v[j].st, &k, sizeof(KState), hipMemcpyHostToDevice, stream));
+    }
+    // partials the kernels reduce in their prologue: unit dot products in
+    // block 0, zeros elsewhere (every launch then takes the full iteration path)
+    std::vector<double> pm((size_t)g.nblk * GMAX * KP, 0.0), pv((size_t)g.nblk * GMAX * KP, 0.0);
+    for (int j = 0; j < g.nsys; ++j)
+      for (int k = 0; k < KP; ++k) pm[j * KP + k] = pv[j * KP + k] = 1.0;
+    HIP_OK(hipMemcpyAsync(g.part_m, pm.data(), sizeof(double) * pm.size(), hipMemcpyHostToDevice,
+                          stream));
+    HIP_OK(hipMemcpyAsync(g.part_v, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice,
+                          stream));
+    HIP_OK(hipStreamSynchronize(stream));
+  }
+  const Mesh& m = *mesh;
+  RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
+             {E, nullptr, nullptr}};
+  auto launch = [&]() {
+    switch (kernel) {
+      case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
+      case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L); break;
+      case IPCS_KERNEL_ASM_CONV:
+        asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+        break;
+      case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;
+      case IPCS_KERNEL_PCG_SPMV_M: pcg_spmv_only(stream, set_corr.L); break;
+      default: fail(IPCS_E_INVALID, "unknown kernel id");
+    }
+  };
+  launch();   // warm
+  HIP_OK(hipEventRecord(ev[0], stream));
+  for (int i = 0; i < nlaunch; ++i) launch();
+  HIP_OK(hipEventRecord(ev[1], stream));
+  HIP_OK(hipEventSynchronize(ev[1]));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  if (S) {
+    std::vector<KState> hs;
+    gather_states(stream, S->L, S->d_poll);
+    HIP_OK(hipMemcpyAsync(pinned, S->d_poll, sizeof(KState) * GMAX, hipMemcpyDeviceToHost,
+                          stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    for (int j = 0; j < S->h_groups[0].nsys; ++j)
+      if (pinned[j].status != KS_RUN)
+      {
+        char msg[512];
+        const KState& k = pinned[j];
+        std::snprintf(msg, sizeof msg,
+                      "profiled kernel %d left system %d in status %d (rr %.3e bb %.3e tol2 %.3e "
+                      "it %d it0 %d maxit %d par %d); timing discarded",
+                      kernel, j, k.status, k.rr, k.bb, k.tol2, k.it, k.it0, k.maxit, k.par);
+        fail(IPCS_E_STATE, msg);
+      }
+  }
+  return 1000.0 * ms / nlaunch;
+}
+
+void Run::export_values(int pattern, const double* dev, double* out) {
+  const Sell& S = mesh->sell(pattern);
+  const Pattern& P = mesh->pattern(pattern);
+  std::vector<double> h(S.nent);
+  HIP_OK(hipMemcpyAsync(h.data(), dev, sizeof(double) * S.nent, hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  for (int64_t i = 0; i < P.nrows; ++i)
+    for (int k = 0; k < P.rowptr[i + 1] - P.rowptr[i]; ++k)
+      out[P.rowptr[i] + k] = h[S.index(i, k)];
 }
 
 }  // namespace ipcs

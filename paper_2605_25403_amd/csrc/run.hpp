@@ -1,6 +1,6 @@
 // One IPCS run: its device workspace layout, constant matrices, state and the
-// three sub-steps of eq. (9) (Section 2.2.1), plus the Krylov driver shared by
-// single runs and batches.
+// three sub-steps of eq. (9) (Section 2.2.1), plus the host side of the Krylov
+// solves shared by single runs and batches.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -27,30 +27,24 @@ struct Carver {
   }
 };
 
-// A group of Krylov systems solved together (one launch per kernel).
-struct SolveSet {
-  int nsys = 0;
-  int G = 16;                  // lanes per row
-  int nblocks = 0;             // total blocks of a launch
-  KSys* d_sys = nullptr;       // [nsys]
-  int2* d_bmap = nullptr;      // [nblocks]
-  std::vector<KSys> h_sys;
-  std::vector<int2> h_bmap;
-  KState* d_poll = nullptr;    // [nsys] contiguous copy of the states for polling
+// Host view of a set of Krylov groups solved by the same launches.
+struct KSet {
+  KLaunch L{};
+  std::vector<KGroup> h_groups;
+  KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
 };
 
 enum class KMethod { PCG, BICG };
 
-// Runs a solve set to completion; h_states receives the final states.
+// Runs a set to completion. h_states[g*GMAX + j] receives the final states.
 // Returns IPCS_OK or the status of the first failed system.
-int krylov_solve(hipStream_t s, const SolveSet& S, KMethod m, int check_every,
+int krylov_solve(hipStream_t s, const KSet& S, KMethod m, int check_every,
                  std::vector<KState>& h_states, KState* pinned);
 
-// Build the interleaved block map for systems with the given block counts.
+int nblk_for(int64_t n, int bs);
+int kblock_for(bool pressure);
+// (group, block) map interleaving the groups block by block
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
-
-int lanes_for(double avg_row);
-int nblk_for(int64_t n, int G);
 
 struct AsmCfg {
   int bs = 256;
@@ -63,7 +57,7 @@ struct Run {
   hipStream_t stream = nullptr;
   int dim = 2;
   int64_t n1 = 0, n2 = 0, nc = 0, nv = 0, nb = 0, nlift = 0;
-  int G22 = 16, G11 = 8, G12 = 16;
+  int64_t ne22 = 0, ne21 = 0, ne11 = 0, ne12 = 0;   // SELL entries per pattern
   AsmCfg cfg_mk, cfg_e, cfg_g, cfg_d, cfg_kp;
 
   // ---- device arrays (all inside the workspace)
@@ -72,8 +66,11 @@ struct Run {
   double* x2 = nullptr;
   uint8_t* bmask = nullptr;
   int32_t* bidx = nullptr;
-  int32_t *rp22 = nullptr, *col22 = nullptr, *rp21 = nullptr, *col21 = nullptr;
-  int32_t *rp11 = nullptr, *col11 = nullptr, *rp12 = nullptr, *col12 = nullptr;
+  // per pattern: SELL slice offsets, SELL columns, CSR row pointer (row lengths)
+  int32_t *sp22 = nullptr, *col22 = nullptr, *rp22 = nullptr;
+  int32_t *sp21 = nullptr, *col21 = nullptr, *rp21 = nullptr;
+  int32_t *sp11 = nullptr, *col11 = nullptr, *rp11 = nullptr;
+  int32_t *sp12 = nullptr, *col12 = nullptr, *rp12 = nullptr;
   int32_t *inc2p = nullptr, *inc2 = nullptr, *inc1p = nullptr, *inc1 = nullptr;
   uint8_t *s22 = nullptr, *s21 = nullptr, *s11 = nullptr, *s12 = nullptr;
   int32_t *lift_ptr = nullptr, *lift_slot = nullptr, *lift_col = nullptr;
@@ -84,24 +81,22 @@ struct Run {
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
          *gfull = nullptr;
   double *P = nullptr, *dP = nullptr, *rP = nullptr;
-  double* kv2 = nullptr;      // Krylov work for the velocity systems [9][dim][n2]
-  double* kv1 = nullptr;      // Krylov work for the Poisson system [5][n1]
+  double* kv2 = nullptr;      // Krylov work of the velocity systems [dim][9][n2]
+  double* kv1 = nullptr;      // Krylov work of the Poisson system [5][n1]
   KState* kst = nullptr;      // [2*dim+1]
-  double* kpart = nullptr;    // [(2*dim+1)][nblkmax][KPART]
-  uint32_t* kcnt = nullptr;   // [2*dim+1]
-  KSys* ksys = nullptr;       // [2*dim+1]
-  int2* bmap_mom = nullptr;
-  int2* bmap_p = nullptr;
-  int2* bmap_corr = nullptr;
-  double* spart = nullptr;    // scratch partials for one-off reductions [8192][KPART]
-  uint32_t* scnt = nullptr;   // [4]
-  double* scal = nullptr;     // [8] device scalars: 0 mean(r), 1 shift(dP), 2 mean(P)
-  KState* poll = nullptr;     // [2*dim+1] polling copies of the Krylov states
+  KGroup* kgroups = nullptr;  // [3]: momentum, pressure, correction
+  double *pm_mom = nullptr, *pv_mom = nullptr, *pm_p = nullptr, *pv_p = nullptr;
+  double *pm_corr = nullptr, *pv_corr = nullptr;
+  int2 *bm_mom = nullptr, *bm_p = nullptr, *bm_corr = nullptr;
+  KState* poll = nullptr;     // [3 * GMAX]
+  double* spart = nullptr;    // scratch partials for one-off reductions [8192*2]
+  uint32_t* scnt = nullptr;
+  double* scal = nullptr;     // [8] device scalars: 0 mean(r), 1 mean(dP), 2 mean(P)
   double* gb = nullptr;       // Dirichlet callback staging [nb][dim]
   double* fq = nullptr;       // forcing callback staging [dim][nc][nq]
   int64_t ws_bytes = 0;
 
-  SolveSet set_mom, set_p, set_corr;
+  KSet set_mom, set_p, set_corr;
   KState* pinned = nullptr;   // host mirror for status polling
 
   // ---- problem data
@@ -118,6 +113,7 @@ struct Run {
   hipEvent_t ev[5] = {};
 
   ~Run();
+  void sizes_from_mesh();
   void layout(Carver& c);
   void create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, int64_t bytes,
               hipStream_t s);
@@ -129,9 +125,11 @@ struct Run {
   void set_state(const double* u, const double* p, double t);
   int phase(int which, ipcs_step_stats* st);
   int step(ipcs_step_stats* st);
-  void normalize_pressure(double* Pdev);
+  double profile_kernel(int kernel, int nlaunch);
+  // host-side CSR values of a device SELL matrix
+  void export_values(int pattern, const double* dev, double* out);
 };
 
-void fill_stats_solve(const std::vector<KState>& hs, int which, ipcs_step_stats* st);
+void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_step_stats* st);
 
 }  // namespace ipcs

@@ -36,6 +36,8 @@ IPCS_FIELD_U, IPCS_FIELD_P, IPCS_FIELD_USTAR, IPCS_FIELD_DP = 0, 1, 2, 3
 IPCS_FIELD_RHS_MOM, IPCS_FIELD_RHS_P = 4, 5
 IPCS_MAT_M, IPCS_MAT_K, IPCS_MAT_KP, IPCS_MAT_A, IPCS_MAT_E = 0, 1, 2, 3, 4
 IPCS_MAT_D0, IPCS_MAT_G0, IPCS_MAT_A_ELIM, IPCS_MAT_M_ELIM = 8, 12, 16, 17
+IPCS_KERNEL_PCG_SPMV_P, IPCS_KERNEL_PCG_UPDATE_P, IPCS_KERNEL_ASM_CONV = 0, 1, 2
+IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_PCG_SPMV_M = 3, 4
 
 
 class IpcsError(RuntimeError):
@@ -105,6 +107,7 @@ _SIGS = {
     "ipcs_get_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
     "ipcs_export_matrix": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, _P, C.c_int64]),
     "ipcs_batch_step": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "ipcs_profile_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ipcs_run_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -280,6 +283,12 @@ def ipcs_export_matrix(r, which, shape_rows, nnz):
     return rp, col, val
 
 
+def ipcs_profile_kernel(r, kernel, nlaunch):
+    us = C.c_double()
+    _check(lib.ipcs_profile_kernel(r, kernel, nlaunch, C.byref(us)))
+    return us.value
+
+
 def ipcs_run_destroy(r):
     lib.ipcs_run_destroy(r)
 
@@ -308,9 +317,9 @@ class Mesh:
     def dim(self):
         return self.counts.dim
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.ipcs_mesh_destroy):
         if getattr(self, "h", None):
-            ipcs_mesh_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
 
@@ -388,7 +397,7 @@ class Run:
         rp, col, val = ipcs_export_matrix(self.h, which, rows, nnz)
         return sp.csr_matrix((val, col, rp), shape=(rows, cols))
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.ipcs_run_destroy):
         if getattr(self, "h", None):
-            ipcs_run_destroy(self.h)
+            _destroy(self.h)
             self.h = None

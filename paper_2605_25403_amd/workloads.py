@@ -1,0 +1,66 @@
+"""Seeded synthetic workloads (inputs only; no part of the method).
+
+The method is run on generated unit-square / unit-cube meshes with closed-form
+manufactured solutions, so every input is a handful of parameters drawn from
+numpy's PCG64 generator:
+* Taylor-Green wave number k in {pi, 2 pi, 4 pi} and viscosity nu log-uniform
+  in [1e-3, 1e-1];
+* a serving request stream: Poisson arrivals at a given rate, mesh size n
+  drawn from a set, and per-request (k, nu).
+"""
+import math
+
+import numpy as np
+
+K_CHOICES = (math.pi, 2 * math.pi, 4 * math.pi)
+
+
+def tg_params(seed):
+    """(k, nu) for the 2D Taylor-Green workload with this seed."""
+    rng = np.random.default_rng(seed)
+    k = float(rng.choice(K_CHOICES))
+    nu = float(10.0 ** rng.uniform(-3.0, -1.0))
+    return k, nu
+
+
+WORKLOADS = {
+    # 16 x 16 squares (512 triangles), TG k = pi, nu = 0.01, dt = 0.01, 10 steps
+    "c1": dict(dim=2, n=16, dt=0.01, steps=10, seed=None, k=math.pi, nu=0.01, tol=1e-12,
+               precision="fp64"),
+    # 512 x 512 squares (524,288 triangles), seed-drawn TG, dt = 1e-3, 100 steps
+    "c2": dict(dim=2, n=512, dt=1e-3, steps=100, seed=0, tol=1e-12, precision="fp64"),
+    # same mesh and problem in the mixed-precision form
+    "c3": dict(dim=2, n=512, dt=1e-3, steps=100, seed=0, tol=1e-12, precision="mixed"),
+    # 64^3 cubes x 6 Kuhn tets, Beltrami a = pi/4, d = pi/2, nu = 0.01, 50 steps
+    "c4": dict(dim=3, n=64, dt=1e-3, steps=50, seed=None, nu=0.01, tol=1e-12,
+               precision="mixed"),
+}
+
+
+def resolve(name):
+    w = dict(WORKLOADS[name])
+    if w.get("seed") is not None:
+        w["k"], w["nu"] = tg_params(w["seed"])
+    return w
+
+
+def serving_requests(seed=0, count=256, rate=20.0, sizes=(32, 64, 128, 256), steps=50,
+                     dt=1e-3):
+    """Request stream: arrival time (s), mesh size n, k, nu, steps, dt."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        k = float(rng.choice(K_CHOICES))
+        nu = float(10.0 ** rng.uniform(-3.0, -1.0))
+        out.append(dict(id=i, t_arrive=float(arrivals[i]), n=n, k=k, nu=nu, steps=steps,
+                        dt=dt))
+    return out
+
+
+def dofs(dim, n):
+    """d*N2 + N1 on the structured meshes."""
+    if dim == 2:
+        return 2 * (2 * n + 1) ** 2 + (n + 1) ** 2
+    return 3 * (2 * n + 1) ** 3 + (n + 1) ** 3
