@@ -29,14 +29,15 @@ def kernel_bytes(kernel, c, dim):
     once, 8-byte values and vectors, 4-byte indices (formulas in the design doc)."""
     n1, n2 = c.n1, c.n2
     nnz22, nnz11 = c.nnz[0], c.nnz[1]
-    if kernel == "pcg_spmv_p":     # vals+cols, rowptr, z and p_old in, p_new and q out
-        return 12 * nnz11 + 4 * (n1 + 1) + 4 * 8 * n1
-    if kernel == "pcg_update_p":   # x, p, r, q, dinv in; x, r, z out
-        return 8 * 8 * n1
-    if kernel == "bicg_spmv":      # matrix once for all components; phat, rhat in, v out
-        return 12 * nnz22 + 4 * (n2 + 1) + dim * 3 * 8 * n2
-    if kernel == "pcg_spmv_m":     # matrix once; z, p_old in; p_new, q out per component
-        return 12 * nnz22 + 4 * (n2 + 1) + dim * 4 * 8 * n2
+    sl1, sl2 = 4 * (n1 // 64 + 2), 4 * (n2 // 64 + 2)     # SELL-64 slice pointers
+    if kernel == "pcg_spmv_p":     # Kp values+cols once; u in, w = Kp u out
+        return 12 * nnz11 + sl1 + 2 * 8 * n1
+    if kernel == "pcg_update_p":   # x, r, p, s, w, dinv in; x, r, p, s, u out
+        return 11 * 8 * n1
+    if kernel == "bicg_spmv":      # A once for all components; phat, rhat in, v out each
+        return 12 * nnz22 + sl2 + dim * 3 * 8 * n2
+    if kernel == "pcg_spmv_m":     # M once for all components; u in, w out each
+        return 12 * nnz22 + sl2 + dim * 2 * 8 * n2
     if kernel == "asm_conv":       # E out, U in, cell DOFs, vertex coordinates
         nloc = 6 if dim == 2 else 10
         return 8 * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv

@@ -58,58 +58,63 @@ __device__ __forceinline__ void block_sum_n(const double (&v)[N], double (&out)[
   }
 }
 
-// Partial sums of a producer kernel, loaded in two phases so the loads can
-// be issued early and overlap other memory traffic: load() only fetches this
-// thread's entries (producer blocks tid, tid + blockDim, ...), reduce() sums
-// them over the block in a fixed order. tot[j][k] = sum over b < nb of
-// part[(b*GMAX + j)*KP + k] for j < ns, k < K; valid in every thread.
-template <int K>
-struct Partials {
-  double v[GMAX][K];
-  __device__ __forceinline__ void load(const double* part, int nb, int ns) {
+// Block sum over a compile-time block size BS (BS/64 waves); same contract as
+// block_sum_n. sh needs (BS/64)*N doubles.
+template <int BS, int N>
+__device__ __forceinline__ void block_sum_t(double (&v)[N], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < GMAX; ++j)
+  for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+  __syncthreads();
+  if (lane == 0)
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[j][k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const double* p = part + (size_t)b * GMAX * KP;
+    for (int n = 0; n < N; ++n) sh[wid * N + n] = v[n];
+  __syncthreads();
 #pragma unroll
-      for (int j = 0; j < GMAX; ++j)
-        if (j < ns)
+  for (int n = 0; n < N; ++n) {
+    double s = 0.0;
 #pragma unroll
-          for (int k = 0; k < K; ++k) v[j][k] += p[j * KP + k];
+    for (int q = 0; q < BS / 64; ++q) s += sh[q * N + n];
+    v[n] = s;
+  }
+}
+
+// This thread's share of the partial records of a producer kernel with nb
+// blocks (nb <= KBS * KPART_Q): records tid, tid + KBS, ... summed in order.
+// Every load is issued before the first use, so the caller can issue its own
+// independent loads first and let all of them overlap. K values of NS systems
+// land in v[j*K + k]; block_sum_t then gives the totals.
+template <int NS, int K>
+__device__ __forceinline__ void load_partials(const double* part, int nb, double* v) {
+#pragma unroll
+  for (int n = 0; n < NS * K; ++n) v[n] = 0.0;
+#pragma unroll
+  for (int q = 0; q < KPART_Q; ++q) {
+    const int b = (int)threadIdx.x + q * KBS;
+    if (q * KBS < nb) {
+      const bool ok = b < nb;
+      const double* p = part + (size_t)(ok ? b : 0) * GMAX * KP;
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[j * K + k] += ok ? p[j * KP + k] : 0.0;
     }
   }
-  __device__ __forceinline__ void reduce(int ns, double (&tot)[GMAX][K], double* sh) const {
-    double flat[GMAX * K], out[GMAX * K];
-#pragma unroll
-    for (int j = 0; j < GMAX; ++j)
-#pragma unroll
-      for (int k = 0; k < K; ++k) flat[j * K + k] = j < ns ? v[j][k] : 0.0;
-    block_sum_n<GMAX * K>(flat, out, sh);
-#pragma unroll
-    for (int j = 0; j < GMAX; ++j)
-#pragma unroll
-      for (int k = 0; k < K; ++k) tot[j][k] = out[j * K + k];
-  }
-};
+}
 
-// Block-reduce acc[j][k] and store them as this block's partials.
-template <int K>
-__device__ __forceinline__ void store_partials(const double (&acc)[GMAX][K], int ns, double* part,
-                                               int lb, double* sh) {
-  double flat[GMAX * K], out[GMAX * K];
+// Block-reduce acc[j*K + k] (KBS threads) and store them as partial record lb.
+template <int NS, int K>
+__device__ __forceinline__ void store_partials(double* acc, double* part, int lb, double* sh) {
+  double v[NS * K];
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j)
-#pragma unroll
-    for (int k = 0; k < K; ++k) flat[j * K + k] = acc[j][k];
-  block_sum_n<GMAX * K>(flat, out, sh);
-  if (threadIdx.x < GMAX * K) {
+  for (int n = 0; n < NS * K; ++n) v[n] = acc[n];
+  block_sum_t<KBS, NS * K>(v, sh);
+  if (threadIdx.x < NS * K) {
     const int j = threadIdx.x / K, k = threadIdx.x % K;
     double val = 0.0;
 #pragma unroll
-    for (int q = 0; q < GMAX * K; ++q) val = (q == (int)threadIdx.x) ? out[q] : val;
-    if (j < ns) part[((size_t)lb * GMAX + j) * KP + k] = val;
+    for (int q = 0; q < NS * K; ++q) val = (q == (int)threadIdx.x) ? v[q] : val;
+    part[((size_t)lb * GMAX + j) * KP + k] = val;
   }
 }
 

@@ -8,14 +8,17 @@
 namespace ipcs {
 
 constexpr int BLOCK = 256;        // threads per block of small utility kernels
-constexpr int KBLOCK_MAX = 1024;  // largest Krylov block (threads = rows / vector entries)
-constexpr int KP = 4;             // partial sums per system per block
+constexpr int KBS = 256;          // threads per block of every Krylov kernel
+constexpr int KEPT_V = 4;         // vector entries per thread of Krylov vector kernels
+constexpr int KPART_Q = 16;       // partial records per thread a consumer block loads
+constexpr int KNB_MAX = KBS * KPART_Q;   // most producer blocks per group and kernel
+constexpr int KP = 8;             // partial sums per system per block
 constexpr int GMAX = 3;           // systems per group (velocity components)
 
 // Krylov system status (device-resident, polled by the host every few iterations)
 enum KStatus : int32_t {
   KS_RUN = 0,        // iterating
-  KS_PENDING = 1,    // recursive residual converged (or maxit): confirm with b - A x
+  KS_PENDING = 1,    // recursive residual converged: confirm with b - A x
   KS_DONE = 2,       // converged, true residual confirmed
   KS_ZERO = 3,       // b == 0: x := 0
   KS_RESTART = 4,    // BiCGStab breakdown: restart from the current x
@@ -24,28 +27,33 @@ enum KStatus : int32_t {
   KS_NONFINITE = -6
 };
 
-// Scalars of one Krylov system. Between kernels of one iteration they are
-// passed through these fields; a field is only written by block 0 of a kernel
-// in which no other block reads it (rho is double-buffered by iteration parity).
+// Scalars of one Krylov system. Iteration scalars are double-buffered by the
+// launch parity par the host passes: a kernel of parity par reads slot par^1
+// (PCG) or par (BiCGStab) and block 0 writes the other slot, so no block reads
+// a slot that another block of the same kernel writes. status is the one field
+// a kernel may both read and write: block 0 only ever writes a status that
+// every block derives from the same reduced values, so either value sends a
+// block down the same branch.
 struct KState {
   double bb, rr;              // ||b||^2, last ||r||^2
-  double rho[2];              // PCG r.z / BiCGStab rhat.r, by iteration parity
-  double alpha, omega;
+  double sc[2];               // PCG gamma = r.u, BiCGStab rho = rhat.r, by parity
+  double alpha[2];            // PCG alpha by parity; BiCGStab alpha in [0]
+  double omega;               // BiCGStab
   double tol2;                // tol^2
-  int32_t status, it, it0, maxit;   // it0: iteration of the last (re)start
-  int32_t par, tt_zero, nchecks, pad;
+  int32_t status, it, nchecks, pad;
 };
 
-// Vectors of one system (FP64). PCG: r, z, p[0..1] (by parity), q = A p.
-// BiCGStab: r, z = rhat, p[0] = p, q = v, s, t, phat, shat.
+// Vectors of one system (FP64).
+//   PCG (Chronopoulos-Gear form): r, u = D^{-1} r, p, s = A p, w = A u
+//   BiCGStab: r, u = rhat, p, s, w = v = A phat, t = A shat, phat, shat
 struct KVecs {
   const double* b;
   double* x;
   double* r;
-  double* z;
-  double* p[2];
-  double* q;
+  double* u;
+  double* p;
   double* s;
+  double* w;
   double* t;
   double* phat;
   double* shat;
@@ -53,19 +61,20 @@ struct KVecs {
 };
 
 // Up to GMAX systems that share one matrix (SELL-64 layout, FP64 values), so
-// the matrix is read once per row for all of them. Every Krylov kernel of a
-// group runs nblk = ceil(n / bs) blocks of the launch's block size bs, one
-// row or vector entry per thread.
+// the matrix is read once per row for all of them. Matrix kernels run
+// nblk_m = ceil(n / (KBS * ept_m)) blocks, vector kernels
+// nblk_v = ceil(n / (KBS * KEPT_V)); both are at most KNB_MAX. Partial sums:
+// part_m is written by matrix kernels, part_v[q] by vector kernels of launch
+// parity q^1; records are [block][GMAX][KP].
 struct KGroup {
   int32_t nsys, n;
   const int32_t* sptr;        // SELL slice offsets
   const int32_t* col;
   const double* val;
   const double* dinv;         // Jacobi: 1 / diag(A)
-  int32_t nblk;
-  int32_t pad;
-  double* part_m;             // [nblk][GMAX][KP] partials of matrix kernels
-  double* part_v;             // [nblk][GMAX][KP] partials of vector kernels
+  int32_t nblk_m, nblk_v;
+  double* part_m;
+  double* part_v[2];
   KVecs v[GMAX];
 };
 
@@ -110,23 +119,31 @@ void inv_diagonal(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* 
 void lift_values(hipStream_t s, int64_t nlift, const int32_t* slot, const double* M,
                  const double* K, double cm, double ck, double* out);
 
-// Krylov (kernels_krylov.hip): ngroups groups, bmap[nblocks] = (group, block)
+// Krylov (kernels_krylov.hip). A launch covers ngroups groups with the same
+// number of systems ns and matrix-kernel rows per thread ept_m; bmap_m/bmap_v
+// map blocks to (group, block in group) for matrix/vector kernels.
 struct KLaunch {
   const KGroup* groups;
   int ngroups;
-  const int2* bmap;
-  int nblocks;
-  int bs;            // threads per block: 256, 512 or 1024
+  int ns;            // systems per group: 1..GMAX
+  int ept_m;         // rows per thread of matrix kernels: 1, 2 or 4
+  const int2* bmap_m;
+  int nblocks_m;
+  const int2* bmap_v;
+  int nblocks_v;
 };
-void pcg_start(hipStream_t s, const KLaunch& L, int mode);    // mode 0 start, 1 confirm
-void pcg_iter(hipStream_t s, const KLaunch& L);
-void bicg_start(hipStream_t s, const KLaunch& L, int mode);
-void bicg_iter(hipStream_t s, const KLaunch& L);
+// Start (mode 0) or confirm/restart (mode 1, systems PENDING or RESTART):
+// r = b - A x, then the status decision. par is the parity of the next
+// iteration launch; exhausted turns a restart into MAXIT.
+void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted);
+void pcg_iter(hipStream_t s, const KLaunch& L, int par);
+void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted);
+void bicg_iter(hipStream_t s, const KLaunch& L, int par);
 void ksys_finish(hipStream_t s, const KLaunch& L);            // b == 0 systems: x := 0
 void gather_states(hipStream_t s, const KLaunch& L, KState* out);   // out[g*GMAX + j]
 // single kernels of an iteration, for timing
 void pcg_spmv_only(hipStream_t s, const KLaunch& L);
-void pcg_update_only(hipStream_t s, const KLaunch& L);
+void pcg_update_only(hipStream_t s, const KLaunch& L, int par);
 void bicg_spmv_only(hipStream_t s, const KLaunch& L);
 
 // Fields and right-hand sides (kernels_fields.hip)

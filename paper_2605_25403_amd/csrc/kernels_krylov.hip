@@ -1,37 +1,48 @@
 // Jacobi-preconditioned CG and BiCGStab for gfx950 on SELL-64 matrices.
 //
-// Layout and parallel shape. Matrices are stored in SELL-64 (see mesh.hpp):
-// a wavefront owns 64 consecutive rows, one row per lane, and reads column k
-// of its slice as one coalesced 64-wide load of values and of column indices;
-// only the gathers x[col] are irregular. The systems of a group share the
-// matrix (the velocity components of a run), so each matrix entry is loaded
-// once and applied to every active system's vector. Every kernel runs one row
-// or vector entry per thread in blocks of BS threads; a launch serves many
+// Parallel shape. Every kernel runs blocks of KBS = 256 threads (4 waves).
+// Matrix kernels give each thread ept_m rows; a wavefront owns 64 consecutive
+// rows, one per lane, and reads column k of its SELL slice as one coalesced
+// 64-wide load of values and of column indices. The loads of a row are batched
+// eight columns at a time: eight (column, value) loads, then the eight gathers
+// of every system, then the FMAs, so that eight gathers per system are in flight
+// per lane. Vector kernels give each thread KEPT_V entries. The systems of a
+// group share the matrix (the velocity components of a run): each matrix entry
+// is loaded once and applied to every system's vector. A launch serves many
 // groups through a (group, block) map, e.g. all runs of a serving batch.
 //
 // Reductions are fence-free and deterministic (dev_util.hpp): a kernel writes
-// per-block partials, the next kernel re-reduces them in every block. Each
-// kernel issues its independent loads (matrix entries, vector entries, the
-// producer's partials, the state words) before it first waits, so their
-// latencies overlap; scalars that depend on the reduction are applied last.
-// Scalars never leave the device; the host only polls status words.
+// one partial record per block, and every block of the next kernel re-reduces
+// all of them in a fixed order. Keeping blocks at 256 threads with several
+// entries per thread keeps the number of records small (at most KNB_MAX).
+// Each kernel issues its independent loads (state words, partial records,
+// vector entries) before its first wait; scalars that depend on the reduction
+// are applied last. Scalars never leave the device; the host polls status
+// words only.
 //
-// PCG (Saad 2003, Alg. 9.1), two kernels per iteration:
-//   spmv  : [r.z, r.r of the last update] -> convergence test, beta;
-//           q = A z + beta A p_{k-1} (= A p_k), p_k = z + beta p_{k-1}
-//           (double-buffered by iteration parity), partial p_k.q
-//   update: [p.q] -> alpha = rho/p.q; x += alpha p, r -= alpha q,
-//           z = D^{-1} r, partials r.z, r.r
-// BiCGStab (van der Vorst 1992, right preconditioning D^{-1}), five kernels:
-//   b1 [r.r, rhat.r] test, beta; p = r + beta (p - omega v), phat = D^{-1} p
-//   b2 v = A phat, partial rhat.v
-//   b3 [rhat.v] alpha; s = r - alpha v, shat = D^{-1} s
-//   b4 t = A shat, partials t.s, t.t
-//   b5 [t.s, t.t] omega; x += alpha phat + omega shat, r = s - omega t,
-//      partials r.r, rhat.r
+// PCG in the Chronopoulos-Gear form (one global reduction per iteration; the
+// iterates are those of Jacobi-PCG, Saad 2003 Alg. 9.1, in exact arithmetic),
+// with u = D^{-1} r, w = A u, s = A p:
+//   spmv  : w = A u, partial u.w                           (no prologue)
+//   update: [gamma = r.u, ||r||^2, delta = u.w] -> stop test;
+//           beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old);
+//           p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+//           u = D^{-1} r, partials r.u, r.r
+// BiCGStab (van der Vorst 1992, right preconditioning D^{-1}), four kernels:
+//   b2 v = A phat, partial rhat.v                          (no prologue)
+//   b3 [rhat.v, ||r||^2] stop test, alpha = rho / rhat.v; s = r - alpha v,
+//      shat = D^{-1} s
+//   b4 t = A shat, partials t.s, t.t, rhat.s, rhat.t       (no prologue)
+//   b5 [t.s, t.t, rhat.s, rhat.t] omega = t.s / t.t; x += alpha phat + omega shat,
+//      r = s - omega t; rho' = rhat.r = rhat.s - omega rhat.t, beta =
+//      (rho' / rho)(alpha / omega); p = r + beta (p - omega v), phat = D^{-1} p;
+//      partial r.r
 // Stopping rule: ||r||_2 <= tol ||b||_2 on the recursive residual, then
 // confirmed with b - A x (restart from x if it fails), up to maxit iterations.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "dev_util.hpp"
@@ -39,484 +50,561 @@
 
 namespace ipcs {
 
-#define GROUP_PROLOGUE                   \
-  const int2 m_ = bmap[blockIdx.x];      \
-  const KGroup& g = groups[m_.x];        \
-  const int lb = m_.y;                   \
-  const int ns = g.nsys;                 \
-  const int i = lb * BS + (int)threadIdx.x; \
-  const bool in = i < g.n;
+#define GROUP_HEAD(BMAP)                  \
+  const int2 m_ = (BMAP)[blockIdx.x];     \
+  const KGroup& g = groups[m_.x];         \
+  const int lb = m_.y;
 
-// SELL-64 row i: slice base and width
-struct SellRow {
-  int base, w;
-  __device__ __forceinline__ SellRow(const int32_t* sptr, int i) {
-    const int s = i >> 6;
-    const int b0 = sptr[s];
-    base = b0 + (i & 63);
-    w = (sptr[s + 1] - b0) >> 6;
+// Row i of the group's SELL-64 matrix applied to NS gathered vectors:
+// acc[j] = sum_k A(i, col_k) * gath(j, col_k). The slice width is uniform in
+// the wavefront; the last chunk of eight re-reads entry w-1 and discards it.
+template <int NS, class G>
+__device__ __forceinline__ void sell_row(const KGroup& g, int i, G gath, double (&acc)[NS]) {
+  const int s = i >> 6;
+  const int b0 = g.sptr[s];
+  const int w = (g.sptr[s + 1] - b0) >> 6;
+  const int base = b0 + (i & 63);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+  for (int k = 0; k < w; k += 8) {
+    int c[8];
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = k + q < w ? k + q : w - 1;
+      c[q] = g.col[base + 64 * kk];
+      a[q] = g.val[base + 64 * kk];
+    }
+    double xv[NS][8];
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[j][q] = gath(j, c[q]);
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[j] += k + q < w ? a[q] * xv[j][q] : 0.0;
   }
-};
+}
 
-__device__ __forceinline__ bool is_run(const KGroup& g, int j) {
-  return j < g.nsys && g.v[j].st->status == KS_RUN;
+template <int EPT>
+__device__ __forceinline__ int row_of(int lb, int e) {
+  return (lb * EPT + e) * KBS + (int)threadIdx.x;
 }
 
 // ------------------------------------------------------------------ start / confirm
-// r = b - A x and partials r.r, r.z (PCG; rhat.r = r.r for BiCGStab), b.b for
-// systems that start (mode 0: all) or are confirmed (mode 1: status PENDING
-// or RESTART).
-template <bool PCG, int BS>
-__global__ void __launch_bounds__(BS) k_start(const KGroup* groups, const int2* bmap,
-                                                  int mode) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool act[GMAX];
+// r = b - A x for the systems that start (mode 0: all) or are confirmed
+// (mode 1: PENDING or RESTART). PCG: u = D^{-1} r, p = s = 0. BiCGStab:
+// rhat = p = r, phat = D^{-1} r. Partials r.r, r.u, b.b.
+template <bool PCG, int NS, int EPT>
+__global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2* bmap, int mode) {
+  GROUP_HEAD(bmap)
+  __shared__ double sh[(KBS / 64) * NS * 3];
+  bool act[NS];
+  bool any = false;
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    act[j] = false;
-    if (j < ns) {
-      const int st = g.v[j].st->status;
-      act[j] = mode == 0 || st == KS_PENDING || st == KS_RESTART;
+  for (int j = 0; j < NS; ++j) {
+    const int st = g.v[j].st->status;
+    act[j] = mode == 0 || st == KS_PENDING || st == KS_RESTART;
+    any |= act[j];
+  }
+  double acc[NS * 3] = {};
+  if (any) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = row_of<EPT>(lb, e);
+      if (i >= g.n) continue;
+      double ax[NS];
+      sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].x[c]; }, ax);
+      const double di = g.dinv[i];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        if (!act[j]) continue;
+        const KVecs& V = g.v[j];
+        const double bi = V.b[i], r = bi - ax[j];
+        V.r[i] = r;
+        if (PCG) {
+          const double u = di * r;
+          V.u[i] = u;
+          V.p[i] = 0.0;
+          V.s[i] = 0.0;
+          acc[j * 3 + 1] += r * u;
+        } else {
+          V.u[i] = r;
+          V.p[i] = r;
+          V.phat[i] = di * r;
+          acc[j * 3 + 1] += r * r;
+        }
+        acc[j * 3 + 0] += r * r;
+        acc[j * 3 + 2] += bi * bi;
+      }
     }
   }
-  double acc[GMAX][3] = {};
-  if (in) {
-    const SellRow R(g.sptr, i);
-    double ax[GMAX] = {};
-    for (int k = 0; k < R.w; ++k) {
-      const int idx = R.base + 64 * k;
-      const double a = g.val[idx];
-      const int c = g.col[idx];
-#pragma unroll
-      for (int j = 0; j < GMAX; ++j)
-        if (act[j]) ax[j] += a * g.v[j].x[c];
-    }
-#pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!act[j]) continue;
-      const KVecs& V = g.v[j];
-      const double bi = V.b[i], r = bi - ax[j];
-      V.r[i] = r;
-      double z = r;
-      if (PCG) z = g.dinv[i] * r;
-      V.z[i] = z;   // PCG: z = D^{-1} r; BiCGStab: rhat = r
-      acc[j][0] = r * r;
-      acc[j][1] = r * z;
-      acc[j][2] = bi * bi;
-    }
-  }
-  store_partials<3>(acc, ns, g.part_m, lb, sh);
+  store_partials<NS, 3>(acc, g.part_m, lb, sh);
 }
 
 // One block per group: decide the status of the systems that were started or
-// confirmed, and seed the partials the first iteration reduces.
-template <bool PCG>
-__global__ void __launch_bounds__(1024) k_decide(const KGroup* groups, int mode) {
+// confirmed, initialize their scalars for an iteration of launch parity par,
+// and seed the partials that iteration's first vector kernel reduces.
+template <bool PCG, int NS>
+__global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, int par,
+                                                int exhausted) {
   const KGroup& g = groups[blockIdx.x];
-  const int ns = g.nsys;
-  __shared__ double sh[16 * GMAX * 3];
-  Partials<3> P;
-  P.load(g.part_m, g.nblk, ns);
-  double tot[GMAX][3];
-  P.reduce(ns, tot, sh);
-  __shared__ int act_s[GMAX];
+  __shared__ double sh[(KBS / 64) * NS * 3];
+  __shared__ int run_s[NS];
+  double tot[NS * 3];
+  load_partials<NS, 3>(g.part_m, g.nblk_m, tot);
+  block_sum_t<KBS, NS * 3>(tot, sh);
   if (threadIdx.x == 0) {
-    for (int j = 0; j < GMAX; ++j) {
-      act_s[j] = 0;
-      if (j >= ns) continue;
+    for (int j = 0; j < NS; ++j) {
+      run_s[j] = 0;
       KState* st = g.v[j].st;
-      const bool part = mode == 0 || st->status == KS_PENDING || st->status == KS_RESTART;
+      const int s0 = st->status;
+      const bool part = mode == 0 || s0 == KS_PENDING || s0 == KS_RESTART;
       if (!part) continue;
       if (mode == 0) {
-        st->bb = tot[j][2];
+        st->bb = tot[j * 3 + 2];
         st->it = 0;
         st->nchecks = 0;
       } else {
         st->nchecks += 1;
       }
-      const double bb = st->bb, rr = tot[j][0];
+      const double bb = st->bb, rr = tot[j * 3];
       st->rr = rr;
       int nst = KS_RUN;
       if (bb == 0.0) nst = KS_ZERO;
       else if (!finite(rr)) nst = KS_NONFINITE;
       else if (rr <= st->tol2 * bb) nst = KS_DONE;
-      else if (mode != 0 && st->it >= st->maxit) nst = KS_MAXIT;
+      else if (exhausted) nst = KS_MAXIT;
       st->status = nst;
-      if (nst == KS_RUN) {
-        st->it0 = st->it;
-        st->alpha = 1.0;
+      if (nst != KS_RUN) continue;
+      if (PCG) {
+        st->sc[par ^ 1] = INFINITY;   // beta = gamma / inf = 0 on the first iteration
+        st->alpha[par ^ 1] = 1.0;
+      } else {
+        st->sc[par] = rr;             // rho_0 = rhat.r = r.r
         st->omega = 1.0;
-        st->tt_zero = 0;
-        act_s[j] = 1;
       }
+      run_s[j] = 1;
     }
   }
   __syncthreads();
-  // the first iteration reduces part_v and must find (r.z, r.r) for PCG or
-  // (r.r, rhat.r) for BiCGStab; only block 0's slot is non-zero
-  for (int b = threadIdx.x; b < g.nblk; b += blockDim.x)
-    for (int j = 0; j < ns; ++j) {
-      if (!act_s[j]) continue;
-      double* p = g.part_v + ((size_t)b * GMAX + j) * KP;
-      p[0] = b == 0 ? (PCG ? tot[j][1] : tot[j][0]) : 0.0;
-      p[1] = b == 0 ? tot[j][0] : 0.0;
+  for (int b = threadIdx.x; b < g.nblk_v; b += KBS)
+    for (int j = 0; j < NS; ++j) {
+      if (!run_s[j]) continue;
+      double* p = g.part_v[par] + ((size_t)b * GMAX + j) * KP;
+      p[0] = b == 0 ? (PCG ? tot[j * 3 + 1] : tot[j * 3]) : 0.0;
+      p[1] = b == 0 ? tot[j * 3] : 0.0;
     }
 }
 
-// ------------------------------------------------------------------ PCG
-template <int BS>
-__global__ void __launch_bounds__(BS) k_pcg_spmv(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  // state words (uniform loads), issued first
-  bool run[GMAX];
-  int par[GMAX];
-#pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    run[j] = is_run(g, j);
-    par[j] = j < ns ? (g.v[j].st->it & 1) : 0;
-  }
-  // A z and A p_{k-1}, independent of beta: their loads overlap the reduction
-  double az[GMAX] = {}, ap[GMAX] = {}, zi[GMAX] = {}, poi[GMAX] = {};
-  if (in) {
-    const SellRow R(g.sptr, i);
-    for (int k = 0; k < R.w; ++k) {
-      const int idx = R.base + 64 * k;
-      const double a = g.val[idx];
-      const int c = g.col[idx];
-#pragma unroll
-      for (int j = 0; j < GMAX; ++j) {
-        if (!run[j]) continue;
-        const KVecs& V = g.v[j];
-        az[j] += a * V.z[c];
-        ap[j] += a * V.p[par[j] ^ 1][c];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!run[j]) continue;
-      zi[j] = g.v[j].z[i];
-      poi[j] = g.v[j].p[par[j] ^ 1][i];
-    }
-  }
-  Partials<2> Pv;
-  Pv.load(g.part_v, g.nblk, ns);   // (r.z, r.r) of the last update
-  double tot[GMAX][2];
-  Pv.reduce(ns, tot, sh);
-  double acc[GMAX][1] = {};
+// ------------------------------------------------------------------ PCG (Chronopoulos-Gear)
+template <int NS, int EPT>
+__global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int2* bmap) {
+  GROUP_HEAD(bmap)
+  __shared__ double sh[(KBS / 64) * NS];
+  bool run[NS];
   bool any = false;
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    if (!run[j]) continue;
-    KState* st = g.v[j].st;
-    const int it = st->it;
-    const bool first = it == st->it0;
-    const double rz = tot[j][0], rr = tot[j][1];
-    bool a = true;
-    double beta = 0.0;
-    if (!first) {
-      if (!finite(rr)) {
-        a = false;
-        if (lb == 0 && threadIdx.x == 0) st->status = KS_NONFINITE;
-      } else if (rr <= st->tol2 * st->bb || it >= st->maxit) {
-        a = false;
-        if (lb == 0 && threadIdx.x == 0) {
-          st->status = KS_PENDING;
-          st->rr = rr;
-        }
-      } else {
-        beta = rz / st->rho[par[j] ^ 1];
-      }
-    }
-    if (!a) continue;
-    any = true;
-    if (lb == 0 && threadIdx.x == 0) {
-      st->rho[par[j]] = rz;
-      st->par = par[j];
-      st->rr = rr;
-    }
-    if (in) {
-      const KVecs& V = g.v[j];
-      const double q = first ? az[j] : az[j] + beta * ap[j];
-      const double pi = first ? zi[j] : zi[j] + beta * poi[j];
-      V.p[par[j]][i] = pi;
-      V.q[i] = q;
-      acc[j][0] = pi * q;
+  for (int j = 0; j < NS; ++j) {
+    run[j] = g.v[j].st->status == KS_RUN;
+    any |= run[j];
+  }
+  double y[EPT][NS], ui[EPT][NS];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = row_of<EPT>(lb, e);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) y[e][j] = ui[e][j] = 0.0;
+    if (i < g.n) {
+      sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].u[c]; }, y[e]);
+#pragma unroll
+      for (int j = 0; j < NS; ++j) ui[e][j] = g.v[j].u[i];
     }
   }
-  // every thread took the same decisions; the block-wide OR makes the exit
-  // provably uniform before the barriers in store_partials
-  if (!__syncthreads_or(any)) return;
-  store_partials<1>(acc, ns, g.part_m, lb, sh);
+  if (!any) return;   // uniform: the states were written by an earlier kernel
+  double acc[NS] = {};
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = row_of<EPT>(lb, e);
+    if (i >= g.n) continue;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      if (!run[j]) continue;
+      g.v[j].w[i] = y[e][j];
+      acc[j] += y[e][j] * ui[e][j];
+    }
+  }
+  store_partials<NS, 1>(acc, g.part_m, lb, sh);
 }
 
-template <int BS>
-__global__ void __launch_bounds__(BS) k_pcg_update(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool run[GMAX];
-  int par[GMAX];
+template <int NS>
+__global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const int2* bmap,
+                                                   int par) {
+  GROUP_HEAD(bmap)
+  __shared__ double sh[(KBS / 64) * NS * 3];
+  int status[NS];
+  double g_old[NS], a_old[NS], lim[NS];
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    run[j] = is_run(g, j);
-    par[j] = j < ns ? g.v[j].st->par : 0;
+  for (int j = 0; j < NS; ++j) {
+    const KState* st = g.v[j].st;
+    status[j] = st->status;
+    g_old[j] = st->sc[par ^ 1];
+    a_old[j] = st->alpha[par ^ 1];
+    lim[j] = st->tol2 * st->bb;
   }
-  double xi[GMAX] = {}, pi[GMAX] = {}, ri[GMAX] = {}, qi[GMAX] = {};
-  double di = 0.0;
-  if (in) {
-    di = g.dinv[i];
+  double t[NS * 3];
+  {
+    double a[NS * 2], b[NS];
+    load_partials<NS, 2>(g.part_v[par], g.nblk_v, a);
+    load_partials<NS, 1>(g.part_m, g.nblk_m, b);
 #pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!run[j]) continue;
-      const KVecs& V = g.v[j];
-      xi[j] = V.x[i];
-      pi[j] = V.p[par[j]][i];
-      ri[j] = V.r[i];
-      qi[j] = V.q[i];
+    for (int j = 0; j < NS; ++j) {
+      t[j * 3 + 0] = a[j * 2];
+      t[j * 3 + 1] = a[j * 2 + 1];
+      t[j * 3 + 2] = b[j];
     }
   }
-  Partials<1> Pm;
-  Pm.load(g.part_m, g.nblk, ns);   // p.q
-  double tot[GMAX][1];
-  Pm.reduce(ns, tot, sh);
-  double acc[GMAX][2] = {};
+  double di[KEPT_V], xi[KEPT_V][NS], ri[KEPT_V][NS], pi[KEPT_V][NS], si[KEPT_V][NS],
+      wi[KEPT_V][NS];
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    if (!run[j]) continue;
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    const bool in = i < g.n;
+    di[e] = in ? g.dinv[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const KVecs& V = g.v[j];
+      xi[e][j] = in ? V.x[i] : 0.0;
+      ri[e][j] = in ? V.r[i] : 0.0;
+      pi[e][j] = in ? V.p[i] : 0.0;
+      si[e][j] = in ? V.s[i] : 0.0;
+      wi[e][j] = in ? V.w[i] : 0.0;
+    }
+  }
+  block_sum_t<KBS, NS * 3>(t, sh);
+  const bool lead = lb == 0 && threadIdx.x == 0;
+  bool go[NS];
+  double al[NS], be[NS];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    go[j] = false;
+    al[j] = be[j] = 0.0;
+    if (status[j] != KS_RUN) continue;
     KState* st = g.v[j].st;
-    const double pq = tot[j][0];
-    if (!finite(pq)) {
-      if (lb == 0 && threadIdx.x == 0) st->status = KS_NONFINITE;
+    const double gam = t[j * 3], rr = t[j * 3 + 1], del = t[j * 3 + 2];
+    if (!(finite(gam) && finite(rr) && finite(del))) {
+      if (lead) st->status = KS_NONFINITE;
       continue;
     }
-    if (!(pq > 0.0)) {
-      if (lb == 0 && threadIdx.x == 0) st->status = KS_BREAKDOWN;
+    if (rr <= lim[j]) {
+      if (lead) {
+        st->status = KS_PENDING;
+        st->rr = rr;
+      }
       continue;
     }
-    const double alpha = st->rho[par[j]] / pq;
-    if (lb == 0 && threadIdx.x == 0) st->it += 1;
-    if (in) {
+    const double beta = gam / g_old[j];
+    const double den = del - beta * gam / a_old[j];
+    if (!(den > 0.0)) {
+      if (lead) st->status = KS_BREAKDOWN;
+      continue;
+    }
+    const double alpha = gam / den;
+    if (lead) {
+      st->sc[par] = gam;
+      st->alpha[par] = alpha;
+      st->rr = rr;
+      st->it += 1;
+    }
+    go[j] = true;
+    al[j] = alpha;
+    be[j] = beta;
+    any = true;
+  }
+  if (!any) return;   // uniform: every thread took the same decisions
+  double acc[NS * 2] = {};
+#pragma unroll
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    if (i >= g.n) continue;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      if (!go[j]) continue;
       const KVecs& V = g.v[j];
-      V.x[i] = xi[j] + alpha * pi[j];
-      const double r = ri[j] - alpha * qi[j];
-      const double z = di * r;
+      const double p = di[e] * ri[e][j] + be[j] * pi[e][j];
+      const double s = wi[e][j] + be[j] * si[e][j];
+      const double x = xi[e][j] + al[j] * p;
+      const double r = ri[e][j] - al[j] * s;
+      const double u = di[e] * r;
+      V.x[i] = x;
       V.r[i] = r;
-      V.z[i] = z;
-      acc[j][0] = r * z;
-      acc[j][1] = r * r;
+      V.p[i] = p;
+      V.s[i] = s;
+      V.u[i] = u;
+      acc[j * 2] += r * u;
+      acc[j * 2 + 1] += r * r;
     }
   }
-  store_partials<2>(acc, ns, g.part_v, lb, sh);
+  store_partials<NS, 2>(acc, g.part_v[par ^ 1], lb, sh);
 }
 
 // ------------------------------------------------------------------ BiCGStab
-template <int BS>
-__global__ void __launch_bounds__(BS) k_bicg_1(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool run[GMAX];
-#pragma unroll
-  for (int j = 0; j < GMAX; ++j) run[j] = is_run(g, j);
-  double ri[GMAX] = {}, pi[GMAX] = {}, vi[GMAX] = {};
-  double di = 0.0;
-  if (in) {
-    di = g.dinv[i];
-#pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!run[j]) continue;
-      ri[j] = g.v[j].r[i];
-      pi[j] = g.v[j].p[0][i];
-      vi[j] = g.v[j].q[i];
-    }
-  }
-  Partials<2> Pv;
-  Pv.load(g.part_v, g.nblk, ns);   // (r.r, rhat.r)
-  double tot[GMAX][2];
-  Pv.reduce(ns, tot, sh);
-#pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    if (!run[j]) continue;
-    KState* st = g.v[j].st;
-    const int it = st->it, par = it & 1;
-    const bool first = it == st->it0;
-    const double rr = tot[j][0], rhr = tot[j][1], omega = st->omega;
-    double beta = 0.0;
-    if (!first) {
-      const bool lead = lb == 0 && threadIdx.x == 0;
-      if (!finite(rr)) {
-        if (lead) st->status = KS_NONFINITE;
-        continue;
-      }
-      if (rr <= st->tol2 * st->bb || st->tt_zero || it >= st->maxit) {
-        if (lead) {
-          st->status = KS_PENDING;
-          st->rr = rr;
-        }
-        continue;
-      }
-      if (fabs(omega) < 1e-300 || fabs(rhr) < 1e-300) {
-        if (lead) {
-          st->status = KS_RESTART;
-          st->rr = rr;
-        }
-        continue;
-      }
-      beta = (rhr / st->rho[par ^ 1]) * (st->alpha / omega);
-    }
-    if (lb == 0 && threadIdx.x == 0) {
-      st->rho[par] = rhr;
-      st->par = par;
-      st->rr = rr;
-    }
-    if (in) {
-      const double p = first ? ri[j] : ri[j] + beta * (pi[j] - omega * vi[j]);
-      g.v[j].p[0][i] = p;
-      g.v[j].phat[i] = di * p;
-    }
-  }
-}
-
-// WHICH = 0: v = A phat, partial rhat.v;  WHICH = 1: t = A shat, partials t.s, t.t
-template <int WHICH, int BS>
-__global__ void __launch_bounds__(BS) k_bicg_spmv(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool run[GMAX];
+// b2 (WHICH = 0): v = A phat, partial rhat.v
+// b4 (WHICH = 1): t = A shat, partials t.s, t.t, rhat.s, rhat.t
+template <int WHICH, int NS, int EPT>
+__global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const int2* bmap) {
+  GROUP_HEAD(bmap)
+  constexpr int K = WHICH == 0 ? 1 : 4;
+  __shared__ double sh[(KBS / 64) * NS * K];
+  bool run[NS];
   bool any = false;
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    run[j] = is_run(g, j);
+  for (int j = 0; j < NS; ++j) {
+    run[j] = g.v[j].st->status == KS_RUN;
     any |= run[j];
   }
-  if (!__syncthreads_or(any)) return;
-  double acc[GMAX][2] = {};
-  if (in) {
-    const SellRow R(g.sptr, i);
-    double y[GMAX] = {};
-    for (int k = 0; k < R.w; ++k) {
-      const int idx = R.base + 64 * k;
-      const double a = g.val[idx];
-      const int c = g.col[idx];
+  double y[EPT][NS], rh[EPT][NS], si[EPT][NS];
 #pragma unroll
-      for (int j = 0; j < GMAX; ++j)
-        if (run[j]) y[j] += a * (WHICH == 0 ? g.v[j].phat[c] : g.v[j].shat[c]);
-    }
+  for (int e = 0; e < EPT; ++e) {
+    const int i = row_of<EPT>(lb, e);
 #pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!run[j]) continue;
-      const KVecs& V = g.v[j];
-      if (WHICH == 0) {
-        V.q[i] = y[j];
-        acc[j][0] = V.z[i] * y[j];
-      } else {
-        V.t[i] = y[j];
-        acc[j][0] = y[j] * V.s[i];
-        acc[j][1] = y[j] * y[j];
+    for (int j = 0; j < NS; ++j) y[e][j] = rh[e][j] = si[e][j] = 0.0;
+    if (i < g.n) {
+      if (WHICH == 0)
+        sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].phat[c]; }, y[e]);
+      else
+        sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].shat[c]; }, y[e]);
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        rh[e][j] = g.v[j].u[i];
+        if (WHICH == 1) si[e][j] = g.v[j].s[i];
       }
     }
   }
-  store_partials<2>(acc, ns, g.part_m, lb, sh);
-}
-
-template <int BS>
-__global__ void __launch_bounds__(BS) k_bicg_3(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool run[GMAX];
+  if (!any) return;
+  double acc[NS * K] = {};
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) run[j] = is_run(g, j);
-  double ri[GMAX] = {}, vi[GMAX] = {};
-  double di = 0.0;
-  if (in) {
-    di = g.dinv[i];
+  for (int e = 0; e < EPT; ++e) {
+    const int i = row_of<EPT>(lb, e);
+    if (i >= g.n) continue;
 #pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
+    for (int j = 0; j < NS; ++j) {
       if (!run[j]) continue;
-      ri[j] = g.v[j].r[i];
-      vi[j] = g.v[j].q[i];
+      const double yv = y[e][j];
+      if (WHICH == 0) {
+        g.v[j].w[i] = yv;
+        acc[j * K] += rh[e][j] * yv;
+      } else {
+        g.v[j].t[i] = yv;
+        acc[j * K + 0] += yv * si[e][j];
+        acc[j * K + 1] += yv * yv;
+        acc[j * K + 2] += rh[e][j] * si[e][j];
+        acc[j * K + 3] += rh[e][j] * yv;
+      }
     }
   }
-  Partials<1> Pm;
-  Pm.load(g.part_m, g.nblk, ns);   // rhat.v
-  double tot[GMAX][1];
-  Pm.reduce(ns, tot, sh);
+  store_partials<NS, K>(acc, g.part_m, lb, sh);
+}
+
+template <int NS>
+__global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2* bmap, int par) {
+  GROUP_HEAD(bmap)
+  __shared__ double sh[(KBS / 64) * NS * 2];
+  int status[NS];
+  double rho[NS], lim[NS];
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    if (!run[j]) continue;
+  for (int j = 0; j < NS; ++j) {
+    const KState* st = g.v[j].st;
+    status[j] = st->status;
+    rho[j] = st->sc[par];
+    lim[j] = st->tol2 * st->bb;
+  }
+  double t[NS * 2];
+  {
+    double a[NS], b[NS];
+    load_partials<NS, 1>(g.part_m, g.nblk_m, a);      // rhat.v
+    load_partials<NS, 1>(g.part_v[par], g.nblk_v, b); // r.r
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      t[j * 2] = a[j];
+      t[j * 2 + 1] = b[j];
+    }
+  }
+  double di[KEPT_V], ri[KEPT_V][NS], vi[KEPT_V][NS];
+#pragma unroll
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    const bool in = i < g.n;
+    di[e] = in ? g.dinv[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      ri[e][j] = in ? g.v[j].r[i] : 0.0;
+      vi[e][j] = in ? g.v[j].w[i] : 0.0;
+    }
+  }
+  block_sum_t<KBS, NS * 2>(t, sh);
+  const bool lead = lb == 0 && threadIdx.x == 0;
+  bool go[NS];
+  double al[NS];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    go[j] = false;
+    al[j] = 0.0;
+    if (status[j] != KS_RUN) continue;
     KState* st = g.v[j].st;
-    const double alpha = st->rho[st->par] / tot[j][0];
-    if (!finite(alpha)) {
-      if (lb == 0 && threadIdx.x == 0) st->status = KS_NONFINITE;
+    const double rv = t[j * 2], rr = t[j * 2 + 1];
+    if (!(finite(rv) && finite(rr))) {
+      if (lead) st->status = KS_NONFINITE;
       continue;
     }
-    if (lb == 0 && threadIdx.x == 0) st->alpha = alpha;
-    if (in) {
-      const double s = ri[j] - alpha * vi[j];
+    if (rr <= lim[j]) {
+      if (lead) {
+        st->status = KS_PENDING;
+        st->rr = rr;
+      }
+      continue;
+    }
+    const double alpha = rho[j] / rv;
+    if (!(std::fabs(rv) >= 1e-300) || !finite(alpha)) {
+      if (lead) {
+        st->status = KS_RESTART;
+        st->rr = rr;
+      }
+      continue;
+    }
+    if (lead) {
+      st->alpha[0] = alpha;
+      st->rr = rr;
+    }
+    go[j] = true;
+    al[j] = alpha;
+    any = true;
+  }
+  if (!any) return;
+#pragma unroll
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    if (i >= g.n) continue;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      if (!go[j]) continue;
+      const double s = ri[e][j] - al[j] * vi[e][j];
       g.v[j].s[i] = s;
-      g.v[j].shat[i] = di * s;
+      g.v[j].shat[i] = di[e] * s;
     }
   }
 }
 
-template <int BS>
-__global__ void __launch_bounds__(BS) k_bicg_5(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  __shared__ double sh[16 * GMAX * 3];
-  bool run[GMAX];
+template <int NS>
+__global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2* bmap, int par) {
+  GROUP_HEAD(bmap)
+  __shared__ double sh[(KBS / 64) * NS * 4];
+  int status[NS];
+  double rho[NS], alpha[NS];
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) run[j] = is_run(g, j);
-  double xi[GMAX] = {}, phi[GMAX] = {}, shi[GMAX] = {}, si[GMAX] = {}, ti[GMAX] = {},
-         rhi[GMAX] = {};
-  if (in) {
+  for (int j = 0; j < NS; ++j) {
+    const KState* st = g.v[j].st;
+    status[j] = st->status;
+    rho[j] = st->sc[par];
+    alpha[j] = st->alpha[0];
+  }
+  double t[NS * 4];
+  load_partials<NS, 4>(g.part_m, g.nblk_m, t);   // t.s, t.t, rhat.s, rhat.t
+  double di[KEPT_V], xi[KEPT_V][NS], phi[KEPT_V][NS], shi[KEPT_V][NS], si[KEPT_V][NS],
+      ti[KEPT_V][NS], pi[KEPT_V][NS], vi[KEPT_V][NS];
 #pragma unroll
-    for (int j = 0; j < GMAX; ++j) {
-      if (!run[j]) continue;
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    const bool in = i < g.n;
+    di[e] = in ? g.dinv[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
       const KVecs& V = g.v[j];
-      xi[j] = V.x[i];
-      phi[j] = V.phat[i];
-      shi[j] = V.shat[i];
-      si[j] = V.s[i];
-      ti[j] = V.t[i];
-      rhi[j] = V.z[i];
+      xi[e][j] = in ? V.x[i] : 0.0;
+      phi[e][j] = in ? V.phat[i] : 0.0;
+      shi[e][j] = in ? V.shat[i] : 0.0;
+      si[e][j] = in ? V.s[i] : 0.0;
+      ti[e][j] = in ? V.t[i] : 0.0;
+      pi[e][j] = in ? V.p[i] : 0.0;
+      vi[e][j] = in ? V.w[i] : 0.0;
     }
   }
-  Partials<2> Pm;
-  Pm.load(g.part_m, g.nblk, ns);   // (t.s, t.t)
-  double tot[GMAX][2];
-  Pm.reduce(ns, tot, sh);
-  double acc[GMAX][2] = {};
+  block_sum_t<KBS, NS * 4>(t, sh);
+  const bool lead = lb == 0 && threadIdx.x == 0;
+  bool go[NS], full[NS];
+  double om[NS], be[NS];
+  bool any = false;
 #pragma unroll
-  for (int j = 0; j < GMAX; ++j) {
-    if (!run[j]) continue;
+  for (int j = 0; j < NS; ++j) {
+    go[j] = full[j] = false;
+    om[j] = be[j] = 0.0;
+    if (status[j] != KS_RUN) continue;
     KState* st = g.v[j].st;
-    const double alpha = st->alpha;
-    const bool zero = tot[j][1] == 0.0;
-    const double omega = zero ? 0.0 : tot[j][0] / tot[j][1];
-    if (lb == 0 && threadIdx.x == 0) {
-      st->omega = omega;
-      st->tt_zero = zero;
-      st->it += 1;
+    const double ts = t[j * 4], tt = t[j * 4 + 1], rs = t[j * 4 + 2], rt = t[j * 4 + 3];
+    if (!(finite(ts) && finite(tt) && finite(rs) && finite(rt))) {
+      if (lead) st->status = KS_NONFINITE;
+      continue;
     }
-    if (in) {
+    // t.t == 0 means A shat = 0, so s = 0: x + alpha phat solves the system
+    const double omega = tt == 0.0 ? 0.0 : ts / tt;
+    const double rho_n = rs - omega * rt;
+    const double beta = (rho_n / rho[j]) * (alpha[j] / omega);
+    int nst = KS_RUN;
+    if (tt == 0.0) nst = KS_PENDING;
+    else if (!(std::fabs(omega) >= 1e-300) || !(std::fabs(rho_n) >= 1e-300) || !finite(beta))
+      nst = KS_RESTART;
+    if (lead) {
+      st->sc[par ^ 1] = rho_n;
+      st->omega = omega;
+      st->it += 1;
+      if (nst != KS_RUN) st->status = nst;
+    }
+    go[j] = true;
+    full[j] = nst == KS_RUN;
+    om[j] = omega;
+    be[j] = beta;
+    any = true;
+  }
+  if (!any) return;
+  double acc[NS] = {};
+#pragma unroll
+  for (int e = 0; e < KEPT_V; ++e) {
+    const int i = row_of<KEPT_V>(lb, e);
+    if (i >= g.n) continue;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      if (!go[j]) continue;
       const KVecs& V = g.v[j];
-      V.x[i] = xi[j] + alpha * phi[j] + omega * shi[j];
-      const double r = si[j] - omega * ti[j];
+      V.x[i] = xi[e][j] + alpha[j] * phi[e][j] + om[j] * shi[e][j];
+      const double r = si[e][j] - om[j] * ti[e][j];
       V.r[i] = r;
-      acc[j][0] = r * r;
-      acc[j][1] = rhi[j] * r;
+      acc[j] += r * r;
+      if (full[j]) {
+        const double p = r + be[j] * (pi[e][j] - om[j] * vi[e][j]);
+        V.p[i] = p;
+        V.phat[i] = di[e] * p;
+      }
     }
   }
-  store_partials<2>(acc, ns, g.part_v, lb, sh);
+  store_partials<NS, 1>(acc, g.part_v[par ^ 1], lb, sh);
 }
 
 // ------------------------------------------------------------------ finish / poll
-template <int BS>
-__global__ void __launch_bounds__(BS) k_finish(const KGroup* groups, const int2* bmap) {
-  GROUP_PROLOGUE
-  if (!in) return;
-  for (int j = 0; j < ns; ++j)
-    if (g.v[j].st->status == KS_ZERO) g.v[j].x[i] = 0.0;
+template <int NS>
+__global__ void __launch_bounds__(KBS) k_finish(const KGroup* groups, const int2* bmap) {
+  GROUP_HEAD(bmap)
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    if (g.v[j].st->status != KS_ZERO) continue;
+#pragma unroll
+    for (int e = 0; e < KEPT_V; ++e) {
+      const int i = row_of<KEPT_V>(lb, e);
+      if (i < g.n) g.v[j].x[i] = 0.0;
+    }
+  }
 }
 
 __global__ void k_gather_states(const KGroup* groups, int ngroups, KState* out) {
@@ -526,65 +614,110 @@ __global__ void k_gather_states(const KGroup* groups, int ngroups, KState* out) 
 }
 
 // ------------------------------------------------------------------ launchers
-#define LK(KER, L, s, ...)                                                                     \
-  do {                                                                                         \
-    switch ((L).bs) {                                                                          \
-      case 256: hipLaunchKernelGGL(KER<256>, dim3((L).nblocks), dim3(256), 0, s, (L).groups,  \
-                                   (L).bmap, ##__VA_ARGS__); break;                            \
-      case 512: hipLaunchKernelGGL(KER<512>, dim3((L).nblocks), dim3(512), 0, s, (L).groups,  \
-                                   (L).bmap, ##__VA_ARGS__); break;                            \
-      case 1024: hipLaunchKernelGGL(KER<1024>, dim3((L).nblocks), dim3(1024), 0, s,           \
-                                    (L).groups, (L).bmap, ##__VA_ARGS__); break;               \
-      default: fail(IPCS_E_INVALID, "unsupported Krylov block size");                         \
-    }                                                                                          \
-    HIP_LAUNCH_OK();                                                                           \
-  } while (0)
+template <int V>
+using ic = std::integral_constant<int, V>;
 
-#define K_START_PCG(B) k_start<true, B>
-#define K_START_BICG(B) k_start<false, B>
-#define K_SPMV0(B) k_bicg_spmv<0, B>
-#define K_SPMV1(B) k_bicg_spmv<1, B>
+template <class F>
+static void with_ns(int ns, F f) {
+  switch (ns) {
+    case 1: f(ic<1>{}); break;
+    case 2: f(ic<2>{}); break;
+    case 3: f(ic<3>{}); break;
+    default: fail(IPCS_E_INVALID, "Krylov groups hold 1 to 3 systems");
+  }
+}
 
-#define LK2(KMAC, L, s, ...)                                                                   \
-  do {                                                                                         \
-    switch ((L).bs) {                                                                          \
-      case 256: hipLaunchKernelGGL(KMAC(256), dim3((L).nblocks), dim3(256), 0, s, (L).groups, \
-                                   (L).bmap, ##__VA_ARGS__); break;                            \
-      case 512: hipLaunchKernelGGL(KMAC(512), dim3((L).nblocks), dim3(512), 0, s, (L).groups, \
-                                   (L).bmap, ##__VA_ARGS__); break;                            \
-      case 1024: hipLaunchKernelGGL(KMAC(1024), dim3((L).nblocks), dim3(1024), 0, s,          \
-                                    (L).groups, (L).bmap, ##__VA_ARGS__); break;               \
-      default: fail(IPCS_E_INVALID, "unsupported Krylov block size");                         \
-    }                                                                                          \
-    HIP_LAUNCH_OK();                                                                           \
-  } while (0)
+template <class F>
+static void with_ns_ept(int ns, int ept, F f) {
+  with_ns(ns, [&](auto N) {
+    switch (ept) {
+      case 1: f(N, ic<1>{}); break;
+      case 2: f(N, ic<2>{}); break;
+      case 4: f(N, ic<4>{}); break;
+      default: fail(IPCS_E_INVALID, "matrix kernels take 1, 2 or 4 rows per thread");
+    }
+  });
+}
 
-void pcg_start(hipStream_t s, const KLaunch& L, int mode) {
-  LK2(K_START_PCG, L, s, mode);
-  hipLaunchKernelGGL(k_decide<true>, dim3(L.ngroups), dim3(1024), 0, s, L.groups, mode);
+#define NSV decltype(N)::value
+#define EPTV decltype(E)::value
+
+template <bool PCG>
+static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
+  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
+    hipLaunchKernelGGL((k_start<PCG, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+                       L.bmap_m, mode);
+  });
+  HIP_LAUNCH_OK();
+  with_ns(L.ns, [&](auto N) {
+    hipLaunchKernelGGL((k_decide<PCG, NSV>), dim3(L.ngroups), dim3(KBS), 0, s, L.groups, mode,
+                       par, exhausted);
+  });
   HIP_LAUNCH_OK();
 }
 
-void pcg_iter(hipStream_t s, const KLaunch& L) {
-  LK(k_pcg_spmv, L, s);
-  LK(k_pcg_update, L, s);
+void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
+  start_impl<true>(s, L, mode, par, exhausted);
 }
 
-void bicg_start(hipStream_t s, const KLaunch& L, int mode) {
-  LK2(K_START_BICG, L, s, mode);
-  hipLaunchKernelGGL(k_decide<false>, dim3(L.ngroups), dim3(1024), 0, s, L.groups, mode);
+void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
+  start_impl<false>(s, L, mode, par, exhausted);
+}
+
+void pcg_spmv_only(hipStream_t s, const KLaunch& L) {
+  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
+    hipLaunchKernelGGL((k_cg_spmv<NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+                       L.bmap_m);
+  });
   HIP_LAUNCH_OK();
 }
 
-void bicg_iter(hipStream_t s, const KLaunch& L) {
-  LK(k_bicg_1, L, s);
-  LK2(K_SPMV0, L, s);
-  LK(k_bicg_3, L, s);
-  LK2(K_SPMV1, L, s);
-  LK(k_bicg_5, L, s);
+void pcg_update_only(hipStream_t s, const KLaunch& L, int par) {
+  with_ns(L.ns, [&](auto N) {
+    hipLaunchKernelGGL((k_cg_update<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+                       par);
+  });
+  HIP_LAUNCH_OK();
 }
 
-void ksys_finish(hipStream_t s, const KLaunch& L) { LK(k_finish, L, s); }
+void pcg_iter(hipStream_t s, const KLaunch& L, int par) {
+  pcg_spmv_only(s, L);
+  pcg_update_only(s, L, par);
+}
+
+void bicg_spmv_only(hipStream_t s, const KLaunch& L) {
+  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
+    hipLaunchKernelGGL((k_bicg_spmv<0, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+                       L.bmap_m);
+  });
+  HIP_LAUNCH_OK();
+}
+
+void bicg_iter(hipStream_t s, const KLaunch& L, int par) {
+  bicg_spmv_only(s, L);
+  with_ns(L.ns, [&](auto N) {
+    hipLaunchKernelGGL((k_bicg_3<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+                       par);
+  });
+  HIP_LAUNCH_OK();
+  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
+    hipLaunchKernelGGL((k_bicg_spmv<1, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+                       L.bmap_m);
+  });
+  HIP_LAUNCH_OK();
+  with_ns(L.ns, [&](auto N) {
+    hipLaunchKernelGGL((k_bicg_5<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+                       par);
+  });
+  HIP_LAUNCH_OK();
+}
+
+void ksys_finish(hipStream_t s, const KLaunch& L) {
+  with_ns(L.ns, [&](auto N) {
+    hipLaunchKernelGGL((k_finish<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v);
+  });
+  HIP_LAUNCH_OK();
+}
 
 void gather_states(hipStream_t s, const KLaunch& L, KState* out) {
   const int n = L.ngroups * GMAX;
@@ -592,9 +725,5 @@ void gather_states(hipStream_t s, const KLaunch& L, KState* out) {
                      L.ngroups, out);
   HIP_LAUNCH_OK();
 }
-
-void pcg_spmv_only(hipStream_t s, const KLaunch& L) { LK(k_pcg_spmv, L, s); }
-void pcg_update_only(hipStream_t s, const KLaunch& L) { LK(k_pcg_update, L, s); }
-void bicg_spmv_only(hipStream_t s, const KLaunch& L) { LK2(K_SPMV0, L, s); }
 
 }  // namespace ipcs

@@ -15,16 +15,18 @@
 
 namespace ipcs {
 
-int nblk_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, div_up(n, bs)); }
-
-// Krylov block size of a group: IPCS_KBLOCK_P / IPCS_KBLOCK_V override the
-// defaults (pressure / velocity systems) for tuning sweeps.
-int kblock_for(bool pressure) {
-  const char* e = std::getenv(pressure ? "IPCS_KBLOCK_P" : "IPCS_KBLOCK_V");
-  int bs = pressure ? 512 : 1024;
-  if (e) bs = std::atoi(e);
-  if (bs != 256 && bs != 512 && bs != 1024) fail(IPCS_E_INVALID, "Krylov block size must be 256, 512 or 1024");
-  return bs;
+int kept_m_for(int64_t n) {
+  for (int e : {1, 2, 4})
+    if (div_up(n, (int64_t)KBS * e) <= KNB_MAX) return e;
+  fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
+}
+int nblk_m_for(int64_t n) {
+  return (int)std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_m_for(n)));
+}
+int nblk_v_for(int64_t n) {
+  const int64_t b = std::max<int64_t>(1, div_up(n, (int64_t)KBS * KEPT_V));
+  if (b > KNB_MAX) fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
+  return (int)b;
 }
 
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap) {
@@ -61,7 +63,12 @@ static int status_to_code(int s) {
   return IPCS_OK;
 }
 
-int krylov_solve(hipStream_t s, const KSet& S, KMethod m, int check_every,
+// Host side of a solve: start, then launch iterations in chunks and poll the
+// status words between chunks. Chunks are sized from the previous solve of the
+// same set (half of the expected remaining iterations, at least check_every),
+// so a solve that takes as long as the last one polls about log2 of its length
+// times. Parity par alternates with every iteration launch.
+int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
                  std::vector<KState>& hs, KState* pinned) {
   const int nslot = S.L.ngroups * GMAX;
   hs.assign(nslot, KState{});
@@ -76,29 +83,42 @@ int krylov_solve(hipStream_t s, const KSet& S, KMethod m, int check_every,
     for (int g = 0; g < S.L.ngroups; ++g)
       for (int j = 0; j < S.h_groups[g].nsys; ++j) f(hs[g * GMAX + j]);
   };
+  int par = 0, launched = 0;
   auto start = [&](int mode) {
-    if (m == KMethod::PCG) pcg_start(s, S.L, mode);
-    else bicg_start(s, S.L, mode);
+    const int exhausted = launched >= maxit;
+    if (m == KMethod::PCG) pcg_start(s, S.L, mode, par, exhausted);
+    else bicg_start(s, S.L, mode, par, exhausted);
   };
   start(0);
-  int chunk = 2;
-  const int cap = std::max(1, check_every);
+  fetch();
+  const int every = std::max(1, check_every);
   for (;;) {
+    bool run = false;
+    each([&](const KState& k) { run |= (k.status == KS_RUN); });
+    if (!run) break;
+    if (launched >= maxit) {
+      each([&](KState& k) {
+        if (k.status == KS_RUN) k.status = KS_MAXIT;
+      });
+      break;
+    }
+    int chunk = std::max(every, (S.last_iters - launched) / 2);
+    chunk = std::min(chunk, maxit - launched);
+    for (int k = 0; k < chunk; ++k) {
+      if (m == KMethod::PCG) pcg_iter(s, S.L, par);
+      else bicg_iter(s, S.L, par);
+      par ^= 1;
+    }
+    launched += chunk;
     fetch();
-    bool pend = false, run = false;
+    bool pend = false;
     each([&](const KState& k) { pend |= (k.status == KS_PENDING || k.status == KS_RESTART); });
     if (pend) {
       start(1);
       fetch();
     }
-    each([&](const KState& k) { run |= (k.status == KS_RUN); });
-    if (!run) break;
-    for (int k = 0; k < chunk; ++k) {
-      if (m == KMethod::PCG) pcg_iter(s, S.L);
-      else bicg_iter(s, S.L);
-    }
-    chunk = std::min(chunk * 2, cap);
   }
+  S.last_iters = launched;
   ksys_finish(s, S.L);
   int rc = IPCS_OK;
   each([&](const KState& k) {
@@ -180,21 +200,19 @@ void Run::layout(Carver& c) {
   P = c.take<double>(n1);
   dP = c.take<double>(n1);
   rP = c.take<double>(n1);
-  kv2 = c.take<double>(9 * dim * n2);
+  kv2 = c.take<double>(8 * dim * n2);
   kv1 = c.take<double>(5 * n1);
   kst = c.take<KState>(nsys);
   kgroups = c.take<KGroup>(3);
-  // partial buffers and block maps are sized for the smallest block size
-  const int b2 = nblk_for(n2, 256), b1 = nblk_for(n1, 256);
-  pm_mom = c.take<double>((int64_t)b2 * GMAX * KP);
-  pv_mom = c.take<double>((int64_t)b2 * GMAX * KP);
-  pm_p = c.take<double>((int64_t)b1 * GMAX * KP);
-  pv_p = c.take<double>((int64_t)b1 * GMAX * KP);
-  pm_corr = c.take<double>((int64_t)b2 * GMAX * KP);
-  pv_corr = c.take<double>((int64_t)b2 * GMAX * KP);
-  bm_mom = c.take<int2>(b2);
-  bm_p = c.take<int2>(b1);
-  bm_corr = c.take<int2>(b2);
+  for (int gi = 0; gi < 3; ++gi) {
+    const int64_t n = gi == 1 ? n1 : n2;
+    const int bm = nblk_m_for(n), bv = nblk_v_for(n);
+    part_m[gi] = c.take<double>((int64_t)bm * GMAX * KP);
+    part_v[gi][0] = c.take<double>((int64_t)bv * GMAX * KP);
+    part_v[gi][1] = c.take<double>((int64_t)bv * GMAX * KP);
+    bmap_m[gi] = c.take<int2>(bm);
+    bmap_v[gi] = c.take<int2>(bv);
+  }
   poll = c.take<KState>(3 * GMAX);
   spart = c.take<double>(8192 * 2);
   scnt = c.take<uint32_t>(4);
@@ -274,11 +292,10 @@ void Run::reform_A() {
   A_dirty = false;
 }
 
-static KState fresh_state(double tol, int maxit) {
+static KState fresh_state(double tol, int /*maxit*/) {
   KState k;
   std::memset(&k, 0, sizeof(k));
   k.tol2 = tol * tol;
-  k.maxit = maxit;
   k.status = KS_DONE;
   return k;
 }
@@ -287,57 +304,53 @@ void Run::setup_solvers() {
   const int nsys = 2 * dim + 1;
   std::vector<KState> st(nsys);
   std::vector<KGroup> grp(3);
-  const int bsv = kblock_for(false), bsp = kblock_for(true);
-  const int b2 = nblk_for(n2, bsv), b1 = nblk_for(n1, bsp);
   for (int gi = 0; gi < 3; ++gi) {
     KGroup& g = grp[gi];
     std::memset(&g, 0, sizeof(g));
-    if (gi == 1) {   // pressure Poisson
+    const int64_t n = gi == 1 ? n1 : n2;
+    g.n = (int32_t)n;
+    g.nblk_m = nblk_m_for(n);
+    g.nblk_v = nblk_v_for(n);
+    g.part_m = part_m[gi];
+    g.part_v[0] = part_v[gi][0];
+    g.part_v[1] = part_v[gi][1];
+    if (gi == 1) {   // pressure Poisson: Kp dP = r
       g.nsys = 1;
-      g.n = (int32_t)n1;
       g.sptr = sp11;
       g.col = col11;
       g.val = Kp;
       g.dinv = dinvKp;
-      g.nblk = b1;
-      g.part_m = pm_p;
-      g.part_v = pv_p;
       KVecs& V = g.v[0];
       V.b = rP;
       V.x = dP;
       V.r = kv1;
-      V.z = kv1 + n1;
-      V.p[0] = kv1 + 2 * n1;
-      V.p[1] = kv1 + 3 * n1;
-      V.q = kv1 + 4 * n1;
+      V.u = kv1 + n1;
+      V.p = kv1 + 2 * n1;
+      V.s = kv1 + 3 * n1;
+      V.w = kv1 + 4 * n1;
       V.st = kst + dim;
       st[dim] = fresh_state(prm.tol_p, prm.maxit);
       continue;
     }
     const bool mom = gi == 0;
     g.nsys = dim;
-    g.n = (int32_t)n2;
     g.sptr = sp22;
     g.col = col22;
     g.val = mom ? Ael : Mel;
     g.dinv = mom ? dinvA : dinvM;
-    g.nblk = b2;
-    g.part_m = mom ? pm_mom : pm_corr;
-    g.part_v = mom ? pv_mom : pv_corr;
     for (int c = 0; c < dim; ++c) {
-      double* base = kv2 + (size_t)c * 9 * n2;
+      double* base = kv2 + (size_t)c * 8 * n2;
       KVecs& V = g.v[c];
       V.b = bU + (size_t)c * n2;
       V.x = (mom ? Ustar : Unew) + (size_t)c * n2;
       V.r = base;
-      V.z = base + n2;
-      V.p[0] = base + 2 * n2;
-      V.p[1] = base + 3 * n2;
-      V.q = base + 4 * n2;
-      V.s = base + 5 * n2;
-      V.t = base + 6 * n2;
-      V.phat = base + 7 * n2;
-      V.shat = base + 8 * n2;
+      V.u = base + n2;
+      V.p = base + 2 * n2;
+      V.s = base + 3 * n2;
+      V.w = base + 4 * n2;
+      V.t = base + 5 * n2;
+      V.phat = base + 6 * n2;
+      V.shat = base + 7 * n2;
       const int sidx = mom ? c : dim + 1 + c;
       V.st = kst + sidx;
       st[sidx] = fresh_state(mom ? prm.tol_mom : prm.tol_corr, prm.maxit);
@@ -345,18 +358,24 @@ void Run::setup_solvers() {
   }
   HIP_OK(hipMemcpyAsync(kgroups, grp.data(), sizeof(KGroup) * 3, hipMemcpyHostToDevice, stream));
   HIP_OK(hipMemcpyAsync(kst, st.data(), sizeof(KState) * nsys, hipMemcpyHostToDevice, stream));
-  std::vector<std::vector<int2>> maps(3);
-  auto mk = [&](KSet& S, int gi, int2* bm) {
+  std::vector<std::vector<int2>> maps_m(3), maps_v(3);
+  auto mk = [&](KSet& S, int gi) {
     S.h_groups = {grp[gi]};
-    build_bmap({grp[gi].nblk}, maps[gi]);
-    HIP_OK(hipMemcpyAsync(bm, maps[gi].data(), sizeof(int2) * maps[gi].size(),
+    build_bmap({grp[gi].nblk_m}, maps_m[gi]);
+    build_bmap({grp[gi].nblk_v}, maps_v[gi]);
+    HIP_OK(hipMemcpyAsync(bmap_m[gi], maps_m[gi].data(), sizeof(int2) * maps_m[gi].size(),
                           hipMemcpyHostToDevice, stream));
-    S.L = KLaunch{kgroups + gi, 1, bm, (int)maps[gi].size(), gi == 1 ? bsp : bsv};
+    HIP_OK(hipMemcpyAsync(bmap_v[gi], maps_v[gi].data(), sizeof(int2) * maps_v[gi].size(),
+                          hipMemcpyHostToDevice, stream));
+    S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n),
+                  bmap_m[gi],        (int)maps_m[gi].size(),
+                  bmap_v[gi],        (int)maps_v[gi].size()};
     S.d_poll = poll + gi * GMAX;
+    S.last_iters = 0;
   };
-  mk(set_mom, 0, bm_mom);
-  mk(set_p, 1, bm_p);
-  mk(set_corr, 2, bm_corr);
+  mk(set_mom, 0);
+  mk(set_p, 1);
+  mk(set_corr, 2);
   HIP_OK(hipStreamSynchronize(stream));
 }
 
@@ -394,7 +413,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   for (double* v : {U, Unew, Ustar, bU, F, gfull}) HIP_OK(hipMemsetAsync(v, 0, vbytes, stream));
   for (double* v : {P, dP, rP}) HIP_OK(hipMemsetAsync(v, 0, sizeof(double) * n1, stream));
   // Krylov vectors start finite (gathers of padding columns read them)
-  HIP_OK(hipMemsetAsync(kv2, 0, sizeof(double) * 9 * dim * n2, stream));
+  HIP_OK(hipMemsetAsync(kv2, 0, sizeof(double) * 8 * dim * n2, stream));
   HIP_OK(hipMemsetAsync(kv1, 0, sizeof(double) * 5 * n1, stream));
   HIP_OK(hipMemsetAsync(scal, 0, sizeof(double) * 8, stream));
   assemble_constant();
@@ -520,7 +539,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     }
     case IPCS_PHASE_MOMENTUM: {
-      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, hs, pinned);
+      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned);
       fill_stats_solve(hs, dim, 1, st);
       HIP_OK(hipEventRecord(ev[2], stream));
       if (rc != IPCS_OK) {
@@ -535,7 +554,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       rhs_pressure(stream, dim, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart, scnt,
                    scal + 0);
       HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
-      rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned);
+      rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned);
       fill_stats_solve(hs, 1, 2, st);
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 2;
@@ -552,7 +571,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
                      prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
       HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
                             stream));
-      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, hs, pinned);
+      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned);
       fill_stats_solve(hs, dim, 3, st);
       phase_next = IPCS_PHASE_ASM;
       if (rc != IPCS_OK) {
@@ -608,24 +627,27 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       KState& k = pinned[j];
       std::memset(&k, 0, sizeof(k));
       k.status = KS_RUN;
-      k.rho[0] = k.rho[1] = 1.0;
-      k.alpha = k.omega = 1.0;
+      k.sc[0] = k.sc[1] = 1.0;
+      k.alpha[0] = k.alpha[1] = 1.0;
+      k.omega = 1.0;
       k.bb = 1.0;
       k.tol2 = 0.0;
-      k.maxit = 1 << 30;
-      k.it = 1;       // not a (re)start: the full iteration path runs
-      k.it0 = 0;
       HIP_OK(hipMemcpyAsync(g.v[j].st, &k, sizeof(KState), hipMemcpyHostToDevice, stream));
     }
-    // partials the kernels reduce in their prologue: unit dot products in
-    // block 0, zeros elsewhere (every launch then takes the full iteration path)
-    std::vector<double> pm((size_t)g.nblk * GMAX * KP, 0.0), pv((size_t)g.nblk * GMAX * KP, 0.0);
+    // partials the kernels reduce in their prologue, in block 0 (zeros
+    // elsewhere): gamma = 1, r.r = 1, delta = 2, so that every timed launch
+    // takes the full iteration path with alpha = beta = 1
+    std::vector<double> pm((size_t)g.nblk_m * GMAX * KP, 0.0), pv((size_t)g.nblk_v * GMAX * KP, 0.0);
     for (int j = 0; j < g.nsys; ++j)
-      for (int k = 0; k < KP; ++k) pm[j * KP + k] = pv[j * KP + k] = 1.0;
+      for (int k = 0; k < KP; ++k) {
+        pm[j * KP + k] = 2.0;
+        pv[j * KP + k] = 1.0;
+      }
     HIP_OK(hipMemcpyAsync(g.part_m, pm.data(), sizeof(double) * pm.size(), hipMemcpyHostToDevice,
                           stream));
-    HIP_OK(hipMemcpyAsync(g.part_v, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice,
-                          stream));
+    for (int q = 0; q < 2; ++q)
+      HIP_OK(hipMemcpyAsync(g.part_v[q], pv.data(), sizeof(double) * pv.size(),
+                            hipMemcpyHostToDevice, stream));
     HIP_OK(hipStreamSynchronize(stream));
   }
   const Mesh& m = *mesh;
@@ -634,7 +656,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   auto launch = [&]() {
     switch (kernel) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
-      case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L); break;
+      case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L, 0); break;
       case IPCS_KERNEL_ASM_CONV:
         asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
         break;
@@ -663,8 +685,8 @@ double Run::profile_kernel(int kernel, int nlaunch) {
         const KState& k = pinned[j];
         std::snprintf(msg, sizeof msg,
                       "profiled kernel %d left system %d in status %d (rr %.3e bb %.3e tol2 %.3e "
-                      "it %d it0 %d maxit %d par %d); timing discarded",
-                      kernel, j, k.status, k.rr, k.bb, k.tol2, k.it, k.it0, k.maxit, k.par);
+                      "it %d); timing discarded",
+                      kernel, j, k.status, k.rr, k.bb, k.tol2, k.it);
         fail(IPCS_E_STATE, msg);
       }
   }

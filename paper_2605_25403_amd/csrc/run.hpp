@@ -32,17 +32,22 @@ struct KSet {
   KLaunch L{};
   std::vector<KGroup> h_groups;
   KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
+  int last_iters = 0;          // iterations the previous solve took (poll schedule)
 };
 
 enum class KMethod { PCG, BICG };
 
-// Runs a set to completion. h_states[g*GMAX + j] receives the final states.
-// Returns IPCS_OK or the status of the first failed system.
-int krylov_solve(hipStream_t s, const KSet& S, KMethod m, int check_every,
+// Runs a set to completion (at most maxit iterations). h_states[g*GMAX + j]
+// receives the final states. Returns IPCS_OK or the status of the first
+// failed system.
+int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
                  std::vector<KState>& h_states, KState* pinned);
 
-int nblk_for(int64_t n, int bs);
-int kblock_for(bool pressure);
+// Rows per thread of matrix kernels for a group of n rows, and the block
+// counts of matrix / vector kernels (each at most KNB_MAX).
+int kept_m_for(int64_t n);
+int nblk_m_for(int64_t n);
+int nblk_v_for(int64_t n);
 // (group, block) map interleaving the groups block by block
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
 
@@ -81,13 +86,14 @@ struct Run {
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
          *gfull = nullptr;
   double *P = nullptr, *dP = nullptr, *rP = nullptr;
-  double* kv2 = nullptr;      // Krylov work of the velocity systems [dim][9][n2]
+  double* kv2 = nullptr;      // Krylov work of the velocity systems [dim][8][n2]
   double* kv1 = nullptr;      // Krylov work of the Poisson system [5][n1]
   KState* kst = nullptr;      // [2*dim+1]
   KGroup* kgroups = nullptr;  // [3]: momentum, pressure, correction
-  double *pm_mom = nullptr, *pv_mom = nullptr, *pm_p = nullptr, *pv_p = nullptr;
-  double *pm_corr = nullptr, *pv_corr = nullptr;
-  int2 *bm_mom = nullptr, *bm_p = nullptr, *bm_corr = nullptr;
+  double* part_m[3] = {};     // per group (momentum, pressure, correction)
+  double* part_v[3][2] = {};
+  int2* bmap_m[3] = {};
+  int2* bmap_v[3] = {};
   KState* poll = nullptr;     // [3 * GMAX]
   double* spart = nullptr;    // scratch partials for one-off reductions [8192*2]
   uint32_t* scnt = nullptr;
