@@ -11,6 +11,7 @@ correction RHS + PCG. The run's mesh, matrices and fields are resident in HBM
 before the timed region. Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +23,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+
+
+# kernel name -> (library kernel id, source file); ids are IPCS_KERNEL_* of include/ipcs.h
+KERNELS = {
+    "pcg_spmv_p": (0, "kernels_krylov.hip"),
+    "pcg_update_p": (1, "kernels_krylov.hip"),
+    "asm_conv": (2, "kernels_asm.hip"),
+    "bicg_spmv": (3, "kernels_krylov.hip"),
+    "pcg_spmv_m": (4, "kernels_krylov.hip"),
+    "bicg_spmv_t": (5, "kernels_krylov.hip"),
+    "bicg_update_s": (6, "kernels_krylov.hip"),
+    "bicg_update_x": (7, "kernels_krylov.hip"),
+    "pcg_update_m": (8, "kernels_krylov.hip"),
+}
 
 
 def kernel_bytes(kernel, c, dim):
@@ -36,12 +51,38 @@ def kernel_bytes(kernel, c, dim):
         return 11 * 8 * n1
     if kernel == "bicg_spmv":      # A once for all components; phat, rhat in, v out each
         return 12 * nnz22 + sl2 + dim * 3 * 8 * n2
+    if kernel == "bicg_spmv_t":    # A once; shat, s, rhat in, t out each
+        return 12 * nnz22 + sl2 + dim * 4 * 8 * n2
+    if kernel == "bicg_update_s":  # dinv; r, v in, s, shat out each
+        return 8 * n2 + dim * 4 * 8 * n2
+    if kernel == "bicg_update_x":  # dinv; x, phat, shat, s, t, p, v in, x, r, p, phat out each
+        return 8 * n2 + dim * 11 * 8 * n2
     if kernel == "pcg_spmv_m":     # M once for all components; u in, w out each
         return 12 * nnz22 + sl2 + dim * 2 * 8 * n2
+    if kernel == "pcg_update_m":   # dinv; x, r, p, s, w in, x, r, p, s, u out each
+        return 8 * n2 + dim * 10 * 8 * n2
     if kernel == "asm_conv":       # E out, U in, cell DOFs, vertex coordinates
         nloc = 6 if dim == 2 else 10
         return 8 * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
     raise KeyError(kernel)
+
+
+def source_sha1(fname):
+    with open(os.path.join(ROOT, "paper_2605_25403_amd", "csrc", fname), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, or None when there is none or the kernel's
+    source has changed since the counters were taken."""
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(tfile):
+        return None
+    t = json.load(open(tfile))
+    if t.get("source_sha1") != source_sha1(KERNELS[kernel][1]):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(w, budget_steps=1):
@@ -68,6 +109,84 @@ def cpu_baseline(w, budget_steps=1):
             "seconds": dt, "iterations": o.iters[-1]}
 
 
+def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; CSV output)
+    of one bench command into HBM bytes per launch of one kernel, each counter
+    scaled by what it reads for a plain device copy of calib_mib MiB in the
+    same run. Writes profiles/traffic_<kernel>_<workload>.json and .txt."""
+    import csv
+    import glob
+    import re
+
+    def rows(d, counter):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
+           "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
+           "asm_conv": r"OpConvExplicit"}[kernel]
+    copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)
+    res = {}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rr = rows(d, counter)
+        k = [v for n, v in rr if sym.replace(" ", "") in n.replace(" ", "")]
+        cp = [v for n, v in rr if copy_re.search(n) and not n.startswith("void ipcs")]
+        if not k or not cp:
+            raise SystemExit(f"pmc-summary: no {counter} rows for {kernel} or the copy kernel in {d}")
+        kib = float(np.median(k))
+        copy_kib = max(cp)                      # the large calibration copy
+        factor = calib_mib * 1024.0 / copy_kib  # true KiB per counted KiB
+        res[name] = {"counter": counter, "kib_per_dispatch_median": kib, "dispatches": len(k),
+                     "copy_kib": copy_kib, "scale": factor,
+                     "bytes_per_launch": kib * factor * 1024.0}
+    fname = KERNELS[kernel][1]
+    summary = {"kernel": kernel, "workload": workload, "command": command,
+               "calibration": f"device copy of {calib_mib} MiB (reads and writes {calib_mib} MiB)",
+               "fetch": res["fetch"], "write": res["write"],
+               "bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"],
+               "source": f"paper_2605_25403_amd/csrc/{fname}", "source_sha1": source_sha1(fname)}
+    base = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}")
+    json.dump(summary, open(base + ".json", "w"), indent=1)
+    with open(base + ".txt", "w") as f:
+        f.write(f"HBM traffic of {kernel} on workload {workload} (rocprofv3 PMC)\n")
+        f.write(f"command: {command}\n")
+        for nm in ("fetch", "write"):
+            r_ = res[nm]
+            f.write(f"{r_['counter']}: median {r_['kib_per_dispatch_median']:.1f} KiB/dispatch over "
+                    f"{r_['dispatches']} dispatches; the copy of {calib_mib} MiB counts "
+                    f"{r_['copy_kib']:.1f} KiB -> scale {r_['scale']:.3f} -> "
+                    f"{r_['bytes_per_launch'] / 1e6:.2f} MB per launch\n")
+        f.write(f"total HBM bytes per launch: {summary['bytes_per_launch'] / 1e6:.2f} MB\n")
+    print(json.dumps(summary))
+
+
+def trace_summary(trace_dir, workload, command):
+    """Writes profiles/kernels_<workload>.txt from the kernel statistics of a
+    rocprofv3 --kernel-trace --stats -f csv run (no GPU use)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"trace-summary: no kernel_stats.csv under {trace_dir}")
+    rows = sorted(csv.DictReader(open(f[0])), key=lambda r: -float(r["TotalDurationNs"]))
+    out = os.path.join(ROOT, "profiles", f"kernels_{workload}.txt")
+    with open(out, "w") as o:
+        o.write(f"rocprofv3 kernel statistics, workload {workload}\n")
+        o.write(f"command: {command}\n\n")
+        o.write(f"{'kernel':70s} {'calls':>7s} {'avg us':>9s} {'min us':>8s} {'max us':>8s} {'%':>6s}\n")
+        for r in rows[:30]:
+            name = r["Name"].replace("ipcs::", "")
+            name = name[:name.index("(")] if "(" in name else name
+            o.write(f"{name[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
+                    f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f} "
+                    f"{float(r['Percentage']):6.2f}\n")
+    print(open(out).read())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,8 +194,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-launches", type=int, default=200)
+    ap.add_argument("--kernel-steps", type=int, default=5,
+                    help="steps after the timed region with per-launch kernel timing")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="end with a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarize two rocprofv3 --pmc runs and exit (no GPU use)")
+    ap.add_argument("--pmc-kernel", default="pcg_update_p")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="summarize a rocprofv3 --kernel-trace --stats -f csv run and exit")
+    ap.add_argument("--pmc-command", default="")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.workload, args.pmc_command)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_kernel, args.workload,
+                    args.calibrate_copy or 256, args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
               "supported (multi-GPU sharding is described in DESIGN.md, not built)",
@@ -115,32 +250,36 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
 
-    # per-kernel live timing (HIP events on the run's stream), outside the timed region
+    # per-kernel durations: every launch of every kernel bracketed by HIP events
+    # on the run's stream, in the normal launch sequence of kernel_steps more steps
     c = m.counts
     it_p = float(np.median([s["it_p"] for s in stats]))
     it_m = float(np.median([max(s["it_mom"][:dim]) for s in stats]))
     it_c = float(np.median([max(s["it_corr"][:dim]) for s in stats]))
-    launches = {"pcg_spmv_p": it_p, "pcg_update_p": it_p, "bicg_spmv": 2 * it_m,
-                "pcg_spmv_m": it_c, "asm_conv": 1.0}
-    ids = {"pcg_spmv_p": I.IPCS_KERNEL_PCG_SPMV_P, "pcg_update_p": I.IPCS_KERNEL_PCG_UPDATE_P,
-           "bicg_spmv": I.IPCS_KERNEL_BICG_SPMV, "pcg_spmv_m": I.IPCS_KERNEL_PCG_SPMV_M,
-           "asm_conv": I.IPCS_KERNEL_ASM_CONV}
+    r.kernel_timing((1 << I.IPCS_NKERNEL) - 1 if args.kernel_steps > 0 else 0)
+    for _ in range(args.kernel_steps):
+        r.advance(1)
+    torch.cuda.synchronize()
+    kms, kcnt = r.kernel_times()
+    r.kernel_timing(0)
+    ksteps = max(1, args.kernel_steps)
     kern = {}
-    for name, kid in ids.items():
-        us = I.ipcs_profile_kernel(r.h, kid, args.profile_launches)
+    for name, (kid, _) in KERNELS.items():
+        if kcnt[kid] == 0:
+            continue
+        us = 1000.0 * kms[kid] / kcnt[kid]
         b = kernel_bytes(name, c, dim)
         kern[name] = {"us_per_launch": us, "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
-                      "launches_per_step": launches[name],
-                      "ms_per_step_est": us * launches[name] / 1000.0}
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step_est"])
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}.json")
-    if os.path.exists(tfile):
-        traffic = json.load(open(tfile)).get("bytes_per_launch")
-    roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBps"], "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": kern[dom]["GBps"] / PEAK_HBM_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": kern[dom]["bytes"],
-            "us_per_launch": kern[dom]["us_per_launch"]}
+                      "launches_per_step": kcnt[kid] / ksteps,
+                      "ms_per_step": kms[kid] / ksteps}
+    roof = None
+    if kern:
+        dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+        roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBps"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": kern[dom]["GBps"] / PEAK_HBM_GBS,
+                "traffic": measured_traffic(dom, args.workload),
+                "algorithmic_bytes_per_launch": kern[dom]["bytes"],
+                "us_per_launch": kern[dom]["us_per_launch"]}
 
     ph = np.array([s["ms"] for s in stats])
     out = {
@@ -172,6 +311,11 @@ def main():
                             "correction": float(np.median(ph[:, 3]))},
         "iterations_median": {"momentum": it_m, "pressure": it_p, "correction": it_c},
     }
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

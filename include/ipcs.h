@@ -224,13 +224,26 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
  * it is stepped alone. stats may be NULL or hold nruns entries. */
 int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats);
 
-enum {                          /* kernels of the step, for ipcs_profile_kernel   */
-  IPCS_KERNEL_PCG_SPMV_P = 0,   /* Poisson PCG: p = z + beta p, q = Kp p, p.q     */
-  IPCS_KERNEL_PCG_UPDATE_P = 1, /* Poisson PCG: x, r, z updates and r.z, r.r      */
-  IPCS_KERNEL_ASM_CONV = 2,     /* convection assembly E = M/dt - C(U^n)           */
-  IPCS_KERNEL_BICG_SPMV = 3,    /* momentum BiCGStab v = A phat, rhat.v (all comps) */
-  IPCS_KERNEL_PCG_SPMV_M = 4    /* correction PCG q = M p, p.q (all components)   */
+enum {                            /* kernels of the step, for the timing hooks       */
+  IPCS_KERNEL_PCG_SPMV_P = 0,     /* Poisson CG: w = Kp u, partial u.w               */
+  IPCS_KERNEL_PCG_UPDATE_P = 1,   /* Poisson CG: p, s, x, r, u updates; r.u, r.r     */
+  IPCS_KERNEL_ASM_CONV = 2,       /* convection assembly E = M/dt - C(U^n)           */
+  IPCS_KERNEL_BICG_SPMV = 3,      /* momentum BiCGStab: v = A phat, rhat.v           */
+  IPCS_KERNEL_PCG_SPMV_M = 4,     /* correction CG: w = M u, u.w (all components)   */
+  IPCS_KERNEL_BICG_SPMV_T = 5,    /* momentum BiCGStab: t = A shat, t.s, t.t, ...    */
+  IPCS_KERNEL_BICG_UPDATE_S = 6,  /* momentum BiCGStab: s = r - alpha v, shat        */
+  IPCS_KERNEL_BICG_UPDATE_X = 7,  /* momentum BiCGStab: x, r, p, phat updates; r.r   */
+  IPCS_KERNEL_PCG_UPDATE_M = 8,   /* correction CG: p, s, x, r, u updates            */
+  IPCS_NKERNEL = 9
 };
+/* Measurement hook (not part of the method): from the next call on, every
+ * launch of a kernel whose bit (1 << IPCS_KERNEL_*) is set in mask is
+ * bracketed by two HIP events on the run's stream, in the normal sequence of
+ * the step; mask = 0 turns this off. Accumulated times are reset. */
+int ipcs_kernel_timing(ipcs_run r, uint32_t mask);
+/* Accumulated event time (ms) and launch count per kernel since the last
+ * ipcs_kernel_timing call; ms and launches hold cap >= IPCS_NKERNEL entries. */
+int ipcs_kernel_times(ipcs_run r, double* ms, int64_t* launches, int32_t cap);
 /* Measurement hook (not part of the method): launches one of the step's
  * kernels nlaunch times back to back on the run's stream with the run's own
  * data and returns the mean duration per launch in microseconds, timed with

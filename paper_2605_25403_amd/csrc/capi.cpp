@@ -391,6 +391,27 @@ int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_
   });
 }
 
+int ipcs_kernel_timing(ipcs_run r, uint32_t mask) {
+  return guard([&]() -> int {
+    need(mask < (1u << IPCS_NKERNEL), "kernel mask has bits beyond IPCS_NKERNEL");
+    R(r).timer.reset(mask);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_kernel_times(ipcs_run r, double* ms, int64_t* launches, int32_t cap) {
+  return guard([&]() -> int {
+    need(ms != nullptr && launches != nullptr && cap >= IPCS_NKERNEL,
+         "need outputs with room for IPCS_NKERNEL entries");
+    const ipcs::KTimer& T = R(r).timer;
+    for (int k = 0; k < IPCS_NKERNEL; ++k) {
+      ms[k] = T.ms[k];
+      launches[k] = T.cnt[k];
+    }
+    return IPCS_OK;
+  });
+}
+
 void ipcs_run_destroy(ipcs_run r) { delete r; }
 
 }  // extern "C"

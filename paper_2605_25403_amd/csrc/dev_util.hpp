@@ -79,11 +79,18 @@ __device__ __forceinline__ void block_sum_t(double (&v)[N], double* sh) {
   }
 }
 
-// This thread's share of the partial records of a producer kernel with nb
-// blocks (nb <= KBS * KPART_Q): records tid, tid + KBS, ... summed in order.
+// Partial sums are stored structure-of-arrays: value k of system j from
+// producer block b is part[(j*KP + k)*nb + b], so a wavefront reading one
+// value of 64 consecutive blocks makes one coalesced 512-byte load.
+__device__ __forceinline__ size_t part_index(int j, int k, int nb, int b) {
+  return ((size_t)(j * KP + k)) * nb + b;
+}
+
+// This thread's share of the partial sums of a producer kernel with nb
+// blocks (nb <= KBS * KPART_Q): blocks tid, tid + KBS, ... summed in order.
 // Every load is issued before the first use, so the caller can issue its own
-// independent loads first and let all of them overlap. K values of NS systems
-// land in v[j*K + k]; block_sum_t then gives the totals.
+// independent loads first and let all of them overlap. Value k of system j
+// lands in v[j*K + k]; block_sum_t then gives the totals.
 template <int NS, int K>
 __device__ __forceinline__ void load_partials(const double* part, int nb, double* v) {
 #pragma unroll
@@ -93,18 +100,20 @@ __device__ __forceinline__ void load_partials(const double* part, int nb, double
     const int b = (int)threadIdx.x + q * KBS;
     if (q * KBS < nb) {
       const bool ok = b < nb;
-      const double* p = part + (size_t)(ok ? b : 0) * GMAX * KP;
 #pragma unroll
       for (int j = 0; j < NS; ++j)
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[j * K + k] += ok ? p[j * KP + k] : 0.0;
+        for (int k = 0; k < K; ++k)
+          v[j * K + k] += ok ? part[part_index(j, k, nb, ok ? b : 0)] : 0.0;
     }
   }
 }
 
-// Block-reduce acc[j*K + k] (KBS threads) and store them as partial record lb.
+// Block-reduce acc[j*K + k] (KBS threads) and store them as the partials of
+// block lb of a kernel with nb blocks.
 template <int NS, int K>
-__device__ __forceinline__ void store_partials(double* acc, double* part, int lb, double* sh) {
+__device__ __forceinline__ void store_partials(double* acc, double* part, int nb, int lb,
+                                               double* sh) {
   double v[NS * K];
 #pragma unroll
   for (int n = 0; n < NS * K; ++n) v[n] = acc[n];
@@ -114,7 +123,7 @@ __device__ __forceinline__ void store_partials(double* acc, double* part, int lb
     double val = 0.0;
 #pragma unroll
     for (int q = 0; q < NS * K; ++q) val = (q == (int)threadIdx.x) ? v[q] : val;
-    part[((size_t)lb * GMAX + j) * KP + k] = val;
+    part[part_index(j, k, nb, lb)] = val;
   }
 }
 

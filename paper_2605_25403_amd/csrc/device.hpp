@@ -144,7 +144,10 @@ void gather_states(hipStream_t s, const KLaunch& L, KState* out);   // out[g*GMA
 // single kernels of an iteration, for timing
 void pcg_spmv_only(hipStream_t s, const KLaunch& L);
 void pcg_update_only(hipStream_t s, const KLaunch& L, int par);
-void bicg_spmv_only(hipStream_t s, const KLaunch& L);
+void bicg_spmv_only(hipStream_t s, const KLaunch& L);                 // v = A phat
+void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par);    // s, shat
+void bicg_spmv_t_only(hipStream_t s, const KLaunch& L);               // t = A shat
+void bicg_update_x_only(hipStream_t s, const KLaunch& L, int par);    // x, r, p, phat
 
 // Fields and right-hand sides (kernels_fields.hip)
 void eval_velocity(hipStream_t s, int dim, const Builtin& bi, const double* x, int64_t n,

@@ -19,6 +19,7 @@
 #include "common.hpp"
 #include "dev_util.hpp"
 #include "device.hpp"
+#include "launch.hpp"
 #include "builtin.hpp"
 #include "rules.hpp"
 
@@ -322,8 +323,7 @@ template <int D, class Op>
 static void launch_rows(hipStream_t s, const RowAsm& a, const Op& op, int bs, size_t lds) {
   if (a.nrows <= 0) return;
   const int nb = (int)div_up(a.nrows, bs);
-  hipLaunchKernelGGL((k_asm_rows<D, Op>), dim3(nb), dim3(bs), lds, s, a, op);
-  HIP_LAUNCH_OK();
+  launch(k_asm_rows<D, Op>, dim3(nb), dim3(bs), (uint32_t)lds, s, a, op);
 }
 
 // a.out[0] <- M, a.out[1] <- K

@@ -12,8 +12,8 @@
 // groups through a (group, block) map, e.g. all runs of a serving batch.
 //
 // Reductions are fence-free and deterministic (dev_util.hpp): a kernel writes
-// one partial record per block, and every block of the next kernel re-reduces
-// all of them in a fixed order. Keeping blocks at 256 threads with several
+// one set of partial sums per block, and every block of the next kernel
+// re-reduces all of them in a fixed order. Keeping blocks at 256 threads with several
 // entries per thread keeps the number of records small (at most KNB_MAX).
 // Each kernel issues its independent loads (state words, partial records,
 // vector entries) before its first wait; scalars that depend on the reduction
@@ -47,6 +47,7 @@
 #include "common.hpp"
 #include "dev_util.hpp"
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace ipcs {
 
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
       }
     }
   }
-  store_partials<NS, 3>(acc, g.part_m, lb, sh);
+  store_partials<NS, 3>(acc, g.part_m, g.nblk_m, lb, sh);
 }
 
 // One block per group: decide the status of the systems that were started or
@@ -192,9 +193,9 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
   for (int b = threadIdx.x; b < g.nblk_v; b += KBS)
     for (int j = 0; j < NS; ++j) {
       if (!run_s[j]) continue;
-      double* p = g.part_v[par] + ((size_t)b * GMAX + j) * KP;
-      p[0] = b == 0 ? (PCG ? tot[j * 3 + 1] : tot[j * 3]) : 0.0;
-      p[1] = b == 0 ? tot[j * 3] : 0.0;
+      double* p = g.part_v[par];
+      p[part_index(j, 0, g.nblk_v, b)] = b == 0 ? (PCG ? tot[j * 3 + 1] : tot[j * 3]) : 0.0;
+      p[part_index(j, 1, g.nblk_v, b)] = b == 0 ? tot[j * 3] : 0.0;
     }
 }
 
@@ -235,7 +236,7 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
       acc[j] += y[e][j] * ui[e][j];
     }
   }
-  store_partials<NS, 1>(acc, g.part_m, lb, sh);
+  store_partials<NS, 1>(acc, g.part_m, g.nblk_m, lb, sh);
 }
 
 template <int NS>
@@ -347,7 +348,7 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
       acc[j * 2 + 1] += r * r;
     }
   }
-  store_partials<NS, 2>(acc, g.part_v[par ^ 1], lb, sh);
+  store_partials<NS, 2>(acc, g.part_v[par ^ 1], g.nblk_v, lb, sh);
 }
 
 // ------------------------------------------------------------------ BiCGStab
@@ -405,7 +406,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
       }
     }
   }
-  store_partials<NS, K>(acc, g.part_m, lb, sh);
+  store_partials<NS, K>(acc, g.part_m, g.nblk_m, lb, sh);
 }
 
 template <int NS>
@@ -589,7 +590,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
       }
     }
   }
-  store_partials<NS, 1>(acc, g.part_v[par ^ 1], lb, sh);
+  store_partials<NS, 1>(acc, g.part_v[par ^ 1], g.nblk_v, lb, sh);
 }
 
 // ------------------------------------------------------------------ finish / poll
@@ -645,12 +646,12 @@ static void with_ns_ept(int ns, int ept, F f) {
 template <bool PCG>
 static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
   with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    hipLaunchKernelGGL((k_start<PCG, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+    launch(k_start<PCG, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m, mode);
   });
   HIP_LAUNCH_OK();
   with_ns(L.ns, [&](auto N) {
-    hipLaunchKernelGGL((k_decide<PCG, NSV>), dim3(L.ngroups), dim3(KBS), 0, s, L.groups, mode,
+    launch(k_decide<PCG, NSV>, dim3(L.ngroups), dim3(KBS), 0, s, L.groups, mode,
                        par, exhausted);
   });
   HIP_LAUNCH_OK();
@@ -666,7 +667,7 @@ void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhauste
 
 void pcg_spmv_only(hipStream_t s, const KLaunch& L) {
   with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    hipLaunchKernelGGL((k_cg_spmv<NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+    launch(k_cg_spmv<NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m);
   });
   HIP_LAUNCH_OK();
@@ -674,7 +675,7 @@ void pcg_spmv_only(hipStream_t s, const KLaunch& L) {
 
 void pcg_update_only(hipStream_t s, const KLaunch& L, int par) {
   with_ns(L.ns, [&](auto N) {
-    hipLaunchKernelGGL((k_cg_update<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+    launch(k_cg_update<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
                        par);
   });
   HIP_LAUNCH_OK();
@@ -687,34 +688,46 @@ void pcg_iter(hipStream_t s, const KLaunch& L, int par) {
 
 void bicg_spmv_only(hipStream_t s, const KLaunch& L) {
   with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    hipLaunchKernelGGL((k_bicg_spmv<0, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+    launch(k_bicg_spmv<0, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m);
+  });
+  HIP_LAUNCH_OK();
+}
+
+void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par) {
+  with_ns(L.ns, [&](auto N) {
+    launch(k_bicg_3<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+                       par);
+  });
+  HIP_LAUNCH_OK();
+}
+
+void bicg_spmv_t_only(hipStream_t s, const KLaunch& L) {
+  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
+    launch(k_bicg_spmv<1, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+                       L.bmap_m);
+  });
+  HIP_LAUNCH_OK();
+}
+
+void bicg_update_x_only(hipStream_t s, const KLaunch& L, int par) {
+  with_ns(L.ns, [&](auto N) {
+    launch(k_bicg_5<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+                       par);
   });
   HIP_LAUNCH_OK();
 }
 
 void bicg_iter(hipStream_t s, const KLaunch& L, int par) {
   bicg_spmv_only(s, L);
-  with_ns(L.ns, [&](auto N) {
-    hipLaunchKernelGGL((k_bicg_3<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
-                       par);
-  });
-  HIP_LAUNCH_OK();
-  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    hipLaunchKernelGGL((k_bicg_spmv<1, NSV, EPTV>), dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
-                       L.bmap_m);
-  });
-  HIP_LAUNCH_OK();
-  with_ns(L.ns, [&](auto N) {
-    hipLaunchKernelGGL((k_bicg_5<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
-                       par);
-  });
-  HIP_LAUNCH_OK();
+  bicg_update_s_only(s, L, par);
+  bicg_spmv_t_only(s, L);
+  bicg_update_x_only(s, L, par);
 }
 
 void ksys_finish(hipStream_t s, const KLaunch& L) {
   with_ns(L.ns, [&](auto N) {
-    hipLaunchKernelGGL((k_finish<NSV>), dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v);
+    launch(k_finish<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v);
   });
   HIP_LAUNCH_OK();
 }

@@ -68,20 +68,60 @@ static int status_to_code(int s) {
 // same set (half of the expected remaining iterations, at least check_every),
 // so a solve that takes as long as the last one polls about log2 of its length
 // times. Parity par alternates with every iteration launch.
+LaunchEvents*& launch_events() {
+  thread_local LaunchEvents* slot = nullptr;
+  return slot;
+}
+
+KTimer::~KTimer() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+void KTimer::reset(uint32_t m) {
+  mask = m;
+  which.clear();
+  for (int k = 0; k < IPCS_NKERNEL; ++k) {
+    ms[k] = 0.0;
+    cnt[k] = 0;
+  }
+}
+
+void KTimer::drain() {
+  for (size_t k = 0; k < which.size(); ++k) {
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+    ms[which[k]] += t;
+    cnt[which[k]] += 1;
+  }
+  which.clear();
+}
+
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
-                 std::vector<KState>& hs, KState* pinned) {
+                 std::vector<KState>& hs, KState* pinned, KTimer& T) {
   const int nslot = S.L.ngroups * GMAX;
   hs.assign(nslot, KState{});
   auto fetch = [&]() {
     gather_states(s, S.L, S.d_poll);
     HIP_OK(hipMemcpyAsync(pinned, S.d_poll, sizeof(KState) * nslot, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    T.drain();
     for (int g = 0; g < S.L.ngroups; ++g)
       for (int j = 0; j < S.h_groups[g].nsys; ++j) hs[g * GMAX + j] = pinned[g * GMAX + j];
   };
   auto each = [&](auto f) {
     for (int g = 0; g < S.L.ngroups; ++g)
       for (int j = 0; j < S.h_groups[g].nsys; ++j) f(hs[g * GMAX + j]);
+  };
+  auto iterate = [&](int par) {
+    if (m == KMethod::PCG) {
+      T.run(s, S.kid[0], [&] { pcg_spmv_only(s, S.L); });
+      T.run(s, S.kid[1], [&] { pcg_update_only(s, S.L, par); });
+    } else {
+      T.run(s, S.kid[0], [&] { bicg_spmv_only(s, S.L); });
+      T.run(s, S.kid[1], [&] { bicg_update_s_only(s, S.L, par); });
+      T.run(s, S.kid[2], [&] { bicg_spmv_t_only(s, S.L); });
+      T.run(s, S.kid[3], [&] { bicg_update_x_only(s, S.L, par); });
+    }
   };
   int par = 0, launched = 0;
   auto start = [&](int mode) {
@@ -105,8 +145,7 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
     int chunk = std::max(every, (S.last_iters - launched) / 2);
     chunk = std::min(chunk, maxit - launched);
     for (int k = 0; k < chunk; ++k) {
-      if (m == KMethod::PCG) pcg_iter(s, S.L, par);
-      else bicg_iter(s, S.L, par);
+      iterate(par);
       par ^= 1;
     }
     launched += chunk;
@@ -376,6 +415,13 @@ void Run::setup_solvers() {
   mk(set_mom, 0);
   mk(set_p, 1);
   mk(set_corr, 2);
+  const int kid_mom[4] = {IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_BICG_UPDATE_S,
+                          IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_X};
+  for (int k = 0; k < 4; ++k) set_mom.kid[k] = kid_mom[k];
+  set_p.kid[0] = IPCS_KERNEL_PCG_SPMV_P;
+  set_p.kid[1] = IPCS_KERNEL_PCG_UPDATE_P;
+  set_corr.kid[0] = IPCS_KERNEL_PCG_SPMV_M;
+  set_corr.kid[1] = IPCS_KERNEL_PCG_UPDATE_M;
   HIP_OK(hipStreamSynchronize(stream));
 }
 
@@ -530,7 +576,9 @@ int Run::phase(int which, ipcs_step_stats* st) {
         asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
         has_F = true;
       }
-      asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+      timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
+        asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+      });
       rhs_momentum(stream, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, has_F ? F : nullptr,
                    lift_ptr, lift_col, liftA, bmask, gfull, bU);
       copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
@@ -539,7 +587,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     }
     case IPCS_PHASE_MOMENTUM: {
-      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned);
+      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned, timer);
       fill_stats_solve(hs, dim, 1, st);
       HIP_OK(hipEventRecord(ev[2], stream));
       if (rc != IPCS_OK) {
@@ -554,7 +602,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       rhs_pressure(stream, dim, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart, scnt,
                    scal + 0);
       HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
-      rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned);
+      rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
       fill_stats_solve(hs, 1, 2, st);
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 2;
@@ -571,7 +619,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
                      prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
       HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
                             stream));
-      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned);
+      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
       fill_stats_solve(hs, dim, 3, st);
       phase_next = IPCS_PHASE_ASM;
       if (rc != IPCS_OK) {
@@ -582,6 +630,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
       HIP_OK(hipEventRecord(ev[4], stream));
       HIP_OK(hipEventSynchronize(ev[4]));
+      timer.drain();
       t = t1;
       if (st) {
         st->t = t;
@@ -617,10 +666,11 @@ int Run::step(ipcs_step_stats* st) {
 // every timed launch must have done its full work.
 double Run::profile_kernel(int kernel, int nlaunch) {
   if (phase_next != IPCS_PHASE_ASM) fail(IPCS_E_STATE, "profile only between steps");
-  const KSet* S = kernel == IPCS_KERNEL_BICG_SPMV     ? &set_mom
-                  : kernel == IPCS_KERNEL_PCG_SPMV_M  ? &set_corr
-                  : kernel == IPCS_KERNEL_ASM_CONV    ? nullptr
-                                                      : &set_p;
+  if (kernel < 0 || kernel >= IPCS_NKERNEL) fail(IPCS_E_INVALID, "unknown kernel id");
+  const bool mom = kernel == IPCS_KERNEL_BICG_SPMV || kernel == IPCS_KERNEL_BICG_SPMV_T ||
+                   kernel == IPCS_KERNEL_BICG_UPDATE_S || kernel == IPCS_KERNEL_BICG_UPDATE_X;
+  const bool corr = kernel == IPCS_KERNEL_PCG_SPMV_M || kernel == IPCS_KERNEL_PCG_UPDATE_M;
+  const KSet* S = mom ? &set_mom : corr ? &set_corr : kernel == IPCS_KERNEL_ASM_CONV ? nullptr : &set_p;
   if (S) {
     const KGroup& g = S->h_groups[0];
     for (int j = 0; j < g.nsys; ++j) {
@@ -635,13 +685,14 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       HIP_OK(hipMemcpyAsync(g.v[j].st, &k, sizeof(KState), hipMemcpyHostToDevice, stream));
     }
     // partials the kernels reduce in their prologue, in block 0 (zeros
-    // elsewhere): gamma = 1, r.r = 1, delta = 2, so that every timed launch
-    // takes the full iteration path with alpha = beta = 1
+    // elsewhere), chosen so that every timed launch takes the full iteration
+    // path: CG gamma = r.r = 1, delta = 2 (alpha = beta = 1); BiCGStab
+    // rhat.v = 2, r.r = 1, t.s = t.t = rhat.s = 2, rhat.t = 1 (omega = 1, rho' = 1)
     std::vector<double> pm((size_t)g.nblk_m * GMAX * KP, 0.0), pv((size_t)g.nblk_v * GMAX * KP, 0.0);
     for (int j = 0; j < g.nsys; ++j)
       for (int k = 0; k < KP; ++k) {
-        pm[j * KP + k] = 2.0;
-        pv[j * KP + k] = 1.0;
+        pm[(size_t)(j * KP + k) * g.nblk_m] = k == 3 ? 1.0 : 2.0;   // block 0, SoA layout
+        pv[(size_t)(j * KP + k) * g.nblk_v] = 1.0;
       }
     HIP_OK(hipMemcpyAsync(g.part_m, pm.data(), sizeof(double) * pm.size(), hipMemcpyHostToDevice,
                           stream));
@@ -662,6 +713,10 @@ double Run::profile_kernel(int kernel, int nlaunch) {
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;
       case IPCS_KERNEL_PCG_SPMV_M: pcg_spmv_only(stream, set_corr.L); break;
+      case IPCS_KERNEL_BICG_SPMV_T: bicg_spmv_t_only(stream, set_mom.L); break;
+      case IPCS_KERNEL_BICG_UPDATE_S: bicg_update_s_only(stream, set_mom.L, 0); break;
+      case IPCS_KERNEL_BICG_UPDATE_X: bicg_update_x_only(stream, set_mom.L, 0); break;
+      case IPCS_KERNEL_PCG_UPDATE_M: pcg_update_only(stream, set_corr.L, 0); break;
       default: fail(IPCS_E_INVALID, "unknown kernel id");
     }
   };

@@ -7,7 +7,9 @@
 #include <memory>
 #include <vector>
 
+#include "common.hpp"
 #include "device.hpp"
+#include "launch.hpp"
 #include "ipcs.h"
 #include "mesh.hpp"
 
@@ -27,12 +29,47 @@ struct Carver {
   }
 };
 
+// Per-launch event timing of selected kernels in the normal launch sequence
+// (measurement hook). Pairs are read back after the stream has synchronized.
+struct KTimer {
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> ev;   // [2k], [2k+1] bracket the k-th timed launch
+  std::vector<int> which;       // kernel id of the k-th timed launch
+  double ms[IPCS_NKERNEL] = {};
+  int64_t cnt[IPCS_NKERNEL] = {};
+  ~KTimer();
+  void reset(uint32_t m);
+  template <class F>
+  void run(hipStream_t s, int kid, F f) {
+    if (kid < 0 || !((mask >> kid) & 1u)) {
+      f();
+      return;
+    }
+    const size_t k = which.size();
+    while (ev.size() < 2 * (k + 1)) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    LaunchEvents le{ev[2 * k], ev[2 * k + 1]};
+    launch_events() = &le;
+    f();   // one kernel launch, which takes the events
+    const bool taken = launch_events() == nullptr;
+    launch_events() = nullptr;
+    if (!taken) fail(IPCS_E_STATE, "timed launcher did not launch a kernel");
+    which.push_back(kid);
+  }
+  void drain();   // the stream must have synchronized
+};
+
 // Host view of a set of Krylov groups solved by the same launches.
 struct KSet {
   KLaunch L{};
   std::vector<KGroup> h_groups;
   KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
   int last_iters = 0;          // iterations the previous solve took (poll schedule)
+  // kernel ids for timing: PCG {spmv, update}, BiCGStab {v, s, t, x}; -1: none
+  int kid[4] = {-1, -1, -1, -1};
 };
 
 enum class KMethod { PCG, BICG };
@@ -41,7 +78,7 @@ enum class KMethod { PCG, BICG };
 // receives the final states. Returns IPCS_OK or the status of the first
 // failed system.
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
-                 std::vector<KState>& h_states, KState* pinned);
+                 std::vector<KState>& h_states, KState* pinned, KTimer& T);
 
 // Rows per thread of matrix kernels for a group of n rows, and the block
 // counts of matrix / vector kernels (each at most KNB_MAX).
@@ -104,6 +141,7 @@ struct Run {
 
   KSet set_mom, set_p, set_corr;
   KState* pinned = nullptr;   // host mirror for status polling
+  KTimer timer;
 
   // ---- problem data
   Builtin bi{};

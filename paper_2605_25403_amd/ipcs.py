@@ -38,6 +38,9 @@ IPCS_MAT_M, IPCS_MAT_K, IPCS_MAT_KP, IPCS_MAT_A, IPCS_MAT_E = 0, 1, 2, 3, 4
 IPCS_MAT_D0, IPCS_MAT_G0, IPCS_MAT_A_ELIM, IPCS_MAT_M_ELIM = 8, 12, 16, 17
 IPCS_KERNEL_PCG_SPMV_P, IPCS_KERNEL_PCG_UPDATE_P, IPCS_KERNEL_ASM_CONV = 0, 1, 2
 IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_PCG_SPMV_M = 3, 4
+IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_S, IPCS_KERNEL_BICG_UPDATE_X = 5, 6, 7
+IPCS_KERNEL_PCG_UPDATE_M = 8
+IPCS_NKERNEL = 9
 
 
 class IpcsError(RuntimeError):
@@ -108,6 +111,8 @@ _SIGS = {
     "ipcs_export_matrix": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, _P, C.c_int64]),
     "ipcs_batch_step": (C.c_int, [_P, C.c_int32, _P, _P]),
     "ipcs_profile_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "ipcs_kernel_timing": (C.c_int, [_P, C.c_uint32]),
+    "ipcs_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "ipcs_run_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -289,6 +294,18 @@ def ipcs_profile_kernel(r, kernel, nlaunch):
     return us.value
 
 
+def ipcs_kernel_timing(r, mask):
+    _check(lib.ipcs_kernel_timing(r, mask))
+
+
+def ipcs_kernel_times(r):
+    """(ms, launches) per kernel id since the last ipcs_kernel_timing call."""
+    ms = (C.c_double * IPCS_NKERNEL)()
+    cnt = (C.c_int64 * IPCS_NKERNEL)()
+    _check(lib.ipcs_kernel_times(r, ms, cnt, IPCS_NKERNEL))
+    return list(ms), list(cnt)
+
+
 def ipcs_run_destroy(r):
     lib.ipcs_run_destroy(r)
 
@@ -381,6 +398,12 @@ class Run:
 
     def time(self):
         return ipcs_get_time(self.h)
+
+    def kernel_timing(self, mask):
+        ipcs_kernel_timing(self.h, mask)
+
+    def kernel_times(self):
+        return ipcs_kernel_times(self.h)
 
     def matrix(self, which):
         """(rowptr, col, val) of a device matrix, as a scipy CSR matrix."""
