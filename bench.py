@@ -76,13 +76,17 @@ def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this kernel and workload, or None when there is none or the kernel's
     source has changed since the counters were taken."""
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(tfile):
         return None
-    t = json.load(open(tfile))
-    if t.get("source_sha1") != source_sha1(KERNELS[kernel][1]):
+    kv = {}
+    for line in open(tfile):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != source_sha1(KERNELS[kernel][1]):
         return None
-    return t.get("bytes_per_launch")
+    return float(kv["bytes_per_launch"])
 
 
 def cpu_baseline(w, budget_steps=1):
@@ -150,7 +154,6 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
                "bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"],
                "source": f"paper_2605_25403_amd/csrc/{fname}", "source_sha1": source_sha1(fname)}
     base = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}")
-    json.dump(summary, open(base + ".json", "w"), indent=1)
     with open(base + ".txt", "w") as f:
         f.write(f"HBM traffic of {kernel} on workload {workload} (rocprofv3 PMC)\n")
         f.write(f"command: {command}\n")
@@ -161,6 +164,9 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
                     f"{r_['copy_kib']:.1f} KiB -> scale {r_['scale']:.3f} -> "
                     f"{r_['bytes_per_launch'] / 1e6:.2f} MB per launch\n")
         f.write(f"total HBM bytes per launch: {summary['bytes_per_launch'] / 1e6:.2f} MB\n")
+        f.write(f"bytes_per_launch: {summary['bytes_per_launch']:.0f}\n")
+        f.write(f"source: {summary['source']}\n")
+        f.write(f"source_sha1: {summary['source_sha1']}\n")
     print(json.dumps(summary))
 
 
