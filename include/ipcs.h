@@ -112,6 +112,19 @@ void ipcs_mesh_destroy(ipcs_mesh m);
 /* ---------------------------------------------------------------- runs */
 typedef struct ipcs_run_s* ipcs_run;
 
+/* Precision forms. IPCS_FP64: every value and operation in FP64.
+ * IPCS_MIXED: quadrature, assembly arithmetic and stored matrix values in FP32
+ * (cell geometry is formed in FP64 and then rounded); fields, Krylov vectors,
+ * dot products, Jacobi diagonals and Dirichlet lifting in FP64, and SpMV
+ * products accumulated in FP64. The pressure Poisson solve is an FP64
+ * iterative refinement on the FP64 Kp, to ||r - Kp dP|| <= tol_ir ||r||,
+ * around Jacobi-CG on Kp rounded to FP32. Each pass asks the inner CG for the
+ * reduction still needed, but not below half of the reduction the previous
+ * pass achieved, nor below tol_p; an inner breakdown (the rounded singular
+ * Kp can be marginally indefinite) ends that pass at its last iterate and
+ * sets a floor (1e-6, then 100 times higher) for later passes. At most 30
+ * passes. The momentum and
+ * correction solves run on the FP32 matrices to tol_mom / tol_corr. */
 enum { IPCS_FP64 = 0, IPCS_MIXED = 1 };
 enum { IPCS_CONV_EXPLICIT = 0, IPCS_CONV_SEMI_IMPLICIT = 1 };
 
@@ -123,7 +136,7 @@ typedef struct {
   int32_t precision;    /* IPCS_FP64 or IPCS_MIXED                             */
   int32_t convection;   /* IPCS_CONV_EXPLICIT (eq. (9)) or SEMI_IMPLICIT       */
   double tol_mom;       /* relative residual tolerance, momentum BiCGStab      */
-  double tol_p;         /* pressure Poisson PCG (FP64 form)                    */
+  double tol_p;         /* pressure Poisson PCG (mixed: inner, see above)      */
   double tol_corr;      /* velocity-correction PCG                             */
   double tol_ir;        /* mixed form: FP64 iterative-refinement tolerance     */
   int32_t maxit;        /* iteration cap per solve                             */

@@ -70,7 +70,7 @@ void check_params(const ipcs_params* p) {
   need(p->maxit > 0, "maxit must be positive");
   need(p->precision == IPCS_FP64 || p->precision == IPCS_MIXED, "unknown precision");
   need(p->convection == IPCS_CONV_EXPLICIT, "only explicit convection is available");
-  need(p->precision == IPCS_FP64, "the mixed-precision form is not available in this build");
+  need(p->precision == IPCS_FP64 || p->tol_ir > 0, "the mixed form needs tol_ir > 0");
 }
 }  // namespace
 
@@ -339,7 +339,7 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
   return guard([&]() -> int {
     ipcs::Run& rr = R(r);
     const ipcs::Mesh& mm = *rr.mesh;
-    const double* src = nullptr;
+    const void* src = nullptr;
     int pat = IPCS_PATTERN_P2P2;
     if (which == IPCS_MAT_M) src = rr.M;
     else if (which == IPCS_MAT_K) src = rr.K;
@@ -368,7 +368,7 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
     need(val != nullptr && cap_nnz >= P.nnz(), "value buffer too small");
     if (col) std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
     if (rr.A_dirty) rr.reform_A();
-    rr.export_values(pat, src, val);
+    rr.export_values(pat, src, rr.vsz, val);
     return IPCS_OK;
   });
 }

@@ -70,7 +70,7 @@ struct KGroup {
   int32_t nsys, n;
   const int32_t* sptr;        // SELL slice offsets
   const int32_t* col;
-  const double* val;
+  const void* val;            // FP64 values, or FP32 (KLaunch::fp32)
   const double* dinv;         // Jacobi: 1 / diag(A)
   int32_t nblk_m, nblk_v;
   double* part_m;
@@ -89,7 +89,7 @@ struct RowAsm {
   const int32_t* c2d;         // [nc][nloc2]
   int32_t nloc2;
   const double* X;            // vertex coordinates [nv][dim]
-  double* out[3];
+  void* out[3];               // FP64 values, or FP32 in the mixed form
 };
 
 // Manufactured solution on the device
@@ -100,24 +100,27 @@ struct Builtin {
 };
 
 // ------------------------------------------------------------ launchers
-// Assembly (kernels_asm.hip). bs = rows per block, lds = dynamic LDS bytes.
-void asm_mass_stiff(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds);
-void asm_conv_explicit(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+// Assembly (kernels_asm.hip). bs = rows per block, lds = dynamic LDS bytes;
+// fp32 selects FP32 arithmetic and FP32 outputs (mixed form).
+void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
+void asm_conv_explicit(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                        const double* U, int64_t n2, double inv_dt);
-void asm_grad(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds);
-void asm_div(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds);
-void asm_kp(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds);
+void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
+void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
+void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w);
 void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, const double* fq,
                  int64_t nc, double t, double* F, int64_t n2);
-// SELL-64 matrices: sptr/col layout, rowptr gives the true row lengths
-void form_eliminated(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
-                     const int32_t* col, const uint8_t* bmask, const double* M, const double* K,
-                     double cm, double ck, double* out, double* dinv);
-void inv_diagonal(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
-                  const int32_t* col, const double* val, double* dinv);
-void lift_values(hipStream_t s, int64_t nlift, const int32_t* slot, const double* M,
-                 const double* K, double cm, double ck, double* out);
+// SELL-64 matrices: sptr/col layout, rowptr gives the true row lengths.
+// Values are FP32 when fp32 is set, else FP64; dinv and lift values are FP64.
+void form_eliminated(hipStream_t s, bool fp32, int64_t n, const int32_t* sptr,
+                     const int32_t* rowptr, const int32_t* col, const uint8_t* bmask,
+                     const void* M, const void* K, double cm, double ck, void* out, double* dinv);
+void inv_diagonal(hipStream_t s, bool fp32, int64_t n, const int32_t* sptr,
+                  const int32_t* rowptr, const int32_t* col, const void* val, double* dinv);
+void lift_values(hipStream_t s, bool fp32, int64_t nlift, const int32_t* slot, const void* M,
+                 const void* K, double cm, double ck, double* out);
+void round_to_f32(hipStream_t s, int64_t n, const double* src, float* dst);
 
 // Krylov (kernels_krylov.hip). A launch covers ngroups groups with the same
 // number of systems ns and matrix-kernel rows per thread ept_m; bmap_m/bmap_v
@@ -127,6 +130,7 @@ struct KLaunch {
   int ngroups;
   int ns;            // systems per group: 1..GMAX
   int ept_m;         // rows per thread of matrix kernels: 1, 2 or 4
+  int fp32;          // matrix values are FP32 (vectors and sums stay FP64)
   const int2* bmap_m;
   int nblocks_m;
   const int2* bmap_v;
@@ -141,6 +145,7 @@ void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhauste
 void bicg_iter(hipStream_t s, const KLaunch& L, int par);
 void ksys_finish(hipStream_t s, const KLaunch& L);            // b == 0 systems: x := 0
 void gather_states(hipStream_t s, const KLaunch& L, KState* out);   // out[g*GMAX + j]
+void set_tolerance(hipStream_t s, const KLaunch& L, double tol2);   // every system's tol^2
 // single kernels of an iteration, for timing
 void pcg_spmv_only(hipStream_t s, const KLaunch& L);
 void pcg_update_only(hipStream_t s, const KLaunch& L, int par);
@@ -160,19 +165,24 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
-void rhs_momentum(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const double* E, const double* U, const int32_t* sp21,
-                  const int32_t* col21, double* const* Gc, const double* P, const double* F,
+void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
+                  const int32_t* col22, const void* E, const double* U, const int32_t* sp21,
+                  const int32_t* col21, void* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b);
 // r = scale * sum_c D_c Us_c, then r -= mean(r) (mean_out receives it)
-void rhs_pressure(hipStream_t s, int dim, int64_t n1, const int32_t* sp12,
-                  const int32_t* col12, double* const* Dc, const double* Us, int64_t n2,
+void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* sp12,
+                  const int32_t* col12, void* const* Dc, const double* Us, int64_t n2,
                   double scale, double* r, double* part, uint32_t* cnt, double* mean_out);
+// res = b - A x (FP64 A), then res -= mean(res); totals[0..1] = sum(res), sum(res^2)
+// before the projection; mean_out receives the mean
+void residual_projected(hipStream_t s, int64_t n, const int32_t* sp, const int32_t* col,
+                        const double* A, const double* x, const double* b, double* res,
+                        double* part_s, double* part_q, double* totals, double* mean_out);
 void sub_scalar(hipStream_t s, int64_t n, const double* scal, double* v);
-void rhs_correction(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
-                    const int32_t* col22, const double* M, const double* Us,
-                    const int32_t* sp21, const int32_t* col21, double* const* Gc,
+void rhs_correction(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
+                    const int32_t* col22, const void* M, const double* Us,
+                    const int32_t* sp21, const int32_t* col21, void* const* Gc,
                     const double* dP, double scale, const int32_t* lift_ptr,
                     const int32_t* lift_col, const double* liftM, const uint8_t* bmask,
                     const double* gfull, double* b);

@@ -16,6 +16,8 @@
 //   Kp_kl = |K| grad psi_k . grad psi_l           w_k = int_K psi_k = |K|/(d+1)
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "dev_util.hpp"
 #include "device.hpp"
@@ -25,91 +27,100 @@
 
 namespace ipcs {
 
-template <int D>
+// Geometry of a cell: formed in FP64 from the vertex coordinates (the
+// differences x_k - x_0 cancel digits on fine meshes), then rounded to the
+// working type R of the quadrature loop.
+template <int D, class R = double>
 struct Geo {
-  double Ji[D][D];   // J^{-1}
-  double det;        // |det J|
+  R Ji[D][D];   // J^{-1}
+  R det;        // |det J|
 };
 
-template <int D>
-__device__ __forceinline__ Geo<D> cell_geo(const double* X, const int32_t* dofs) {
-  double x0[D], J[D][D];
+template <int D, class R = double>
+__device__ __forceinline__ Geo<D, R> cell_geo(const double* X, const int32_t* dofs) {
+  double x0[D], J[D][D], Ji[D][D], det;
 #pragma unroll
   for (int r = 0; r < D; ++r) x0[r] = X[(size_t)dofs[0] * D + r];
 #pragma unroll
   for (int k = 0; k < D; ++k)
 #pragma unroll
     for (int r = 0; r < D; ++r) J[r][k] = X[(size_t)dofs[k + 1] * D + r] - x0[r];
-  Geo<D> g;
   if constexpr (D == 2) {
-    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double id = 1.0 / det;
-    g.Ji[0][0] = J[1][1] * id;
-    g.Ji[0][1] = -J[0][1] * id;
-    g.Ji[1][0] = -J[1][0] * id;
-    g.Ji[1][1] = J[0][0] * id;
-    g.det = fabs(det);
+    Ji[0][0] = J[1][1] * id;
+    Ji[0][1] = -J[0][1] * id;
+    Ji[1][0] = -J[1][0] * id;
+    Ji[1][1] = J[0][0] * id;
   } else {
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
     const double id = 1.0 / det;
-    g.Ji[0][0] = c00 * id;
-    g.Ji[1][0] = c01 * id;
-    g.Ji[2][0] = c02 * id;
-    g.Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    g.Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    g.Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    g.Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    g.Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    g.Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-    g.det = fabs(det);
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
   }
+  Geo<D, R> g;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) g.Ji[a][b] = (R)Ji[a][b];
+  g.det = (R)fabs(det);
   return g;
 }
 
 // Reference-element tables at the quadrature points, built at compile time
-// and kept in constant memory: indices that are uniform across a wavefront
-// (q, j) are served by the scalar cache, the row-dependent entries (the row's
-// local index li) by ordinary cached loads.
-template <int D>
+// (in FP64, then rounded to R) and kept in constant memory: indices that are
+// uniform across a wavefront (q, j) are served by the scalar cache, the
+// row-dependent entries (the row's local index li) by ordinary cached loads.
+template <int D, class R = double>
 struct Tab {
   static constexpr int NQ = Rule<D>::NQ, NL = P2<D>::NLOC;
-  double w[NQ];
-  double lam[NQ][D + 1];
-  double phi[NQ][NL];
-  double dphi[NQ][NL][D];
+  R w[NQ];
+  R lam[NQ][D + 1];
+  R phi[NQ][NL];
+  R dphi[NQ][NL][D];
   constexpr Tab() : w(), lam(), phi(), dphi() {
     for (int q = 0; q < NQ; ++q) {
       double l[D + 1] = {};
       for (int k = 0; k <= D; ++k) l[k] = Rule<D>::lam(q, k);
-      w[q] = Rule<D>::w(q);
-      for (int k = 0; k <= D; ++k) lam[q][k] = l[k];
+      w[q] = (R)Rule<D>::w(q);
+      for (int k = 0; k <= D; ++k) lam[q][k] = (R)l[k];
       for (int j = 0; j < NL; ++j) {
-        phi[q][j] = P2<D>::phi(j, l);
-        for (int r = 0; r < D; ++r) dphi[q][j][r] = P2<D>::dphi(j, r, l);
+        phi[q][j] = (R)P2<D>::phi(j, l);
+        for (int r = 0; r < D; ++r) dphi[q][j][r] = (R)P2<D>::dphi(j, r, l);
       }
     }
   }
 };
 
-__constant__ Tab<2> c_tab2 = Tab<2>();
-__constant__ Tab<3> c_tab3 = Tab<3>();
+__constant__ Tab<2, double> c_tab2 = Tab<2, double>();
+__constant__ Tab<3, double> c_tab3 = Tab<3, double>();
+__constant__ Tab<2, float> c_tab2f = Tab<2, float>();
+__constant__ Tab<3, float> c_tab3f = Tab<3, float>();
 
-template <int D>
-__device__ __forceinline__ const Tab<D>& tab();
-template <>
-__device__ __forceinline__ const Tab<2>& tab<2>() { return c_tab2; }
-template <>
-__device__ __forceinline__ const Tab<3>& tab<3>() { return c_tab3; }
+template <int D, class R>
+__device__ __forceinline__ const Tab<D, R>& tab() {
+  if constexpr (D == 2 && std::is_same_v<R, double>) return c_tab2;
+  else if constexpr (D == 3 && std::is_same_v<R, double>) return c_tab3;
+  else if constexpr (D == 2) return c_tab2f;
+  else return c_tab3f;
+}
 
 // physical gradient components of reference gradient gr: g_b = sum_a Ji[a][b] gr_a
-template <int D>
-__device__ __forceinline__ void phys(const Geo<D>& g, const double* gr, double* out) {
+template <int D, class R>
+__device__ __forceinline__ void phys(const Geo<D, R>& g, const R* gr, R* out) {
 #pragma unroll
   for (int b = 0; b < D; ++b) {
-    double s = 0.0;
+    R s = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) s += g.Ji[a][b] * gr[a];
     out[b] = s;
@@ -117,28 +128,30 @@ __device__ __forceinline__ void phys(const Geo<D>& g, const double* gr, double* 
 }
 
 // ------------------------------------------------------------------ ops
-// Each op fills v[NOUT][NCOL] = the local row li of NOUT matrices.
-template <int D, int WHICH>
+// Each op fills v[NOUT][NCOL] = the local row li of NOUT matrices, computed and
+// accumulated in its working type R (double, or float in the mixed form).
+template <int D, int WHICH, class R>
 struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
+  using real = R;
   static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
-  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
-                             double (&v)[NOUT][NCOL]) const {
-    const Tab<D>& T = tab<D>();
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
-      const double wq = T.w[q] * g.det;
+      const R wq = T.w[q] * g.det;
       if (WHICH == 0) {
-        const double ci = wq * T.phi[q][li];
+        const R ci = wq * T.phi[q][li];
 #pragma unroll
         for (int j = 0; j < NCOL; ++j) v[0][j] += ci * T.phi[q][j];
       } else {
-        double gi[D];
-        phys<D>(g, T.dphi[q][li], gi);
+        R gi[D];
+        phys<D, R>(g, T.dphi[q][li], gi);
 #pragma unroll
         for (int j = 0; j < NCOL; ++j) {
-          double gj[D];
-          phys<D>(g, T.dphi[q][j], gj);
-          double s = 0.0;
+          R gj[D];
+          phys<D, R>(g, T.dphi[q][j], gj);
+          R s = 0;
 #pragma unroll
           for (int b = 0; b < D; ++b) s += gi[b] * gj[b];
           v[0][j] += wq * s;
@@ -148,68 +161,71 @@ struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
   }
 };
 
-template <int D>
+template <int D, class R>
 struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
+  using real = R;
   static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
   const double* U;        // [D][n2]
   int64_t n2;
   double inv_dt;
-  __device__ void operator()(const Geo<D>& g, const int32_t* dofs, int li,
-                             double (&v)[NOUT][NCOL]) const {
-    const Tab<D>& T = tab<D>();
-    double Uc[D][NCOL];
+  __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
+    R Uc[D][NCOL];
 #pragma unroll
     for (int c = 0; c < D; ++c)
 #pragma unroll
-      for (int m = 0; m < NCOL; ++m) Uc[c][m] = U[(size_t)c * n2 + dofs[m]];
+      for (int m = 0; m < NCOL; ++m) Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
+    const R idt = (R)inv_dt;
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
-      double uq[D];
+      R uq[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        double s = 0.0;
+        R s = 0;
 #pragma unroll
         for (int m = 0; m < NCOL; ++m) s += Uc[c][m] * T.phi[q][m];
         uq[c] = s;
       }
-      double beta[D];   // J^{-1} u_h: reference-frame velocity
+      R beta[D];   // J^{-1} u_h: reference-frame velocity
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        double s = 0.0;
+        R s = 0;
 #pragma unroll
         for (int c = 0; c < D; ++c) s += g.Ji[a][c] * uq[c];
         beta[a] = s;
       }
-      const double ci = T.w[q] * g.det * T.phi[q][li];
+      const R ci = T.w[q] * g.det * T.phi[q][li];
 #pragma unroll
       for (int j = 0; j < NCOL; ++j) {
-        double adv = 0.0;
+        R adv = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) adv += beta[a] * T.dphi[q][j][a];
-        v[0][j] += ci * (T.phi[q][j] * inv_dt - adv);
+        v[0][j] += ci * (T.phi[q][j] * idt - adv);
       }
     }
   }
 };
 
-template <int D>
+template <int D, class R>
 struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
+  using real = R;
   static constexpr int NOUT = 1, NCOL = D + 1;
   int c;
-  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
-                             double (&v)[NOUT][NCOL]) const {
-    const Tab<D>& T = tab<D>();
-    double int_phi = 0.0;
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
+    R int_phi = 0;
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) int_phi += T.w[q] * T.phi[q][li];
     int_phi *= g.det;
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-      double gr[D], gp[D];
+      R gr[D], gp[D];
 #pragma unroll
-      for (int a = 0; a < D; ++a) gr[a] = P2<D>::template dlam<double>(k, a);
-      phys<D>(g, gr, gp);
-      double gc = gp[0];
+      for (int a = 0; a < D; ++a) gr[a] = (R)P2<D>::template dlam<double>(k, a);
+      phys<D, R>(g, gr, gp);
+      R gc = gp[0];
 #pragma unroll
       for (int cc = 1; cc < D; ++cc) gc = (c == cc) ? gp[cc] : gc;
       v[0][k] += int_phi * gc;
@@ -217,21 +233,22 @@ struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
   }
 };
 
-template <int D>
+template <int D, class R>
 struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
+  using real = R;
   static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
   int c;
-  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
-                             double (&v)[NOUT][NCOL]) const {
-    const Tab<D>& T = tab<D>();
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
-      const double ci = T.w[q] * g.det * T.lam[q][li];
+      const R ci = T.w[q] * g.det * T.lam[q][li];
 #pragma unroll
       for (int j = 0; j < NCOL; ++j) {
-        double gp[D];
-        phys<D>(g, T.dphi[q][j], gp);
-        double gc = gp[0];
+        R gp[D];
+        phys<D, R>(g, T.dphi[q][j], gp);
+        R gc = gp[0];
 #pragma unroll
         for (int cc = 1; cc < D; ++cc) gc = (c == cc) ? gp[cc] : gc;
         v[0][j] += ci * gc;
@@ -240,31 +257,32 @@ struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
   }
 };
 
-template <int D>
+template <int D, class R>
 struct OpKp {   // P1 x P1 stiffness
+  using real = R;
   static constexpr int NOUT = 1, NCOL = D + 1;
-  __device__ void operator()(const Geo<D>& g, const int32_t*, int li,
-                             double (&v)[NOUT][NCOL]) const {
-    double gl[D + 1][D];
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    R gl[D + 1][D];
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-      double gr[D];
+      R gr[D];
 #pragma unroll
-      for (int a = 0; a < D; ++a) gr[a] = P2<D>::template dlam<double>(k, a);
-      phys<D>(g, gr, gl[k]);
+      for (int a = 0; a < D; ++a) gr[a] = (R)P2<D>::template dlam<double>(k, a);
+      phys<D, R>(g, gr, gl[k]);
     }
-    double gi[D];
+    R gi[D];
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-      double s = gl[0][b];
+      R s = gl[0][b];
 #pragma unroll
       for (int m = 1; m <= D; ++m) s = (li == m) ? gl[m][b] : s;
       gi[b] = s;
     }
-    const double vol = g.det * ref_measure<D>();
+    const R vol = g.det * (R)ref_measure<D>();
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-      double s = 0.0;
+      R s = 0;
 #pragma unroll
       for (int b = 0; b < D; ++b) s += gi[b] * gl[k][b];
       v[0][k] += vol * s;
@@ -275,17 +293,20 @@ struct OpKp {   // P1 x P1 stiffness
 // ------------------------------------------------------------------ kernel
 // One thread per output row; the block owns whole SELL-64 slices (blockDim a
 // multiple of 64), accumulates their values in LDS in the SELL layout and
-// writes them back as one contiguous, coalesced range.
+// writes them back as one contiguous, coalesced range. Values are of the op's
+// working type (double, or float in the mixed form).
 template <int D, class Op>
 __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
-  extern __shared__ double lds[];
+  using R = typename Op::real;
+  extern __shared__ double lds_raw[];
+  R* lds = reinterpret_cast<R*>(lds_raw);
   constexpr int NOUT = Op::NOUT, NCOL = Op::NCOL;
   const int r0 = blockIdx.x * blockDim.x;
   const int s0 = r0 >> 6;
   const int s1 = min((r0 + (int)blockDim.x + 63) >> 6, (a.nrows + 63) >> 6);
   const int base = a.sptr[s0];
   const int bent = a.sptr[s1] - base;
-  for (int k = threadIdx.x; k < NOUT * bent; k += blockDim.x) lds[k] = 0.0;
+  for (int k = threadIdx.x; k < NOUT * bent; k += blockDim.x) lds[k] = R(0);
   __syncthreads();
   const int row = r0 + threadIdx.x;
   if (row < a.nrows) {
@@ -297,12 +318,12 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
       int32_t dl[P2<D>::NLOC];
 #pragma unroll
       for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = dofs[m];
-      const Geo<D> g = cell_geo<D>(a.X, dl);
-      double v[NOUT][NCOL];
+      const Geo<D, R> g = cell_geo<D, R>(a.X, dl);
+      R v[NOUT][NCOL];
 #pragma unroll
       for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-        for (int j = 0; j < NCOL; ++j) v[o][j] = 0.0;
+        for (int j = 0; j < NCOL; ++j) v[o][j] = R(0);
       op(g, dl, li, v);
       const uint8_t* sl = a.slot + (size_t)p * a.stride;
 #pragma unroll
@@ -316,7 +337,7 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
   __syncthreads();
   for (int k = threadIdx.x; k < bent; k += blockDim.x)
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) a.out[o][base + k] = lds[o * bent + k];
+    for (int o = 0; o < NOUT; ++o) static_cast<R*>(a.out[o])[base + k] = lds[o * bent + k];
 }
 
 template <int D, class Op>
@@ -326,44 +347,50 @@ static void launch_rows(hipStream_t s, const RowAsm& a, const Op& op, int bs, si
   launch(k_asm_rows<D, Op>, dim3(nb), dim3(bs), (uint32_t)lds, s, a, op);
 }
 
+// Dispatch over dimension and working type.
+template <template <int, class> class OpT, class... P>
+static void rows_dr(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+                    P... prm) {
+  if (dim == 2 && !fp32) launch_rows<2>(s, a, OpT<2, double>{prm...}, bs, lds);
+  else if (dim == 2) launch_rows<2>(s, a, OpT<2, float>{prm...}, bs, lds);
+  else if (!fp32) launch_rows<3>(s, a, OpT<3, double>{prm...}, bs, lds);
+  else launch_rows<3>(s, a, OpT<3, float>{prm...}, bs, lds);
+}
+
+template <int D, class R>
+using OpMass = OpMassStiff<D, 0, R>;
+template <int D, class R>
+using OpStiff = OpMassStiff<D, 1, R>;
+
 // a.out[0] <- M, a.out[1] <- K
-void asm_mass_stiff(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   RowAsm am = a, ak = a;
   ak.out[0] = a.out[1];
-  if (dim == 2) {
-    launch_rows<2>(s, am, OpMassStiff<2, 0>{}, bs, lds);
-    launch_rows<2>(s, ak, OpMassStiff<2, 1>{}, bs, lds);
-  } else {
-    launch_rows<3>(s, am, OpMassStiff<3, 0>{}, bs, lds);
-    launch_rows<3>(s, ak, OpMassStiff<3, 1>{}, bs, lds);
-  }
+  rows_dr<OpMass>(dim, fp32, s, am, bs, lds);
+  rows_dr<OpStiff>(dim, fp32, s, ak, bs, lds);
 }
-void asm_conv_explicit(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+void asm_conv_explicit(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                        const double* U, int64_t n2, double inv_dt) {
-  if (dim == 2) launch_rows<2>(s, a, OpConvExplicit<2>{U, n2, inv_dt}, bs, lds);
-  else launch_rows<3>(s, a, OpConvExplicit<3>{U, n2, inv_dt}, bs, lds);
+  rows_dr<OpConvExplicit>(dim, fp32, s, a, bs, lds, U, n2, inv_dt);
 }
 // a.out[c] <- G_c (one launch per component)
-void asm_grad(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    if (dim == 2) launch_rows<2>(s, ac, OpGrad<2>{c}, bs, lds);
-    else launch_rows<3>(s, ac, OpGrad<3>{c}, bs, lds);
+    rows_dr<OpGrad>(dim, fp32, s, ac, bs, lds, c);
   }
 }
 // a.out[c] <- D_c
-void asm_div(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    if (dim == 2) launch_rows<2>(s, ac, OpDiv<2>{c}, bs, lds);
-    else launch_rows<3>(s, ac, OpDiv<3>{c}, bs, lds);
+    rows_dr<OpDiv>(dim, fp32, s, ac, bs, lds, c);
   }
 }
-void asm_kp(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
-  if (dim == 2) launch_rows<2>(s, a, OpKp<2>{}, bs, lds);
-  else launch_rows<3>(s, a, OpKp<3>{}, bs, lds);
+void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  rows_dr<OpKp>(dim, fp32, s, a, bs, lds);
 }
 
 // ------------------------------------------------------------------ vectors
@@ -407,7 +434,7 @@ __global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const dou
 #pragma unroll
     for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
     const Geo<D> g = cell_geo<D>(a.X, dl);
-    const Tab<D>& T = tab<D>();
+    const Tab<D, double>& T = tab<D, double>();
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
       const double ci = T.w[q] * g.det * T.phi[q][li];
@@ -447,13 +474,15 @@ void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, con
 
 // ------------------------------------------------------------------ elimination
 // out = cm*M + ck*K with Dirichlet rows and columns eliminated (zero, unit
-// diagonal on boundary rows); dinv = 1/diag(out). One thread per row, SELL-64
-// layout; padding entries are left untouched (zero).
+// diagonal on boundary rows); dinv = 1/diag(out) in FP64. One thread per row,
+// SELL-64 layout; padding entries are left untouched (zero). VT is the value
+// type of M, K and out.
+template <class VT>
 __global__ void __launch_bounds__(256) k_form_elim(int64_t n, const int32_t* sptr,
                                                    const int32_t* rowptr, const int32_t* col,
-                                                   const uint8_t* bmask, const double* M,
-                                                   const double* K, double cm, double ck,
-                                                   double* out, double* dinv) {
+                                                   const uint8_t* bmask, const VT* M,
+                                                   const VT* K, double cm, double ck,
+                                                   VT* out, double* dinv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const bool bi = bmask[i];
@@ -463,55 +492,85 @@ __global__ void __launch_bounds__(256) k_form_elim(int64_t n, const int32_t* spt
   for (int k = 0; k < len; ++k) {
     const int idx = base + 64 * k;
     const int j = col[idx];
-    double v;
-    if (bi || bmask[j]) v = (j == i) ? 1.0 : 0.0;
-    else v = cm * M[idx] + (K ? ck * K[idx] : 0.0);
+    VT v;
+    if (bi || bmask[j]) v = (j == i) ? VT(1) : VT(0);
+    else v = (VT)(cm * (double)M[idx] + (K ? ck * (double)K[idx] : 0.0));
     out[idx] = v;
-    if (j == i) diag = v;
+    if (j == i) diag = (double)v;
   }
   dinv[i] = 1.0 / diag;
 }
 
-void form_eliminated(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
-                     const int32_t* col, const uint8_t* bmask, const double* M, const double* K,
-                     double cm, double ck, double* out, double* dinv) {
-  hipLaunchKernelGGL(k_form_elim, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, sptr,
-                     rowptr, col, bmask, M, K, cm, ck, out, dinv);
+void form_eliminated(hipStream_t s, bool fp32, int64_t n, const int32_t* sptr,
+                     const int32_t* rowptr, const int32_t* col, const uint8_t* bmask,
+                     const void* M, const void* K, double cm, double ck, void* out,
+                     double* dinv) {
+  const dim3 g((unsigned)div_up(n, 256));
+  if (fp32)
+    hipLaunchKernelGGL(k_form_elim<float>, g, dim3(256), 0, s, n, sptr, rowptr, col, bmask,
+                       (const float*)M, (const float*)K, cm, ck, (float*)out, dinv);
+  else
+    hipLaunchKernelGGL(k_form_elim<double>, g, dim3(256), 0, s, n, sptr, rowptr, col, bmask,
+                       (const double*)M, (const double*)K, cm, ck, (double*)out, dinv);
   HIP_LAUNCH_OK();
 }
 
+template <class VT>
 __global__ void k_inv_diag(int64_t n, const int32_t* sptr, const int32_t* rowptr,
-                           const int32_t* col, const double* val, double* dinv) {
+                           const int32_t* col, const VT* val, double* dinv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int len = rowptr[i + 1] - rowptr[i];
   const int base = sptr[i >> 6] + (int)(i & 63);
   double d = 0.0;
   for (int k = 0; k < len; ++k)
-    if (col[base + 64 * k] == i) d = val[base + 64 * k];
+    if (col[base + 64 * k] == i) d = (double)val[base + 64 * k];
   dinv[i] = 1.0 / d;
 }
 
-void inv_diagonal(hipStream_t s, int64_t n, const int32_t* sptr, const int32_t* rowptr,
-                  const int32_t* col, const double* val, double* dinv) {
-  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, sptr,
-                     rowptr, col, val, dinv);
+void inv_diagonal(hipStream_t s, bool fp32, int64_t n, const int32_t* sptr,
+                  const int32_t* rowptr, const int32_t* col, const void* val, double* dinv) {
+  const dim3 g((unsigned)div_up(n, 256));
+  if (fp32)
+    hipLaunchKernelGGL(k_inv_diag<float>, g, dim3(256), 0, s, n, sptr, rowptr, col,
+                       (const float*)val, dinv);
+  else
+    hipLaunchKernelGGL(k_inv_diag<double>, g, dim3(256), 0, s, n, sptr, rowptr, col,
+                       (const double*)val, dinv);
   HIP_LAUNCH_OK();
 }
 
-__global__ void k_lift_vals(int64_t n, const int32_t* slot, const double* M, const double* K,
-                            double cm, double ck, double* out) {
+// Lifting values (FP64) of the boundary columns: out[e] = cm*M[slot] + ck*K[slot]
+template <class VT>
+__global__ void k_lift_vals(int64_t n, const int32_t* slot, const VT* M, const VT* K, double cm,
+                            double ck, double* out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int k = slot[e];
-  out[e] = cm * M[k] + (K ? ck * K[k] : 0.0);
+  out[e] = (double)(VT)(cm * (double)M[k] + (K ? ck * (double)K[k] : 0.0));
 }
 
-void lift_values(hipStream_t s, int64_t nlift, const int32_t* slot, const double* M,
-                 const double* K, double cm, double ck, double* out) {
+void lift_values(hipStream_t s, bool fp32, int64_t nlift, const int32_t* slot, const void* M,
+                 const void* K, double cm, double ck, double* out) {
   if (nlift <= 0) return;
-  hipLaunchKernelGGL(k_lift_vals, dim3((unsigned)div_up(nlift, 256)), dim3(256), 0, s, nlift,
-                     slot, M, K, cm, ck, out);
+  const dim3 g((unsigned)div_up(nlift, 256));
+  if (fp32)
+    hipLaunchKernelGGL(k_lift_vals<float>, g, dim3(256), 0, s, nlift, slot, (const float*)M,
+                       (const float*)K, cm, ck, out);
+  else
+    hipLaunchKernelGGL(k_lift_vals<double>, g, dim3(256), 0, s, nlift, slot, (const double*)M,
+                       (const double*)K, cm, ck, out);
+  HIP_LAUNCH_OK();
+}
+
+__global__ void k_round_f32(int64_t n, const double* src, float* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+void round_to_f32(hipStream_t s, int64_t n, const double* src, float* dst) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_round_f32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, n, src, dst);
   HIP_LAUNCH_OK();
 }
 

@@ -115,19 +115,21 @@ void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
 }
 
 // ---------------------------------------------------------------- right-hand sides
+// Matrices are FP64, or FP32 in the mixed form (VT); vectors and sums are FP64.
+template <class VT>
 struct Ptrs3 {
-  const double* p[3];
+  const VT* p[3];
 };
 
 // b_c[i] = sum_j A[ij] X_c[j] - sc * sum_k Gc[ik] Y[k] + F_c[i] - sum lift[i] g_c
 // on interior rows; g_c[i] on boundary rows. One thread per row, both matrices
 // in SELL-64 layout (coalesced value and column loads across the wavefront).
-template <int D>
+template <int D, class VT>
 __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
-                                                const int32_t* col22, const double* A,
+                                                const int32_t* col22, const VT* A,
                                                 const double* X, const int32_t* sp21,
-                                                const int32_t* col21, Ptrs3 Gc, const double* Y,
-                                                double sc, const double* F,
+                                                const int32_t* col21, Ptrs3<VT> Gc,
+                                                const double* Y, double sc, const double* F,
                                                 const int32_t* lift_ptr, const int32_t* lift_col,
                                                 const double* lift, const uint8_t* bmask,
                                                 const double* g, double* b) {
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
     const int sl = (int)(i >> 6), b0 = sp22[sl], w = (sp22[sl + 1] - b0) >> 6;
     const int base = b0 + (int)(i & 63);
     for (int k = 0; k < w; ++k) {
-      const double a = A[base + 64 * k];
+      const double a = (double)A[base + 64 * k];
       const int j = col22[base + 64 * k];
 #pragma unroll
       for (int c = 0; c < D; ++c) s[c] += a * X[c * n2 + j];
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
     for (int k = 0; k < w; ++k) {
       const double y = Y[col21[base + 64 * k]];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s[c] -= sc * (Gc.p[c][base + 64 * k] * y);
+      for (int c = 0; c < D; ++c) s[c] -= sc * ((double)Gc.p[c][base + 64 * k] * y);
     }
   }
   for (int e = lift_ptr[i]; e < lift_ptr[i + 1]; ++e) {
@@ -170,44 +172,58 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
   for (int c = 0; c < D; ++c) b[c * n2 + i] = s[c] + (F ? F[c * n2 + i] : 0.0);
 }
 
-void rhs_momentum(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const double* E, const double* U, const int32_t* sp21,
-                  const int32_t* col21, double* const* Gc, const double* P, const double* F,
-                  const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
-                  const uint8_t* bmask, const double* gfull, double* b) {
-  Ptrs3 gp{{Gc[0], Gc[1], dim == 3 ? Gc[2] : nullptr}};
+template <class VT>
+static void rhs_p2_launch(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
+                          const int32_t* col22, const void* A, const double* X,
+                          const int32_t* sp21, const int32_t* col21, void* const* Gc,
+                          const double* Y, double sc, const double* F, const int32_t* lift_ptr,
+                          const int32_t* lift_col, const double* lift, const uint8_t* bmask,
+                          const double* g, double* b) {
+  Ptrs3<VT> gp{{(const VT*)Gc[0], (const VT*)Gc[1], dim == 3 ? (const VT*)Gc[2] : nullptr}};
   const unsigned nb = (unsigned)div_up(n2, 256);
   if (dim == 2)
-    hipLaunchKernelGGL(k_rhs_p2<2>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, E, U, sp21, col21,
-                       gp, P, 1.0, F, lift_ptr, lift_col, liftA, bmask, gfull, b);
+    hipLaunchKernelGGL((k_rhs_p2<2, VT>), dim3(nb), dim3(256), 0, s, n2, sp22, col22,
+                       (const VT*)A, X, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
+                       bmask, g, b);
   else
-    hipLaunchKernelGGL(k_rhs_p2<3>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, E, U, sp21, col21,
-                       gp, P, 1.0, F, lift_ptr, lift_col, liftA, bmask, gfull, b);
+    hipLaunchKernelGGL((k_rhs_p2<3, VT>), dim3(nb), dim3(256), 0, s, n2, sp22, col22,
+                       (const VT*)A, X, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
+                       bmask, g, b);
   HIP_LAUNCH_OK();
 }
 
-void rhs_correction(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
-                    const int32_t* col22, const double* M, const double* Us,
-                    const int32_t* sp21, const int32_t* col21, double* const* Gc,
+void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
+                  const int32_t* col22, const void* E, const double* U, const int32_t* sp21,
+                  const int32_t* col21, void* const* Gc, const double* P, const double* F,
+                  const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
+                  const uint8_t* bmask, const double* gfull, double* b) {
+  if (fp32)
+    rhs_p2_launch<float>(s, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, 1.0, F, lift_ptr,
+                         lift_col, liftA, bmask, gfull, b);
+  else
+    rhs_p2_launch<double>(s, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, 1.0, F, lift_ptr,
+                          lift_col, liftA, bmask, gfull, b);
+}
+
+void rhs_correction(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
+                    const int32_t* col22, const void* M, const double* Us,
+                    const int32_t* sp21, const int32_t* col21, void* const* Gc,
                     const double* dP, double scale, const int32_t* lift_ptr,
                     const int32_t* lift_col, const double* liftM, const uint8_t* bmask,
                     const double* gfull, double* b) {
-  Ptrs3 gp{{Gc[0], Gc[1], dim == 3 ? Gc[2] : nullptr}};
-  const unsigned nb = (unsigned)div_up(n2, 256);
-  if (dim == 2)
-    hipLaunchKernelGGL(k_rhs_p2<2>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, M, Us, sp21,
-                       col21, gp, dP, scale, nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
+  if (fp32)
+    rhs_p2_launch<float>(s, dim, n2, sp22, col22, M, Us, sp21, col21, Gc, dP, scale, nullptr,
+                         lift_ptr, lift_col, liftM, bmask, gfull, b);
   else
-    hipLaunchKernelGGL(k_rhs_p2<3>, dim3(nb), dim3(256), 0, s, n2, sp22, col22, M, Us, sp21,
-                       col21, gp, dP, scale, nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
-  HIP_LAUNCH_OK();
+    rhs_p2_launch<double>(s, dim, n2, sp22, col22, M, Us, sp21, col21, Gc, dP, scale, nullptr,
+                          lift_ptr, lift_col, liftM, bmask, gfull, b);
 }
 
 // r[k] = scale * sum_c sum_j D_c[kj] Us_c[j] (SELL-64, one thread per row) and
 // per-block partial sums of r; k_sub_mean finishes the mean and subtracts it.
-template <int D>
+template <int D, class VT>
 __global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t* sp,
-                                                      const int32_t* col, Ptrs3 Dc,
+                                                      const int32_t* col, Ptrs3<VT> Dc,
                                                       const double* Us, int64_t n2, double scale,
                                                       double* r, double* part) {
   __shared__ double sh[16];
@@ -220,13 +236,55 @@ __global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t*
     for (int e = 0; e < w; ++e) {
       const int j = col[base + 64 * e];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s += Dc.p[c][base + 64 * e] * Us[c * n2 + j];
+      for (int c = 0; c < D; ++c) s += (double)Dc.p[c][base + 64 * e] * Us[c * n2 + j];
     }
     v = scale * s;
     r[k] = v;
   }
   const double t = block_sum(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// res = b - A x for an FP64 matrix A (SELL-64), with per-block partial sums of
+// res (part_s) and res^2 (part_q)
+__global__ void __launch_bounds__(256) k_resid(int64_t n, const int32_t* sp, const int32_t* col,
+                                               const double* A, const double* x,
+                                               const double* b, double* res, double* part_s,
+                                               double* part_q) {
+  __shared__ double sh[16];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const int sl = (int)(i >> 6), b0 = sp[sl], w = (sp[sl + 1] - b0) >> 6;
+    const int base = b0 + (int)(i & 63);
+    double s = 0.0;
+    for (int e = 0; e < w; ++e) s += A[base + 64 * e] * x[col[base + 64 * e]];
+    v = b[i] - s;
+    res[i] = v;
+  }
+  const double t = block_sum(v, sh);
+  const double q = block_sum(v * v, sh);
+  if (threadIdx.x == 0) {
+    part_s[blockIdx.x] = t;
+    part_q[blockIdx.x] = q;
+  }
+}
+
+// out[0] = sum of part_s, out[1] = sum of part_q (one block, fixed order)
+__global__ void __launch_bounds__(256) k_total2(int nb, const double* part_s,
+                                                const double* part_q, double* out) {
+  __shared__ double sh[16];
+  double a = 0.0, c = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    a += part_s[b];
+    c += part_q[b];
+  }
+  a = block_sum(a, sh);
+  c = block_sum(c, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = c;
+  }
 }
 
 // v -= (sum of nb partials) / n, every block reducing the partials itself
@@ -242,21 +300,41 @@ __global__ void __launch_bounds__(256) k_sub_mean(int64_t n, int nb, const doubl
     v[i] -= mean;
 }
 
-void rhs_pressure(hipStream_t s, int dim, int64_t n1, const int32_t* sp12,
-                  const int32_t* col12, double* const* Dc, const double* Us, int64_t n2,
+void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* sp12,
+                  const int32_t* col12, void* const* Dc, const double* Us, int64_t n2,
                   double scale, double* r, double* part, uint32_t* cnt, double* mean_out) {
   (void)cnt;
-  Ptrs3 dp{{Dc[0], Dc[1], dim == 3 ? Dc[2] : nullptr}};
   const int nb = (int)div_up(n1, 256);
   if (nb > 8192) fail(IPCS_E_INVALID, "pressure space too large for the partial buffer");
-  if (dim == 2)
-    hipLaunchKernelGGL(k_rhs_pressure<2>, dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp, Us, n2,
-                       scale, r, part);
-  else
-    hipLaunchKernelGGL(k_rhs_pressure<3>, dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp, Us, n2,
-                       scale, r, part);
+  auto go = [&](auto vt) {
+    using VT = decltype(vt);
+    Ptrs3<VT> dp{{(const VT*)Dc[0], (const VT*)Dc[1], dim == 3 ? (const VT*)Dc[2] : nullptr}};
+    if (dim == 2)
+      hipLaunchKernelGGL((k_rhs_pressure<2, VT>), dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp,
+                         Us, n2, scale, r, part);
+    else
+      hipLaunchKernelGGL((k_rhs_pressure<3, VT>), dim3(nb), dim3(256), 0, s, n1, sp12, col12, dp,
+                         Us, n2, scale, r, part);
+  };
+  if (fp32) go(0.0f);
+  else go(0.0);
   HIP_LAUNCH_OK();
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n1, 256)), dim3(256), 0, s, n1, nb, part, r,
+                     mean_out);
+  HIP_LAUNCH_OK();
+}
+
+void residual_projected(hipStream_t s, int64_t n, const int32_t* sp, const int32_t* col,
+                        const double* A, const double* x, const double* b, double* res,
+                        double* part_s, double* part_q, double* totals, double* mean_out) {
+  const int nb = (int)div_up(n, 256);
+  if (nb > 8192) fail(IPCS_E_INVALID, "pressure space too large for the partial buffer");
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(256), 0, s, n, sp, col, A, x, b, res, part_s,
+                     part_q);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_total2, dim3(1), dim3(256), 0, s, nb, part_s, part_q, totals);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n, 256)), dim3(256), 0, s, n, nb, part_s, res,
                      mean_out);
   HIP_LAUNCH_OK();
 }

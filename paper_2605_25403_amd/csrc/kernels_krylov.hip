@@ -57,10 +57,12 @@ namespace ipcs {
   const int lb = m_.y;
 
 // Row i of the group's SELL-64 matrix applied to NS gathered vectors:
-// acc[j] = sum_k A(i, col_k) * gath(j, col_k). The slice width is uniform in
-// the wavefront; the last chunk of eight re-reads entry w-1 and discards it.
-template <int NS, class G>
+// acc[j] = sum_k A(i, col_k) * gath(j, col_k), in FP64 whatever the stored
+// value type VT. The slice width is uniform in the wavefront; the last chunk
+// of eight re-reads entry w-1 and discards it.
+template <int NS, class VT, class G>
 __device__ __forceinline__ void sell_row(const KGroup& g, int i, G gath, double (&acc)[NS]) {
+  const VT* val = static_cast<const VT*>(g.val);
   const int s = i >> 6;
   const int b0 = g.sptr[s];
   const int w = (g.sptr[s + 1] - b0) >> 6;
@@ -74,7 +76,7 @@ __device__ __forceinline__ void sell_row(const KGroup& g, int i, G gath, double 
     for (int q = 0; q < 8; ++q) {
       const int kk = k + q < w ? k + q : w - 1;
       c[q] = g.col[base + 64 * kk];
-      a[q] = g.val[base + 64 * kk];
+      a[q] = (double)val[base + 64 * kk];
     }
     double xv[NS][8];
 #pragma unroll
@@ -97,7 +99,7 @@ __device__ __forceinline__ int row_of(int lb, int e) {
 // r = b - A x for the systems that start (mode 0: all) or are confirmed
 // (mode 1: PENDING or RESTART). PCG: u = D^{-1} r, p = s = 0. BiCGStab:
 // rhat = p = r, phat = D^{-1} r. Partials r.r, r.u, b.b.
-template <bool PCG, int NS, int EPT>
+template <bool PCG, int NS, int EPT, class VT>
 __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2* bmap, int mode) {
   GROUP_HEAD(bmap)
   __shared__ double sh[(KBS / 64) * NS * 3];
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
       const int i = row_of<EPT>(lb, e);
       if (i >= g.n) continue;
       double ax[NS];
-      sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].x[c]; }, ax);
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].x[c]; }, ax);
       const double di = g.dinv[i];
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
 }
 
 // ------------------------------------------------------------------ PCG (Chronopoulos-Gear)
-template <int NS, int EPT>
+template <int NS, int EPT, class VT>
 __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int2* bmap) {
   GROUP_HEAD(bmap)
   __shared__ double sh[(KBS / 64) * NS];
@@ -218,7 +220,7 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
 #pragma unroll
     for (int j = 0; j < NS; ++j) y[e][j] = ui[e][j] = 0.0;
     if (i < g.n) {
-      sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].u[c]; }, y[e]);
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].u[c]; }, y[e]);
 #pragma unroll
       for (int j = 0; j < NS; ++j) ui[e][j] = g.v[j].u[i];
     }
@@ -354,7 +356,7 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
 // ------------------------------------------------------------------ BiCGStab
 // b2 (WHICH = 0): v = A phat, partial rhat.v
 // b4 (WHICH = 1): t = A shat, partials t.s, t.t, rhat.s, rhat.t
-template <int WHICH, int NS, int EPT>
+template <int WHICH, int NS, int EPT, class VT>
 __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const int2* bmap) {
   GROUP_HEAD(bmap)
   constexpr int K = WHICH == 0 ? 1 : 4;
@@ -374,9 +376,9 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
     for (int j = 0; j < NS; ++j) y[e][j] = rh[e][j] = si[e][j] = 0.0;
     if (i < g.n) {
       if (WHICH == 0)
-        sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].phat[c]; }, y[e]);
+        sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].phat[c]; }, y[e]);
       else
-        sell_row<NS>(g, i, [&](int j, int c) { return g.v[j].shat[c]; }, y[e]);
+        sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].shat[c]; }, y[e]);
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         rh[e][j] = g.v[j].u[i];
@@ -608,6 +610,12 @@ __global__ void __launch_bounds__(KBS) k_finish(const KGroup* groups, const int2
   }
 }
 
+__global__ void k_set_tol2(const KGroup* groups, int ngroups, double tol2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gi = t / GMAX, j = t % GMAX;
+  if (gi < ngroups && j < groups[gi].nsys) groups[gi].v[j].st->tol2 = tol2;
+}
+
 __global__ void k_gather_states(const KGroup* groups, int ngroups, KState* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int gi = t / GMAX, j = t % GMAX;
@@ -628,13 +636,18 @@ static void with_ns(int ns, F f) {
   }
 }
 
+// matrix kernels: systems per group, rows per thread, stored value type
 template <class F>
-static void with_ns_ept(int ns, int ept, F f) {
-  with_ns(ns, [&](auto N) {
-    switch (ept) {
-      case 1: f(N, ic<1>{}); break;
-      case 2: f(N, ic<2>{}); break;
-      case 4: f(N, ic<4>{}); break;
+static void with_ns_ept(const KLaunch& L, F f) {
+  with_ns(L.ns, [&](auto N) {
+    auto vt = [&](auto E) {
+      if (L.fp32) f(N, E, float{});
+      else f(N, E, double{});
+    };
+    switch (L.ept_m) {
+      case 1: vt(ic<1>{}); break;
+      case 2: vt(ic<2>{}); break;
+      case 4: vt(ic<4>{}); break;
       default: fail(IPCS_E_INVALID, "matrix kernels take 1, 2 or 4 rows per thread");
     }
   });
@@ -642,11 +655,12 @@ static void with_ns_ept(int ns, int ept, F f) {
 
 #define NSV decltype(N)::value
 #define EPTV decltype(E)::value
+#define VTV decltype(V)
 
 template <bool PCG>
 static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
-  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    launch(k_start<PCG, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+  with_ns_ept(L, [&](auto N, auto E, auto V) {
+    launch(k_start<PCG, NSV, EPTV, VTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m, mode);
   });
   HIP_LAUNCH_OK();
@@ -666,8 +680,8 @@ void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhauste
 }
 
 void pcg_spmv_only(hipStream_t s, const KLaunch& L) {
-  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    launch(k_cg_spmv<NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+  with_ns_ept(L, [&](auto N, auto E, auto V) {
+    launch(k_cg_spmv<NSV, EPTV, VTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m);
   });
   HIP_LAUNCH_OK();
@@ -687,8 +701,8 @@ void pcg_iter(hipStream_t s, const KLaunch& L, int par) {
 }
 
 void bicg_spmv_only(hipStream_t s, const KLaunch& L) {
-  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    launch(k_bicg_spmv<0, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+  with_ns_ept(L, [&](auto N, auto E, auto V) {
+    launch(k_bicg_spmv<0, NSV, EPTV, VTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m);
   });
   HIP_LAUNCH_OK();
@@ -703,8 +717,8 @@ void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par) {
 }
 
 void bicg_spmv_t_only(hipStream_t s, const KLaunch& L) {
-  with_ns_ept(L.ns, L.ept_m, [&](auto N, auto E) {
-    launch(k_bicg_spmv<1, NSV, EPTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
+  with_ns_ept(L, [&](auto N, auto E, auto V) {
+    launch(k_bicg_spmv<1, NSV, EPTV, VTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m);
   });
   HIP_LAUNCH_OK();
@@ -729,6 +743,13 @@ void ksys_finish(hipStream_t s, const KLaunch& L) {
   with_ns(L.ns, [&](auto N) {
     launch(k_finish<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v);
   });
+  HIP_LAUNCH_OK();
+}
+
+void set_tolerance(hipStream_t s, const KLaunch& L, double tol2) {
+  const int n = L.ngroups * GMAX;
+  hipLaunchKernelGGL(k_set_tol2, dim3((unsigned)div_up(n, 64)), dim3(64), 0, s, L.groups,
+                     L.ngroups, tol2);
   HIP_LAUNCH_OK();
 }
 

@@ -23,6 +23,8 @@ int kept_m_for(int64_t n) {
 int nblk_m_for(int64_t n) {
   return (int)std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_m_for(n)));
 }
+constexpr int kMaxRefine = 30;   // mixed form: refinement passes
+
 int nblk_v_for(int64_t n) {
   const int64_t b = std::max<int64_t>(1, div_up(n, (int64_t)KBS * KEPT_V));
   if (b > KNB_MAX) fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
@@ -38,9 +40,9 @@ void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap) {
       if (b < nblk[g]) bmap.push_back(make_int2((int)g, b));
 }
 
-// LDS needed by the assembly kernel with bs rows per block: NOUT * the largest
-// number of SELL entries of the bs/64 slices a block owns.
-static AsmCfg asm_cfg(const Sell& S, int nout) {
+// LDS needed by the assembly kernel with bs rows per block: the largest
+// number of SELL entries of the bs/64 slices a block owns, times the value size.
+static AsmCfg asm_cfg(const Sell& S, int vbytes) {
   for (int bs : {256, 128, 64}) {
     int64_t mx = 0;
     const int per = bs / 64;
@@ -48,7 +50,7 @@ static AsmCfg asm_cfg(const Sell& S, int nout) {
       const int64_t s1 = std::min<int64_t>(s0 + per, S.nslices);
       mx = std::max<int64_t>(mx, S.sptr[s1] - S.sptr[s0]);
     }
-    const size_t lds = (size_t)nout * mx * sizeof(double);
+    const size_t lds = (size_t)mx * vbytes;
     if (lds <= 65536) return AsmCfg{bs, std::max<size_t>(lds, 8)};
   }
   fail(IPCS_E_INVALID, "matrix rows too long for the assembly kernel");
@@ -214,15 +216,17 @@ void Run::layout(Carver& c) {
   lift_ptr = c.take<int32_t>(n2 + 1);
   lift_slot = c.take<int32_t>(std::max<int64_t>(nlift, 1));
   lift_col = c.take<int32_t>(std::max<int64_t>(nlift, 1));
-  M = c.take<double>(ne22);
-  K = c.take<double>(ne22);
-  E = c.take<double>(ne22);
-  Ael = c.take<double>(ne22);
-  Mel = c.take<double>(ne22);
-  Kp = c.take<double>(ne11);
+  auto vals = [&](int64_t n) -> void* { return c.take<char>(n * vsz); };
+  M = vals(ne22);
+  K = vals(ne22);
+  E = vals(ne22);
+  Ael = vals(ne22);
+  Mel = vals(ne22);
+  Kp = vals(ne11);
+  Kp64 = mixed ? c.take<double>(ne11) : static_cast<double*>(Kp);
   for (int k = 0; k < 3; ++k) {
-    Dc[k] = k < dim ? c.take<double>(ne12) : nullptr;
-    Gc[k] = k < dim ? c.take<double>(ne21) : nullptr;
+    Dc[k] = k < dim ? vals(ne12) : nullptr;
+    Gc[k] = k < dim ? vals(ne21) : nullptr;
   }
   liftA = c.take<double>(std::max<int64_t>(nlift, 1));
   liftM = c.take<double>(std::max<int64_t>(nlift, 1));
@@ -241,6 +245,8 @@ void Run::layout(Carver& c) {
   rP = c.take<double>(n1);
   kv2 = c.take<double>(8 * dim * n2);
   kv1 = c.take<double>(5 * n1);
+  rIR = mixed ? c.take<double>(n1) : nullptr;
+  dIR = mixed ? c.take<double>(n1) : nullptr;
   kst = c.take<KState>(nsys);
   kgroups = c.take<KGroup>(3);
   for (int gi = 0; gi < 3; ++gi) {
@@ -308,25 +314,31 @@ void Run::upload_mesh() {
 void Run::assemble_constant() {
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr}};
-  asm_mass_stiff(dim, stream, a22, cfg_mk.bs, cfg_mk.lds);
+  asm_mass_stiff(dim, mixed, stream, a22, cfg_mk.bs, cfg_mk.lds);
   RowAsm a21{(int32_t)n2, sp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
              {Gc[0], Gc[1], Gc[2]}};
-  asm_grad(dim, stream, a21, cfg_g.bs, cfg_g.lds);
+  asm_grad(dim, mixed, stream, a21, cfg_g.bs, cfg_g.lds);
   RowAsm a12{(int32_t)n1, sp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
              {Dc[0], Dc[1], Dc[2]}};
-  asm_div(dim, stream, a12, cfg_d.bs, cfg_d.lds);
+  asm_div(dim, mixed, stream, a12, cfg_d.bs, cfg_d.lds);
+  // Kp is assembled in FP64 in both forms. The mixed form keeps that FP64
+  // copy for the refinement residual and gives the inner CG the same matrix
+  // rounded to FP32, the FP32 operator closest to it, so that a refinement
+  // pass is limited by the inner tolerance rather than by the operator.
   RowAsm a11{(int32_t)n1, sp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
-             {Kp, nullptr, nullptr}};
-  asm_kp(dim, stream, a11, cfg_kp.bs, cfg_kp.lds);
+             {Kp64, nullptr, nullptr}};
+  asm_kp(dim, false, stream, a11, cfg_kp.bs, cfg_kp.lds * (8 / vsz));
+  if (mixed) round_to_f32(stream, ne11, Kp64, static_cast<float*>(Kp));
   asm_lumped_p1(dim, stream, a11, w);
-  inv_diagonal(stream, n1, sp11, rp11, col11, Kp, dinvKp);
-  form_eliminated(stream, n2, sp22, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
-  lift_values(stream, nlift, lift_slot, M, nullptr, 1.0, 0.0, liftM);
+  inv_diagonal(stream, mixed, n1, sp11, rp11, col11, Kp, dinvKp);
+  form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
+  lift_values(stream, mixed, nlift, lift_slot, M, nullptr, 1.0, 0.0, liftM);
 }
 
 void Run::reform_A() {
-  form_eliminated(stream, n2, sp22, rp22, col22, bmask, M, K, 1.0 / prm.dt, prm.nu, Ael, dinvA);
-  lift_values(stream, nlift, lift_slot, M, K, 1.0 / prm.dt, prm.nu, liftA);
+  form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, M, K, 1.0 / prm.dt, prm.nu, Ael,
+                  dinvA);
+  lift_values(stream, mixed, nlift, lift_slot, M, K, 1.0 / prm.dt, prm.nu, liftA);
   bi.nu = prm.nu;
   A_dirty = false;
 }
@@ -353,15 +365,15 @@ void Run::setup_solvers() {
     g.part_m = part_m[gi];
     g.part_v[0] = part_v[gi][0];
     g.part_v[1] = part_v[gi][1];
-    if (gi == 1) {   // pressure Poisson: Kp dP = r
+    if (gi == 1) {   // pressure Poisson: Kp dP = r (mixed: Kp d = refinement residual)
       g.nsys = 1;
       g.sptr = sp11;
       g.col = col11;
       g.val = Kp;
       g.dinv = dinvKp;
       KVecs& V = g.v[0];
-      V.b = rP;
-      V.x = dP;
+      V.b = mixed ? rIR : rP;
+      V.x = mixed ? dIR : dP;
       V.r = kv1;
       V.u = kv1 + n1;
       V.p = kv1 + 2 * n1;
@@ -406,7 +418,7 @@ void Run::setup_solvers() {
                           hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(bmap_v[gi], maps_v[gi].data(), sizeof(int2) * maps_v[gi].size(),
                           hipMemcpyHostToDevice, stream));
-    S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n),
+    S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n), mixed ? 1 : 0,
                   bmap_m[gi],        (int)maps_m[gi].size(),
                   bmap_v[gi],        (int)maps_v[gi].size()};
     S.d_poll = poll + gi * GMAX;
@@ -430,13 +442,15 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   mesh = std::move(m);
   prm = p;
   stream = s;
+  mixed = prm.precision == IPCS_MIXED;
+  vsz = mixed ? 4 : 8;
   sizes_from_mesh();
   const Mesh& mm = *mesh;
-  cfg_mk = asm_cfg(mm.e22, 1);
-  cfg_e = asm_cfg(mm.e22, 1);
-  cfg_g = asm_cfg(mm.e21, 1);
-  cfg_d = asm_cfg(mm.e12, 1);
-  cfg_kp = asm_cfg(mm.e11, 1);
+  cfg_mk = asm_cfg(mm.e22, vsz);
+  cfg_e = asm_cfg(mm.e22, vsz);
+  cfg_g = asm_cfg(mm.e21, vsz);
+  cfg_d = asm_cfg(mm.e12, vsz);
+  cfg_kp = asm_cfg(mm.e11, vsz);
   Carver meas;
   layout(meas);
   if (!ws || bytes < meas.off)
@@ -449,11 +463,16 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   upload_mesh();
   // value arrays: SELL padding entries must read as zero
-  for (double* v : {M, K, E, Ael, Mel}) HIP_OK(hipMemsetAsync(v, 0, sizeof(double) * ne22, stream));
-  HIP_OK(hipMemsetAsync(Kp, 0, sizeof(double) * ne11, stream));
+  for (void* v : {M, K, E, Ael, Mel}) HIP_OK(hipMemsetAsync(v, 0, (size_t)vsz * ne22, stream));
+  HIP_OK(hipMemsetAsync(Kp, 0, (size_t)vsz * ne11, stream));
+  if (mixed) {
+    HIP_OK(hipMemsetAsync(Kp64, 0, sizeof(double) * ne11, stream));
+    HIP_OK(hipMemsetAsync(rIR, 0, sizeof(double) * n1, stream));
+    HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
+  }
   for (int k = 0; k < dim; ++k) {
-    HIP_OK(hipMemsetAsync(Dc[k], 0, sizeof(double) * ne12, stream));
-    HIP_OK(hipMemsetAsync(Gc[k], 0, sizeof(double) * ne21, stream));
+    HIP_OK(hipMemsetAsync(Dc[k], 0, (size_t)vsz * ne12, stream));
+    HIP_OK(hipMemsetAsync(Gc[k], 0, (size_t)vsz * ne21, stream));
   }
   const size_t vbytes = sizeof(double) * dim * n2;
   for (double* v : {U, Unew, Ustar, bU, F, gfull}) HIP_OK(hipMemsetAsync(v, 0, vbytes, stream));
@@ -577,9 +596,9 @@ int Run::phase(int which, ipcs_step_stats* st) {
         has_F = true;
       }
       timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
-        asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+        asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
       });
-      rhs_momentum(stream, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, has_F ? F : nullptr,
+      rhs_momentum(stream, dim, mixed, n2, sp22, col22, E, U, sp21, col21, Gc, P, has_F ? F : nullptr,
                    lift_ptr, lift_col, liftA, bmask, gfull, bU);
       copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
       HIP_OK(hipEventRecord(ev[1], stream));
@@ -599,11 +618,10 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     }
     case IPCS_PHASE_PRESSURE: {
-      rhs_pressure(stream, dim, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart, scnt,
-                   scal + 0);
+      rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
+                   scnt, scal + 0);
       HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
-      rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
-      fill_stats_solve(hs, 1, 2, st);
+      rc = pressure_solve(hs, st);
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 2;
         phase_next = IPCS_PHASE_ASM;
@@ -615,7 +633,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     }
     case IPCS_PHASE_CORRECTION: {
-      rhs_correction(stream, dim, n2, sp22, col22, M, Ustar, sp21, col21, Gc, dP,
+      rhs_correction(stream, dim, mixed, n2, sp22, col22, M, Ustar, sp21, col21, Gc, dP,
                      prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
       HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
                             stream));
@@ -709,7 +727,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
       case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L, 0); break;
       case IPCS_KERNEL_ASM_CONV:
-        asm_conv_explicit(dim, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+        asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;
       case IPCS_KERNEL_PCG_SPMV_M: pcg_spmv_only(stream, set_corr.L); break;
@@ -748,15 +766,85 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   return 1000.0 * ms / nlaunch;
 }
 
-void Run::export_values(int pattern, const double* dev, double* out) {
+void Run::export_values(int pattern, const void* dev, int vbytes, double* out) {
   const Sell& S = mesh->sell(pattern);
   const Pattern& P = mesh->pattern(pattern);
   std::vector<double> h(S.nent);
-  HIP_OK(hipMemcpyAsync(h.data(), dev, sizeof(double) * S.nent, hipMemcpyDeviceToHost, stream));
-  HIP_OK(hipStreamSynchronize(stream));
+  if (vbytes == 4) {
+    std::vector<float> hf(S.nent);
+    HIP_OK(hipMemcpyAsync(hf.data(), dev, sizeof(float) * S.nent, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    for (int64_t k = 0; k < S.nent; ++k) h[k] = hf[k];
+  } else {
+    HIP_OK(hipMemcpyAsync(h.data(), dev, sizeof(double) * S.nent, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+  }
   for (int64_t i = 0; i < P.nrows; ++i)
     for (int k = 0; k < P.rowptr[i + 1] - P.rowptr[i]; ++k)
       out[P.rowptr[i] + k] = h[S.index(i, k)];
+}
+
+// Pressure Poisson solve (eq. (9), second line). FP64 form: one Jacobi-CG
+// solve of Kp dP = r to tol_p. Mixed form: iterative refinement in FP64 on
+// the FP64 Kp: res = r - Kp dP (projected to zero sum), stop when
+// ||res|| <= tol_ir ||r||, else solve Kp32 d = res with Jacobi-CG on the FP32
+// matrix (FP64 vectors and sums) to a loose relative tolerance and add d.
+int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
+  if (!mixed) {
+    const int rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs,
+                                pinned, timer);
+    fill_stats_solve(hs, 1, 2, st);
+    return rc;
+  }
+  double* tot = scal + 3;   // [3] sum(res), [4] sum(res^2); [5] mean
+  double host[2];
+  double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0;
+  double floor_in = 0.0;   // raised after an inner breakdown
+  int inner_total = 0, outer = 0, rc = IPCS_OK;
+  for (;; ++outer) {
+    residual_projected(stream, n1, sp11, col11, Kp64, dP, rP, rIR, spart, spart + 8192, tot,
+                       scal + 5);
+    HIP_OK(hipMemcpyAsync(host, tot, sizeof(host), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    const double rr = std::max(0.0, host[1] - host[0] * host[0] / (double)n1);
+    if (bb < 0.0) bb = rr;   // dP = 0 on the first pass: res = r
+    rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    if (!std::isfinite(rr)) {
+      rc = IPCS_E_NONFINITE;
+      break;
+    }
+    if (rr <= prm.tol_ir * prm.tol_ir * bb) break;
+    if (outer >= kMaxRefine) {
+      rc = IPCS_E_NOT_CONVERGED;
+      break;
+    }
+    // inner tolerance: the reduction still needed, but not below half of the
+    // reduction the last pass achieved (the FP32 operator's limit)
+    if (outer > 0) contraction = rel / prev;
+    prev = rel;
+    const double need = prm.tol_ir / rel;
+    const double tol_in =
+        std::min(0.5, std::max({need, 0.5 * contraction, floor_in, prm.tol_p}));
+    set_tolerance(stream, set_p.L, tol_in * tol_in);
+    HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
+    rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
+    inner_total += hs[0].it;
+    if (rc == IPCS_E_BREAKDOWN) {
+      // Kp rounded to FP32 is singular only up to rounding and can be
+      // marginally indefinite: the pass ends at its last iterate (x is not
+      // updated by the breaking iteration) and later passes stop earlier
+      floor_in = floor_in == 0.0 ? 1e-6 : std::min(1e-2, floor_in * 100.0);
+      rc = IPCS_OK;
+    }
+    if (rc != IPCS_OK) break;
+    axpy_inplace(stream, n1, 1.0, dIR, dP);
+  }
+  if (st) {
+    st->it_p = inner_total;
+    st->res_p = rel;
+    st->ir_outer = outer;
+  }
+  return rc;
 }
 
 }  // namespace ipcs

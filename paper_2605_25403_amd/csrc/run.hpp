@@ -116,8 +116,13 @@ struct Run {
   int32_t *inc2p = nullptr, *inc2 = nullptr, *inc1p = nullptr, *inc1 = nullptr;
   uint8_t *s22 = nullptr, *s21 = nullptr, *s11 = nullptr, *s12 = nullptr;
   int32_t *lift_ptr = nullptr, *lift_slot = nullptr, *lift_col = nullptr;
-  double *M = nullptr, *K = nullptr, *E = nullptr, *Ael = nullptr, *Mel = nullptr;
-  double *Kp = nullptr, *Dc[3] = {}, *Gc[3] = {};
+  // matrix values: FP64, or FP32 in the mixed form (vsz bytes per value)
+  bool mixed = false;
+  int vsz = 8;
+  void *M = nullptr, *K = nullptr, *E = nullptr, *Ael = nullptr, *Mel = nullptr;
+  void *Kp = nullptr, *Dc[3] = {}, *Gc[3] = {};
+  double* Kp64 = nullptr;     // FP64 Kp (the same array as Kp in the FP64 form)
+  double *rIR = nullptr, *dIR = nullptr;   // mixed form: refinement residual, correction
   double *liftA = nullptr, *liftM = nullptr;
   double *dinvA = nullptr, *dinvM = nullptr, *dinvKp = nullptr, *w = nullptr;
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
@@ -170,8 +175,9 @@ struct Run {
   int phase(int which, ipcs_step_stats* st);
   int step(ipcs_step_stats* st);
   double profile_kernel(int kernel, int nlaunch);
-  // host-side CSR values of a device SELL matrix
-  void export_values(int pattern, const double* dev, double* out);
+  // host-side CSR values (FP64) of a device SELL matrix of value size vbytes
+  void export_values(int pattern, const void* dev, int vbytes, double* out);
+  int pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st);
 };
 
 void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_step_stats* st);
