@@ -28,9 +28,11 @@
  *     IPCS_E_INVALID and writes nothing.
  *   - Device memory: a run lives entirely inside one caller-provided device
  *     workspace (dev_ws, ws_bytes >= ipcs_run_workspace_bytes); the library
- *     never frees it and allocates no other device memory except small pinned
- *     host staging buffers. All device work of a run is issued on the HIP
- *     stream given at creation (or to ipcs_batch_step).
+ *     never frees it. Besides small pinned host staging buffers, the only
+ *     other allocation is ipcs_batch_step's stream-ordered one (hipMallocAsync,
+ *     released with hipFreeAsync before it returns) for the descriptors of its
+ *     shared launches. All device work of a run is issued on the HIP stream
+ *     given at creation (or to ipcs_batch_step).
  *   - Layout: velocity is component-major [dim][N2]. P2 DOFs are the mesh
  *     vertices (input order) followed by the edges sorted by (min vertex, max
  *     vertex); P1 DOFs are the vertices. All host-side fields are FP64,
@@ -231,10 +233,16 @@ enum { IPCS_MAT_M = 0, IPCS_MAT_K = 1, IPCS_MAT_KP = 2, IPCS_MAT_A = 3,
 int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_rows,
                        int32_t* col, double* val, int64_t cap_nnz);
 
-/* One IPCS step for every run in runs[0..nruns) with shared kernel launches
- * on one stream (serving form): the runs' Krylov iterations advance together
- * with per-run scalars and convergence. Each run's result is the same as when
- * it is stepped alone. stats may be NULL or hold nruns entries. */
+/* One IPCS step (eq. (9)) for every run in runs[0..nruns) on one stream
+ * (serving form). Assembly and right-hand sides are launched run by run; each
+ * Krylov iteration of all runs is one set of shared launches, with per-run
+ * scalars, reductions and stopping decisions, so every run's result is bitwise
+ * the one it gets when stepped alone. Runs may differ in mesh, viscosity and
+ * time step, and may mix the FP64 and mixed forms; they must share the
+ * dimension and be between steps. A run whose solve fails keeps its state at
+ * the last completed step (stats[i].status and failed_solve say which); the
+ * others complete their step. Returns IPCS_OK or the first failure. stats may
+ * be NULL or hold nruns entries; their phase times are the batch's. */
 int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats);
 
 enum {                            /* kernels of the step, for the timing hooks       */

@@ -375,11 +375,14 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
 
 int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats) {
   return guard([&]() -> int {
-    (void)runs;
-    (void)nruns;
-    (void)hip_stream;
-    (void)stats;
-    ipcs::fail(IPCS_E_STATE, "batched stepping is not available in this build");
+    need(runs != nullptr && nruns > 0, "need at least one run");
+    std::vector<ipcs::Run*> rs((size_t)nruns);
+    for (int i = 0; i < nruns; ++i) {
+      need(runs[i] != nullptr, "null run in the batch");
+      rs[i] = &R(runs[i]);
+      for (int k = 0; k < i; ++k) need(rs[k] != rs[i], "a run appears twice in the batch");
+    }
+    return ipcs::batch_step(rs.data(), nruns, static_cast<hipStream_t>(hip_stream), stats);
   });
 }
 

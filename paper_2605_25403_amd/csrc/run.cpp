@@ -56,7 +56,7 @@ static AsmCfg asm_cfg(const Sell& S, int vbytes) {
   fail(IPCS_E_INVALID, "matrix rows too long for the assembly kernel");
 }
 
-static int status_to_code(int s) {
+int status_to_code(int s) {
   switch (s) {
     case KS_MAXIT: return IPCS_E_NOT_CONVERGED;
     case KS_BREAKDOWN: return IPCS_E_BREAKDOWN;
@@ -555,6 +555,93 @@ void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_s
   }
 }
 
+// Step pieces shared by single runs and batches (all on the run's stream).
+
+// Dirichlet data and forcing at t^{n+1}, E = M/dt - C(U^n), momentum RHS, U* start.
+void Run::asm_phase() {
+  if (A_dirty) reform_A();
+  t1 = t + prm.dt;
+  HIP_OK(hipEventRecord(ev[0], stream));
+  if (g_cb) {
+    std::vector<double> vals((size_t)nb * dim);
+    g_cb(g_ctx, dim, nb, h_xb.data(), t1, vals.data());
+    HIP_OK(hipMemcpyAsync(gb, vals.data(), sizeof(double) * vals.size(), hipMemcpyHostToDevice,
+                          stream));
+    dirichlet_scatter(stream, dim, gb, bidx, nb, gfull, n2);
+    HIP_OK(hipStreamSynchronize(stream));
+  } else if (bi.kind) {
+    dirichlet_builtin(stream, dim, bi, x2, bidx, nb, t1, gfull, n2);
+  }
+  const Mesh& m = *mesh;
+  RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
+             {E, nullptr, nullptr}};
+  has_F = false;
+  if (f_cb) {
+    const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
+    std::vector<double> vals((size_t)nc * nq * dim), tr(vals.size());
+    f_cb(f_ctx, dim, nc * nq, h_xq.data(), t1, vals.data());
+    for (int64_t i = 0; i < nc * nq; ++i)
+      for (int c = 0; c < dim; ++c) tr[(size_t)c * nc * nq + i] = vals[i * dim + c];
+    HIP_OK(hipMemcpyAsync(fq, tr.data(), sizeof(double) * tr.size(), hipMemcpyHostToDevice,
+                          stream));
+    asm_forcing(dim, stream, a22, bi, fq, nc, t1, F, n2);
+    HIP_OK(hipStreamSynchronize(stream));
+    has_F = true;
+  } else if (builtin_has_force(bi.kind)) {
+    asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
+    has_F = true;
+  }
+  timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
+    asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+  });
+  rhs_momentum(stream, dim, mixed, n2, sp22, col22, E, U, sp21, col21, Gc, P,
+               has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask, gfull, bU);
+  copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
+  HIP_OK(hipEventRecord(ev[1], stream));
+}
+
+// r = -(rho/dt) sum_c D_c U*_c projected to zero sum; dP = 0.
+void Run::pressure_rhs() {
+  rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
+               scnt, scal + 0);
+  HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
+}
+
+// dP shifted to zero integral mean.
+void Run::pressure_end() {
+  sub_weighted_mean(stream, n1, w, dP, spart, scal + 1);
+  HIP_OK(hipEventRecord(ev[3], stream));
+}
+
+// b_c = M U*_c - (dt/rho) G_c dP with Dirichlet data; U^{n+1} starts at U*.
+void Run::correction_rhs() {
+  rhs_correction(stream, dim, mixed, n2, sp22, col22, M, Ustar, sp21, col21, Gc, dP,
+                 prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
+  HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
+                        stream));
+}
+
+// P^{n+1} = P^n + dP, U^{n+1} (enqueued).
+void Run::correction_commit() {
+  axpy_inplace(stream, n1, 1.0, dP, P);
+  HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipEventRecord(ev[4], stream));
+}
+
+// Waits for the step to finish, then t^{n+1} and the phase timings.
+void Run::finish_step(ipcs_step_stats* st) {
+  HIP_OK(hipEventSynchronize(ev[4]));
+  timer.drain();
+  t = t1;
+  if (st) {
+    st->t = t;
+    HIP_OK(hipEventElapsedTime(&st->ms_asm, ev[0], ev[1]));
+    HIP_OK(hipEventElapsedTime(&st->ms_mom, ev[1], ev[2]));
+    HIP_OK(hipEventElapsedTime(&st->ms_p, ev[2], ev[3]));
+    HIP_OK(hipEventElapsedTime(&st->ms_corr, ev[3], ev[4]));
+  }
+}
+
 int Run::phase(int which, ipcs_step_stats* st) {
   if (which != phase_next)
     fail(IPCS_E_STATE, "IPCS phases must run in order; expected phase " +
@@ -562,51 +649,13 @@ int Run::phase(int which, ipcs_step_stats* st) {
   std::vector<KState> hs;
   int rc = IPCS_OK;
   switch (which) {
-    case IPCS_PHASE_ASM: {
-      if (A_dirty) reform_A();
-      t1 = t + prm.dt;
-      HIP_OK(hipEventRecord(ev[0], stream));
-      if (g_cb) {
-        std::vector<double> vals((size_t)nb * dim);
-        g_cb(g_ctx, dim, nb, h_xb.data(), t1, vals.data());
-        HIP_OK(hipMemcpyAsync(gb, vals.data(), sizeof(double) * vals.size(),
-                              hipMemcpyHostToDevice, stream));
-        dirichlet_scatter(stream, dim, gb, bidx, nb, gfull, n2);
-        HIP_OK(hipStreamSynchronize(stream));
-      } else if (bi.kind) {
-        dirichlet_builtin(stream, dim, bi, x2, bidx, nb, t1, gfull, n2);
-      }
-      const Mesh& m = *mesh;
-      RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-                 {E, nullptr, nullptr}};
-      has_F = false;
-      if (f_cb) {
-        const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
-        std::vector<double> vals((size_t)nc * nq * dim), tr(vals.size());
-        f_cb(f_ctx, dim, nc * nq, h_xq.data(), t1, vals.data());
-        for (int64_t i = 0; i < nc * nq; ++i)
-          for (int c = 0; c < dim; ++c) tr[(size_t)c * nc * nq + i] = vals[i * dim + c];
-        HIP_OK(hipMemcpyAsync(fq, tr.data(), sizeof(double) * tr.size(), hipMemcpyHostToDevice,
-                              stream));
-        asm_forcing(dim, stream, a22, bi, fq, nc, t1, F, n2);
-        HIP_OK(hipStreamSynchronize(stream));
-        has_F = true;
-      } else if (builtin_has_force(bi.kind)) {
-        asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
-        has_F = true;
-      }
-      timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
-        asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
-      });
-      rhs_momentum(stream, dim, mixed, n2, sp22, col22, E, U, sp21, col21, Gc, P, has_F ? F : nullptr,
-                   lift_ptr, lift_col, liftA, bmask, gfull, bU);
-      copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
-      HIP_OK(hipEventRecord(ev[1], stream));
+    case IPCS_PHASE_ASM:
+      asm_phase();
       phase_next = IPCS_PHASE_MOMENTUM;
       return IPCS_OK;
-    }
-    case IPCS_PHASE_MOMENTUM: {
-      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned, timer);
+    case IPCS_PHASE_MOMENTUM:
+      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned,
+                        timer);
       fill_stats_solve(hs, dim, 1, st);
       HIP_OK(hipEventRecord(ev[2], stream));
       if (rc != IPCS_OK) {
@@ -616,49 +665,30 @@ int Run::phase(int which, ipcs_step_stats* st) {
       }
       phase_next = IPCS_PHASE_PRESSURE;
       return IPCS_OK;
-    }
-    case IPCS_PHASE_PRESSURE: {
-      rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
-                   scnt, scal + 0);
-      HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
+    case IPCS_PHASE_PRESSURE:
+      pressure_rhs();
       rc = pressure_solve(hs, st);
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 2;
         phase_next = IPCS_PHASE_ASM;
         return rc;
       }
-      sub_weighted_mean(stream, n1, w, dP, spart, scal + 1);
-      HIP_OK(hipEventRecord(ev[3], stream));
+      pressure_end();
       phase_next = IPCS_PHASE_CORRECTION;
       return IPCS_OK;
-    }
-    case IPCS_PHASE_CORRECTION: {
-      rhs_correction(stream, dim, mixed, n2, sp22, col22, M, Ustar, sp21, col21, Gc, dP,
-                     prm.dt / prm.rho, lift_ptr, lift_col, liftM, bmask, gfull, bU);
-      HIP_OK(hipMemcpyAsync(Unew, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
-                            stream));
-      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
+    case IPCS_PHASE_CORRECTION:
+      correction_rhs();
+      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned,
+                        timer);
       fill_stats_solve(hs, dim, 3, st);
       phase_next = IPCS_PHASE_ASM;
       if (rc != IPCS_OK) {
         if (st) st->failed_solve = 3;
         return rc;
       }
-      axpy_inplace(stream, n1, 1.0, dP, P);
-      HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
-      HIP_OK(hipEventRecord(ev[4], stream));
-      HIP_OK(hipEventSynchronize(ev[4]));
-      timer.drain();
-      t = t1;
-      if (st) {
-        st->t = t;
-        HIP_OK(hipEventElapsedTime(&st->ms_asm, ev[0], ev[1]));
-        HIP_OK(hipEventElapsedTime(&st->ms_mom, ev[1], ev[2]));
-        HIP_OK(hipEventElapsedTime(&st->ms_p, ev[2], ev[3]));
-        HIP_OK(hipEventElapsedTime(&st->ms_corr, ev[3], ev[4]));
-      }
+      correction_commit();
+      finish_step(st);
       return IPCS_OK;
-    }
   }
   fail(IPCS_E_INVALID, "unknown phase " + std::to_string(which));
 }

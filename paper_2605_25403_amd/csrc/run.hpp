@@ -79,6 +79,7 @@ enum class KMethod { PCG, BICG };
 // failed system.
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
                  std::vector<KState>& h_states, KState* pinned, KTimer& T);
+int status_to_code(int kstatus);
 
 // Rows per thread of matrix kernels for a group of n rows, and the block
 // counts of matrix / vector kernels (each at most KNB_MAX).
@@ -173,12 +174,21 @@ struct Run {
   void set_builtin(int kind, const double* prm, int nprm);
   void set_state(const double* u, const double* p, double t);
   int phase(int which, ipcs_step_stats* st);
+  void asm_phase();
+  void pressure_rhs();
+  void pressure_end();
+  void correction_rhs();
+  void correction_commit();
+  void finish_step(ipcs_step_stats* st);
   int step(ipcs_step_stats* st);
   double profile_kernel(int kernel, int nlaunch);
   // host-side CSR values (FP64) of a device SELL matrix of value size vbytes
   void export_values(int pattern, const void* dev, int vbytes, double* out);
   int pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st);
 };
+
+// One step of every run with shared Krylov launches on stream s (serving form).
+int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats);
 
 void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_step_stats* st);
 

@@ -262,6 +262,19 @@ def ipcs_advance(r, nsteps, with_stats=True):
     return [s.as_dict() for s in st][:nsteps] if st is not None else None
 
 
+def ipcs_batch_step(runs, stream):
+    """One step of every run handle in runs, with shared launches on stream
+    (an int HIP stream handle). Returns (rc, per-run stats dicts); a failed
+    solve of some run is reported in rc and its stats, not raised."""
+    n = len(runs)
+    arr = (_P * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in runs])
+    st = (ipcs_step_stats * n)()
+    rc = lib.ipcs_batch_step(arr, n, C.c_void_p(stream), C.cast(st, C.c_void_p))
+    if rc in (IPCS_E_INVALID, IPCS_E_STATE, IPCS_E_DEVICE, IPCS_E_NOMEM):
+        raise IpcsError(rc, lib.ipcs_last_error().decode())
+    return rc, [s.as_dict() for s in st]
+
+
 def ipcs_step_phase(r, phase):
     st = ipcs_step_stats()
     _check(lib.ipcs_step_phase(r, phase, C.byref(st)))

@@ -1,0 +1,166 @@
+"""Serving form: a request loop with continuous batching of IPCS runs.
+
+Requests (mesh size, viscosity, wave number, number of steps) arrive over
+time. The loop keeps the runs it has admitted resident on the GPU (mesh, CSR
+patterns, matrices and fields in the run's workspace) and advances all of them
+together, one IPCS step per round, with `ipcs_batch_step`: the Krylov
+iterations of all runs share kernel launches. Before each round it admits the
+requests that have arrived, in arrival order, while the number of runs stays
+within `max_slots` and their summed HBM footprint (each run's workspace, from
+`ipcs_run_workspace_bytes`) within `hbm_budget`. A run leaves as soon as its
+steps are done and its workspace is released, so that waiting requests take
+its place in the next round.
+
+Per-step latency of a request is the time between two consecutive completions
+of its steps (the first is counted from its admission); the report gives
+their p50 and p99 beside the aggregate DOF-steps/s and the queueing delays.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    id: int
+    t_arrive: float          # seconds after the start of the stream
+    n: int                   # unit square with n x n squares
+    k: float                 # Taylor-Green wave number
+    nu: float
+    steps: int
+    dt: float
+
+
+@dataclass
+class Active:
+    req: Request
+    run: object
+    footprint: int
+    t_admit: float
+    done: int = 0
+    t_last: float = 0.0
+    lat: list = field(default_factory=list)
+
+
+def admit(queue, now, active_count, active_bytes, footprint_of, max_slots, hbm_budget):
+    """Admission policy: the longest prefix of the arrival-ordered queue that
+    has arrived by `now` and fits both limits (head-of-line order: a request
+    that does not fit blocks the ones behind it, so none is starved). Returns
+    the number of requests to admit."""
+    k = 0
+    slots, used = active_count, active_bytes
+    for req in queue:
+        if req.t_arrive > now or slots >= max_slots:
+            break
+        f = footprint_of(req)
+        if used + f > hbm_budget and slots > 0:
+            break
+        if f > hbm_budget:
+            raise ValueError(f"request {req.id} needs {f} bytes, more than the HBM budget")
+        slots += 1
+        used += f
+        k += 1
+    return k
+
+
+class Server:
+    def __init__(self, dim=2, precision=None, max_slots=64, hbm_budget=200 << 30, tol=1e-12,
+                 tol_ir=1e-10, stream=None):
+        import torch
+        from paper_2605_25403_amd import ipcs as I
+        if dim != 2:
+            raise ValueError("the request stream uses the 2D Taylor-Green problem")
+        self.I, self.torch = I, torch
+        self.precision = I.IPCS_MIXED if precision is None else precision
+        self.max_slots, self.hbm_budget = max_slots, hbm_budget
+        self.tol, self.tol_ir = tol, tol_ir
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self._meshes = {}
+
+    def mesh(self, n):
+        if n not in self._meshes:
+            self._meshes[n] = self.I.Mesh.unit_square(n)
+        return self._meshes[n]
+
+    def params(self, req):
+        return self.I.ipcs_params_default(nu=req.nu, dt=req.dt, precision=self.precision,
+                                          tol_mom=self.tol, tol_p=self.tol, tol_corr=self.tol,
+                                          tol_ir=self.tol_ir)
+
+    def footprint(self, req):
+        return self.I.ipcs_run_workspace_bytes(self.mesh(req.n).h, self.params(req))
+
+    def start_run(self, req):
+        r = self.I.Run(self.mesh(req.n), self.params(req), stream=self.stream)
+        r.set_builtin(self.I.IPCS_SOL_TAYLOR_GREEN_2D, (req.k,))
+        return r
+
+    def serve(self, requests, keep_fields=False, clock=time.perf_counter):
+        """Runs the whole stream; returns a report dict (and the final fields
+        per request id when keep_fields)."""
+        I = self.I
+        queue = sorted(requests, key=lambda q: (q.t_arrive, q.id))
+        active, results = [], {}
+        dof_steps, rounds, max_active, fails = 0, 0, 0, 0
+        t0 = clock()
+        while queue or active:
+            now = clock() - t0
+            k = admit(queue, now, len(active), sum(a.footprint for a in active),
+                      self.footprint, self.max_slots, self.hbm_budget)
+            for req in queue[:k]:
+                run = self.start_run(req)
+                ta = clock() - t0
+                active.append(Active(req, run, self.footprint(req), ta, t_last=ta))
+            del queue[:k]
+            if not active:
+                # nothing to do until the next arrival
+                time.sleep(max(0.0, queue[0].t_arrive - (clock() - t0)))
+                continue
+            max_active = max(max_active, len(active))
+            rc, stats = I.ipcs_batch_step([a.run.h for a in active], self.stream.cuda_stream)
+            tdone = clock() - t0
+            rounds += 1
+            keep = []
+            for a, st in zip(active, stats):
+                if st["status"] != I.IPCS_OK:
+                    fails += 1
+                    results[a.req.id] = dict(status=st["status"], t_admit=a.t_admit,
+                                             t_arrive=a.req.t_arrive, lat=a.lat)
+                    continue
+                a.lat.append(tdone - a.t_last)
+                a.t_last = tdone
+                a.done += 1
+                dof_steps += 2 * (2 * a.req.n + 1) ** 2 + (a.req.n + 1) ** 2
+                if a.done == a.req.steps:
+                    res = dict(status=0, t_arrive=a.req.t_arrive, t_admit=a.t_admit,
+                               t_done=tdone, lat=a.lat, n=a.req.n)
+                    if keep_fields:
+                        res["U"], res["P"] = a.run.velocity(), a.run.pressure()
+                    results[a.req.id] = res
+                    del a.run   # releases the workspace
+                else:
+                    keep.append(a)
+            active = keep
+        wall = clock() - t0
+        lat = np.concatenate([np.asarray(r["lat"]) for r in results.values() if r["lat"]])
+        qd = np.array([r["t_admit"] - r["t_arrive"] for r in results.values()])
+        first = min(q.t_arrive for q in requests)
+        report = {
+            "requests": len(requests), "failed": fails, "rounds": rounds,
+            "max_active": max_active, "max_slots": self.max_slots,
+            "hbm_budget_bytes": self.hbm_budget,
+            "dof_steps": dof_steps, "wall_s": wall,
+            "dof_steps_per_s": dof_steps / max(wall - first, 1e-9),
+            "p50_step_ms": 1000 * float(np.percentile(lat, 50)),
+            "p99_step_ms": 1000 * float(np.percentile(lat, 99)),
+            "queue_delay_p50_ms": 1000 * float(np.percentile(qd, 50)),
+            "queue_delay_p99_ms": 1000 * float(np.percentile(qd, 99)),
+        }
+        return report, results
+
+
+def requests_from(stream_spec):
+    """Request objects from workloads.serving_requests dicts."""
+    return [Request(id=d["id"], t_arrive=d["t_arrive"], n=d["n"], k=d["k"], nu=d["nu"],
+                    steps=d["steps"], dt=d["dt"]) for d in stream_spec]
