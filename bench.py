@@ -193,6 +193,75 @@ def trace_summary(trace_dir, workload, command):
     print(open(out).read())
 
 
+def mixed_form(w, steps, torch, I):
+    """The mixed-precision form against the FP64 form on the same problem and
+    start: per-step relative L2 (nodal) difference of u and p, and throughput."""
+    from paper_2605_25403_amd.workloads import dofs
+    m = I.Mesh.unit_square(w["n"]) if w["dim"] == 2 else I.Mesh.unit_cube(w["n"])
+    runs = {}
+    for name, prec in (("fp64", I.IPCS_FP64), ("mixed", I.IPCS_MIXED)):
+        p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
+                                  tol_corr=w["tol"], tol_ir=1e-10, precision=prec)
+        r = I.Run(m, p, stream=torch.cuda.Stream())
+        if w["dim"] == 2:
+            r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        else:
+            r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+        runs[name] = r
+    err_u, err_p, lat = [], [], {"fp64": [], "mixed": []}
+    it = {"fp64": [], "mixed": []}
+    for _ in range(steps):
+        for name, r in runs.items():
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat[name].append(time.perf_counter() - t0)
+            it[name].append(st["it_p"])
+        U64, U32 = runs["fp64"].velocity(), runs["mixed"].velocity()
+        P64, P32 = runs["fp64"].pressure(), runs["mixed"].pressure()
+        err_u.append(float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)))
+        err_p.append(float(np.linalg.norm(P32 - P64) / np.linalg.norm(P64)))
+    nd = dofs(w["dim"], w["n"])
+    out = {}
+    for name in ("fp64", "mixed"):
+        ms = 1000.0 * float(np.median(lat[name]))
+        out[name] = {"value": nd / (ms / 1000.0), "p50_step_ms": ms,
+                     "p99_step_ms": 1000.0 * float(np.percentile(lat[name], 99)),
+                     "pressure_iterations_median": float(np.median(it[name]))}
+    out["steps"] = steps
+    out["rel_l2_diff_vs_fp64_u"] = err_u
+    out["rel_l2_diff_vs_fp64_p"] = err_p
+    out["speedup_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16):
+    """C5: Poisson-arrival stream of 2D TG requests (n in {32,64,128,256},
+    seed-drawn k and nu, 50 steps at dt = 1e-3), mixed form, continuous
+    batching; beside it the same accuracy target run one request after the
+    other (sequential, each alone) on the first seq_sample requests."""
+    from paper_2605_25403_amd.serve import Server, requests_from
+    from paper_2605_25403_amd.workloads import serving_requests
+    reqs = requests_from(serving_requests(seed=0, count=count, rate=rate))
+    srv = Server(max_slots=max_slots)
+    report, _ = srv.serve(reqs)
+    # sequential baseline: same requests, no arrivals gaps, one run at a time
+    sample = reqs[:seq_sample]
+    t0 = time.perf_counter()
+    dsteps = 0
+    for q in sample:
+        r = srv.start_run(q)
+        r.advance(q.steps)
+        torch.cuda.synchronize()
+        dsteps += (2 * (2 * q.n + 1) ** 2 + (q.n + 1) ** 2) * q.steps
+        del r
+    seq = dsteps / (time.perf_counter() - t0)
+    report["sequential_sample"] = {"requests": seq_sample, "dof_steps_per_s": seq}
+    report["workload"] = (f"c5: {count} requests, Poisson arrivals at {rate}/s, 2D TG, "
+                          "n in {32,64,128,256}, 50 steps at dt=1e-3, mixed form, "
+                          f"max_slots {max_slots}")
+    return report
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +276,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarize two rocprofv3 --pmc runs and exit (no GPU use)")
     ap.add_argument("--pmc-kernel", default="pcg_update_p")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and serving form reports")
+    ap.add_argument("--form-steps", type=int, default=10)
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats -f csv run and exit")
     ap.add_argument("--pmc-command", default="")
@@ -317,6 +389,9 @@ def main():
                             "correction": float(np.median(ph[:, 3]))},
         "iterations_median": {"momentum": it_m, "pressure": it_p, "correction": it_c},
     }
+    if not args.no_forms and not mixed:
+        out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
+                        "serving": serving_form(torch, I)}
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
