@@ -188,7 +188,7 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
   struct IR {
     double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0, floor_in = 0.0;
     int outer = 0;
-    double host[2] = {0.0, 0.0};
+    double host[4] = {0.0, 0.0, 0.0, 0.0};
   };
   std::map<Run*, IR> ir;
   std::vector<Run*> active = runs;
@@ -196,7 +196,7 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
     for (Run* r : active) {
       residual_projected(s, r->n1, r->sp11, r->col11, r->Kp64, r->dP, r->rP, r->rIR, r->spart,
                          r->spart + 8192, r->scal + 3, r->scal + 5);
-      HIP_OK(hipMemcpyAsync(ir[r].host, r->scal + 3, 2 * sizeof(double), hipMemcpyDeviceToHost,
+      HIP_OK(hipMemcpyAsync(ir[r].host, r->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost,
                             s));
     }
     HIP_OK(hipStreamSynchronize(s));
@@ -210,7 +210,7 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
         rc[r] = IPCS_E_NONFINITE;
         continue;
       }
-      if (rr <= r->prm.tol_ir * r->prm.tol_ir * q.bb) continue;   // done
+      if (rr <= r->prm.tol_ir * r->prm.tol_ir * q.bb || rr <= q.host[3]) continue;   // done
       if (q.outer >= 30) {
         rc[r] = IPCS_E_NOT_CONVERGED;
         continue;

@@ -40,6 +40,7 @@ struct KState {
   double alpha[2];            // PCG alpha by parity; BiCGStab alpha in [0]
   double omega;               // BiCGStab
   double tol2;                // tol^2
+  double atol2;               // absolute floor on ||r||^2 (rounding level of b), 0 if none
   int32_t status, it, nchecks, pad;
 };
 
@@ -171,9 +172,13 @@ void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* 
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b);
 // r = scale * sum_c D_c Us_c, then r -= mean(r) (mean_out receives it)
+// r = scale * sum_c D_c Us_c projected to zero sum (mean_out receives the mean).
+// floor_out[0..1] (if not null) receive (64 eps)^2 * sum_k (scale sum_c |D_c||Us_c|)_k^2,
+// the squared rounding level of r: part needs 2 * 8192 doubles.
 void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* sp12,
                   const int32_t* col12, void* const* Dc, const double* Us, int64_t n2,
-                  double scale, double* r, double* part, uint32_t* cnt, double* mean_out);
+                  double scale, double* r, double* part, double* mean_out, double* floor_out0,
+                  double* floor_out1);
 // res = b - A x (FP64 A), then res -= mean(res); totals[0..1] = sum(res), sum(res^2)
 // before the projection; mean_out receives the mean
 void residual_projected(hipStream_t s, int64_t n, const int32_t* sp, const int32_t* col,

@@ -221,6 +221,8 @@ void rhs_correction(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t
 
 // r[k] = scale * sum_c sum_j D_c[kj] Us_c[j] (SELL-64, one thread per row) and
 // per-block partial sums of r; k_sub_mean finishes the mean and subtracts it.
+// Also the rounding level of each r_k: mag_k = |scale| sum |D_c[kj]| |Us_c[j]|,
+// with per-block partial sums of r (part) and of mag^2 (part + 8192).
 template <int D, class VT>
 __global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t* sp,
                                                       const int32_t* col, Ptrs3<VT> Dc,
@@ -228,21 +230,44 @@ __global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t*
                                                       double* r, double* part) {
   __shared__ double sh[16];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v = 0.0;
+  double v = 0.0, mag = 0.0;
   if (k < n1) {
     const int sl = (int)(k >> 6), b0 = sp[sl], w = (sp[sl + 1] - b0) >> 6;
     const int base = b0 + (int)(k & 63);
-    double s = 0.0;
+    double s = 0.0, a = 0.0;
     for (int e = 0; e < w; ++e) {
       const int j = col[base + 64 * e];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s += (double)Dc.p[c][base + 64 * e] * Us[c * n2 + j];
+      for (int c = 0; c < D; ++c) {
+        const double t = (double)Dc.p[c][base + 64 * e] * Us[c * n2 + j];
+        s += t;
+        a += fabs(t);
+      }
     }
     v = scale * s;
+    mag = fabs(scale) * a;
     r[k] = v;
   }
   const double t = block_sum(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  const double q = block_sum(mag * mag, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = t;
+    part[8192 + blockIdx.x] = q;
+  }
+}
+
+// floor = (64 eps)^2 * (sum of nb partials of mag^2), written to two places
+__global__ void __launch_bounds__(256) k_noise_floor(int nb, const double* part, double* out0,
+                                                     double* out1) {
+  __shared__ double sh[16];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) a += part[b];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) {
+    const double c = 64.0 * 2.220446049250313e-16;
+    if (out0) *out0 = c * c * a;
+    if (out1) *out1 = c * c * a;
+  }
 }
 
 // res = b - A x for an FP64 matrix A (SELL-64), with per-block partial sums of
@@ -302,8 +327,8 @@ __global__ void __launch_bounds__(256) k_sub_mean(int64_t n, int nb, const doubl
 
 void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* sp12,
                   const int32_t* col12, void* const* Dc, const double* Us, int64_t n2,
-                  double scale, double* r, double* part, uint32_t* cnt, double* mean_out) {
-  (void)cnt;
+                  double scale, double* r, double* part, double* mean_out, double* floor_out0,
+                  double* floor_out1) {
   const int nb = (int)div_up(n1, 256);
   if (nb > 8192) fail(IPCS_E_INVALID, "pressure space too large for the partial buffer");
   auto go = [&](auto vt) {
@@ -322,6 +347,11 @@ void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* 
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n1, 256)), dim3(256), 0, s, n1, nb, part, r,
                      mean_out);
   HIP_LAUNCH_OK();
+  if (floor_out0 || floor_out1) {
+    hipLaunchKernelGGL(k_noise_floor, dim3(1), dim3(256), 0, s, nb, part + 8192, floor_out0,
+                       floor_out1);
+    HIP_LAUNCH_OK();
+  }
 }
 
 void residual_projected(hipStream_t s, int64_t n, const int32_t* sp, const int32_t* col,

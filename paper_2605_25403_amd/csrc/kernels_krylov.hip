@@ -37,8 +37,11 @@
 //      r = s - omega t; rho' = rhat.r = rhat.s - omega rhat.t, beta =
 //      (rho' / rho)(alpha / omega); p = r + beta (p - omega v), phat = D^{-1} p;
 //      partial r.r
-// Stopping rule: ||r||_2 <= tol ||b||_2 on the recursive residual, then
-// confirmed with b - A x (restart from x if it fails), up to maxit iterations.
+// Stopping rule: ||r||_2 <= max(tol ||b||_2, atol) on the recursive residual,
+// then confirmed with b - A x (restart from x if it fails), up to maxit
+// iterations. atol is 0 except for the pressure Poisson system, whose
+// right-hand side is a difference of terms: there it is the rounding level of
+// b, below which the residual carries no information.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -177,7 +180,7 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
       int nst = KS_RUN;
       if (bb == 0.0) nst = KS_ZERO;
       else if (!finite(rr)) nst = KS_NONFINITE;
-      else if (rr <= st->tol2 * bb) nst = KS_DONE;
+      else if (rr <= st->tol2 * bb || rr <= st->atol2) nst = KS_DONE;
       else if (exhausted) nst = KS_MAXIT;
       st->status = nst;
       if (nst != KS_RUN) continue;
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
     status[j] = st->status;
     g_old[j] = st->sc[par ^ 1];
     a_old[j] = st->alpha[par ^ 1];
-    lim[j] = st->tol2 * st->bb;
+    lim[j] = fmax(st->tol2 * st->bb, st->atol2);
   }
   double t[NS * 3];
   {
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
     const KState* st = g.v[j].st;
     status[j] = st->status;
     rho[j] = st->sc[par];
-    lim[j] = st->tol2 * st->bb;
+    lim[j] = fmax(st->tol2 * st->bb, st->atol2);
   }
   double t[NS * 2];
   {

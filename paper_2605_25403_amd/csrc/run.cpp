@@ -602,8 +602,11 @@ void Run::asm_phase() {
 
 // r = -(rho/dt) sum_c D_c U*_c projected to zero sum; dP = 0.
 void Run::pressure_rhs() {
+  // the Poisson stopping test gets an absolute floor at the rounding level of
+  // r (a difference of terms that cancel): in the FP64 form on the solve's
+  // own state, in the mixed form for the refinement test (scal[6])
   rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
-               scnt, scal + 0);
+               scal + 0, mixed ? nullptr : &(kst + dim)->atol2, scal + 6);
   HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
 }
 
@@ -826,8 +829,8 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     fill_stats_solve(hs, 1, 2, st);
     return rc;
   }
-  double* tot = scal + 3;   // [3] sum(res), [4] sum(res^2); [5] mean
-  double host[2];
+  double* tot = scal + 3;   // [3] sum(res), [4] sum(res^2); [5] mean; [6] noise floor
+  double host[4];
   double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0;
   double floor_in = 0.0;   // raised after an inner breakdown
   int inner_total = 0, outer = 0, rc = IPCS_OK;
@@ -837,13 +840,14 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     HIP_OK(hipMemcpyAsync(host, tot, sizeof(host), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     const double rr = std::max(0.0, host[1] - host[0] * host[0] / (double)n1);
+    const double floor2 = host[3];
     if (bb < 0.0) bb = rr;   // dP = 0 on the first pass: res = r
     rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
     if (!std::isfinite(rr)) {
       rc = IPCS_E_NONFINITE;
       break;
     }
-    if (rr <= prm.tol_ir * prm.tol_ir * bb) break;
+    if (rr <= prm.tol_ir * prm.tol_ir * bb || rr <= floor2) break;
     if (outer >= kMaxRefine) {
       rc = IPCS_E_NOT_CONVERGED;
       break;

@@ -1,0 +1,126 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (2D 512 x 512 squares; 3D 64^3 cubes). The oracle cannot afford every
+output at these sizes, so the checks are:
+* sampled matrix rows, which the oracle computes cell by cell from its own
+  local element matrices (bar 1e-12 relative to the largest entry);
+* properties that hold at any size: total mass, zero row sums, the discrete
+  divergence of a divergence-free quadratic, G = -D^T on interior rows;
+* the exact polynomial fixed point of one full IPCS step;
+* one full FP64 step of the 2D workload against the oracle from the same
+  state, both sides at Krylov tolerance 1e-13 (distance to the exact discrete
+  solution at most kappa * tol: kappa(Kp) ~ 1e5 at n = 512, so the pressure
+  bar is 2e-8, the velocity bar 1e-9).
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, mesh
+from tests.gpu_common import make_pair, rel, require_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+ROW_TOL = 1e-12
+
+
+def sampled_rows(S, rows, local_fn, row_map, col_map):
+    """Rows of the assembled matrix, computed from the local matrices of the
+    cells that contain each row's DOF (the oracle's own routines on a Space
+    made of just those cells). Returns {row: {col: value}}."""
+    out = {}
+    for i in rows:
+        cells = np.nonzero((row_map == i).any(axis=1))[0]
+        sub = fem.Space(S.X, S.cells[cells])
+        loc = local_fn(sub)                              # (nsub, nr, nc)
+        acc = {}
+        for a, c in enumerate(cells):
+            li = int(np.nonzero(row_map[c] == i)[0][0])
+            for lj, j in enumerate(col_map[c]):
+                acc[int(j)] = acc.get(int(j), 0.0) + loc[a, li, lj]
+        out[int(i)] = acc
+    return out
+
+
+def check_rows(A, ref):
+    scale = np.abs(A.data).max()
+    for i, row in ref.items():
+        got = {int(j): v for j, v in zip(A.indices[A.indptr[i]:A.indptr[i + 1]],
+                                         A.data[A.indptr[i]:A.indptr[i + 1]])}
+        assert set(got) == set(row), i
+        err = max(abs(got[j] - row[j]) for j in row)
+        assert err <= ROW_TOL * scale, (i, err / scale)
+
+
+def library_run(I, dim, n, kind, nu=0.01, dt=1e-3, k=np.pi, tol=1e-12):
+    m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
+    p = I.ipcs_params_default(nu=nu, dt=dt, tol_mom=tol, tol_p=tol, tol_corr=tol)
+    r = I.Run(m, p)
+    kinds = {"tg": I.IPCS_SOL_TAYLOR_GREEN_2D, "beltrami": I.IPCS_SOL_BELTRAMI_3D,
+             "poly": I.IPCS_SOL_POLY_STEADY_2D if dim == 2 else I.IPCS_SOL_POLY_STEADY_3D}
+    r.set_builtin(kinds[kind], (k,) if kind == "tg" else ())
+    return m, r
+
+
+@pytest.mark.parametrize("dim,n", [(2, 512), (3, 64)])
+def test_full_size_matrices_sampled_rows_and_invariants(dim, n):
+    torch, I = require_gpu()
+    print(f"full-size matrices dim={dim} n={n}", flush=True)
+    S = fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)))
+    m, r = library_run(I, dim, n, "tg" if dim == 2 else "beltrami")
+    rng = np.random.default_rng(1)
+    rows2 = np.concatenate([rng.choice(S.N2, 12, replace=False), [0, S.Nv, S.N2 - 1]])
+    rows1 = np.concatenate([rng.choice(S.N1, 8, replace=False), [0, S.N1 - 1]])
+    M = r.matrix(I.IPCS_MAT_M)
+    check_rows(M, sampled_rows(S, rows2, fem.local_mass_p2, S.c2d2, S.c2d2))
+    K = r.matrix(I.IPCS_MAT_K)
+    check_rows(K, sampled_rows(S, rows2, fem.local_stiff_p2, S.c2d2, S.c2d2))
+    Kp = r.matrix(I.IPCS_MAT_KP)
+    check_rows(Kp, sampled_rows(S, rows1, fem.local_stiff_p1, S.c2d1, S.c2d1))
+    D0 = r.matrix(I.IPCS_MAT_D0)
+    check_rows(D0, sampled_rows(S, rows1, lambda s: fem.local_div(s, 0), S.c2d1, S.c2d2))
+    G1 = r.matrix(I.IPCS_MAT_G0 + 1)
+    check_rows(G1, sampled_rows(S, rows2, lambda s: fem.local_grad(s, 1), S.c2d2, S.c2d1))
+    # invariants at any size
+    assert abs(M.sum() - 1.0) <= 1e-12
+    for A in (K, Kp):
+        assert np.abs(np.asarray(A.sum(axis=1))).max() <= 1e-11 * np.abs(A.data).max()
+    x2 = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2)
+    if dim == 2:   # u = (y^2, x^2) is divergence-free
+        u = [x2[:, 1] ** 2, x2[:, 0] ** 2]
+    else:          # u = (y^2 + z^2, z^2 + x^2, x^2 + y^2)
+        u = [x2[:, 1] ** 2 + x2[:, 2] ** 2, x2[:, 2] ** 2 + x2[:, 0] ** 2,
+             x2[:, 0] ** 2 + x2[:, 1] ** 2]
+    Ds = [r.matrix(I.IPCS_MAT_D0 + c) for c in range(dim)]
+    div = sum(Ds[c] @ u[c] for c in range(dim))
+    assert np.abs(div).max() <= 1e-12 * max(np.abs(D.data).max() for D in Ds)
+    interior = I.ipcs_mesh_boundary(m.h) == 0
+    G = r.matrix(I.IPCS_MAT_G0)
+    diff = (G + Ds[0].T.tocsr())[interior]
+    assert np.abs(diff.data).max(initial=0.0) <= 1e-12 * np.abs(G.data).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 512), (3, 64)])
+def test_full_size_polynomial_fixed_point(dim, n):
+    torch, I = require_gpu()
+    print(f"full-size fixed point dim={dim} n={n}", flush=True)
+    m, r = library_run(I, dim, n, "poly", nu=0.07, dt=0.05, tol=1e-13)
+    U0, P0 = r.velocity().copy(), r.pressure().copy()
+    st = r.advance(1)[0]
+    dU = np.abs(r.velocity() - U0).max() / np.abs(U0).max()
+    dP = np.abs(r.pressure() - P0).max() / np.abs(P0).max()
+    print(dU, dP, st["it_mom"], st["it_p"], flush=True)
+    assert dU <= 1e-11 and dP <= 1e-10, (dU, dP)
+
+
+def test_full_size_2d_step_against_oracle():
+    torch, I = require_gpu()
+    print("full-size 2D step vs oracle", flush=True)
+    from paper_2605_25403_amd.workloads import resolve
+    w = resolve("c2")
+    S, o, r = make_pair(I, 2, 512, "tg", w["nu"], w["dt"], tol=1e-13, k=w["k"])
+    r.advance(1)
+    o.step()
+    U, P = r.velocity(), r.pressure()
+    eu = max(rel(U[c], o.U[c]) for c in range(2))
+    ep = rel(P, o.P)
+    print(eu, ep, flush=True)
+    assert eu <= 1e-9 and ep <= 2e-8, (eu, ep)
