@@ -187,6 +187,7 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
                           std::map<Run*, ipcs_step_stats*>& st) {
   struct IR {
     double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0, floor_in = 0.0;
+    double last_tol = 1.0, op_limit = 0.0;
     int outer = 0;
     double host[4] = {0.0, 0.0, 0.0, 0.0};
   };
@@ -210,16 +211,24 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
         rc[r] = IPCS_E_NONFINITE;
         continue;
       }
-      if (rr <= r->prm.tol_ir * r->prm.tol_ir * q.bb || rr <= q.host[3]) continue;   // done
+      // done; an r at its own rounding level on the first pass is zero
+      if (rr <= r->prm.tol_ir * r->prm.tol_ir * q.bb || (q.outer == 0 && rr <= q.host[3]))
+        continue;
       if (q.outer >= 30) {
         rc[r] = IPCS_E_NOT_CONVERGED;
         continue;
       }
-      if (q.outer > 0) q.contraction = q.rel / q.prev;
+      if (q.outer > 0) {   // as in Run::pressure_solve
+        q.contraction = q.rel / q.prev;
+        if (q.contraction > 2.0 * q.last_tol) q.op_limit = std::max(q.op_limit, q.contraction);
+      } else {
+        q.contraction = r->ir_c;
+      }
       q.prev = q.rel;
       const double need = r->prm.tol_ir / q.rel;
       const double tol_in =
           std::min(0.5, std::max({need, 0.5 * q.contraction, q.floor_in, r->prm.tol_p}));
+      q.last_tol = tol_in;
       set_tolerance(s, r->set_p.L, tol_in * tol_in);
       HIP_OK(hipMemsetAsync(r->dIR, 0, sizeof(double) * r->n1, s));
       q.outer += 1;
@@ -243,11 +252,14 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
       active.push_back(r);
     }
   }
-  for (Run* r : runs)
+  for (Run* r : runs) {
+    const IR& q = ir[r];
+    if (q.op_limit > 0.0) r->ir_c = q.op_limit;   // as in Run::pressure_solve
     if (st[r]) {
-      st[r]->res_p = ir[r].rel;
-      st[r]->ir_outer = ir[r].outer;
+      st[r]->res_p = q.rel;
+      st[r]->ir_outer = q.outer;
     }
+  }
 }
 
 int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats) {

@@ -9,8 +9,10 @@ namespace ipcs {
 
 constexpr int BLOCK = 256;        // threads per block of small utility kernels
 constexpr int KBS = 256;          // threads per block of every Krylov kernel
-constexpr int KEPT_V = 4;         // vector entries per thread of Krylov vector kernels
-constexpr int KPART_Q = 16;       // partial records per thread a consumer block loads
+// vector entries per thread of Krylov vector kernels, by systems per group
+// (more systems hold more vectors in registers per entry)
+constexpr int kept_v(int ns) { return ns == 3 ? 2 : 4; }
+constexpr int KPART_Q = 32;       // partial records per thread a consumer block loads
 constexpr int KNB_MAX = KBS * KPART_Q;   // most producer blocks per group and kernel
 constexpr int KP = 8;             // partial sums per system per block
 constexpr int GMAX = 3;           // systems per group (velocity components)
@@ -40,7 +42,7 @@ struct KState {
   double alpha[2];            // PCG alpha by parity; BiCGStab alpha in [0]
   double omega;               // BiCGStab
   double tol2;                // tol^2
-  double atol2;               // absolute floor on ||r||^2 (rounding level of b), 0 if none
+  double zero2;               // ||b||^2 at or below this is treated as b = 0 (0: none)
   int32_t status, it, nchecks, pad;
 };
 
@@ -64,7 +66,7 @@ struct KVecs {
 // Up to GMAX systems that share one matrix (SELL-64 layout, FP64 values), so
 // the matrix is read once per row for all of them. Matrix kernels run
 // nblk_m = ceil(n / (KBS * ept_m)) blocks, vector kernels
-// nblk_v = ceil(n / (KBS * KEPT_V)); both are at most KNB_MAX. Partial sums:
+// nblk_v = ceil(n / (KBS * kept_v(nsys))); both are at most KNB_MAX. Partial sums:
 // part_m is written by matrix kernels, part_v[q] by vector kernels of launch
 // parity q^1; records are [block][GMAX][KP].
 struct KGroup {
@@ -173,8 +175,8 @@ void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* 
                   const uint8_t* bmask, const double* gfull, double* b);
 // r = scale * sum_c D_c Us_c, then r -= mean(r) (mean_out receives it)
 // r = scale * sum_c D_c Us_c projected to zero sum (mean_out receives the mean).
-// floor_out[0..1] (if not null) receive (64 eps)^2 * sum_k (scale sum_c |D_c||Us_c|)_k^2,
-// the squared rounding level of r: part needs 2 * 8192 doubles.
+// floor_out0/1 (if not null) receive (64 eps)^2 * sum_k (scale sum_c |D_c||Us_c|)_k^2,
+// a generous bound on ||rounding error of r||^2: part needs 2 * 8192 doubles.
 void rhs_pressure(hipStream_t s, int dim, bool fp32, int64_t n1, const int32_t* sp12,
                   const int32_t* col12, void* const* Dc, const double* Us, int64_t n2,
                   double scale, double* r, double* part, double* mean_out, double* floor_out0,

@@ -6,7 +6,7 @@
 // 64-wide load of values and of column indices. The loads of a row are batched
 // eight columns at a time: eight (column, value) loads, then the eight gathers
 // of every system, then the FMAs, so that eight gathers per system are in flight
-// per lane. Vector kernels give each thread KEPT_V entries. The systems of a
+// per lane. Vector kernels give each thread kept_v(NS) entries. The systems of a
 // group share the matrix (the velocity components of a run): each matrix entry
 // is loaded once and applied to every system's vector. A launch serves many
 // groups through a (group, block) map, e.g. all runs of a serving batch.
@@ -37,11 +37,11 @@
 //      r = s - omega t; rho' = rhat.r = rhat.s - omega rhat.t, beta =
 //      (rho' / rho)(alpha / omega); p = r + beta (p - omega v), phat = D^{-1} p;
 //      partial r.r
-// Stopping rule: ||r||_2 <= max(tol ||b||_2, atol) on the recursive residual,
-// then confirmed with b - A x (restart from x if it fails), up to maxit
-// iterations. atol is 0 except for the pressure Poisson system, whose
-// right-hand side is a difference of terms: there it is the rounding level of
-// b, below which the residual carries no information.
+// Stopping rule: ||r||_2 <= tol ||b||_2 on the recursive residual, then
+// confirmed with b - A x (restart from x if it fails), up to maxit iterations.
+// A right-hand side whose norm is at the rounding level of the terms it was
+// formed from (the pressure Poisson b is a difference of terms that cancel
+// exactly at a discrete steady state) is treated as zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -178,9 +178,11 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
       const double bb = st->bb, rr = tot[j * 3];
       st->rr = rr;
       int nst = KS_RUN;
-      if (bb == 0.0) nst = KS_ZERO;
+      // b at or below the rounding level of the terms it was formed from
+      // (zero2, set by the caller; 0 if none) carries no information: x = 0
+      if (bb == 0.0 || bb <= st->zero2) nst = KS_ZERO;
       else if (!finite(rr)) nst = KS_NONFINITE;
-      else if (rr <= st->tol2 * bb || rr <= st->atol2) nst = KS_DONE;
+      else if (rr <= st->tol2 * bb) nst = KS_DONE;
       else if (exhausted) nst = KS_MAXIT;
       st->status = nst;
       if (nst != KS_RUN) continue;
@@ -248,6 +250,7 @@ template <int NS>
 __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const int2* bmap,
                                                    int par) {
   GROUP_HEAD(bmap)
+  constexpr int EV = kept_v(NS);
   __shared__ double sh[(KBS / 64) * NS * 3];
   int status[NS];
   double g_old[NS], a_old[NS], lim[NS];
@@ -257,7 +260,7 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
     status[j] = st->status;
     g_old[j] = st->sc[par ^ 1];
     a_old[j] = st->alpha[par ^ 1];
-    lim[j] = fmax(st->tol2 * st->bb, st->atol2);
+    lim[j] = st->tol2 * st->bb;
   }
   double t[NS * 3];
   {
@@ -271,11 +274,11 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
       t[j * 3 + 2] = b[j];
     }
   }
-  double di[KEPT_V], xi[KEPT_V][NS], ri[KEPT_V][NS], pi[KEPT_V][NS], si[KEPT_V][NS],
-      wi[KEPT_V][NS];
+  double di[EV], xi[EV][NS], ri[EV][NS], pi[EV][NS], si[EV][NS],
+      wi[EV][NS];
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     const bool in = i < g.n;
     di[e] = in ? g.dinv[i] : 0.0;
 #pragma unroll
@@ -332,8 +335,8 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
   if (!any) return;   // uniform: every thread took the same decisions
   double acc[NS * 2] = {};
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     if (i >= g.n) continue;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -417,6 +420,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
 template <int NS>
 __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2* bmap, int par) {
   GROUP_HEAD(bmap)
+  constexpr int EV = kept_v(NS);
   __shared__ double sh[(KBS / 64) * NS * 2];
   int status[NS];
   double rho[NS], lim[NS];
@@ -425,7 +429,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
     const KState* st = g.v[j].st;
     status[j] = st->status;
     rho[j] = st->sc[par];
-    lim[j] = fmax(st->tol2 * st->bb, st->atol2);
+    lim[j] = st->tol2 * st->bb;
   }
   double t[NS * 2];
   {
@@ -438,10 +442,10 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
       t[j * 2 + 1] = b[j];
     }
   }
-  double di[KEPT_V], ri[KEPT_V][NS], vi[KEPT_V][NS];
+  double di[EV], ri[EV][NS], vi[EV][NS];
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     const bool in = i < g.n;
     di[e] = in ? g.dinv[i] : 0.0;
 #pragma unroll
@@ -491,8 +495,8 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
   }
   if (!any) return;
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     if (i >= g.n) continue;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -507,6 +511,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
 template <int NS>
 __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2* bmap, int par) {
   GROUP_HEAD(bmap)
+  constexpr int EV = kept_v(NS);
   __shared__ double sh[(KBS / 64) * NS * 4];
   int status[NS];
   double rho[NS], alpha[NS];
@@ -519,11 +524,11 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
   }
   double t[NS * 4];
   load_partials<NS, 4>(g.part_m, g.nblk_m, t);   // t.s, t.t, rhat.s, rhat.t
-  double di[KEPT_V], xi[KEPT_V][NS], phi[KEPT_V][NS], shi[KEPT_V][NS], si[KEPT_V][NS],
-      ti[KEPT_V][NS], pi[KEPT_V][NS], vi[KEPT_V][NS];
+  double di[EV], xi[EV][NS], phi[EV][NS], shi[EV][NS], si[EV][NS],
+      ti[EV][NS], pi[EV][NS], vi[EV][NS];
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     const bool in = i < g.n;
     di[e] = in ? g.dinv[i] : 0.0;
 #pragma unroll
@@ -577,8 +582,8 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
   if (!any) return;
   double acc[NS] = {};
 #pragma unroll
-  for (int e = 0; e < KEPT_V; ++e) {
-    const int i = row_of<KEPT_V>(lb, e);
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_of<EV>(lb, e);
     if (i >= g.n) continue;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -602,12 +607,13 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
 template <int NS>
 __global__ void __launch_bounds__(KBS) k_finish(const KGroup* groups, const int2* bmap) {
   GROUP_HEAD(bmap)
+  constexpr int EV = kept_v(NS);
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     if (g.v[j].st->status != KS_ZERO) continue;
 #pragma unroll
-    for (int e = 0; e < KEPT_V; ++e) {
-      const int i = row_of<KEPT_V>(lb, e);
+    for (int e = 0; e < EV; ++e) {
+      const int i = row_of<EV>(lb, e);
       if (i < g.n) g.v[j].x[i] = 0.0;
     }
   }

@@ -15,18 +15,23 @@
 
 namespace ipcs {
 
-int kept_m_for(int64_t n) {
+// Every block of a vector kernel re-reads the partial sums of every block of
+// the matrix kernel before it, so groups of several systems (whose vector
+// kernels have many blocks) keep their matrix kernels within KNB_MAX / 2 blocks.
+int kept_m_for(int64_t n, int ns) {
+  const int64_t cap = ns == 1 ? KNB_MAX : KNB_MAX / 2;
   for (int e : {1, 2, 4})
-    if (div_up(n, (int64_t)KBS * e) <= KNB_MAX) return e;
+    if (div_up(n, (int64_t)KBS * e) <= cap) return e;
+  if (div_up(n, (int64_t)KBS * 4) <= KNB_MAX) return 4;
   fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
 }
-int nblk_m_for(int64_t n) {
-  return (int)std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_m_for(n)));
+int nblk_m_for(int64_t n, int ns) {
+  return (int)std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_m_for(n, ns)));
 }
 constexpr int kMaxRefine = 30;   // mixed form: refinement passes
 
-int nblk_v_for(int64_t n) {
-  const int64_t b = std::max<int64_t>(1, div_up(n, (int64_t)KBS * KEPT_V));
+int nblk_v_for(int64_t n, int ns) {
+  const int64_t b = std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_v(ns)));
   if (b > KNB_MAX) fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
   return (int)b;
 }
@@ -251,7 +256,8 @@ void Run::layout(Carver& c) {
   kgroups = c.take<KGroup>(3);
   for (int gi = 0; gi < 3; ++gi) {
     const int64_t n = gi == 1 ? n1 : n2;
-    const int bm = nblk_m_for(n), bv = nblk_v_for(n);
+    const int ns = gi == 1 ? 1 : dim;
+    const int bm = nblk_m_for(n, ns), bv = nblk_v_for(n, ns);
     part_m[gi] = c.take<double>((int64_t)bm * GMAX * KP);
     part_v[gi][0] = c.take<double>((int64_t)bv * GMAX * KP);
     part_v[gi][1] = c.take<double>((int64_t)bv * GMAX * KP);
@@ -360,8 +366,8 @@ void Run::setup_solvers() {
     std::memset(&g, 0, sizeof(g));
     const int64_t n = gi == 1 ? n1 : n2;
     g.n = (int32_t)n;
-    g.nblk_m = nblk_m_for(n);
-    g.nblk_v = nblk_v_for(n);
+    g.nblk_m = nblk_m_for(n, gi == 1 ? 1 : dim);
+    g.nblk_v = nblk_v_for(n, gi == 1 ? 1 : dim);
     g.part_m = part_m[gi];
     g.part_v[0] = part_v[gi][0];
     g.part_v[1] = part_v[gi][1];
@@ -418,7 +424,7 @@ void Run::setup_solvers() {
                           hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(bmap_v[gi], maps_v[gi].data(), sizeof(int2) * maps_v[gi].size(),
                           hipMemcpyHostToDevice, stream));
-    S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n), mixed ? 1 : 0,
+    S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n, grp[gi].nsys), mixed ? 1 : 0,
                   bmap_m[gi],        (int)maps_m[gi].size(),
                   bmap_v[gi],        (int)maps_v[gi].size()};
     S.d_poll = poll + gi * GMAX;
@@ -602,11 +608,12 @@ void Run::asm_phase() {
 
 // r = -(rho/dt) sum_c D_c U*_c projected to zero sum; dP = 0.
 void Run::pressure_rhs() {
-  // the Poisson stopping test gets an absolute floor at the rounding level of
-  // r (a difference of terms that cancel): in the FP64 form on the solve's
-  // own state, in the mixed form for the refinement test (scal[6])
+  // r is a difference of terms that cancel exactly at a discrete steady
+  // state; an r no larger than a bound on its own rounding error is treated
+  // as zero (dP = 0): on the solve's state in the FP64 form, in the
+  // refinement test (scal[6]) in the mixed form
   rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
-               scal + 0, mixed ? nullptr : &(kst + dim)->atol2, scal + 6);
+               scal + 0, mixed ? nullptr : &(kst + dim)->zero2, scal + 6);
   HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
 }
 
@@ -831,7 +838,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
   }
   double* tot = scal + 3;   // [3] sum(res), [4] sum(res^2); [5] mean; [6] noise floor
   double host[4];
-  double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0;
+  double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0, last_tol = 1.0, op_limit = 0.0;
   double floor_in = 0.0;   // raised after an inner breakdown
   int inner_total = 0, outer = 0, rc = IPCS_OK;
   for (;; ++outer) {
@@ -847,18 +854,27 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
       rc = IPCS_E_NONFINITE;
       break;
     }
-    if (rr <= prm.tol_ir * prm.tol_ir * bb || rr <= floor2) break;
+    if (rr <= prm.tol_ir * prm.tol_ir * bb || (outer == 0 && rr <= floor2)) break;
     if (outer >= kMaxRefine) {
       rc = IPCS_E_NOT_CONVERGED;
       break;
     }
     // inner tolerance: the reduction still needed, but not below half of the
-    // reduction the last pass achieved (the FP32 operator's limit)
-    if (outer > 0) contraction = rel / prev;
+    // reduction a pass achieves (the FP32 operator's limit: seen on the
+    // previous pass, or on the previous step for the first pass)
+    if (outer > 0) {
+      contraction = rel / prev;
+      // a pass that stopped well short of its inner tolerance was limited by
+      // the FP32 operator: remember that reduction for the next step
+      if (contraction > 2.0 * last_tol) op_limit = std::max(op_limit, contraction);
+    } else {
+      contraction = ir_c;
+    }
     prev = rel;
     const double need = prm.tol_ir / rel;
     const double tol_in =
         std::min(0.5, std::max({need, 0.5 * contraction, floor_in, prm.tol_p}));
+    last_tol = tol_in;
     set_tolerance(stream, set_p.L, tol_in * tol_in);
     HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
     rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
@@ -873,6 +889,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     if (rc != IPCS_OK) break;
     axpy_inplace(stream, n1, 1.0, dIR, dP);
   }
+  if (op_limit > 0.0) ir_c = op_limit;   // kept while the operator keeps limiting passes
   if (st) {
     st->it_p = inner_total;
     st->res_p = rel;

@@ -83,9 +83,9 @@ int status_to_code(int kstatus);
 
 // Rows per thread of matrix kernels for a group of n rows, and the block
 // counts of matrix / vector kernels (each at most KNB_MAX).
-int kept_m_for(int64_t n);
-int nblk_m_for(int64_t n);
-int nblk_v_for(int64_t n);
+int kept_m_for(int64_t n, int ns);
+int nblk_m_for(int64_t n, int ns);
+int nblk_v_for(int64_t n, int ns);
 // (group, block) map interleaving the groups block by block
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
 
@@ -124,6 +124,7 @@ struct Run {
   void *Kp = nullptr, *Dc[3] = {}, *Gc[3] = {};
   double* Kp64 = nullptr;     // FP64 Kp (the same array as Kp in the FP64 form)
   double *rIR = nullptr, *dIR = nullptr;   // mixed form: refinement residual, correction
+  double ir_c = 0.0;          // mixed form: reduction per refinement pass seen last step
   double *liftA = nullptr, *liftM = nullptr;
   double *dinvA = nullptr, *dinvM = nullptr, *dinvKp = nullptr, *w = nullptr;
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
