@@ -153,14 +153,11 @@ void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream
   std::vector<Shared> sets = make_shared(runs, which, s, buf);
   KTimer none;
   for (Shared& sh : sets) {
-    int check_every = 1 << 30, maxit = 0;
-    for (Run* r : sh.owner) {
-      check_every = std::min(check_every, r->prm.check_every);
-      maxit = std::max(maxit, r->prm.maxit);
-    }
+    int check_every = 1 << 30;
+    for (Run* r : sh.owner) check_every = std::min(check_every, r->prm.check_every);
     std::vector<KState> hs;
     KState* pin = pinned_states(GMAX * (int)sh.owner.size());
-    krylov_solve(s, sh.S, m, check_every, maxit, hs, pin, none);
+    krylov_solve(s, sh.S, m, check_every, hs, pin, none);
     for (size_t g = 0; g < sh.owner.size(); ++g) {
       Run* r = sh.owner[g];
       set_of(*r, which).last_iters = sh.S.last_iters;

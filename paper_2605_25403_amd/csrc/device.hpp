@@ -76,6 +76,7 @@ struct KGroup {
   const void* val;            // FP64 values, or FP32 (KLaunch::fp32)
   const double* dinv;         // Jacobi: 1 / diag(A)
   int32_t nblk_m, nblk_v;
+  int32_t maxit, pad;         // iteration cap of the group's systems
   double* part_m;
   double* part_v[2];
   KVecs v[GMAX];
@@ -141,10 +142,13 @@ struct KLaunch {
 };
 // Start (mode 0) or confirm/restart (mode 1, systems PENDING or RESTART):
 // r = b - A x, then the status decision. par is the parity of the next
-// iteration launch; exhausted turns a restart into MAXIT.
-void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted);
+// iteration launch; a restart of a group whose maxit iterations have been
+// launched (launched >= maxit) becomes MAXIT instead.
+void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int launched);
 void pcg_iter(hipStream_t s, const KLaunch& L, int par);
-void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted);
+void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int launched);
+// Systems of group g still iterating become MAXIT (their cap was reached).
+void stop_group(hipStream_t s, const KLaunch& L, int g);
 void bicg_iter(hipStream_t s, const KLaunch& L, int par);
 void ksys_finish(hipStream_t s, const KLaunch& L);            // b == 0 systems: x := 0
 void gather_states(hipStream_t s, const KLaunch& L, KState* out);   // out[g*GMAX + j]

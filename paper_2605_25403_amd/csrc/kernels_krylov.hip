@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
 // and seed the partials that iteration's first vector kernel reduces.
 template <bool PCG, int NS>
 __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, int par,
-                                                int exhausted) {
+                                                int launched) {
   const KGroup& g = groups[blockIdx.x];
   __shared__ double sh[(KBS / 64) * NS * 3];
   __shared__ int run_s[NS];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
       if (bb == 0.0 || bb <= st->zero2) nst = KS_ZERO;
       else if (!finite(rr)) nst = KS_NONFINITE;
       else if (rr <= st->tol2 * bb) nst = KS_DONE;
-      else if (exhausted) nst = KS_MAXIT;
+      else if (launched >= g.maxit) nst = KS_MAXIT;
       st->status = nst;
       if (nst != KS_RUN) continue;
       if (PCG) {
@@ -667,7 +667,7 @@ static void with_ns_ept(const KLaunch& L, F f) {
 #define VTV decltype(V)
 
 template <bool PCG>
-static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
+static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int launched) {
   with_ns_ept(L, [&](auto N, auto E, auto V) {
     launch(k_start<PCG, NSV, EPTV, VTV>, dim3(L.nblocks_m), dim3(KBS), 0, s, L.groups,
                        L.bmap_m, mode);
@@ -675,17 +675,28 @@ static void start_impl(hipStream_t s, const KLaunch& L, int mode, int par, int e
   HIP_LAUNCH_OK();
   with_ns(L.ns, [&](auto N) {
     launch(k_decide<PCG, NSV>, dim3(L.ngroups), dim3(KBS), 0, s, L.groups, mode,
-                       par, exhausted);
+                       par, launched);
   });
   HIP_LAUNCH_OK();
 }
 
-void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
-  start_impl<true>(s, L, mode, par, exhausted);
+void pcg_start(hipStream_t s, const KLaunch& L, int mode, int par, int launched) {
+  start_impl<true>(s, L, mode, par, launched);
 }
 
-void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int exhausted) {
-  start_impl<false>(s, L, mode, par, exhausted);
+void bicg_start(hipStream_t s, const KLaunch& L, int mode, int par, int launched) {
+  start_impl<false>(s, L, mode, par, launched);
+}
+
+__global__ void k_stop_group(const KGroup* groups, int g) {
+  const int j = threadIdx.x;
+  if (j < groups[g].nsys && groups[g].v[j].st->status == KS_RUN)
+    groups[g].v[j].st->status = KS_MAXIT;
+}
+
+void stop_group(hipStream_t s, const KLaunch& L, int g) {
+  hipLaunchKernelGGL(k_stop_group, dim3(1), dim3(64), 0, s, L.groups, g);
+  HIP_LAUNCH_OK();
 }
 
 void pcg_spmv_only(hipStream_t s, const KLaunch& L) {

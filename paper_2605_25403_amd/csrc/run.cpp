@@ -103,8 +103,8 @@ void KTimer::drain() {
   which.clear();
 }
 
-int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
-                 std::vector<KState>& hs, KState* pinned, KTimer& T) {
+int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector<KState>& hs,
+                 KState* pinned, KTimer& T) {
   const int nslot = S.L.ngroups * GMAX;
   hs.assign(nslot, KState{});
   auto fetch = [&]() {
@@ -132,25 +132,48 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
   };
   int par = 0, launched = 0;
   auto start = [&](int mode) {
-    const int exhausted = launched >= maxit;
-    if (m == KMethod::PCG) pcg_start(s, S.L, mode, par, exhausted);
-    else bicg_start(s, S.L, mode, par, exhausted);
+    if (m == KMethod::PCG) pcg_start(s, S.L, mode, par, launched);
+    else bicg_start(s, S.L, mode, par, launched);
+  };
+  // groups with systems still iterating: the least remaining cap among them
+  auto remaining = [&]() {
+    int rem = -1;
+    for (int g = 0; g < S.L.ngroups; ++g) {
+      bool run = false;
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) run |= hs[g * GMAX + j].status == KS_RUN;
+      if (run) rem = rem < 0 ? S.h_groups[g].maxit - launched
+                             : std::min(rem, S.h_groups[g].maxit - launched);
+    }
+    return rem;
   };
   start(0);
   fetch();
   const int every = std::max(1, check_every);
+  bool restarted = false;
   for (;;) {
     bool run = false;
     each([&](const KState& k) { run |= (k.status == KS_RUN); });
     if (!run) break;
-    if (launched >= maxit) {
-      each([&](KState& k) {
-        if (k.status == KS_RUN) k.status = KS_MAXIT;
-      });
-      break;
+    // groups whose cap is reached stop (on the device too), the others go on
+    bool stopped = false;
+    for (int g = 0; g < S.L.ngroups; ++g) {
+      if (launched < S.h_groups[g].maxit) continue;
+      bool here = false;
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) {
+        KState& k = hs[g * GMAX + j];
+        if (k.status == KS_RUN) {
+          k.status = KS_MAXIT;
+          here = true;
+        }
+      }
+      if (here) stop_group(s, S.L, g);
+      stopped |= here;
     }
-    int chunk = std::max(every, (S.last_iters - launched) / 2);
-    chunk = std::min(chunk, maxit - launched);
+    if (stopped) continue;
+    const int rem = remaining();
+    // after a restart the remaining iterations are few and unknown
+    int chunk = restarted ? every : std::max(every, (S.last_iters - launched) / 2);
+    chunk = std::max(1, std::min(chunk, rem));
     for (int k = 0; k < chunk; ++k) {
       iterate(par);
       par ^= 1;
@@ -162,9 +185,12 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
     if (pend) {
       start(1);
       fetch();
+      each([&](const KState& k) { restarted |= k.status == KS_RUN; });
     }
   }
-  S.last_iters = launched;
+  int iters = 0;
+  each([&](const KState& k) { iters = std::max(iters, k.it); });
+  S.last_iters = iters;   // the poll schedule of the next solve of this set
   ksys_finish(s, S.L);
   int rc = IPCS_OK;
   each([&](const KState& k) {
@@ -368,6 +394,7 @@ void Run::setup_solvers() {
     g.n = (int32_t)n;
     g.nblk_m = nblk_m_for(n, gi == 1 ? 1 : dim);
     g.nblk_v = nblk_v_for(n, gi == 1 ? 1 : dim);
+    g.maxit = prm.maxit;
     g.part_m = part_m[gi];
     g.part_v[0] = part_v[gi][0];
     g.part_v[1] = part_v[gi][1];
@@ -664,7 +691,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       phase_next = IPCS_PHASE_MOMENTUM;
       return IPCS_OK;
     case IPCS_PHASE_MOMENTUM:
-      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, prm.maxit, hs, pinned,
+      rc = krylov_solve(stream, set_mom, KMethod::BICG, prm.check_every, hs, pinned,
                         timer);
       fill_stats_solve(hs, dim, 1, st);
       HIP_OK(hipEventRecord(ev[2], stream));
@@ -688,7 +715,7 @@ int Run::phase(int which, ipcs_step_stats* st) {
       return IPCS_OK;
     case IPCS_PHASE_CORRECTION:
       correction_rhs();
-      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned,
+      rc = krylov_solve(stream, set_corr, KMethod::PCG, prm.check_every, hs, pinned,
                         timer);
       fill_stats_solve(hs, dim, 3, st);
       phase_next = IPCS_PHASE_ASM;
@@ -831,7 +858,7 @@ void Run::export_values(int pattern, const void* dev, int vbytes, double* out) {
 // matrix (FP64 vectors and sums) to a loose relative tolerance and add d.
 int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
   if (!mixed) {
-    const int rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs,
+    const int rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs,
                                 pinned, timer);
     fill_stats_solve(hs, 1, 2, st);
     return rc;
@@ -877,7 +904,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     last_tol = tol_in;
     set_tolerance(stream, set_p.L, tol_in * tol_in);
     HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
-    rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, prm.maxit, hs, pinned, timer);
+    rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned, timer);
     inner_total += hs[0].it;
     if (rc == IPCS_E_BREAKDOWN) {
       // Kp rounded to FP32 is singular only up to rounding and can be

@@ -74,10 +74,10 @@ struct KSet {
 
 enum class KMethod { PCG, BICG };
 
-// Runs a set to completion (at most maxit iterations). h_states[g*GMAX + j]
+// Runs a set to completion (each group at most its maxit iterations). h_states[g*GMAX + j]
 // receives the final states. Returns IPCS_OK or the status of the first
 // failed system.
-int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, int maxit,
+int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every,
                  std::vector<KState>& h_states, KState* pinned, KTimer& T);
 int status_to_code(int kstatus);
 

@@ -1,0 +1,136 @@
+"""The C ABI's behaviour on the GPU beyond parity: failures leave the state at
+the last completed step, phase order is enforced, a failing run in a batch
+does not disturb the others, results are deterministic and resumable, and
+host callbacks give the built-in data's results."""
+import numpy as np
+import pytest
+
+from oracle import problems
+from tests.gpu_common import rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def tg_run(I, n=12, k=np.pi, nu=0.01, dt=0.01, stream=None, **kw):
+    p = I.ipcs_params_default(nu=nu, dt=dt, **kw)
+    r = I.Run(I.Mesh.unit_square(n), p, stream=stream)
+    r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (k,))
+    return r
+
+
+def test_maxit_failure_keeps_last_completed_step():
+    torch, I = require_gpu()
+    print("maxit failure", flush=True)
+    r = tg_run(I, maxit=3)
+    U0, P0, t0 = r.velocity().copy(), r.pressure().copy(), r.time()
+    with pytest.raises(I.IpcsError) as e:
+        r.advance(1)
+    assert e.value.code == I.IPCS_E_NOT_CONVERGED
+    st = e.value.stats[0]
+    assert st.status == I.IPCS_E_NOT_CONVERGED and st.failed_solve in (1, 2, 3)
+    np.testing.assert_array_equal(r.velocity(), U0)
+    np.testing.assert_array_equal(r.pressure(), P0)
+    assert r.time() == t0
+
+
+def test_nonfinite_state_is_reported():
+    torch, I = require_gpu()
+    print("nonfinite", flush=True)
+    r = tg_run(I)
+    U, P = r.velocity().copy(), r.pressure().copy()
+    U[0, 5] = np.nan
+    r.set_state(U, P, 0.0)
+    with pytest.raises(I.IpcsError) as e:
+        r.advance(1)
+    assert e.value.code == I.IPCS_E_NONFINITE
+    assert r.time() == 0.0
+
+
+def test_phase_order_is_enforced():
+    torch, I = require_gpu()
+    print("phase order", flush=True)
+    r = tg_run(I)
+    with pytest.raises(I.IpcsError) as e:
+        r.phase(I.IPCS_PHASE_PRESSURE)
+    assert e.value.code == I.IPCS_E_STATE
+    r.phase(I.IPCS_PHASE_ASM)
+    with pytest.raises(I.IpcsError) as e:
+        r.advance(1)          # a step is in progress
+    assert e.value.code == I.IPCS_E_STATE
+    for ph in (I.IPCS_PHASE_MOMENTUM, I.IPCS_PHASE_PRESSURE, I.IPCS_PHASE_CORRECTION):
+        r.phase(ph)
+    r.advance(1)
+    assert abs(r.time() - 0.02) < 1e-15
+
+
+def test_batch_failure_is_isolated():
+    torch, I = require_gpu()
+    print("batch failure isolation", flush=True)
+    s = torch.cuda.Stream()
+    good = tg_run(I, n=10, stream=s)
+    bad = tg_run(I, n=14, maxit=2, stream=s)
+    ref = tg_run(I, n=10)
+    ref.advance(2)
+    U0, t0 = bad.velocity().copy(), bad.time()
+    for _ in range(2):
+        rc, st = I.ipcs_batch_step([good.h, bad.h], s.cuda_stream)
+        assert rc == I.IPCS_E_NOT_CONVERGED
+        assert st[0]["status"] == 0 and st[1]["status"] == I.IPCS_E_NOT_CONVERGED
+    np.testing.assert_array_equal(good.velocity(), ref.velocity())
+    np.testing.assert_array_equal(good.pressure(), ref.pressure())
+    np.testing.assert_array_equal(bad.velocity(), U0)
+    assert bad.time() == t0
+
+
+def test_runs_are_deterministic_and_resumable():
+    torch, I = require_gpu()
+    print("determinism and resume", flush=True)
+    a, b = tg_run(I, n=20, k=2 * np.pi, nu=0.004, dt=0.003), tg_run(I, n=20, k=2 * np.pi,
+                                                                     nu=0.004, dt=0.003)
+    a.advance(5)
+    b.advance(3)
+    U, P, t = b.velocity(), b.pressure(), b.time()
+    c = tg_run(I, n=20, k=2 * np.pi, nu=0.004, dt=0.003)
+    c.set_state(U, P, t)          # checkpoint / resume through the host
+    b.advance(2)
+    c.advance(2)
+    for r in (b, c):
+        np.testing.assert_array_equal(r.velocity(), a.velocity())
+        np.testing.assert_array_equal(r.pressure(), a.pressure())
+        assert r.time() == a.time()
+
+
+def test_set_viscosity_matches_a_fresh_run():
+    torch, I = require_gpu()
+    print("set_viscosity", flush=True)
+    a = tg_run(I, n=16, nu=0.01)
+    a.advance(2)
+    I.ipcs_set_viscosity(a.h, 0.03)
+    b = tg_run(I, n=16, nu=0.03)
+    b.set_state(a.velocity(), a.pressure(), a.time())
+    # the built-in data (Dirichlet values) follow the run's own viscosity
+    a.advance(2)
+    b.advance(2)
+    np.testing.assert_array_equal(a.velocity(), b.velocity())
+    np.testing.assert_array_equal(a.pressure(), b.pressure())
+
+
+def test_host_callbacks_match_builtin_data():
+    """John's forced problem: forcing and Dirichlet data from host callbacks
+    (quadrature points and boundary nodes) against the built-in closed forms."""
+    torch, I = require_gpu()
+    print("callbacks", flush=True)
+    pb = problems.John2D(1.0)
+    m = I.Mesh.unit_square(12)
+    p = I.ipcs_params_default(nu=1.0, dt=0.002, callbacks=1)
+    a = I.Run(m, p)
+    a.set_builtin(I.IPCS_SOL_JOHN_2D)
+    U0, P0 = a.velocity().copy(), a.pressure().copy()
+    b = I.Run(m, p)
+    b.set_state(U0, P0, 0.0)
+    b.set_dirichlet(lambda x, t: pb.u(x, t))
+    b.set_forcing(lambda x, t: pb.f(x, t))
+    a.advance(3)
+    b.advance(3)
+    assert rel(b.velocity(), a.velocity()) <= 1e-12
+    assert rel(b.pressure(), a.pressure()) <= 1e-10
