@@ -8,6 +8,7 @@ numpy's PCG64 generator:
 * a serving request stream: Poisson arrivals at a given rate, mesh size n
   drawn from a set, and per-request (k, nu).
 """
+import itertools
 import math
 
 import numpy as np
@@ -64,3 +65,43 @@ def dofs(dim, n):
     if dim == 2:
         return 2 * (2 * n + 1) ** 2 + (n + 1) ** 2
     return 3 * (2 * n + 1) ** 3 + (n + 1) ** 3
+
+
+def jittered_mesh(dim, n, seed, amp=0.2):
+    """Unstructured simplicial mesh of the unit square (dim 2) or cube (dim 3):
+    an n^dim vertex grid whose interior vertices move by up to amp * h in each
+    coordinate (uniform), with vertices relabelled at random, cells listed in a
+    random order and about half of them given the opposite orientation. In 2D
+    each square is cut along a diagonal picked at random; in 3D each cube gives
+    the six tetrahedra around its (0,0,0)-(1,1,1) diagonal (conforming).
+    Returns (x (nv, dim) float64, cells (nc, dim + 1) int32)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    ax = np.arange(n + 1)
+    grid = np.stack(np.meshgrid(*([ax] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    x = grid * h
+    inner = np.all((grid > 0) & (grid < n), axis=1)
+    x[inner] += amp * h * rng.uniform(-1.0, 1.0, (int(inner.sum()), dim))
+    stride = np.array([(n + 1) ** (dim - 1 - a) for a in range(dim)])
+    cells = []
+    for corner in itertools.product(range(n), repeat=dim):
+        v0 = np.array(corner)
+        if dim == 2:
+            a, b, c, d = [int((v0 + o) @ stride) for o in ((0, 0), (1, 0), (1, 1), (0, 1))]
+            cells += [(a, b, c), (a, c, d)] if rng.random() < 0.5 else [(a, b, d), (b, c, d)]
+        else:
+            for perm in itertools.permutations(range(dim)):
+                path, v = [int(v0 @ stride)], v0.copy()
+                for axis in perm:
+                    v = v.copy()
+                    v[axis] += 1
+                    path.append(int(v @ stride))
+                cells.append(tuple(path))
+    cells = np.array(cells, dtype=np.int64)
+    relabel = rng.permutation(len(x))          # old index -> new index
+    xn = np.empty_like(x)
+    xn[relabel] = x
+    cells = relabel[cells][rng.permutation(len(cells))]
+    flip = rng.random(len(cells)) < 0.5
+    cells[flip] = cells[flip][:, [1, 0] + list(range(2, dim + 1))]
+    return xn, cells.astype(np.int32)

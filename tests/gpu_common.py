@@ -36,14 +36,20 @@ def oracle_space(dim, n):
     return fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)))
 
 
-def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=True, **kw):
+def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=True,
+              arrays=None, **kw):
     """Oracle IPCS object and library run for the same problem. With
-    same_state the library starts from the oracle's initial arrays."""
-    S = oracle_space(dim, n)
+    same_state the library starts from the oracle's initial arrays. arrays =
+    (x, cells) replaces the structured n-mesh by that mesh on both sides."""
+    if arrays is None:
+        S = oracle_space(dim, n)
+        m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
+    else:
+        S = fem.Space(*arrays)
+        m = I.Mesh.from_arrays(*arrays)
     pb = oracle_problem(kind, dim, nu, k)
     o = ipcs.IPCS(S, pb, ipcs.Params(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol,
                                      tol_corr=tol))
-    m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
     p = I.ipcs_params_default(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol, tol_corr=tol, **kw)
     r = I.Run(m, p)
     prm = (k,) if kind == "tg" else ()

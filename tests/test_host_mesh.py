@@ -117,3 +117,13 @@ def test_workspace_size_grows_with_the_mesh_and_covers_the_values():
     assert big > 4 * small          # fixed-size scratch dominates tiny meshes
     # at least the five P2P2 value arrays and the velocity vectors
     assert big > 5 * 8 * m.counts.nnz[0] + 6 * 8 * 2 * m.counts.n2
+
+
+@pytest.mark.parametrize("dim,n,seed", [(2, 7, 0), (2, 12, 5), (3, 3, 1)])
+def test_jittered_relabelled_meshes_match_oracle(dim, n, seed):
+    """Seeded unstructured meshes (moved interior vertices, random vertex
+    labels, cell order and orientation): DOF numbering, boundary and patterns
+    agree exactly."""
+    from paper_2605_25403_amd.workloads import jittered_mesh
+    X, cells = jittered_mesh(dim, n, seed)
+    compare(fem.Space(X, cells), I.Mesh.from_arrays(X, cells))
