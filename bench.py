@@ -36,34 +36,39 @@ KERNELS = {
     "bicg_update_s": (6, "kernels_krylov.hip"),
     "bicg_update_x": (7, "kernels_krylov.hip"),
     "pcg_update_m": (8, "kernels_krylov.hip"),
+    "pcg_fused_p": (9, "kernels_fcg.hip"),
 }
 
 
-def kernel_bytes(kernel, c, dim):
+def kernel_bytes(kernel, c, dim, vsz=8):
     """Algorithmic bytes per launch: each array read once, each output written
-    once, 8-byte values and vectors, 4-byte indices (formulas in the design doc)."""
+    once, vsz-byte matrix values, 8-byte vectors, 4-byte indices (2-byte local
+    indices in the fused Poisson CG; its halo re-reads are not counted)
+    (formulas in DESIGN.md)."""
     n1, n2 = c.n1, c.n2
+    if kernel == "pcg_fused_p":    # Kp values + local cols; dinv, x, p, r, s, w in; x, p, s, r, w out
+        return (vsz + 2) * c.nnz[1] + 11 * 8 * n1
     nnz22, nnz11 = c.nnz[0], c.nnz[1]
     sl1, sl2 = 4 * (n1 // 64 + 2), 4 * (n2 // 64 + 2)     # SELL-64 slice pointers
     if kernel == "pcg_spmv_p":     # Kp values+cols once; u in, w = Kp u out
-        return 12 * nnz11 + sl1 + 2 * 8 * n1
+        return (vsz + 4) * nnz11 + sl1 + 2 * 8 * n1
     if kernel == "pcg_update_p":   # x, r, p, s, w, dinv in; x, r, p, s, u out
         return 11 * 8 * n1
     if kernel == "bicg_spmv":      # A once for all components; phat, rhat in, v out each
-        return 12 * nnz22 + sl2 + dim * 3 * 8 * n2
+        return (vsz + 4) * nnz22 + sl2 + dim * 3 * 8 * n2
     if kernel == "bicg_spmv_t":    # A once; shat, s, rhat in, t out each
-        return 12 * nnz22 + sl2 + dim * 4 * 8 * n2
+        return (vsz + 4) * nnz22 + sl2 + dim * 4 * 8 * n2
     if kernel == "bicg_update_s":  # dinv; r, v in, s, shat out each
         return 8 * n2 + dim * 4 * 8 * n2
     if kernel == "bicg_update_x":  # dinv; x, phat, shat, s, t, p, v in, x, r, p, phat out each
         return 8 * n2 + dim * 11 * 8 * n2
     if kernel == "pcg_spmv_m":     # M once for all components; u in, w out each
-        return 12 * nnz22 + sl2 + dim * 2 * 8 * n2
+        return (vsz + 4) * nnz22 + sl2 + dim * 2 * 8 * n2
     if kernel == "pcg_update_m":   # dinv; x, r, p, s, w in, x, r, p, s, u out each
         return 8 * n2 + dim * 10 * 8 * n2
     if kernel == "asm_conv":       # E out, U in, cell DOFs, vertex coordinates
         nloc = 6 if dim == 2 else 10
-        return 8 * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
+        return vsz * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
     raise KeyError(kernel)
 
 
@@ -131,6 +136,7 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
         return out
 
     sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
+           "pcg_fused_p": r"k_fcg_iter<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
            "asm_conv": r"OpConvExplicit"}[kernel]
     copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)
@@ -346,7 +352,7 @@ def main():
         if kcnt[kid] == 0:
             continue
         us = 1000.0 * kms[kid] / kcnt[kid]
-        b = kernel_bytes(name, c, dim)
+        b = kernel_bytes(name, c, dim, 4 if mixed else 8)
         kern[name] = {"us_per_launch": us, "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
                       "launches_per_step": kcnt[kid] / ksteps,
                       "ms_per_step": kms[kid] / ksteps}

@@ -105,6 +105,23 @@ int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap);
 /* CSR pattern (row pointer [rows+1], sorted column indices [nnz]). */
 int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
                       int32_t* col, int64_t cap_nnz);
+/* Row partition of the P1-P1 pattern into parts of at most rows_max rows
+ * (64..2048) that the one-kernel-per-iteration Poisson CG uses (host data, for
+ * inspection). Parts are compact patches of vertices (recursive coordinate
+ * bisection); rows are renumbered part by part ("part order"). sizes[0..4]
+ * receives nparts, the halo length, the number of SELL-64 slices, the number
+ * of entries and the largest own + halo count of a part. With non-NULL
+ * arrays also: perm[n1] (part-order row -> original row), part_ptr[nparts+1],
+ * halo_ptr[nparts+1], halo[] (part-order rows each part reads from other
+ * parts), slice_ptr[nparts+1] (first slice of each part), sptr[nslices+1]
+ * (entry offsets; entry k of a part's local row l = 64 j + q sits at
+ * sptr[slice_ptr[p] + j] + 64 k + q), lcol[] (local columns: < own for the
+ * part's rows, own + h for halo[halo_ptr[p] + h]) and src[] (entry index in
+ * the global SELL-64 layout of the pattern, -1 for padding). The arrays must
+ * be all NULL or all non-NULL and as large as sizes[] says. */
+int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int32_t* perm,
+                           int32_t* part_ptr, int32_t* halo_ptr, int32_t* halo,
+                           int32_t* slice_ptr, int32_t* sptr, uint16_t* lcol, int32_t* src);
 /* The degree-5 cell quadrature rule the kernels use, in barycentric
  * coordinates lam[nq*(dim+1)] with weights w[nq] summing to 1/dim!.
  * *nq receives the number of points; pass NULL buffers to query it. */
@@ -144,7 +161,13 @@ typedef struct {
   int32_t maxit;        /* iteration cap per solve                             */
   int32_t check_every;  /* host convergence poll interval (iterations)         */
   int32_t callbacks;    /* 1: reserve staging for host-callback forcing        */
-  int32_t reserved;
+  int32_t poisson_part_rows; /* pressure Poisson CG form: 0 (default) one kernel
+                           * per iteration on a row partition of Kp into parts
+                           * of at most 384 rows, falling back to two kernels
+                           * where a part's halo does not fit in LDS; 64..2048
+                           * the same with that part size (IPCS_E_CAPACITY if
+                           * it does not fit); -1 two kernels per iteration
+                           * (SpMV, then the vector update)                  */
 } ipcs_params;
 
 /* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12
@@ -196,6 +219,10 @@ typedef struct {
   int32_t it_corr[3];       /* correction PCG iterations per component          */
   int32_t ir_outer;         /* mixed form: refinement sweeps of the Poisson     */
   int32_t failed_solve;     /* 0 none, 1 momentum, 2 pressure, 3 correction     */
+  int32_t checks_p;         /* Poisson: true-residual checks b - A x (1: the
+                             * recursive residual was confirmed at once; each
+                             * further check follows a restart)                */
+  int32_t reserved;
   double res_mom[3], res_p, res_corr[3];   /* final relative residuals         */
   double t;                 /* time reached                                     */
   float ms_asm, ms_mom, ms_p, ms_corr;     /* phase times (stream events)      */
@@ -255,7 +282,9 @@ enum {                            /* kernels of the step, for the timing hooks  
   IPCS_KERNEL_BICG_UPDATE_S = 6,  /* momentum BiCGStab: s = r - alpha v, shat        */
   IPCS_KERNEL_BICG_UPDATE_X = 7,  /* momentum BiCGStab: x, r, p, phat updates; r.r   */
   IPCS_KERNEL_PCG_UPDATE_M = 8,   /* correction CG: p, s, x, r, u updates            */
-  IPCS_NKERNEL = 9
+  IPCS_KERNEL_PCG_FUSED_P = 9,    /* Poisson CG, one kernel per iteration: update,
+                                   * halo recomputation, w = Kp u; r.u, r.r, w.u    */
+  IPCS_NKERNEL = 10
 };
 /* Measurement hook (not part of the method): from the next call on, every
  * launch of a kernel whose bit (1 << IPCS_KERNEL_*) is set in mask is
@@ -268,10 +297,19 @@ int ipcs_kernel_times(ipcs_run r, double* ms, int64_t* launches, int32_t cap);
 /* Measurement hook (not part of the method): launches one of the step's
  * kernels nlaunch times back to back on the run's stream with the run's own
  * data and returns the mean duration per launch in microseconds, timed with
- * HIP events on that stream. Leaves the run's Krylov scratch vectors and
- * states undefined (the next solve re-initializes them); the state U, P and t
- * are not touched. Call between steps only. */
+ * HIP events on that stream. Leaves the run's Krylov scratch vectors
+ * undefined (the next solve re-initializes them); the solver states
+ * (tolerances) are restored and U, P and t are not touched, so the run steps on
+ * as before. Call between steps only. */
 int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_per_launch);
+
+/* The pressure Poisson CG form the run uses. *rows_max receives the part size
+ * of its row partition (0: two kernels per iteration, no partition), *nparts
+ * the number of parts, *halo_rows the summed halo sizes (the rows a part reads
+ * from other parts, once per part), *lds_rows the largest own + halo count of
+ * a part. Any output pointer may be NULL. */
+int ipcs_poisson_partition(ipcs_run r, int32_t* rows_max, int32_t* nparts, int64_t* halo_rows,
+                           int32_t* lds_rows);
 
 void ipcs_run_destroy(ipcs_run r);
 

@@ -10,7 +10,10 @@
 // a run's result in a batch is bitwise the one it gets alone.
 //
 // Launch sets are split by (systems per group, rows per thread of matrix
-// kernels, matrix value type), which the kernels take as template arguments.
+// kernels, matrix value type), which the kernels take as template arguments;
+// Poisson systems in the one-kernel-per-iteration form (kernels_fcg.hip) form
+// sets of their own by (rows per thread, value type), with the largest LDS
+// size of their members.
 // Their device descriptors (group table, block maps, polling slots) come from
 // one stream-ordered allocation per solve, released stream-ordered.
 #include <algorithm>
@@ -70,10 +73,12 @@ KSet& set_of(Run& r, int which) {
 // caller keeps alive until the solves have been enqueued.
 std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStream_t s,
                                 std::unique_ptr<DevBuf>& buf) {
-  std::map<std::tuple<int, int, int>, std::vector<Run*>> cls;
+  // fused Poisson sets: (1, rows per thread, value type); others: (0, ns, ept_m, value type)
+  std::map<std::tuple<int, int, int, int>, std::vector<Run*>> cls;
   for (Run* r : runs) {
-    const KLaunch& L = set_of(*r, which).L;
-    cls[{L.ns, L.ept_m, L.fp32}].push_back(r);
+    const KSet& K = set_of(*r, which);
+    if (K.fused) cls[{1, 1, K.F.ept, K.F.fp32}].push_back(r);
+    else cls[{0, K.L.ns, K.L.ept_m, K.L.fp32}].push_back(r);
   }
   // sizes
   size_t bytes = 0;
@@ -84,19 +89,22 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     return off;
   };
   struct Plan {
+    bool fused = false;
     std::vector<Run*> rs;
-    std::vector<int2> bm, bv;
-    size_t o_groups, o_bm, o_bv, o_poll;
+    std::vector<int2> bm, bv, bf;
+    size_t o_groups, o_bm, o_bv, o_poll, o_fgroups = 0, o_bf = 0;
   };
   std::vector<Plan> plans;
   for (auto& kv : cls) {
     Plan p;
+    p.fused = std::get<0>(kv.first) == 1;
     p.rs = kv.second;
-    std::vector<int> nm, nv;
+    std::vector<int> nm, nv, nf;
     for (Run* r : p.rs) {
-      const KGroup& g = set_of(*r, which).h_groups[0];
-      nm.push_back(g.nblk_m);
-      nv.push_back(g.nblk_v);
+      const KSet& K = set_of(*r, which);
+      nm.push_back(K.h_groups[0].nblk_m);
+      nv.push_back(K.h_groups[0].nblk_v);
+      if (p.fused) nf.push_back(K.h_fgroups[0].nparts);
     }
     build_bmap(nm, p.bm);
     build_bmap(nv, p.bv);
@@ -104,6 +112,14 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     p.o_bm = take(sizeof(int2) * p.bm.size());
     p.o_bv = take(sizeof(int2) * p.bv.size());
     p.o_poll = take(sizeof(KState) * GMAX * p.rs.size());
+    if (p.fused) {
+      // group by group, each XCD taking a contiguous range (neighbouring parts)
+      for (size_t gi = 0; gi < nf.size(); ++gi)
+        for (int b = 0; b < nf[gi]; ++b) p.bf.push_back(make_int2((int)gi, b));
+      xcd_order(p.bf);
+      p.o_fgroups = take(sizeof(FGroup) * p.rs.size());
+      p.o_bf = take(sizeof(int2) * p.bf.size());
+    }
     plans.push_back(std::move(p));
   }
   buf.reset(new DevBuf(s, bytes));
@@ -133,6 +149,21 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
                   reinterpret_cast<const int2*>(buf->base + p.o_bv),
                   (int)p.bv.size()};
     S.d_poll = reinterpret_cast<KState*>(buf->base + p.o_poll);
+    if (p.fused) {
+      size_t lds = 0;
+      for (Run* r : p.rs) {
+        const KSet& own = set_of(*r, which);
+        S.h_fgroups.push_back(own.h_fgroups[0]);
+        lds = std::max(lds, own.F.lds);
+      }
+      std::memcpy(host.data() + p.o_fgroups, S.h_fgroups.data(), sizeof(FGroup) * p.rs.size());
+      std::memcpy(host.data() + p.o_bf, p.bf.data(), sizeof(int2) * p.bf.size());
+      const FLaunch& F0 = set_of(*p.rs[0], which).F;
+      S.fused = true;
+      S.F = FLaunch{reinterpret_cast<const FGroup*>(buf->base + p.o_fgroups), (int)p.rs.size(),
+                    F0.ept, F0.fp32, reinterpret_cast<const int2*>(buf->base + p.o_bf),
+                    (int)p.bf.size(), lds};
+    }
     S.last_iters = last;
     std::copy(std::begin(set_of(*p.rs[0], which).kid), std::end(set_of(*p.rs[0], which).kid),
               std::begin(S.kid));
@@ -170,7 +201,10 @@ void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream
       }
       rc[r] = code;
       if (which != 1 || !r->mixed) fill_stats_solve(mine, ns, which + 1, st[r]);
-      else if (st[r]) st[r]->it_p += mine[0].it;
+      else if (st[r]) {
+        st[r]->it_p += mine[0].it;
+        st[r]->checks_p += mine[0].nchecks;
+      }
     }
   }
 }

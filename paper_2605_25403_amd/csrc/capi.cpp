@@ -71,6 +71,9 @@ void check_params(const ipcs_params* p) {
   need(p->precision == IPCS_FP64 || p->precision == IPCS_MIXED, "unknown precision");
   need(p->convection == IPCS_CONV_EXPLICIT, "only explicit convection is available");
   need(p->precision == IPCS_FP64 || p->tol_ir > 0, "the mixed form needs tol_ir > 0");
+  need(p->poisson_part_rows == 0 || p->poisson_part_rows == -1 ||
+           (p->poisson_part_rows >= 64 && p->poisson_part_rows <= 2048),
+       "poisson_part_rows must be 0, -1 or in [64, 2048]");
 }
 }  // namespace
 
@@ -156,6 +159,37 @@ int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_r
     need(col != nullptr && cap_nnz >= P.nnz(), "col buffer too small");
     std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
     std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
+    return IPCS_OK;
+  });
+}
+
+int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int32_t* perm,
+                           int32_t* part_ptr, int32_t* halo_ptr, int32_t* halo,
+                           int32_t* slice_ptr, int32_t* sptr, uint16_t* lcol, int32_t* src) {
+  return guard([&]() -> int {
+    need(sizes != nullptr, "null sizes");
+    need(rows_max >= 64 && rows_max <= 2048, "rows_max must be in [64, 2048]");
+    const auto q = M(m).parts11(rows_max);
+    sizes[0] = q->nparts;
+    sizes[1] = (int64_t)q->halo.size();
+    sizes[2] = (int64_t)q->sptr.size() - 1;
+    sizes[3] = q->nent;
+    sizes[4] = q->lds_max;
+    const bool any = perm || part_ptr || halo_ptr || halo || slice_ptr || sptr || lcol || src;
+    if (!any) return IPCS_OK;
+    need(perm && part_ptr && halo_ptr && halo && slice_ptr && sptr && lcol && src,
+         "partition arrays must be all NULL or all non-NULL");
+    auto cp = [](auto* dst, const auto& v) {
+      if (!v.empty()) std::memcpy(dst, v.data(), sizeof(v[0]) * v.size());
+    };
+    cp(perm, q->perm);
+    cp(part_ptr, q->part_ptr);
+    cp(halo_ptr, q->halo_ptr);
+    cp(halo, q->halo);
+    cp(slice_ptr, q->slice_ptr);
+    cp(sptr, q->sptr);
+    cp(lcol, q->lcol);
+    cp(src, q->src);
     return IPCS_OK;
   });
 }
@@ -411,6 +445,18 @@ int ipcs_kernel_times(ipcs_run r, double* ms, int64_t* launches, int32_t cap) {
       ms[k] = T.ms[k];
       launches[k] = T.cnt[k];
     }
+    return IPCS_OK;
+  });
+}
+
+int ipcs_poisson_partition(ipcs_run r, int32_t* rows_max, int32_t* nparts, int64_t* halo_rows,
+                           int32_t* lds_rows) {
+  return guard([&]() -> int {
+    const auto& pp = R(r).pp;
+    if (rows_max) *rows_max = pp ? pp->rows_max : 0;
+    if (nparts) *nparts = pp ? pp->nparts : 0;
+    if (halo_rows) *halo_rows = pp ? (int64_t)pp->halo.size() : 0;
+    if (lds_rows) *lds_rows = pp ? pp->lds_max : 0;
     return IPCS_OK;
   });
 }

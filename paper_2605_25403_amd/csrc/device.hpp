@@ -82,6 +82,38 @@ struct KGroup {
   KVecs v[GMAX];
 };
 
+// One pressure Poisson system for the one-kernel-per-iteration CG
+// (kernels_fcg.hip): the matrix in the part-local SELL-64 layout of a row
+// partition (mesh.hpp, PartSell), Krylov vectors in part order. r, s and w are
+// double-buffered by launch parity (parts read their halo rows of the buffer
+// that no block writes in that launch); x and p are only touched by their
+// owning part. part[q] holds the partials [gamma = r.u, r.r, delta = w.u]
+// written by launches of parity q^1 (and by the start with parity q).
+struct FGroup {
+  int32_t n, nparts;
+  const int32_t* perm;        // part-order row -> original row
+  const int32_t* part_ptr;    // [nparts+1]
+  const int32_t* halo_ptr;    // [nparts+1]
+  const int32_t* halo;        // part-order rows
+  const int32_t* slice_ptr;   // [nparts+1]
+  const int32_t* sptr;        // slice entry offsets
+  const uint16_t* lcol;       // local column indices
+  const void* val;            // FP64, or FP32 (FLaunch::fp32)
+  const double* dinv;         // part order
+  const double* b;            // right-hand side, original order
+  double* x;                  // initial guess in, solution out; original order
+  double* bp;                 // b in part order
+  double* xp;                 // x in part order
+  double* p;
+  double* r[2];
+  double* s[2];
+  double* w[2];
+  double* part[2];            // [KP][nparts] SoA partials by parity
+  double* part_s;             // start partials [r.r, b.b]
+  KState* st;
+  int32_t maxit, pad;
+};
+
 // Row-owner assembly inputs (see mesh.hpp)
 struct RowAsm {
   int32_t nrows;
@@ -160,6 +192,31 @@ void bicg_spmv_only(hipStream_t s, const KLaunch& L);                 // v = A p
 void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par);    // s, shat
 void bicg_spmv_t_only(hipStream_t s, const KLaunch& L);               // t = A shat
 void bicg_update_x_only(hipStream_t s, const KLaunch& L, int par);    // x, r, p, phat
+
+// One-kernel-per-iteration Jacobi-CG (kernels_fcg.hip) over ngroups FGroups
+// with the same rows per thread ept (parts have at most KBS * ept rows);
+// bmap maps blocks to (group, part); lds = dynamic LDS bytes (8 per local
+// row of the largest part, own + halo).
+struct FLaunch {
+  const FGroup* groups;
+  int ngroups;
+  int ept;           // 1, 2, 4 or 8
+  int fp32;
+  const int2* bmap;
+  int nblocks;
+  size_t lds;
+};
+// Mode 0: x and b to part order, r = b - A x, w = A D^{-1} r, status decision.
+// Mode 1 (systems PENDING or RESTART): the same from the current iterate.
+void fcg_start(hipStream_t s, const FLaunch& F, int mode, int par, int launched);
+void fcg_iter(hipStream_t s, const FLaunch& F, int par);
+// x (original order) := the part-order iterate, or 0 for b == 0 systems
+void fcg_finish(hipStream_t s, const FLaunch& F);
+// part-order copies of a matrix's values and of its Jacobi diagonal
+void fcg_gather_values(hipStream_t s, bool fp32, int64_t nent, const int32_t* src,
+                       const void* val, void* out);
+void fcg_gather_dinv(hipStream_t s, int64_t n, const int32_t* perm, const double* dinv,
+                     double* out);
 
 // Fields and right-hand sides (kernels_fields.hip)
 void eval_velocity(hipStream_t s, int dim, const Builtin& bi, const double* x, int64_t n,

@@ -9,6 +9,8 @@
 // so the scatter needs no atomics and is deterministic.
 #pragma once
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 namespace ipcs {
@@ -45,6 +47,27 @@ struct SlotMap {
   std::vector<uint8_t> slot;
 };
 
+// Rows of a square pattern partitioned into parts of at most rows_max rows
+// (compact patches of DOFs), renumbered so that each part is contiguous
+// ("part order": perm[i] is the original row of part-order row i), with a
+// SELL-64 layout per part whose column indices are local to the part:
+// 0 .. own-1 for its own rows, own + q for its q-th halo column (a column
+// referenced by its rows and owned by another part, in part order). src maps
+// each entry to the pattern's SELL-64 value index (-1: padding, value 0).
+struct PartSell {
+  int64_t n = 0, nent = 0;
+  int rows_max = 0, nparts = 0, maxw = 0;
+  int lds_max = 0;                  // largest own + halo count of a part
+  std::vector<int32_t> perm;        // [n]
+  std::vector<int32_t> part_ptr;    // [nparts+1] part-order rows
+  std::vector<int32_t> halo_ptr;    // [nparts+1]
+  std::vector<int32_t> halo;        // part-order rows
+  std::vector<int32_t> slice_ptr;   // [nparts+1] first slice of each part
+  std::vector<int32_t> sptr;        // [nslices+1] entry offsets
+  std::vector<uint16_t> lcol;       // [nent]
+  std::vector<int32_t> src;         // [nent]
+};
+
 struct Mesh {
   int dim = 0;
   int64_t nv = 0, nc = 0, ne = 0;
@@ -68,7 +91,17 @@ struct Mesh {
 
   const Pattern& pattern(int which) const;
   const Sell& sell(int which) const;
+  // partition of the P1-P1 pattern by the P1 DOF (vertex) coordinates, built
+  // on first use for each part size and kept with the mesh
+  std::shared_ptr<const PartSell> parts11(int rows_max) const;
+
+ private:
+  mutable std::mutex parts_mu;
+  mutable std::vector<std::shared_ptr<const PartSell>> parts_cache;
 };
+
+std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, const double* X,
+                                            int dim, int rows_max);
 
 // Builders. All throw ipcs::Error on invalid input.
 Mesh* build_unit_square(int nx, int ny);

@@ -45,6 +45,17 @@ void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap) {
       if (b < nblk[g]) bmap.push_back(make_int2((int)g, b));
 }
 
+void xcd_order(std::vector<int2>& bmap) {
+  constexpr int kXcd = 8;
+  const int n = (int)bmap.size(), q = n / kXcd, rem = n % kXcd;
+  std::vector<int2> out(n);
+  for (int b = 0; b < n; ++b) {
+    const int x = b % kXcd;
+    out[b] = bmap[x * q + std::min(x, rem) + b / kXcd];
+  }
+  bmap.swap(out);
+}
+
 // LDS needed by the assembly kernel with bs rows per block: the largest
 // number of SELL entries of the bs/64 slices a block owns, times the value size.
 static AsmCfg asm_cfg(const Sell& S, int vbytes) {
@@ -119,8 +130,11 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
     for (int g = 0; g < S.L.ngroups; ++g)
       for (int j = 0; j < S.h_groups[g].nsys; ++j) f(hs[g * GMAX + j]);
   };
+  const bool fused = m == KMethod::PCG && S.fused;
   auto iterate = [&](int par) {
-    if (m == KMethod::PCG) {
+    if (fused) {
+      T.run(s, S.kid[0], [&] { fcg_iter(s, S.F, par); });
+    } else if (m == KMethod::PCG) {
       T.run(s, S.kid[0], [&] { pcg_spmv_only(s, S.L); });
       T.run(s, S.kid[1], [&] { pcg_update_only(s, S.L, par); });
     } else {
@@ -132,7 +146,8 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
   };
   int par = 0, launched = 0;
   auto start = [&](int mode) {
-    if (m == KMethod::PCG) pcg_start(s, S.L, mode, par, launched);
+    if (fused) fcg_start(s, S.F, mode, par, launched);
+    else if (m == KMethod::PCG) pcg_start(s, S.L, mode, par, launched);
     else bicg_start(s, S.L, mode, par, launched);
   };
   // groups with systems still iterating: the least remaining cap among them
@@ -191,7 +206,8 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
   int iters = 0;
   each([&](const KState& k) { iters = std::max(iters, k.it); });
   S.last_iters = iters;   // the poll schedule of the next solve of this set
-  ksys_finish(s, S.L);
+  if (fused) fcg_finish(s, S.F);
+  else ksys_finish(s, S.L);
   int rc = IPCS_OK;
   each([&](const KState& k) {
     const int c = status_to_code(k.status);
@@ -214,6 +230,40 @@ void Run::sizes_from_mesh() {
   ne21 = m.e21.nent;
   ne11 = m.e11.nent;
   ne12 = m.e12.nent;
+  choose_poisson_form();
+}
+
+// Largest own + halo row count of a part the fused Poisson CG keeps in LDS
+// (8 bytes each, under 64 KiB with the kernel's static reduction space).
+constexpr int kFcgLocalMax = 8000;
+// Default part size: about 2-3 parts per CU on the 2D and 3D workloads; the
+// block streams its own rows once and gathers its halo from neighbours that
+// the block map places on the same XCD.
+constexpr int kFcgRows = 384;
+
+// The pressure Poisson CG runs one kernel per iteration on a row partition of
+// Kp when its parts fit (LDS, partial-sum capacity); otherwise two kernels.
+void Run::choose_poisson_form() {
+  pp.reset();
+  fcg_ept = 0;
+  const int req = prm.poisson_part_rows;
+  if (req < 0) return;
+  auto q = mesh->parts11(req > 0 ? req : kFcgRows);
+  int biggest = 0;
+  for (int p = 0; p < q->nparts; ++p)
+    biggest = std::max(biggest, q->part_ptr[p + 1] - q->part_ptr[p]);
+  const bool fits = q->lds_max <= kFcgLocalMax && q->nparts <= KNB_MAX;
+  if (!fits) {
+    if (req > 0)
+      fail(IPCS_E_CAPACITY, "the Poisson partition's parts reference more rows than fit in LDS");
+    return;
+  }
+  pp = q;
+  for (int e : {1, 2, 4, 8})
+    if (KBS * e >= biggest) {
+      fcg_ept = e;
+      break;
+    }
 }
 
 void Run::layout(Carver& c) {
@@ -291,6 +341,27 @@ void Run::layout(Carver& c) {
     bmap_v[gi] = c.take<int2>(bv);
   }
   poll = c.take<KState>(3 * GMAX);
+  if (pp) {
+    const PartSell& q = *pp;
+    f_perm = c.take<int32_t>(n1);
+    f_part_ptr = c.take<int32_t>(q.nparts + 1);
+    f_halo_ptr = c.take<int32_t>(q.nparts + 1);
+    f_halo = c.take<int32_t>(std::max<int64_t>((int64_t)q.halo.size(), 1));
+    f_slice_ptr = c.take<int32_t>(q.nparts + 1);
+    f_sptr = c.take<int32_t>((int64_t)q.sptr.size());
+    f_src = c.take<int32_t>(std::max<int64_t>(q.nent, 1));
+    f_lcol = c.take<uint16_t>(std::max<int64_t>(q.nent, 1));
+    f_val = c.take<char>(std::max<int64_t>(q.nent, 1) * vsz);
+    f_dinv = c.take<double>(n1);
+    f_bp = c.take<double>(n1);
+    f_xp = c.take<double>(n1);
+    f_p = c.take<double>(n1);
+    f_vec = c.take<double>(6 * n1);
+    for (int k = 0; k < 2; ++k) f_part[k] = c.take<double>((int64_t)KP * q.nparts);
+    f_part_s = c.take<double>((int64_t)KP * q.nparts);
+    f_bmap = c.take<int2>(q.nparts);
+    fgroup = c.take<FGroup>(1);
+  }
   spart = c.take<double>(8192 * 2);
   scnt = c.take<uint32_t>(4);
   scal = c.take<double>(8);
@@ -341,6 +412,23 @@ void Run::upload_mesh() {
   up(stream, lift_ptr, m.lift_ptr);
   up(stream, lift_slot, m.lift_slot);
   up(stream, lift_col, m.lift_col);
+  if (pp) {
+    const PartSell& q = *pp;
+    up(stream, f_perm, q.perm);
+    up(stream, f_part_ptr, q.part_ptr);
+    up(stream, f_halo_ptr, q.halo_ptr);
+    up(stream, f_halo, q.halo);
+    up(stream, f_slice_ptr, q.slice_ptr);
+    up(stream, f_sptr, q.sptr);
+    up(stream, f_src, q.src);
+    up(stream, f_lcol, q.lcol);
+    std::vector<int2> bm(q.nparts);
+    for (int p = 0; p < q.nparts; ++p) bm[p] = make_int2(0, p);
+    xcd_order(bm);
+    up(stream, f_bmap, bm);
+    // bm is a stack copy: the transfer must end before it goes away
+    HIP_OK(hipStreamSynchronize(stream));
+  }
 }
 
 void Run::assemble_constant() {
@@ -363,6 +451,10 @@ void Run::assemble_constant() {
   if (mixed) round_to_f32(stream, ne11, Kp64, static_cast<float*>(Kp));
   asm_lumped_p1(dim, stream, a11, w);
   inv_diagonal(stream, mixed, n1, sp11, rp11, col11, Kp, dinvKp);
+  if (pp) {
+    fcg_gather_values(stream, mixed, pp->nent, f_src, Kp, f_val);
+    fcg_gather_dinv(stream, n1, f_perm, dinvKp, f_dinv);
+  }
   form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
   lift_values(stream, mixed, nlift, lift_slot, M, nullptr, 1.0, 0.0, liftM);
 }
@@ -460,11 +552,47 @@ void Run::setup_solvers() {
   mk(set_mom, 0);
   mk(set_p, 1);
   mk(set_corr, 2);
+  set_p.fused = pp != nullptr;
+  if (pp) {
+    const KVecs& V = grp[1].v[0];
+    FGroup f;
+    std::memset(&f, 0, sizeof(f));
+    f.n = (int32_t)n1;
+    f.nparts = pp->nparts;
+    f.perm = f_perm;
+    f.part_ptr = f_part_ptr;
+    f.halo_ptr = f_halo_ptr;
+    f.halo = f_halo;
+    f.slice_ptr = f_slice_ptr;
+    f.sptr = f_sptr;
+    f.lcol = f_lcol;
+    f.val = f_val;
+    f.dinv = f_dinv;
+    f.b = V.b;
+    f.x = V.x;
+    f.bp = f_bp;
+    f.xp = f_xp;
+    f.p = f_p;
+    for (int k = 0; k < 2; ++k) {
+      f.r[k] = f_vec + (size_t)k * n1;
+      f.s[k] = f_vec + (size_t)(2 + k) * n1;
+      f.w[k] = f_vec + (size_t)(4 + k) * n1;
+      f.part[k] = f_part[k];
+    }
+    f.part_s = f_part_s;
+    f.st = V.st;
+    f.maxit = prm.maxit;
+    set_p.h_fgroups = {f};
+    HIP_OK(hipMemcpyAsync(fgroup, set_p.h_fgroups.data(), sizeof(f), hipMemcpyHostToDevice,
+                          stream));
+    set_p.F = FLaunch{fgroup, 1, fcg_ept, mixed ? 1 : 0, f_bmap, pp->nparts,
+                      sizeof(double) * (size_t)pp->lds_max};
+  }
   const int kid_mom[4] = {IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_BICG_UPDATE_S,
                           IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_X};
   for (int k = 0; k < 4; ++k) set_mom.kid[k] = kid_mom[k];
-  set_p.kid[0] = IPCS_KERNEL_PCG_SPMV_P;
-  set_p.kid[1] = IPCS_KERNEL_PCG_UPDATE_P;
+  set_p.kid[0] = pp ? IPCS_KERNEL_PCG_FUSED_P : IPCS_KERNEL_PCG_SPMV_P;
+  set_p.kid[1] = pp ? -1 : IPCS_KERNEL_PCG_UPDATE_P;
   set_corr.kid[0] = IPCS_KERNEL_PCG_SPMV_M;
   set_corr.kid[1] = IPCS_KERNEL_PCG_UPDATE_M;
   HIP_OK(hipStreamSynchronize(stream));
@@ -581,6 +709,7 @@ void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_s
     } else if (which == 2) {
       st->it_p = k.it;
       st->res_p = res;
+      st->checks_p = k.nchecks;
     } else {
       st->it_corr[c] = k.it;
       st->res_corr[c] = res;
@@ -756,8 +885,18 @@ double Run::profile_kernel(int kernel, int nlaunch) {
                    kernel == IPCS_KERNEL_BICG_UPDATE_S || kernel == IPCS_KERNEL_BICG_UPDATE_X;
   const bool corr = kernel == IPCS_KERNEL_PCG_SPMV_M || kernel == IPCS_KERNEL_PCG_UPDATE_M;
   const KSet* S = mom ? &set_mom : corr ? &set_corr : kernel == IPCS_KERNEL_ASM_CONV ? nullptr : &set_p;
+  const bool fused = kernel == IPCS_KERNEL_PCG_FUSED_P;
+  if (fused != (S == &set_p && set_p.fused) && S == &set_p)
+    fail(IPCS_E_INVALID, fused ? "this run's Poisson CG is not the fused form"
+                               : "this run's Poisson CG is the fused form");
+  // the solver states (tolerances, zero level) are restored after timing
+  std::vector<KState> saved;
   if (S) {
     const KGroup& g = S->h_groups[0];
+    saved.resize(g.nsys);
+    for (int j = 0; j < g.nsys; ++j)
+      HIP_OK(hipMemcpyAsync(&saved[j], g.v[j].st, sizeof(KState), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
     for (int j = 0; j < g.nsys; ++j) {
       KState& k = pinned[j];
       std::memset(&k, 0, sizeof(k));
@@ -773,6 +912,14 @@ double Run::profile_kernel(int kernel, int nlaunch) {
     // elsewhere), chosen so that every timed launch takes the full iteration
     // path: CG gamma = r.r = 1, delta = 2 (alpha = beta = 1); BiCGStab
     // rhat.v = 2, r.r = 1, t.s = t.t = rhat.s = 2, rhat.t = 1 (omega = 1, rho' = 1)
+    if (fused) {
+      // fused CG partials [gamma, r.r, delta] = [1, 1, 2] in part 0
+      std::vector<double> pf((size_t)KP * set_p.F.nblocks, 0.0);
+      for (int k = 0; k < 3; ++k) pf[(size_t)k * set_p.F.nblocks] = k == 2 ? 2.0 : 1.0;
+      HIP_OK(hipMemcpyAsync(f_part[0], pf.data(), sizeof(double) * pf.size(),
+                            hipMemcpyHostToDevice, stream));
+      HIP_OK(hipStreamSynchronize(stream));
+    }
     std::vector<double> pm((size_t)g.nblk_m * GMAX * KP, 0.0), pv((size_t)g.nblk_v * GMAX * KP, 0.0);
     for (int j = 0; j < g.nsys; ++j)
       for (int k = 0; k < KP; ++k) {
@@ -802,6 +949,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       case IPCS_KERNEL_BICG_UPDATE_S: bicg_update_s_only(stream, set_mom.L, 0); break;
       case IPCS_KERNEL_BICG_UPDATE_X: bicg_update_x_only(stream, set_mom.L, 0); break;
       case IPCS_KERNEL_PCG_UPDATE_M: pcg_update_only(stream, set_corr.L, 0); break;
+      case IPCS_KERNEL_PCG_FUSED_P: fcg_iter(stream, set_p.F, 0); break;
       default: fail(IPCS_E_INVALID, "unknown kernel id");
     }
   };
@@ -813,16 +961,20 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
   if (S) {
-    std::vector<KState> hs;
     gather_states(stream, S->L, S->d_poll);
     HIP_OK(hipMemcpyAsync(pinned, S->d_poll, sizeof(KState) * GMAX, hipMemcpyDeviceToHost,
                           stream));
     HIP_OK(hipStreamSynchronize(stream));
-    for (int j = 0; j < S->h_groups[0].nsys; ++j)
-      if (pinned[j].status != KS_RUN)
+    const KGroup& g = S->h_groups[0];
+    std::vector<KState> after(pinned, pinned + g.nsys);
+    for (int j = 0; j < g.nsys; ++j)
+      HIP_OK(hipMemcpyAsync(g.v[j].st, &saved[j], sizeof(KState), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    for (int j = 0; j < g.nsys; ++j)
+      if (after[j].status != KS_RUN)
       {
         char msg[512];
-        const KState& k = pinned[j];
+        const KState& k = after[j];
         std::snprintf(msg, sizeof msg,
                       "profiled kernel %d left system %d in status %d (rr %.3e bb %.3e tol2 %.3e "
                       "it %d); timing discarded",
@@ -867,7 +1019,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
   double host[4];
   double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0, last_tol = 1.0, op_limit = 0.0;
   double floor_in = 0.0;   // raised after an inner breakdown
-  int inner_total = 0, outer = 0, rc = IPCS_OK;
+  int inner_total = 0, checks_total = 0, outer = 0, rc = IPCS_OK;
   for (;; ++outer) {
     residual_projected(stream, n1, sp11, col11, Kp64, dP, rP, rIR, spart, spart + 8192, tot,
                        scal + 5);
@@ -906,6 +1058,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
     rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned, timer);
     inner_total += hs[0].it;
+    checks_total += hs[0].nchecks;
     if (rc == IPCS_E_BREAKDOWN) {
       // Kp rounded to FP32 is singular only up to rounding and can be
       // marginally indefinite: the pass ends at its last iterate (x is not
@@ -919,6 +1072,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
   if (op_limit > 0.0) ir_c = op_limit;   // kept while the operator keeps limiting passes
   if (st) {
     st->it_p = inner_total;
+    st->checks_p = checks_total;
     st->res_p = rel;
     st->ir_outer = outer;
   }

@@ -65,10 +65,16 @@ struct KTimer {
 // Host view of a set of Krylov groups solved by the same launches.
 struct KSet {
   KLaunch L{};
+  // pressure Poisson CG in one kernel per iteration (kernels_fcg.hip): the
+  // launch uses F; L still serves status polling, caps and tolerances
+  bool fused = false;
+  FLaunch F{};
+  std::vector<FGroup> h_fgroups;
   std::vector<KGroup> h_groups;
   KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
   int last_iters = 0;          // iterations the previous solve took (poll schedule)
-  // kernel ids for timing: PCG {spmv, update}, BiCGStab {v, s, t, x}; -1: none
+  // kernel ids for timing: PCG {spmv, update} (fused: {iteration}),
+  // BiCGStab {v, s, t, x}; -1: none
   int kid[4] = {-1, -1, -1, -1};
 };
 
@@ -88,6 +94,11 @@ int nblk_m_for(int64_t n, int ns);
 int nblk_v_for(int64_t n, int ns);
 // (group, block) map interleaving the groups block by block
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
+// The blocks of a launch are dealt to the 8 XCDs in turn (block b runs on XCD
+// b % 8, each XCD with its own L2). Reorders a block map so that each XCD runs
+// one contiguous range of its entries: neighbouring parts of a row partition
+// (which share halo rows) then share an L2.
+void xcd_order(std::vector<int2>& bmap);
 
 struct AsmCfg {
   int bs = 256;
@@ -139,6 +150,19 @@ struct Run {
   int2* bmap_m[3] = {};
   int2* bmap_v[3] = {};
   KState* poll = nullptr;     // [3 * GMAX]
+  // pressure Poisson CG in one kernel per iteration on a row partition of Kp
+  // (null pp: the two-kernel CG of the velocity solves)
+  std::shared_ptr<const PartSell> pp;
+  int fcg_ept = 0;
+  int32_t *f_perm = nullptr, *f_part_ptr = nullptr, *f_halo_ptr = nullptr, *f_halo = nullptr,
+          *f_slice_ptr = nullptr, *f_sptr = nullptr, *f_src = nullptr;
+  uint16_t* f_lcol = nullptr;
+  void* f_val = nullptr;      // Kp (inner CG values) in the partition's layout
+  double *f_dinv = nullptr, *f_bp = nullptr, *f_xp = nullptr, *f_p = nullptr;
+  double* f_vec = nullptr;    // r[2], s[2], w[2]
+  double *f_part[2] = {}, *f_part_s = nullptr;
+  int2* f_bmap = nullptr;
+  FGroup* fgroup = nullptr;
   double* spart = nullptr;    // scratch partials for one-off reductions [8192*2]
   uint32_t* scnt = nullptr;
   double* scal = nullptr;     // [8] device scalars: 0 mean(r), 1 mean(dP), 2 mean(P)
@@ -165,6 +189,7 @@ struct Run {
 
   ~Run();
   void sizes_from_mesh();
+  void choose_poisson_form();
   void layout(Carver& c);
   void create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, int64_t bytes,
               hipStream_t s);

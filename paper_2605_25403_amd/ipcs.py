@@ -40,7 +40,8 @@ IPCS_KERNEL_PCG_SPMV_P, IPCS_KERNEL_PCG_UPDATE_P, IPCS_KERNEL_ASM_CONV = 0, 1, 2
 IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_PCG_SPMV_M = 3, 4
 IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_S, IPCS_KERNEL_BICG_UPDATE_X = 5, 6, 7
 IPCS_KERNEL_PCG_UPDATE_M = 8
-IPCS_NKERNEL = 9
+IPCS_KERNEL_PCG_FUSED_P = 9
+IPCS_NKERNEL = 10
 
 
 class IpcsError(RuntimeError):
@@ -59,12 +60,13 @@ class ipcs_params(C.Structure):
                 ("precision", C.c_int32), ("convection", C.c_int32),
                 ("tol_mom", C.c_double), ("tol_p", C.c_double), ("tol_corr", C.c_double),
                 ("tol_ir", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
-                ("callbacks", C.c_int32), ("reserved", C.c_int32)]
+                ("callbacks", C.c_int32), ("poisson_part_rows", C.c_int32)]
 
 
 class ipcs_step_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("it_mom", C.c_int32 * 3), ("it_p", C.c_int32),
                 ("it_corr", C.c_int32 * 3), ("ir_outer", C.c_int32), ("failed_solve", C.c_int32),
+                ("checks_p", C.c_int32), ("reserved", C.c_int32),
                 ("res_mom", C.c_double * 3), ("res_p", C.c_double), ("res_corr", C.c_double * 3),
                 ("t", C.c_double), ("ms_asm", C.c_float), ("ms_mom", C.c_float),
                 ("ms_p", C.c_float), ("ms_corr", C.c_float)]
@@ -72,6 +74,7 @@ class ipcs_step_stats(C.Structure):
     def as_dict(self):
         return {"status": self.status, "it_mom": list(self.it_mom), "it_p": self.it_p,
                 "it_corr": list(self.it_corr), "ir_outer": self.ir_outer,
+                "checks_p": self.checks_p,
                 "res_mom": list(self.res_mom), "res_p": self.res_p,
                 "res_corr": list(self.res_corr), "t": self.t,
                 "ms": [self.ms_asm, self.ms_mom, self.ms_p, self.ms_corr]}
@@ -91,6 +94,7 @@ _SIGS = {
     "ipcs_mesh_cell_dofs": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
     "ipcs_mesh_boundary": (C.c_int, [_P, _P, C.c_int64]),
     "ipcs_mesh_pattern": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
+    "ipcs_mesh_p1_partition": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64)] + [_P] * 8),
     "ipcs_quadrature_rule": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), _P, _P, C.c_int64]),
     "ipcs_mesh_destroy": (None, [_P]),
     "ipcs_params_default": (None, [C.POINTER(ipcs_params)]),
@@ -113,6 +117,8 @@ _SIGS = {
     "ipcs_profile_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ipcs_kernel_timing": (C.c_int, [_P, C.c_uint32]),
     "ipcs_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "ipcs_poisson_partition": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "ipcs_run_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -195,6 +201,27 @@ def ipcs_mesh_pattern(m, which):
     col = np.empty(c.nnz[which], dtype=np.int32)
     _check(lib.ipcs_mesh_pattern(m, which, _ptr(rp), rp.size, _ptr(col), col.size))
     return rp, col
+
+
+def ipcs_mesh_p1_partition(m, rows_max):
+    """The P1-P1 row partition for parts of at most rows_max rows: dict of
+    numpy arrays perm, part_ptr, halo_ptr, halo, slice_ptr, sptr, lcol, src and
+    the largest own + halo count lds_rows."""
+    sz = (C.c_int64 * 5)()
+    _check(lib.ipcs_mesh_p1_partition(m, rows_max, sz, *([None] * 8)))
+    nparts, nhalo, nsl, nent, lds = (int(v) for v in sz)
+    c = ipcs_mesh_counts(m)
+    out = {"perm": np.empty(c.n1, np.int32), "part_ptr": np.empty(nparts + 1, np.int32),
+           "halo_ptr": np.empty(nparts + 1, np.int32), "halo": np.empty(max(nhalo, 1), np.int32),
+           "slice_ptr": np.empty(nparts + 1, np.int32), "sptr": np.empty(nsl + 1, np.int32),
+           "lcol": np.empty(max(nent, 1), np.uint16), "src": np.empty(max(nent, 1), np.int32)}
+    keys = ("perm", "part_ptr", "halo_ptr", "halo", "slice_ptr", "sptr", "lcol", "src")
+    _check(lib.ipcs_mesh_p1_partition(m, rows_max, sz, *[_ptr(out[k]) for k in keys]))
+    out["halo"] = out["halo"][:nhalo]
+    out["lcol"] = out["lcol"][:nent]
+    out["src"] = out["src"][:nent]
+    out["lds_rows"] = lds
+    return out
 
 
 def ipcs_quadrature_rule(dim):
@@ -319,6 +346,15 @@ def ipcs_kernel_times(r):
     return list(ms), list(cnt)
 
 
+def ipcs_poisson_partition(r):
+    """dict(rows_max, nparts, halo_rows, lds_rows) of the run's Poisson CG form
+    (rows_max 0: two kernels per iteration)."""
+    a, b, d = C.c_int32(), C.c_int32(), C.c_int32()
+    h = C.c_int64()
+    _check(lib.ipcs_poisson_partition(r, C.byref(a), C.byref(b), C.byref(h), C.byref(d)))
+    return {"rows_max": a.value, "nparts": b.value, "halo_rows": h.value, "lds_rows": d.value}
+
+
 def ipcs_run_destroy(r):
     lib.ipcs_run_destroy(r)
 
@@ -417,6 +453,9 @@ class Run:
 
     def kernel_times(self):
         return ipcs_kernel_times(self.h)
+
+    def poisson_partition(self):
+        return ipcs_poisson_partition(self.h)
 
     def matrix(self, which):
         """(rowptr, col, val) of a device matrix, as a scipy CSR matrix."""
