@@ -55,7 +55,10 @@ enum {
   IPCS_E_INVALID = -1,        /* bad argument, handle or buffer size          */
   IPCS_E_NOMEM = -2,          /* workspace too small / host allocation failed */
   IPCS_E_DEVICE = -3,         /* HIP runtime error                            */
-  IPCS_E_NOT_CONVERGED = -4,  /* a Krylov solve hit maxit                     */
+  IPCS_E_NOT_CONVERGED = -4,  /* a Krylov solve hit maxit, or its tolerance is
+                               * out of reach: three restarts in a row left
+                               * the true residual b - A x above 90% of its
+                               * least value so far                           */
   IPCS_E_BREAKDOWN = -5,      /* unrecoverable Krylov breakdown               */
   IPCS_E_NONFINITE = -6,      /* NaN/Inf met in a solve                       */
   IPCS_E_STATE = -7,          /* call not valid in the run's current state    */

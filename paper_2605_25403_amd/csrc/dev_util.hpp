@@ -13,6 +13,19 @@
 
 namespace ipcs {
 
+// Global-memory view of a generic pointer. Pointers read from the group
+// structs are generic, and loads through them compile to flat instructions,
+// which count against both the vector and the scalar wait counters, so every
+// wait for a scalar load drains them too. Through this view they are global
+// loads and stores, counted by the vector counter only: a kernel can issue
+// all of its independent loads before its first wait.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+  return (gptr<T>)p;
+}
+
 // Sum over an aligned group of G lanes (G a power of two <= 64); every lane
 // of the group receives the result.
 template <int G>
@@ -88,23 +101,32 @@ __device__ __forceinline__ size_t part_index(int j, int k, int nb, int b) {
 
 // This thread's share of the partial sums of a producer kernel with nb
 // blocks (nb <= KBS * KPART_Q): blocks tid, tid + KBS, ... summed in order.
-// Every load is issued before the first use, so the caller can issue its own
-// independent loads first and let all of them overlap. Value k of system j
-// lands in v[j*K + k]; block_sum_t then gives the totals.
+// Records are loaded four per thread at a time from always-valid (clamped)
+// addresses before any of them is used, so the loads of a chunk overlap each
+// other and the caller's own independent loads; records past nb add zero.
+// Value k of system j lands in v[j*K + k]; block_sum_t then gives the totals.
 template <int NS, int K>
 __device__ __forceinline__ void load_partials(const double* part, int nb, double* v) {
+  constexpr int QC = 4;
 #pragma unroll
   for (int n = 0; n < NS * K; ++n) v[n] = 0.0;
+  const gptr<const double> P = G(part);
+  for (int q0 = 0; q0 * KBS < nb; q0 += QC) {
+    double x[QC][NS * K];
 #pragma unroll
-  for (int q = 0; q < KPART_Q; ++q) {
-    const int b = (int)threadIdx.x + q * KBS;
-    if (q * KBS < nb) {
-      const bool ok = b < nb;
+    for (int q = 0; q < QC; ++q) {
+      const int b = (int)threadIdx.x + (q0 + q) * KBS;
+      const int bc = b < nb ? b : nb - 1;
 #pragma unroll
       for (int j = 0; j < NS; ++j)
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-          v[j * K + k] += ok ? part[part_index(j, k, nb, ok ? b : 0)] : 0.0;
+        for (int k = 0; k < K; ++k) x[q][j * K + k] = P[part_index(j, k, nb, bc)];
+    }
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const bool ok = (int)threadIdx.x + (q0 + q) * KBS < nb;
+#pragma unroll
+      for (int n = 0; n < NS * K; ++n) v[n] += ok ? x[q][n] : 0.0;
     }
   }
 }
@@ -123,7 +145,7 @@ __device__ __forceinline__ void store_partials(double* acc, double* part, int nb
     double val = 0.0;
 #pragma unroll
     for (int q = 0; q < NS * K; ++q) val = (q == (int)threadIdx.x) ? v[q] : val;
-    part[part_index(j, k, nb, lb)] = val;
+    G(part)[part_index(j, k, nb, lb)] = val;
   }
 }
 

@@ -26,8 +26,12 @@ enum KStatus : int32_t {
   KS_RESTART = 4,    // BiCGStab breakdown: restart from the current x
   KS_MAXIT = -4,
   KS_BREAKDOWN = -5,
-  KS_NONFINITE = -6
+  KS_NONFINITE = -6,
+  KS_STALL = -7      // restarts stopped lowering the true residual: tol out of reach
 };
+// Restarts in a row whose true residual is not 10% below the best one so far
+// after which a solve stops as out of reach (KS_STALL).
+constexpr int KSTALL_CHECKS = 3;
 
 // Scalars of one Krylov system. Iteration scalars are double-buffered by the
 // launch parity par the host passes: a kernel of parity par reads slot par^1
@@ -43,7 +47,9 @@ struct KState {
   double omega;               // BiCGStab
   double tol2;                // tol^2
   double zero2;               // ||b||^2 at or below this is treated as b = 0 (0: none)
-  int32_t status, it, nchecks, pad;
+  double rr_best;             // least ||b - A x||^2 at a start or check
+  int32_t status, it, nchecks;
+  int32_t nstall;             // checks in a row without a 10% gain on rr_best
 };
 
 // Vectors of one system (FP64).

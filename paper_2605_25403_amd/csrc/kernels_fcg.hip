@@ -188,6 +188,15 @@ __global__ void __launch_bounds__(KBS) k_fcg_decide(const FGroup* groups, int mo
   else if (!finite(rr)) nst = KS_NONFINITE;
   else if (rr <= st->tol2 * bb) nst = KS_DONE;
   else if (launched >= g.maxit) nst = KS_MAXIT;
+  // true residuals that stop falling: the tolerance is below the
+  // attainable accuracy
+  if (mode == 0 || rr <= 0.81 * st->rr_best) {
+    st->rr_best = rr;
+    st->nstall = 0;
+  } else {
+    st->nstall += 1;
+  }
+  if (nst == KS_RUN && st->nstall >= KSTALL_CHECKS) nst = KS_STALL;
   if (nst == KS_RUN) {
     st->sc[par ^ 1] = INFINITY;   // beta = gamma / inf = 0
     st->alpha[par ^ 1] = 1.0;
@@ -211,38 +220,46 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
   __shared__ double sh[(KBS / 64) * 3];
   const int s0 = g.slice_ptr[lb], s1 = g.slice_ptr[lb + 1];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const VT* val = static_cast<const VT*>(g.val);
+  const gptr<const VT> val = G(static_cast<const VT*>(g.val));
+  // index words: this wave's slices (waves past a part's last slice re-read
+  // it and discard the result) and the first halo row
   int sb[EPT], sw[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int sl = s0 + (KBS / 64) * e + wv;
-    const bool in = sl < s1;
-    sb[e] = in ? g.sptr[sl] + lane : 0;
-    sw[e] = in ? (g.sptr[sl + 1] - g.sptr[sl]) >> 6 : 0;
+    const int sl0 = s0 + (KBS / 64) * e + wv;
+    const int sl = sl0 < s1 ? sl0 : s1 - 1;
+    const int a = G(g.sptr)[sl], z = G(g.sptr)[sl + 1];
+    sb[e] = a + lane;
+    sw[e] = sl0 < s1 ? (z - a) >> 6 : 0;
   }
   const bool h_in = (int)threadIdx.x < nh;
-  const int c0 = h_in ? g.halo[h0 + threadIdx.x] : 0;
-
-  const KState* st = g.st;
+  // (the halo array always holds at least one word; threads past the halo
+  // use row 0 and discard what they read)
+  const int c0r = G(g.halo)[h_in ? h0 + (int)threadIdx.x : 0];
+  const int c0 = h_in ? c0r : 0;
+  // own rows (rows past the part's end read its first row and are discarded)
+  const gptr<const double> r0 = G((const double*)g.r[par]), s0v = G((const double*)g.s[par]),
+                           w0 = G((const double*)g.w[par]), dv = G(g.dinv);
+  double di[EPT], xi[EPT], ri[EPT], pi[EPT], si[EPT], wi[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int l = KBS * e + (int)threadIdx.x;
+    const int i = p0 + (l < own ? l : 0);
+    di[e] = dv[i];
+    xi[e] = G(g.xp)[i];
+    ri[e] = r0[i];
+    pi[e] = G(g.p)[i];
+    si[e] = s0v[i];
+    wi[e] = w0[i];
+  }
+  const gptr<const KState> st = G((const KState*)g.st);
   const int status = st->status;
   const double g_old = st->sc[par ^ 1], a_old = st->alpha[par ^ 1];
   const double lim = st->tol2 * st->bb;
   double t[3];
   load_partials<1, 3>(g.part[par], g.nparts, t);
-  const double *r0 = g.r[par], *s0v = g.s[par], *w0 = g.w[par];
-  double di[EPT], xi[EPT], ri[EPT], pi[EPT], si[EPT], wi[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int l = KBS * e + (int)threadIdx.x;
-    const bool in = l < own;
-    const int i = p0 + (in ? l : 0);
-    di[e] = in ? g.dinv[i] : 0.0;
-    xi[e] = in ? g.xp[i] : 0.0;
-    ri[e] = in ? r0[i] : 0.0;
-    pi[e] = in ? g.p[i] : 0.0;
-    si[e] = in ? s0v[i] : 0.0;
-    wi[e] = in ? w0[i] : 0.0;
-  }
+  // what depends on the index words: the first chunk of matrix entries and
+  // the first halo row's vectors, used after the reduction
   int mc[PF ? EPT : 1][8];
   double mv[PF ? EPT : 1][8];
   if constexpr (PF) {
@@ -251,16 +268,15 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int kk = q < sw[e] ? q : (sw[e] > 0 ? sw[e] - 1 : 0);
-        mc[e][q] = sw[e] > 0 ? g.lcol[sb[e] + 64 * kk] : 0;
-        mv[e][q] = sw[e] > 0 ? (double)val[sb[e] + 64 * kk] : 0.0;
+        mc[e][q] = G(g.lcol)[sb[e] + 64 * kk];
+        mv[e][q] = (double)val[sb[e] + 64 * kk];
       }
   }
-  const double hr = h_in ? r0[c0] : 0.0, hs = h_in ? s0v[c0] : 0.0;
-  const double hw = h_in ? w0[c0] : 0.0, hd = h_in ? g.dinv[c0] : 0.0;
+  const double hr = r0[c0], hs = s0v[c0], hw = w0[c0], hd = dv[c0];
 
   block_sum_t<KBS, 3>(t, sh);
   if (status != KS_RUN) return;
-  KState* stw = g.st;
+  const gptr<KState> stw = G(g.st);
   const bool lead = lb == 0 && threadIdx.x == 0;
   const double gam = t[0], rr = t[1], del = t[2];
   if (!(finite(gam) && finite(rr) && finite(del))) {
@@ -287,8 +303,7 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
     stw->rr = rr;
     stw->it += 1;
   }
-  double* r1 = g.r[par ^ 1];
-  double* s1v = g.s[par ^ 1];
+  const gptr<double> r1 = G(g.r[par ^ 1]), s1v = G(g.s[par ^ 1]);
   double rn[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -299,8 +314,8 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
     const double p = fma(beta, pi[e], di[e] * ri[e]);
     const double s = fma(beta, si[e], wi[e]);
     const double r = fma(-alpha, s, ri[e]);
-    g.xp[i] = fma(alpha, p, xi[e]);
-    g.p[i] = p;
+    G(g.xp)[i] = fma(alpha, p, xi[e]);
+    G(g.p)[i] = p;
     s1v[i] = s;
     r1[i] = r;
     rn[e] = r;
@@ -313,10 +328,10 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
     loc[own + threadIdx.x] = hd * r;
   }
   for (int q = threadIdx.x + KBS; q < nh; q += KBS) {
-    const int c = g.halo[h0 + q];
+    const int c = G(g.halo)[h0 + q];
     const double s = fma(beta, s0v[c], w0[c]);
     const double r = fma(-alpha, s, r0[c]);
-    loc[own + q] = g.dinv[c] * r;
+    loc[own + q] = dv[c] * r;
   }
   __syncthreads();
   double y[EPT];
@@ -336,14 +351,14 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int kk = k + q < w ? k + q : w - 1;
-        c[q] = g.lcol[sb[e] + 64 * kk];
+        c[q] = G(g.lcol)[sb[e] + 64 * kk];
         a[q] = (double)val[sb[e] + 64 * kk];
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) y[e] += k + q < w ? a[q] * loc[c[q]] : 0.0;
     }
   }
-  double* w1 = g.w[par ^ 1];
+  const gptr<double> w1 = G(g.w[par ^ 1]);
   double acc[3] = {};
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {

@@ -15,9 +15,11 @@
 // one set of partial sums per block, and every block of the next kernel
 // re-reduces all of them in a fixed order. Keeping blocks at 256 threads with several
 // entries per thread keeps the number of records small (at most KNB_MAX).
-// Each kernel issues its independent loads (state words, partial records,
-// vector entries) before its first wait; scalars that depend on the reduction
-// are applied last. Scalars never leave the device; the host polls status
+// Each kernel issues its independent loads (state words, vector entries, then
+// partial records) before its first wait: every load goes through a global
+// (not flat) pointer, from an always-valid address (rows past the end read row
+// 0 and are discarded), so no branch or wait separates them; scalars that
+// depend on the reduction are applied last. Scalars never leave the device; the host polls status
 // words only.
 //
 // PCG in the Chronopoulos-Gear form (one global reduction per iteration; the
@@ -63,12 +65,13 @@ namespace ipcs {
 // acc[j] = sum_k A(i, col_k) * gath(j, col_k), in FP64 whatever the stored
 // value type VT. The slice width is uniform in the wavefront; the last chunk
 // of eight re-reads entry w-1 and discards it.
-template <int NS, class VT, class G>
-__device__ __forceinline__ void sell_row(const KGroup& g, int i, G gath, double (&acc)[NS]) {
-  const VT* val = static_cast<const VT*>(g.val);
+template <int NS, class VT, class GF>
+__device__ __forceinline__ void sell_row(const KGroup& g, int i, GF gath, double (&acc)[NS]) {
+  const gptr<const VT> val = G(static_cast<const VT*>(g.val));
+  const gptr<const int32_t> col = G(g.col);
   const int s = i >> 6;
-  const int b0 = g.sptr[s];
-  const int w = (g.sptr[s + 1] - b0) >> 6;
+  const int b0 = G(g.sptr)[s];
+  const int w = (G(g.sptr)[s + 1] - b0) >> 6;
   const int base = b0 + (i & 63);
 #pragma unroll
   for (int j = 0; j < NS; ++j) acc[j] = 0.0;
@@ -78,7 +81,7 @@ __device__ __forceinline__ void sell_row(const KGroup& g, int i, G gath, double 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kk = k + q < w ? k + q : w - 1;
-      c[q] = g.col[base + 64 * kk];
+      c[q] = col[base + 64 * kk];
       a[q] = (double)val[base + 64 * kk];
     }
     double xv[NS][8];
@@ -98,6 +101,10 @@ __device__ __forceinline__ int row_of(int lb, int e) {
   return (lb * EPT + e) * KBS + (int)threadIdx.x;
 }
 
+// Rows past the end of the last block load row 0 (always valid) and discard
+// the result, so loads need no branch around them.
+__device__ __forceinline__ int row_clamp(int i, int n) { return i < n ? i : 0; }
+
 // ------------------------------------------------------------------ start / confirm
 // r = b - A x for the systems that start (mode 0: all) or are confirmed
 // (mode 1: PENDING or RESTART). PCG: u = D^{-1} r, p = s = 0. BiCGStab:
@@ -110,7 +117,7 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
   bool any = false;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const int st = g.v[j].st->status;
+    const int st = G(g.v[j].st)->status;
     act[j] = mode == 0 || st == KS_PENDING || st == KS_RESTART;
     any |= act[j];
   }
@@ -121,8 +128,8 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
       const int i = row_of<EPT>(lb, e);
       if (i >= g.n) continue;
       double ax[NS];
-      sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].x[c]; }, ax);
-      const double di = g.dinv[i];
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].x)[c]; }, ax);
+      const double di = G(g.dinv)[i];
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         if (!act[j]) continue;
@@ -184,6 +191,15 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
       else if (!finite(rr)) nst = KS_NONFINITE;
       else if (rr <= st->tol2 * bb) nst = KS_DONE;
       else if (launched >= g.maxit) nst = KS_MAXIT;
+      // true residuals that stop falling: the tolerance is below the
+      // attainable accuracy
+      if (mode == 0 || rr <= 0.81 * st->rr_best) {
+        st->rr_best = rr;
+        st->nstall = 0;
+      } else {
+        st->nstall += 1;
+      }
+      if (nst == KS_RUN && st->nstall >= KSTALL_CHECKS) nst = KS_STALL;
       st->status = nst;
       if (nst != KS_RUN) continue;
       if (PCG) {
@@ -215,20 +231,16 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
   bool any = false;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    run[j] = g.v[j].st->status == KS_RUN;
+    run[j] = G(g.v[j].st)->status == KS_RUN;
     any |= run[j];
   }
   double y[EPT][NS], ui[EPT][NS];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int i = row_of<EPT>(lb, e);
+    const int i = row_clamp(row_of<EPT>(lb, e), g.n);
+    sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].u)[c]; }, y[e]);
 #pragma unroll
-    for (int j = 0; j < NS; ++j) y[e][j] = ui[e][j] = 0.0;
-    if (i < g.n) {
-      sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].u[c]; }, y[e]);
-#pragma unroll
-      for (int j = 0; j < NS; ++j) ui[e][j] = g.v[j].u[i];
-    }
+    for (int j = 0; j < NS; ++j) ui[e][j] = G(g.v[j].u)[i];
   }
   if (!any) return;   // uniform: the states were written by an earlier kernel
   double acc[NS] = {};
@@ -239,7 +251,7 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       if (!run[j]) continue;
-      g.v[j].w[i] = y[e][j];
+      G(g.v[j].w)[i] = y[e][j];
       acc[j] += y[e][j] * ui[e][j];
     }
   }
@@ -256,11 +268,27 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
   double g_old[NS], a_old[NS], lim[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const KState* st = g.v[j].st;
+    const gptr<const KState> st = G((const KState*)g.v[j].st);
     status[j] = st->status;
     g_old[j] = st->sc[par ^ 1];
     a_old[j] = st->alpha[par ^ 1];
     lim[j] = st->tol2 * st->bb;
+  }
+  double di[EV], xi[EV][NS], ri[EV][NS], pi[EV][NS], si[EV][NS],
+      wi[EV][NS];
+#pragma unroll
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_clamp(row_of<EV>(lb, e), g.n);
+    di[e] = G(g.dinv)[i];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const KVecs& V = g.v[j];
+      xi[e][j] = G(V.x)[i];
+      ri[e][j] = G(V.r)[i];
+      pi[e][j] = G(V.p)[i];
+      si[e][j] = G(V.s)[i];
+      wi[e][j] = G(V.w)[i];
+    }
   }
   double t[NS * 3];
   {
@@ -272,23 +300,6 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
       t[j * 3 + 0] = a[j * 2];
       t[j * 3 + 1] = a[j * 2 + 1];
       t[j * 3 + 2] = b[j];
-    }
-  }
-  double di[EV], xi[EV][NS], ri[EV][NS], pi[EV][NS], si[EV][NS],
-      wi[EV][NS];
-#pragma unroll
-  for (int e = 0; e < EV; ++e) {
-    const int i = row_of<EV>(lb, e);
-    const bool in = i < g.n;
-    di[e] = in ? g.dinv[i] : 0.0;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const KVecs& V = g.v[j];
-      xi[e][j] = in ? V.x[i] : 0.0;
-      ri[e][j] = in ? V.r[i] : 0.0;
-      pi[e][j] = in ? V.p[i] : 0.0;
-      si[e][j] = in ? V.s[i] : 0.0;
-      wi[e][j] = in ? V.w[i] : 0.0;
     }
   }
   block_sum_t<KBS, NS * 3>(t, sh);
@@ -347,11 +358,11 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
       const double x = xi[e][j] + al[j] * p;
       const double r = ri[e][j] - al[j] * s;
       const double u = di[e] * r;
-      V.x[i] = x;
-      V.r[i] = r;
-      V.p[i] = p;
-      V.s[i] = s;
-      V.u[i] = u;
+      G(V.x)[i] = x;
+      G(V.r)[i] = r;
+      G(V.p)[i] = p;
+      G(V.s)[i] = s;
+      G(V.u)[i] = u;
       acc[j * 2] += r * u;
       acc[j * 2 + 1] += r * r;
     }
@@ -371,25 +382,21 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
   bool any = false;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    run[j] = g.v[j].st->status == KS_RUN;
+    run[j] = G(g.v[j].st)->status == KS_RUN;
     any |= run[j];
   }
   double y[EPT][NS], rh[EPT][NS], si[EPT][NS];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int i = row_of<EPT>(lb, e);
+    const int i = row_clamp(row_of<EPT>(lb, e), g.n);
+    if (WHICH == 0)
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].phat)[c]; }, y[e]);
+    else
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].shat)[c]; }, y[e]);
 #pragma unroll
-    for (int j = 0; j < NS; ++j) y[e][j] = rh[e][j] = si[e][j] = 0.0;
-    if (i < g.n) {
-      if (WHICH == 0)
-        sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].phat[c]; }, y[e]);
-      else
-        sell_row<NS, VT>(g, i, [&](int j, int c) { return g.v[j].shat[c]; }, y[e]);
-#pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        rh[e][j] = g.v[j].u[i];
-        if (WHICH == 1) si[e][j] = g.v[j].s[i];
-      }
+    for (int j = 0; j < NS; ++j) {
+      rh[e][j] = G(g.v[j].u)[i];
+      si[e][j] = WHICH == 1 ? G(g.v[j].s)[i] : 0.0;
     }
   }
   if (!any) return;
@@ -403,10 +410,10 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
       if (!run[j]) continue;
       const double yv = y[e][j];
       if (WHICH == 0) {
-        g.v[j].w[i] = yv;
+        G(g.v[j].w)[i] = yv;
         acc[j * K] += rh[e][j] * yv;
       } else {
-        g.v[j].t[i] = yv;
+        G(g.v[j].t)[i] = yv;
         acc[j * K + 0] += yv * si[e][j];
         acc[j * K + 1] += yv * yv;
         acc[j * K + 2] += rh[e][j] * si[e][j];
@@ -426,10 +433,21 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
   double rho[NS], lim[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const KState* st = g.v[j].st;
+    const gptr<const KState> st = G((const KState*)g.v[j].st);
     status[j] = st->status;
     rho[j] = st->sc[par];
     lim[j] = st->tol2 * st->bb;
+  }
+  double di[EV], ri[EV][NS], vi[EV][NS];
+#pragma unroll
+  for (int e = 0; e < EV; ++e) {
+    const int i = row_clamp(row_of<EV>(lb, e), g.n);
+    di[e] = G(g.dinv)[i];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      ri[e][j] = G(g.v[j].r)[i];
+      vi[e][j] = G(g.v[j].w)[i];
+    }
   }
   double t[NS * 2];
   {
@@ -440,18 +458,6 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
     for (int j = 0; j < NS; ++j) {
       t[j * 2] = a[j];
       t[j * 2 + 1] = b[j];
-    }
-  }
-  double di[EV], ri[EV][NS], vi[EV][NS];
-#pragma unroll
-  for (int e = 0; e < EV; ++e) {
-    const int i = row_of<EV>(lb, e);
-    const bool in = i < g.n;
-    di[e] = in ? g.dinv[i] : 0.0;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      ri[e][j] = in ? g.v[j].r[i] : 0.0;
-      vi[e][j] = in ? g.v[j].w[i] : 0.0;
     }
   }
   block_sum_t<KBS, NS * 2>(t, sh);
@@ -502,8 +508,8 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
     for (int j = 0; j < NS; ++j) {
       if (!go[j]) continue;
       const double s = ri[e][j] - al[j] * vi[e][j];
-      g.v[j].s[i] = s;
-      g.v[j].shat[i] = di[e] * s;
+      G(g.v[j].s)[i] = s;
+      G(g.v[j].shat)[i] = di[e] * s;
     }
   }
 }
@@ -517,32 +523,31 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
   double rho[NS], alpha[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const KState* st = g.v[j].st;
+    const gptr<const KState> st = G((const KState*)g.v[j].st);
     status[j] = st->status;
     rho[j] = st->sc[par];
     alpha[j] = st->alpha[0];
   }
-  double t[NS * 4];
-  load_partials<NS, 4>(g.part_m, g.nblk_m, t);   // t.s, t.t, rhat.s, rhat.t
   double di[EV], xi[EV][NS], phi[EV][NS], shi[EV][NS], si[EV][NS],
       ti[EV][NS], pi[EV][NS], vi[EV][NS];
 #pragma unroll
   for (int e = 0; e < EV; ++e) {
-    const int i = row_of<EV>(lb, e);
-    const bool in = i < g.n;
-    di[e] = in ? g.dinv[i] : 0.0;
+    const int i = row_clamp(row_of<EV>(lb, e), g.n);
+    di[e] = G(g.dinv)[i];
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const KVecs& V = g.v[j];
-      xi[e][j] = in ? V.x[i] : 0.0;
-      phi[e][j] = in ? V.phat[i] : 0.0;
-      shi[e][j] = in ? V.shat[i] : 0.0;
-      si[e][j] = in ? V.s[i] : 0.0;
-      ti[e][j] = in ? V.t[i] : 0.0;
-      pi[e][j] = in ? V.p[i] : 0.0;
-      vi[e][j] = in ? V.w[i] : 0.0;
+      xi[e][j] = G(V.x)[i];
+      phi[e][j] = G(V.phat)[i];
+      shi[e][j] = G(V.shat)[i];
+      si[e][j] = G(V.s)[i];
+      ti[e][j] = G(V.t)[i];
+      pi[e][j] = G(V.p)[i];
+      vi[e][j] = G(V.w)[i];
     }
   }
+  double t[NS * 4];
+  load_partials<NS, 4>(g.part_m, g.nblk_m, t);   // t.s, t.t, rhat.s, rhat.t
   block_sum_t<KBS, NS * 4>(t, sh);
   const bool lead = lb == 0 && threadIdx.x == 0;
   bool go[NS], full[NS];
@@ -589,14 +594,14 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
     for (int j = 0; j < NS; ++j) {
       if (!go[j]) continue;
       const KVecs& V = g.v[j];
-      V.x[i] = xi[e][j] + alpha[j] * phi[e][j] + om[j] * shi[e][j];
+      G(V.x)[i] = xi[e][j] + alpha[j] * phi[e][j] + om[j] * shi[e][j];
       const double r = si[e][j] - om[j] * ti[e][j];
-      V.r[i] = r;
+      G(V.r)[i] = r;
       acc[j] += r * r;
       if (full[j]) {
         const double p = r + be[j] * (pi[e][j] - om[j] * vi[e][j]);
-        V.p[i] = p;
-        V.phat[i] = di[e] * p;
+        G(V.p)[i] = p;
+        G(V.phat)[i] = di[e] * p;
       }
     }
   }

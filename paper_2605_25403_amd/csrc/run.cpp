@@ -75,6 +75,7 @@ static AsmCfg asm_cfg(const Sell& S, int vbytes) {
 int status_to_code(int s) {
   switch (s) {
     case KS_MAXIT: return IPCS_E_NOT_CONVERGED;
+    case KS_STALL: return IPCS_E_NOT_CONVERGED;
     case KS_BREAKDOWN: return IPCS_E_BREAKDOWN;
     case KS_NONFINITE: return IPCS_E_NONFINITE;
   }

@@ -66,7 +66,7 @@ def admit(queue, now, active_count, active_bytes, footprint_of, max_slots, hbm_b
 
 class Server:
     def __init__(self, dim=2, precision=None, max_slots=64, hbm_budget=200 << 30, tol=1e-12,
-                 tol_ir=1e-10, stream=None):
+                 tol_ir=1e-10, stream=None, poisson_part_rows=0):
         import torch
         from paper_2605_25403_amd import ipcs as I
         if dim != 2:
@@ -75,6 +75,7 @@ class Server:
         self.precision = I.IPCS_MIXED if precision is None else precision
         self.max_slots, self.hbm_budget = max_slots, hbm_budget
         self.tol, self.tol_ir = tol, tol_ir
+        self.part_rows = poisson_part_rows
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self._meshes = {}
 
@@ -86,7 +87,7 @@ class Server:
     def params(self, req):
         return self.I.ipcs_params_default(nu=req.nu, dt=req.dt, precision=self.precision,
                                           tol_mom=self.tol, tol_p=self.tol, tol_corr=self.tol,
-                                          tol_ir=self.tol_ir)
+                                          tol_ir=self.tol_ir, poisson_part_rows=self.part_rows)
 
     def footprint(self, req):
         return self.I.ipcs_run_workspace_bytes(self.mesh(req.n).h, self.params(req))

@@ -134,3 +134,25 @@ def test_host_callbacks_match_builtin_data():
     b.advance(3)
     assert rel(b.velocity(), a.velocity()) <= 1e-12
     assert rel(b.pressure(), a.pressure()) <= 1e-10
+
+
+@pytest.mark.parametrize("rows", [0, -1])
+def test_unreachable_tolerance_stops_early(rows):
+    """A tolerance below what FP64 can attain: the solve ends with an error
+    long before maxit (20000) and the state stays at the last completed step.
+    Either the recursive residual gets there and three restarts in a row
+    bring the true residual no 10% below its best (NOT_CONVERGED), or the CG
+    scalars lose positivity at the rounding level first (BREAKDOWN)."""
+    torch, I = require_gpu()
+    print(f"unreachable tolerance (poisson_part_rows={rows})", flush=True)
+    r = tg_run(I, n=24, tol_p=1e-15, poisson_part_rows=rows)
+    U0 = r.velocity().copy()
+    with pytest.raises(I.IpcsError) as e:
+        r.advance(1)
+    assert e.value.code in (I.IPCS_E_NOT_CONVERGED, I.IPCS_E_BREAKDOWN)
+    st = e.value.stats[0]
+    print(e.value.code, st.checks_p, st.it_p, flush=True)
+    assert st.failed_solve == 2 and 0 < st.it_p < 5000, (st.checks_p, st.it_p)
+    if e.value.code == I.IPCS_E_NOT_CONVERGED:
+        assert st.checks_p >= 3
+    np.testing.assert_array_equal(r.velocity(), U0)
