@@ -138,7 +138,7 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
     sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
            "pcg_fused_p": r"k_fcg_iter<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
-           "asm_conv": r"OpConvExplicit"}[kernel]
+           "asm_conv": r"OpConv<"}[kernel]
     copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
@@ -237,6 +237,55 @@ def mixed_form(w, steps, torch, I):
     out["rel_l2_diff_vs_fp64_u"] = err_u
     out["rel_l2_diff_vs_fp64_p"] = err_p
     out["speedup_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def semi_form(w, steps, torch, I):
+    """The semi-implicit convection form against the explicit one on the same
+    problem, start and precision (FP64): throughput, iterations, and each
+    form's relative L2 (nodal) distance to the interpolated exact solution
+    after `steps` steps (both are first-order-in-time approximations)."""
+    from paper_2605_25403_amd.workloads import dofs
+    m = I.Mesh.unit_square(w["n"]) if w["dim"] == 2 else I.Mesh.unit_cube(w["n"])
+
+    def builtin(r):
+        if w["dim"] == 2:
+            r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        else:
+            r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+
+    base = dict(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"], tol_corr=w["tol"])
+    runs = {}
+    for name, conv in (("explicit", I.IPCS_CONV_EXPLICIT), ("semi_implicit",
+                                                            I.IPCS_CONV_SEMI_IMPLICIT)):
+        r = I.Run(m, I.ipcs_params_default(convection=conv, **base), stream=torch.cuda.Stream())
+        builtin(r)
+        runs[name] = r
+    lat = {k: [] for k in runs}
+    it_m = {k: [] for k in runs}
+    it_p = {k: [] for k in runs}
+    for _ in range(steps):
+        for name, r in runs.items():
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat[name].append(time.perf_counter() - t0)
+            it_m[name].append(max(st["it_mom"][:w["dim"]]))
+            it_p[name].append(st["it_p"])
+    exact = I.Run(m, I.ipcs_params_default(t0=runs["explicit"].time(), **base))
+    builtin(exact)
+    Ue, Pe = exact.velocity(), exact.pressure()
+    nd = dofs(w["dim"], w["n"])
+    out = {"steps": steps}
+    for name, r in runs.items():
+        ms = 1000.0 * float(np.median(lat[name]))
+        out[name] = {"value": nd / (ms / 1000.0), "p50_step_ms": ms,
+                     "momentum_iterations_median": float(np.median(it_m[name])),
+                     "pressure_iterations_median": float(np.median(it_p[name])),
+                     "rel_l2_to_exact_u": float(np.linalg.norm(r.velocity() - Ue)
+                                                / np.linalg.norm(Ue)),
+                     "rel_l2_to_exact_p": float(np.linalg.norm(r.pressure() - Pe)
+                                                / np.linalg.norm(Pe))}
+    out["speedup_vs_explicit"] = out["semi_implicit"]["value"] / out["explicit"]["value"]
     return out
 
 
@@ -397,6 +446,7 @@ def main():
     }
     if not args.no_forms and not mixed:
         out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
+                        "semi_implicit": semi_form(w, args.form_steps, torch, I),
                         "serving": serving_form(torch, I)}
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")

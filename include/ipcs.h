@@ -148,6 +148,14 @@ typedef struct ipcs_run_s* ipcs_run;
  * passes. The momentum and
  * correction solves run on the FP32 matrices to tol_mom / tol_corr. */
 enum { IPCS_FP64 = 0, IPCS_MIXED = 1 };
+/* Convection forms. IPCS_CONV_EXPLICIT: eq. (9) as printed, the convection
+ * term with u^n on the right-hand side (b = (M/dt - C(U^n)) U^n - G P^n + F)
+ * and the constant A = M/dt + nu K. IPCS_CONV_SEMI_IMPLICIT: the convection
+ * operator moves into the momentum matrix, A^n = M/dt + nu K + C(U^n), with
+ * its Dirichlet elimination and lifting re-formed every step, and
+ * b = M U^n / dt - G P^n + F; BiCGStab then solves a nonsymmetric system
+ * (Section 2.2.1, eq. (9), first line, with the convection term linearized
+ * at u^n). */
 enum { IPCS_CONV_EXPLICIT = 0, IPCS_CONV_SEMI_IMPLICIT = 1 };
 
 typedef struct {
@@ -162,7 +170,9 @@ typedef struct {
   double tol_corr;      /* velocity-correction PCG                             */
   double tol_ir;        /* mixed form: FP64 iterative-refinement tolerance     */
   int32_t maxit;        /* iteration cap per solve                             */
-  int32_t check_every;  /* host convergence poll interval (iterations)         */
+  int32_t check_every;  /* most iterations a solve launches between two status
+                         * polls near its expected end (fewer when one
+                         * iteration costs more than a poll)                */
   int32_t callbacks;    /* 1: reserve staging for host-callback forcing        */
   int32_t poisson_part_rows; /* pressure Poisson CG form: 0 (default) one kernel
                            * per iteration on a row partition of Kp into parts
@@ -254,10 +264,13 @@ enum { IPCS_FIELD_U = 0, IPCS_FIELD_P = 1, IPCS_FIELD_USTAR = 2, IPCS_FIELD_DP =
 int ipcs_get_field(ipcs_run r, int32_t which, double* out, int64_t cap);
 
 enum { IPCS_MAT_M = 0, IPCS_MAT_K = 1, IPCS_MAT_KP = 2, IPCS_MAT_A = 3,
-       IPCS_MAT_E = 4,          /* M/dt - C(U^n), the explicit momentum operator */
+       IPCS_MAT_E = 4,          /* M/dt - C(U^n) (explicit form) or M/dt + C(U^n)
+                                 * (semi-implicit), assembled in the ASM phase */
        IPCS_MAT_D0 = 8,         /* D_c = IPCS_MAT_D0 + c                          */
        IPCS_MAT_G0 = 12,        /* G_c = IPCS_MAT_G0 + c                          */
-       IPCS_MAT_A_ELIM = 16, IPCS_MAT_M_ELIM = 17 };
+       IPCS_MAT_A_ELIM = 16,    /* momentum matrix, Dirichlet-eliminated (semi-
+                                 * implicit: of the current step)             */
+       IPCS_MAT_M_ELIM = 17 };
 /* Copy a device matrix to the host as CSR (values in FP64). rowptr/col may be
  * NULL to fetch values only. */
 int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_rows,

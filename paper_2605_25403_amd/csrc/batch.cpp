@@ -130,10 +130,12 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     sh.owner = p.rs;
     KSet& S = sh.S;
     int last = 0;
+    double us = 0.0;
     for (Run* r : p.rs) {
       const KSet& own = set_of(*r, which);
       S.h_groups.push_back(own.h_groups[0]);
       last = std::max(last, own.last_iters);
+      us = std::max(us, own.us_per_launch);
     }
     std::memcpy(host.data() + p.o_groups, S.h_groups.data(), sizeof(KGroup) * p.rs.size());
     std::memcpy(host.data() + p.o_bm, p.bm.data(), sizeof(int2) * p.bm.size());
@@ -165,6 +167,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
                     (int)p.bf.size(), lds};
     }
     S.last_iters = last;
+    S.us_per_launch = us;
     std::copy(std::begin(set_of(*p.rs[0], which).kid), std::end(set_of(*p.rs[0], which).kid),
               std::begin(S.kid));
     out.push_back(std::move(sh));
@@ -192,6 +195,7 @@ void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream
     for (size_t g = 0; g < sh.owner.size(); ++g) {
       Run* r = sh.owner[g];
       set_of(*r, which).last_iters = sh.S.last_iters;
+      set_of(*r, which).us_per_launch = sh.S.us_per_launch;
       const int ns = sh.S.h_groups[g].nsys;
       std::vector<KState> mine(hs.begin() + g * GMAX, hs.begin() + g * GMAX + ns);
       int code = IPCS_OK;

@@ -69,7 +69,8 @@ void check_params(const ipcs_params* p) {
   need(p->tol_mom > 0 && p->tol_p > 0 && p->tol_corr > 0, "tolerances must be positive");
   need(p->maxit > 0, "maxit must be positive");
   need(p->precision == IPCS_FP64 || p->precision == IPCS_MIXED, "unknown precision");
-  need(p->convection == IPCS_CONV_EXPLICIT, "only explicit convection is available");
+  need(p->convection == IPCS_CONV_EXPLICIT || p->convection == IPCS_CONV_SEMI_IMPLICIT,
+       "unknown convection form");
   need(p->precision == IPCS_FP64 || p->tol_ir > 0, "the mixed form needs tol_ir > 0");
   need(p->poisson_part_rows == 0 || p->poisson_part_rows == -1 ||
            (p->poisson_part_rows >= 64 && p->poisson_part_rows <= 2048),

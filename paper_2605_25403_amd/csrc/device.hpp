@@ -145,8 +145,10 @@ struct Builtin {
 // Assembly (kernels_asm.hip). bs = rows per block, lds = dynamic LDS bytes;
 // fp32 selects FP32 arithmetic and FP32 outputs (mixed form).
 void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
-void asm_conv_explicit(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
-                       const double* U, int64_t n2, double inv_dt);
+// E = M/dt + cs C(U): cs = -1 gives the explicit form's E = M/dt - C(U^n),
+// cs = +1 the semi-implicit form's M/dt + C(U^n)
+void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+              const double* U, int64_t n2, double inv_dt, double cs);
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
@@ -235,8 +237,11 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
+// b_c = sa E U_c - G_c P + F_c with Dirichlet lifting (explicit: E = M/dt -
+// C(U^n), sa = 1; semi-implicit: E = M, sa = 1/dt)
 void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const void* E, const double* U, const int32_t* sp21,
+                  const int32_t* col22, const void* E, double sa, const double* U,
+                  const int32_t* sp21,
                   const int32_t* col21, void* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b);

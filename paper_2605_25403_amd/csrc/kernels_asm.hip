@@ -162,12 +162,13 @@ struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
 };
 
 template <int D, class R>
-struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
+struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi-implicit)
   using real = R;
   static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
   const double* U;        // [D][n2]
   int64_t n2;
   double inv_dt;
+  double cs;
   __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
                              R (&v)[NOUT][NCOL]) const {
     const Tab<D, R>& T = tab<D, R>();
@@ -176,7 +177,7 @@ struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
     for (int c = 0; c < D; ++c)
 #pragma unroll
       for (int m = 0; m < NCOL; ++m) Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
-    const R idt = (R)inv_dt;
+    const R idt = (R)inv_dt, csr = (R)cs;
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
       R uq[D];
@@ -201,7 +202,7 @@ struct OpConvExplicit {   // P2 x P2: E = M/dt - C(U)
         R adv = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) adv += beta[a] * T.dphi[q][j][a];
-        v[0][j] += ci * (T.phi[q][j] * idt - adv);
+        v[0][j] += ci * (T.phi[q][j] * idt + csr * adv);
       }
     }
   }
@@ -369,9 +370,9 @@ void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, 
   rows_dr<OpMass>(dim, fp32, s, am, bs, lds);
   rows_dr<OpStiff>(dim, fp32, s, ak, bs, lds);
 }
-void asm_conv_explicit(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
-                       const double* U, int64_t n2, double inv_dt) {
-  rows_dr<OpConvExplicit>(dim, fp32, s, a, bs, lds, U, n2, inv_dt);
+void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+              const double* U, int64_t n2, double inv_dt, double cs) {
+  rows_dr<OpConv>(dim, fp32, s, a, bs, lds, U, n2, inv_dt, cs);
 }
 // a.out[c] <- G_c (one launch per component)
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {

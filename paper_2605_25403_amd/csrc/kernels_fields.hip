@@ -127,7 +127,8 @@ struct Ptrs3 {
 template <int D, class VT>
 __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
                                                 const int32_t* col22, const VT* A,
-                                                const double* X, const int32_t* sp21,
+                                                const double* X, double sa,
+                                                const int32_t* sp21,
                                                 const int32_t* col21, Ptrs3<VT> Gc,
                                                 const double* Y, double sc, const double* F,
                                                 const int32_t* lift_ptr, const int32_t* lift_col,
@@ -152,6 +153,8 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
 #pragma unroll
       for (int c = 0; c < D; ++c) s[c] += a * X[c * n2 + j];
     }
+#pragma unroll
+    for (int c = 0; c < D; ++c) s[c] *= sa;
   }
   {
     const int sl = (int)(i >> 6), b0 = sp21[sl], w = (sp21[sl + 1] - b0) >> 6;
@@ -174,7 +177,7 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
 
 template <class VT>
 static void rhs_p2_launch(hipStream_t s, int dim, int64_t n2, const int32_t* sp22,
-                          const int32_t* col22, const void* A, const double* X,
+                          const int32_t* col22, const void* A, const double* X, double sa,
                           const int32_t* sp21, const int32_t* col21, void* const* Gc,
                           const double* Y, double sc, const double* F, const int32_t* lift_ptr,
                           const int32_t* lift_col, const double* lift, const uint8_t* bmask,
@@ -183,26 +186,27 @@ static void rhs_p2_launch(hipStream_t s, int dim, int64_t n2, const int32_t* sp2
   const unsigned nb = (unsigned)div_up(n2, 256);
   if (dim == 2)
     hipLaunchKernelGGL((k_rhs_p2<2, VT>), dim3(nb), dim3(256), 0, s, n2, sp22, col22,
-                       (const VT*)A, X, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
+                       (const VT*)A, X, sa, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
                        bmask, g, b);
   else
     hipLaunchKernelGGL((k_rhs_p2<3, VT>), dim3(nb), dim3(256), 0, s, n2, sp22, col22,
-                       (const VT*)A, X, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
+                       (const VT*)A, X, sa, sp21, col21, gp, Y, sc, F, lift_ptr, lift_col, lift,
                        bmask, g, b);
   HIP_LAUNCH_OK();
 }
 
 void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const void* E, const double* U, const int32_t* sp21,
+                  const int32_t* col22, const void* E, double sa, const double* U,
+                  const int32_t* sp21,
                   const int32_t* col21, void* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b) {
   if (fp32)
-    rhs_p2_launch<float>(s, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, 1.0, F, lift_ptr,
-                         lift_col, liftA, bmask, gfull, b);
+    rhs_p2_launch<float>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, 1.0, F,
+                         lift_ptr, lift_col, liftA, bmask, gfull, b);
   else
-    rhs_p2_launch<double>(s, dim, n2, sp22, col22, E, U, sp21, col21, Gc, P, 1.0, F, lift_ptr,
-                          lift_col, liftA, bmask, gfull, b);
+    rhs_p2_launch<double>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, 1.0, F,
+                          lift_ptr, lift_col, liftA, bmask, gfull, b);
 }
 
 void rhs_correction(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
@@ -212,11 +216,11 @@ void rhs_correction(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t
                     const int32_t* lift_col, const double* liftM, const uint8_t* bmask,
                     const double* gfull, double* b) {
   if (fp32)
-    rhs_p2_launch<float>(s, dim, n2, sp22, col22, M, Us, sp21, col21, Gc, dP, scale, nullptr,
-                         lift_ptr, lift_col, liftM, bmask, gfull, b);
+    rhs_p2_launch<float>(s, dim, n2, sp22, col22, M, Us, 1.0, sp21, col21, Gc, dP, scale,
+                         nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
   else
-    rhs_p2_launch<double>(s, dim, n2, sp22, col22, M, Us, sp21, col21, Gc, dP, scale, nullptr,
-                          lift_ptr, lift_col, liftM, bmask, gfull, b);
+    rhs_p2_launch<double>(s, dim, n2, sp22, col22, M, Us, 1.0, sp21, col21, Gc, dP, scale,
+                          nullptr, lift_ptr, lift_col, liftM, bmask, gfull, b);
 }
 
 // r[k] = scale * sum_c sum_j D_c[kj] Us_c[j] (SELL-64, one thread per row) and

@@ -3,6 +3,7 @@
 #include "run.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -84,9 +85,13 @@ int status_to_code(int s) {
 
 // Host side of a solve: start, then launch iterations in chunks and poll the
 // status words between chunks. Chunks are sized from the previous solve of the
-// same set (half of the expected remaining iterations, at least check_every),
-// so a solve that takes as long as the last one polls about log2 of its length
-// times. Parity par alternates with every iteration launch.
+// same set: half of the expected remaining iterations, but at least as many
+// launches as take the time of one poll (measured from the previous solve;
+// check_every before the first one, and never more than check_every). A solve
+// that takes as long as the last one polls about log2 of its length times, and
+// overshoots its convergence by about the cost of one poll. Launches past
+// convergence are not free: kernels issue their loads before they read the
+// status. Parity par alternates with every iteration launch.
 LaunchEvents*& launch_events() {
   thread_local LaunchEvents* slot = nullptr;
   return slot;
@@ -115,8 +120,13 @@ void KTimer::drain() {
   which.clear();
 }
 
+// Host time of one poll (the GPU drains, the host reads the status words and
+// launches again), against which the least chunk is sized.
+constexpr double kPollUs = 30.0;
+
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector<KState>& hs,
                  KState* pinned, KTimer& T) {
+  const auto t_begin = std::chrono::steady_clock::now();
   const int nslot = S.L.ngroups * GMAX;
   hs.assign(nslot, KState{});
   auto fetch = [&]() {
@@ -165,6 +175,10 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
   start(0);
   fetch();
   const int every = std::max(1, check_every);
+  const int least =
+      S.us_per_launch > 0.0
+          ? std::max(1, std::min(every, (int)std::ceil(kPollUs / S.us_per_launch)))
+          : every;
   bool restarted = false;
   for (;;) {
     bool run = false;
@@ -188,7 +202,7 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
     if (stopped) continue;
     const int rem = remaining();
     // after a restart the remaining iterations are few and unknown
-    int chunk = restarted ? every : std::max(every, (S.last_iters - launched) / 2);
+    int chunk = restarted ? least : std::max(least, (S.last_iters - launched) / 2);
     chunk = std::max(1, std::min(chunk, rem));
     for (int k = 0; k < chunk; ++k) {
       iterate(par);
@@ -207,6 +221,11 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
   int iters = 0;
   each([&](const KState& k) { iters = std::max(iters, k.it); });
   S.last_iters = iters;   // the poll schedule of the next solve of this set
+  if (launched > 0) {
+    const double us = std::chrono::duration<double, std::micro>(
+                          std::chrono::steady_clock::now() - t_begin).count();
+    S.us_per_launch = us / launched;
+  }
   if (fused) fcg_finish(s, S.F);
   else ksys_finish(s, S.L);
   int rc = IPCS_OK;
@@ -720,9 +739,15 @@ void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_s
 
 // Step pieces shared by single runs and batches (all on the run's stream).
 
-// Dirichlet data and forcing at t^{n+1}, E = M/dt - C(U^n), momentum RHS, U* start.
+// Dirichlet data and forcing at t^{n+1}, the convection term, momentum RHS, U* start.
+// Explicit (eq. (9) as printed): E = M/dt - C(U^n) and b = E U^n - G P^n + F;
+// A = M/dt + nu K is constant. Semi-implicit: E = M/dt + C(U^n), A = E + nu K
+// with its Dirichlet elimination and lifting re-formed every step, and
+// b = M U^n / dt - G P^n + F.
 void Run::asm_phase() {
-  if (A_dirty) reform_A();
+  const bool semi = prm.convection == IPCS_CONV_SEMI_IMPLICIT;
+  if (A_dirty && !semi) reform_A();
+  bi.nu = prm.nu;
   t1 = t + prm.dt;
   HIP_OK(hipEventRecord(ev[0], stream));
   if (g_cb) {
@@ -755,10 +780,17 @@ void Run::asm_phase() {
     has_F = true;
   }
   timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
-    asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+    asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt,
+             semi ? 1.0 : -1.0);
   });
-  rhs_momentum(stream, dim, mixed, n2, sp22, col22, E, U, sp21, col21, Gc, P,
-               has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask, gfull, bU);
+  if (semi) {
+    form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, E, K, 1.0, prm.nu, Ael, dinvA);
+    lift_values(stream, mixed, nlift, lift_slot, E, K, 1.0, prm.nu, liftA);
+    A_dirty = false;
+  }
+  rhs_momentum(stream, dim, mixed, n2, sp22, col22, semi ? M : E, semi ? 1.0 / prm.dt : 1.0, U,
+               sp21, col21, Gc, P, has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask, gfull,
+               bU);
   copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
   HIP_OK(hipEventRecord(ev[1], stream));
 }
@@ -942,7 +974,8 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
       case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L, 0); break;
       case IPCS_KERNEL_ASM_CONV:
-        asm_conv_explicit(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt);
+        asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt,
+                 prm.convection == IPCS_CONV_SEMI_IMPLICIT ? 1.0 : -1.0);
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;
       case IPCS_KERNEL_PCG_SPMV_M: pcg_spmv_only(stream, set_corr.L); break;

@@ -73,6 +73,7 @@ struct KSet {
   std::vector<KGroup> h_groups;
   KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
   int last_iters = 0;          // iterations the previous solve took (poll schedule)
+  double us_per_launch = 0.0;  // host time per iteration launch in the previous solve (0: none)
   // kernel ids for timing: PCG {spmv, update} (fused: {iteration}),
   // BiCGStab {v, s, t, x}; -1: none
   int kid[4] = {-1, -1, -1, -1};

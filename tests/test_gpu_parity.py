@@ -96,11 +96,12 @@ def test_c1_taylor_green_ten_steps():
         assert st["status"] == 0 and st["it_p"] > 0
 
 
-@pytest.mark.parametrize("dim,n,semi", [(2, 6, False), (3, 2, False)])
+@pytest.mark.parametrize("dim,n,semi", [(2, 6, False), (3, 2, False), (2, 6, True),
+                                        (3, 2, True)])
 def test_polynomial_fixed_point(dim, n, semi):
     torch, I = require_gpu()
-    print(f"fixed point dim={dim}", flush=True)
-    S, o, r = make_pair(I, dim, n, "poly", 0.07, 0.05, tol=1e-14, same_state=False)
+    print(f"fixed point dim={dim} semi={semi}", flush=True)
+    S, o, r = make_pair(I, dim, n, "poly", 0.07, 0.05, tol=1e-14, same_state=False, semi=semi)
     U0, P0 = r.velocity().copy(), r.pressure().copy()
     np.testing.assert_allclose(U0, o.U, atol=1e-14)
     r.advance(2)

@@ -106,6 +106,11 @@ def test_invalid_arguments_are_reported():
     p = I.ipcs_params_default(dt=-1.0)
     with pytest.raises(I.IpcsError):
         I.ipcs_run_workspace_bytes(m.h, p)
+    with pytest.raises(I.IpcsError):
+        I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(convection=5))
+    semi = I.ipcs_params_default(convection=I.IPCS_CONV_SEMI_IMPLICIT)
+    assert I.ipcs_run_workspace_bytes(m.h, semi) == I.ipcs_run_workspace_bytes(
+        m.h, I.ipcs_params_default())
 
 
 def test_workspace_size_grows_with_the_mesh_and_covers_the_values():
