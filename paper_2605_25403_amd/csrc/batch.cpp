@@ -92,7 +92,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     bool fused = false;
     std::vector<Run*> rs;
     std::vector<int2> bm, bv, bf;
-    size_t o_groups, o_bm, o_bv, o_poll, o_fgroups = 0, o_bf = 0;
+    size_t o_groups, o_bm, o_bv, o_poll, o_fgroups = 0, o_bf = 0, o_compact = 0;
   };
   std::vector<Plan> plans;
   for (auto& kv : cls) {
@@ -120,6 +120,8 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
       p.o_fgroups = take(sizeof(FGroup) * p.rs.size());
       p.o_bf = take(sizeof(int2) * p.bf.size());
     }
+    // room for the block maps over unfinished groups (krylov_solve)
+    p.o_compact = take(sizeof(int2) * (p.bm.size() + p.bv.size() + p.bf.size()));
     plans.push_back(std::move(p));
   }
   buf.reset(new DevBuf(s, bytes));
@@ -130,12 +132,13 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     sh.owner = p.rs;
     KSet& S = sh.S;
     int last = 0;
-    double us = 0.0;
+    double us = 0.0, up = 0.0;
     for (Run* r : p.rs) {
       const KSet& own = set_of(*r, which);
       S.h_groups.push_back(own.h_groups[0]);
       last = std::max(last, own.last_iters);
       us = std::max(us, own.us_per_launch);
+      up = std::max(up, own.us_per_poll);
     }
     std::memcpy(host.data() + p.o_groups, S.h_groups.data(), sizeof(KGroup) * p.rs.size());
     std::memcpy(host.data() + p.o_bm, p.bm.data(), sizeof(int2) * p.bm.size());
@@ -151,6 +154,8 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
                   reinterpret_cast<const int2*>(buf->base + p.o_bv),
                   (int)p.bv.size()};
     S.d_poll = reinterpret_cast<KState*>(buf->base + p.o_poll);
+    S.d_compact = reinterpret_cast<int2*>(buf->base + p.o_compact);
+    S.compact_cap = (int)(p.bm.size() + p.bv.size() + p.bf.size());
     if (p.fused) {
       size_t lds = 0;
       for (Run* r : p.rs) {
@@ -168,6 +173,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     }
     S.last_iters = last;
     S.us_per_launch = us;
+    S.us_per_poll = up;
     std::copy(std::begin(set_of(*p.rs[0], which).kid), std::end(set_of(*p.rs[0], which).kid),
               std::begin(S.kid));
     out.push_back(std::move(sh));
@@ -196,6 +202,7 @@ void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream
       Run* r = sh.owner[g];
       set_of(*r, which).last_iters = sh.S.last_iters;
       set_of(*r, which).us_per_launch = sh.S.us_per_launch;
+      set_of(*r, which).us_per_poll = sh.S.us_per_poll;
       const int ns = sh.S.h_groups[g].nsys;
       std::vector<KState> mine(hs.begin() + g * GMAX, hs.begin() + g * GMAX + ns);
       int code = IPCS_OK;

@@ -3,7 +3,6 @@
 #include "run.hpp"
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -57,6 +56,23 @@ void xcd_order(std::vector<int2>& bmap) {
   bmap.swap(out);
 }
 
+void xcd_chunks(std::vector<int2>& bmap, int chunk) {
+  constexpr int kXcd = 8;
+  const int n = (int)bmap.size();
+  const int span = kXcd * chunk;
+  std::vector<int2> out;
+  out.reserve(n);
+  std::vector<char> used(n, 0);
+  // full spans: the k-th block of XCD x in span s is logical block
+  // s*span + x*chunk + k
+  const int full = n / span;
+  for (int sp = 0; sp < full; ++sp)
+    for (int k = 0; k < chunk; ++k)
+      for (int x = 0; x < kXcd; ++x) out.push_back(bmap[sp * span + x * chunk + k]);
+  for (int b = full * span; b < n; ++b) out.push_back(bmap[b]);   // tail in order
+  bmap.swap(out);
+}
+
 // LDS needed by the assembly kernel with bs rows per block: the largest
 // number of SELL entries of the bs/64 slices a block owns, times the value size.
 static AsmCfg asm_cfg(const Sell& S, int vbytes) {
@@ -86,10 +102,12 @@ int status_to_code(int s) {
 // Host side of a solve: start, then launch iterations in chunks and poll the
 // status words between chunks. Chunks are sized from the previous solve of the
 // same set: half of the expected remaining iterations, but at least as many
-// launches as take the time of one poll (measured from the previous solve;
-// check_every before the first one, and never more than check_every). A solve
+// launches as take the device time one poll leaves idle (both measured with
+// events in the previous solve; check_every before the first one, and never
+// more than check_every). A solve
 // that takes as long as the last one polls about log2 of its length times, and
-// overshoots its convergence by about the cost of one poll. Launches past
+// overshoots its convergence by about the cost of one poll. Past the expected
+// length, or after a restart, chunks double from the least one. Launches past
 // convergence are not free: kernels issue their loads before they read the
 // status. Parity par alternates with every iteration launch.
 LaunchEvents*& launch_events() {
@@ -120,13 +138,41 @@ void KTimer::drain() {
   which.clear();
 }
 
-// Host time of one poll (the GPU drains, the host reads the status words and
-// launches again), against which the least chunk is sized.
-constexpr double kPollUs = 30.0;
+// Timing events that bracket the chunks of a solve (per host thread, reused).
+// From them a solve measures the device time per iteration launch and the gap
+// a poll leaves on the device (the status read-back, the host's turn and the
+// next launch), against which the least chunk of the next solve is sized.
+static hipEvent_t* chunk_events(int n) {
+  thread_local std::vector<hipEvent_t> pool;
+  while ((int)pool.size() < n) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool.data();
+}
+constexpr int kChunkEvents = 128;   // chunks timed per solve (the rest are not)
 
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector<KState>& hs,
                  KState* pinned, KTimer& T) {
-  const auto t_begin = std::chrono::steady_clock::now();
+  // bursts of device work (the start, each chunk of iterations, each
+  // confirmation) are bracketed by events while any are left: the gap between
+  // the end of one burst and the start of the next is the cost of a poll
+  hipEvent_t* ev = chunk_events(2 * kChunkEvents);
+  int nburst = 0, timed_launches = 0;
+  double busy_ms = 0.0;
+  std::vector<int> iter_burst;   // bursts that are chunks of iterations
+  auto burst = [&](bool iters, auto work) {
+    const bool timed = nburst < kChunkEvents;
+    if (timed) HIP_OK(hipEventRecord(ev[2 * nburst], s));
+    work();
+    if (timed) {
+      HIP_OK(hipEventRecord(ev[2 * nburst + 1], s));
+      if (iters) iter_burst.push_back(nburst);
+      ++nburst;
+    }
+    return timed;
+  };
   const int nslot = S.L.ngroups * GMAX;
   hs.assign(nslot, KState{});
   auto fetch = [&]() {
@@ -172,14 +218,66 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
     }
     return rem;
   };
-  start(0);
+  // block maps over the unfinished groups (sets of several groups): rebuilt
+  // when finished groups hold at least a sixth of the launch's blocks.
+  // A group's own blocks and partial sums are the same in every map, so
+  // results do not depend on the compaction.
+  std::vector<int2> cm, cv, cf;   // host copies, alive until the next sync
+  const KLaunch L_full = S.L;
+  const FLaunch F_full = S.F;
+  auto compact = [&]() {
+    if (!S.d_compact || S.L.ngroups < 2) return;
+    std::vector<int> nm(S.L.ngroups, 0), nv(S.L.ngroups, 0), nf(S.L.ngroups, 0);
+    int tm = 0;
+    for (int g = 0; g < S.L.ngroups; ++g) {
+      bool open = false;
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) {
+        const int st = hs[g * GMAX + j].status;
+        open |= st == KS_RUN || st == KS_PENDING || st == KS_RESTART;
+      }
+      if (!open) continue;
+      nm[g] = S.h_groups[g].nblk_m;
+      nv[g] = S.h_groups[g].nblk_v;
+      if (fused) nf[g] = S.h_fgroups[g].nparts;
+      tm += fused ? nf[g] : nm[g];
+    }
+    const int now = fused ? S.F.nblocks : S.L.nblocks_m;
+    if (tm == 0 || 6 * (now - tm) < now) return;
+    build_bmap(nm, cm);
+    build_bmap(nv, cv);
+    cf.clear();
+    if (fused) {
+      for (int g = 0; g < S.L.ngroups; ++g)
+        for (int b = 0; b < nf[g]; ++b) cf.push_back(make_int2(g, b));
+      xcd_order(cf);
+    }
+    const size_t need = cm.size() + cv.size() + cf.size();
+    if ((int)need > S.compact_cap) return;
+    int2* d = S.d_compact;
+    HIP_OK(hipMemcpyAsync(d, cm.data(), sizeof(int2) * cm.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d + cm.size(), cv.data(), sizeof(int2) * cv.size(),
+                          hipMemcpyHostToDevice, s));
+    if (!cf.empty())
+      HIP_OK(hipMemcpyAsync(d + cm.size() + cv.size(), cf.data(), sizeof(int2) * cf.size(),
+                            hipMemcpyHostToDevice, s));
+    S.L.bmap_m = d;
+    S.L.nblocks_m = (int)cm.size();
+    S.L.bmap_v = d + cm.size();
+    S.L.nblocks_v = (int)cv.size();
+    if (fused) {
+      S.F.bmap = d + cm.size() + cv.size();
+      S.F.nblocks = (int)cf.size();
+    }
+  };
+  burst(false, [&] { start(0); });
   fetch();
   const int every = std::max(1, check_every);
   const int least =
-      S.us_per_launch > 0.0
-          ? std::max(1, std::min(every, (int)std::ceil(kPollUs / S.us_per_launch)))
+      S.us_per_launch > 0.0 && S.us_per_poll > 0.0
+          ? std::max(1, std::min(every, (int)std::ceil(S.us_per_poll / S.us_per_launch)))
           : every;
   bool restarted = false;
+  int tail = 0;   // polls made in the unknown tail of the solve
   for (;;) {
     bool run = false;
     each([&](const KState& k) { run |= (k.status == KS_RUN); });
@@ -201,30 +299,57 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
     }
     if (stopped) continue;
     const int rem = remaining();
-    // after a restart the remaining iterations are few and unknown
-    int chunk = restarted ? least : std::max(least, (S.last_iters - launched) / 2);
-    chunk = std::max(1, std::min(chunk, rem));
-    for (int k = 0; k < chunk; ++k) {
-      iterate(par);
-      par ^= 1;
+    // after a restart, or past the previous solve's length, the remaining
+    // iterations are unknown: chunks grow geometrically from the least one
+    int chunk;
+    if (restarted || launched >= S.last_iters) {
+      chunk = least << std::min(tail, 10);
+      ++tail;
+    } else {
+      chunk = std::max(least, (S.last_iters - launched) / 2);
     }
+    chunk = std::max(1, std::min(chunk, rem));
+    if (burst(true, [&] {
+          for (int k = 0; k < chunk; ++k) {
+            iterate(par);
+            par ^= 1;
+          }
+        }))
+      timed_launches += chunk;
     launched += chunk;
     fetch();
+    compact();
     bool pend = false;
     each([&](const KState& k) { pend |= (k.status == KS_PENDING || k.status == KS_RESTART); });
     if (pend) {
-      start(1);
+      burst(false, [&] { start(1); });
       fetch();
-      each([&](const KState& k) { restarted |= k.status == KS_RUN; });
+      bool again = false;
+      each([&](const KState& k) { again |= k.status == KS_RUN; });
+      if (again && !restarted) tail = 0;
+      restarted |= again;
     }
   }
   int iters = 0;
   each([&](const KState& k) { iters = std::max(iters, k.it); });
   S.last_iters = iters;   // the poll schedule of the next solve of this set
-  if (launched > 0) {
-    const double us = std::chrono::duration<double, std::micro>(
-                          std::chrono::steady_clock::now() - t_begin).count();
-    S.us_per_launch = us / launched;
+  S.L = L_full;           // the finish covers every group
+  S.F = F_full;
+  // the stream has synchronized (last fetch): every recorded event is done
+  for (int k : iter_burst) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    busy_ms += ms;
+  }
+  if (timed_launches > 0) S.us_per_launch = 1000.0 * busy_ms / timed_launches;
+  if (nburst > 1) {
+    double gaps = 0.0;
+    for (int k = 1; k < nburst; ++k) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, ev[2 * k - 1], ev[2 * k]));
+      gaps += ms;
+    }
+    S.us_per_poll = 1000.0 * gaps / (nburst - 1);
   }
   if (fused) fcg_finish(s, S.F);
   else ksys_finish(s, S.L);
@@ -559,6 +684,11 @@ void Run::setup_solvers() {
     S.h_groups = {grp[gi]};
     build_bmap({grp[gi].nblk_m}, maps_m[gi]);
     build_bmap({grp[gi].nblk_v}, maps_v[gi]);
+    // matrix kernels gather from a band of rows around their own: runs of 8
+    // consecutive row blocks per XCD share those gathers in its L2 (one
+    // contiguous range per XCD instead is slower: the 8 streams at a stride
+    // of 1/8 of the matrix contend for the same memory channels)
+    xcd_chunks(maps_m[gi], 8);
     HIP_OK(hipMemcpyAsync(bmap_m[gi], maps_m[gi].data(), sizeof(int2) * maps_m[gi].size(),
                           hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(bmap_v[gi], maps_v[gi].data(), sizeof(int2) * maps_v[gi].size(),

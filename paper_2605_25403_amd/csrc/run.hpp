@@ -73,10 +73,16 @@ struct KSet {
   std::vector<KGroup> h_groups;
   KState* d_poll = nullptr;    // [ngroups * GMAX] polling copies of the states
   int last_iters = 0;          // iterations the previous solve took (poll schedule)
-  double us_per_launch = 0.0;  // host time per iteration launch in the previous solve (0: none)
+  double us_per_launch = 0.0;  // device time per iteration launch in the previous solve (0: none)
+  double us_per_poll = 0.0;    // device idle time per status poll in the previous solve
   // kernel ids for timing: PCG {spmv, update} (fused: {iteration}),
   // BiCGStab {v, s, t, x}; -1: none
   int kid[4] = {-1, -1, -1, -1};
+  // sets of several groups: device room for block maps over the groups that
+  // are still unfinished (matrix, vector and fused maps back to back), so that
+  // finished groups stop taking blocks; null: no compaction
+  int2* d_compact = nullptr;
+  int compact_cap = 0;
 };
 
 enum class KMethod { PCG, BICG };
@@ -100,6 +106,9 @@ void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
 // one contiguous range of its entries: neighbouring parts of a row partition
 // (which share halo rows) then share an L2.
 void xcd_order(std::vector<int2>& bmap);
+// Deals runs of `chunk` consecutive entries to the XCDs in turn: XCD x takes
+// runs x, x + 8, ... (the tail past the last full round stays in order).
+void xcd_chunks(std::vector<int2>& bmap, int chunk);
 
 struct AsmCfg {
   int bs = 256;
