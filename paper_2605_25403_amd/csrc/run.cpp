@@ -62,7 +62,6 @@ void xcd_chunks(std::vector<int2>& bmap, int chunk) {
   const int span = kXcd * chunk;
   std::vector<int2> out;
   out.reserve(n);
-  std::vector<char> used(n, 0);
   // full spans: the k-th block of XCD x in span s is logical block
   // s*span + x*chunk + k
   const int full = n / span;
