@@ -144,6 +144,9 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     std::memcpy(host.data() + p.o_bm, p.bm.data(), sizeof(int2) * p.bm.size());
     std::memcpy(host.data() + p.o_bv, p.bv.data(), sizeof(int2) * p.bv.size());
     const KLaunch& L0 = set_of(*p.rs[0], which).L;
+    // folded totals are bitwise the re-reduced ones: fold if any member would
+    int fold = 0;
+    for (Run* r : p.rs) fold |= set_of(*r, which).L.fold;
     S.L = KLaunch{reinterpret_cast<const KGroup*>(buf->base + p.o_groups),
                   (int)p.rs.size(),
                   L0.ns,
@@ -152,7 +155,8 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
                   reinterpret_cast<const int2*>(buf->base + p.o_bm),
                   (int)p.bm.size(),
                   reinterpret_cast<const int2*>(buf->base + p.o_bv),
-                  (int)p.bv.size()};
+                  (int)p.bv.size(),
+                  fold};
     S.d_poll = reinterpret_cast<KState*>(buf->base + p.o_poll);
     S.d_compact = reinterpret_cast<int2*>(buf->base + p.o_compact);
     S.compact_cap = (int)(p.bm.size() + p.bv.size() + p.bf.size());

@@ -85,6 +85,7 @@ struct KGroup {
   int32_t maxit, pad;         // iteration cap of the group's systems
   double* part_m;
   double* part_v[2];
+  double* fold;               // [GMAX * KP] totals folded once from the records
   KVecs v[GMAX];
 };
 
@@ -179,6 +180,11 @@ struct KLaunch {
   int nblocks_m;
   const int2* bmap_v;
   int nblocks_v;
+  // 1: after each matrix kernel, one block per group folds the partial-sum
+  // records its vector kernel needs into KGroup::fold, and every block of the
+  // vector kernel reads those totals instead of re-reducing all records
+  // (bitwise the same totals); 0: every block re-reduces the records
+  int fold;
 };
 // Start (mode 0) or confirm/restart (mode 1, systems PENDING or RESTART):
 // r = b - A x, then the status decision. par is the parity of the next

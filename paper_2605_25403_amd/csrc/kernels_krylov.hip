@@ -222,6 +222,62 @@ __global__ void __launch_bounds__(KBS) k_decide(const KGroup* groups, int mode, 
     }
 }
 
+// ------------------------------------------------------------------ reduction totals
+// This thread's share of the totals a vector kernel needs (block_sum_t then
+// completes them): the same loads and order in a vector kernel's blocks and in
+// the fold kernel, so folded totals are bitwise those a block would form.
+// PCG update: [r.u, r.r] of the last update (part_v[par]), u.w of the SpMV
+template <int NS>
+__device__ __forceinline__ void cg_update_totals(const KGroup& g, int par, double (&t)[NS * 3]) {
+  double a[NS * 2], b[NS];
+  load_partials<NS, 2>(g.part_v[par], g.nblk_v, a);
+  load_partials<NS, 1>(g.part_m, g.nblk_m, b);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    t[j * 3 + 0] = a[j * 2];
+    t[j * 3 + 1] = a[j * 2 + 1];
+    t[j * 3 + 2] = b[j];
+  }
+}
+// BiCGStab s-update: [rhat.v (SpMV), r.r (last x-update)]
+template <int NS>
+__device__ __forceinline__ void bicg3_totals(const KGroup& g, int par, double (&t)[NS * 2]) {
+  double a[NS], b[NS];
+  load_partials<NS, 1>(g.part_m, g.nblk_m, a);
+  load_partials<NS, 1>(g.part_v[par], g.nblk_v, b);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    t[j * 2] = a[j];
+    t[j * 2 + 1] = b[j];
+  }
+}
+// BiCGStab x-update: [t.s, t.t, rhat.s, rhat.t] (SpMV)
+template <int NS>
+__device__ __forceinline__ void bicg5_totals(const KGroup& g, double (&t)[NS * 4]) {
+  load_partials<NS, 4>(g.part_m, g.nblk_m, t);
+}
+
+// One block per group: the totals of kernel KIND (0 PCG update, 1 BiCGStab
+// s-update, 2 BiCGStab x-update) into g.fold, read by every block of that
+// kernel in its folding form.
+template <int KIND, int NS>
+__global__ void __launch_bounds__(KBS) k_fold(const KGroup* groups, int par) {
+  const KGroup& g = groups[blockIdx.x];
+  constexpr int K = KIND == 0 ? 3 : KIND == 1 ? 2 : 4;
+  __shared__ double sh[(KBS / 64) * NS * K];
+  double t[NS * K];
+  if constexpr (KIND == 0) cg_update_totals<NS>(g, par, t);
+  else if constexpr (KIND == 1) bicg3_totals<NS>(g, par, t);
+  else bicg5_totals<NS>(g, t);
+  block_sum_t<KBS, NS * K>(t, sh);
+  if ((int)threadIdx.x < NS * K) {
+    double v = 0.0;
+#pragma unroll
+    for (int n = 0; n < NS * K; ++n) v = n == (int)threadIdx.x ? t[n] : v;
+    G(g.fold)[threadIdx.x] = v;
+  }
+}
+
 // ------------------------------------------------------------------ PCG (Chronopoulos-Gear)
 template <int NS, int EPT, class VT>
 __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int2* bmap) {
@@ -258,7 +314,7 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
   store_partials<NS, 1>(acc, g.part_m, g.nblk_m, lb, sh);
 }
 
-template <int NS>
+template <int NS, bool FOLD>
 __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const int2* bmap,
                                                    int par) {
   GROUP_HEAD(bmap)
@@ -291,18 +347,13 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
     }
   }
   double t[NS * 3];
-  {
-    double a[NS * 2], b[NS];
-    load_partials<NS, 2>(g.part_v[par], g.nblk_v, a);
-    load_partials<NS, 1>(g.part_m, g.nblk_m, b);
+  if constexpr (FOLD) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      t[j * 3 + 0] = a[j * 2];
-      t[j * 3 + 1] = a[j * 2 + 1];
-      t[j * 3 + 2] = b[j];
-    }
+    for (int n = 0; n < NS * 3; ++n) t[n] = G((const double*)g.fold)[n];
+  } else {
+    cg_update_totals<NS>(g, par, t);
+    block_sum_t<KBS, NS * 3>(t, sh);
   }
-  block_sum_t<KBS, NS * 3>(t, sh);
   const bool lead = lb == 0 && threadIdx.x == 0;
   bool go[NS];
   double al[NS], be[NS];
@@ -424,7 +475,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
   store_partials<NS, K>(acc, g.part_m, g.nblk_m, lb, sh);
 }
 
-template <int NS>
+template <int NS, bool FOLD>
 __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2* bmap, int par) {
   GROUP_HEAD(bmap)
   constexpr int EV = kept_v(NS);
@@ -449,18 +500,14 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
       vi[e][j] = G(g.v[j].w)[i];
     }
   }
-  double t[NS * 2];
-  {
-    double a[NS], b[NS];
-    load_partials<NS, 1>(g.part_m, g.nblk_m, a);      // rhat.v
-    load_partials<NS, 1>(g.part_v[par], g.nblk_v, b); // r.r
+  double t[NS * 2];   // rhat.v, r.r
+  if constexpr (FOLD) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      t[j * 2] = a[j];
-      t[j * 2 + 1] = b[j];
-    }
+    for (int n = 0; n < NS * 2; ++n) t[n] = G((const double*)g.fold)[n];
+  } else {
+    bicg3_totals<NS>(g, par, t);
+    block_sum_t<KBS, NS * 2>(t, sh);
   }
-  block_sum_t<KBS, NS * 2>(t, sh);
   const bool lead = lb == 0 && threadIdx.x == 0;
   bool go[NS];
   double al[NS];
@@ -514,7 +561,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
   }
 }
 
-template <int NS>
+template <int NS, bool FOLD>
 __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2* bmap, int par) {
   GROUP_HEAD(bmap)
   constexpr int EV = kept_v(NS);
@@ -546,9 +593,14 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
       vi[e][j] = G(V.w)[i];
     }
   }
-  double t[NS * 4];
-  load_partials<NS, 4>(g.part_m, g.nblk_m, t);   // t.s, t.t, rhat.s, rhat.t
-  block_sum_t<KBS, NS * 4>(t, sh);
+  double t[NS * 4];   // t.s, t.t, rhat.s, rhat.t
+  if constexpr (FOLD) {
+#pragma unroll
+    for (int n = 0; n < NS * 4; ++n) t[n] = G((const double*)g.fold)[n];
+  } else {
+    bicg5_totals<NS>(g, t);
+    block_sum_t<KBS, NS * 4>(t, sh);
+  }
   const bool lead = lb == 0 && threadIdx.x == 0;
   bool go[NS], full[NS];
   double om[NS], be[NS];
@@ -712,10 +764,19 @@ void pcg_spmv_only(hipStream_t s, const KLaunch& L) {
   HIP_LAUNCH_OK();
 }
 
+// The fold kernel is launched directly (not through launch()), so that a
+// timing hook around the update times the update itself.
 void pcg_update_only(hipStream_t s, const KLaunch& L, int par) {
   with_ns(L.ns, [&](auto N) {
-    launch(k_cg_update<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
-                       par);
+    if (L.fold) {
+      hipLaunchKernelGGL((k_fold<0, NSV>), dim3(L.ngroups), dim3(KBS), 0, s, L.groups, par);
+      HIP_LAUNCH_OK();
+      launch(k_cg_update<NSV, true>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+             par);
+    } else {
+      launch(k_cg_update<NSV, false>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+             par);
+    }
   });
   HIP_LAUNCH_OK();
 }
@@ -735,8 +796,14 @@ void bicg_spmv_only(hipStream_t s, const KLaunch& L) {
 
 void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par) {
   with_ns(L.ns, [&](auto N) {
-    launch(k_bicg_3<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
-                       par);
+    if (L.fold) {
+      hipLaunchKernelGGL((k_fold<1, NSV>), dim3(L.ngroups), dim3(KBS), 0, s, L.groups, par);
+      HIP_LAUNCH_OK();
+      launch(k_bicg_3<NSV, true>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v, par);
+    } else {
+      launch(k_bicg_3<NSV, false>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+             par);
+    }
   });
   HIP_LAUNCH_OK();
 }
@@ -751,8 +818,14 @@ void bicg_spmv_t_only(hipStream_t s, const KLaunch& L) {
 
 void bicg_update_x_only(hipStream_t s, const KLaunch& L, int par) {
   with_ns(L.ns, [&](auto N) {
-    launch(k_bicg_5<NSV>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
-                       par);
+    if (L.fold) {
+      hipLaunchKernelGGL((k_fold<2, NSV>), dim3(L.ngroups), dim3(KBS), 0, s, L.groups, par);
+      HIP_LAUNCH_OK();
+      launch(k_bicg_5<NSV, true>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v, par);
+    } else {
+      launch(k_bicg_5<NSV, false>, dim3(L.nblocks_v), dim3(KBS), 0, s, L.groups, L.bmap_v,
+             par);
+    }
   });
   HIP_LAUNCH_OK();
 }

@@ -30,6 +30,15 @@ int nblk_m_for(int64_t n, int ns) {
 }
 constexpr int kMaxRefine = 30;   // mixed form: refinement passes
 
+// Fold the partial-sum records once per group (KLaunch::fold) when the vector
+// kernels' blocks would otherwise re-read more than kFoldBytes of records from
+// L2 per launch (each block reads every record of the kernels before it).
+constexpr double kFoldBytes = 16.0 * (1 << 20);
+int fold_for(int64_t n, int ns) {
+  const double nm = nblk_m_for(n, ns), nv = nblk_v_for(n, ns);
+  return ns * (4.0 * nm + 2.0 * nv) * nv * 8.0 >= kFoldBytes ? 1 : 0;
+}
+
 int nblk_v_for(int64_t n, int ns) {
   const int64_t b = std::max<int64_t>(1, div_up(n, (int64_t)KBS * kept_v(ns)));
   if (b > KNB_MAX) fail(IPCS_E_CAPACITY, "a Krylov system has more rows than one group supports");
@@ -481,6 +490,7 @@ void Run::layout(Carver& c) {
     part_m[gi] = c.take<double>((int64_t)bm * GMAX * KP);
     part_v[gi][0] = c.take<double>((int64_t)bv * GMAX * KP);
     part_v[gi][1] = c.take<double>((int64_t)bv * GMAX * KP);
+    fold[gi] = c.take<double>((int64_t)GMAX * KP);
     bmap_m[gi] = c.take<int2>(bm);
     bmap_v[gi] = c.take<int2>(bv);
   }
@@ -634,6 +644,7 @@ void Run::setup_solvers() {
     g.part_m = part_m[gi];
     g.part_v[0] = part_v[gi][0];
     g.part_v[1] = part_v[gi][1];
+    g.fold = fold[gi];
     if (gi == 1) {   // pressure Poisson: Kp dP = r (mixed: Kp d = refinement residual)
       g.nsys = 1;
       g.sptr = sp11;
@@ -694,7 +705,8 @@ void Run::setup_solvers() {
                           hipMemcpyHostToDevice, stream));
     S.L = KLaunch{kgroups + gi,      1, grp[gi].nsys, kept_m_for(grp[gi].n, grp[gi].nsys), mixed ? 1 : 0,
                   bmap_m[gi],        (int)maps_m[gi].size(),
-                  bmap_v[gi],        (int)maps_v[gi].size()};
+                  bmap_v[gi],        (int)maps_v[gi].size(),
+                  fold_for(grp[gi].n, grp[gi].nsys)};
     S.d_poll = poll + gi * GMAX;
     S.last_iters = 0;
   };

@@ -99,6 +99,7 @@ int status_to_code(int kstatus);
 int kept_m_for(int64_t n, int ns);
 int nblk_m_for(int64_t n, int ns);
 int nblk_v_for(int64_t n, int ns);
+int fold_for(int64_t n, int ns);   // KLaunch::fold for a group of n rows, ns systems
 // (group, block) map interleaving the groups block by block
 void build_bmap(const std::vector<int>& nblk, std::vector<int2>& bmap);
 // The blocks of a launch are dealt to the 8 XCDs in turn (block b runs on XCD
@@ -157,6 +158,7 @@ struct Run {
   KGroup* kgroups = nullptr;  // [3]: momentum, pressure, correction
   double* part_m[3] = {};     // per group (momentum, pressure, correction)
   double* part_v[3][2] = {};
+  double* fold[3] = {};       // folded totals per group
   int2* bmap_m[3] = {};
   int2* bmap_v[3] = {};
   KState* poll = nullptr;     // [3 * GMAX]
