@@ -108,9 +108,11 @@ int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap);
 /* CSR pattern (row pointer [rows+1], sorted column indices [nnz]). */
 int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
                       int32_t* col, int64_t cap_nnz);
-/* Row partition of the P1-P1 pattern into parts of at most rows_max rows
- * (64..2048) that the one-kernel-per-iteration Poisson CG uses (host data, for
- * inspection). Parts are compact patches of vertices (recursive coordinate
+/* Row partition of the P1-P1 pattern (the rows of Kp, the matrix of the
+ * pressure-increment Poisson problem, Section 2.2.1, eq. (9), second line)
+ * into parts of at most rows_max rows (64..2048) that the one-kernel-per-
+ * iteration Poisson CG uses (host data, for inspection; ownership stays with
+ * the mesh, the arrays are copied out). Parts are compact patches of vertices (recursive coordinate
  * bisection); rows are renumbered part by part ("part order"). sizes[0..4]
  * receives nparts, the halo length, the number of SELL-64 slices, the number
  * of entries and the largest own + halo count of a part. With non-NULL
@@ -319,7 +321,8 @@ int ipcs_kernel_times(ipcs_run r, double* ms, int64_t* launches, int32_t cap);
  * as before. Call between steps only. */
 int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_per_launch);
 
-/* The pressure Poisson CG form the run uses. *rows_max receives the part size
+/* The pressure Poisson CG form the run uses for Kp dP = r (eq. (9), second
+ * line; measurement and inspection). *rows_max receives the part size
  * of its row partition (0: two kernels per iteration, no partition), *nparts
  * the number of parts, *halo_rows the summed halo sizes (the rows a part reads
  * from other parts, once per part), *lds_rows the largest own + halo count of
