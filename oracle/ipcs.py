@@ -24,6 +24,12 @@ t = t0 + (n+1) dt is, in matrix form:
 
 Solvers: Jacobi-BiCGStab for step 1 (x0 = U^n with boundary values g),
 Jacobi-PCG for steps 2 (x0 = 0) and 3 (x0 = U*).
+
+With chorin=True the step is the non-incremental projection of Chorin and
+Temam, the scheme Section 2.2.1 states before IPCS (eq. (8)): the momentum
+step has no pressure term, the Poisson solve gives the new pressure itself
+(Kp P^{n+1} = -(rho/dt) sum_c D_c U*_c, the same sign reading as for IPCS),
+P^{n+1} is shifted to zero integral mean, and the correction uses P^{n+1}.
 """
 import numpy as np
 
@@ -32,11 +38,12 @@ from . import fem, krylov
 
 class Params:
     def __init__(self, nu, dt, rho=1.0, t0=0.0, tol_mom=1e-12, tol_p=1e-12,
-                 tol_corr=1e-12, maxit=20000, semi_implicit=False):
+                 tol_corr=1e-12, maxit=20000, semi_implicit=False, chorin=False):
         self.nu, self.dt, self.rho, self.t0 = float(nu), float(dt), float(rho), float(t0)
         self.tol_mom, self.tol_p, self.tol_corr = tol_mom, tol_p, tol_corr
         self.maxit = maxit
         self.semi_implicit = semi_implicit
+        self.chorin = chorin
 
 
 class IPCS:
@@ -99,7 +106,9 @@ class IPCS:
         else:
             A, A_el, dinv = self.A, self.A_el, self.dinv_A
         for c in range(S.dim):
-            b = self.M @ self.U[c] / prm.dt - self.G[c] @ self.P + F[c]
+            b = self.M @ self.U[c] / prm.dt + F[c]
+            if not prm.chorin:
+                b = b - self.G[c] @ self.P
             if not prm.semi_implicit:
                 b = b - C @ self.U[c]
             b = fem.lift(A, b, self.bmask, g[c])
@@ -136,7 +145,7 @@ class IPCS:
         dP, it_p = self.pressure(Ustar)
         Unew, it_c = self.correction(Ustar, dP, g)
         self.U = Unew
-        self.P = self.P + dP
+        self.P = dP if self.prm.chorin else self.P + dP
         self.t = t
         self.iters.append((it_m, it_p, it_c))
         return self.U, self.P

@@ -10,7 +10,11 @@
 * convergence orders of the Taylor-Green problem: velocity -> 3, pressure -> 2
   (the theoretical Taylor-Hood orders, also observed by the paper's table
   "convergence_ipcs"), with a guard that the time error is negligible;
-* Taylor-Green kinetic-energy decay rate e^{-4 nu k^2 t}.
+* Taylor-Green kinetic-energy decay rate e^{-4 nu k^2 t};
+* the Chorin-Temam projection (the non-incremental scheme stated before IPCS):
+  its step does not depend on P^n at all and equals the IPCS step from P^n = 0
+  (both bitwise), its velocity error is first order in dt, and IPCS is more
+  accurate (the paper's reason for IPCS).
 """
 import numpy as np
 import pytest
@@ -130,3 +134,45 @@ def test_golden_ipcs_table_orders_are_the_theoretical_ones():
     ep = [r[2] for r in rows]
     assert abs(np.log2(eu[-2] / eu[-1]) - 3) < 0.05
     assert abs(np.log2(ep[-2] / ep[-1]) - 2) < 0.1
+
+
+def _tg_pair(chorin, n=8, nu=0.05, dt=0.02):
+    S = fem.Space(*mesh.unit_square(n, n))
+    pb = problems.TaylorGreen2D(np.pi, nu)
+    return S, pb, ipcs.IPCS(S, pb, ipcs.Params(nu=nu, dt=dt, tol_mom=1e-13, tol_p=1e-13,
+                                               tol_corr=1e-13, chorin=chorin))
+
+
+def test_chorin_step_ignores_old_pressure_and_equals_ipcs_from_zero():
+    S, pb, a = _tg_pair(True)
+    _, _, b = _tg_pair(True)
+    _, _, c = _tg_pair(False)
+    rng = np.random.default_rng(3)
+    b.set_state(a.U, a.normalize(rng.standard_normal(S.N1)), a.t)
+    c.set_state(a.U, np.zeros(S.N1), a.t)
+    for o in (a, b, c):
+        o.step()
+    np.testing.assert_array_equal(a.U, b.U)
+    np.testing.assert_array_equal(a.P, b.P)
+    np.testing.assert_array_equal(a.U, c.U)
+    np.testing.assert_array_equal(a.P, c.P)
+    # and it is not IPCS: from the interpolated pressure the two schemes differ
+    _, _, d = _tg_pair(False)
+    d.step()
+    assert np.linalg.norm(d.U - a.U) > 1e-6 * np.linalg.norm(a.U)
+
+
+def test_chorin_is_first_order_in_time_and_less_accurate_than_ipcs():
+    T, n = 0.16, 16
+    err = {}
+    for chorin in (False, True):
+        for dt in (0.04, 0.02):
+            S, pb, o = _tg_pair(chorin, n=n, dt=dt)
+            for _ in range(int(round(T / dt))):
+                o.step()
+            ue = pb.u(S.x2, o.t).T
+            err[chorin, dt] = np.linalg.norm(o.U - ue) / np.linalg.norm(ue)
+    order = np.log2(err[True, 0.04] / err[True, 0.02])
+    assert 0.6 <= order <= 1.3, order
+    for dt in (0.04, 0.02):
+        assert err[False, dt] * 5 <= err[True, dt], (dt, err)
