@@ -106,9 +106,10 @@ class IPCS:
         else:
             A, A_el, dinv = self.A, self.A_el, self.dinv_A
         for c in range(S.dim):
-            b = self.M @ self.U[c] / prm.dt + F[c]
+            b = self.M @ self.U[c] / prm.dt
             if not prm.chorin:
                 b = b - self.G[c] @ self.P
+            b = b + F[c]
             if not prm.semi_implicit:
                 b = b - C @ self.U[c]
             b = fem.lift(A, b, self.bmask, g[c])
