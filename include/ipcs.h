@@ -159,6 +159,14 @@ enum { IPCS_FP64 = 0, IPCS_MIXED = 1 };
  * (Section 2.2.1, eq. (9), first line, with the convection term linearized
  * at u^n). */
 enum { IPCS_CONV_EXPLICIT = 0, IPCS_CONV_SEMI_IMPLICIT = 1 };
+/* Projection schemes of Section 2.2.1. IPCS_SCHEME_IPCS: eq. (9), the
+ * incremental pressure correction (momentum with -(p^n, div v), Poisson for
+ * the increment, P^{n+1} = P^n + dP). IPCS_SCHEME_CHORIN: the non-incremental
+ * projection of Chorin and Temam stated before it (eq. (8)): no pressure term
+ * in the momentum step, the Poisson solve gives P^{n+1} itself (shifted to
+ * zero integral mean) and the correction uses it; the right-hand-side sign
+ * is read as for IPCS. */
+enum { IPCS_SCHEME_IPCS = 0, IPCS_SCHEME_CHORIN = 1 };
 
 typedef struct {
   double nu;            /* kinematic viscosity                                 */
@@ -183,6 +191,8 @@ typedef struct {
                            * the same with that part size (IPCS_E_CAPACITY if
                            * it does not fit); -1 two kernels per iteration
                            * (SpMV, then the vector update)                  */
+  int32_t scheme;       /* IPCS_SCHEME_IPCS (default) or IPCS_SCHEME_CHORIN    */
+  int32_t reserved;
 } ipcs_params;
 
 /* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12

@@ -75,6 +75,7 @@ void check_params(const ipcs_params* p) {
   need(p->poisson_part_rows == 0 || p->poisson_part_rows == -1 ||
            (p->poisson_part_rows >= 64 && p->poisson_part_rows <= 2048),
        "poisson_part_rows must be 0, -1 or in [64, 2048]");
+  need(p->scheme == IPCS_SCHEME_IPCS || p->scheme == IPCS_SCHEME_CHORIN, "unknown scheme");
 }
 }  // namespace
 

@@ -243,10 +243,11 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
-// b_c = sa E U_c - G_c P + F_c with Dirichlet lifting (explicit: E = M/dt -
-// C(U^n), sa = 1; semi-implicit: E = M, sa = 1/dt)
+// b_c = sa E U_c - sg G_c P + F_c with Dirichlet lifting (explicit: E = M/dt -
+// C(U^n), sa = 1; semi-implicit: E = M, sa = 1/dt; sg = 1 for IPCS, 0 for the
+// Chorin projection, whose momentum step has no pressure term)
 void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const void* E, double sa, const double* U,
+                  const int32_t* col22, const void* E, double sa, double sg, const double* U,
                   const int32_t* sp21,
                   const int32_t* col21, void* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,

@@ -196,16 +196,16 @@ static void rhs_p2_launch(hipStream_t s, int dim, int64_t n2, const int32_t* sp2
 }
 
 void rhs_momentum(hipStream_t s, int dim, bool fp32, int64_t n2, const int32_t* sp22,
-                  const int32_t* col22, const void* E, double sa, const double* U,
+                  const int32_t* col22, const void* E, double sa, double sg, const double* U,
                   const int32_t* sp21,
                   const int32_t* col21, void* const* Gc, const double* P, const double* F,
                   const int32_t* lift_ptr, const int32_t* lift_col, const double* liftA,
                   const uint8_t* bmask, const double* gfull, double* b) {
   if (fp32)
-    rhs_p2_launch<float>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, 1.0, F,
+    rhs_p2_launch<float>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, sg, F,
                          lift_ptr, lift_col, liftA, bmask, gfull, b);
   else
-    rhs_p2_launch<double>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, 1.0, F,
+    rhs_p2_launch<double>(s, dim, n2, sp22, col22, E, U, sa, sp21, col21, Gc, P, sg, F,
                           lift_ptr, lift_col, liftA, bmask, gfull, b);
 }
 

@@ -929,9 +929,10 @@ void Run::asm_phase() {
     lift_values(stream, mixed, nlift, lift_slot, E, K, 1.0, prm.nu, liftA);
     A_dirty = false;
   }
-  rhs_momentum(stream, dim, mixed, n2, sp22, col22, semi ? M : E, semi ? 1.0 / prm.dt : 1.0, U,
-               sp21, col21, Gc, P, has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask, gfull,
-               bU);
+  const double sg = prm.scheme == IPCS_SCHEME_CHORIN ? 0.0 : 1.0;
+  rhs_momentum(stream, dim, mixed, n2, sp22, col22, semi ? M : E, semi ? 1.0 / prm.dt : 1.0, sg,
+               U, sp21, col21, Gc, P, has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask,
+               gfull, bU);
   copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
   HIP_OK(hipEventRecord(ev[1], stream));
 }
@@ -961,9 +962,12 @@ void Run::correction_rhs() {
                         stream));
 }
 
-// P^{n+1} = P^n + dP, U^{n+1} (enqueued).
+// P^{n+1} = P^n + dP (IPCS) or dP (Chorin), U^{n+1} (enqueued).
 void Run::correction_commit() {
-  axpy_inplace(stream, n1, 1.0, dP, P);
+  if (prm.scheme == IPCS_SCHEME_CHORIN)
+    HIP_OK(hipMemcpyAsync(P, dP, sizeof(double) * n1, hipMemcpyDeviceToDevice, stream));
+  else
+    axpy_inplace(stream, n1, 1.0, dP, P);
   HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
   HIP_OK(hipEventRecord(ev[4], stream));
 }

@@ -37,11 +37,12 @@ def oracle_space(dim, n):
 
 
 def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=True,
-              arrays=None, semi=False, **kw):
+              arrays=None, semi=False, chorin=False, **kw):
     """Oracle IPCS object and library run for the same problem. With
     same_state the library starts from the oracle's initial arrays. arrays =
     (x, cells) replaces the structured n-mesh by that mesh on both sides; semi
-    selects the semi-implicit convection form on both sides."""
+    selects the semi-implicit convection form and chorin the Chorin-Temam
+    projection on both sides."""
     if arrays is None:
         S = oracle_space(dim, n)
         m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
@@ -50,9 +51,11 @@ def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=Tr
         m = I.Mesh.from_arrays(*arrays)
     pb = oracle_problem(kind, dim, nu, k)
     o = ipcs.IPCS(S, pb, ipcs.Params(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol,
-                                     tol_corr=tol, semi_implicit=semi))
+                                     tol_corr=tol, semi_implicit=semi, chorin=chorin))
     if semi:
         kw["convection"] = I.IPCS_CONV_SEMI_IMPLICIT
+    if chorin:
+        kw["scheme"] = I.IPCS_SCHEME_CHORIN
     p = I.ipcs_params_default(nu=nu, dt=dt, t0=t0, tol_mom=tol, tol_p=tol, tol_corr=tol, **kw)
     r = I.Run(m, p)
     prm = (k,) if kind == "tg" else ()

@@ -108,6 +108,8 @@ def test_invalid_arguments_are_reported():
         I.ipcs_run_workspace_bytes(m.h, p)
     with pytest.raises(I.IpcsError):
         I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(convection=5))
+    with pytest.raises(I.IpcsError):
+        I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(scheme=2))
     semi = I.ipcs_params_default(convection=I.IPCS_CONV_SEMI_IMPLICIT)
     assert I.ipcs_run_workspace_bytes(m.h, semi) == I.ipcs_run_workspace_bytes(
         m.h, I.ipcs_params_default())
