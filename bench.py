@@ -37,6 +37,7 @@ KERNELS = {
     "bicg_update_x": (7, "kernels_krylov.hip"),
     "pcg_update_m": (8, "kernels_krylov.hip"),
     "pcg_fused_p": (9, "kernels_fcg.hip"),
+    "asm_sum": (10, "kernels_asm.hip"),
 }
 
 
@@ -66,9 +67,13 @@ def kernel_bytes(kernel, c, dim, vsz=8):
         return (vsz + 4) * nnz22 + sl2 + dim * 2 * 8 * n2
     if kernel == "pcg_update_m":   # dinv; x, r, p, s, w in, x, r, p, s, u out each
         return 8 * n2 + dim * 10 * 8 * n2
-    if kernel == "asm_conv":       # E out, U in, cell DOFs, vertex coordinates
-        nloc = 6 if dim == 2 else 10
+    nloc = 6 if dim == 2 else 10
+    if kernel == "asm_conv" and dim == 2:   # row-owner: E out; U, cell DOFs, vertices in
         return vsz * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
+    if kernel == "asm_conv":       # 3D cell pass: local matrices out; U, DOFs, vertices in
+        return vsz * nloc * nloc * c.nc + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
+    if kernel == "asm_sum":        # local matrices in, E out, incidences and slots in
+        return vsz * nloc * nloc * c.nc + vsz * nnz22 + 4 * nloc * c.nc + nloc * nloc * c.nc
     raise KeyError(kernel)
 
 
@@ -138,12 +143,12 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
     sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
            "pcg_fused_p": r"k_fcg_iter<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
-           "asm_conv": r"OpConv<"}[kernel]
+           "asm_conv": r"OpConv<|k_conv_cells<", "asm_sum": r"k_asm_local<"}[kernel]
     copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rr = rows(d, counter)
-        k = [v for n, v in rr if sym.replace(" ", "") in n.replace(" ", "")]
+        k = [v for n, v in rr if re.search(sym, n.replace(" ", ""))]
         cp = [v for n, v in rr if copy_re.search(n) and not n.startswith("void ipcs")]
         if not k or not cp:
             raise SystemExit(f"pmc-summary: no {counter} rows for {kernel} or the copy kernel in {d}")

@@ -303,7 +303,9 @@ int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_s
 enum {                            /* kernels of the step, for the timing hooks       */
   IPCS_KERNEL_PCG_SPMV_P = 0,     /* Poisson CG: w = Kp u, partial u.w               */
   IPCS_KERNEL_PCG_UPDATE_P = 1,   /* Poisson CG: p, s, x, r, u updates; r.u, r.r     */
-  IPCS_KERNEL_ASM_CONV = 2,       /* convection assembly E = M/dt - C(U^n)           */
+  IPCS_KERNEL_ASM_CONV = 2,       /* convection assembly E = M/dt -+ C(U^n): row-
+                                   * owner (2D), or the cell-batched local matrices
+                                   * (3D, first pass)                               */
   IPCS_KERNEL_BICG_SPMV = 3,      /* momentum BiCGStab: v = A phat, rhat.v           */
   IPCS_KERNEL_PCG_SPMV_M = 4,     /* correction CG: w = M u, u.w (all components)   */
   IPCS_KERNEL_BICG_SPMV_T = 5,    /* momentum BiCGStab: t = A shat, t.s, t.t, ...    */
@@ -312,7 +314,9 @@ enum {                            /* kernels of the step, for the timing hooks  
   IPCS_KERNEL_PCG_UPDATE_M = 8,   /* correction CG: p, s, x, r, u updates            */
   IPCS_KERNEL_PCG_FUSED_P = 9,    /* Poisson CG, one kernel per iteration: update,
                                    * halo recomputation, w = Kp u; r.u, r.r, w.u    */
-  IPCS_NKERNEL = 10
+  IPCS_KERNEL_ASM_SUM = 10,       /* convection assembly, second pass (3D): the
+                                   * cells' local rows added into the matrix rows   */
+  IPCS_NKERNEL = 11
 };
 /* Measurement hook (not part of the method): from the next call on, every
  * launch of a kernel whose bit (1 << IPCS_KERNEL_*) is set in mask is

@@ -146,10 +146,18 @@ struct Builtin {
 // Assembly (kernels_asm.hip). bs = rows per block, lds = dynamic LDS bytes;
 // fp32 selects FP32 arithmetic and FP32 outputs (mixed form).
 void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
-// E = M/dt + cs C(U): cs = -1 gives the explicit form's E = M/dt - C(U^n),
-// cs = +1 the semi-implicit form's M/dt + C(U^n)
+// E = M/dt + cs C(U) (cs = -1: the explicit form's E = M/dt - C(U^n); cs = +1:
+// the semi-implicit form's M/dt + C(U^n)), row-owner in one pass (asm_conv),
+// or in two passes: asm_conv_cells forms
+// the local matrices of all nc cells into buf ([nc][n_loc][n_loc] values of the
+// working type, cell-batched), asm_local_sum adds them into the rows of
+// a.out[0] (row-owner, conflict-free).
 void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
               const double* U, int64_t n2, double inv_dt, double cs);
+void asm_conv_cells(int dim, bool fp32, hipStream_t s, const RowAsm& a, int64_t nc,
+                    const double* U, int64_t n2, double inv_dt, double cs, void* buf);
+void asm_local_sum(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
+                   const void* buf);
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);

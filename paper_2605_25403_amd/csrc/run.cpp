@@ -454,6 +454,7 @@ void Run::layout(Carver& c) {
   M = vals(ne22);
   K = vals(ne22);
   E = vals(ne22);
+  Eloc = dim == 3 ? c.take<char>(nc * (int64_t)m.nloc2 * m.nloc2 * vsz) : nullptr;
   Ael = vals(ne22);
   Mel = vals(ne22);
   Kp = vals(ne11);
@@ -920,10 +921,19 @@ void Run::asm_phase() {
     asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
     has_F = true;
   }
-  timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
-    asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt,
-             semi ? 1.0 : -1.0);
-  });
+  // 3D: cell-batched local matrices, then their row-owner sum; 2D: one
+  // row-owner pass (cheaper where a cell has 6 rows and 7 quadrature points)
+  const double cs = semi ? 1.0 : -1.0;
+  if (dim == 3) {
+    timer.run(stream, IPCS_KERNEL_ASM_CONV,
+              [&] { asm_conv_cells(dim, mixed, stream, a22, nc, U, n2, 1.0 / prm.dt, cs, Eloc); });
+    timer.run(stream, IPCS_KERNEL_ASM_SUM,
+              [&] { asm_local_sum(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, Eloc); });
+  } else {
+    timer.run(stream, IPCS_KERNEL_ASM_CONV, [&] {
+      asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt, cs);
+    });
+  }
   if (semi) {
     form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, E, K, 1.0, prm.nu, Ael, dinvA);
     lift_values(stream, mixed, nlift, lift_slot, E, K, 1.0, prm.nu, liftA);
@@ -1062,7 +1072,8 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   const bool mom = kernel == IPCS_KERNEL_BICG_SPMV || kernel == IPCS_KERNEL_BICG_SPMV_T ||
                    kernel == IPCS_KERNEL_BICG_UPDATE_S || kernel == IPCS_KERNEL_BICG_UPDATE_X;
   const bool corr = kernel == IPCS_KERNEL_PCG_SPMV_M || kernel == IPCS_KERNEL_PCG_UPDATE_M;
-  const KSet* S = mom ? &set_mom : corr ? &set_corr : kernel == IPCS_KERNEL_ASM_CONV ? nullptr : &set_p;
+  const bool assembly = kernel == IPCS_KERNEL_ASM_CONV || kernel == IPCS_KERNEL_ASM_SUM;
+  const KSet* S = mom ? &set_mom : corr ? &set_corr : assembly ? nullptr : &set_p;
   const bool fused = kernel == IPCS_KERNEL_PCG_FUSED_P;
   if (fused != (S == &set_p && set_p.fused) && S == &set_p)
     fail(IPCS_E_INVALID, fused ? "this run's Poisson CG is not the fused form"
@@ -1118,9 +1129,15 @@ double Run::profile_kernel(int kernel, int nlaunch) {
     switch (kernel) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
       case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L, 0); break;
-      case IPCS_KERNEL_ASM_CONV:
-        asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt,
-                 prm.convection == IPCS_CONV_SEMI_IMPLICIT ? 1.0 : -1.0);
+      case IPCS_KERNEL_ASM_CONV: {
+        const double cs = prm.convection == IPCS_CONV_SEMI_IMPLICIT ? 1.0 : -1.0;
+        if (dim == 3) asm_conv_cells(dim, mixed, stream, a22, nc, U, n2, 1.0 / prm.dt, cs, Eloc);
+        else asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt, cs);
+        break;
+      }
+      case IPCS_KERNEL_ASM_SUM:
+        if (dim != 3) fail(IPCS_E_INVALID, "the two-pass convection assembly is used in 3D only");
+        asm_local_sum(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, Eloc);
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;
       case IPCS_KERNEL_PCG_SPMV_M: pcg_spmv_only(stream, set_corr.L); break;

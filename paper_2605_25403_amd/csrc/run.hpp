@@ -144,6 +144,7 @@ struct Run {
   int vsz = 8;
   void *M = nullptr, *K = nullptr, *E = nullptr, *Ael = nullptr, *Mel = nullptr;
   void *Kp = nullptr, *Dc[3] = {}, *Gc[3] = {};
+  void* Eloc = nullptr;       // local matrices of the convection operator [nc][nloc][nloc]
   double* Kp64 = nullptr;     // FP64 Kp (the same array as Kp in the FP64 form)
   double *rIR = nullptr, *dIR = nullptr;   // mixed form: refinement residual, correction
   double ir_c = 0.0;          // mixed form: reduction per refinement pass seen last step

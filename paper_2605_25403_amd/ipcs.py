@@ -42,7 +42,8 @@ IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_PCG_SPMV_M = 3, 4
 IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_S, IPCS_KERNEL_BICG_UPDATE_X = 5, 6, 7
 IPCS_KERNEL_PCG_UPDATE_M = 8
 IPCS_KERNEL_PCG_FUSED_P = 9
-IPCS_NKERNEL = 10
+IPCS_KERNEL_ASM_SUM = 10
+IPCS_NKERNEL = 11
 
 
 class IpcsError(RuntimeError):
