@@ -141,7 +141,7 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
         return out
 
     sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
-           "pcg_fused_p": r"k_fcg_iter<",
+           "pcg_fused_p": r"k_fcg_iter1?<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
            "asm_conv": r"OpConv<|k_conv_cells<", "asm_sum": r"k_asm_local<"}[kernel]
     copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)

@@ -131,6 +131,57 @@ __device__ __forceinline__ void load_partials(const double* part, int nb, double
   }
 }
 
+// load_partials in two steps, for kernels that issue other loads in between:
+// partials_first loads this thread's first chunk (QC records) without using
+// it, partials_rest adds that chunk and then the remaining ones, in the order
+// of load_partials (same totals, bitwise).
+template <int NS, int K>
+__device__ __forceinline__ void partials_first(const double* part, int nb,
+                                               double (&x)[4][NS * K]) {
+  const gptr<const double> P = G(part);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = (int)threadIdx.x + q * KBS;
+    const int bc = b < nb ? b : nb - 1;
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) x[q][j * K + k] = P[part_index(j, k, nb, bc)];
+  }
+}
+template <int NS, int K>
+__device__ __forceinline__ void partials_rest(const double* part, int nb,
+                                              const double (&x)[4][NS * K], double* v) {
+  constexpr int QC = 4;
+#pragma unroll
+  for (int n = 0; n < NS * K; ++n) v[n] = 0.0;
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const bool ok = (int)threadIdx.x + q * KBS < nb;
+#pragma unroll
+    for (int n = 0; n < NS * K; ++n) v[n] += ok ? x[q][n] : 0.0;
+  }
+  const gptr<const double> P = G(part);
+  for (int q0 = QC; q0 * KBS < nb; q0 += QC) {
+    double y[QC][NS * K];
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const int b = (int)threadIdx.x + (q0 + q) * KBS;
+      const int bc = b < nb ? b : nb - 1;
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[q][j * K + k] = P[part_index(j, k, nb, bc)];
+    }
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const bool ok = (int)threadIdx.x + (q0 + q) * KBS < nb;
+#pragma unroll
+      for (int n = 0; n < NS * K; ++n) v[n] += ok ? y[q][n] : 0.0;
+    }
+  }
+}
+
 // Block-reduce acc[j*K + k] (KBS threads) and store them as the partials of
 // block lb of a kernel with nb blocks.
 template <int NS, int K>

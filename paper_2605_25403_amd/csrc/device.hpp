@@ -215,10 +215,24 @@ void bicg_update_s_only(hipStream_t s, const KLaunch& L, int par);    // s, shat
 void bicg_spmv_t_only(hipStream_t s, const KLaunch& L);               // t = A shat
 void bicg_update_x_only(hipStream_t s, const KLaunch& L, int par);    // x, r, p, phat
 
+// One block of a one-group fused CG launch, addressed by the block index
+// alone: the part's row and halo ranges and, for each of its slices k, the
+// first entry sl[k].x and the width sl[k].y (slots k >= ns repeat the last
+// slice's start with width 0, so every address is valid without a test), so
+// that a block reaches its matrix entries one dependent load after it starts.
+constexpr int FBLK_SL = 32;   // parts of up to FBLK_SL * 64 rows
+struct FBlk {
+  int32_t lb, p0, own, h0, nh, ns, pad[2];
+  int2 sl[FBLK_SL];
+};
+
 // One-kernel-per-iteration Jacobi-CG (kernels_fcg.hip) over ngroups FGroups
 // with the same rows per thread ept (parts have at most KBS * ept rows);
 // bmap maps blocks to (group, part); lds = dynamic LDS bytes (8 per local
-// row of the largest part, own + halo).
+// row of the largest part, own + halo). A one-group launch may also carry
+// blk (one FBlk per block, in bmap's order), hfirst (per block, the first KBS
+// halo rows, 0 past the halo) and a host copy of its group: its iterations
+// then take the group by value and the per-block data by block index.
 struct FLaunch {
   const FGroup* groups;
   int ngroups;
@@ -227,6 +241,9 @@ struct FLaunch {
   const int2* bmap;
   int nblocks;
   size_t lds;
+  const FBlk* blk;
+  const int32_t* hfirst;
+  FGroup one;
 };
 // Mode 0: x and b to part order, r = b - A x, w = A D^{-1} r, status decision.
 // Mode 1 (systems PENDING or RESTART): the same from the current iterate.

@@ -211,35 +211,19 @@ __global__ void __launch_bounds__(KBS) k_fcg_decide(const FGroup* groups, int mo
 // every row, the first halo row's vectors), all before the first wait, so that
 // a block spends one memory latency before the reduction instead of several.
 // PF: the first chunk is kept in registers (parts of at most 4 KBS rows).
+// sb[e], sw[e]: entry offset (with the lane) and width of this wave's slice
+// of rows e; c0: the halo row of this thread (row 0 past the halo).
 template <int EPT, class VT>
-__global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const int2* bmap,
-                                                  int par) {
-  FGROUP_HEAD(bmap)
+__device__ __forceinline__ void fcg_iter_body(const FGroup& g, int lb, int p0, int own, int h0,
+                                              int nh, const int (&sb)[EPT], const int (&sw)[EPT],
+                                              int c0, int par, double* loc, double* sh) {
   constexpr bool PF = EPT <= 4;
-  extern __shared__ double loc[];
-  __shared__ double sh[(KBS / 64) * 3];
-  const int s0 = g.slice_ptr[lb], s1 = g.slice_ptr[lb + 1];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const gptr<const VT> val = G(static_cast<const VT*>(g.val));
-  // index words: this wave's slices (waves past a part's last slice re-read
-  // it and discard the result) and the first halo row
-  int sb[EPT], sw[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int sl0 = s0 + (KBS / 64) * e + wv;
-    const int sl = sl0 < s1 ? sl0 : s1 - 1;
-    const int a = G(g.sptr)[sl], z = G(g.sptr)[sl + 1];
-    sb[e] = a + lane;
-    sw[e] = sl0 < s1 ? (z - a) >> 6 : 0;
-  }
   const bool h_in = (int)threadIdx.x < nh;
-  // (the halo array always holds at least one word; threads past the halo
-  // use row 0 and discard what they read)
-  const int c0r = G(g.halo)[h_in ? h0 + (int)threadIdx.x : 0];
-  const int c0 = h_in ? c0r : 0;
+  const gptr<const VT> val = G(static_cast<const VT*>(g.val));
   // own rows (rows past the part's end read its first row and are discarded)
-  const gptr<const double> r0 = G((const double*)g.r[par]), s0v = G((const double*)g.s[par]),
-                           w0 = G((const double*)g.w[par]), dv = G(g.dinv);
+  const gptr<const double> r0 = G((const double*)(par ? g.r[1] : g.r[0])),
+                           s0v = G((const double*)(par ? g.s[1] : g.s[0])),
+                           w0 = G((const double*)(par ? g.w[1] : g.w[0])), dv = G(g.dinv);
   double di[EPT], xi[EPT], ri[EPT], pi[EPT], si[EPT], wi[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -256,10 +240,12 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
   const int status = st->status;
   const double g_old = st->sc[par ^ 1], a_old = st->alpha[par ^ 1];
   const double lim = st->tol2 * st->bb;
-  double t[3];
-  load_partials<1, 3>(g.part[par], g.nparts, t);
+  const double* part_in = par ? g.part[1] : g.part[0];
+  double px[4][3];
+  partials_first<1, 3>(part_in, g.nparts, px);
   // what depends on the index words: the first chunk of matrix entries and
-  // the first halo row's vectors, used after the reduction
+  // the first halo row's vectors, used after the reduction (issued before the
+  // partial sums are added, which waits for every load before it)
   int mc[PF ? EPT : 1][8];
   double mv[PF ? EPT : 1][8];
   if constexpr (PF) {
@@ -272,8 +258,12 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
         mv[e][q] = (double)val[sb[e] + 64 * kk];
       }
   }
+  // keep the loads above in flight here: the scheduler would otherwise sink
+  // them below the waits for the halo row and the partial sums
+  __builtin_amdgcn_sched_barrier(0);
   const double hr = r0[c0], hs = s0v[c0], hw = w0[c0], hd = dv[c0];
-
+  double t[3];
+  partials_rest<1, 3>(part_in, g.nparts, px, t);
   block_sum_t<KBS, 3>(t, sh);
   if (status != KS_RUN) return;
   const gptr<KState> stw = G(g.st);
@@ -303,7 +293,7 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
     stw->rr = rr;
     stw->it += 1;
   }
-  const gptr<double> r1 = G(g.r[par ^ 1]), s1v = G(g.s[par ^ 1]);
+  const gptr<double> r1 = G(par ? g.r[0] : g.r[1]), s1v = G(par ? g.s[0] : g.s[1]);
   double rn[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -358,7 +348,7 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
       for (int q = 0; q < 8; ++q) y[e] += k + q < w ? a[q] * loc[c[q]] : 0.0;
     }
   }
-  const gptr<double> w1 = G(g.w[par ^ 1]);
+  const gptr<double> w1 = G(par ? g.w[0] : g.w[1]);
   double acc[3] = {};
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -370,7 +360,57 @@ __global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const in
     acc[1] += rn[e] * rn[e];
     acc[2] += y[e] * u;
   }
-  store_partials<1, 3>(acc, g.part[par ^ 1], g.nparts, lb, sh);
+  store_partials<1, 3>(acc, par ? g.part[0] : g.part[1], g.nparts, lb, sh);
+}
+
+// Groups and parts through the block map (any number of groups).
+template <int EPT, class VT>
+__global__ void __launch_bounds__(KBS) k_fcg_iter(const FGroup* groups, const int2* bmap,
+                                                  int par) {
+  FGROUP_HEAD(bmap)
+  extern __shared__ double loc[];
+  __shared__ double sh[(KBS / 64) * 3];
+  const int s0 = g.slice_ptr[lb], s1 = g.slice_ptr[lb + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // index words: this wave's slices (waves past a part's last slice re-read
+  // it and discard the result) and the first halo row
+  int sb[EPT], sw[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int sl0 = s0 + (KBS / 64) * e + wv;
+    const int sl = sl0 < s1 ? sl0 : s1 - 1;
+    const int a = G(g.sptr)[sl], z = G(g.sptr)[sl + 1];
+    sb[e] = a + lane;
+    sw[e] = sl0 < s1 ? (z - a) >> 6 : 0;
+  }
+  // (the halo array always holds at least one word; threads past the halo
+  // use row 0 and discard what they read)
+  const bool h_in = (int)threadIdx.x < nh;
+  const int c0r = G(g.halo)[h_in ? h0 + (int)threadIdx.x : 0];
+  fcg_iter_body<EPT, VT>(g, lb, p0, own, h0, nh, sb, sw, h_in ? c0r : 0, par, loc, sh);
+}
+
+// One group, passed by value, and one FBlk per block: the slice offsets and
+// the first halo row come one dependent load after the block starts, where
+// the block map, the group and the part tables take three.
+template <int EPT, class VT>
+__global__ void __launch_bounds__(KBS) k_fcg_iter1(const FGroup g, const FBlk* blk,
+                                                   const int32_t* hfirst, int par) {
+  extern __shared__ double loc[];
+  __shared__ double sh[(KBS / 64) * 3];
+  const FBlk& B = blk[blockIdx.x];
+  const int lb = B.lb, p0 = B.p0, own = B.own, h0 = B.h0, nh = B.nh;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  static_assert((KBS / 64) * EPT <= FBLK_SL, "slice slots of an FBlk");
+  int sb[EPT], sw[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int2 d = B.sl[(KBS / 64) * e + wv];
+    sb[e] = d.x + lane;
+    sw[e] = d.y;
+  }
+  const int c0 = G(hfirst)[(size_t)blockIdx.x * KBS + threadIdx.x];
+  fcg_iter_body<EPT, VT>(g, lb, p0, own, h0, nh, sb, sw, c0, par, loc, sh);
 }
 
 // x (original order) := part-order iterate; b == 0 systems: x := 0
@@ -434,8 +474,12 @@ void fcg_start(hipStream_t s, const FLaunch& L, int mode, int par, int launched)
 
 void fcg_iter(hipStream_t s, const FLaunch& L, int par) {
   with_ept_vt(L, [&](auto E, auto V) {
-    launch(k_fcg_iter<FEPT, FVT>, dim3(L.nblocks), dim3(KBS), (uint32_t)L.lds, s, L.groups,
-           L.bmap, par);
+    if (L.blk)
+      launch(k_fcg_iter1<FEPT, FVT>, dim3(L.nblocks), dim3(KBS), (uint32_t)L.lds, s, L.one,
+             L.blk, L.hfirst, par);
+    else
+      launch(k_fcg_iter<FEPT, FVT>, dim3(L.nblocks), dim3(KBS), (uint32_t)L.lds, s, L.groups,
+             L.bmap, par);
   });
   HIP_LAUNCH_OK();
 }

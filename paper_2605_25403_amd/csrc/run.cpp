@@ -399,6 +399,7 @@ constexpr int kFcgRows = 384;
 void Run::choose_poisson_form() {
   pp.reset();
   fcg_ept = 0;
+  f_blk_ok = false;
   const int req = prm.poisson_part_rows;
   if (req < 0) return;
   auto q = mesh->parts11(req > 0 ? req : kFcgRows);
@@ -417,6 +418,10 @@ void Run::choose_poisson_form() {
       fcg_ept = e;
       break;
     }
+  int most_slices = 0;
+  for (int p = 0; p < q->nparts; ++p)
+    most_slices = std::max(most_slices, q->slice_ptr[p + 1] - q->slice_ptr[p]);
+  f_blk_ok = most_slices <= FBLK_SL;
 }
 
 void Run::layout(Carver& c) {
@@ -515,6 +520,8 @@ void Run::layout(Carver& c) {
     for (int k = 0; k < 2; ++k) f_part[k] = c.take<double>((int64_t)KP * q.nparts);
     f_part_s = c.take<double>((int64_t)KP * q.nparts);
     f_bmap = c.take<int2>(q.nparts);
+    f_blk = c.take<FBlk>(q.nparts);
+    f_hfirst = c.take<int32_t>((int64_t)KBS * q.nparts);
     fgroup = c.take<FGroup>(1);
   }
   spart = c.take<double>(8192 * 2);
@@ -581,7 +588,29 @@ void Run::upload_mesh() {
     for (int p = 0; p < q.nparts; ++p) bm[p] = make_int2(0, p);
     xcd_order(bm);
     up(stream, f_bmap, bm);
-    // bm is a stack copy: the transfer must end before it goes away
+    // per-block descriptors and first halo rows, in the block map's order
+    std::vector<FBlk> blk(q.nparts);
+    std::vector<int32_t> hf((size_t)KBS * q.nparts, 0);
+    for (int b = 0; b < q.nparts; ++b) {
+      const int lb = bm[b].y;
+      FBlk& d = blk[b];
+      std::memset(&d, 0, sizeof(d));
+      d.lb = lb;
+      d.p0 = q.part_ptr[lb];
+      d.own = q.part_ptr[lb + 1] - d.p0;
+      d.h0 = q.halo_ptr[lb];
+      d.nh = q.halo_ptr[lb + 1] - d.h0;
+      const int s0 = q.slice_ptr[lb];
+      d.ns = q.slice_ptr[lb + 1] - s0;
+      for (int k = 0; k < FBLK_SL; ++k) {
+        const int sl = s0 + std::min(k, d.ns - 1);
+        d.sl[k] = make_int2(q.sptr[sl], k < d.ns ? (q.sptr[sl + 1] - q.sptr[sl]) / 64 : 0);
+      }
+      for (int t = 0; t < std::min(d.nh, KBS); ++t) hf[(size_t)b * KBS + t] = q.halo[d.h0 + t];
+    }
+    up(stream, f_blk, blk);
+    up(stream, f_hfirst, hf);
+    // bm, blk, hf are stack copies: the transfers must end before they go away
     HIP_OK(hipStreamSynchronize(stream));
   }
 }
@@ -749,6 +778,11 @@ void Run::setup_solvers() {
                           stream));
     set_p.F = FLaunch{fgroup, 1, fcg_ept, mixed ? 1 : 0, f_bmap, pp->nparts,
                       sizeof(double) * (size_t)pp->lds_max};
+    if (f_blk_ok) {
+      set_p.F.blk = f_blk;
+      set_p.F.hfirst = f_hfirst;
+      set_p.F.one = f;
+    }
   }
   const int kid_mom[4] = {IPCS_KERNEL_BICG_SPMV, IPCS_KERNEL_BICG_UPDATE_S,
                           IPCS_KERNEL_BICG_SPMV_T, IPCS_KERNEL_BICG_UPDATE_X};

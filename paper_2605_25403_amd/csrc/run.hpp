@@ -175,6 +175,9 @@ struct Run {
   double* f_vec = nullptr;    // r[2], s[2], w[2]
   double *f_part[2] = {}, *f_part_s = nullptr;
   int2* f_bmap = nullptr;
+  FBlk* f_blk = nullptr;
+  int32_t* f_hfirst = nullptr;
+  bool f_blk_ok = false;       // every part's slice offsets fit an FBlk
   FGroup* fgroup = nullptr;
   double* spart = nullptr;    // scratch partials for one-off reductions [8192*2]
   uint32_t* scnt = nullptr;

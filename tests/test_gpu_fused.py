@@ -113,3 +113,37 @@ def test_fused_kernel_profile_hook():
     for k in (I.IPCS_KERNEL_PCG_SPMV_P, I.IPCS_KERNEL_PCG_UPDATE_P, I.IPCS_KERNEL_BICG_UPDATE_X):
         assert I.ipcs_profile_kernel(two.h, k, 5) > 0.0
     two.advance(1)   # profiling leaves the tolerances as they were
+
+
+def test_wide_halo_parts_block_and_map_paths_bitwise():
+    """Parts whose halo exceeds one block's threads (3D, parts of up to 2048
+    rows: 8 rows per thread, up to 376 halo rows). Alone, a run's iterations
+    take its per-block descriptors; in a batch, the block map. The two must
+    give bitwise the same fields, and agree with the two-kernel CG."""
+    torch, I = require_gpu()
+    print("wide-halo parts: descriptor vs block-map launches", flush=True)
+    m = I.Mesh.unit_cube(16)
+    q = I.ipcs_mesh_p1_partition(m.h, 2048)
+    assert np.diff(q["halo_ptr"]).max() > 256
+
+    def new_run(rows, stream=None):
+        p = I.ipcs_params_default(nu=0.01, dt=0.01, tol_p=1e-13, poisson_part_rows=rows)
+        r = I.Run(m, p, stream=stream)
+        r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+        return r
+
+    alone = new_run(2048)
+    alone.advance(2)
+    two = new_run(-1)
+    two.advance(2)
+    s = torch.cuda.Stream()
+    pair = [new_run(2048, stream=s), new_run(2048, stream=s)]
+    for _ in range(2):
+        rc, st = I.ipcs_batch_step([r.h for r in pair], s.cuda_stream)
+        assert rc == I.IPCS_OK, st
+    for r in pair:
+        np.testing.assert_array_equal(r.velocity(), alone.velocity())
+        np.testing.assert_array_equal(r.pressure(), alone.pressure())
+    for c in range(3):
+        assert rel(alone.velocity()[c], two.velocity()[c]) <= FIELD_TOL
+    assert rel(alone.pressure(), two.pressure()) <= FIELD_TOL
