@@ -37,6 +37,31 @@ __device__ __forceinline__ double group_sum(double v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
+// DPP lane move of a double (two 32-bit moves), CTRL a DPP control code.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes of a wavefront, the same in every lane: a fixed
+// pairwise tree with no round trip through LDS. Quads by two quad
+// permutations ([1,0,3,2], then [2,3,0,1]), the four quads of each row of 16
+// lanes by rotations of 4 and 8 lanes (lane 0 of a row then holds
+// (Q0 + Q1) + (Q2 + Q3)), and the four rows from lanes 0, 16, 32, 48.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_d<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);   // row_ror 4
+  v += dpp_d<0x128>(v);   // row_ror 8
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
 // Sum over the block (blockDim.x a multiple of 64, at most 1024); result valid
 // in every thread; fixed order of additions. sh needs blockDim.x/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -77,7 +102,7 @@ template <int BS, int N>
 __device__ __forceinline__ void block_sum_t(double (&v)[N], double* sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+  for (int n = 0; n < N; ++n) v[n] = wave_total(v[n]);
   __syncthreads();
   if (lane == 0)
 #pragma unroll
