@@ -1,4 +1,5 @@
-"""Plain FP64 CPU oracle for one IPCS time step on Taylor-Hood P2-P1 simplices.
+"""Plain FP64 CPU oracle for one IPCS time step on Taylor-Hood simplices
+(P2-P1 on triangles and tetrahedra, P3-P2 on triangles).
 
 THIS PACKAGE IS TEST INFRASTRUCTURE. Only the test suite, the smoke check and
 the CPU-baseline leg of the benchmark may import it. The product library never
@@ -8,13 +9,14 @@ It is a slow, obviously correct NumPy/SciPy implementation of what the paper
 (arXiv 2605.25403, FEALPy.CFD) computes for the incremental pressure-correction
 scheme (IPCS, Section 2.2.1, eq. (9)) with the Taylor-Hood pair P2-P1
 (Section 2.2.1, the spaces V_h and Q_h of eqs. (4)-(5); Section 4.2 selects
-Lagrange p=2 for velocity and p=1 for pressure). It shares no code, tables or
-constants with the HIP library.
+Lagrange p=2 for velocity and p=1 for pressure; its higher-order study, table
+"convergence_p3_p2", takes p=3 and p=2 on triangles). It shares no code,
+tables or constants with the HIP library.
 
 Modules
-  quadrature  - degree-5 cell rules and high-order error rules, derived here
+  quadrature  - cell rules (degree 5; degree 9 for P3-P2) and error rules
   mesh        - structured unit-square / unit-cube simplex meshes
-  fem         - P1/P2 spaces, local matrices, COO->CSR assembly, Dirichlet
+  fem         - P1/P2/P3 spaces, local matrices, COO->CSR assembly, Dirichlet
   krylov      - Jacobi-PCG and Jacobi-BiCGStab (textbook definitions)
   problems    - manufactured solutions (Taylor-Green, John, Beltrami, polynomial)
   ipcs        - the IPCS time step in the paper's order

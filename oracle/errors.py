@@ -7,7 +7,7 @@ is only determined up to a constant).
 """
 import numpy as np
 
-from . import fem, quadrature
+from . import quadrature
 
 
 def _rule(space):
@@ -16,20 +16,20 @@ def _rule(space):
 
 def l2_velocity(space, U, u_exact, t):
     lam, w = _rule(space)
-    phi, _ = fem.p2_basis(lam)
+    phi, _ = space.basis_u(lam)
     xq = space.map_points(lam)
     uex = u_exact(xq, t)                                          # (Nc, nq, d)
-    uh = np.einsum('qm,acm->cqa', phi, U[:, space.c2d2])
+    uh = np.einsum('qm,acm->cqa', phi, U[:, space.c2du])
     e2 = np.einsum('q,c,cqa->', w, space.absdet, (uex - uh) ** 2)
     return float(np.sqrt(e2))
 
 
 def l2_pressure(space, P, p_exact, t):
     lam, w = _rule(space)
-    psi, _ = fem.p1_basis(lam)
+    psi, _ = space.basis_p(lam)
     xq = space.map_points(lam)
     pex = p_exact(xq, t)
-    ph = np.einsum('qm,cm->cq', psi, P[space.c2d1])
+    ph = np.einsum('qm,cm->cq', psi, P[space.c2dp])
     wq = np.einsum('q,c->cq', w, space.absdet)
     vol = wq.sum()
     diff = (pex - (wq * pex).sum() / vol) - (ph - (wq * ph).sum() / vol)

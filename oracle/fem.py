@@ -1,7 +1,9 @@
-"""P1/P2 Lagrange spaces, local matrices and assembly (oracle).
+"""P1/P2/P3 Lagrange spaces, local matrices and assembly (oracle).
 
 Spaces (Section 2.2.1, eqs. (4)-(5)): velocity in continuous P2 per component,
-pressure in continuous P1 (Taylor-Hood P2-P1, Section 4.2).
+pressure in continuous P1 (Taylor-Hood P2-P1, Section 4.2); or, on triangles,
+velocity in P3 and pressure in P2 (the P3-P2 Taylor-Hood pair of the paper's
+higher-order study, table "convergence_p3_p2").
 
 Numbering adopted here (the paper does not fix one):
 * P1 DOFs are the mesh vertices in input order.
@@ -11,6 +13,17 @@ Numbering adopted here (the paper does not fix one):
   tetrahedron: v0..v3, e01, e02, e03, e12, e13, e23.
 * Basis in barycentrics: P1 lam_i; P2 vertex lam_i (2 lam_i - 1); P2 edge
   4 lam_a lam_b.
+* P3 (triangles) DOFs: the vertices, then two per edge (edges numbered as for
+  P2; edge k with sorted vertices lo < hi owns Nv + 2k at (2 x_lo + x_hi)/3 and
+  Nv + 2k + 1 at (x_lo + 2 x_hi)/3), then one per cell at its centroid.
+  Local order: v0, v1, v2; for each local edge (a, b) of (v1v2, v2v0, v0v1)
+  the node nearer a, then the node nearer b; the centroid. Basis: vertex
+  lam_i (3 lam_i - 1)(3 lam_i - 2) / 2; edge node nearer a
+  9/2 lam_a lam_b (3 lam_a - 1); centroid 27 lam_0 lam_1 lam_2.
+* The space of the pair is chosen by `order` (2: P2-P1, 3: P3-P2). The
+  generic names (Nu, c2du, xu, bmask_u for velocity; Np, c2dp, xp for
+  pressure) are what the IPCS step uses; N1/N2, c2d1/c2d2, x2, boundary2
+  keep their P1/P2 meaning for either pair.
 
 Local matrices are written out as the defining sums over quadrature points
 (w_q |det J| times products of basis values and physical gradients), then
@@ -67,11 +80,38 @@ def p2_basis(lam):
     return phi, dphi
 
 
+def p3_basis(lam):
+    """Values (nq, 10) and reference gradients (nq, 10, 2) of P3 on triangles."""
+    nq, dp1 = lam.shape
+    if dp1 != 3:
+        raise ValueError("P3 is defined here for triangles only")
+    G = bary_grad(2)
+    phi = np.zeros((nq, 10))
+    dphi = np.zeros((nq, 10, 2))
+    for i in range(3):
+        L = lam[:, i]
+        phi[:, i] = 0.5 * L * (3.0 * L - 1.0) * (3.0 * L - 2.0)
+        dphi[:, i, :] = (0.5 * (27.0 * L * L - 18.0 * L + 2.0))[:, None] * G[i][None, :]
+    for e, (a, b) in enumerate(EDGES_2D):
+        for k, (p, q) in enumerate(((a, b), (b, a))):   # node nearer p
+            Lp, Lq = lam[:, p], lam[:, q]
+            j = 3 + 2 * e + k
+            phi[:, j] = 4.5 * Lp * Lq * (3.0 * Lp - 1.0)
+            # d/dLp = 4.5 Lq (6 Lp - 1), d/dLq = 4.5 Lp (3 Lp - 1)
+            dphi[:, j, :] = ((4.5 * Lq * (6.0 * Lp - 1.0))[:, None] * G[p][None, :]
+                             + (4.5 * Lp * (3.0 * Lp - 1.0))[:, None] * G[q][None, :])
+    L0, L1, L2 = lam[:, 0], lam[:, 1], lam[:, 2]
+    phi[:, 9] = 27.0 * L0 * L1 * L2
+    dphi[:, 9, :] = 27.0 * ((L1 * L2)[:, None] * G[0][None, :] + (L0 * L2)[:, None] * G[1][None, :]
+                            + (L0 * L1)[:, None] * G[2][None, :])
+    return phi, dphi
+
+
 # ----------------------------------------------------------------- spaces
 class Space:
-    """Mesh + P1/P2 DOF maps + geometry for one simplicial mesh."""
+    """Mesh + DOF maps of a Taylor-Hood pair + geometry for one simplicial mesh."""
 
-    def __init__(self, X, cells):
+    def __init__(self, X, cells, order=2):
         self.X = np.asarray(X, dtype=np.float64)
         self.cells = np.asarray(cells, dtype=np.int64)
         self.dim = self.X.shape[1]
@@ -99,6 +139,43 @@ class Space:
         self.absdet = np.abs(self.detJ)
         self.Jinv = np.linalg.inv(self.J)
         self.boundary2 = self._boundary_p2()
+        if order not in (2, 3) or (order == 3 and d != 2):
+            raise ValueError("pairs: P2-P1 (triangles, tetrahedra) or P3-P2 (triangles)")
+        self.order = order
+        if order == 2:
+            self.Nu, self.c2du, self.xu, self.bmask_u = self.N2, self.c2d2, self.x2, self.boundary2
+            self.Np, self.c2dp, self.xp = self.N1, self.c2d1, self.X
+            self.basis_u, self.basis_p = p2_basis, p1_basis
+        else:
+            self._p3_dofs(inv.reshape(self.Nc, len(edges)))
+            self.Np, self.c2dp, self.xp = self.N2, self.c2d2, self.x2
+            self.basis_u, self.basis_p = p3_basis, p2_basis
+
+    def _p3_dofs(self, cell_edges):
+        """P3 DOF numbering, node coordinates and boundary mask (triangles)."""
+        Nv, Ne, Nc = self.Nv, self.edges.shape[0], self.Nc
+        self.N3 = Nv + 2 * Ne + Nc
+        c2d = np.zeros((Nc, 10), dtype=np.int64)
+        c2d[:, :3] = self.cells
+        for e, (a, b) in enumerate(EDGES_2D):
+            k = cell_edges[:, e]
+            fwd = self.cells[:, a] < self.cells[:, b]        # a is the edge's lower vertex
+            c2d[:, 3 + 2 * e] = np.where(fwd, Nv + 2 * k, Nv + 2 * k + 1)
+            c2d[:, 4 + 2 * e] = np.where(fwd, Nv + 2 * k + 1, Nv + 2 * k)
+        c2d[:, 9] = Nv + 2 * Ne + np.arange(Nc)
+        lo, hi = self.X[self.edges[:, 0]], self.X[self.edges[:, 1]]
+        ex = np.empty((2 * Ne, 2))
+        ex[0::2] = (2.0 * lo + hi) / 3.0
+        ex[1::2] = (lo + 2.0 * hi) / 3.0
+        cx = self.X[self.cells].mean(axis=1)
+        self.Nu, self.c2du = self.N3, c2d
+        self.xu = np.concatenate([self.X, ex, cx])
+        mask = np.zeros(self.N3, dtype=bool)
+        mask[:Nv] = self.boundary2[:Nv]
+        be = self.boundary2[Nv:]                  # boundary edges (P2 mask)
+        mask[Nv:Nv + 2 * Ne:2] = be
+        mask[Nv + 1:Nv + 2 * Ne:2] = be
+        self.bmask_u = mask
 
     def _boundary_p2(self):
         """Topological boundary: facets owned by exactly one cell; their vertices
@@ -132,62 +209,71 @@ class Space:
 
 # ----------------------------------------------------------------- local matrices
 def _rule(space):
-    lam, w = quadrature.cell_rule(space.dim)
-    return lam, w
+    """Cell rule: degree 5 for P2-P1 (every integrand has degree <= 5);
+    the collapsed Gauss rule exact to degree 9 for P3-P2 (convection
+    P3 (P3 . grad P3) has degree 8)."""
+    if space.order == 2:
+        return quadrature.cell_rule(space.dim)
+    return quadrature.triangle_collapsed(5)
 
 
-def local_mass_p2(space):
+def local_mass_u(space):
     lam, w = _rule(space)
-    phi, _ = p2_basis(lam)
+    phi, _ = space.basis_u(lam)
     return np.einsum('q,c,qi,qj->cij', w, space.absdet, phi, phi)
 
 
-def local_mass_p1(space):
+def local_mass_p(space):
     lam, w = _rule(space)
-    psi, _ = p1_basis(lam)
+    psi, _ = space.basis_p(lam)
     return np.einsum('q,c,qi,qj->cij', w, space.absdet, psi, psi)
 
 
-def local_stiff_p2(space):
+def local_stiff_u(space):
     lam, w = _rule(space)
-    _, dref = p2_basis(lam)
+    _, dref = space.basis_u(lam)
     g = space.phys_grad(dref)
     return np.einsum('q,c,cqia,cqja->cij', w, space.absdet, g, g)
 
 
-def local_stiff_p1(space):
+def local_stiff_p(space):
     lam, w = _rule(space)
-    _, dref = p1_basis(lam)
+    _, dref = space.basis_p(lam)
     g = space.phys_grad(dref)
     return np.einsum('q,c,cqia,cqja->cij', w, space.absdet, g, g)
+
+
+# the P2-P1 names (the pair's velocity/pressure spaces when order == 2)
+local_mass_p2, local_mass_p1 = local_mass_u, local_mass_p
+local_stiff_p2, local_stiff_p1 = local_stiff_u, local_stiff_p
 
 
 def local_convection(space, U):
     """C_ij = sum_q w |J| phi_i (u_h . grad phi_j), u_h = sum_m U_m phi_m.
-    U has shape (d, N2)."""
+    U has shape (d, Nu)."""
     lam, w = _rule(space)
-    phi, dref = p2_basis(lam)
+    phi, dref = space.basis_u(lam)
     g = space.phys_grad(dref)                                  # (Nc,nq,nloc,d)
-    Uloc = U[:, space.c2d2]                                    # (d, Nc, nloc)
+    Uloc = U[:, space.c2du]                                    # (d, Nc, nloc)
     uq = np.einsum('qm,acm->cqa', phi, Uloc)                  # (Nc, nq, d)
     adv = np.einsum('cqa,cqja->cqj', uq, g)                   # u_h . grad phi_j
     return np.einsum('q,c,qi,cqj->cij', w, space.absdet, phi, adv)
 
 
 def local_div(space, c):
-    """(D_c)_kj = sum_q w |J| psi_k d_c phi_j  (P1 rows, P2 columns)."""
+    """(D_c)_kj = sum_q w |J| psi_k d_c phi_j  (pressure rows, velocity columns)."""
     lam, w = _rule(space)
-    psi, _ = p1_basis(lam)
-    _, dref = p2_basis(lam)
+    psi, _ = space.basis_p(lam)
+    _, dref = space.basis_u(lam)
     g = space.phys_grad(dref)
     return np.einsum('q,c,qk,cqj->ckj', w, space.absdet, psi, g[..., c])
 
 
 def local_grad(space, c):
-    """(G_c)_ik = sum_q w |J| phi_i d_c psi_k  (P2 rows, P1 columns)."""
+    """(G_c)_ik = sum_q w |J| phi_i d_c psi_k  (velocity rows, pressure columns)."""
     lam, w = _rule(space)
-    phi, _ = p2_basis(lam)
-    _, dref1 = p1_basis(lam)
+    phi, _ = space.basis_u(lam)
+    _, dref1 = space.basis_p(lam)
     g1 = space.phys_grad(dref1)
     return np.einsum('q,c,qi,cqk->cik', w, space.absdet, phi, g1[..., c])
 
@@ -195,7 +281,7 @@ def local_grad(space, c):
 def local_load(space, f, t):
     """F_{c,i} = sum_q w |J| f_c(x_q, t) phi_i ; f(x, t) -> (..., d)."""
     lam, w = _rule(space)
-    phi, _ = p2_basis(lam)
+    phi, _ = space.basis_u(lam)
     xq = space.map_points(lam)                                 # (Nc, nq, d)
     fq = f(xq, t)                                              # (Nc, nq, d)
     return np.einsum('q,c,cqa,qi->aci', w, space.absdet, fq, phi)  # (d, Nc, nloc)
@@ -219,38 +305,41 @@ def assemble_vector(loc, rows_map, n):
     return out
 
 
-def mass_p2(space):
-    return assemble(local_mass_p2(space), space.c2d2, space.c2d2, (space.N2, space.N2))
+def mass_u(space):
+    return assemble(local_mass_u(space), space.c2du, space.c2du, (space.Nu, space.Nu))
 
 
-def mass_p1(space):
-    return assemble(local_mass_p1(space), space.c2d1, space.c2d1, (space.N1, space.N1))
+def mass_p(space):
+    return assemble(local_mass_p(space), space.c2dp, space.c2dp, (space.Np, space.Np))
 
 
-def stiff_p2(space):
-    return assemble(local_stiff_p2(space), space.c2d2, space.c2d2, (space.N2, space.N2))
+def stiff_u(space):
+    return assemble(local_stiff_u(space), space.c2du, space.c2du, (space.Nu, space.Nu))
 
 
-def stiff_p1(space):
-    return assemble(local_stiff_p1(space), space.c2d1, space.c2d1, (space.N1, space.N1))
+def stiff_p(space):
+    return assemble(local_stiff_p(space), space.c2dp, space.c2dp, (space.Np, space.Np))
+
+
+mass_p2, mass_p1, stiff_p2, stiff_p1 = mass_u, mass_p, stiff_u, stiff_p
 
 
 def convection(space, U):
-    return assemble(local_convection(space, U), space.c2d2, space.c2d2,
-                    (space.N2, space.N2))
+    return assemble(local_convection(space, U), space.c2du, space.c2du,
+                    (space.Nu, space.Nu))
 
 
 def divergence(space, c):
-    return assemble(local_div(space, c), space.c2d1, space.c2d2, (space.N1, space.N2))
+    return assemble(local_div(space, c), space.c2dp, space.c2du, (space.Np, space.Nu))
 
 
 def gradient(space, c):
-    return assemble(local_grad(space, c), space.c2d2, space.c2d1, (space.N2, space.N1))
+    return assemble(local_grad(space, c), space.c2du, space.c2dp, (space.Nu, space.Np))
 
 
 def load(space, f, t):
     loc = local_load(space, f, t)
-    return np.stack([assemble_vector(loc[a], space.c2d2, space.N2)
+    return np.stack([assemble_vector(loc[a], space.c2du, space.Nu)
                      for a in range(space.dim)])
 
 

@@ -1,4 +1,4 @@
-"""One IPCS time step with Taylor-Hood P2-P1 elements (oracle).
+"""One IPCS time step with Taylor-Hood elements, P2-P1 or P3-P2 (oracle).
 
 The scheme is eq. (9) of Section 2.2.1 (incremental pressure correction,
 Goda). With density rho and time step dt, one step n -> n+1 at
@@ -53,14 +53,14 @@ class IPCS:
         self.prm = params
         S = space
         d = S.dim
-        self.M = fem.mass_p2(S)
-        self.K = fem.stiff_p2(S)
-        self.Kp = fem.stiff_p1(S)
-        self.Mp = fem.mass_p1(S)
+        self.M = fem.mass_u(S)
+        self.K = fem.stiff_u(S)
+        self.Kp = fem.stiff_p(S)
+        self.Mp = fem.mass_p(S)
         self.D = [fem.divergence(S, c) for c in range(d)]
         self.G = [fem.gradient(S, c) for c in range(d)]
-        self.w = self.Mp @ np.ones(S.N1)
-        self.bmask = S.boundary2
+        self.w = self.Mp @ np.ones(S.Np)
+        self.bmask = S.bmask_u
         self.A = (self.M / params.dt + params.nu * self.K).tocsr()
         self.A.sort_indices()
         self.A_el = fem.eliminate(self.A, self.bmask)
@@ -69,26 +69,26 @@ class IPCS:
         self.dinv_M = 1.0 / self.M_el.diagonal()
         self.dinv_Kp = 1.0 / self.Kp.diagonal()
         self.t = params.t0
-        self.U = problem.u(S.x2, self.t).T.copy()          # (d, N2)
-        self.P = self.normalize(problem.p(S.X, self.t))
+        self.U = problem.u(S.xu, self.t).T.copy()          # (d, Nu)
+        self.P = self.normalize(problem.p(S.xp, self.t))
         self.iters = []
 
     def normalize(self, P):
-        """Shift a P1 field to zero integral mean."""
+        """Shift a pressure field to zero integral mean."""
         return P - np.dot(self.w, P) / self.w.sum()
 
     def set_state(self, U, P, t):
-        self.U = np.array(U, dtype=np.float64).reshape(self.S.dim, self.S.N2).copy()
+        self.U = np.array(U, dtype=np.float64).reshape(self.S.dim, self.S.Nu).copy()
         self.P = np.array(P, dtype=np.float64).copy()
         self.t = float(t)
 
     def dirichlet(self, t):
-        """g(t) at every P2 node (only boundary entries are used)."""
-        return self.pb.u(self.S.x2, t).T
+        """g(t) at every velocity node (only boundary entries are used)."""
+        return self.pb.u(self.S.xu, t).T
 
     def forcing(self, t):
         if self.pb.f is None:
-            return np.zeros((self.S.dim, self.S.N2))
+            return np.zeros((self.S.dim, self.S.Nu))
         return fem.load(self.S, self.pb.f, t)
 
     # ---- the three sub-steps, in the paper's order
@@ -122,7 +122,7 @@ class IPCS:
         S, prm = self.S, self.prm
         r = -(prm.rho / prm.dt) * sum(self.D[c] @ Ustar[c] for c in range(S.dim))
         r = r - r.mean()
-        dP, it = krylov.pcg(self.Kp, r, np.zeros(S.N1), self.dinv_Kp, prm.tol_p,
+        dP, it = krylov.pcg(self.Kp, r, np.zeros(S.Np), self.dinv_Kp, prm.tol_p,
                             prm.maxit, project=True)
         dP = self.normalize(dP)
         return dP, it

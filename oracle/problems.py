@@ -12,6 +12,9 @@ against symbolic differentiation in the tests.
 * PolySteady2D / PolySteady3D: quadratic divergence-free u, linear p with
   zero mean; every IPCS integrand is a polynomial of degree <= 5, so the
   interpolated exact state is a fixed point of one step.
+* PolySteady2DCubic: the same for the P3-P2 pair: cubic divergence-free u
+  (from a quartic stream function), quadratic zero-mean p; every integrand
+  of the P3-P2 step has degree <= 8.
 Points x have shape (..., d); returns have shape (..., d) or (...).
 """
 import numpy as np
@@ -155,3 +158,32 @@ class PolySteady3D:
         f2 = c + 2 * X * u1 + 2 * Z * u3
         f3 = c + 2 * X * u1 + 2 * Y * u2
         return np.stack([f1, f2, f3], axis=-1)
+
+
+class PolySteady2DCubic:
+    """Stream function psi = x^3 y + x^2 y^2, u = (psi_y, -psi_x)
+    = (x^3 + 2x^2 y, -3x^2 y - 2x y^2), p = x^2 - y^2 + xy - 1/4 (zero mean on
+    the unit square), f = (u . grad) u - nu Lap u + grad p with
+    Lap u = (6x + 4y, -4x - 6y), grad p = (2x + y, x - 2y)."""
+    dim = 2
+
+    def __init__(self, nu=0.1):
+        self.nu = float(nu)
+
+    def u(self, x, t):
+        X, Y = x[..., 0], x[..., 1]
+        return np.stack([X ** 3 + 2 * X * X * Y, -3 * X * X * Y - 2 * X * Y * Y], axis=-1)
+
+    def p(self, x, t):
+        X, Y = x[..., 0], x[..., 1]
+        return X * X - Y * Y + X * Y - 0.25
+
+    def f(self, x, t):
+        X, Y = x[..., 0], x[..., 1]
+        u1 = X ** 3 + 2 * X * X * Y
+        u2 = -3 * X * X * Y - 2 * X * Y * Y
+        u1x, u1y = 3 * X * X + 4 * X * Y, 2 * X * X
+        u2x, u2y = -6 * X * Y - 2 * Y * Y, -3 * X * X - 4 * X * Y
+        f1 = u1 * u1x + u2 * u1y - self.nu * (6 * X + 4 * Y) + (2 * X + Y)
+        f2 = u1 * u2x + u2 * u2y - self.nu * (-4 * X - 6 * Y) + (X - 2 * Y)
+        return np.stack([f1, f2], axis=-1)

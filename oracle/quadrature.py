@@ -11,7 +11,9 @@ reproduces the matrices up to rounding. The oracle uses:
 * tetrahedra: Stroud's conical-product rule, 3 Gauss-Jacobi points per
   collapsed direction (27 points, exact to degree 5), built from
   scipy.special.roots_jacobi;
-* error norms: collapsed Gauss rules with more points (degree >= 9).
+* error norms: collapsed Gauss rules with more points (degree >= 9);
+* the P3-P2 pair (triangles), whose convection integrand P3 (P3 . grad P3)
+  has degree 8: the collapsed rule with 5 x 5 points (degree 9).
 
 All rules return barycentric coordinates lam[q, 0..d] and weights that sum to
 the reference-simplex measure 1/d! (area 1/2, volume 1/6).

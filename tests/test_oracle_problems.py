@@ -35,6 +35,9 @@ def sym_fields(name, nu, k=None):
         return u, p, [x, y, z]
     if name == "poly2":
         return [y ** 2, x ** 2], x + y - 1, [x, y]
+    if name == "poly2c":
+        return ([x ** 3 + 2 * x ** 2 * y, -3 * x ** 2 * y - 2 * x * y ** 2],
+                x ** 2 - y ** 2 + x * y - sp.Rational(1, 4), [x, y])
     if name == "poly3":
         return [y ** 2 + z ** 2, z ** 2 + x ** 2, x ** 2 + y ** 2], x + y + z - sp.Rational(3, 2), [x, y, z]
     raise KeyError(name)
@@ -47,6 +50,7 @@ CASES = [
     ("beltrami", problems.Beltrami3D(nu=0.01), dict(nu=sp.Rational(1, 100))),
     ("poly2", problems.PolySteady2D(0.3), dict(nu=sp.Rational(3, 10))),
     ("poly3", problems.PolySteady3D(0.3), dict(nu=sp.Rational(3, 10))),
+    ("poly2c", problems.PolySteady2DCubic(0.3), dict(nu=sp.Rational(3, 10))),
 ]
 
 
