@@ -14,7 +14,7 @@ Lagrange p=2 for velocity and p=1 for pressure; its higher-order study, table
 tables or constants with the HIP library.
 
 Modules
-  quadrature  - cell rules (degree 5; degree 9 for P3-P2) and error rules
+  quadrature  - cell rules (degree 5; degree 8 for P3-P2) and error rules
   mesh        - structured unit-square / unit-cube simplex meshes
   fem         - P1/P2/P3 spaces, local matrices, COO->CSR assembly, Dirichlet
   krylov      - Jacobi-PCG and Jacobi-BiCGStab (textbook definitions)

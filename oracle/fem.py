@@ -210,11 +210,11 @@ class Space:
 # ----------------------------------------------------------------- local matrices
 def _rule(space):
     """Cell rule: degree 5 for P2-P1 (every integrand has degree <= 5);
-    the collapsed Gauss rule exact to degree 9 for P3-P2 (convection
-    P3 (P3 . grad P3) has degree 8)."""
+    the collapsed 5 x 5 Gauss-Legendre rule, exact to degree 8, for P3-P2
+    (convection P3 (P3 . grad P3) has degree 8)."""
     if space.order == 2:
         return quadrature.cell_rule(space.dim)
-    return quadrature.triangle_collapsed(5)
+    return quadrature.triangle_collapsed_gl(5)
 
 
 def local_mass_u(space):

@@ -13,7 +13,12 @@ reproduces the matrices up to rounding. The oracle uses:
   scipy.special.roots_jacobi;
 * error norms: collapsed Gauss rules with more points (degree >= 9);
 * the P3-P2 pair (triangles), whose convection integrand P3 (P3 . grad P3)
-  has degree 8: the collapsed rule with 5 x 5 points (degree 9).
+  has degree 8: the collapsed (Duffy) product of two 5-point Gauss-Legendre
+  rules, from numpy.polynomial.legendre.leggauss. The Jacobian factor 1 - u
+  is carried by the weights, so the rule is exact to degree 8. Any rule exact
+  to degree 8 gives the step's polynomial integrands up to rounding; the
+  non-polynomial forcing terms depend on the rule, and this is the rule the
+  kernels implement.
 
 All rules return barycentric coordinates lam[q, 0..d] and weights that sum to
 the reference-simplex measure 1/d! (area 1/2, volume 1/6).
@@ -57,6 +62,21 @@ def triangle_collapsed(n):
     v, wv = _gauss_jacobi_01(n, 0.0)
     U, V = np.meshgrid(u, v, indexing="ij")
     W = np.outer(wu, wv)
+    x = U.ravel()
+    y = (V * (1.0 - U)).ravel()
+    lam = np.stack([1.0 - x - y, x, y], axis=1)
+    return lam, W.ravel()
+
+
+def triangle_collapsed_gl(n):
+    """Collapsed product of n-point Gauss-Legendre rules, exact to degree 2n-2.
+
+    x = u, y = v (1 - u); the Jacobian (1 - u) multiplies the weights.
+    """
+    t, w = np.polynomial.legendre.leggauss(n)
+    u, wu = 0.5 * (1.0 + t), 0.5 * w
+    U, V = np.meshgrid(u, u, indexing="ij")
+    W = np.outer(wu, wu) * (1.0 - U)
     x = U.ravel()
     y = (V * (1.0 - U)).ravel()
     lam = np.stack([1.0 - x - y, x, y], axis=1)

@@ -28,6 +28,7 @@ def moments(dim, degree):
     (3, quadrature.tet_deg5, 5),
     (2, lambda: quadrature.triangle_collapsed(5), 9),
     (3, lambda: quadrature.tet_collapsed(5), 9),
+    (2, lambda: quadrature.triangle_collapsed_gl(5), 8),
 ])
 def test_rule_exact_on_all_monomials(dim, rule, deg):
     lam, w = rule()
@@ -47,3 +48,13 @@ def test_radon_rule_is_not_exact_at_degree_6():
             for a in itertools.product(range(7), repeat=3) if sum(a) == 6]
     assert max(errs) > 1e-6
     assert len(w) == 7 and np.all(w > 0)
+
+
+def test_collapsed_gauss_legendre_rule_stops_at_degree_8():
+    """The P3-P2 rule: the Jacobian factor 1 - u costs one degree against the
+    Gauss-Jacobi version, so some degree-9 moment is missed."""
+    lam, w = quadrature.triangle_collapsed_gl(5)
+    errs = [abs(np.sum(w * np.prod(lam ** np.array(a), axis=1)) - exact_moment(a))
+            for a in itertools.product(range(10), repeat=3) if sum(a) == 9]
+    assert max(errs) > 1e-8
+    assert len(w) == 25 and np.all(w > 0)
