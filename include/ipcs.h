@@ -70,7 +70,16 @@ const char* ipcs_last_error(void);
 /* ---------------------------------------------------------------- mesh */
 typedef struct ipcs_mesh_s* ipcs_mesh;
 
-enum { IPCS_SPACE_P1 = 1, IPCS_SPACE_P2 = 2 };
+/* Taylor-Hood pairs (Section 2.2.1, eqs. (4)-(5); Section 4.2 takes P2-P1,
+ * the higher-order study of Section 5.1, table "convergence_p3_p2", P3-P2).
+ * The space and pattern names below keep the P2-P1 pair's vocabulary:
+ * "P2" is the velocity space and "P1" the pressure space of the mesh's pair
+ * (for IPCS_PAIR_P3P2: P3 velocity, P2 pressure). */
+enum {
+  IPCS_PAIR_P2P1 = 0,          /* triangles and tetrahedra                      */
+  IPCS_PAIR_P3P2 = 1           /* triangles only                                */
+};
+enum { IPCS_SPACE_P1 = 1, IPCS_SPACE_P2 = 2 };   /* pressure, velocity space */
 enum {                         /* sparsity patterns of the step's matrices      */
   IPCS_PATTERN_P2P2 = 0,       /* M, K, C, A (velocity x velocity)             */
   IPCS_PATTERN_P1P1 = 1,       /* Kp (pressure x pressure)                     */
@@ -81,15 +90,21 @@ enum {                         /* sparsity patterns of the step's matrices      
 typedef struct {
   int32_t dim;                 /* 2 or 3                                       */
   int64_t nv, nc;              /* vertices, cells                              */
-  int64_t n1, n2;              /* P1 and P2 DOFs per component                 */
+  int64_t n1, n2;              /* pressure and velocity DOFs per component     */
   int64_t nnz[4];              /* nnz of IPCS_PATTERN_* patterns               */
-  int64_t nb2;                 /* boundary P2 nodes                            */
+  int64_t nb2;                 /* boundary velocity nodes                      */
 } ipcs_counts;
 
 /* Unit square, nx x ny squares, each split by its SW-NE diagonal into two
  * counter-clockwise triangles; vertex (i,j) = (i/nx, j/ny) has index
  * j*(nx+1)+i (Section 2.2.1: conforming simplicial mesh T_h). */
 int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out);
+/* The same square with the DOF maps of a Taylor-Hood pair (IPCS_PAIR_*).
+ * P3-P2 numbering: velocity DOFs are the vertices, then two per edge (edges
+ * sorted by (lower, higher) vertex; edge k owns n_v + 2k at (2 x_lo + x_hi)/3
+ * and n_v + 2k + 1 at (x_lo + 2 x_hi)/3), then one per cell at its centroid;
+ * pressure DOFs are the P2 nodes (vertices, then edge midpoints). */
+int ipcs_mesh_unit_square_pair(int32_t nx, int32_t ny, int32_t pair, ipcs_mesh* out);
 /* Unit cube, nx*ny*nz cubes, each split into the 6 Kuhn tetrahedra around its
  * main diagonal; vertex (i,j,k) has index (k(ny+1)+j)(nx+1)+i. */
 int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out);
@@ -97,13 +112,20 @@ int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out);
  * vertex indices (0-based). Cells of negative orientation are accepted. */
 int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
                           const int32_t* cells, ipcs_mesh* out);
+/* The same with a Taylor-Hood pair (IPCS_PAIR_P3P2 needs dim = 2). */
+int ipcs_mesh_from_arrays_pair(int32_t dim, int64_t nv, const double* x, int64_t nc,
+                               const int32_t* cells, int32_t pair, ipcs_mesh* out);
+/* The mesh's Taylor-Hood pair (IPCS_PAIR_*). */
+int ipcs_mesh_pair(ipcs_mesh m, int32_t* pair);
 int ipcs_mesh_counts(ipcs_mesh m, ipcs_counts* out);
 /* Coordinates of the DOFs of a space, [n*dim]. cap in doubles. */
 int ipcs_mesh_dof_coords(ipcs_mesh m, int32_t space, double* out, int64_t cap);
 /* Cell -> DOF table of a space, [nc * nloc] (P2 local order: vertices, then
- * edges v1v2, v2v0, v0v1 (2D) or 01,02,03,12,13,23 (3D)). cap in int32s. */
+ * edges v1v2, v2v0, v0v1 (2D) or 01,02,03,12,13,23 (3D); P3 local order:
+ * vertices, then for each edge (a, b) of v1v2, v2v0, v0v1 the node nearer a
+ * and the node nearer b, then the centroid). cap in int32s. */
 int ipcs_mesh_cell_dofs(ipcs_mesh m, int32_t space, int32_t* out, int64_t cap);
-/* Boundary flags of the P2 nodes (1 = on the boundary), [n2]. */
+/* Boundary flags of the velocity nodes (1 = on the boundary), [n2]. */
 int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap);
 /* CSR pattern (row pointer [rows+1], sorted column indices [nnz]). */
 int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
@@ -228,7 +250,10 @@ enum {
   IPCS_SOL_JOHN_2D = 2,         /* Section 5.1 benchmark; prm unused             */
   IPCS_SOL_BELTRAMI_3D = 3,     /* Ethier-Steinman, prm = {a, d}; f = 0           */
   IPCS_SOL_POLY_STEADY_2D = 4,  /* u=(y^2,x^2), p=x+y-1                           */
-  IPCS_SOL_POLY_STEADY_3D = 5   /* u=(y^2+z^2,z^2+x^2,x^2+y^2), p=x+y+z-3/2      */
+  IPCS_SOL_POLY_STEADY_3D = 5,  /* u=(y^2+z^2,z^2+x^2,x^2+y^2), p=x+y+z-3/2      */
+  IPCS_SOL_POLY_CUBIC_2D = 6    /* u=(x^3+2x^2y, -3x^2y-2xy^2), p=x^2-y^2+xy-1/4,
+                                 * steady, f = (u.grad)u - nu Lap u + grad p: a
+                                 * fixed point of the P3-P2 step                 */
 };
 /* Closed-form manufactured solution evaluated on the device: Dirichlet data,
  * forcing and the initial state U = I_h u(t), P = I_h p(t) shifted to zero

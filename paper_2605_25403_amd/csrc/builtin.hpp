@@ -40,6 +40,10 @@ __host__ __device__ inline void builtin_velocity(const Builtin& bi, const double
         u[0] = Y * Y;
         u[1] = X * X;
         return;
+      case IPCS_SOL_POLY_CUBIC_2D:   // stream function x^3 y + x^2 y^2
+        u[0] = X * X * X + 2.0 * X * X * Y;
+        u[1] = -3.0 * X * X * Y - 2.0 * X * Y * Y;
+        return;
     }
     u[0] = u[1] = 0.0;
   } else {
@@ -73,6 +77,7 @@ __host__ __device__ inline double builtin_pressure(const Builtin& bi, const doub
       }
       case IPCS_SOL_JOHN_2D: return 20.0 * sin(t) * (X * X * Y - 1.0 / 6.0);
       case IPCS_SOL_POLY_STEADY_2D: return X + Y - 1.0;
+      case IPCS_SOL_POLY_CUBIC_2D: return X * X - Y * Y + X * Y - 0.25;
     }
     return 0.0;
   } else {
@@ -122,6 +127,15 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
       f[1] = 1.0 - 2.0 * nu + 2.0 * X * Y * Y;
       return;
     }
+    if (bi.kind == IPCS_SOL_POLY_CUBIC_2D) {
+      // (u.grad)u - nu Lap u + grad p; Lap u = (6x + 4y, -4x - 6y)
+      const double u1 = X * X * X + 2.0 * X * X * Y, u2 = -3.0 * X * X * Y - 2.0 * X * Y * Y;
+      const double u1x = 3.0 * X * X + 4.0 * X * Y, u1y = 2.0 * X * X;
+      const double u2x = -6.0 * X * Y - 2.0 * Y * Y, u2y = -3.0 * X * X - 4.0 * X * Y;
+      f[0] = u1 * u1x + u2 * u1y - nu * (6.0 * X + 4.0 * Y) + (2.0 * X + Y);
+      f[1] = u1 * u2x + u2 * u2y - nu * (-4.0 * X - 6.0 * Y) + (X - 2.0 * Y);
+      return;
+    }
     f[0] = f[1] = 0.0;
   } else {
     const double X = x[0], Y = x[1], Z = x[2];
@@ -139,7 +153,7 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
 
 inline bool builtin_has_force(int kind) {
   return kind == IPCS_SOL_JOHN_2D || kind == IPCS_SOL_POLY_STEADY_2D ||
-         kind == IPCS_SOL_POLY_STEADY_3D;
+         kind == IPCS_SOL_POLY_STEADY_3D || kind == IPCS_SOL_POLY_CUBIC_2D;
 }
 
 }  // namespace ipcs

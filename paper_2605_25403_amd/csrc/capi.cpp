@@ -90,6 +90,13 @@ int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out) {
   });
 }
 
+int ipcs_mesh_unit_square_pair(int32_t nx, int32_t ny, int32_t pair, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_unit_square(nx, ny, pair), out);
+  });
+}
+
 int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out) {
   return guard([&]() -> int {
     need(out != nullptr, "null output handle");
@@ -102,6 +109,23 @@ int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
   return guard([&]() -> int {
     need(out != nullptr, "null output handle");
     return wrap_mesh(ipcs::build_from_arrays(dim, nv, x, nc, cells), out);
+  });
+}
+
+int ipcs_mesh_from_arrays_pair(int32_t dim, int64_t nv, const double* x, int64_t nc,
+                               const int32_t* cells, int32_t pair, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_from_arrays(dim, nv, x, nc, cells, pair), out);
+  });
+}
+
+int ipcs_mesh_pair(ipcs_mesh m, int32_t* pair) {
+  return guard([&]() -> int {
+    const ipcs::Mesh& mm = M(m);
+    need(pair != nullptr, "null output");
+    *pair = mm.pair;
+    return IPCS_OK;
   });
 }
 
@@ -127,7 +151,7 @@ int ipcs_mesh_dof_coords(ipcs_mesh m, int32_t space, double* out, int64_t cap) {
     need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
     const int64_t n = (space == IPCS_SPACE_P1 ? mm.n1 : mm.n2) * mm.dim;
     need(out != nullptr && cap >= n, "output buffer too small");
-    std::memcpy(out, mm.x2.data(), sizeof(double) * n);   // P1 nodes are the first n1
+    std::memcpy(out, space == IPCS_SPACE_P1 ? mm.xp.data() : mm.x2.data(), sizeof(double) * n);
     return IPCS_OK;
   });
 }
@@ -138,8 +162,8 @@ int ipcs_mesh_cell_dofs(ipcs_mesh m, int32_t space, int32_t* out, int64_t cap) {
     need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
     const int nl = space == IPCS_SPACE_P1 ? mm.nloc1 : mm.nloc2;
     need(out != nullptr && cap >= mm.nc * nl, "output buffer too small");
-    for (int64_t c = 0; c < mm.nc; ++c)
-      for (int j = 0; j < nl; ++j) out[c * nl + j] = mm.c2d[c * mm.nloc2 + j];
+    const std::vector<int32_t>& t = space == IPCS_SPACE_P1 ? mm.c2dp : mm.c2d;
+    for (int64_t i = 0; i < mm.nc * nl; ++i) out[i] = t[i];
     return IPCS_OK;
   });
 }

@@ -133,6 +133,7 @@ struct RowAsm {
   int32_t nloc2;
   const double* X;            // vertex coordinates [nv][dim]
   void* out[3];               // FP64 values, or FP32 in the mixed form
+  int32_t pair;               // IPCS_PAIR_P2P1 (0) or IPCS_PAIR_P3P2 (2D)
 };
 
 // Manufactured solution on the device

@@ -1,8 +1,9 @@
 // Cell-quadrature assembly kernels for gfx950 (row-owner, conflict-free).
 //
-// Each thread owns one matrix row (a P2 or P1 DOF). It walks the cells incident
-// to its DOF, evaluates that cell's local matrix row by the degree-5 rule
-// (reference tables in constant memory) and adds it into the row's slots,
+// Each thread owns one matrix row (a velocity or pressure DOF). It walks the
+// cells incident to its DOF, evaluates that cell's local matrix row by the
+// cell rule (degree 5 for P2-P1, degree 8 for P3-P2; reference tables in
+// constant memory) and adds it into the row's slots,
 // which live in LDS in the same SELL-64 layout as the value array. After a
 // barrier the block writes its slices back with coalesced stores. No value is
 // written by two threads, so there are no atomics and the result is
@@ -133,7 +134,7 @@ __device__ __forceinline__ void phys(const Geo<D, R>& g, const R* gr, R* out) {
 template <int D, int WHICH, class R>
 struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     const Tab<D, R>& T = tab<D, R>();
@@ -165,7 +166,7 @@ struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
 template <int D, class R>
 struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi-implicit)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
   const double* U;        // [D][n2]
   int64_t n2;
   double inv_dt;
@@ -211,7 +212,7 @@ struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi
 template <int D, class R>
 struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
   using real = R;
-  static constexpr int NOUT = 1, NCOL = D + 1;
+  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = P2<D>::NLOC;
   int c;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -237,7 +238,7 @@ struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
 template <int D, class R>
 struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
   int c;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -261,7 +262,7 @@ struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
 template <int D, class R>
 struct OpKp {   // P1 x P1 stiffness
   using real = R;
-  static constexpr int NOUT = 1, NCOL = D + 1;
+  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = P2<D>::NLOC;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     R gl[D + 1][D];
@@ -291,6 +292,178 @@ struct OpKp {   // P1 x P1 stiffness
   }
 };
 
+// ------------------------------------------------------------------ P3-P2 (triangles)
+// Tables of the P3-P2 pair at the points of its degree-8 rule: P3 velocity
+// basis phi (10) and P2 pressure basis psi (6), values and reference
+// gradients.
+template <class R>
+struct Tab3 {
+  static constexpr int NQ = RuleT9::NQ, NL = P3T::NLOC, NP = P2<2>::NLOC;
+  R w[NQ];
+  R lam[NQ][3];
+  R phi[NQ][NL];
+  R dphi[NQ][NL][2];
+  R psi[NQ][NP];
+  R dpsi[NQ][NP][2];
+  constexpr Tab3() : w(), lam(), phi(), dphi(), psi(), dpsi() {
+    for (int q = 0; q < NQ; ++q) {
+      double l[3] = {};
+      for (int k = 0; k < 3; ++k) l[k] = RuleT9::lam(q, k);
+      w[q] = (R)RuleT9::w(q);
+      for (int k = 0; k < 3; ++k) lam[q][k] = (R)l[k];
+      for (int j = 0; j < NL; ++j) {
+        phi[q][j] = (R)P3T::phi(j, l);
+        for (int r = 0; r < 2; ++r) dphi[q][j][r] = (R)P3T::dphi(j, r, l);
+      }
+      for (int j = 0; j < NP; ++j) {
+        psi[q][j] = (R)P2<2>::phi(j, l);
+        for (int r = 0; r < 2; ++r) dpsi[q][j][r] = (R)P2<2>::dphi(j, r, l);
+      }
+    }
+  }
+};
+
+__constant__ Tab3<double> c_tab3p = Tab3<double>();
+__constant__ Tab3<float> c_tab3pf = Tab3<float>();
+
+template <class R>
+__device__ __forceinline__ const Tab3<R>& tab3() {
+  if constexpr (std::is_same_v<R, double>) return c_tab3p;
+  else return c_tab3pf;
+}
+
+// the c-th physical gradient component of a reference gradient
+template <class R>
+__device__ __forceinline__ R phys_c(const Geo<2, R>& g, const R* gr, int c) {
+  R p[2];
+  phys<2, R>(g, gr, p);
+  return c == 0 ? p[0] : p[1];
+}
+
+template <int WHICH, class R>
+struct Op3MassStiff {   // P3 x P3: M (WHICH 0) or K (WHICH 1)
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 3;   // geometry only
+  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab3<R>& T = tab3<R>();
+#pragma unroll 1
+    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+      const R wq = T.w[q] * g.det;
+      if (WHICH == 0) {
+        const R ci = wq * T.phi[q][li];
+#pragma unroll
+        for (int j = 0; j < NCOL; ++j) v[0][j] += ci * T.phi[q][j];
+      } else {
+        R gi[2];
+        phys<2, R>(g, T.dphi[q][li], gi);
+#pragma unroll
+        for (int j = 0; j < NCOL; ++j) {
+          R gj[2];
+          phys<2, R>(g, T.dphi[q][j], gj);
+          v[0][j] += wq * (gi[0] * gj[0] + gi[1] * gj[1]);
+        }
+      }
+    }
+  }
+};
+
+template <class R>
+struct Op3Conv {   // P3 x P3: E = M/dt + cs C(U)
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = P3T::NLOC;
+  const double* U;        // [2][n2]
+  int64_t n2;
+  double inv_dt;
+  double cs;
+  __device__ void operator()(const Geo<2, R>& g, const int32_t* dofs, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab3<R>& T = tab3<R>();
+    R Uc[2][NCOL];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int m = 0; m < NCOL; ++m) Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
+    const R idt = (R)inv_dt, csr = (R)cs;
+#pragma unroll 1
+    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+      R uq[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        R s = 0;
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m) s += Uc[c][m] * T.phi[q][m];
+        uq[c] = s;
+      }
+      R beta[2];   // J^{-1} u_h
+#pragma unroll
+      for (int a = 0; a < 2; ++a) beta[a] = g.Ji[a][0] * uq[0] + g.Ji[a][1] * uq[1];
+      const R ci = T.w[q] * g.det * T.phi[q][li];
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) {
+        const R adv = beta[0] * T.dphi[q][j][0] + beta[1] * T.dphi[q][j][1];
+        v[0][j] += ci * (T.phi[q][j] * idt + csr * adv);
+      }
+    }
+  }
+};
+
+template <class R>
+struct Op3Grad {   // P3 rows x P2 cols: (G_c)_ik = sum_q w |J| phi_i d_c psi_k
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 3;
+  int c;
+  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab3<R>& T = tab3<R>();
+#pragma unroll 1
+    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+      const R ci = T.w[q] * g.det * T.phi[q][li];
+#pragma unroll
+      for (int k = 0; k < NCOL; ++k) v[0][k] += ci * phys_c<R>(g, T.dpsi[q][k], c);
+    }
+  }
+};
+
+template <class R>
+struct Op3Div {   // P2 rows x P3 cols: (D_c)_kj = sum_q w |J| psi_k d_c phi_j
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 3;
+  int c;
+  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab3<R>& T = tab3<R>();
+#pragma unroll 1
+    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+      const R ci = T.w[q] * g.det * T.psi[q][li];
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) v[0][j] += ci * phys_c<R>(g, T.dphi[q][j], c);
+    }
+  }
+};
+
+template <class R>
+struct Op3Kp {   // P2 x P2 stiffness of the pressure space
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 3;
+  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab3<R>& T = tab3<R>();
+#pragma unroll 1
+    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+      const R wq = T.w[q] * g.det;
+      R gi[2];
+      phys<2, R>(g, T.dpsi[q][li], gi);
+#pragma unroll
+      for (int k = 0; k < NCOL; ++k) {
+        R gk[2];
+        phys<2, R>(g, T.dpsi[q][k], gk);
+        v[0][k] += wq * (gi[0] * gk[0] + gi[1] * gk[1]);
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------------ kernel
 // One thread per output row; the block owns whole SELL-64 slices (blockDim a
 // multiple of 64), accumulates their values in LDS in the SELL layout and
@@ -316,9 +489,9 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
       const int code = a.inc[p];
       const int cell = code >> 4, li = code & 15;
       const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
-      int32_t dl[P2<D>::NLOC];
+      int32_t dl[Op::NDOF];
 #pragma unroll
-      for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = dofs[m];
+      for (int m = 0; m < Op::NDOF; ++m) dl[m] = dofs[m];
       const Geo<D, R> g = cell_geo<D, R>(a.X, dl);
       R v[NOUT][NCOL];
 #pragma unroll
@@ -363,15 +536,32 @@ using OpMass = OpMassStiff<D, 0, R>;
 template <int D, class R>
 using OpStiff = OpMassStiff<D, 1, R>;
 
+// The P3-P2 pair (2D) over its ops, in the working type
+template <template <class> class OpT, class... P>
+static void rows_p3(bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds, P... prm) {
+  if (!fp32) launch_rows<2>(s, a, OpT<double>{prm...}, bs, lds);
+  else launch_rows<2>(s, a, OpT<float>{prm...}, bs, lds);
+}
+template <class R>
+using Op3Mass = Op3MassStiff<0, R>;
+template <class R>
+using Op3Stiff = Op3MassStiff<1, R>;
+
 // a.out[0] <- M, a.out[1] <- K
 void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   RowAsm am = a, ak = a;
   ak.out[0] = a.out[1];
+  if (a.pair == IPCS_PAIR_P3P2) {
+    rows_p3<Op3Mass>(fp32, s, am, bs, lds);
+    rows_p3<Op3Stiff>(fp32, s, ak, bs, lds);
+    return;
+  }
   rows_dr<OpMass>(dim, fp32, s, am, bs, lds);
   rows_dr<OpStiff>(dim, fp32, s, ak, bs, lds);
 }
 void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
               const double* U, int64_t n2, double inv_dt, double cs) {
+  if (a.pair == IPCS_PAIR_P3P2) return rows_p3<Op3Conv>(fp32, s, a, bs, lds, U, n2, inv_dt, cs);
   rows_dr<OpConv>(dim, fp32, s, a, bs, lds, U, n2, inv_dt, cs);
 }
 // a.out[c] <- G_c (one launch per component)
@@ -379,7 +569,8 @@ void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    rows_dr<OpGrad>(dim, fp32, s, ac, bs, lds, c);
+    if (a.pair == IPCS_PAIR_P3P2) rows_p3<Op3Grad>(fp32, s, ac, bs, lds, c);
+    else rows_dr<OpGrad>(dim, fp32, s, ac, bs, lds, c);
   }
 }
 // a.out[c] <- D_c
@@ -387,10 +578,12 @@ void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t 
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    rows_dr<OpDiv>(dim, fp32, s, ac, bs, lds, c);
+    if (a.pair == IPCS_PAIR_P3P2) rows_p3<Op3Div>(fp32, s, ac, bs, lds, c);
+    else rows_dr<OpDiv>(dim, fp32, s, ac, bs, lds, c);
   }
 }
 void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  if (a.pair == IPCS_PAIR_P3P2) return rows_p3<Op3Kp>(fp32, s, a, bs, lds);
   rows_dr<OpKp>(dim, fp32, s, a, bs, lds);
 }
 
@@ -560,9 +753,28 @@ __global__ void __launch_bounds__(256) k_lumped_p1(RowAsm a, double* w) {
   w[row] = s;
 }
 
+// P2 pressure (P3-P2 pair): w_k = sum over incident cells of sum_q w_q |J| psi_k(x_q)
+__global__ void __launch_bounds__(256) k_lumped_p2(RowAsm a, double* w) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  const Tab3<double>& T = tab3<double>();
+  double s = 0.0;
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int cell = a.inc[p] >> 4, li = a.inc[p] & 15;
+    int32_t dl[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    double iq = 0.0;
+    for (int q = 0; q < Tab3<double>::NQ; ++q) iq += T.w[q] * T.psi[q][li];
+    s += cell_geo<2>(a.X, dl).det * iq;
+  }
+  w[row] = s;
+}
+
 void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w) {
   const int nb = (int)div_up(a.nrows, 256);
-  if (dim == 2) hipLaunchKernelGGL((k_lumped_p1<2>), dim3(nb), dim3(256), 0, s, a, w);
+  if (a.pair == IPCS_PAIR_P3P2) hipLaunchKernelGGL(k_lumped_p2, dim3(nb), dim3(256), 0, s, a, w);
+  else if (dim == 2) hipLaunchKernelGGL((k_lumped_p1<2>), dim3(nb), dim3(256), 0, s, a, w);
   else hipLaunchKernelGGL((k_lumped_p1<3>), dim3(nb), dim3(256), 0, s, a, w);
   HIP_LAUNCH_OK();
 }
@@ -612,10 +824,50 @@ __global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const dou
   for (int c = 0; c < D; ++c) F[(size_t)c * n2 + row] = acc[c];
 }
 
+// The same for P3 velocity rows (P3-P2 pair) on its degree-8 rule; fq holds
+// f at its RuleT9::NQ points per cell.
+__global__ void __launch_bounds__(256) k_forcing_p3(RowAsm a, Builtin bi, const double* fq,
+                                                    int64_t nc, double t, double* F, int64_t n2) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  const Tab3<double>& T = tab3<double>();
+  double acc[2] = {0.0, 0.0};
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int code = a.inc[p];
+    const int cell = code >> 4, li = code & 15;
+    int32_t dl[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    const Geo<2> g = cell_geo<2>(a.X, dl);
+#pragma unroll 1
+    for (int q = 0; q < Tab3<double>::NQ; ++q) {
+      const double ci = T.w[q] * g.det * T.phi[q][li];
+      double f[2];
+      if (fq) {
+        for (int c = 0; c < 2; ++c) f[c] = fq[((size_t)c * nc + cell) * Tab3<double>::NQ + q];
+      } else {
+        double x[2];
+        for (int r = 0; r < 2; ++r) {
+          double sx = 0.0;
+          for (int k = 0; k < 3; ++k) sx += T.lam[q][k] * a.X[(size_t)dl[k] * 2 + r];
+          x[r] = sx;
+        }
+        builtin_force<2>(bi, x, t, f);
+      }
+      acc[0] += ci * f[0];
+      acc[1] += ci * f[1];
+    }
+  }
+  F[row] = acc[0];
+  F[(size_t)n2 + row] = acc[1];
+}
+
 void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, const double* fq,
                  int64_t nc, double t, double* F, int64_t n2) {
   const int nb = (int)div_up(a.nrows, 256);
-  if (dim == 2)
+  if (a.pair == IPCS_PAIR_P3P2)
+    hipLaunchKernelGGL(k_forcing_p3, dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
+  else if (dim == 2)
     hipLaunchKernelGGL((k_forcing<2>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
   else
     hipLaunchKernelGGL((k_forcing<3>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);

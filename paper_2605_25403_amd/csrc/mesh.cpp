@@ -1,6 +1,7 @@
-// Mesh generators, P1/P2 DOF maps, CSR patterns and row-owner assembly maps.
-// Integer work done once per mesh on the host (Section 2.2.1: conforming
-// simplicial mesh, continuous Lagrange P2 velocity and P1 pressure spaces).
+// Mesh generators, velocity/pressure DOF maps, CSR patterns and row-owner
+// assembly maps. Integer work done once per mesh on the host (Section 2.2.1:
+// conforming simplicial mesh, continuous Lagrange spaces of a Taylor-Hood pair:
+// P2 velocity and P1 pressure, or on triangles P3 velocity and P2 pressure).
 #include "mesh.hpp"
 
 #include <algorithm>
@@ -155,6 +156,10 @@ void finalize(Mesh& m) {
   const int d = m.dim;
   const int64_t nc = m.nc, nv = m.nv;
   const int ne_loc = d == 2 ? 3 : 6;
+  if (m.pair != IPCS_PAIR_P2P1 && m.pair != IPCS_PAIR_P3P2)
+    fail(IPCS_E_INVALID, "unknown Taylor-Hood pair " + std::to_string(m.pair));
+  if (m.pair == IPCS_PAIR_P3P2 && d != 2)
+    fail(IPCS_E_INVALID, "the P3-P2 pair is built on triangles only");
   m.nloc1 = d + 1;
   m.nloc2 = d + 1 + ne_loc;
   if (nc >= (int64_t(1) << 27)) fail(IPCS_E_INVALID, "too many cells");
@@ -237,19 +242,71 @@ void finalize(Mesh& m) {
       i = j;
     }
   }
+  if (m.pair == IPCS_PAIR_P2P1) {
+    // pressure P1: the vertices
+    m.c2dp.resize(nc * m.nloc1);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int k = 0; k <= d; ++k) m.c2dp[c * m.nloc1 + k] = m.c2d[c * m.nloc2 + k];
+    m.xp = m.X;
+  } else {
+    // pressure P2: the P2 maps built above; velocity P3 (triangles)
+    m.c2dp.swap(m.c2d);
+    m.nloc1 = m.nloc2;
+    m.xp.swap(m.x2);
+    std::vector<uint8_t> bm2;
+    bm2.swap(m.bmask);
+    m.nloc2 = 10;
+    m.n1 = m.n2;
+    m.n2 = nv + 2 * m.ne + nc;
+    if (m.n2 >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "too many DOFs");
+    m.c2d.resize(nc * 10);
+#pragma omp parallel for
+    for (int64_t c = 0; c < nc; ++c) {
+      const int32_t* p = m.c2dp.data() + c * 6;
+      int32_t* o = m.c2d.data() + c * 10;
+      for (int k = 0; k < 3; ++k) o[k] = p[k];
+      for (int e = 0; e < 3; ++e) {
+        const int64_t k = p[3 + e] - nv;               // edge index
+        const bool fwd = p[Edges<2>::a(e)] < p[Edges<2>::b(e)];
+        o[3 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 0 : 1));
+        o[4 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 1 : 0));
+      }
+      o[9] = int32_t(nv + 2 * m.ne + c);
+    }
+    m.x2.resize(m.n2 * 2);
+    for (int64_t i = 0; i < nv * 2; ++i) m.x2[i] = m.X[i];
+    for (int64_t e = 0; e < m.ne; ++e)
+      for (int r = 0; r < 2; ++r) {
+        const double lo = m.X[(int64_t)m.edges[2 * e] * 2 + r];
+        const double hi = m.X[(int64_t)m.edges[2 * e + 1] * 2 + r];
+        m.x2[(nv + 2 * e) * 2 + r] = (2.0 * lo + hi) / 3.0;
+        m.x2[(nv + 2 * e + 1) * 2 + r] = (lo + 2.0 * hi) / 3.0;
+      }
+    for (int64_t c = 0; c < nc; ++c)
+      for (int r = 0; r < 2; ++r)
+        m.x2[(nv + 2 * m.ne + c) * 2 + r] =
+            (m.X[(int64_t)m.c2d[c * 10] * 2 + r] + m.X[(int64_t)m.c2d[c * 10 + 1] * 2 + r] +
+             m.X[(int64_t)m.c2d[c * 10 + 2] * 2 + r]) / 3.0;
+    // boundary: boundary vertices and both nodes of boundary edges
+    m.bmask.assign(m.n2, 0);
+    for (int64_t i = 0; i < nv; ++i) m.bmask[i] = bm2[i];
+    for (int64_t e = 0; e < m.ne; ++e)
+      if (bm2[nv + e]) m.bmask[nv + 2 * e] = m.bmask[nv + 2 * e + 1] = 1;
+  }
   m.bidx.clear();
   for (int64_t i = 0; i < m.n2; ++i)
     if (m.bmask[i]) m.bidx.push_back(int32_t(i));
-  // --- incidence, patterns, slot maps
+  // --- incidence, patterns, slot maps (velocity rows/columns from c2d,
+  // pressure rows/columns from c2dp)
   build_incidence(m.c2d, nc, m.nloc2, m.nloc2, m.n2, m.inc2);
-  build_incidence(m.c2d, nc, m.nloc2, m.nloc1, m.n1, m.inc1);
+  build_incidence(m.c2dp, nc, m.nloc1, m.nloc1, m.n1, m.inc1);
   build_pattern(m.inc2, m.c2d, m.nloc2, m.nloc2, m.n2, m.n2, m.p22, m.max_row22);
-  build_pattern(m.inc2, m.c2d, m.nloc2, m.nloc1, m.n2, m.n1, m.p21, m.max_row21);
-  build_pattern(m.inc1, m.c2d, m.nloc2, m.nloc1, m.n1, m.n1, m.p11, m.max_row11);
+  build_pattern(m.inc2, m.c2dp, m.nloc1, m.nloc1, m.n2, m.n1, m.p21, m.max_row21);
+  build_pattern(m.inc1, m.c2dp, m.nloc1, m.nloc1, m.n1, m.n1, m.p11, m.max_row11);
   build_pattern(m.inc1, m.c2d, m.nloc2, m.nloc2, m.n1, m.n2, m.p12, m.max_row12);
   build_slots(m.inc2, m.c2d, m.nloc2, m.nloc2, m.p22, m.s22);
-  build_slots(m.inc2, m.c2d, m.nloc2, m.nloc1, m.p21, m.s21);
-  build_slots(m.inc1, m.c2d, m.nloc2, m.nloc1, m.p11, m.s11);
+  build_slots(m.inc2, m.c2dp, m.nloc1, m.nloc1, m.p21, m.s21);
+  build_slots(m.inc1, m.c2dp, m.nloc1, m.nloc1, m.p11, m.s11);
   build_slots(m.inc1, m.c2d, m.nloc2, m.nloc2, m.p12, m.s12);
   build_sell(m.p22, m.e22);
   build_sell(m.p21, m.e21);
@@ -272,11 +329,12 @@ void finalize(Mesh& m) {
 
 }  // namespace
 
-Mesh* build_unit_square(int nx, int ny) {
+Mesh* build_unit_square(int nx, int ny, int pair) {
   if (nx < 1 || ny < 1) fail(IPCS_E_INVALID, "unit square needs nx, ny >= 1");
   if (int64_t(nx) * ny > (int64_t(1) << 26)) fail(IPCS_E_INVALID, "mesh too large");
   Mesh* m = new Mesh;
   m->dim = 2;
+  m->pair = pair;
   m->nv = int64_t(nx + 1) * (ny + 1);
   m->nc = 2 * int64_t(nx) * ny;
   m->X.resize(m->nv * 2);
@@ -354,11 +412,13 @@ Mesh* build_unit_cube(int nx, int ny, int nz) {
   return m;
 }
 
-Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells) {
+Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells,
+                        int pair) {
   if (dim != 2 && dim != 3) fail(IPCS_E_INVALID, "dim must be 2 or 3");
   if (nv < dim + 1 || nc < 1 || !x || !cells) fail(IPCS_E_INVALID, "empty mesh");
   Mesh* m = new Mesh;
   m->dim = dim;
+  m->pair = pair;
   m->nv = nv;
   m->nc = nc;
   m->X.assign(x, x + nv * dim);

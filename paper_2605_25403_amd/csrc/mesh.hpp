@@ -1,4 +1,4 @@
-// Host-side discretization data built once per mesh: P1/P2 DOF maps, CSR
+// Host-side discretization data built once per mesh: velocity/pressure DOF maps, CSR
 // sparsity patterns of the IPCS matrices and the row-owner assembly maps.
 //
 // Row-owner assembly: every CSR row is produced by exactly one GPU thread,
@@ -68,17 +68,28 @@ struct PartSell {
   std::vector<int32_t> src;         // [nent]
 };
 
+// The Taylor-Hood pair fixes the two spaces. Names keep the P2-P1 pair's
+// vocabulary: "2" is the velocity space, "1" the pressure space.
+//   P2-P1 (triangles, tetrahedra): velocity P2 (vertices, then edges), pressure
+//   P1 (vertices).
+//   P3-P2 (triangles): velocity P3 (vertices; two nodes per edge, edge k with
+//   sorted vertices lo < hi owning nv + 2k at (2 x_lo + x_hi)/3 and nv + 2k + 1
+//   at (x_lo + 2 x_hi)/3; one node per cell at its centroid), pressure P2.
+// In both, the first dim+1 local velocity DOFs of a cell are its vertices.
 struct Mesh {
   int dim = 0;
+  int pair = 0;                   // IPCS_PAIR_P2P1 or IPCS_PAIR_P3P2
   int64_t nv = 0, nc = 0, ne = 0;
   int nloc2 = 0, nloc1 = 0;
   std::vector<double> X;          // [nv][dim]
-  std::vector<int32_t> c2d;       // [nc][nloc2]; first dim+1 entries = P1 DOFs
+  std::vector<int32_t> c2d;       // [nc][nloc2] velocity DOFs; first dim+1 = vertices
+  std::vector<int32_t> c2dp;      // [nc][nloc1] pressure DOFs
   std::vector<int32_t> edges;     // [ne][2] sorted pairs
   int64_t n1 = 0, n2 = 0;
-  std::vector<double> x2;         // [n2][dim] P2 node coordinates
+  std::vector<double> x2;         // [n2][dim] velocity node coordinates
+  std::vector<double> xp;         // [n1][dim] pressure node coordinates
   std::vector<uint8_t> bmask;     // [n2]
-  std::vector<int32_t> bidx;      // boundary P2 nodes, ascending
+  std::vector<int32_t> bidx;      // boundary velocity nodes, ascending
   Pattern p22, p11, p12, p21;
   Sell e22, e11, e12, e21;        // SELL-64 layouts of the four patterns
   Incidence inc2, inc1;
@@ -91,8 +102,8 @@ struct Mesh {
 
   const Pattern& pattern(int which) const;
   const Sell& sell(int which) const;
-  // partition of the P1-P1 pattern by the P1 DOF (vertex) coordinates, built
-  // on first use for each part size and kept with the mesh
+  // partition of the pressure-pressure pattern by the pressure node
+  // coordinates, built on first use for each part size and kept with the mesh
   std::shared_ptr<const PartSell> parts11(int rows_max) const;
 
  private:
@@ -104,8 +115,9 @@ std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, con
                                             int dim, int rows_max);
 
 // Builders. All throw ipcs::Error on invalid input.
-Mesh* build_unit_square(int nx, int ny);
+Mesh* build_unit_square(int nx, int ny, int pair = 0);
 Mesh* build_unit_cube(int nx, int ny, int nz);
-Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells);
+Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells,
+                        int pair = 0);
 
 }  // namespace ipcs

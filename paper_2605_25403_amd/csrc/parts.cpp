@@ -147,7 +147,7 @@ std::shared_ptr<const PartSell> Mesh::parts11(int rows_max) const {
   std::lock_guard<std::mutex> lk(parts_mu);
   for (auto& q : parts_cache)
     if (q->rows_max == rows_max) return q;
-  auto q = build_parts(p11, e11, X.data(), dim, rows_max);
+  auto q = build_parts(p11, e11, xp.data(), dim, rows_max);
   parts_cache.push_back(q);
   return q;
 }

@@ -1,5 +1,5 @@
-// Degree-5 cell quadrature rules and P1/P2 Lagrange bases on the reference
-// simplex, usable from host and device code.
+// Cell quadrature rules and P1/P2/P3 Lagrange bases on the reference simplex,
+// usable from host and device code.
 //
 // Every integrand of the IPCS step with P2-P1 elements (Section 2.2.1, eq. (9))
 // is a polynomial of degree <= 5 on each cell (mass 4, convection 5, the rest
@@ -96,6 +96,79 @@ struct P2 {
     const int e = j - NV;
     const int ka = Edges<D>::a(e), kb = Edges<D>::b(e);
     return T(4) * (lam[kb] * dlam<T>(ka, r) + lam[ka] * dlam<T>(kb, r));
+  }
+};
+
+// ------------------------------------------------------------------ P3-P2 (triangles)
+// Cell rule for the P3-P2 pair, whose convection integrand P3 (P3 . grad P3)
+// has degree 8: the collapsed (Duffy) product of 5-point Gauss-Legendre rules.
+// With x = u, y = v (1 - u) the triangle integral is the integral over the unit
+// square of f(u, v (1 - u)) (1 - u); for f of degree <= 8 that integrand has
+// degree <= 9 in u and <= 8 in v, which the 5-point rule integrates exactly
+// (the rule is exact to degree 8, not 9: the factor 1 - u costs one degree).
+// Gauss-Legendre on [-1, 1], 5 points: 0 and +-(1/3) sqrt(5 -+ 2 sqrt(10/7)),
+// weights 128/225 and (322 +- 13 sqrt 70)/900; mapped to [0, 1] by t -> (1+t)/2
+// with weights halved. Point q = 5 i + j takes u from node i and v from node j.
+struct GL5 {
+  __host__ __device__ static constexpr double t(int i) {
+    constexpr double a = 0.5384693101056830910, b = 0.9061798459386639928;
+    return i == 0 ? -b : i == 1 ? -a : i == 2 ? 0.0 : i == 3 ? a : b;
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    constexpr double wa = 0.4786286704993664680, wb = 0.2369268850561890875;
+    return (i == 0 || i == 4) ? wb : (i == 1 || i == 3) ? wa : 128.0 / 225.0;
+  }
+};
+
+struct RuleT9 {
+  static constexpr int NQ = 25;
+  __host__ __device__ static constexpr double u(int q) { return 0.5 * (1.0 + GL5::t(q / 5)); }
+  __host__ __device__ static constexpr double v(int q) { return 0.5 * (1.0 + GL5::t(q % 5)); }
+  // barycentric coordinates of x = u, y = v (1 - u): lam = (1 - x - y, x, y)
+  __host__ __device__ static constexpr double lam(int q, int k) {
+    const double x = u(q), y = v(q) * (1.0 - u(q));
+    return k == 0 ? 1.0 - x - y : (k == 1 ? x : y);
+  }
+  __host__ __device__ static constexpr double w(int q) {
+    return 0.25 * GL5::w(q / 5) * GL5::w(q % 5) * (1.0 - u(q));
+  }
+};
+
+// P3 on triangles. Local order: v0, v1, v2; for each local edge (a, b) of
+// (v1v2, v2v0, v0v1) the node at lam_a = 2/3, then the node at lam_b = 2/3; the
+// centroid. Basis: vertex lam_i (3 lam_i - 1)(3 lam_i - 2) / 2; edge node p
+// of edge (p, q) 9/2 lam_p lam_q (3 lam_p - 1); centroid 27 lam_0 lam_1 lam_2.
+struct P3T {
+  static constexpr int NV = 3;
+  static constexpr int NLOC = 10;
+  // for local node j = 3 + 2e + k: the nearer vertex p and the other q
+  __host__ __device__ static constexpr int ep(int j) {
+    return ((j - 3) & 1) ? Edges<2>::b((j - 3) >> 1) : Edges<2>::a((j - 3) >> 1);
+  }
+  __host__ __device__ static constexpr int eq(int j) {
+    return ((j - 3) & 1) ? Edges<2>::a((j - 3) >> 1) : Edges<2>::b((j - 3) >> 1);
+  }
+  template <class T>
+  __host__ __device__ static constexpr T phi(int j, const T* lam) {
+    if (j < 3) return T(0.5) * lam[j] * (T(3) * lam[j] - T(1)) * (T(3) * lam[j] - T(2));
+    if (j < 9) {
+      const T lp = lam[ep(j)], lq = lam[eq(j)];
+      return T(4.5) * lp * lq * (T(3) * lp - T(1));
+    }
+    return T(27) * lam[0] * lam[1] * lam[2];
+  }
+  template <class T>
+  __host__ __device__ static constexpr T dphi(int j, int r, const T* lam) {
+    if (j < 3)
+      return T(0.5) * (T(27) * lam[j] * lam[j] - T(18) * lam[j] + T(2)) * P2<2>::dlam<T>(j, r);
+    if (j < 9) {
+      const int p = ep(j), q = eq(j);
+      const T lp = lam[p], lq = lam[q];
+      return T(4.5) * lq * (T(6) * lp - T(1)) * P2<2>::dlam<T>(p, r) +
+             T(4.5) * lp * (T(3) * lp - T(1)) * P2<2>::dlam<T>(q, r);
+    }
+    return T(27) * (lam[1] * lam[2] * P2<2>::dlam<T>(0, r) + lam[0] * lam[2] * P2<2>::dlam<T>(1, r) +
+                    lam[0] * lam[1] * P2<2>::dlam<T>(2, r));
   }
 };
 

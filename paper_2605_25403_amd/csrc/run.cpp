@@ -430,6 +430,7 @@ void Run::layout(Carver& c) {
   X = c.take<double>(nv * dim);
   c2d = c.take<int32_t>(nc * m.nloc2);
   x2 = c.take<double>(n2 * dim);
+  xp = m.pair == IPCS_PAIR_P2P1 ? X : c.take<double>(n1 * dim);
   bmask = c.take<uint8_t>(n2);
   bidx = c.take<int32_t>(std::max<int64_t>(nb, 1));
   sp22 = c.take<int32_t>(m.e22.nslices + 1);
@@ -528,8 +529,7 @@ void Run::layout(Carver& c) {
   scnt = c.take<uint32_t>(4);
   scal = c.take<double>(8);
   gb = c.take<double>(std::max<int64_t>(nb, 1) * dim);
-  const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
-  fq = c.take<double>(prm.callbacks ? (int64_t)dim * nc * nq : 1);
+  fq = c.take<double>(prm.callbacks ? (int64_t)dim * nc * cell_nq() : 1);
 }
 
 Run::~Run() {
@@ -549,6 +549,7 @@ void Run::upload_mesh() {
   up(stream, X, m.X);
   up(stream, c2d, m.c2d);
   up(stream, x2, m.x2);
+  if (xp != X) up(stream, xp, m.xp);
   up(stream, bmask, m.bmask);
   up(stream, bidx, m.bidx);
   up(stream, sp22, m.e22.sptr);
@@ -617,20 +618,21 @@ void Run::upload_mesh() {
 
 void Run::assemble_constant() {
   const Mesh& m = *mesh;
-  RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr}};
+  RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr},
+             m.pair};
   asm_mass_stiff(dim, mixed, stream, a22, cfg_mk.bs, cfg_mk.lds);
   RowAsm a21{(int32_t)n2, sp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
-             {Gc[0], Gc[1], Gc[2]}};
+             {Gc[0], Gc[1], Gc[2]}, m.pair};
   asm_grad(dim, mixed, stream, a21, cfg_g.bs, cfg_g.lds);
   RowAsm a12{(int32_t)n1, sp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
-             {Dc[0], Dc[1], Dc[2]}};
+             {Dc[0], Dc[1], Dc[2]}, m.pair};
   asm_div(dim, mixed, stream, a12, cfg_d.bs, cfg_d.lds);
   // Kp is assembled in FP64 in both forms. The mixed form keeps that FP64
   // copy for the refinement residual and gives the inner CG the same matrix
   // rounded to FP32, the FP32 operator closest to it, so that a refinement
   // pass is limited by the inner tolerance rather than by the operator.
   RowAsm a11{(int32_t)n1, sp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
-             {Kp64, nullptr, nullptr}};
+             {Kp64, nullptr, nullptr}, m.pair};
   asm_kp(dim, false, stream, a11, cfg_kp.bs, cfg_kp.lds * (8 / vsz));
   if (mixed) round_to_f32(stream, ne11, Kp64, static_cast<float*>(Kp));
   asm_lumped_p1(dim, stream, a11, w);
@@ -843,14 +845,16 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   setup_solvers();
   t = prm.t0;
   if (prm.callbacks) {
-    const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
+    const int nq = cell_nq();
     h_xq.resize((size_t)nc * nq * dim);
     for (int64_t cc = 0; cc < nc; ++cc)
       for (int q = 0; q < nq; ++q)
         for (int r = 0; r < dim; ++r) {
           double x = 0.0;
           for (int k = 0; k <= dim; ++k) {
-            const double l = dim == 2 ? Rule<2>::lam(q, k) : Rule<3>::lam(q, k);
+            const double l = mm.pair == IPCS_PAIR_P3P2 ? RuleT9::lam(q, k)
+                             : dim == 2               ? Rule<2>::lam(q, k)
+                                                      : Rule<3>::lam(q, k);
             x += l * mm.X[(size_t)mm.c2d[cc * mm.nloc2 + k] * dim + r];
           }
           h_xq[((size_t)cc * nq + q) * dim + r] = x;
@@ -864,7 +868,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
 
 void Run::set_builtin(int kind, const double* p, int np) {
   const bool ok2 = kind == IPCS_SOL_TAYLOR_GREEN_2D || kind == IPCS_SOL_JOHN_2D ||
-                   kind == IPCS_SOL_POLY_STEADY_2D;
+                   kind == IPCS_SOL_POLY_STEADY_2D || kind == IPCS_SOL_POLY_CUBIC_2D;
   const bool ok3 = kind == IPCS_SOL_BELTRAMI_3D || kind == IPCS_SOL_POLY_STEADY_3D;
   if (!((dim == 2 && ok2) || (dim == 3 && ok3)))
     fail(IPCS_E_INVALID, "built-in solution kind does not match the mesh dimension");
@@ -880,7 +884,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
   bi = b;
   f_cb = g_cb = nullptr;
   eval_velocity(stream, dim, bi, x2, n2, t, U, n2);
-  eval_pressure(stream, dim, bi, X, nv, t, P);
+  eval_pressure(stream, dim, bi, xp, n1, t, P);
   sub_weighted_mean(stream, n1, w, P, spart, scal + 2);
   phase_next = IPCS_PHASE_ASM;
   HIP_OK(hipStreamSynchronize(stream));
@@ -938,10 +942,10 @@ void Run::asm_phase() {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}};
+             {E, nullptr, nullptr}, m.pair};
   has_F = false;
   if (f_cb) {
-    const int nq = dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
+    const int nq = cell_nq();
     std::vector<double> vals((size_t)nc * nq * dim), tr(vals.size());
     f_cb(f_ctx, dim, nc * nq, h_xq.data(), t1, vals.data());
     for (int64_t i = 0; i < nc * nq; ++i)
@@ -1158,7 +1162,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}};
+             {E, nullptr, nullptr}, m.pair};
   auto launch = [&]() {
     switch (kernel) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;

@@ -12,6 +12,7 @@
 #include "launch.hpp"
 #include "ipcs.h"
 #include "mesh.hpp"
+#include "rules.hpp"
 
 namespace ipcs {
 
@@ -129,6 +130,7 @@ struct Run {
   double* X = nullptr;
   int32_t* c2d = nullptr;
   double* x2 = nullptr;
+  double* xp = nullptr;        // pressure node coordinates (X itself for P2-P1)
   uint8_t* bmask = nullptr;
   int32_t* bidx = nullptr;
   // per pattern: SELL slice offsets, SELL columns, CSR row pointer (row lengths)
@@ -207,6 +209,10 @@ struct Run {
   void sizes_from_mesh();
   void choose_poisson_form();
   void layout(Carver& c);
+  // points per cell of the pair's cell rule (the forcing quadrature)
+  int cell_nq() const {
+    return mesh->pair == IPCS_PAIR_P3P2 ? RuleT9::NQ : dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
+  }
   void create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, int64_t bytes,
               hipStream_t s);
   void upload_mesh();

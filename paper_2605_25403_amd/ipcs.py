@@ -26,12 +26,14 @@ IPCS_OK, IPCS_E_INVALID, IPCS_E_NOMEM, IPCS_E_DEVICE = 0, -1, -2, -3
 IPCS_E_NOT_CONVERGED, IPCS_E_BREAKDOWN, IPCS_E_NONFINITE = -4, -5, -6
 IPCS_E_STATE, IPCS_E_CAPACITY = -7, -8
 IPCS_SPACE_P1, IPCS_SPACE_P2 = 1, 2
+IPCS_PAIR_P2P1, IPCS_PAIR_P3P2 = 0, 1
 IPCS_PATTERN_P2P2, IPCS_PATTERN_P1P1, IPCS_PATTERN_P1P2, IPCS_PATTERN_P2P1 = 0, 1, 2, 3
 IPCS_FP64, IPCS_MIXED = 0, 1
 IPCS_CONV_EXPLICIT, IPCS_CONV_SEMI_IMPLICIT = 0, 1
 IPCS_SCHEME_IPCS, IPCS_SCHEME_CHORIN = 0, 1
 IPCS_SOL_TAYLOR_GREEN_2D, IPCS_SOL_JOHN_2D, IPCS_SOL_BELTRAMI_3D = 1, 2, 3
 IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D = 4, 5
+IPCS_SOL_POLY_CUBIC_2D = 6
 IPCS_PHASE_ASM, IPCS_PHASE_MOMENTUM, IPCS_PHASE_PRESSURE, IPCS_PHASE_CORRECTION = 0, 1, 2, 3
 IPCS_FIELD_U, IPCS_FIELD_P, IPCS_FIELD_USTAR, IPCS_FIELD_DP = 0, 1, 2, 3
 IPCS_FIELD_RHS_MOM, IPCS_FIELD_RHS_P = 4, 5
@@ -92,6 +94,10 @@ _SIGS = {
     "ipcs_mesh_unit_square": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_P)]),
     "ipcs_mesh_unit_cube": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "ipcs_mesh_from_arrays": (C.c_int, [C.c_int32, C.c_int64, _P, C.c_int64, _P, C.POINTER(_P)]),
+    "ipcs_mesh_unit_square_pair": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "ipcs_mesh_from_arrays_pair": (C.c_int, [C.c_int32, C.c_int64, _P, C.c_int64, _P, C.c_int32,
+                                             C.POINTER(_P)]),
+    "ipcs_mesh_pair": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "ipcs_mesh_counts": (C.c_int, [_P, C.POINTER(ipcs_counts)]),
     "ipcs_mesh_dof_coords": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
     "ipcs_mesh_cell_dofs": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
@@ -153,6 +159,12 @@ def ipcs_mesh_unit_square(nx, ny):
     return h
 
 
+def ipcs_mesh_unit_square_pair(nx, ny, pair):
+    h = C.c_void_p()
+    _check(lib.ipcs_mesh_unit_square_pair(nx, ny, pair, C.byref(h)))
+    return h
+
+
 def ipcs_mesh_unit_cube(nx, ny, nz):
     h = C.c_void_p()
     _check(lib.ipcs_mesh_unit_cube(nx, ny, nz, C.byref(h)))
@@ -166,6 +178,21 @@ def ipcs_mesh_from_arrays(x, cells):
     _check(lib.ipcs_mesh_from_arrays(x.shape[1], x.shape[0], _ptr(x), cells.shape[0],
                                      _ptr(cells), C.byref(h)))
     return h
+
+
+def ipcs_mesh_from_arrays_pair(x, cells, pair):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib.ipcs_mesh_from_arrays_pair(x.shape[1], x.shape[0], _ptr(x), cells.shape[0],
+                                          _ptr(cells), pair, C.byref(h)))
+    return h
+
+
+def ipcs_mesh_pair(m):
+    v = C.c_int32()
+    _check(lib.ipcs_mesh_pair(m, C.byref(v)))
+    return v.value
 
 
 def ipcs_mesh_counts(m):
@@ -184,7 +211,10 @@ def ipcs_mesh_dof_coords(m, space):
 
 def ipcs_mesh_cell_dofs(m, space):
     c = ipcs_mesh_counts(m)
-    nl = c.dim + 1 if space == IPCS_SPACE_P1 else (6 if c.dim == 2 else 10)
+    if ipcs_mesh_pair(m) == IPCS_PAIR_P3P2:
+        nl = 6 if space == IPCS_SPACE_P1 else 10
+    else:
+        nl = c.dim + 1 if space == IPCS_SPACE_P1 else (6 if c.dim == 2 else 10)
     out = np.empty((c.nc, nl), dtype=np.int32)
     _check(lib.ipcs_mesh_cell_dofs(m, space, _ptr(out), out.size))
     return out
@@ -371,20 +401,28 @@ class Mesh:
         self.counts = ipcs_mesh_counts(handle)
 
     @classmethod
-    def unit_square(cls, nx, ny=None):
-        return cls(ipcs_mesh_unit_square(nx, ny or nx))
+    def unit_square(cls, nx, ny=None, pair=IPCS_PAIR_P2P1):
+        if pair == IPCS_PAIR_P2P1:
+            return cls(ipcs_mesh_unit_square(nx, ny or nx))
+        return cls(ipcs_mesh_unit_square_pair(nx, ny or nx, pair))
 
     @classmethod
     def unit_cube(cls, nx, ny=None, nz=None):
         return cls(ipcs_mesh_unit_cube(nx, ny or nx, nz or nx))
 
     @classmethod
-    def from_arrays(cls, x, cells):
-        return cls(ipcs_mesh_from_arrays(x, cells))
+    def from_arrays(cls, x, cells, pair=IPCS_PAIR_P2P1):
+        if pair == IPCS_PAIR_P2P1:
+            return cls(ipcs_mesh_from_arrays(x, cells))
+        return cls(ipcs_mesh_from_arrays_pair(x, cells, pair))
 
     @property
     def dim(self):
         return self.counts.dim
+
+    @property
+    def pair(self):
+        return ipcs_mesh_pair(self.h)
 
     def __del__(self, _destroy=lib.ipcs_mesh_destroy):
         if getattr(self, "h", None):

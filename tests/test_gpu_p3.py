@@ -1,0 +1,197 @@
+"""GPU parity of the P3-P2 Taylor-Hood pair (triangles; the paper's
+higher-order study, table "convergence_p3_p2") against the FP64 oracle,
+through the C ABI.
+
+Bars as for P2-P1: assembled matrices max|dA|/max|A| <= 1e-12, fields
+||dx||/||x|| <= 1e-10 per step (both sides solve to 1e-13); the mixed form
+within its stated bounds (matrices 1e-6, velocity 1e-5 per step, pressure
+1e-4 per step, the reason at its test). Cases: the
+structured square at sizes spanning several SELL slices with ragged tails,
+an unstructured jittered mesh, the forced John problem, the cubic steady
+state (a fixed point of the step) at a small and a large size, both Poisson
+CG forms, and a batch mixing P3-P2 and P2-P1 runs (bitwise their alone
+results).
+"""
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_2605_25403_amd.workloads import jittered_mesh
+from tests.gpu_common import field_errors, make_pair, mat_rel, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+MAT_TOL = 1e-12
+FIELD_TOL = 1e-10
+
+
+def _matrices_match(I, dim, o, r, tol):
+    assert mat_rel(r.matrix(I.IPCS_MAT_M), o.M) <= tol
+    assert mat_rel(r.matrix(I.IPCS_MAT_K), o.K) <= tol
+    assert mat_rel(r.matrix(I.IPCS_MAT_KP), o.Kp) <= tol
+    assert mat_rel(r.matrix(I.IPCS_MAT_A_ELIM), o.A_el) <= tol
+    assert mat_rel(r.matrix(I.IPCS_MAT_M_ELIM), o.M_el) <= tol
+    for c in range(dim):
+        assert mat_rel(r.matrix(I.IPCS_MAT_D0 + c), o.D[c]) <= tol
+        assert mat_rel(r.matrix(I.IPCS_MAT_G0 + c), o.G[c]) <= tol
+
+
+@pytest.mark.parametrize("n", [3, 8, 13])
+def test_p3_constant_matrices(n):
+    torch, I = require_gpu()
+    print(f"P3-P2 constant matrices n={n}", flush=True)
+    S, o, r = make_pair(I, 2, n, "tg", 0.013, 0.007, p3=True)
+    assert r.mesh.pair == I.IPCS_PAIR_P3P2
+    assert r.mesh.counts.n2 == S.Nu and r.mesh.counts.n1 == S.Np
+    _matrices_match(I, 2, o, r, MAT_TOL)
+
+
+def test_p3_constant_matrices_unstructured():
+    torch, I = require_gpu()
+    print("P3-P2 constant matrices, jittered mesh", flush=True)
+    S, o, r = make_pair(I, 2, 0, "tg", 0.013, 0.007, p3=True, arrays=jittered_mesh(2, 9, 5))
+    _matrices_match(I, 2, o, r, MAT_TOL)
+
+
+@pytest.mark.parametrize("n,kind", [(8, "tg"), (6, "john")])
+def test_p3_convection_operator_and_momentum_rhs(n, kind):
+    torch, I = require_gpu()
+    print(f"P3-P2 convection/rhs n={n} {kind}", flush=True)
+    nu, dt = 0.02, 0.01
+    S, o, r = make_pair(I, 2, n, kind, nu, dt, p3=True)
+    r.phase(I.IPCS_PHASE_ASM)
+    C = fem.convection(S, o.U)
+    E = (o.M / dt - C).tocsr()
+    E.sort_indices()
+    assert mat_rel(r.matrix(I.IPCS_MAT_E), E) <= MAT_TOL
+    t1 = o.t + dt
+    g = o.dirichlet(t1)
+    F = o.forcing(t1)
+    b = r.field(I.IPCS_FIELD_RHS_MOM)
+    for c in range(2):
+        ref = o.M @ o.U[c] / dt - o.G[c] @ o.P + F[c] - C @ o.U[c]
+        ref = fem.lift(o.A, ref, o.bmask, g[c])
+        assert rel(b[c], ref) <= MAT_TOL
+
+
+@pytest.mark.parametrize("n,kind,arrays", [(8, "tg", None), (7, "john", None),
+                                           (0, "tg", "jittered")])
+def test_p3_each_substep_from_identical_state(n, kind, arrays):
+    torch, I = require_gpu()
+    print(f"P3-P2 substeps n={n} {kind} {arrays}", flush=True)
+    nu, dt = 0.01, 0.01
+    arr = jittered_mesh(2, 10, 7) if arrays else None
+    S, o, r = make_pair(I, 2, n, kind, nu, dt, p3=True, arrays=arr)
+    t1 = o.t + dt
+    g = o.dirichlet(t1)
+    r.phase(I.IPCS_PHASE_ASM)
+    st = r.phase(I.IPCS_PHASE_MOMENTUM)
+    Us_o, _, _ = o.momentum(t1, g)
+    Us = r.field(I.IPCS_FIELD_USTAR)
+    for c in range(2):
+        assert rel(Us[c], Us_o[c]) <= FIELD_TOL, (c, st)
+    st = r.phase(I.IPCS_PHASE_PRESSURE)
+    dP_o, _ = o.pressure(Us_o)
+    assert rel(r.field(I.IPCS_FIELD_DP), dP_o) <= FIELD_TOL, st
+    r.phase(I.IPCS_PHASE_CORRECTION)
+    Un_o, _ = o.correction(Us_o, dP_o, g)
+    U = r.velocity()
+    for c in range(2):
+        assert rel(U[c], Un_o[c]) <= FIELD_TOL
+    assert rel(r.pressure(), o.P + dP_o) <= FIELD_TOL
+
+
+@pytest.mark.parametrize("semi", [False, True])
+def test_p3_taylor_green_ten_steps(semi):
+    """The library starts from its own device-evaluated state (P3 velocity and
+    P2 pressure interpolation at its node coordinates)."""
+    torch, I = require_gpu()
+    print(f"P3-P2 ten steps semi={semi}", flush=True)
+    S, o, r = make_pair(I, 2, 8, "tg", 0.01, 0.01, same_state=False, semi=semi, p3=True)
+    errs = field_errors(o, r)
+    assert max(errs) <= 1e-13, errs
+    for step in range(10):
+        st = r.advance(1)[0]
+        o.step()
+        errs = field_errors(o, r)
+        assert max(errs) <= FIELD_TOL, (step, errs, st)
+
+
+@pytest.mark.parametrize("n,semi", [(6, False), (6, True), (96, False)])
+def test_p3_cubic_fixed_point(n, semi):
+    """Cubic velocity and quadratic pressure are reproduced by the step (every
+    integrand has degree <= 8). n = 96: 85k velocity DOFs per component, the
+    fused Poisson CG over many parts."""
+    torch, I = require_gpu()
+    print(f"P3-P2 cubic fixed point n={n} semi={semi}", flush=True)
+    S, o, r = make_pair(I, 2, n, "cubic", 0.07, 0.05, tol=1e-14, same_state=False, semi=semi,
+                        p3=True)
+    U0, P0 = r.velocity().copy(), r.pressure().copy()
+    np.testing.assert_allclose(U0, o.U, atol=1e-14)
+    np.testing.assert_allclose(P0, o.P, atol=1e-14)
+    r.advance(2)
+    scale = np.abs(U0).max()
+    assert np.abs(r.velocity() - U0).max() < 1e-11 * scale
+    assert np.abs(r.pressure() - P0).max() < 1e-10
+
+
+def test_p3_mixed_form_within_bound():
+    """Velocity within the mixed form's 1e-5 per step. The pressure bar is
+    1e-4: the increment comes from -(1/dt) D U*, a sum of terms far larger
+    than the result (U* is nearly divergence-free, more so with P3 than with
+    P2), so the FP32 rounding of D and U* (about 6e-8 of each term) is
+    amplified by the ratio of the terms to the sum, several hundred here."""
+    torch, I = require_gpu()
+    print("P3-P2 mixed form", flush=True)
+    S, o, r = make_pair(I, 2, 8, "tg", 0.01, 0.01, p3=True, precision=I.IPCS_MIXED,
+                        tol_ir=1e-10)
+    _matrices_match(I, 2, o, r, 1e-6)
+    for step in range(3):
+        r.advance(1)
+        o.step()
+        errs = field_errors(o, r)
+        assert max(errs[:2]) <= 1e-5 and errs[2] <= 1e-4, (step, errs)
+
+
+def test_p3_fused_and_two_kernel_poisson_forms_agree():
+    torch, I = require_gpu()
+    print("P3-P2 fused vs two-kernel", flush=True)
+    m = I.Mesh.unit_square(24, pair=I.IPCS_PAIR_P3P2)
+    out = []
+    for rows in (0, -1):
+        p = I.ipcs_params_default(nu=0.004, dt=0.003, tol_p=1e-13, poisson_part_rows=rows)
+        r = I.Run(m, p)
+        r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (2 * np.pi,))
+        r.advance(3)
+        out.append(r)
+    a, b = out
+    assert a.poisson_partition()["rows_max"] > 0 and b.poisson_partition()["rows_max"] == 0
+    for c in range(2):
+        assert rel(a.velocity()[c], b.velocity()[c]) <= FIELD_TOL
+    assert rel(a.pressure(), b.pressure()) <= FIELD_TOL
+
+
+def test_p3_and_p2_runs_in_one_batch_bitwise():
+    torch, I = require_gpu()
+    print("P3-P2 with P2-P1 in one batch", flush=True)
+
+    def new_run(n, pair, stream=None):
+        p = I.ipcs_params_default(nu=0.01, dt=0.01)
+        r = I.Run(I.Mesh.unit_square(n, pair=pair), p, stream=stream)
+        r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (np.pi,))
+        return r
+
+    cases = [(8, I.IPCS_PAIR_P3P2), (12, I.IPCS_PAIR_P2P1), (11, I.IPCS_PAIR_P3P2)]
+    alone = []
+    for n, pair in cases:
+        r = new_run(n, pair)
+        r.advance(3)
+        alone.append((r.velocity(), r.pressure()))
+    s = torch.cuda.Stream()
+    runs = [new_run(n, pair, stream=s) for n, pair in cases]
+    for _ in range(3):
+        rc, st = I.ipcs_batch_step([r.h for r in runs], s.cuda_stream)
+        assert rc == I.IPCS_OK, st
+    for (U, P), r in zip(alone, runs):
+        np.testing.assert_array_equal(r.velocity(), U)
+        np.testing.assert_array_equal(r.pressure(), P)

@@ -41,19 +41,23 @@ def lib_mesh(dim, n):
 
 
 def compare(S, m):
+    """Counts, DOF numbering and coordinates, boundary and the four patterns of
+    the mesh's pair (velocity: the P2 names, pressure: the P1 names) against
+    the oracle's space of the same pair, exactly."""
     c = m.counts
-    assert (c.dim, c.nv, c.nc, c.n1, c.n2) == (S.dim, S.Nv, S.Nc, S.N1, S.N2)
-    np.testing.assert_array_equal(I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2), S.x2)
-    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P2), S.c2d2)
-    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P1), S.c2d1)
-    np.testing.assert_array_equal(I.ipcs_mesh_boundary(m.h).astype(bool), S.boundary2)
-    assert c.nb2 == S.boundary2.sum()
+    assert (c.dim, c.nv, c.nc, c.n1, c.n2) == (S.dim, S.Nv, S.Nc, S.Np, S.Nu)
+    np.testing.assert_array_equal(I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2), S.xu)
+    np.testing.assert_array_equal(I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P1), S.xp)
+    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P2), S.c2du)
+    np.testing.assert_array_equal(I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P1), S.c2dp)
+    np.testing.assert_array_equal(I.ipcs_mesh_boundary(m.h).astype(bool), S.bmask_u)
+    assert c.nb2 == S.bmask_u.sum()
     ones = lambda rows, cols: fem.assemble(np.ones((S.Nc, rows.shape[1], cols.shape[1])),
                                            rows, cols, (rows.max() + 1, cols.max() + 1))
-    for which, (r, cc) in {I.IPCS_PATTERN_P2P2: (S.c2d2, S.c2d2),
-                           I.IPCS_PATTERN_P1P1: (S.c2d1, S.c2d1),
-                           I.IPCS_PATTERN_P1P2: (S.c2d1, S.c2d2),
-                           I.IPCS_PATTERN_P2P1: (S.c2d2, S.c2d1)}.items():
+    for which, (r, cc) in {I.IPCS_PATTERN_P2P2: (S.c2du, S.c2du),
+                           I.IPCS_PATTERN_P1P1: (S.c2dp, S.c2dp),
+                           I.IPCS_PATTERN_P1P2: (S.c2dp, S.c2du),
+                           I.IPCS_PATTERN_P2P1: (S.c2du, S.c2dp)}.items():
         A = ones(r, cc)
         rp, col = I.ipcs_mesh_pattern(m.h, which)
         np.testing.assert_array_equal(rp, A.indptr)
@@ -134,3 +138,30 @@ def test_jittered_relabelled_meshes_match_oracle(dim, n, seed):
     from paper_2605_25403_amd.workloads import jittered_mesh
     X, cells = jittered_mesh(dim, n, seed)
     compare(fem.Space(X, cells), I.Mesh.from_arrays(X, cells))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16])
+def test_p3_p2_square_matches_oracle_exactly(n):
+    m = I.Mesh.unit_square(n, pair=I.IPCS_PAIR_P3P2)
+    assert m.pair == I.IPCS_PAIR_P3P2
+    compare(fem.Space(*mesh.unit_square(n, n), order=3), m)
+
+
+@pytest.mark.parametrize("n,seed", [(7, 0), (12, 5)])
+def test_p3_p2_jittered_meshes_match_oracle(n, seed):
+    """Random vertex labels and orientations exercise the edge-node order (the
+    node nearer the edge's lower vertex first)."""
+    from paper_2605_25403_amd.workloads import jittered_mesh
+    X, cells = jittered_mesh(2, n, seed)
+    compare(fem.Space(X, cells, order=3), I.Mesh.from_arrays(X, cells, pair=I.IPCS_PAIR_P3P2))
+
+
+def test_pair_arguments_are_checked():
+    with pytest.raises(I.IpcsError):
+        I.ipcs_mesh_unit_square_pair(2, 2, 7)
+    from paper_2605_25403_amd.workloads import jittered_mesh
+    X, cells = jittered_mesh(3, 2, 0)
+    with pytest.raises(I.IpcsError) as e:
+        I.ipcs_mesh_from_arrays_pair(X, cells, I.IPCS_PAIR_P3P2)
+    assert "triangles" in I.ipcs_last_error()
+    assert I.Mesh.unit_square(3).pair == I.IPCS_PAIR_P2P1
