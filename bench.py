@@ -296,6 +296,51 @@ def scheme_forms(w, steps, torch, I):
     return out
 
 
+def pair_forms(w, steps, torch, I):
+    """The P3-P2 pair against P2-P1 on 2D Taylor-Green (the workload's k, nu,
+    dt, tolerance; FP64), with the same pressure system size: P2-P1 on the
+    workload's n x n squares, P3-P2 on n/2 x n/2 (both pressure spaces have
+    (n+1)^2 nodes). Per pair: throughput, iterations, per-launch times of the
+    convection assembly and the Poisson CG, and the nodal relative L2
+    distance to the interpolated exact solution after `steps` steps."""
+    out = {"steps": steps}
+    for name, pair, n in (("p2p1", I.IPCS_PAIR_P2P1, w["n"]),
+                          ("p3p2", I.IPCS_PAIR_P3P2, w["n"] // 2)):
+        m = I.Mesh.unit_square(n, pair=pair)
+        c = m.counts
+        ndof = 2 * c.n2 + c.n1
+        base = dict(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"], tol_corr=w["tol"])
+        r = I.Run(m, I.ipcs_params_default(**base), stream=torch.cuda.Stream())
+        r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        lat, it_p = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat.append(time.perf_counter() - t0)
+            it_p.append(st["it_p"])
+        ex = I.Run(m, I.ipcs_params_default(t0=r.time(), **base))
+        ex.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        Ue, Pe = ex.velocity(), ex.pressure()
+        eu = float(np.linalg.norm(r.velocity() - Ue) / np.linalg.norm(Ue))
+        ep = float(np.linalg.norm(r.pressure() - Pe) / np.linalg.norm(Pe))
+        del ex
+        # per-launch kernel times over two more steps (after the errors)
+        r.kernel_timing((1 << I.IPCS_NKERNEL) - 1)
+        r.advance(2)
+        torch.cuda.synchronize()
+        kms, kcnt = r.kernel_times()
+        r.kernel_timing(0)
+        us = lambda k: 1000.0 * kms[k] / kcnt[k] if kcnt[k] else None
+        ms = 1000.0 * float(np.median(lat))
+        out[name] = {"n": n, "dofs": int(ndof), "velocity_dofs_per_component": int(c.n2),
+                     "pressure_dofs": int(c.n1), "value": ndof / (ms / 1000.0),
+                     "p50_step_ms": ms, "pressure_iterations_median": float(np.median(it_p)),
+                     "asm_conv_us": us(I.IPCS_KERNEL_ASM_CONV),
+                     "pcg_fused_p_us": us(I.IPCS_KERNEL_PCG_FUSED_P),
+                     "rel_l2_to_exact_u": eu, "rel_l2_to_exact_p": ep}
+    return out
+
+
 def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16):
     """C5: Poisson-arrival stream of 2D TG requests (n in {32,64,128,256},
     seed-drawn k and nu, 50 steps at dt = 1e-3), mixed form, continuous
@@ -455,6 +500,8 @@ def main():
         out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
                         "schemes": scheme_forms(w, args.form_steps, torch, I),
                         "serving": serving_form(torch, I)}
+        if w["dim"] == 2:
+            out["forms"]["pairs"] = pair_forms(w, args.form_steps, torch, I)
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
