@@ -41,7 +41,7 @@ KERNELS = {
 }
 
 
-def kernel_bytes(kernel, c, dim, vsz=8):
+def kernel_bytes(kernel, c, dim, vsz=8, p3=False):
     """Algorithmic bytes per launch: each array read once, each output written
     once, vsz-byte matrix values, 8-byte vectors, 4-byte indices (2-byte local
     indices in the fused Poisson CG; its halo re-reads are not counted)
@@ -67,7 +67,7 @@ def kernel_bytes(kernel, c, dim, vsz=8):
         return (vsz + 4) * nnz22 + sl2 + dim * 2 * 8 * n2
     if kernel == "pcg_update_m":   # dinv; x, r, p, s, w in, x, r, p, s, u out each
         return 8 * n2 + dim * 10 * 8 * n2
-    nloc = 6 if dim == 2 else 10
+    nloc = 10 if (p3 or dim == 3) else 6
     if kernel == "asm_conv" and dim == 2:   # row-owner: E out; U, cell DOFs, vertices in
         return vsz * nnz22 + 8 * dim * n2 + 4 * nloc * c.nc + 8 * dim * c.nv
     if kernel == "asm_conv":       # 3D cell pass: local matrices out; U, DOFs, vertices in
@@ -105,7 +105,8 @@ def cpu_baseline(w, budget_steps=1):
     from threadpoolctl import threadpool_info
     from oracle import fem, ipcs, mesh, problems
     dim, n = w["dim"], w["n"]
-    S = fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)))
+    order = 3 if w.get("pair", 0) == 1 else 2
+    S = fem.Space(*(mesh.unit_square(n, n) if dim == 2 else mesh.unit_cube(n, n, n)), order=order)
     pb = problems.TaylorGreen2D(w["k"], w["nu"]) if dim == 2 else problems.Beltrami3D(nu=w["nu"])
     o = ipcs.IPCS(S, pb, ipcs.Params(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
                                      tol_corr=w["tol"]))
@@ -114,8 +115,7 @@ def cpu_baseline(w, budget_steps=1):
         o.step()
     dt = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    from paper_2605_25403_amd.workloads import dofs
-    return {"value": dofs(dim, n) * budget_steps / dt, "unit": "DOF-steps/s",
+    return {"value": (dim * S.Nu + S.Np) * budget_steps / dt, "unit": "DOF-steps/s",
             "cores": int(threads), "kind": "oracle",
             "sample": f"{budget_steps} of {w['steps']} IPCS steps of the same workload from "
                       f"the interpolated initial state ({dt:.1f} s; setup not timed; "
@@ -332,11 +332,14 @@ def pair_forms(w, steps, torch, I):
         r.kernel_timing(0)
         us = lambda k: 1000.0 * kms[k] / kcnt[k] if kcnt[k] else None
         ms = 1000.0 * float(np.median(lat))
+        fus = us(I.IPCS_KERNEL_PCG_FUSED_P)
+        fgb = kernel_bytes("pcg_fused_p", c, 2, 8) / (fus * 1e-6) / 1e9 if fus else None
         out[name] = {"n": n, "dofs": int(ndof), "velocity_dofs_per_component": int(c.n2),
                      "pressure_dofs": int(c.n1), "value": ndof / (ms / 1000.0),
                      "p50_step_ms": ms, "pressure_iterations_median": float(np.median(it_p)),
                      "asm_conv_us": us(I.IPCS_KERNEL_ASM_CONV),
-                     "pcg_fused_p_us": us(I.IPCS_KERNEL_PCG_FUSED_P),
+                     "pcg_fused_p_us": fus, "pcg_fused_p_GBps": fgb,
+                     "pcg_fused_p_frac_of_hbm_peak": fgb / PEAK_HBM_GBS if fgb else None,
                      "rel_l2_to_exact_u": eu, "rel_l2_to_exact_p": ep}
     return out
 
@@ -411,7 +414,8 @@ def main():
     steps = args.steps if args.steps is not None else w["steps"]
     dim, n = w["dim"], w["n"]
     mixed = w["precision"] == "mixed"
-    m = I.Mesh.unit_square(n) if dim == 2 else I.Mesh.unit_cube(n)
+    p3 = w.get("pair", 0) == I.IPCS_PAIR_P3P2
+    m = I.Mesh.unit_square(n, pair=w.get("pair", 0)) if dim == 2 else I.Mesh.unit_cube(n)
     p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
                               tol_corr=w["tol"],
                               precision=I.IPCS_MIXED if mixed else I.IPCS_FP64)
@@ -421,7 +425,7 @@ def main():
         r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
     else:
         r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
-    ndof = dofs(dim, n)
+    ndof = dim * m.counts.n2 + m.counts.n1      # velocity components and pressure
 
     for _ in range(args.warmup):
         r.advance(1)
@@ -453,7 +457,7 @@ def main():
         if kcnt[kid] == 0:
             continue
         us = 1000.0 * kms[kid] / kcnt[kid]
-        b = kernel_bytes(name, c, dim, 4 if mixed else 8)
+        b = kernel_bytes(name, c, dim, 4 if mixed else 8, p3)
         kern[name] = {"us_per_launch": us, "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
                       "launches_per_step": kcnt[kid] / ksteps,
                       "ms_per_step": kms[kid] / ksteps}
@@ -482,7 +486,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {dim}D P2-P1 IPCS "
+        "config": {"workload": f"{args.workload}: {dim}D {'P3-P2' if p3 else 'P2-P1'} IPCS "
                                f"{'mixed' if mixed else 'FP64 plain'}, "
                                f"unit {'square' if dim == 2 else 'cube'} {n}^{dim} "
                                f"({c.nc} cells), {'TG' if dim == 2 else 'Beltrami'} "
@@ -496,7 +500,7 @@ def main():
                             "correction": float(np.median(ph[:, 3]))},
         "iterations_median": {"momentum": it_m, "pressure": it_p, "correction": it_c},
     }
-    if not args.no_forms and not mixed:
+    if not args.no_forms and not mixed and not p3:
         out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
                         "schemes": scheme_forms(w, args.form_steps, torch, I),
                         "serving": serving_form(torch, I)}

@@ -35,6 +35,10 @@ WORKLOADS = {
     # 64^3 cubes x 6 Kuhn tets, Beltrami a = pi/4, d = pi/2, nu = 0.01, 50 steps
     "c4": dict(dim=3, n=64, dt=1e-3, steps=50, seed=None, nu=0.01, tol=1e-12,
                precision="mixed"),
+    # the c2 problem with the P3-P2 pair on 256 x 256 squares: P3 velocity
+    # (591,361 nodes per component), P2 pressure with as many nodes as c2's P1
+    "c2p3": dict(dim=2, n=256, dt=1e-3, steps=100, seed=0, tol=1e-12, precision="fp64",
+                 pair=1),
 }
 
 
