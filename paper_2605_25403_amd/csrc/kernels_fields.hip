@@ -124,6 +124,10 @@ struct Ptrs3 {
 // b_c[i] = sum_j A[ij] X_c[j] - sc * sum_k Gc[ik] Y[k] + F_c[i] - sum lift[i] g_c
 // on interior rows; g_c[i] on boundary rows. One thread per row, both matrices
 // in SELL-64 layout (coalesced value and column loads across the wavefront).
+// Entries are taken eight at a time: their values and columns are loaded,
+// then all their gathers, before any is added (the last chunk re-reads entry
+// w-1 and adds zero for it), so that a lane keeps 8 D gathers in flight; the
+// additions keep the entry order. Rows past n2 compute row 0 and discard it.
 template <int D, class VT>
 __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
                                                 const int32_t* col22, const VT* A,
@@ -134,45 +138,74 @@ __global__ void __launch_bounds__(256) k_rhs_p2(int64_t n2, const int32_t* sp22,
                                                 const int32_t* lift_ptr, const int32_t* lift_col,
                                                 const double* lift, const uint8_t* bmask,
                                                 const double* g, double* b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n2) return;
-  if (bmask[i]) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) b[c * n2 + i] = g[c * n2 + i];
-    return;
-  }
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i0 < n2;
+  const int64_t i = live ? i0 : 0;
+  const gptr<const double> Xg = G(X), Yg = G(Y), gg = G(g);
   double s[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) s[c] = 0.0;
   {
-    const int sl = (int)(i >> 6), b0 = sp22[sl], w = (sp22[sl + 1] - b0) >> 6;
+    const gptr<const VT> Ag = G(A);
+    const gptr<const int32_t> cg = G(col22);
+    const int sl = (int)(i >> 6), b0 = G(sp22)[sl], w = (G(sp22)[sl + 1] - b0) >> 6;
     const int base = b0 + (int)(i & 63);
-    for (int k = 0; k < w; ++k) {
-      const double a = (double)A[base + 64 * k];
-      const int j = col22[base + 64 * k];
+    for (int k = 0; k < w; k += 8) {
+      int jj[8];
+      double a[8];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s[c] += a * X[c * n2 + j];
+      for (int q = 0; q < 8; ++q) {
+        const int kk = k + q < w ? k + q : w - 1;
+        jj[q] = cg[base + 64 * kk];
+        a[q] = (double)Ag[base + 64 * kk];
+      }
+      double xv[D][8];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[c][q] = Xg[c * n2 + jj[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int c = 0; c < D; ++c) s[c] += k + q < w ? a[q] * xv[c][q] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) s[c] *= sa;
   }
   {
-    const int sl = (int)(i >> 6), b0 = sp21[sl], w = (sp21[sl + 1] - b0) >> 6;
+    const gptr<const int32_t> cg = G(col21);
+    const int sl = (int)(i >> 6), b0 = G(sp21)[sl], w = (G(sp21)[sl + 1] - b0) >> 6;
     const int base = b0 + (int)(i & 63);
-    for (int k = 0; k < w; ++k) {
-      const double y = Y[col21[base + 64 * k]];
+    for (int k = 0; k < w; k += 8) {
+      double y[8], gv[D][8];
 #pragma unroll
-      for (int c = 0; c < D; ++c) s[c] -= sc * ((double)Gc.p[c][base + 64 * k] * y);
+      for (int q = 0; q < 8; ++q) {
+        const int kk = k + q < w ? k + q : w - 1;
+#pragma unroll
+        for (int c = 0; c < D; ++c) gv[c][q] = (double)G(Gc.p[c])[base + 64 * kk];
+        y[q] = Yg[cg[base + 64 * kk]];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int c = 0; c < D; ++c) s[c] -= k + q < w ? sc * (gv[c][q] * y[q]) : 0.0;
     }
   }
-  for (int e = lift_ptr[i]; e < lift_ptr[i + 1]; ++e) {
-    const double l = lift[e];
-    const int j = lift_col[e];
+  for (int e = G(lift_ptr)[i]; e < G(lift_ptr)[i + 1]; ++e) {
+    const double l = G(lift)[e];
+    const int j = G(lift_col)[e];
 #pragma unroll
-    for (int c = 0; c < D; ++c) s[c] -= l * g[c * n2 + j];
+    for (int c = 0; c < D; ++c) s[c] -= l * gg[c * n2 + j];
+  }
+  if (!live) return;
+  const gptr<double> bg = G(b);
+  if (G(bmask)[i]) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) bg[c * n2 + i] = gg[c * n2 + i];
+    return;
   }
 #pragma unroll
-  for (int c = 0; c < D; ++c) b[c * n2 + i] = s[c] + (F ? F[c * n2 + i] : 0.0);
+  for (int c = 0; c < D; ++c) bg[c * n2 + i] = s[c] + (F ? G(F)[c * n2 + i] : 0.0);
 }
 
 template <class VT>
@@ -233,24 +266,43 @@ __global__ void __launch_bounds__(256) k_rhs_pressure(int64_t n1, const int32_t*
                                                       const double* Us, int64_t n2, double scale,
                                                       double* r, double* part) {
   __shared__ double sh[16];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = k0 < n1;
+  const int64_t k = live ? k0 : 0;
   double v = 0.0, mag = 0.0;
-  if (k < n1) {
-    const int sl = (int)(k >> 6), b0 = sp[sl], w = (sp[sl + 1] - b0) >> 6;
+  {
+    // eight entries at a time, loads before additions, entry order kept (as in k_rhs_p2)
+    const gptr<const int32_t> cg = G(col);
+    const gptr<const double> ug = G(Us);
+    const int sl = (int)(k >> 6), b0 = G(sp)[sl], w = (G(sp)[sl + 1] - b0) >> 6;
     const int base = b0 + (int)(k & 63);
     double s = 0.0, a = 0.0;
-    for (int e = 0; e < w; ++e) {
-      const int j = col[base + 64 * e];
+    for (int e = 0; e < w; e += 8) {
+      double dv[D][8], uv[D][8];
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double t = (double)Dc.p[c][base + 64 * e] * Us[c * n2 + j];
-        s += t;
-        a += fabs(t);
+      for (int q = 0; q < 8; ++q) {
+        const int ee = e + q < w ? e + q : w - 1;
+        const int j = cg[base + 64 * ee];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          dv[c][q] = (double)G(Dc.p[c])[base + 64 * ee];
+          uv[c][q] = ug[c * n2 + j];
+        }
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double t = e + q < w ? dv[c][q] * uv[c][q] : 0.0;
+          s += t;
+          a += fabs(t);
+        }
     }
-    v = scale * s;
-    mag = fabs(scale) * a;
-    r[k] = v;
+    if (live) {
+      v = scale * s;
+      mag = fabs(scale) * a;
+      G(r)[k] = v;
+    }
   }
   const double t = block_sum(v, sh);
   const double q = block_sum(mag * mag, sh);
