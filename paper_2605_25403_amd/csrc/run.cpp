@@ -15,11 +15,12 @@
 
 namespace ipcs {
 
-// Every block of a vector kernel re-reads the partial sums of every block of
-// the matrix kernel before it, so groups of several systems (whose vector
-// kernels have many blocks) keep their matrix kernels within KNB_MAX / 2 blocks.
+// Rows per thread of the matrix kernels: the fewest that keep a launch within
+// KNB_MAX blocks (the partial-sum capacity). Where the vector kernels' blocks
+// would re-read many records, the records are folded once (fold_for), so a
+// larger matrix-kernel grid costs them nothing.
 int kept_m_for(int64_t n, int ns) {
-  const int64_t cap = ns == 1 ? KNB_MAX : KNB_MAX / 2;
+  const int64_t cap = KNB_MAX;
   for (int e : {1, 2, 4})
     if (div_up(n, (int64_t)KBS * e) <= cap) return e;
   if (div_up(n, (int64_t)KBS * 4) <= KNB_MAX) return 4;
