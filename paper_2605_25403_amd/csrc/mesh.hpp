@@ -70,12 +70,15 @@ struct PartSell {
 
 // The Taylor-Hood pair fixes the two spaces. Names keep the P2-P1 pair's
 // vocabulary: "2" is the velocity space, "1" the pressure space.
-//   P2-P1 (triangles, tetrahedra): velocity P2 (vertices, then edges), pressure
-//   P1 (vertices).
-//   P3-P2 (triangles): velocity P3 (vertices; two nodes per edge, edge k with
-//   sorted vertices lo < hi owning nv + 2k at (2 x_lo + x_hi)/3 and nv + 2k + 1
-//   at (x_lo + 2 x_hi)/3; one node per cell at its centroid), pressure P2.
-// In both, the first dim+1 local velocity DOFs of a cell are its vertices.
+//   P2-P1 (triangles, tetrahedra): velocity P2 (vertices and edge midpoints),
+//   pressure P1 (vertices).
+//   P3-P2 (triangles): velocity P3 (vertices; two nodes per edge, at
+//   (2 x_lo + x_hi)/3 and (x_lo + 2 x_hi)/3 for sorted vertices lo < hi; one
+//   node per cell at its centroid), pressure P2 (vertices, then the edges
+//   sorted by (lo, hi)).
+// Velocity DOFs: the vertices in input order, then the other velocity nodes in
+// lexicographic order of their coordinates (last coordinate most significant).
+// In both pairs the first dim+1 local velocity DOFs of a cell are its vertices.
 struct Mesh {
   int dim = 0;
   int pair = 0;                   // IPCS_PAIR_P2P1 or IPCS_PAIR_P3P2
