@@ -129,11 +129,13 @@ struct RowAsm {
   const int32_t* inc;         // cell << 4 | local row index
   const uint8_t* slot;
   int32_t stride;
-  const int32_t* c2d;         // [nc][nloc2]
+  const int32_t* c2d;         // [nc][nloc2] velocity DOFs
   int32_t nloc2;
   const double* X;            // vertex coordinates [nv][dim]
   void* out[3];               // FP64 values, or FP32 in the mixed form
   int32_t pair;               // IPCS_PAIR_P2P1 (0) or IPCS_PAIR_P3P2 (2D)
+  const int32_t* c2v;         // [nc][nv_stride]; first dim+1 entries: the vertices
+  int32_t nv_stride;          //   (the pressure cell table; its vertices come first)
 };
 
 // Manufactured solution on the device

@@ -78,6 +78,13 @@ __device__ __forceinline__ Geo<D, R> cell_geo(const double* X, const int32_t* do
   return g;
 }
 
+// The vertex ids of a cell (for its geometry), from the cell-vertex table.
+template <int D>
+__device__ __forceinline__ void cell_vertices(const RowAsm& a, int64_t cell, int32_t (&v)[D + 1]) {
+#pragma unroll
+  for (int k = 0; k <= D; ++k) v[k] = a.c2v[cell * a.nv_stride + k];
+}
+
 // Reference-element tables at the quadrature points, built at compile time
 // (in FP64, then rounded to R) and kept in constant memory: indices that are
 // uniform across a wavefront (q, j) are served by the scalar cache, the
@@ -134,7 +141,7 @@ __device__ __forceinline__ void phys(const Geo<D, R>& g, const R* gr, R* out) {
 template <int D, int WHICH, class R>
 struct OpMassStiff {   // P2 x P2: M (WHICH 0) or K (WHICH 1)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = 0;   // geometry only
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     const Tab<D, R>& T = tab<D, R>();
@@ -212,7 +219,7 @@ struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi
 template <int D, class R>
 struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
   using real = R;
-  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = 0;   // geometry only
   int c;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -238,7 +245,7 @@ struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
 template <int D, class R>
 struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = 0;   // geometry only
   int c;
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -262,7 +269,7 @@ struct OpDiv {   // P1 rows x P2 cols: D_c for one component c
 template <int D, class R>
 struct OpKp {   // P1 x P1 stiffness
   using real = R;
-  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = P2<D>::NLOC;
+  static constexpr int NOUT = 1, NCOL = D + 1, NDOF = 0;   // geometry only
   __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     R gl[D + 1][D];
@@ -343,7 +350,7 @@ __device__ __forceinline__ R phys_c(const Geo<2, R>& g, const R* gr, int c) {
 template <int WHICH, class R>
 struct Op3MassStiff {   // P3 x P3: M (WHICH 0) or K (WHICH 1)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 3;   // geometry only
+  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 0;   // geometry only
   __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     const Tab3<R>& T = tab3<R>();
@@ -411,7 +418,7 @@ struct Op3Conv {   // P3 x P3: E = M/dt + cs C(U)
 template <class R>
 struct Op3Grad {   // P3 rows x P2 cols: (G_c)_ik = sum_q w |J| phi_i d_c psi_k
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 3;
+  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 0;
   int c;
   __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -428,7 +435,7 @@ struct Op3Grad {   // P3 rows x P2 cols: (G_c)_ik = sum_q w |J| phi_i d_c psi_k
 template <class R>
 struct Op3Div {   // P2 rows x P3 cols: (D_c)_kj = sum_q w |J| psi_k d_c phi_j
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 3;
+  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 0;
   int c;
   __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
@@ -445,7 +452,7 @@ struct Op3Div {   // P2 rows x P3 cols: (D_c)_kj = sum_q w |J| psi_k d_c phi_j
 template <class R>
 struct Op3Kp {   // P2 x P2 stiffness of the pressure space
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 3;
+  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 0;
   __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
     const Tab3<R>& T = tab3<R>();
@@ -488,11 +495,16 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
     for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
       const int code = a.inc[p];
       const int cell = code >> 4, li = code & 15;
-      const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
-      int32_t dl[Op::NDOF];
+      // velocity DOFs only for ops that read U (NDOF > 0)
+      int32_t dl[Op::NDOF > 0 ? Op::NDOF : 1];
+      if constexpr (Op::NDOF > 0) {
+        const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
 #pragma unroll
-      for (int m = 0; m < Op::NDOF; ++m) dl[m] = dofs[m];
-      const Geo<D, R> g = cell_geo<D, R>(a.X, dl);
+        for (int m = 0; m < Op::NDOF; ++m) dl[m] = dofs[m];
+      }
+      int32_t vx[D + 1];
+      cell_vertices<D>(a, cell, vx);
+      const Geo<D, R> g = cell_geo<D, R>(a.X, vx);
       R v[NOUT][NCOL];
 #pragma unroll
       for (int o = 0; o < NOUT; ++o)
@@ -602,9 +614,10 @@ void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t l
 // buffer [cell][local row][local column]; k_asm_local then adds them into the
 // matrix rows with the conflict-free row-owner scatter.
 template <int D, class R>
-__global__ void __launch_bounds__(256) k_conv_cells(int64_t nc, const int32_t* c2d, int nloc2,
-                                                    const double* X, const double* U, int64_t n2,
-                                                    double inv_dt, double cs, R* out) {
+__global__ void __launch_bounds__(256) k_conv_cells(RowAsm a, int64_t nc, const double* U,
+                                                    int64_t n2, double inv_dt, double cs, R* out) {
+  const int32_t* c2d = a.c2d;
+  const int nloc2 = a.nloc2;
   constexpr int NL = P2<D>::NLOC, NQ = Rule<D>::NQ, CPB = 256 / NL;
   __shared__ R s_u[CPB][D][NL];          // U_c at the cell's DOFs
   __shared__ R s_beta[CPB][NQ][D];       // J^{-1} u_h(x_q)
@@ -621,7 +634,9 @@ __global__ void __launch_bounds__(256) k_conv_cells(int64_t nc, const int32_t* c
 #pragma unroll
     for (int c = 0; c < D; ++c) s_u[cl][c][li] = (R)U[(size_t)c * n2 + dl[li]];
     if (li == 0) {
-      const Geo<D, R> g = cell_geo<D, R>(X, dl);
+      int32_t vx[D + 1];
+      cell_vertices<D>(a, cell, vx);
+      const Geo<D, R> g = cell_geo<D, R>(a.X, vx);
       s_det[cl] = g.det;
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -709,8 +724,8 @@ static void conv_cells(hipStream_t s, const RowAsm& a, int64_t nc, const double*
                        double inv_dt, double cs, void* buf) {
   constexpr int CPB = 256 / P2<D>::NLOC;
   if (nc <= 0) return;
-  launch(k_conv_cells<D, R>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, nc, a.c2d,
-         a.nloc2, a.X, U, n2, inv_dt, cs, static_cast<R*>(buf));
+  launch(k_conv_cells<D, R>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, a, nc, U, n2,
+         inv_dt, cs, static_cast<R*>(buf));
 }
 
 template <int D, class R>
@@ -746,8 +761,7 @@ __global__ void __launch_bounds__(256) k_lumped_p1(RowAsm a, double* w) {
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
     const int cell = a.inc[p] >> 4;
     int32_t dl[D + 1];
-#pragma unroll
-    for (int m = 0; m <= D; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    cell_vertices<D>(a, cell, dl);
     s += cell_geo<D>(a.X, dl).det * (ref_measure<D>() / (D + 1));
   }
   w[row] = s;
@@ -762,8 +776,7 @@ __global__ void __launch_bounds__(256) k_lumped_p2(RowAsm a, double* w) {
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
     const int cell = a.inc[p] >> 4, li = a.inc[p] & 15;
     int32_t dl[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    cell_vertices<2>(a, cell, dl);
     double iq = 0.0;
     for (int q = 0; q < Tab3<double>::NQ; ++q) iq += T.w[q] * T.psi[q][li];
     s += cell_geo<2>(a.X, dl).det * iq;
@@ -792,9 +805,8 @@ __global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const dou
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
     const int code = a.inc[p];
     const int cell = code >> 4, li = code & 15;
-    int32_t dl[P2<D>::NLOC];
-#pragma unroll
-    for (int m = 0; m < P2<D>::NLOC; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    int32_t dl[D + 1];
+    cell_vertices<D>(a, cell, dl);
     const Geo<D> g = cell_geo<D>(a.X, dl);
     const Tab<D, double>& T = tab<D, double>();
 #pragma unroll 1
@@ -836,8 +848,7 @@ __global__ void __launch_bounds__(256) k_forcing_p3(RowAsm a, Builtin bi, const 
     const int code = a.inc[p];
     const int cell = code >> 4, li = code & 15;
     int32_t dl[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) dl[m] = a.c2d[(size_t)cell * a.nloc2 + m];
+    cell_vertices<2>(a, cell, dl);
     const Geo<2> g = cell_geo<2>(a.X, dl);
 #pragma unroll 1
     for (int q = 0; q < Tab3<double>::NQ; ++q) {

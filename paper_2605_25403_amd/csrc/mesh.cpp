@@ -152,12 +152,14 @@ void build_incidence(const std::vector<int32_t>& c2d, int64_t nc, int nloc, int 
     for (int j = 0; j < nrowloc; ++j) I.code[fill[c2d[c * nloc + j]]++] = int32_t((c << 4) | j);
 }
 
-// Velocity DOFs: the vertices keep their numbers (they index the vertex
-// coordinates for the cell geometry); every other velocity node is numbered
-// in lexicographic order of its coordinates, last coordinate most significant
-// (y, x in 2D; z, y, x in 3D), ties (none on a valid mesh) by the listing
-// order. Rows that are neighbours in this order reference nearby columns, so
-// a SELL-64 slice's gathers touch few cache lines.
+// Velocity DOFs: the vertices keep their numbers; every other velocity node
+// is numbered in lexicographic order of its coordinates, last coordinate most
+// significant (y, x in 2D; z, y, x in 3D), ties (none on a valid mesh) by the
+// listing order. Rows that are neighbours in this order reference nearby
+// columns, so a SELL-64 slice's gathers touch few cache lines; keeping the
+// vertices apart keeps each slice to rows of one kind and length (one
+// coordinate order over all nodes interleaves vertex and edge rows and was
+// slower).
 void renumber_velocity(Mesh& m) {
   const int d = m.dim;
   const int64_t nv = m.nv, n = m.n2;

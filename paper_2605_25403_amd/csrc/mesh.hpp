@@ -78,15 +78,17 @@ struct PartSell {
 //   sorted by (lo, hi)).
 // Velocity DOFs: the vertices in input order, then the other velocity nodes in
 // lexicographic order of their coordinates (last coordinate most significant).
-// In both pairs the first dim+1 local velocity DOFs of a cell are its vertices.
+// A cell's local velocity DOFs start with its vertices. Kernels take the cell
+// geometry from the pressure cell table, which starts with the vertex ids in
+// both pairs (P1: the vertices; P2: vertices, then edges).
 struct Mesh {
   int dim = 0;
   int pair = 0;                   // IPCS_PAIR_P2P1 or IPCS_PAIR_P3P2
   int64_t nv = 0, nc = 0, ne = 0;
   int nloc2 = 0, nloc1 = 0;
   std::vector<double> X;          // [nv][dim]
-  std::vector<int32_t> c2d;       // [nc][nloc2] velocity DOFs; first dim+1 = vertices
-  std::vector<int32_t> c2dp;      // [nc][nloc1] pressure DOFs
+  std::vector<int32_t> c2d;       // [nc][nloc2] velocity DOFs (local order: vertices first)
+  std::vector<int32_t> c2dp;      // [nc][nloc1] pressure DOFs; first dim+1 = vertex ids
   std::vector<int32_t> edges;     // [ne][2] sorted pairs
   int64_t n1 = 0, n2 = 0;
   std::vector<double> x2;         // [n2][dim] velocity node coordinates

@@ -430,6 +430,7 @@ void Run::layout(Carver& c) {
   const int nsys = 2 * dim + 1;
   X = c.take<double>(nv * dim);
   c2d = c.take<int32_t>(nc * m.nloc2);
+  c2v = c.take<int32_t>(nc * m.nloc1);
   x2 = c.take<double>(n2 * dim);
   xp = m.pair == IPCS_PAIR_P2P1 ? X : c.take<double>(n1 * dim);
   bmask = c.take<uint8_t>(n2);
@@ -549,6 +550,7 @@ void Run::upload_mesh() {
   const Mesh& m = *mesh;
   up(stream, X, m.X);
   up(stream, c2d, m.c2d);
+  up(stream, c2v, m.c2dp);
   up(stream, x2, m.x2);
   if (xp != X) up(stream, xp, m.xp);
   up(stream, bmask, m.bmask);
@@ -620,20 +622,20 @@ void Run::upload_mesh() {
 void Run::assemble_constant() {
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X, {M, K, nullptr},
-             m.pair};
+             m.pair, c2v, m.nloc1};
   asm_mass_stiff(dim, mixed, stream, a22, cfg_mk.bs, cfg_mk.lds);
   RowAsm a21{(int32_t)n2, sp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
-             {Gc[0], Gc[1], Gc[2]}, m.pair};
+             {Gc[0], Gc[1], Gc[2]}, m.pair, c2v, m.nloc1};
   asm_grad(dim, mixed, stream, a21, cfg_g.bs, cfg_g.lds);
   RowAsm a12{(int32_t)n1, sp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
-             {Dc[0], Dc[1], Dc[2]}, m.pair};
+             {Dc[0], Dc[1], Dc[2]}, m.pair, c2v, m.nloc1};
   asm_div(dim, mixed, stream, a12, cfg_d.bs, cfg_d.lds);
   // Kp is assembled in FP64 in both forms. The mixed form keeps that FP64
   // copy for the refinement residual and gives the inner CG the same matrix
   // rounded to FP32, the FP32 operator closest to it, so that a refinement
   // pass is limited by the inner tolerance rather than by the operator.
   RowAsm a11{(int32_t)n1, sp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
-             {Kp64, nullptr, nullptr}, m.pair};
+             {Kp64, nullptr, nullptr}, m.pair, c2v, m.nloc1};
   asm_kp(dim, false, stream, a11, cfg_kp.bs, cfg_kp.lds * (8 / vsz));
   if (mixed) round_to_f32(stream, ne11, Kp64, static_cast<float*>(Kp));
   asm_lumped_p1(dim, stream, a11, w);
@@ -856,7 +858,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
             const double l = mm.pair == IPCS_PAIR_P3P2 ? RuleT9::lam(q, k)
                              : dim == 2               ? Rule<2>::lam(q, k)
                                                       : Rule<3>::lam(q, k);
-            x += l * mm.X[(size_t)mm.c2d[cc * mm.nloc2 + k] * dim + r];
+            x += l * mm.X[(size_t)mm.c2dp[cc * mm.nloc1 + k] * dim + r];
           }
           h_xq[((size_t)cc * nq + q) * dim + r] = x;
         }
@@ -943,7 +945,7 @@ void Run::asm_phase() {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}, m.pair};
+             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1};
   has_F = false;
   if (f_cb) {
     const int nq = cell_nq();
@@ -1163,7 +1165,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}, m.pair};
+             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1};
   auto launch = [&]() {
     switch (kernel) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;

@@ -129,6 +129,7 @@ struct Run {
   // ---- device arrays (all inside the workspace)
   double* X = nullptr;
   int32_t* c2d = nullptr;
+  int32_t* c2v = nullptr;      // pressure cell table: its first dim+1 entries are the vertices
   double* x2 = nullptr;
   double* xp = nullptr;        // pressure node coordinates (X itself for P2-P1)
   uint8_t* bmask = nullptr;
