@@ -195,3 +195,26 @@ def test_p3_and_p2_runs_in_one_batch_bitwise():
     for (U, P), r in zip(alone, runs):
         np.testing.assert_array_equal(r.velocity(), U)
         np.testing.assert_array_equal(r.pressure(), P)
+
+
+@pytest.mark.parametrize("rows", [0, -1])
+@pytest.mark.parametrize("n", [1, 2])
+def test_p3_degenerate_small_meshes(n, rows):
+    """One or two squares per direction: at n = 1 the only interior velocity
+    nodes are the diagonal edge's two nodes and the two centroids, and the P2
+    pressure system has 9 rows in one part. Three steps against the oracle in
+    both Poisson CG forms (fields that vanish up to rounding are compared with
+    an RMS floor of 0.01, as for P2-P1)."""
+    torch, I = require_gpu()
+    print(f"P3-P2 degenerate n={n} poisson_part_rows={rows}", flush=True)
+    S, o, r = make_pair(I, 2, n, "tg", 0.01, 0.01, p3=True, poisson_part_rows=rows)
+
+    def err(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-2 * np.sqrt(b.size))
+
+    for step in range(3):
+        st = r.advance(1)[0]
+        o.step()
+        U, P = r.velocity(), r.pressure()
+        errs = [err(U[c], o.U[c]) for c in range(2)] + [err(P, o.P)]
+        assert max(errs) <= FIELD_TOL, (step, errs, st)
