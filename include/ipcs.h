@@ -1,13 +1,15 @@
 /*
  * ipcs.h -- C ABI of the MI355X (gfx950) incremental pressure-correction
  * (IPCS) solver for the incompressible Navier-Stokes equations with
- * Taylor-Hood P2-P1 elements on triangles and tetrahedra.
+ * Taylor-Hood elements: P2-P1 on triangles and tetrahedra, P3-P2 on
+ * triangles.
  *
  * What is computed (arXiv 2605.25403, FEALPy.CFD):
  *   PDE      : Section 2.1, eq. (3): du/dt - nu Lap u + (u.grad)u + grad p = f,
  *              div u = 0, density rho = 1 unless set.
  *   Spaces   : Section 2.2.1, eqs. (4)-(5): V_h = continuous P2 per velocity
- *              component with Dirichlet data, Q_h = continuous P1 pressure.
+ *              component with Dirichlet data, Q_h = continuous P1 pressure;
+ *              or P3 and P2 (Section 5.1, table "convergence_p3_p2").
  *   Scheme   : Section 2.2.1, eq. (9) (IPCS): momentum with explicit convection
  *              ((u^n.grad)u^n, v) and pressure p^n, pressure-increment Poisson,
  *              velocity correction. The Poisson right-hand side is taken as
@@ -33,10 +35,10 @@
  *     released with hipFreeAsync before it returns) for the descriptors of its
  *     shared launches. All device work of a run is issued on the HIP stream
  *     given at creation (or to ipcs_batch_step).
- *   - Layout: velocity is component-major [dim][N2]. P2 DOFs are the mesh
- *     vertices (input order) followed by the edges sorted by (min vertex, max
- *     vertex); P1 DOFs are the vertices. All host-side fields are FP64,
- *     whatever the internal precision.
+ *   - Layout: velocity is component-major [dim][N2] (N2 velocity DOFs per
+ *     component, N1 pressure DOFs; the numbering is stated at
+ *     ipcs_mesh_unit_square_pair). All host-side fields are FP64, whatever
+ *     the internal precision.
  *   - Threading: a run is not thread-safe; distinct runs may be driven from
  *     distinct threads.
  */
@@ -133,12 +135,13 @@ int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap);
 /* CSR pattern (row pointer [rows+1], sorted column indices [nnz]). */
 int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
                       int32_t* col, int64_t cap_nnz);
-/* Row partition of the P1-P1 pattern (the rows of Kp, the matrix of the
- * pressure-increment Poisson problem, Section 2.2.1, eq. (9), second line)
- * into parts of at most rows_max rows (64..2048) that the one-kernel-per-
- * iteration Poisson CG uses (host data, for inspection; ownership stays with
- * the mesh, the arrays are copied out). Parts are compact patches of vertices (recursive coordinate
- * bisection); rows are renumbered part by part ("part order"). sizes[0..4]
+/* Row partition of the pressure-pressure pattern IPCS_PATTERN_P1P1 (the rows
+ * of Kp, the matrix of the pressure-increment Poisson problem, Section 2.2.1,
+ * eq. (9), second line) into parts of at most rows_max rows (64..2048) that
+ * the one-kernel-per-iteration Poisson CG uses (host data, for inspection;
+ * ownership stays with the mesh, the arrays are copied out). Parts are compact
+ * patches of pressure nodes (recursive coordinate bisection); rows are
+ * renumbered part by part ("part order"). sizes[0..4]
  * receives nparts, the halo length, the number of SELL-64 slices, the number
  * of entries and the largest own + halo count of a part. With non-NULL
  * arrays also: perm[n1] (part-order row -> original row), part_ptr[nparts+1],
@@ -152,9 +155,11 @@ int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_r
 int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int32_t* perm,
                            int32_t* part_ptr, int32_t* halo_ptr, int32_t* halo,
                            int32_t* slice_ptr, int32_t* sptr, uint16_t* lcol, int32_t* src);
-/* The degree-5 cell quadrature rule the kernels use, in barycentric
- * coordinates lam[nq*(dim+1)] with weights w[nq] summing to 1/dim!.
- * *nq receives the number of points; pass NULL buffers to query it. */
+/* The degree-5 cell quadrature rule the kernels use for the P2-P1 pair, in
+ * barycentric coordinates lam[nq*(dim+1)] with weights w[nq] summing to
+ * 1/dim!. *nq receives the number of points; pass NULL buffers to query it.
+ * (P3-P2 runs integrate with the collapsed product of two 5-point
+ * Gauss-Legendre rules, 25 points, exact to degree 8.) */
 int ipcs_quadrature_rule(int32_t dim, int32_t* nq, double* lam, double* w, int64_t cap);
 void ipcs_mesh_destroy(ipcs_mesh m);
 
@@ -245,7 +250,7 @@ typedef void (*ipcs_field_fn)(void* ctx, int32_t dim, int64_t npts, const double
  * with params.callbacks = 1 (else IPCS_E_STATE). */
 int ipcs_set_forcing(ipcs_run r, ipcs_field_fn f, void* ctx);
 /* Dirichlet data g (the velocity on the boundary, H^1_0 lifting of V_h);
- * evaluated on the host at the boundary P2 nodes every step. */
+ * evaluated on the host at the boundary velocity nodes every step. */
 int ipcs_set_dirichlet(ipcs_run r, ipcs_field_fn g, void* ctx);
 
 enum {
