@@ -61,8 +61,8 @@ def kernel_bytes(kernel, c, dim, vsz=8, p3=False):
         return (vsz + 4) * nnz22 + sl2 + dim * 4 * 8 * n2
     if kernel == "bicg_update_s":  # dinv; r, v in, s, shat out each
         return 8 * n2 + dim * 4 * 8 * n2
-    if kernel == "bicg_update_x":  # dinv; x, phat, shat, s, t, p, v in, x, r, p, phat out each
-        return 8 * n2 + dim * 11 * 8 * n2
+    if kernel == "bicg_update_x":  # dinv; x, s, t, p, v in, x, r, p, phat out each
+        return 8 * n2 + dim * 9 * 8 * n2
     if kernel == "pcg_spmv_m":     # M once for all components; u in, w out each
         return (vsz + 4) * nnz22 + sl2 + dim * 2 * 8 * n2
     if kernel == "pcg_update_m":   # dinv; x, r, p, s, w in, x, r, p, s, u out each

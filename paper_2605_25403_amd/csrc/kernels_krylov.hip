@@ -35,7 +35,8 @@
 //   b3 [rhat.v, ||r||^2] stop test, alpha = rho / rhat.v; s = r - alpha v,
 //      shat = D^{-1} s
 //   b4 t = A shat, partials t.s, t.t, rhat.s, rhat.t       (no prologue)
-//   b5 [t.s, t.t, rhat.s, rhat.t] omega = t.s / t.t; x += alpha phat + omega shat,
+//   b5 [t.s, t.t, rhat.s, rhat.t] omega = t.s / t.t; x += D^{-1}(alpha p + omega s)
+//      (= alpha phat + omega shat, from vectors this kernel reads anyway),
 //      r = s - omega t; rho' = rhat.r = rhat.s - omega rhat.t, beta =
 //      (rho' / rho)(alpha / omega); p = r + beta (p - omega v), phat = D^{-1} p;
 //      partial r.r
@@ -575,8 +576,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
     rho[j] = st->sc[par];
     alpha[j] = st->alpha[0];
   }
-  double di[EV], xi[EV][NS], phi[EV][NS], shi[EV][NS], si[EV][NS],
-      ti[EV][NS], pi[EV][NS], vi[EV][NS];
+  double di[EV], xi[EV][NS], si[EV][NS], ti[EV][NS], pi[EV][NS], vi[EV][NS];
 #pragma unroll
   for (int e = 0; e < EV; ++e) {
     const int i = row_clamp(row_of<EV>(lb, e), g.n);
@@ -585,8 +585,6 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
     for (int j = 0; j < NS; ++j) {
       const KVecs& V = g.v[j];
       xi[e][j] = G(V.x)[i];
-      phi[e][j] = G(V.phat)[i];
-      shi[e][j] = G(V.shat)[i];
       si[e][j] = G(V.s)[i];
       ti[e][j] = G(V.t)[i];
       pi[e][j] = G(V.p)[i];
@@ -646,7 +644,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
     for (int j = 0; j < NS; ++j) {
       if (!go[j]) continue;
       const KVecs& V = g.v[j];
-      G(V.x)[i] = xi[e][j] + alpha[j] * phi[e][j] + om[j] * shi[e][j];
+      G(V.x)[i] = xi[e][j] + di[e] * (alpha[j] * pi[e][j] + om[j] * si[e][j]);
       const double r = si[e][j] - om[j] * ti[e][j];
       G(V.r)[i] = r;
       acc[j] += r * r;
