@@ -281,8 +281,17 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
       inner.push_back(r);
     }
     if (inner.empty()) break;
+    // each pass sizes its polls from the same pass of the run's last step
+    for (Run* r : inner) {
+      const int k = ir[r].outer - 1;
+      r->set_p.last_iters = k < Run::kIrHist ? r->ir_last[k] : 0;
+    }
     std::map<Run*, int> rin;
     solve_shared(inner, 1, KMethod::PCG, s, rin, st);
+    for (Run* r : inner) {
+      const int k = ir[r].outer - 1;
+      if (k < Run::kIrHist) r->ir_last[k] = r->set_p.last_iters;
+    }
     active.clear();
     for (Run* r : inner) {
       int c = rin[r];

@@ -1293,7 +1293,9 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
     last_tol = tol_in;
     set_tolerance(stream, set_p.L, tol_in * tol_in);
     HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
+    set_p.last_iters = outer < kIrHist ? ir_last[outer] : 0;
     rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned, timer);
+    if (outer < kIrHist) ir_last[outer] = set_p.last_iters;
     inner_total += hs[0].it;
     checks_total += hs[0].nchecks;
     if (rc == IPCS_E_BREAKDOWN) {

@@ -151,6 +151,10 @@ struct Run {
   double* Kp64 = nullptr;     // FP64 Kp (the same array as Kp in the FP64 form)
   double *rIR = nullptr, *dIR = nullptr;   // mixed form: refinement residual, correction
   double ir_c = 0.0;          // mixed form: reduction per refinement pass seen last step
+  // mixed form: iterations of each refinement pass of the last step; pass k's
+  // inner solve sizes its polls from entry k (passes differ widely in length)
+  static constexpr int kIrHist = 4;
+  int ir_last[kIrHist] = {};
   double *liftA = nullptr, *liftM = nullptr;
   double *dinvA = nullptr, *dinvM = nullptr, *dinvKp = nullptr, *w = nullptr;
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
