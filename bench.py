@@ -446,8 +446,7 @@ def main():
     it_m = float(np.median([max(s["it_mom"][:dim]) for s in stats]))
     it_c = float(np.median([max(s["it_corr"][:dim]) for s in stats]))
     r.kernel_timing((1 << I.IPCS_NKERNEL) - 1 if args.kernel_steps > 0 else 0)
-    for _ in range(args.kernel_steps):
-        r.advance(1)
+    kstats = [r.advance(1)[0] for _ in range(args.kernel_steps)]
     torch.cuda.synchronize()
     kms, kcnt = r.kernel_times()
     r.kernel_timing(0)
@@ -495,6 +494,13 @@ def main():
                    "k": w.get("k"), "nu": w["nu"], "dt": w["dt"], "seed": w.get("seed")},
         "roofline": roof,
         "kernels": kern,
+        # iterations of the kernel-timed steps (the launches_per_step above
+        # count launches of the same steps: their excess over these is the
+        # polling overrun)
+        "kernel_steps_iterations_mean": None if not kstats else {
+            "momentum": float(np.mean([max(k["it_mom"][:dim]) for k in kstats])),
+            "pressure": float(np.mean([k["it_p"] for k in kstats])),
+            "correction": float(np.mean([max(k["it_corr"][:dim]) for k in kstats]))},
         "phase_ms_median": {"asm": float(np.median(ph[:, 0])), "momentum": float(np.median(ph[:, 1])),
                             "pressure": float(np.median(ph[:, 2])),
                             "correction": float(np.median(ph[:, 3]))},
