@@ -401,9 +401,8 @@ def main():
                     args.calibrate_copy or 256, args.pmc_command)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (multi-GPU sharding is described in DESIGN.md, not built)",
-              file=sys.stderr)
+        print(f"bench.py: the IPCS step runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the solver is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
