@@ -44,8 +44,7 @@ KERNELS = {
 def kernel_bytes(kernel, c, dim, vsz=8, p3=False):
     """Algorithmic bytes per launch: each array read once, each output written
     once, vsz-byte matrix values, 8-byte vectors, 4-byte indices (2-byte local
-    indices in the fused Poisson CG; its halo re-reads are not counted)
-    (formulas in DESIGN.md)."""
+    indices in the fused Poisson CG; its halo re-reads are not counted)."""
     n1, n2 = c.n1, c.n2
     if kernel == "pcg_fused_p":    # Kp values + local cols; dinv, x, p, r, s, w in; x, p, s, r, w out
         return (vsz + 2) * c.nnz[1] + 11 * 8 * n1
