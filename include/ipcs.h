@@ -102,13 +102,18 @@ typedef struct {
  * j*(nx+1)+i (Section 2.2.1: conforming simplicial mesh T_h). */
 int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out);
 /* The same square with the DOF maps of a Taylor-Hood pair (IPCS_PAIR_*).
- * Velocity DOFs (both pairs): the vertices in input order, then the other
- * velocity nodes (P2: edge midpoints; P3: the two nodes of each edge at
- * (2 x_lo + x_hi)/3 and (x_lo + 2 x_hi)/3, and the cell centroids) in
- * lexicographic order of their coordinates, last coordinate most significant
- * (y, x in 2D; z, y, x in 3D). Pressure DOFs: P1, the vertices; P2 (P3-P2
- * pair), the vertices, then the edge midpoints with the edges sorted by
- * (lower, higher) vertex. */
+ * Numbering of every array that crosses this interface (fields, DOF
+ * coordinates, cell DOF tables, boundary masks, patterns, matrices):
+ * velocity DOFs (P2-P1) are the vertices in input order, then the edge
+ * midpoints with the edges sorted by (lower, higher) vertex; velocity DOFs
+ * (P3-P2) are the vertices, then two nodes per edge in that edge order (the
+ * node at (2 x_lo + x_hi)/3, then the one at (x_lo + 2 x_hi)/3), then one node
+ * per cell at its centroid, in cell order. Pressure DOFs: P1, the vertices;
+ * P2 (P3-P2 pair), the vertices, then the edge midpoints in edge order.
+ * Internally the library numbers the non-vertex velocity nodes in
+ * lexicographic order of their coordinates (last coordinate most
+ * significant), so that neighbouring nodes have neighbouring indices; it
+ * converts at this interface, outside any timed step. */
 int ipcs_mesh_unit_square_pair(int32_t nx, int32_t ny, int32_t pair, ipcs_mesh* out);
 /* Unit cube, nx*ny*nz cubes, each split into the 6 Kuhn tetrahedra around its
  * main diagonal; vertex (i,j,k) has index (k(ny+1)+j)(nx+1)+i. */

@@ -9,11 +9,10 @@ Numbering adopted here (the paper does not fix one):
 * P1 DOFs are the mesh vertices in input order.
 * P2 nodes are the vertices and the edge midpoints (edges = unique vertex
   pairs of cells, listed sorted by (min vertex, max vertex)).
-* Velocity DOFs are numbered: the vertices in input order, then every other
-  node of the velocity space in lexicographic order of its coordinates (last
-  coordinate first: y then x in 2D; z, y, x in 3D), ties (none on a valid
-  mesh) by the listing order. Neighbouring DOFs are then near each other,
-  which the library's sparse kernels rely on; both sides number this way.
+* Velocity DOFs are numbered in listing order: the vertices in input order,
+  then the other nodes of the velocity space (P2: the edge midpoints in edge
+  order; P3: below). This is the numbering of every velocity array exchanged
+  with the library.
 * The P3-P2 pressure (P2) keeps the listing order: vertices, then edges.
 * Local P2 order in a triangle: v0, v1, v2, e(v1v2), e(v2v0), e(v0v1); in a
   tetrahedron: v0..v3, e01, e02, e03, e12, e13, e23.
@@ -21,8 +20,7 @@ Numbering adopted here (the paper does not fix one):
   4 lam_a lam_b.
 * P3 (triangles) nodes: the vertices, two per edge (edge k with sorted
   vertices lo < hi has nodes at (2 x_lo + x_hi)/3 and (x_lo + 2 x_hi)/3), one
-  per cell at its centroid; listed in that order, then numbered as velocity
-  DOFs above.
+  per cell at its centroid; numbered in that order.
   Local order: v0, v1, v2; for each local edge (a, b) of (v1v2, v2v0, v0v1)
   the node nearer a, then the node nearer b; the centroid. Basis: vertex
   lam_i (3 lam_i - 1)(3 lam_i - 2) / 2; edge node nearer a
@@ -115,23 +113,6 @@ def p3_basis(lam):
 
 
 # ----------------------------------------------------------------- spaces
-def renumber_by_coordinates(nfix, c2d, x, mask):
-    """Keep DOFs 0..nfix-1; number the rest in lexicographic order of their
-    coordinates (last coordinate most significant), ties by current index.
-    Returns the cell table, coordinates and mask in the new numbering."""
-    n, d = x.shape
-    rest = np.arange(nfix, n)
-    keys = [rest] + [x[nfix:, a] for a in range(d)]     # lexsort: last key primary
-    order = rest[np.lexsort(keys)]                       # old indices in new order
-    new_of_old = np.arange(n)
-    new_of_old[order] = np.arange(nfix, n)
-    x_new = np.empty_like(x)
-    x_new[new_of_old] = x
-    m_new = np.empty_like(mask)
-    m_new[new_of_old] = mask
-    return new_of_old[c2d], x_new, m_new
-
-
 class Space:
     """Mesh + DOF maps of a Taylor-Hood pair + geometry for one simplicial mesh."""
 
@@ -167,15 +148,11 @@ class Space:
             raise ValueError("pairs: P2-P1 (triangles, tetrahedra) or P3-P2 (triangles)")
         self.order = order
         if order == 2:
-            self.c2d2, self.x2, self.boundary2 = renumber_by_coordinates(
-                self.Nv, self.c2d2, self.x2, self.boundary2)
             self.Nu, self.c2du, self.xu, self.bmask_u = self.N2, self.c2d2, self.x2, self.boundary2
             self.Np, self.c2dp, self.xp = self.N1, self.c2d1, self.X
             self.basis_u, self.basis_p = p2_basis, p1_basis
         else:
             self._p3_dofs(inv.reshape(self.Nc, len(edges)))
-            self.c2du, self.xu, self.bmask_u = renumber_by_coordinates(
-                self.Nv, self.c2du, self.xu, self.bmask_u)
             self.Np, self.c2dp, self.xp = self.N2, self.c2d2, self.x2
             self.basis_u, self.basis_p = p3_basis, p2_basis
 

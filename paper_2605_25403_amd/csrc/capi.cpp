@@ -1,9 +1,12 @@
 // extern "C" entry points declared in include/ipcs.h. Every call converts
 // exceptions into status codes and records a thread-local message.
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 #include "ipcs.h"
@@ -77,6 +80,53 @@ void check_params(const ipcs_params* p) {
        "poisson_part_rows must be 0, -1 or in [64, 2048]");
   need(p->scheme == IPCS_SCHEME_IPCS || p->scheme == IPCS_SCHEME_CHORIN, "unknown scheme");
 }
+
+// The interface numbers velocity DOFs in listing order, the library
+// internally in coordinate order (mesh.hpp: v_out, v_in). These convert the
+// velocity-indexed data that crosses the interface.
+// out[c][v_out[i]] = in[c][i] for ncomp components of n2 values
+void vel_to_interface(const ipcs::Mesh& m, int ncomp, const double* in, double* out) {
+  const int64_t n = m.n2;
+  for (int c = 0; c < ncomp; ++c)
+    for (int64_t i = 0; i < n; ++i) out[c * n + m.v_out[i]] = in[c * n + i];
+}
+// out[c][i] = in[c][v_out[i]]
+void vel_to_internal(const ipcs::Mesh& m, int ncomp, const double* in, double* out) {
+  const int64_t n = m.n2;
+  for (int c = 0; c < ncomp; ++c)
+    for (int64_t i = 0; i < n; ++i) out[c * n + i] = in[c * n + m.v_out[i]];
+}
+// A CSR pattern (and values, if val) of the internal numbering in the
+// interface numbering: velocity rows and/or columns relabelled, rows in
+// interface order, columns ascending within each row.
+void csr_to_interface(const ipcs::Mesh& m, const ipcs::Pattern& P, bool vrows, bool vcols,
+                      const double* val, int32_t* rowptr, int32_t* col, double* vout) {
+  std::vector<int32_t> rp(P.nrows + 1, 0);
+  for (int64_t e = 0; e < P.nrows; ++e) {
+    const int64_t r = vrows ? m.v_in[e] : e;
+    rp[e + 1] = rp[e] + (P.rowptr[r + 1] - P.rowptr[r]);
+  }
+  std::vector<std::pair<int32_t, int32_t>> row;   // (interface column, internal entry)
+  for (int64_t e = 0; e < P.nrows; ++e) {
+    const int64_t r = vrows ? m.v_in[e] : e;
+    row.clear();
+    for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k)
+      row.emplace_back(vcols ? m.v_out[P.col[k]] : P.col[k], k);
+    std::sort(row.begin(), row.end());
+    for (size_t q = 0; q < row.size(); ++q) {
+      if (col) col[rp[e] + q] = row[q].first;
+      if (vout) vout[rp[e] + q] = val[row[q].second];
+    }
+  }
+  if (rowptr) std::memcpy(rowptr, rp.data(), sizeof(int32_t) * (P.nrows + 1));
+}
+bool velocity_rows(int pattern) {
+  return pattern == IPCS_PATTERN_P2P2 || pattern == IPCS_PATTERN_P2P1;
+}
+bool velocity_cols(int pattern) {
+  return pattern == IPCS_PATTERN_P2P2 || pattern == IPCS_PATTERN_P1P2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -151,7 +201,12 @@ int ipcs_mesh_dof_coords(ipcs_mesh m, int32_t space, double* out, int64_t cap) {
     need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
     const int64_t n = (space == IPCS_SPACE_P1 ? mm.n1 : mm.n2) * mm.dim;
     need(out != nullptr && cap >= n, "output buffer too small");
-    std::memcpy(out, space == IPCS_SPACE_P1 ? mm.xp.data() : mm.x2.data(), sizeof(double) * n);
+    if (space == IPCS_SPACE_P1) {
+      std::memcpy(out, mm.xp.data(), sizeof(double) * n);
+    } else {
+      for (int64_t i = 0; i < mm.n2; ++i)
+        for (int a = 0; a < mm.dim; ++a) out[(int64_t)mm.v_out[i] * mm.dim + a] = mm.x2[i * mm.dim + a];
+    }
     return IPCS_OK;
   });
 }
@@ -162,8 +217,10 @@ int ipcs_mesh_cell_dofs(ipcs_mesh m, int32_t space, int32_t* out, int64_t cap) {
     need(space == IPCS_SPACE_P1 || space == IPCS_SPACE_P2, "unknown space");
     const int nl = space == IPCS_SPACE_P1 ? mm.nloc1 : mm.nloc2;
     need(out != nullptr && cap >= mm.nc * nl, "output buffer too small");
-    const std::vector<int32_t>& t = space == IPCS_SPACE_P1 ? mm.c2dp : mm.c2d;
-    for (int64_t i = 0; i < mm.nc * nl; ++i) out[i] = t[i];
+    if (space == IPCS_SPACE_P1)
+      for (int64_t i = 0; i < mm.nc * nl; ++i) out[i] = mm.c2dp[i];
+    else
+      for (int64_t i = 0; i < mm.nc * nl; ++i) out[i] = mm.v_out[mm.c2d[i]];
     return IPCS_OK;
   });
 }
@@ -172,7 +229,7 @@ int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap) {
   return guard([&]() -> int {
     const ipcs::Mesh& mm = M(m);
     need(out != nullptr && cap >= mm.n2, "output buffer too small");
-    std::memcpy(out, mm.bmask.data(), mm.n2);
+    for (int64_t i = 0; i < mm.n2; ++i) out[mm.v_out[i]] = mm.bmask[i];
     return IPCS_OK;
   });
 }
@@ -180,11 +237,12 @@ int ipcs_mesh_boundary(ipcs_mesh m, uint8_t* out, int64_t cap) {
 int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_rows,
                       int32_t* col, int64_t cap_nnz) {
   return guard([&]() -> int {
-    const ipcs::Pattern& P = M(m).pattern(which);
+    const ipcs::Mesh& mm = M(m);
+    const ipcs::Pattern& P = mm.pattern(which);
     need(rowptr != nullptr && cap_rows >= P.nrows + 1, "rowptr buffer too small");
     need(col != nullptr && cap_nnz >= P.nnz(), "col buffer too small");
-    std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
-    std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
+    csr_to_interface(mm, P, velocity_rows(which), velocity_cols(which), nullptr, rowptr, col,
+                     nullptr);
     return IPCS_OK;
   });
 }
@@ -331,7 +389,10 @@ int ipcs_set_builtin_solution(ipcs_run r, int32_t kind, const double* prm, int32
 int ipcs_set_state(ipcs_run r, const double* u, const double* p, double t) {
   return guard([&]() -> int {
     need(u != nullptr && p != nullptr, "null state arrays");
-    R(r).set_state(u, p, t);
+    ipcs::Run& rr = R(r);
+    std::vector<double> ui((size_t)rr.dim * rr.n2);
+    vel_to_internal(*rr.mesh, rr.dim, u, ui.data());
+    rr.set_state(ui.data(), p, t);
     return IPCS_OK;
   });
 }
@@ -363,8 +424,19 @@ static int copy_out(ipcs::Run& rr, const double* src, int64_t n, double* out, in
   return IPCS_OK;
 }
 
+// a velocity field [dim][n2] of the run, in the interface numbering
+static int copy_out_velocity(ipcs::Run& rr, const double* src, double* out, int64_t cap) {
+  const int64_t n = (int64_t)rr.dim * rr.n2;
+  need(out != nullptr && cap >= n, "output buffer too small");
+  std::vector<double> h((size_t)n);
+  HIP_OK(hipMemcpyAsync(h.data(), src, sizeof(double) * n, hipMemcpyDeviceToHost, rr.stream));
+  HIP_OK(hipStreamSynchronize(rr.stream));
+  vel_to_interface(*rr.mesh, rr.dim, h.data(), out);
+  return IPCS_OK;
+}
+
 int ipcs_get_velocity(ipcs_run r, double* u, int64_t cap) {
-  return guard([&]() -> int { ipcs::Run& rr = R(r); return copy_out(rr, rr.U, rr.dim * rr.n2, u, cap); });
+  return guard([&]() -> int { ipcs::Run& rr = R(r); return copy_out_velocity(rr, rr.U, u, cap); });
 }
 
 int ipcs_get_pressure(ipcs_run r, double* p, int64_t cap) {
@@ -383,11 +455,11 @@ int ipcs_get_field(ipcs_run r, int32_t which, double* out, int64_t cap) {
   return guard([&]() -> int {
     ipcs::Run& rr = R(r);
     switch (which) {
-      case IPCS_FIELD_U: return copy_out(rr, rr.U, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_U: return copy_out_velocity(rr, rr.U, out, cap);
       case IPCS_FIELD_P: return copy_out(rr, rr.P, rr.n1, out, cap);
-      case IPCS_FIELD_USTAR: return copy_out(rr, rr.Ustar, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_USTAR: return copy_out_velocity(rr, rr.Ustar, out, cap);
       case IPCS_FIELD_DP: return copy_out(rr, rr.dP, rr.n1, out, cap);
-      case IPCS_FIELD_RHS_MOM: return copy_out(rr, rr.bU, rr.dim * rr.n2, out, cap);
+      case IPCS_FIELD_RHS_MOM: return copy_out_velocity(rr, rr.bU, out, cap);
       case IPCS_FIELD_RHS_P: return copy_out(rr, rr.rP, rr.n1, out, cap);
     }
     ipcs::fail(IPCS_E_INVALID, "unknown field id");
@@ -421,14 +493,12 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
       ipcs::fail(IPCS_E_INVALID, "unknown matrix id");
     }
     const ipcs::Pattern& P = mm.pattern(pat);
-    if (rowptr) {
-      need(cap_rows >= P.nrows + 1, "rowptr buffer too small");
-      std::memcpy(rowptr, P.rowptr.data(), sizeof(int32_t) * (P.nrows + 1));
-    }
+    if (rowptr) need(cap_rows >= P.nrows + 1, "rowptr buffer too small");
     need(val != nullptr && cap_nnz >= P.nnz(), "value buffer too small");
-    if (col) std::memcpy(col, P.col.data(), sizeof(int32_t) * P.nnz());
     if (rr.A_dirty) rr.reform_A();
-    rr.export_values(pat, src, rr.vsz, val);
+    std::vector<double> v((size_t)P.nnz());
+    rr.export_values(pat, src, rr.vsz, v.data());
+    csr_to_interface(mm, P, velocity_rows(pat), velocity_cols(pat), v.data(), rowptr, col, val);
     return IPCS_OK;
   });
 }

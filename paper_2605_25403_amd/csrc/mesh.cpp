@@ -152,8 +152,10 @@ void build_incidence(const std::vector<int32_t>& c2d, int64_t nc, int nloc, int 
     for (int j = 0; j < nrowloc; ++j) I.code[fill[c2d[c * nloc + j]]++] = int32_t((c << 4) | j);
 }
 
-// Velocity DOFs: the vertices keep their numbers; every other velocity node
-// is numbered in lexicographic order of its coordinates, last coordinate most
+// Internal numbering of the velocity DOFs (the interface keeps the listing
+// order; v_out and v_in map between the two): the vertices keep their
+// numbers; every other velocity node is numbered in lexicographic order of its
+// coordinates, last coordinate most
 // significant (y, x in 2D; z, y, x in 3D), ties (none on a valid mesh) by the
 // listing order. Rows that are neighbours in this order reference nearby
 // columns, so a SELL-64 slice's gathers touch few cache lines; keeping the
@@ -175,6 +177,9 @@ void renumber_velocity(Mesh& m) {
   for (int64_t i = 0; i < nv; ++i) nw[i] = int32_t(i);
   for (int64_t k = 0; k < n - nv; ++k) nw[ord[k]] = int32_t(nv + k);
   for (auto& v : m.c2d) v = nw[v];
+  m.v_in = nw;
+  m.v_out.assign(n, 0);
+  for (int64_t i = 0; i < n; ++i) m.v_out[nw[i]] = int32_t(i);
   std::vector<double> x2(m.x2.size());
   std::vector<uint8_t> bm(n);
   for (int64_t i = 0; i < n; ++i) {

@@ -76,8 +76,13 @@ struct PartSell {
 //   (2 x_lo + x_hi)/3 and (x_lo + 2 x_hi)/3 for sorted vertices lo < hi; one
 //   node per cell at its centroid), pressure P2 (vertices, then the edges
 //   sorted by (lo, hi)).
-// Velocity DOFs: the vertices in input order, then the other velocity nodes in
-// lexicographic order of their coordinates (last coordinate most significant).
+// Velocity DOFs, internal numbering (every array below): the vertices in input
+// order, then the other velocity nodes in lexicographic order of their
+// coordinates (last coordinate most significant), so that neighbouring nodes
+// have neighbouring indices. The interface numbering differs: the vertices,
+// then the other nodes in listing order (P2: the edge midpoints with the edges
+// sorted by (lo, hi); P3: two nodes per edge in edge order, then the cell
+// centroids). v_out maps internal to interface ids, v_in back.
 // A cell's local velocity DOFs start with its vertices. Kernels take the cell
 // geometry from the pressure cell table, which starts with the vertex ids in
 // both pairs (P1: the vertices; P2: vertices, then edges).
@@ -95,6 +100,8 @@ struct Mesh {
   std::vector<double> xp;         // [n1][dim] pressure node coordinates
   std::vector<uint8_t> bmask;     // [n2]
   std::vector<int32_t> bidx;      // boundary velocity nodes, ascending
+  std::vector<int32_t> v_out;     // [n2] internal velocity id -> interface id
+  std::vector<int32_t> v_in;      // [n2] interface velocity id -> internal id
   Pattern p22, p11, p12, p21;
   Sell e22, e11, e12, e21;        // SELL-64 layouts of the four patterns
   Incidence inc2, inc1;

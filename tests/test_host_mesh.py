@@ -165,3 +165,38 @@ def test_pair_arguments_are_checked():
         I.ipcs_mesh_from_arrays_pair(X, cells, I.IPCS_PAIR_P3P2)
     assert "triangles" in I.ipcs_last_error()
     assert I.Mesh.unit_square(3).pair == I.IPCS_PAIR_P2P1
+
+
+@pytest.mark.parametrize("dim,n,pair", [(2, 3, 0), (3, 2, 0), (2, 3, 1)])
+def test_interface_velocity_numbering_is_the_listing_order(dim, n, pair):
+    """The velocity numbering of the interface, built here by brute force from
+    the library's own vertex and cell tables (independently of the oracle): the
+    vertices in input order, then the edges' nodes with the edges sorted by
+    (lower, higher) vertex (P2: the midpoint; P3: the node at
+    (2 x_lo + x_hi)/3, then the one at (x_lo + 2 x_hi)/3), then (P3) the cell
+    centroids in cell order. The library numbers these nodes differently inside
+    and converts at the interface."""
+    m = I.Mesh.unit_square(n, pair=pair) if dim == 2 else I.Mesh.unit_cube(n)
+    c = I.ipcs_mesh_counts(m.h)
+    xp = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P1).reshape(-1, dim)
+    X = xp[:c.nv]
+    cp = I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P1).reshape(c.nc, -1)[:, :dim + 1]
+    edges = sorted({tuple(sorted((int(a), int(b)))) for cell in cp
+                    for a, b in itertools.combinations(cell, 2)})
+    if pair == 0:
+        want = np.vstack([X] + [0.5 * (X[a] + X[b]) for a, b in edges])
+    else:
+        nodes = [X]
+        for a, b in edges:
+            nodes += [(2.0 * X[a] + X[b]) / 3.0, (X[a] + 2.0 * X[b]) / 3.0]
+        nodes += [X[cell].mean(axis=0) for cell in cp]
+        want = np.vstack(nodes)
+    x2 = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2).reshape(-1, dim)
+    assert x2.shape == want.shape
+    np.testing.assert_allclose(x2, want, rtol=0, atol=1e-15)
+    # the cell table and the boundary mask speak the same numbering
+    c2 = I.ipcs_mesh_cell_dofs(m.h, I.IPCS_SPACE_P2).reshape(c.nc, -1)
+    np.testing.assert_array_equal(c2[:, :dim + 1], cp)
+    b = I.ipcs_mesh_boundary(m.h)
+    on_edge = np.any((np.abs(want) < 1e-14) | (np.abs(want - 1.0) < 1e-14), axis=1)
+    np.testing.assert_array_equal(b.astype(bool), on_edge)
