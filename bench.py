@@ -109,17 +109,26 @@ def cpu_baseline(w, budget_steps=1):
     pb = problems.TaylorGreen2D(w["k"], w["nu"]) if dim == 2 else problems.Beltrami3D(nu=w["nu"])
     o = ipcs.IPCS(S, pb, ipcs.Params(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
                                      tol_corr=w["tol"]))
+    from threadpoolctl import threadpool_limits
     t0 = time.perf_counter()
     for _ in range(budget_steps):
         o.step()
     dt = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    return {"value": (dim * S.Nu + S.Np) * budget_steps / dt, "unit": "DOF-steps/s",
+    # the next step again, with every thread pool limited to one thread
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        o.step()
+        dt1 = time.perf_counter() - t1
+    ndof = dim * S.Nu + S.Np
+    return {"value": ndof * budget_steps / dt, "unit": "DOF-steps/s",
             "cores": int(threads), "kind": "oracle",
             "sample": f"{budget_steps} of {w['steps']} IPCS steps of the same workload from "
                       f"the interpolated initial state ({dt:.1f} s; setup not timed; "
-                      f"scipy CSR products single-threaded, BLAS up to {threads} threads)",
-            "seconds": dt, "iterations": o.iters[-1]}
+                      f"scipy CSR products single-threaded, BLAS up to {threads} threads); "
+                      f"the following step with one thread: {dt1:.1f} s",
+            "seconds": dt, "iterations": o.iters[-2] if len(o.iters) > 1 else o.iters[-1],
+            "value_1thread": ndof / dt1}
 
 
 def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
