@@ -382,6 +382,30 @@ def seed_forms(w, steps, torch, I, seeds=(0, 1, 2)):
     return out
 
 
+def microbench(r, torch, I, c, dim, vsz, p3, reps=5):
+    """Stand-alone launches of the velocity SpMV and the convection assembly on
+    the run's own data: 20 back to back (warm: the data stays in the caches),
+    and single launches after writing a 1 GiB buffer (cold: the Infinity Cache
+    holds none of their data), median of reps."""
+    names = ["bicg_spmv", "asm_conv"] + (["asm_sum"] if dim == 3 else [])
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    out = {}
+    for name in names:
+        kid = KERNELS[name][0]
+        warm = I.ipcs_profile_kernel(r.h, kid, 20)
+        cold = []
+        for _ in range(reps):
+            flush.fill_(1)
+            torch.cuda.synchronize()
+            cold.append(I.ipcs_profile_kernel(r.h, kid, 1))
+        cold_us = float(np.median(cold))
+        b = kernel_bytes(name, c, dim, vsz, p3)
+        out[name] = {"bytes": b, "warm_us": warm, "cold_us": cold_us,
+                     "warm_GBps": b / (warm * 1e-6) / 1e9, "cold_GBps": b / (cold_us * 1e-6) / 1e9}
+    del flush
+    return out
+
+
 def copy_peak(torch, mib=1024, reps=5):
     """Device-to-device copy bandwidth (GB/s, bytes read + written), best of
     reps copies of mib MiB, timed with events on the current stream."""
@@ -525,6 +549,7 @@ def main():
                 "algorithmic_bytes_per_launch": kern[dom]["bytes"],
                 "us_per_launch": kern[dom]["us_per_launch"]}
 
+    micro = microbench(r, torch, I, c, dim, 4 if mixed else 8, p3)
     ph = np.array([s["ms"] for s in stats])
     out = {
         "metric": "P2-P1 IPCS DOF-steps/s & HBM GB/s vs FP64 plain; p50/p99 step latency",
@@ -565,6 +590,7 @@ def main():
                          "pressure": float(np.percentile(ph[:, 2], 90)),
                          "correction": float(np.percentile(ph[:, 3], 90))},
         "iterations_median": {"momentum": it_m, "pressure": it_p, "correction": it_c},
+        "microbench": micro,
     }
     if not args.no_forms and not mixed and not p3:
         out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
