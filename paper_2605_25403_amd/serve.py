@@ -146,6 +146,7 @@ class Server:
         wall = clock() - t0
         lat = np.concatenate([np.asarray(r["lat"]) for r in results.values() if r["lat"]])
         qd = np.array([r["t_admit"] - r["t_arrive"] for r in results.values()])
+        e2e = np.array([r["t_done"] - r["t_arrive"] for r in results.values() if "t_done" in r])
         first = min(q.t_arrive for q in requests)
         report = {
             "requests": len(requests), "failed": fails, "rounds": rounds,
@@ -157,6 +158,9 @@ class Server:
             "p99_step_ms": 1000 * float(np.percentile(lat, 99)),
             "queue_delay_p50_ms": 1000 * float(np.percentile(qd, 50)),
             "queue_delay_p99_ms": 1000 * float(np.percentile(qd, 99)),
+            # arrival to the end of the last step, completed requests
+            "end_to_end_p50_ms": 1000 * float(np.percentile(e2e, 50)) if e2e.size else None,
+            "end_to_end_p99_ms": 1000 * float(np.percentile(e2e, 99)) if e2e.size else None,
         }
         return report, results
 
