@@ -156,3 +156,31 @@ def test_unreachable_tolerance_stops_early(rows):
     if e.value.code == I.IPCS_E_NOT_CONVERGED:
         assert st.checks_p >= 3
     np.testing.assert_array_equal(r.velocity(), U0)
+
+
+@pytest.mark.parametrize("pair,arrays", [(0, False), (0, True), (1, False)])
+def test_state_round_trip_in_interface_numbering(pair, arrays):
+    """set_state then velocity()/pressure() give back the arrays bit for bit,
+    and the velocity the library interpolates itself sits at the interface
+    numbering's node coordinates (the library renumbers internally)."""
+    torch, I = require_gpu()
+    print(f"state round trip pair={pair} arrays={arrays}", flush=True)
+    from paper_2605_25403_amd.workloads import jittered_mesh
+    if arrays:
+        x, cells = jittered_mesh(2, 9, 3)
+        m = I.Mesh.from_arrays(x, cells, pair=pair)
+    else:
+        m = I.Mesh.unit_square(7, pair=pair)
+    r = I.Run(m, I.ipcs_params_default(nu=0.01, dt=0.01))
+    c = I.ipcs_mesh_counts(m.h)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((2, c.n2))
+    P = rng.standard_normal(c.n1)
+    r.set_state(U, P, 0.25)
+    np.testing.assert_array_equal(r.velocity(), U)
+    np.testing.assert_array_equal(r.pressure(), P)
+    k = np.pi
+    r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (k,))
+    X = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2).reshape(-1, 2)
+    want = problems.TaylorGreen2D(k, 0.01).u(X, r.time())       # [n2, 2]
+    assert np.abs(r.velocity() - want.T).max() < 1e-12
