@@ -10,6 +10,10 @@
 * convergence orders of the Taylor-Green problem: velocity -> 3, pressure -> 2
   (the theoretical Taylor-Hood orders, also observed by the paper's table
   "convergence_ipcs"), with a guard that the time error is negligible;
+* convergence orders of John's unsteady benchmark of Section 5.1 (nu = rho =
+  1, the problem of the paper's table "convergence_ipcs"): velocity -> 3,
+  pressure -> 2, with the same time-error guard, and the orders agree with
+  the ones that table prints;
 * Taylor-Green kinetic-energy decay rate e^{-4 nu k^2 t};
 * the Chorin-Temam projection (the non-incremental scheme stated before IPCS):
   its step does not depend on P^n at all and equals the IPCS step from P^n = 0
@@ -109,6 +113,40 @@ def test_taylor_green_convergence_orders():
     assert abs(ou - 3.0) <= 0.15, ou
     assert abs(op - 2.0) <= 0.2, op
     assert np.log2(e[8][0] / e[16][0]) > 2.4 and np.log2(e[8][1] / e[16][1]) > 1.8
+
+
+def _john_errors(n, dt, t0=1.0, T=1e-3):
+    """L2 errors after T / dt steps of John's benchmark (nu = rho = 1) from the
+    interpolated exact state at t0. The fields vary like sin t, so the
+    splitting error of the pressure is O(dt) with a large constant: dt is
+    taken small enough that the spatial error dominates at every n used."""
+    pb = problems.John2D(1.0)
+    S = fem.Space(*mesh.unit_square(n, n))
+    st = ipcs.IPCS(S, pb, ipcs.Params(nu=1.0, dt=dt, t0=t0))
+    st.run(int(round(T / dt)))
+    return (errors.l2_velocity(S, st.U, pb.u, st.t), errors.l2_pressure(S, st.P, pb.p, st.t))
+
+
+def test_john_convergence_orders():
+    """Section 5.1, table "convergence_ipcs": velocity -> 3, pressure -> 2 on
+    John's problem. The paper states neither dt nor the final time, so only
+    the orders are compared: ours against the theory and against the last
+    orders the table prints (2.99 and 2.07)."""
+    e = {n: _john_errors(n, 1e-4) for n in (8, 16, 32)}
+    eh = _john_errors(32, 5e-5)
+    assert abs(eh[0] / e[32][0] - 1) < 0.05 and abs(eh[1] / e[32][1] - 1) < 0.05, (eh, e[32])
+    ou = np.log2(e[16][0] / e[32][0])
+    op = np.log2(e[16][1] / e[32][1])
+    assert abs(ou - 3.0) <= 0.15, ou
+    assert abs(op - 2.0) <= 0.2, op
+    assert np.log2(e[8][0] / e[16][0]) > 2.7 and np.log2(e[8][1] / e[16][1]) > 1.8
+    import os
+    rows = [list(map(float, l.split())) for l in
+            open(os.path.join(os.path.dirname(__file__), "golden", "convergence_ipcs.txt"))
+            if l.strip() and not l.startswith("#")]
+    pu = np.log2(rows[-2][1] / rows[-1][1])
+    pp = np.log2(rows[-2][2] / rows[-1][2])
+    assert abs(ou - pu) <= 0.1 and abs(op - pp) <= 0.15, (ou, pu, op, pp)
 
 
 def test_taylor_green_energy_decay():
