@@ -175,7 +175,10 @@ typedef struct ipcs_run_s* ipcs_run;
  * IPCS_MIXED: quadrature, assembly arithmetic and stored matrix values in FP32
  * (cell geometry is formed in FP64 and then rounded); fields, Krylov vectors,
  * dot products, Jacobi diagonals and Dirichlet lifting in FP64, and SpMV
- * products accumulated in FP64. The pressure Poisson solve is an FP64
+ * products accumulated in FP64. The divergence matrices D_c stay FP64: the
+ * pressure right-hand side -(rho/dt) sum_c D_c U*_c cancels to within a
+ * factor of about 1e7 of its terms' magnitudes on fine meshes, so FP32 values
+ * would leave it dominated by their rounding. The pressure Poisson solve is an FP64
  * iterative refinement on the FP64 Kp, to ||r - Kp dP|| <= tol_ir ||r||,
  * around Jacobi-CG on Kp rounded to FP32. Each pass asks the inner CG for the
  * reduction still needed, but not below half of the reduction the previous

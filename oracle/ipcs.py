@@ -31,6 +31,8 @@ step has no pressure term, the Poisson solve gives the new pressure itself
 (Kp P^{n+1} = -(rho/dt) sum_c D_c U*_c, the same sign reading as for IPCS),
 P^{n+1} is shifted to zero integral mean, and the correction uses P^{n+1}.
 """
+import time
+
 import numpy as np
 
 from . import fem, krylov
@@ -72,6 +74,10 @@ class IPCS:
         self.U = problem.u(S.xu, self.t).T.copy()          # (d, Nu)
         self.P = self.normalize(problem.p(S.xp, self.t))
         self.iters = []
+        # wall time (s) of each step's phases, for reporting only: the
+        # momentum system (boundary data, forcing, convection matrix and
+        # right-hand sides), its solves, the pressure step, the correction
+        self.times = []
 
     def normalize(self, P):
         """Shift a pressure field to zero integral mean."""
@@ -91,13 +97,14 @@ class IPCS:
             return np.zeros((self.S.dim, self.S.Nu))
         return fem.load(self.S, self.pb.f, t)
 
-    # ---- the three sub-steps, in the paper's order
-    def momentum(self, t, g):
+    # ---- the three sub-steps, in the paper's order. Each *_system method
+    # forms the linear system of its sub-step (matrix with Dirichlet rows and
+    # columns eliminated, right-hand sides, initial guesses, Jacobi inverse
+    # diagonal); the sub-step solves it.
+    def momentum_system(self, t, g):
         S, prm = self.S, self.prm
         C = fem.convection(S, self.U)
         F = self.forcing(t)
-        Ustar = np.zeros_like(self.U)
-        its = []
         if prm.semi_implicit:
             A = (self.A + C).tocsr()
             A.sort_indices()
@@ -105,6 +112,7 @@ class IPCS:
             dinv = 1.0 / A_el.diagonal()
         else:
             A, A_el, dinv = self.A, self.A_el, self.dinv_A
+        bs, x0s = [], []
         for c in range(S.dim):
             b = self.M @ self.U[c] / prm.dt
             if not prm.chorin:
@@ -112,39 +120,65 @@ class IPCS:
             b = b + F[c]
             if not prm.semi_implicit:
                 b = b - C @ self.U[c]
-            b = fem.lift(A, b, self.bmask, g[c])
-            x0 = np.where(self.bmask, g[c], self.U[c])
-            Ustar[c], it = krylov.bicgstab(A_el, b, x0, dinv, prm.tol_mom, prm.maxit)
+            bs.append(fem.lift(A, b, self.bmask, g[c]))
+            x0s.append(np.where(self.bmask, g[c], self.U[c]))
+        return A_el, bs, x0s, dinv, C
+
+    def momentum(self, t, g):
+        prm = self.prm
+        A_el, bs, x0s, dinv, C = self.momentum_system(t, g)
+        t0 = time.perf_counter()
+        Ustar = np.zeros_like(self.U)
+        its = []
+        for c in range(self.S.dim):
+            Ustar[c], it = krylov.bicgstab(A_el, bs[c], x0s[c], dinv, prm.tol_mom, prm.maxit)
             its.append(it)
+        self._t_solve = time.perf_counter() - t0
         return Ustar, C, its
+
+    def pressure_system(self, Ustar):
+        prm = self.prm
+        r = -(prm.rho / prm.dt) * sum(self.D[c] @ Ustar[c] for c in range(self.S.dim))
+        return self.Kp, r - r.mean()
 
     def pressure(self, Ustar):
         S, prm = self.S, self.prm
-        r = -(prm.rho / prm.dt) * sum(self.D[c] @ Ustar[c] for c in range(S.dim))
-        r = r - r.mean()
-        dP, it = krylov.pcg(self.Kp, r, np.zeros(S.Np), self.dinv_Kp, prm.tol_p,
+        Kp, r = self.pressure_system(Ustar)
+        dP, it = krylov.pcg(Kp, r, np.zeros(S.Np), self.dinv_Kp, prm.tol_p,
                             prm.maxit, project=True)
         dP = self.normalize(dP)
         return dP, it
 
+    def correction_system(self, Ustar, dP, g):
+        prm = self.prm
+        bs = []
+        for c in range(self.S.dim):
+            b = self.M @ Ustar[c] - (prm.dt / prm.rho) * (self.G[c] @ dP)
+            bs.append(fem.lift(self.M, b, self.bmask, g[c]))
+        return self.M_el, bs
+
     def correction(self, Ustar, dP, g):
-        S, prm = self.S, self.prm
+        prm = self.prm
+        M_el, bs = self.correction_system(Ustar, dP, g)
         Unew = np.zeros_like(Ustar)
         its = []
-        for c in range(S.dim):
-            b = self.M @ Ustar[c] - (prm.dt / prm.rho) * (self.G[c] @ dP)
-            b = fem.lift(self.M, b, self.bmask, g[c])
-            Unew[c], it = krylov.pcg(self.M_el, b, Ustar[c], self.dinv_M,
-                                     prm.tol_corr, prm.maxit)
+        for c in range(self.S.dim):
+            Unew[c], it = krylov.pcg(M_el, bs[c], Ustar[c], self.dinv_M, prm.tol_corr, prm.maxit)
             its.append(it)
         return Unew, its
 
     def step(self):
+        c0 = time.perf_counter()
         t = self.t + self.prm.dt
         g = self.dirichlet(t)
         Ustar, _, it_m = self.momentum(t, g)
+        c1 = time.perf_counter()
         dP, it_p = self.pressure(Ustar)
+        c2 = time.perf_counter()
         Unew, it_c = self.correction(Ustar, dP, g)
+        c3 = time.perf_counter()
+        self.times.append({"asm": (c1 - c0) - self._t_solve, "momentum": self._t_solve,
+                           "pressure": c2 - c1, "correction": c3 - c2})
         self.U = Unew
         self.P = dP if self.prm.chorin else self.P + dP
         self.t = t

@@ -497,7 +497,7 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
     need(val != nullptr && cap_nnz >= P.nnz(), "value buffer too small");
     if (rr.A_dirty) rr.reform_A();
     std::vector<double> v((size_t)P.nnz());
-    rr.export_values(pat, src, rr.vsz, v.data());
+    rr.export_values(pat, src, pat == IPCS_PATTERN_P1P2 ? 8 : rr.vsz, v.data());
     csr_to_interface(mm, P, velocity_rows(pat), velocity_cols(pat), v.data(), rowptr, col, val);
     return IPCS_OK;
   });

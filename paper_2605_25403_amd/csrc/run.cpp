@@ -468,7 +468,8 @@ void Run::layout(Carver& c) {
   Kp = vals(ne11);
   Kp64 = mixed ? c.take<double>(ne11) : static_cast<double*>(Kp);
   for (int k = 0; k < 3; ++k) {
-    Dc[k] = k < dim ? vals(ne12) : nullptr;
+    // the divergence matrices stay FP64 in both forms (Run::assemble_constant)
+    Dc[k] = k < dim ? c.take<double>(ne12) : nullptr;
     Gc[k] = k < dim ? vals(ne21) : nullptr;
   }
   liftA = c.take<double>(std::max<int64_t>(nlift, 1));
@@ -627,9 +628,14 @@ void Run::assemble_constant() {
   RowAsm a21{(int32_t)n2, sp21, inc2p, inc2, s21, m.s21.stride, c2d, m.nloc2, X,
              {Gc[0], Gc[1], Gc[2]}, m.pair, c2v, m.nloc1};
   asm_grad(dim, mixed, stream, a21, cfg_g.bs, cfg_g.lds);
+  // D_c is assembled and stored in FP64 in both forms. The pressure
+  // right-hand side -(rho/dt) sum_c D_c U*_c is a sum of terms that cancel to
+  // within a factor ~1e7 of their magnitudes at 512^2 (U* is nearly
+  // divergence-free), so FP32 values would leave it with rounding noise of
+  // the order of the result itself. One FP64 product per step costs little.
   RowAsm a12{(int32_t)n1, sp12, inc1p, inc1, s12, m.s12.stride, c2d, m.nloc2, X,
              {Dc[0], Dc[1], Dc[2]}, m.pair, c2v, m.nloc1};
-  asm_div(dim, mixed, stream, a12, cfg_d.bs, cfg_d.lds);
+  asm_div(dim, false, stream, a12, cfg_d.bs, cfg_d.lds);
   // Kp is assembled in FP64 in both forms. The mixed form keeps that FP64
   // copy for the refinement residual and gives the inner CG the same matrix
   // rounded to FP32, the FP32 operator closest to it, so that a refinement
@@ -811,7 +817,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   cfg_mk = asm_cfg(mm.e22, vsz);
   cfg_e = asm_cfg(mm.e22, vsz);
   cfg_g = asm_cfg(mm.e21, vsz);
-  cfg_d = asm_cfg(mm.e12, vsz);
+  cfg_d = asm_cfg(mm.e12, 8);
   cfg_kp = asm_cfg(mm.e11, vsz);
   Carver meas;
   layout(meas);
@@ -833,7 +839,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
     HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
   }
   for (int k = 0; k < dim; ++k) {
-    HIP_OK(hipMemsetAsync(Dc[k], 0, (size_t)vsz * ne12, stream));
+    HIP_OK(hipMemsetAsync(Dc[k], 0, sizeof(double) * ne12, stream));
     HIP_OK(hipMemsetAsync(Gc[k], 0, (size_t)vsz * ne21, stream));
   }
   const size_t vbytes = sizeof(double) * dim * n2;
@@ -994,7 +1000,7 @@ void Run::pressure_rhs() {
   // state; an r no larger than a bound on its own rounding error is treated
   // as zero (dP = 0): on the solve's state in the FP64 form, in the
   // refinement test (scal[6]) in the mixed form
-  rhs_pressure(stream, dim, mixed, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
+  rhs_pressure(stream, dim, false, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
                scal + 0, mixed ? nullptr : &(kst + dim)->zero2, scal + 6);
   HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
 }

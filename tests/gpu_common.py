@@ -72,8 +72,68 @@ def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=Tr
 
 
 def rel(a, b):
+    """Relative difference of a field from its reference, in norm and per
+    entry: the larger of ||a - b|| / ||b|| and max|a - b| / max|b|, so that an
+    error confined to a few rows (a part halo, a boundary row) cannot hide
+    under the norm."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    nb, mb = np.linalg.norm(b), np.abs(b).max(initial=0.0)
+    d = a - b
+    return max(np.linalg.norm(d) / (nb if nb > 0 else 1.0),
+               np.abs(d).max(initial=0.0) / (mb if mb > 0 else 1.0))
+
+
+def residual(A, x, b):
+    """||b - A x|| / ||b|| of a candidate solution x on a given system."""
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    return np.linalg.norm(b - A @ x) / (nb if nb > 0 else 1.0)
+
+
+def step_residuals(I, o, r):
+    """One library step, phase by phase, from the oracle's current state;
+    each of the library's three solve outputs (U*, dP, U^{n+1}) is put into
+    the oracle's own matrix of that sub-step, with the right-hand side formed
+    from the library's inputs to it: the common state for the momentum
+    system, the library's U* and dP for the correction. Returns relative
+    residuals (bar: the solve tolerance, up to the rounding of b - A x), the
+    largest deviation of the library's P^{n+1} - P^n from its dP, the check
+    of the library's pressure right-hand side below, and the library's
+    outputs. The oracle's state is unchanged.
+
+    The pressure right-hand side r = -(rho/dt) sum_c D_c U*_c is a sum of
+    terms far larger than itself (U* is close to discretely divergence-free:
+    at 512^2 the summed magnitudes exceed |r| by ~1e7), so the last-bit
+    differences of two correct evaluations move r by ~1e-9 relative. The
+    library's dP is therefore put into the oracle's Kp with the library's own
+    r, and that r is held against the oracle's sum over the library's U*
+    entry by entry, relative to the rounding scale of the sum (the summed
+    magnitudes (rho/dt) sum_c |D_c| |U*_c| plus their mean, for the
+    projection to zero sum)."""
+    dim, dt = o.S.dim, o.prm.dt
+    t1 = o.t + dt
+    g = o.dirichlet(t1)
+    res = {}
+    r.phase(I.IPCS_PHASE_ASM)
+    r.phase(I.IPCS_PHASE_MOMENTUM)
+    Us = r.field(I.IPCS_FIELD_USTAR)
+    A_el, bs, _, _, _ = o.momentum_system(t1, g)
+    for c in range(dim):
+        res[f"momentum{c}"] = residual(A_el, Us[c], bs[c])
+    r.phase(I.IPCS_PHASE_PRESSURE)
+    dP = r.field(I.IPCS_FIELD_DP)
+    rp_lib = r.field(I.IPCS_FIELD_RHS_P)
+    Kp, rp = o.pressure_system(Us)
+    mag = (o.prm.rho / dt) * sum(abs(o.D[c]) @ np.abs(Us[c]) for c in range(dim))
+    res["pressure_rhs"] = np.max(np.abs(rp_lib - rp) / (mag + mag.mean()))
+    res["pressure"] = residual(Kp, dP, rp_lib)
+    r.phase(I.IPCS_PHASE_CORRECTION)
+    U = r.velocity()
+    M_el, bc = o.correction_system(Us, dP, g)
+    for c in range(dim):
+        res[f"correction{c}"] = residual(M_el, U[c], bc[c])
+    P = r.pressure()
+    res["p_update"] = np.abs((P - o.P) - dP).max() / max(np.abs(dP).max(), 1e-300)
+    return res, Us, dP, U, P
 
 
 def field_errors(o, r):

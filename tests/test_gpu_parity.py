@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from oracle import fem
-from tests.gpu_common import field_errors, make_pair, mat_rel, oracle_space, rel, require_gpu
+from tests.gpu_common import (field_errors, make_pair, mat_rel, oracle_space, rel, require_gpu,
+                              step_residuals)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +130,53 @@ def test_beltrami_3d_steps():
         o.step()
         errs = field_errors(o, r)
         assert max(errs) <= FIELD_TOL, (step, errs)
+
+
+def test_beltrami_3d_multipart_steps_fp64_and_mixed():
+    """3D Beltrami on 24^3 cubes (82,944 tetrahedra; 117,649 velocity and
+    15,625 pressure nodes), in the launch configuration of the 64^3 workload
+    at a size the oracle finishes: the two-pass convection assembly, and the
+    one-kernel Poisson CG on 384-row parts (41 parts, a halo near N1 as at
+    64^3). FP64: the first step phase by phase with each solve's output put
+    into the oracle's own system (relative residual <= 1e-12), then two steps
+    of fields against the oracle (norm and per entry, five times the
+    measured 1.4e-13). Mixed form:
+    two steps from the same state against the FP64 oracle, bars five times
+    the measured differences (u 7.5e-7, p 3.6e-5: the 3D divergence
+    amplifies the FP32 rounding of U* more than in 2D)."""
+    torch, I = require_gpu()
+    print("Beltrami 3D n=24 multi-part, FP64 and mixed", flush=True)
+    S, o, r = make_pair(I, 3, 24, "beltrami", 0.01, 1e-3)
+    part = r.poisson_partition()
+    print("partition", part, flush=True)
+    assert part["rows_max"] == 384 and part["nparts"] > 8
+    assert part["halo_rows"] > 0.5 * S.N1
+    U0, P0, t0 = o.U.copy(), o.P.copy(), o.t
+    res, _, _, _, _ = step_residuals(I, o, r)
+    print("residuals", {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
+    for k, v in res.items():
+        assert v <= 1e-12, (k, v)
+    for step in range(2):
+        if step:
+            r.advance(1)
+        o.step()
+        errs = field_errors(o, r)
+        print(f"fp64 step {step}:", [f"{e:.2e}" for e in errs], flush=True)
+        assert max(errs) <= 7e-13, (step, errs)   # measured: 1.4e-13
+    del r
+    o.set_state(U0, P0, t0)
+    m = I.Mesh.unit_cube(24)
+    rm = I.Run(m, I.ipcs_params_default(nu=0.01, dt=1e-3, tol_mom=1e-13, tol_p=1e-13,
+                                        tol_corr=1e-13, tol_ir=1e-10,
+                                        precision=I.IPCS_MIXED))
+    rm.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+    rm.set_state(U0, P0, t0)
+    for step in range(2):
+        st = rm.advance(1)[0]
+        o.step()
+        errs = field_errors(o, rm)
+        print(f"mixed step {step}:", [f"{e:.2e}" for e in errs], st["ir_outer"], flush=True)
+        assert max(errs[:3]) <= 4e-6 and errs[3] <= 2e-4, (step, errs)
 
 
 @pytest.mark.parametrize("rows", [0, -1])
