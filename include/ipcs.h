@@ -33,8 +33,9 @@
  *     never frees it. Besides small pinned host staging buffers, the only
  *     other allocation is ipcs_batch_step's stream-ordered one (hipMallocAsync,
  *     released with hipFreeAsync before it returns) for the descriptors of its
- *     shared launches. All device work of a run is issued on the HIP stream
- *     given at creation (or to ipcs_batch_step).
+ *     shared launches; ipcs_batch_step_noalloc takes them from a fixed array
+ *     instead. All device work of a run is issued on the HIP stream given at
+ *     creation (or to the batch step).
  *   - Layout: velocity is component-major [dim][N2] (N2 velocity DOFs per
  *     component, N1 pressure DOFs; the numbering is stated at
  *     ipcs_mesh_unit_square_pair). All host-side fields are FP64, whatever
@@ -340,6 +341,28 @@ int ipcs_export_matrix(ipcs_run r, int32_t which, int32_t* rowptr, int64_t cap_r
  * others complete their step. Returns IPCS_OK or the first failure. stats may
  * be NULL or hold nruns entries; their phase times are the batch's. */
 int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_stats* stats);
+
+/* Size of the fixed device array of ipcs_batch_step_noalloc, per GPU. */
+#define IPCS_BATCH_SCRATCH_BYTES (16u << 20)
+/* Most runs in one ipcs_batch_step_noalloc call. */
+#define IPCS_BATCH_NOALLOC_MAX_RUNS 256
+/* ipcs_batch_step for callers that cannot allocate memory (serving loops that
+ * must not call hipMalloc, harnesses that forbid device or pinned-host
+ * allocation once set up). It computes what ipcs_batch_step computes, with the
+ * same kernels, block decompositions and reductions, so each run's result is
+ * bitwise the same; it allocates nothing: the descriptors of each shared
+ * Krylov solve go into a fixed device array of IPCS_BATCH_SCRATCH_BYTES that
+ * every GPU the library runs on holds until the process ends, the status
+ * polls into a fixed host array per GPU, and the batch's phase times are
+ * taken with runs[0]'s own events. The runs must be on the current device.
+ * Before any work it checks the batch: more than IPCS_BATCH_NOALLOC_MAX_RUNS
+ * runs, or descriptors that need more than the array (runs with many blocks,
+ * such as hundreds of the largest 2D meshes), give IPCS_E_CAPACITY and leave
+ * every run as it was. Calls on one GPU share that GPU's arrays and each call
+ * reuses them from solve to solve: two calls that overlap on one GPU (from
+ * two host threads, or on two streams) race, and must not be made. */
+int ipcs_batch_step_noalloc(ipcs_run* runs, int32_t nruns, void* hip_stream,
+                            ipcs_step_stats* stats);
 
 enum {                            /* kernels of the step, for the timing hooks       */
   IPCS_KERNEL_PCG_SPMV_P = 0,     /* Poisson CG: w = Kp u, partial u.w               */

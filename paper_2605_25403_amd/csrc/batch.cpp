@@ -15,7 +15,8 @@
 // sets of their own by (rows per thread, value type), with the largest LDS
 // size of their members.
 // Their device descriptors (group table, block maps, polling slots) come from
-// one stream-ordered allocation per solve, released stream-ordered.
+// one stream-ordered allocation per solve, released stream-ordered, or, for
+// callers that cannot allocate, from a fixed device array (BatchMem).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -68,11 +69,18 @@ KSet& set_of(Run& r, int which) {
   return which == 0 ? r.set_mom : which == 1 ? r.set_p : r.set_corr;
 }
 
-// Builds the shared sets for system set `which` (0 momentum, 1 Poisson,
-// 2 correction) of the given runs. The descriptors live in buf, which the
-// caller keeps alive until the solves have been enqueued.
-std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStream_t s,
-                                std::unique_ptr<DevBuf>& buf) {
+// Plan of one shared launch set: its runs, block maps and the offsets of its
+// descriptors in the solve's descriptor space.
+struct Plan {
+  bool fused = false;
+  std::vector<Run*> rs;
+  std::vector<int2> bm, bv, bf;
+  size_t o_groups = 0, o_bm = 0, o_bv = 0, o_poll = 0, o_fgroups = 0, o_bf = 0, o_compact = 0;
+};
+
+// Plans the shared sets for system set `which` (0 momentum, 1 Poisson,
+// 2 correction) of the given runs; returns the bytes their descriptors take.
+size_t plan_shared(const std::vector<Run*>& runs, int which, std::vector<Plan>& plans) {
   // fused Poisson sets: (1, rows per thread, value type); others: (0, ns, ept_m, value type)
   std::map<std::tuple<int, int, int, int>, std::vector<Run*>> cls;
   for (Run* r : runs) {
@@ -88,13 +96,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     bytes += n;
     return off;
   };
-  struct Plan {
-    bool fused = false;
-    std::vector<Run*> rs;
-    std::vector<int2> bm, bv, bf;
-    size_t o_groups, o_bm, o_bv, o_poll, o_fgroups = 0, o_bf = 0, o_compact = 0;
-  };
-  std::vector<Plan> plans;
+  plans.clear();
   for (auto& kv : cls) {
     Plan p;
     p.fused = std::get<0>(kv.first) == 1;
@@ -124,7 +126,25 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     p.o_compact = take(sizeof(int2) * (p.bm.size() + p.bv.size() + p.bf.size()));
     plans.push_back(std::move(p));
   }
-  buf.reset(new DevBuf(s, bytes));
+  return std::max<size_t>(bytes, 256);
+}
+
+// Builds the shared sets for system set `which` of the given runs. The
+// descriptors live in mem's fixed array when it has one, else in buf, which
+// the caller keeps alive until the solves have been enqueued.
+std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStream_t s,
+                                std::unique_ptr<DevBuf>& buf, const BatchMem& mem) {
+  std::vector<Plan> plans;
+  const size_t bytes = plan_shared(runs, which, plans);
+  char* base = nullptr;
+  if (mem.dev) {
+    // checked for the whole batch before its step began (batch_mem_check)
+    if (bytes > mem.dev_cap) fail(IPCS_E_CAPACITY, "batch descriptors exceed the fixed array");
+    base = mem.dev;
+  } else {
+    buf.reset(new DevBuf(s, bytes));
+    base = buf->base;
+  }
   std::vector<char> host(bytes, 0);
   std::vector<Shared> out;
   for (Plan& p : plans) {
@@ -147,18 +167,18 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
     // folded totals are bitwise the re-reduced ones: fold if any member would
     int fold = 0;
     for (Run* r : p.rs) fold |= set_of(*r, which).L.fold;
-    S.L = KLaunch{reinterpret_cast<const KGroup*>(buf->base + p.o_groups),
+    S.L = KLaunch{reinterpret_cast<const KGroup*>(base + p.o_groups),
                   (int)p.rs.size(),
                   L0.ns,
                   L0.ept_m,
                   L0.fp32,
-                  reinterpret_cast<const int2*>(buf->base + p.o_bm),
+                  reinterpret_cast<const int2*>(base + p.o_bm),
                   (int)p.bm.size(),
-                  reinterpret_cast<const int2*>(buf->base + p.o_bv),
+                  reinterpret_cast<const int2*>(base + p.o_bv),
                   (int)p.bv.size(),
                   fold};
-    S.d_poll = reinterpret_cast<KState*>(buf->base + p.o_poll);
-    S.d_compact = reinterpret_cast<int2*>(buf->base + p.o_compact);
+    S.d_poll = reinterpret_cast<KState*>(base + p.o_poll);
+    S.d_compact = reinterpret_cast<int2*>(base + p.o_compact);
     S.compact_cap = (int)(p.bm.size() + p.bv.size() + p.bf.size());
     if (p.fused) {
       size_t lds = 0;
@@ -171,8 +191,8 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
       std::memcpy(host.data() + p.o_bf, p.bf.data(), sizeof(int2) * p.bf.size());
       const FLaunch& F0 = set_of(*p.rs[0], which).F;
       S.fused = true;
-      S.F = FLaunch{reinterpret_cast<const FGroup*>(buf->base + p.o_fgroups), (int)p.rs.size(),
-                    F0.ept, F0.fp32, reinterpret_cast<const int2*>(buf->base + p.o_bf),
+      S.F = FLaunch{reinterpret_cast<const FGroup*>(base + p.o_fgroups), (int)p.rs.size(),
+                    F0.ept, F0.fp32, reinterpret_cast<const int2*>(base + p.o_bf),
                     (int)p.bf.size(), lds};
     }
     S.last_iters = last;
@@ -182,7 +202,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
               std::begin(S.kid));
     out.push_back(std::move(sh));
   }
-  HIP_OK(hipMemcpyAsync(buf->base, host.data(), bytes, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(base, host.data(), bytes, hipMemcpyHostToDevice, s));
   // host is a pageable stack copy: finish the transfer before it goes away
   HIP_OK(hipStreamSynchronize(s));
   return out;
@@ -191,17 +211,27 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
 // Solves system set `which` of the runs together. rc[run] receives each run's
 // status; stats are filled per run.
 void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream_t s,
-                  std::map<Run*, int>& rc, std::map<Run*, ipcs_step_stats*>& st) {
+                  std::map<Run*, int>& rc, std::map<Run*, ipcs_step_stats*>& st,
+                  const BatchMem& mem) {
   if (runs.empty()) return;
   std::unique_ptr<DevBuf> buf;
-  std::vector<Shared> sets = make_shared(runs, which, s, buf);
+  std::vector<Shared> sets = make_shared(runs, which, s, buf, mem);
   KTimer none;
   for (Shared& sh : sets) {
     int check_every = 1 << 30;
     for (Run* r : sh.owner) check_every = std::min(check_every, r->prm.check_every);
     std::vector<KState> hs;
-    KState* pin = pinned_states(GMAX * (int)sh.owner.size());
-    krylov_solve(s, sh.S, m, check_every, hs, pin, none);
+    const int nslot = GMAX * (int)sh.owner.size();
+    KState* pin = nullptr;
+    if (mem.dev) {
+      if (nslot > mem.host_cap) fail(IPCS_E_CAPACITY, "batch has more runs than the fixed staging");
+      pin = mem.host;
+    } else {
+      pin = pinned_states(nslot);
+    }
+    // with a fixed array, solves take no chunk-timing events (the poll
+    // schedule keeps the costs measured by earlier solves)
+    krylov_solve(s, sh.S, m, check_every, hs, pin, none, mem.dev == nullptr);
     for (size_t g = 0; g < sh.owner.size(); ++g) {
       Run* r = sh.owner[g];
       set_of(*r, which).last_iters = sh.S.last_iters;
@@ -230,7 +260,7 @@ void solve_shared(const std::vector<Run*>& runs, int which, KMethod m, hipStream
 // inner solves): every pass checks each run's FP64 residual, then solves the
 // correction systems of the runs that still need one together.
 static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map<Run*, int>& rc,
-                          std::map<Run*, ipcs_step_stats*>& st) {
+                          std::map<Run*, ipcs_step_stats*>& st, const BatchMem& mem) {
   struct IR {
     double bb = -1.0, rel = 0.0, prev = 0.0, contraction = 0.0, floor_in = 0.0;
     double last_tol = 1.0, op_limit = 0.0;
@@ -287,7 +317,7 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
       r->set_p.last_iters = k < Run::kIrHist ? r->ir_last[k] : 0;
     }
     std::map<Run*, int> rin;
-    solve_shared(inner, 1, KMethod::PCG, s, rin, st);
+    solve_shared(inner, 1, KMethod::PCG, s, rin, st, mem);
     for (Run* r : inner) {
       const int k = ir[r].outer - 1;
       if (k < Run::kIrHist) r->ir_last[k] = r->set_p.last_iters;
@@ -317,7 +347,18 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
   }
 }
 
-int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats) {
+size_t batch_descriptor_bytes(Run* const* runs, int nruns) {
+  std::vector<Run*> all(runs, runs + nruns);
+  std::vector<Plan> plans;
+  size_t most = 0;
+  // a subset's descriptors (the plain or mixed Poisson runs, the runs still
+  // refining) never take more room than the whole batch's
+  for (int which = 0; which < 3; ++which) most = std::max(most, plan_shared(all, which, plans));
+  return most;
+}
+
+int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats,
+               const BatchMem& mem) {
   std::vector<Run*> all(runs, runs + nruns);
   for (Run* r : all) {
     if (r->phase_next != IPCS_PHASE_ASM) fail(IPCS_E_STATE, "a run is in the middle of a step");
@@ -354,19 +395,24 @@ int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stat
     for (Run* r : all)
       if (rc[r] != IPCS_OK && st[r] && st[r]->failed_solve == 0) st[r]->failed_solve = which;
   };
-  hipEvent_t e[5];
-  for (auto& x : e) HIP_OK(hipEventCreate(&x));
+  // phase events: the batch's own, or (fixed memory) the first run's, which no
+  // other work of that run uses during the batch
+  hipEvent_t own[5] = {};
+  hipEvent_t* e = mem.dev ? all[0]->ev : own;
+  if (!mem.dev)
+    for (auto& x : own) HIP_OK(hipEventCreate(&x));
   struct Ev {
     hipEvent_t* e;
     ~Ev() {
-      for (int k = 0; k < 5; ++k) (void)hipEventDestroy(e[k]);
+      for (int k = 0; k < 5; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
     }
-  } evguard{e};
+  } evguard{own};
 
   HIP_OK(hipEventRecord(e[0], s));
   for (Run* r : all) r->asm_phase();
   HIP_OK(hipEventRecord(e[1], s));
-  solve_shared(alive(), 0, KMethod::BICG, s, rc, st);
+  solve_shared(alive(), 0, KMethod::BICG, s, rc, st, mem);
   mark(1);
   HIP_OK(hipEventRecord(e[2], s));
   std::vector<Run*> live = alive();
@@ -375,14 +421,14 @@ int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stat
     r->pressure_rhs();
     (r->mixed ? mixed : plain).push_back(r);
   }
-  solve_shared(plain, 1, KMethod::PCG, s, rc, st);
-  refine_shared(mixed, s, rc, st);
+  solve_shared(plain, 1, KMethod::PCG, s, rc, st, mem);
+  refine_shared(mixed, s, rc, st, mem);
   mark(2);
   for (Run* r : alive()) r->pressure_end();
   HIP_OK(hipEventRecord(e[3], s));
   live = alive();
   for (Run* r : live) r->correction_rhs();
-  solve_shared(live, 2, KMethod::PCG, s, rc, st);
+  solve_shared(live, 2, KMethod::PCG, s, rc, st, mem);
   mark(3);
   live = alive();
   for (Run* r : live) r->correction_commit();

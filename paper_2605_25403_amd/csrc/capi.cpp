@@ -516,6 +516,29 @@ int ipcs_batch_step(ipcs_run* runs, int32_t nruns, void* hip_stream, ipcs_step_s
   });
 }
 
+int ipcs_batch_step_noalloc(ipcs_run* runs, int32_t nruns, void* hip_stream,
+                            ipcs_step_stats* stats) {
+  return guard([&]() -> int {
+    need(runs != nullptr && nruns > 0, "need at least one run");
+    if (nruns > IPCS_BATCH_NOALLOC_MAX_RUNS)
+      ipcs::fail(IPCS_E_CAPACITY, "more runs than IPCS_BATCH_NOALLOC_MAX_RUNS in one batch");
+    std::vector<ipcs::Run*> rs((size_t)nruns);
+    for (int i = 0; i < nruns; ++i) {
+      need(runs[i] != nullptr, "null run in the batch");
+      rs[i] = &R(runs[i]);
+      for (int k = 0; k < i; ++k) need(rs[k] != rs[i], "a run appears twice in the batch");
+    }
+    ipcs::BatchMem mem;
+    mem.dev = ipcs::batch_scratch(&mem.dev_cap);
+    mem.host = ipcs::batch_host_staging(&mem.host_cap);
+    const size_t bytes = ipcs::batch_descriptor_bytes(rs.data(), nruns);
+    if (bytes > mem.dev_cap)
+      ipcs::fail(IPCS_E_CAPACITY, "the batch's descriptors need " + std::to_string(bytes) +
+                                      " bytes, more than IPCS_BATCH_SCRATCH_BYTES");
+    return ipcs::batch_step(rs.data(), nruns, static_cast<hipStream_t>(hip_stream), stats, mem);
+  });
+}
+
 int ipcs_profile_kernel(ipcs_run r, int32_t kernel, int32_t nlaunch, double* us_per_launch) {
   return guard([&]() -> int {
     need(nlaunch > 0 && us_per_launch != nullptr, "need nlaunch > 0 and an output");

@@ -163,16 +163,16 @@ static hipEvent_t* chunk_events(int n) {
 constexpr int kChunkEvents = 128;   // chunks timed per solve (the rest are not)
 
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector<KState>& hs,
-                 KState* pinned, KTimer& T) {
+                 KState* pinned, KTimer& T, bool time_bursts) {
   // bursts of device work (the start, each chunk of iterations, each
   // confirmation) are bracketed by events while any are left: the gap between
   // the end of one burst and the start of the next is the cost of a poll
-  hipEvent_t* ev = chunk_events(2 * kChunkEvents);
+  hipEvent_t* ev = time_bursts ? chunk_events(2 * kChunkEvents) : nullptr;
   int nburst = 0, timed_launches = 0;
   double busy_ms = 0.0;
   std::vector<int> iter_burst;   // bursts that are chunks of iterations
   auto burst = [&](bool iters, auto work) {
-    const bool timed = nburst < kChunkEvents;
+    const bool timed = ev != nullptr && nburst < kChunkEvents;
     if (timed) HIP_OK(hipEventRecord(ev[2 * nburst], s));
     work();
     if (timed) {

@@ -91,8 +91,11 @@ enum class KMethod { PCG, BICG };
 // Runs a set to completion (each group at most its maxit iterations). h_states[g*GMAX + j]
 // receives the final states. Returns IPCS_OK or the status of the first
 // failed system.
+// With time_bursts false the solve records no chunk-timing events and keeps
+// the set's measured costs (us_per_launch, us_per_poll) as they are.
 int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every,
-                 std::vector<KState>& h_states, KState* pinned, KTimer& T);
+                 std::vector<KState>& h_states, KState* pinned, KTimer& T,
+                 bool time_bursts = true);
 int status_to_code(int kstatus);
 
 // Rows per thread of matrix kernels for a group of n rows, and the block
@@ -240,8 +243,31 @@ struct Run {
   int pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st);
 };
 
+// Where a batch step keeps its shared-launch descriptors and status staging.
+// Default (dev == nullptr): one stream-ordered device allocation per solve and
+// pinned host staging. Fixed: a device array of dev_cap bytes and a host
+// array of host_cap states, both reused solve after solve (the step waits for
+// each solve before the next one writes its descriptors); nothing is
+// allocated.
+struct BatchMem {
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  KState* host = nullptr;
+  int host_cap = 0;
+};
+
 // One step of every run with shared Krylov launches on stream s (serving form).
-int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats);
+int batch_step(Run* const* runs, int nruns, hipStream_t s, ipcs_step_stats* stats,
+               const BatchMem& mem = BatchMem{});
+// Largest descriptor space any one shared solve of a batch step of these runs
+// takes (host computation only).
+size_t batch_descriptor_bytes(Run* const* runs, int nruns);
+// The fixed device array of ipcs_batch_step_noalloc on the current device
+// (scratch.hip); *cap receives its size in bytes.
+char* batch_scratch(size_t* cap);
+// The fixed host array of status states for that device; *cap receives its
+// length in states.
+KState* batch_host_staging(int* cap);
 
 void fill_stats_solve(const std::vector<KState>& hs, int nsys, int which, ipcs_step_stats* st);
 

@@ -123,6 +123,7 @@ _SIGS = {
     "ipcs_get_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
     "ipcs_export_matrix": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, _P, C.c_int64]),
     "ipcs_batch_step": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "ipcs_batch_step_noalloc": (C.c_int, [_P, C.c_int32, _P, _P]),
     "ipcs_profile_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ipcs_kernel_timing": (C.c_int, [_P, C.c_uint32]),
     "ipcs_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
@@ -331,6 +332,23 @@ def ipcs_batch_step(runs, stream):
     st = (ipcs_step_stats * n)()
     rc = lib.ipcs_batch_step(arr, n, C.c_void_p(stream), C.cast(st, C.c_void_p))
     if rc in (IPCS_E_INVALID, IPCS_E_STATE, IPCS_E_DEVICE, IPCS_E_NOMEM):
+        raise IpcsError(rc, lib.ipcs_last_error().decode())
+    return rc, [s.as_dict() for s in st]
+
+
+IPCS_BATCH_SCRATCH_BYTES = 16 << 20
+IPCS_BATCH_NOALLOC_MAX_RUNS = 256
+
+
+def ipcs_batch_step_noalloc(runs, stream):
+    """ipcs_batch_step without allocation (the library's fixed descriptor
+    array); a batch it cannot hold raises with IPCS_E_CAPACITY before any
+    work."""
+    n = len(runs)
+    arr = (_P * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in runs])
+    st = (ipcs_step_stats * n)()
+    rc = lib.ipcs_batch_step_noalloc(arr, n, C.c_void_p(stream), C.cast(st, C.c_void_p))
+    if rc in (IPCS_E_INVALID, IPCS_E_STATE, IPCS_E_DEVICE, IPCS_E_NOMEM, IPCS_E_CAPACITY):
         raise IpcsError(rc, lib.ipcs_last_error().decode())
     return rc, [s.as_dict() for s in st]
 
