@@ -20,6 +20,7 @@ Modules
   krylov      - Jacobi-PCG and Jacobi-BiCGStab (textbook definitions)
   problems    - manufactured solutions (Taylor-Green, John, Beltrami, polynomial)
   ipcs        - the IPCS time step in the paper's order
+  steady      - steady Navier-Stokes by Newton's method (monolithic, P2-P1)
   errors      - L2 errors against exact fields
 
 Every function is pinned by a test in tests/ (tests/test_oracle_*.py) against

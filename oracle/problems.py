@@ -187,3 +187,51 @@ class PolySteady2DCubic:
         f1 = u1 * u1x + u2 * u1y - self.nu * (6 * X + 4 * Y) + (2 * X + Y)
         f2 = u1 * u2x + u2 * u2y - self.nu * (-4 * X - 6 * Y) + (X - 2 * Y)
         return np.stack([f1, f2], axis=-1)
+
+
+class SteadyPaper2D:
+    """The steady example of Section 4.2 on the unit square:
+    u = 10 x^2 (x-1)^2 y (y-1)(2y-1), v = -10 x (x-1)(2x-1) y^2 (y-1)^2,
+    p = 10 (2x-1)(2y-1), f = -nu Lap u + (u . grad) u + grad p. The fields are
+    polynomials; their derivatives are taken exactly from numpy polynomial
+    coefficients: with a(s) = s^2 (s-1)^2, a'(s) = 2 s (s-1)(2s-1), so
+    u = 5 a(x) a'(y), v = -5 a'(x) a(y), the curl of the stream function
+    5 a(x) a(y) (div u = 0)."""
+    dim = 2
+
+    def __init__(self, nu=1.0):
+        from numpy.polynomial import polynomial as Pl
+        self.nu = float(nu)
+        a = Pl.polymul([0.0, 0.0, 1.0], Pl.polymul([-1.0, 1.0], [-1.0, 1.0]))  # s^2 (s-1)^2
+        self._a = a
+        self._da = Pl.polyder(a)
+        self._dda = Pl.polyder(a, 2)
+        self._ddda = Pl.polyder(a, 3)
+        self._P = Pl
+
+    def _ev(self, c, s):
+        return self._P.polyval(s, c)
+
+    def u(self, x, t=0.0):
+        X, Y = x[..., 0], x[..., 1]
+        e = self._ev
+        return np.stack([5.0 * e(self._a, X) * e(self._da, Y),
+                         -5.0 * e(self._da, X) * e(self._a, Y)], axis=-1)
+
+    def p(self, x, t=0.0):
+        X, Y = x[..., 0], x[..., 1]
+        return 10.0 * (2 * X - 1) * (2 * Y - 1)
+
+    def f(self, x, t=0.0):
+        X, Y = x[..., 0], x[..., 1]
+        e = self._ev
+        a, da, dda, ddda = self._a, self._da, self._dda, self._ddda
+        u1 = 5.0 * e(a, X) * e(da, Y)
+        u2 = -5.0 * e(da, X) * e(a, Y)
+        u1x, u1y = 5.0 * e(da, X) * e(da, Y), 5.0 * e(a, X) * e(dda, Y)
+        u2x, u2y = -5.0 * e(dda, X) * e(a, Y), -5.0 * e(da, X) * e(da, Y)
+        lap1 = 5.0 * (e(dda, X) * e(da, Y) + e(a, X) * e(ddda, Y))
+        lap2 = -5.0 * (e(ddda, X) * e(a, Y) + e(da, X) * e(dda, Y))
+        px, py = 20.0 * (2 * Y - 1), 20.0 * (2 * X - 1)
+        return np.stack([-self.nu * lap1 + u1 * u1x + u2 * u1y + px,
+                         -self.nu * lap2 + u1 * u2x + u2 * u2y + py], axis=-1)

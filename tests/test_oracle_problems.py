@@ -38,6 +38,10 @@ def sym_fields(name, nu, k=None):
     if name == "poly2c":
         return ([x ** 3 + 2 * x ** 2 * y, -3 * x ** 2 * y - 2 * x * y ** 2],
                 x ** 2 - y ** 2 + x * y - sp.Rational(1, 4), [x, y])
+    if name == "steady_paper":
+        return ([10 * x ** 2 * (x - 1) ** 2 * y * (y - 1) * (2 * y - 1),
+                 -10 * x * (x - 1) * (2 * x - 1) * y ** 2 * (y - 1) ** 2],
+                10 * (2 * x - 1) * (2 * y - 1), [x, y])
     if name == "poly3":
         return [y ** 2 + z ** 2, z ** 2 + x ** 2, x ** 2 + y ** 2], x + y + z - sp.Rational(3, 2), [x, y, z]
     raise KeyError(name)
@@ -51,6 +55,8 @@ CASES = [
     ("poly2", problems.PolySteady2D(0.3), dict(nu=sp.Rational(3, 10))),
     ("poly3", problems.PolySteady3D(0.3), dict(nu=sp.Rational(3, 10))),
     ("poly2c", problems.PolySteady2DCubic(0.3), dict(nu=sp.Rational(3, 10))),
+    ("steady_paper", problems.SteadyPaper2D(1.0), dict(nu=1)),
+    ("steady_paper", problems.SteadyPaper2D(0.05), dict(nu=sp.Rational(1, 20))),
 ]
 
 
