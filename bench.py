@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def log(msg):
+    """Progress of the benchmark's stages, on stderr (the JSON line is stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 # kernel name -> (library kernel id, source file); ids are IPCS_KERNEL_* of include/ipcs.h
 KERNELS = {
     "pcg_spmv_p": (0, "kernels_krylov.hip"),
@@ -76,6 +81,46 @@ def kernel_bytes(kernel, c, dim, vsz=8, p3=False):
     raise KeyError(kernel)
 
 
+def unit_bytes(kernel, c, dim, vsz=8):
+    """Algorithmic bytes per launch in the units of the method's byte model:
+    each array read once, each output written once, vsz-byte matrix values,
+    8-byte vectors, 4-byte CSR indices (column per entry, row pointer per row).
+    SpMV of a pattern with N rows: (vsz + 4) nnz + 4 (N + 1) + 2 * 8 * N per
+    vector; a vector pass: 8 * N. One launch of the one-kernel Poisson CG is
+    one iteration: an SpMV of Kp and five P1 vector passes. The velocity
+    SpMVs apply A (or M) to d vectors at once. None when the model has no unit
+    for the kernel (then kernel_bytes is used)."""
+    n1, n2, nnz22, nnz11 = c.n1, c.n2, c.nnz[0], c.nnz[1]
+    spmv = lambda nnz, n, nvec: (vsz + 4) * nnz + 4 * (n + 1) + 2 * 8 * n * nvec
+    if kernel == "pcg_fused_p":
+        return spmv(nnz11, n1, 1) + 5 * 8 * n1
+    if kernel in ("bicg_spmv", "bicg_spmv_t", "pcg_spmv_m"):
+        return spmv(nnz22, n2, dim)
+    if kernel == "pcg_spmv_p":
+        return spmv(nnz11, n1, 1)
+    if kernel == "asm_conv" and dim == 2:
+        return kernel_bytes(kernel, c, dim, vsz)
+    return None
+
+
+def rocprof_avg_us(kernel, workload):
+    """Average duration (us) of a kernel in the committed rocprofv3 kernel
+    statistics of a workload (profiles/kernels_<workload>.txt), or None."""
+    import re
+    f = os.path.join(ROOT, "profiles", f"kernels_{workload}.txt")
+    sym = {"pcg_fused_p": r"^void k_fcg_iter1<", "bicg_spmv": r"^void k_bicg_spmv<0,",
+           "bicg_spmv_t": r"^void k_bicg_spmv<1,", "asm_conv": r"^void k_(asm_rows<2, OpConv|conv_cells)",
+           "asm_sum": r"^void k_asm_local<"}.get(kernel)
+    if sym is None or not os.path.exists(f):
+        return None
+    for line in open(f):
+        if re.search(sym, line):
+            parts = line.split()
+            # name ... calls avg min max %
+            return float(parts[-4])
+    return None
+
+
 def source_sha1(fname):
     with open(os.path.join(ROOT, "paper_2605_25403_amd", "csrc", fname), "rb") as f:
         return hashlib.sha1(f.read()).hexdigest()
@@ -98,10 +143,12 @@ def measured_traffic(kernel, workload):
     return float(kv["bytes_per_launch"])
 
 
-def cpu_baseline(w, budget_steps=1):
-    """The FP64 oracle on the host cores: one step of the same workload from
-    the same initial state (setup not timed)."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline(w, budget_steps=3):
+    """The FP64 oracle on the host cores: the first budget_steps steps of the
+    same workload from the same initial state (setup not timed), with the
+    wall time of each phase per step, then one more step with every thread
+    pool limited to one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import fem, ipcs, mesh, problems
     dim, n = w["dim"], w["n"]
     order = 3 if w.get("pair", 0) == 1 else 2
@@ -109,12 +156,12 @@ def cpu_baseline(w, budget_steps=1):
     pb = problems.TaylorGreen2D(w["k"], w["nu"]) if dim == 2 else problems.Beltrami3D(nu=w["nu"])
     o = ipcs.IPCS(S, pb, ipcs.Params(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
                                      tol_corr=w["tol"]))
-    from threadpoolctl import threadpool_limits
     t0 = time.perf_counter()
     for _ in range(budget_steps):
         o.step()
     dt = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    phases = {k: [round(tt[k] * 1000.0, 1) for tt in o.times] for k in o.times[0]}
     # the next step again, with every thread pool limited to one thread
     with threadpool_limits(limits=1):
         t1 = time.perf_counter()
@@ -123,11 +170,13 @@ def cpu_baseline(w, budget_steps=1):
     ndof = dim * S.Nu + S.Np
     return {"value": ndof * budget_steps / dt, "unit": "DOF-steps/s",
             "cores": int(threads), "kind": "oracle",
-            "sample": f"{budget_steps} of {w['steps']} IPCS steps of the same workload from "
-                      f"the interpolated initial state ({dt:.1f} s; setup not timed; "
+            "sample": f"the first {budget_steps} of {w['steps']} IPCS steps of the same workload "
+                      f"from the interpolated initial state ({dt:.1f} s; setup not timed; "
                       f"scipy CSR products single-threaded, BLAS up to {threads} threads); "
                       f"the following step with one thread: {dt1:.1f} s",
-            "seconds": dt, "iterations": o.iters[-2] if len(o.iters) > 1 else o.iters[-1],
+            "seconds": dt, "phase_ms_per_step": phases,
+            "iterations": [[list(map(int, m)), int(pi), list(map(int, cc))]
+                           for m, pi, cc in o.iters[:budget_steps]],
             "value_1thread": ndof / dt1}
 
 
@@ -152,7 +201,9 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
            "pcg_fused_p": r"k_fcg_iter1?<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
            "asm_conv": r"OpConv<|k_conv_cells<", "asm_sum": r"k_asm_local<"}[kernel]
-    copy_re = re.compile(r"copyBuffer|elementwise|copy", re.I)
+    # the calibration copy is a device-to-device hipMemcpy (torch's copy_ of
+    # contiguous tensors); fills (torch's elementwise FillFunctor) are not
+    copy_re = re.compile(r"copyBuffer")
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rr = rows(d, counter)
@@ -187,6 +238,55 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
         f.write(f"source: {summary['source']}\n")
         f.write(f"source_sha1: {summary['source_sha1']}\n")
     print(json.dumps(summary))
+
+
+def counters_summary(run_dirs, kernel_regex, name, workload, command, clock_ghz=2.4):
+    """Writes profiles/counters_<name>_<workload>.txt from rocprofv3 --pmc runs
+    (CSV output; one directory per pass) of one bench command: the median per
+    dispatch of each counter for the kernels whose name matches kernel_regex,
+    and the VALU utilization they imply. A wave64 FP64 (or non-packed FP32)
+    VALU instruction occupies a 16-lane SIMD for 4 cycles, so the VALU issue
+    fraction is 4 SQ_INSTS_VALU / (SIMDs x kernel cycles), with 1024 SIMDs
+    (256 CUs x 4) and the kernel's cycles from its dispatch timestamps at the
+    engine clock; SQ_ACTIVE_INST_VALU (quad-cycles) gives the busy form of
+    the same ratio. No GPU use."""
+    import csv
+    import glob
+    import re
+    rx = re.compile(kernel_regex)
+    vals, durs = {}, []
+    for d in run_dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if not rx.search(r["Kernel_Name"].replace(" ", "")):
+                    continue
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                if "Start_Timestamp" in r and r.get("End_Timestamp"):
+                    durs.append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    if not vals:
+        raise SystemExit(f"counters-summary: no rows for {kernel_regex} under {run_dirs}")
+    med = {k: float(np.median(v)) for k, v in vals.items()}
+    dur = float(np.median(durs)) if durs else None
+    out = os.path.join(ROOT, "profiles", f"counters_{name}_{workload}.txt")
+    with open(out, "w") as o:
+        o.write(f"rocprofv3 counters of {name} ({kernel_regex}) on workload {workload}\n")
+        o.write(f"command: {command}\n")
+        for k in sorted(med):
+            o.write(f"{k}: median {med[k]:.6g} per dispatch over {len(vals[k])} dispatches\n")
+        if dur:
+            o.write(f"dispatch duration (median, counter run): {dur * 1e6:.2f} us\n")
+            cyc = dur * clock_ghz * 1e9
+            if "SQ_INSTS_VALU" in med:
+                o.write(f"VALU issue fraction 4*SQ_INSTS_VALU/(1024*cycles): "
+                        f"{4 * med['SQ_INSTS_VALU'] / (1024 * cyc):.3f}\n")
+            if "SQ_ACTIVE_INST_VALU" in med:
+                o.write(f"VALU busy 4*SQ_ACTIVE_INST_VALU/(1024*cycles): "
+                        f"{4 * med['SQ_ACTIVE_INST_VALU'] / (1024 * cyc):.3f}\n")
+        if "GRBM_GUI_ACTIVE" in med and "SQ_ACTIVE_INST_VALU" in med:
+            # GRBM_GUI_ACTIVE reads the busy cycles of the 8 XCDs summed
+            o.write(f"VALU busy 4*SQ_ACTIVE_INST_VALU/(1024*GRBM_GUI_ACTIVE/8): "
+                    f"{32 * med['SQ_ACTIVE_INST_VALU'] / (1024 * med['GRBM_GUI_ACTIVE']):.3f}\n")
+    print(open(out).read())
 
 
 def trace_summary(trace_dir, workload, command):
@@ -425,32 +525,147 @@ def copy_peak(torch, mib=1024, reps=5):
     return best
 
 
-def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16):
+def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
+                 lanes=((32,), (64,), (128,), (256,))):
     """C5: Poisson-arrival stream of 2D TG requests (n in {32,64,128,256},
     seed-drawn k and nu, 50 steps at dt = 1e-3), mixed form, continuous
-    batching; beside it the same accuracy target run one request after the
-    other (sequential, each alone) on the first seq_sample requests."""
+    batching in one lane per mesh size (each with its own stream), and the
+    same stream in a single lane for comparison. Beside them, the first
+    seq_sample requests run one after the other, each alone, in the mixed form
+    (the served form's alone latency per mesh size) and in the plain FP64
+    form at tolerance 1e-12 (the baseline): per-step latency p50/p99 and
+    throughput, and each served result's relative difference from its FP64
+    run (nodal L2 and per entry, largest over u and p)."""
     from paper_2605_25403_amd.serve import Server, requests_from
     from paper_2605_25403_amd.workloads import serving_requests
     reqs = requests_from(serving_requests(seed=0, count=count, rate=rate))
-    srv = Server(max_slots=max_slots)
-    report, _ = srv.serve(reqs)
-    # sequential baseline: same requests, no arrivals gaps, one run at a time
     sample = reqs[:seq_sample]
-    t0 = time.perf_counter()
-    dsteps = 0
-    for q in sample:
-        r = srv.start_run(q)
-        r.advance(q.steps)
-        torch.cuda.synchronize()
-        dsteps += (2 * (2 * q.n + 1) ** 2 + (q.n + 1) ** 2) * q.steps
-        del r
-    seq = dsteps / (time.perf_counter() - t0)
-    report["sequential_sample"] = {"requests": seq_sample, "dof_steps_per_s": seq}
+    srv = Server(max_slots=max_slots, lanes=lanes)
+    report, res = srv.serve(reqs, keep_ids={q.id for q in sample})
+    one, _ = Server(max_slots=max_slots).serve(reqs)
+    report["one_lane"] = {k: one[k] for k in ("dof_steps_per_s", "p50_step_ms", "p99_step_ms",
+                                              "step_ms_by_n", "queue_delay_p99_ms",
+                                              "end_to_end_p99_ms", "rounds")}
+
+    def alone(prec):
+        base = Server(precision=prec)
+        lat, by_n, fields = [], {}, {}
+        dsteps, t_all = 0, 0.0
+        for q in sample:
+            r = base.start_run(q)
+            torch.cuda.synchronize()
+            for _ in range(q.steps):
+                t0 = time.perf_counter()
+                r.advance(1)
+                dt = time.perf_counter() - t0
+                lat.append(dt)
+                by_n.setdefault(q.n, []).append(dt)
+                t_all += dt
+            dsteps += (2 * (2 * q.n + 1) ** 2 + (q.n + 1) ** 2) * q.steps
+            fields[q.id] = (r.velocity(), r.pressure())
+            del r
+        out = {"requests": len(sample), "dof_steps_per_s": dsteps / t_all,
+               "p50_step_ms": 1000 * float(np.percentile(lat, 50)),
+               "p99_step_ms": 1000 * float(np.percentile(lat, 99)),
+               "step_ms_by_n": {str(n): {"p50_step_ms": 1000 * float(np.percentile(v, 50)),
+                                         "p99_step_ms": 1000 * float(np.percentile(v, 99))}
+                                for n, v in sorted(by_n.items())}}
+        return out, fields
+
+    mixed_alone, _ = alone(I.IPCS_MIXED)
+    fp64, f64 = alone(I.IPCS_FP64)
+
+    def diff(a, b):
+        return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                   float(np.abs(a - b).max() / np.abs(b).max()))
+
+    errs = [max(diff(res[q.id]["U"], f64[q.id][0]), diff(res[q.id]["P"], f64[q.id][1]))
+            for q in sample]
+    report["sequential_mixed_alone"] = mixed_alone
+    report["sequential_fp64_plain"] = fp64
+    report["served_vs_fp64_rel_diff"] = {"max": max(errs), "median": float(np.median(errs)),
+                                         "requests": len(errs)}
+    report["speedup_vs_sequential_fp64"] = report["dof_steps_per_s"] / fp64["dof_steps_per_s"]
     report["workload"] = (f"c5: {count} requests, Poisson arrivals at {rate}/s, 2D TG, "
                           "n in {32,64,128,256}, 50 steps at dt=1e-3, mixed form, "
-                          f"max_slots {max_slots}")
+                          f"max_slots {max_slots}, lanes {[list(l) for l in lanes]}")
     return report
+
+
+def c4_form(torch, I, steps=10, warmup=2):
+    """The 3D workload (64^3 cubes x 6 Kuhn tetrahedra, Beltrami a = pi/4,
+    d = pi/2, nu = 0.01, dt = 1e-3) in the mixed form and in the plain FP64
+    form, from the same start, stepped in lockstep: DOF-steps/s of each over
+    `steps` steps after `warmup`, phase medians, the mixed fields' relative
+    difference from the FP64 ones per step, and per-launch times of the
+    velocity SpMV and the one-kernel Poisson CG (two more steps with
+    per-launch events) with their unit bytes and fraction of the HBM peak."""
+    from paper_2605_25403_amd.workloads import resolve
+    w = resolve("c4")
+    m = I.Mesh.unit_cube(w["n"])
+    c = m.counts
+    ndof = 3 * c.n2 + c.n1
+    runs = {}
+    for name, prec in (("fp64", I.IPCS_FP64), ("mixed", I.IPCS_MIXED)):
+        p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
+                                  tol_corr=w["tol"], tol_ir=1e-10, precision=prec)
+        r = I.Run(m, p, stream=torch.cuda.Stream())
+        r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+        runs[name] = r
+    for _ in range(warmup):
+        for r in runs.values():
+            r.advance(1)
+    lat = {k: [] for k in runs}
+    ph = {k: [] for k in runs}
+    it_p = {k: [] for k in runs}
+    du, dp = [], []
+    for step in range(steps):
+        for name, r in runs.items():
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat[name].append(time.perf_counter() - t0)
+            ph[name].append(st["ms"])
+            it_p[name].append(st["it_p"])
+        if step in (0, steps // 2, steps - 1):
+            U64, U32 = runs["fp64"].velocity(), runs["mixed"].velocity()
+            P64, P32 = runs["fp64"].pressure(), runs["mixed"].pressure()
+            du.append(float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)))
+            dp.append(float(np.linalg.norm(P32 - P64) / np.linalg.norm(P64)))
+    out = {"workload": "c4: 3D P2-P1 IPCS, unit cube 64^3 (1572864 tets), Beltrami, dt=1e-3, "
+                       "tol=1e-12 (mixed: refinement of the Poisson solve to 1e-10)",
+           "dofs": ndof, "steps": steps, "warmup": warmup,
+           "rel_l2_diff_mixed_vs_fp64_u": du, "rel_l2_diff_mixed_vs_fp64_p": dp,
+           "diff_steps": [0, steps // 2, steps - 1]}
+    for name, r in runs.items():
+        vb = 4 if name == "mixed" else 8
+        tot = float(np.sum(lat[name]))
+        a = np.array(ph[name])
+        r.kernel_timing((1 << I.IPCS_NKERNEL) - 1)
+        r.advance(2)
+        torch.cuda.synchronize()
+        kms, kcnt = r.kernel_times()
+        r.kernel_timing(0)
+        kern = {}
+        for kname in ("bicg_spmv", "bicg_spmv_t", "pcg_fused_p", "asm_conv", "asm_sum"):
+            kid = KERNELS[kname][0]
+            if kcnt[kid] == 0:
+                continue
+            us = 1000.0 * kms[kid] / kcnt[kid]
+            ub = unit_bytes(kname, c, 3, vb)
+            b = ub if ub is not None else kernel_bytes(kname, c, 3, vb)
+            kern[kname] = {"us_per_launch": us, "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
+                           "frac_of_hbm_peak": b / (us * 1e-6) / 1e9 / PEAK_HBM_GBS,
+                           "launches_per_step": kcnt[kid] / 2.0}
+        out[name] = {"value": ndof * steps / tot, "ms_per_step": 1000.0 * tot / steps,
+                     "p50_step_ms": 1000.0 * float(np.percentile(lat[name], 50)),
+                     "p99_step_ms": 1000.0 * float(np.percentile(lat[name], 99)),
+                     "phase_ms_median": {k: float(np.median(a[:, i])) for i, k in
+                                         enumerate(("asm", "momentum", "pressure", "correction"))},
+                     "pressure_iterations_median": float(np.median(it_p[name])),
+                     "kernels": kern}
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    del runs
+    return out
 
 
 def main():
@@ -473,7 +688,15 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats -f csv run and exit")
     ap.add_argument("--pmc-command", default="")
+    ap.add_argument("--counters-summary", nargs="+", metavar="DIR",
+                    help="summarize rocprofv3 --pmc runs of one kernel (see --counters-kernel) "
+                         "and exit (no GPU use)")
+    ap.add_argument("--counters-kernel", nargs=2, metavar=("NAME", "REGEX"))
     args = ap.parse_args()
+    if args.counters_summary:
+        counters_summary(args.counters_summary, args.counters_kernel[1], args.counters_kernel[0],
+                         args.workload, args.pmc_command)
+        return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.workload, args.pmc_command)
         return
@@ -543,13 +766,25 @@ def main():
     roof = None
     if kern:
         dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-        roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBps"], "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": kern[dom]["GBps"] / PEAK_HBM_GBS,
+        vb = 4 if mixed else 8
+        ub = unit_bytes(dom, c, dim, vb)
+        us = kern[dom]["us_per_launch"]
+        b = ub if ub is not None else kern[dom]["bytes"]
+        ach = b / (us * 1e-6) / 1e9
+        rp = rocprof_avg_us(dom, args.workload)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                 "traffic": measured_traffic(dom, args.workload),
-                "algorithmic_bytes_per_launch": kern[dom]["bytes"],
-                "us_per_launch": kern[dom]["us_per_launch"]}
+                "algorithmic_bytes_per_launch": b,
+                "bytes_model": "unit" if ub is not None else "kernel",
+                "kernel_bytes_per_launch": kern[dom]["bytes"],
+                "us_per_launch": us,
+                "rocprof_us_per_launch": rp,
+                "frac_at_rocprof_us": (b / (rp * 1e-6) / 1e9 / PEAK_HBM_GBS) if rp else None}
 
+    log(f"timed region done ({steps} steps), kernel timing done")
     micro = microbench(r, torch, I, c, dim, 4 if mixed else 8, p3)
+    log("microbenchmarks done")
     ph = np.array([s["ms"] for s in stats])
     out = {
         "metric": "P2-P1 IPCS DOF-steps/s & HBM GB/s vs FP64 plain; p50/p99 step latency",
@@ -593,12 +828,18 @@ def main():
         "microbench": micro,
     }
     if not args.no_forms and not mixed and not p3:
-        out["forms"] = {"mixed": mixed_form(w, args.form_steps, torch, I),
-                        "schemes": scheme_forms(w, args.form_steps, torch, I),
-                        "serving": serving_form(torch, I)}
-        if w["dim"] == 2:
-            out["forms"]["pairs"] = pair_forms(w, args.form_steps, torch, I)
-            out["forms"]["seeds"] = seed_forms(w, 20, torch, I)
+        out["forms"] = {}
+        for name, fn in (("mixed", lambda: mixed_form(w, args.form_steps, torch, I)),
+                         ("schemes", lambda: scheme_forms(w, args.form_steps, torch, I)),
+                         ("serving", lambda: serving_form(torch, I)),
+                         ("c4", lambda: c4_form(torch, I)),
+                         ("pairs", lambda: pair_forms(w, args.form_steps, torch, I)),
+                         ("seeds", lambda: seed_forms(w, 20, torch, I))):
+            if name in ("pairs", "seeds") and w["dim"] != 2:
+                continue
+            out["forms"][name] = fn()
+            torch.cuda.empty_cache()
+            log(f"form {name} done")
     if roof is not None:
         # the measured device copy rate beside the published peak
         roof["copy_GBps"] = copy_peak(torch)
@@ -610,6 +851,7 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        log("cpu baseline done")
     print(json.dumps(out))
 
 

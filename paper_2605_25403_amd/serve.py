@@ -11,10 +11,22 @@ within `max_slots` and their summed HBM footprint (each run's workspace, from
 steps are done and its workspace is released, so that waiting requests take
 its place in the next round.
 
+Lanes. A round of one batch lasts as long as its slowest run, so a small
+request batched with the largest meshes would wait for them at every step.
+The loop therefore serves requests in lanes, by mesh size: each lane has its
+own stream and host thread and batches only its own size class, so the rounds
+of small runs are not paced by the large ones, and the lanes' launches
+overlap on the GPU. Admission is shared: one slot cap and one HBM budget over
+all lanes, each lane admitting its own requests in arrival order. A run's
+result does not depend on what it is batched with, or on the stream, so it is
+the same alone and in the mix.
+
 Per-step latency of a request is the time between two consecutive completions
 of its steps (the first is counted from its admission); the report gives
-their p50 and p99 beside the aggregate DOF-steps/s and the queueing delays.
+their p50 and p99, overall and per mesh size, beside the aggregate
+DOF-steps/s and the queueing delays.
 """
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -66,7 +78,10 @@ def admit(queue, now, active_count, active_bytes, footprint_of, max_slots, hbm_b
 
 class Server:
     def __init__(self, dim=2, precision=None, max_slots=64, hbm_budget=200 << 30, tol=1e-12,
-                 tol_ir=1e-10, stream=None, poisson_part_rows=0):
+                 tol_ir=1e-10, stream=None, poisson_part_rows=0, lanes=None):
+        """lanes: tuple of tuples of mesh sizes, one lane per tuple (each with
+        its own stream and host thread); None: one lane for every size (on
+        `stream` if given)."""
         import torch
         from paper_2605_25403_amd import ipcs as I
         if dim != 2:
@@ -76,13 +91,16 @@ class Server:
         self.max_slots, self.hbm_budget = max_slots, hbm_budget
         self.tol, self.tol_ir = tol, tol_ir
         self.part_rows = poisson_part_rows
+        self.lanes = tuple(tuple(l) for l in lanes) if lanes else None
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self._meshes = {}
+        self._lock = threading.Lock()
 
     def mesh(self, n):
-        if n not in self._meshes:
-            self._meshes[n] = self.I.Mesh.unit_square(n)
-        return self._meshes[n]
+        with self._lock:
+            if n not in self._meshes:
+                self._meshes[n] = self.I.Mesh.unit_square(n)
+            return self._meshes[n]
 
     def params(self, req):
         return self.I.ipcs_params_default(nu=req.nu, dt=req.dt, precision=self.precision,
@@ -92,70 +110,63 @@ class Server:
     def footprint(self, req):
         return self.I.ipcs_run_workspace_bytes(self.mesh(req.n).h, self.params(req))
 
-    def start_run(self, req):
-        r = self.I.Run(self.mesh(req.n), self.params(req), stream=self.stream)
+    def start_run(self, req, stream=None):
+        r = self.I.Run(self.mesh(req.n), self.params(req),
+                       stream=self.stream if stream is None else stream)
         r.set_builtin(self.I.IPCS_SOL_TAYLOR_GREEN_2D, (req.k,))
         return r
 
-    def serve(self, requests, keep_fields=False, clock=time.perf_counter):
-        """Runs the whole stream; returns a report dict (and the final fields
-        per request id when keep_fields)."""
-        I = self.I
+    def serve(self, requests, keep_fields=False, clock=time.perf_counter, keep_ids=None):
+        """Runs the whole stream; returns a report dict and the results per
+        request id (with the final fields when keep_fields, or for the ids in
+        keep_ids)."""
         queue = sorted(requests, key=lambda q: (q.t_arrive, q.id))
-        active, results = [], {}
-        dof_steps, rounds, max_active, fails = 0, 0, 0, 0
+        if self.lanes is None:
+            lanes = [(None, queue, self.stream)]
+        else:
+            sizes = {q.n for q in queue}
+            missing = sizes - {n for l in self.lanes for n in l}
+            if missing:
+                raise ValueError(f"no lane serves mesh sizes {sorted(missing)}")
+            lanes = [(l, [q for q in queue if q.n in l], self.torch.cuda.Stream())
+                     for l in self.lanes]
+        keep = (lambda q: True) if keep_fields else (
+            (lambda q: q.id in keep_ids) if keep_ids else (lambda q: False))
+        shared = {"slots": 0, "bytes": 0, "max_active": 0}
+        results = {}
+        counters = {"dof_steps": 0, "rounds": 0, "fails": 0}
+        errors = []
         t0 = clock()
-        while queue or active:
-            now = clock() - t0
-            k = admit(queue, now, len(active), sum(a.footprint for a in active),
-                      self.footprint, self.max_slots, self.hbm_budget)
-            for req in queue[:k]:
-                run = self.start_run(req)
-                ta = clock() - t0
-                active.append(Active(req, run, self.footprint(req), ta, t_last=ta))
-            del queue[:k]
-            if not active:
-                # nothing to do until the next arrival
-                time.sleep(max(0.0, queue[0].t_arrive - (clock() - t0)))
-                continue
-            max_active = max(max_active, len(active))
-            rc, stats = I.ipcs_batch_step([a.run.h for a in active], self.stream.cuda_stream)
-            tdone = clock() - t0
-            rounds += 1
-            keep = []
-            for a, st in zip(active, stats):
-                if st["status"] != I.IPCS_OK:
-                    fails += 1
-                    results[a.req.id] = dict(status=st["status"], t_admit=a.t_admit,
-                                             t_arrive=a.req.t_arrive, lat=a.lat)
-                    continue
-                a.lat.append(tdone - a.t_last)
-                a.t_last = tdone
-                a.done += 1
-                dof_steps += 2 * (2 * a.req.n + 1) ** 2 + (a.req.n + 1) ** 2
-                if a.done == a.req.steps:
-                    res = dict(status=0, t_arrive=a.req.t_arrive, t_admit=a.t_admit,
-                               t_done=tdone, lat=a.lat, n=a.req.n)
-                    if keep_fields:
-                        res["U"], res["P"] = a.run.velocity(), a.run.pressure()
-                    results[a.req.id] = res
-                    del a.run   # releases the workspace
-                else:
-                    keep.append(a)
-            active = keep
+        threads = [threading.Thread(target=self._lane, args=(lq, st, t0, clock, shared, results,
+                                                             counters, keep, errors))
+                   for _, lq, st in lanes]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        if errors:
+            raise errors[0]
         wall = clock() - t0
-        lat = np.concatenate([np.asarray(r["lat"]) for r in results.values() if r["lat"]])
-        qd = np.array([r["t_admit"] - r["t_arrive"] for r in results.values()])
-        e2e = np.array([r["t_done"] - r["t_arrive"] for r in results.values() if "t_done" in r])
+        done = list(results.values())
+        lat = np.concatenate([np.asarray(r["lat"]) for r in done if r["lat"]])
+        qd = np.array([r["t_admit"] - r["t_arrive"] for r in done])
+        e2e = np.array([r["t_done"] - r["t_arrive"] for r in done if "t_done" in r])
         first = min(q.t_arrive for q in requests)
+        by_n = {}
+        for n in sorted({r["n"] for r in done}):
+            ln = np.concatenate([np.asarray(r["lat"]) for r in done if r["n"] == n and r["lat"]])
+            by_n[str(n)] = {"p50_step_ms": 1000 * float(np.percentile(ln, 50)),
+                            "p99_step_ms": 1000 * float(np.percentile(ln, 99))}
         report = {
-            "requests": len(requests), "failed": fails, "rounds": rounds,
-            "max_active": max_active, "max_slots": self.max_slots,
+            "requests": len(requests), "failed": counters["fails"],
+            "rounds": counters["rounds"], "lanes": [list(l) for l, _, _ in lanes if l] or None,
+            "max_active": shared["max_active"], "max_slots": self.max_slots,
             "hbm_budget_bytes": self.hbm_budget,
-            "dof_steps": dof_steps, "wall_s": wall,
-            "dof_steps_per_s": dof_steps / max(wall - first, 1e-9),
+            "dof_steps": counters["dof_steps"], "wall_s": wall,
+            "dof_steps_per_s": counters["dof_steps"] / max(wall - first, 1e-9),
             "p50_step_ms": 1000 * float(np.percentile(lat, 50)),
             "p99_step_ms": 1000 * float(np.percentile(lat, 99)),
+            "step_ms_by_n": by_n,
             "queue_delay_p50_ms": 1000 * float(np.percentile(qd, 50)),
             "queue_delay_p99_ms": 1000 * float(np.percentile(qd, 99)),
             # arrival to the end of the last step, completed requests
@@ -163,6 +174,75 @@ class Server:
             "end_to_end_p99_ms": 1000 * float(np.percentile(e2e, 99)) if e2e.size else None,
         }
         return report, results
+
+    def _lane(self, queue, stream, t0, clock, shared, results, counters, keep, errors):
+        """One lane: admits its own requests (arrival order, shared limits),
+        steps its resident runs together on its stream, one step per round."""
+        I = self.I
+        active = []
+        try:
+            while queue or active:
+                now = clock() - t0
+                with self._lock:
+                    k = admit(queue, now, shared["slots"], shared["bytes"], self.footprint_nolock,
+                              self.max_slots, self.hbm_budget)
+                    adm = queue[:k]
+                    for req in adm:
+                        shared["slots"] += 1
+                        shared["bytes"] += self.footprint_nolock(req)
+                    shared["max_active"] = max(shared["max_active"], shared["slots"])
+                for req in adm:
+                    run = self.start_run(req, stream)
+                    ta = clock() - t0
+                    active.append(Active(req, run, self.footprint(req), ta, t_last=ta))
+                del queue[:k]
+                if not active:
+                    # nothing to do until the next arrival (or until another
+                    # lane frees room)
+                    wait = queue[0].t_arrive - (clock() - t0)
+                    time.sleep(max(0.0005, wait) if wait > 0 else 0.0005)
+                    continue
+                rc, stats = I.ipcs_batch_step([a.run.h for a in active], stream.cuda_stream)
+                tdone = clock() - t0
+                stay, freed = [], []
+                for a, st in zip(active, stats):
+                    if st["status"] != I.IPCS_OK:
+                        results[a.req.id] = dict(status=st["status"], t_admit=a.t_admit,
+                                                 t_arrive=a.req.t_arrive, lat=a.lat, n=a.req.n)
+                        freed.append(a)
+                        continue
+                    a.lat.append(tdone - a.t_last)
+                    a.t_last = tdone
+                    a.done += 1
+                    if a.done == a.req.steps:
+                        res = dict(status=0, t_arrive=a.req.t_arrive, t_admit=a.t_admit,
+                                   t_done=tdone, lat=a.lat, n=a.req.n)
+                        if keep(a.req):
+                            res["U"], res["P"] = a.run.velocity(), a.run.pressure()
+                        results[a.req.id] = res
+                        freed.append(a)
+                    else:
+                        stay.append(a)
+                with self._lock:
+                    counters["rounds"] += 1
+                    counters["dof_steps"] += sum(2 * (2 * a.req.n + 1) ** 2 + (a.req.n + 1) ** 2
+                                                 for a, st in zip(active, stats)
+                                                 if st["status"] == I.IPCS_OK)
+                    counters["fails"] += sum(st["status"] != I.IPCS_OK for st in stats)
+                    for a in freed:
+                        shared["slots"] -= 1
+                        shared["bytes"] -= a.footprint
+                for a in freed:
+                    del a.run   # releases the workspace
+                active = stay
+        except Exception as e:   # reported by serve() after every lane has ended
+            errors.append(e)
+
+    def footprint_nolock(self, req):
+        n = req.n
+        if n not in self._meshes:
+            self._meshes[n] = self.I.Mesh.unit_square(n)
+        return self.I.ipcs_run_workspace_bytes(self._meshes[n].h, self.params(req))
 
 
 def requests_from(stream_spec):

@@ -77,6 +77,29 @@ def test_serving_loop_small_stream_equals_alone():
         assert len(res[q.id]["lat"]) == q.steps
 
 
+def test_serving_lanes_by_size_equal_alone():
+    """Lanes by mesh size, each with its own stream and host thread, sharing
+    the slot cap: every result is bitwise the result alone, and the report
+    gives per-size latencies."""
+    torch, I = require_gpu()
+    print("serving lanes", flush=True)
+    from paper_2605_25403_amd.serve import Request, Server
+    reqs = [Request(id=i, t_arrive=0.001 * i, n=n, k=k, nu=nu, steps=2 + (i % 4), dt=dt)
+            for i, (n, k, nu, dt) in enumerate(CASES * 3)]
+    srv = Server(max_slots=4, hbm_budget=1 << 34, lanes=((8, 12), (16, 24)))
+    report, res = srv.serve(reqs, keep_fields=True)
+    print(report, flush=True)
+    assert report["failed"] == 0 and len(res) == len(reqs)
+    assert report["max_active"] <= 4
+    assert set(report["step_ms_by_n"]) == {"8", "12", "16", "24"}
+    for q in reqs:
+        r = new_run(I, q.n, q.k, q.nu, q.dt, I.IPCS_MIXED)
+        r.advance(q.steps)
+        np.testing.assert_array_equal(res[q.id]["U"], r.velocity())
+        np.testing.assert_array_equal(res[q.id]["P"], r.pressure())
+        assert len(res[q.id]["lat"]) == q.steps
+
+
 def test_serving_admission_by_footprint_queues_requests():
     torch, I = require_gpu()
     print("serving admission", flush=True)
