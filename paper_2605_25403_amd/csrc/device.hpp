@@ -136,7 +136,21 @@ struct RowAsm {
   int32_t pair;               // IPCS_PAIR_P2P1 (0) or IPCS_PAIR_P3P2 (2D)
   const int32_t* c2v;         // [nc][nv_stride]; first dim+1 entries: the vertices
   int32_t nv_stride;          //   (the pressure cell table; its vertices come first)
+  // row-owner kernels: runs of xcd_chunk consecutive row blocks are dealt to
+  // the 8 XCDs in turn (0: blocks in order), so that rows that share cells
+  // are assembled through one XCD's L2
+  int32_t xcd_chunk;
 };
+
+// Row block of a row-owner launch for hardware block b of nb: with chunk c > 0,
+// XCD x (= b mod 8) runs blocks x c .. x c + c - 1, then 8 c + x c .. and so
+// on; the tail past the last full round of 8 c blocks stays in order.
+__device__ __forceinline__ int xcd_block(int b, int nb, int c) {
+  if (c <= 0) return b;
+  const int round = 8 * c;
+  if (b >= nb / round * round) return b;
+  return b / round * round + (b & 7) * c + (b >> 3) % c;
+}
 
 // Manufactured solution on the device
 struct Builtin {

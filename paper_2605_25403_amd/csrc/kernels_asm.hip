@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   constexpr int NOUT = Op::NOUT, NCOL = Op::NCOL;
-  const int r0 = blockIdx.x * blockDim.x;
+  const int r0 = xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk) * blockDim.x;
   const int s0 = r0 >> 6;
   const int s1 = min((r0 + (int)blockDim.x + 63) >> 6, (a.nrows + 63) >> 6);
   const int base = a.sptr[s0];
@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(256) k_asm_local(RowAsm a, const R* loc) {
   constexpr int NL = P2<D>::NLOC;
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
-  const int r0 = blockIdx.x * blockDim.x;
+  const int r0 = xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk) * blockDim.x;
   const int s0 = r0 >> 6;
   const int s1 = min((r0 + (int)blockDim.x + 63) >> 6, (a.nrows + 63) >> 6);
   const int base = a.sptr[s0];

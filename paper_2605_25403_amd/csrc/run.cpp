@@ -387,6 +387,11 @@ void Run::sizes_from_mesh() {
   choose_poisson_form();
 }
 
+// Row blocks of the convection assembly (row-owner and local-sum passes) are
+// dealt to the XCDs in runs of this many: consecutive rows share cells and
+// velocity values, which one XCD's L2 then serves
+constexpr int kAsmXcdChunk = 8;
+
 // Largest own + halo row count of a part the fused Poisson CG keeps in LDS
 // (8 bytes each, under 64 KiB with the kernel's static reduction space).
 constexpr int kFcgLocalMax = 8000;
@@ -951,7 +956,7 @@ void Run::asm_phase() {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1};
+             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1, kAsmXcdChunk};
   has_F = false;
   if (f_cb) {
     const int nq = cell_nq();
@@ -1171,7 +1176,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
   }
   const Mesh& m = *mesh;
   RowAsm a22{(int32_t)n2, sp22, inc2p, inc2, s22, m.s22.stride, c2d, m.nloc2, X,
-             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1};
+             {E, nullptr, nullptr}, m.pair, c2v, m.nloc1, kAsmXcdChunk};
   auto launch = [&]() {
     switch (kernel) {
       case IPCS_KERNEL_PCG_SPMV_P: pcg_spmv_only(stream, set_p.L); break;
