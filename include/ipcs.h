@@ -268,9 +268,14 @@ enum {
   IPCS_SOL_BELTRAMI_3D = 3,     /* Ethier-Steinman, prm = {a, d}; f = 0           */
   IPCS_SOL_POLY_STEADY_2D = 4,  /* u=(y^2,x^2), p=x+y-1                           */
   IPCS_SOL_POLY_STEADY_3D = 5,  /* u=(y^2+z^2,z^2+x^2,x^2+y^2), p=x+y+z-3/2      */
-  IPCS_SOL_POLY_CUBIC_2D = 6    /* u=(x^3+2x^2y, -3x^2y-2xy^2), p=x^2-y^2+xy-1/4,
+  IPCS_SOL_POLY_CUBIC_2D = 6,   /* u=(x^3+2x^2y, -3x^2y-2xy^2), p=x^2-y^2+xy-1/4,
                                  * steady, f = (u.grad)u - nu Lap u + grad p: a
                                  * fixed point of the P3-P2 step                 */
+  IPCS_SOL_STEADY_PAPER_2D = 7  /* the steady example of Section 4.2:
+                                 * u = 10x^2(x-1)^2 y(y-1)(2y-1),
+                                 * v = -10x(x-1)(2x-1) y^2(y-1)^2,
+                                 * p = 10(2x-1)(2y-1), f = -nu Lap u + (u.grad)u
+                                 * + grad p (steady solver only)                 */
 };
 /* Closed-form manufactured solution evaluated on the device: Dirichlet data,
  * forcing and the initial state U = I_h u(t), P = I_h p(t) shifted to zero
@@ -409,6 +414,69 @@ int ipcs_poisson_partition(ipcs_run r, int32_t* rows_max, int32_t* nparts, int64
                            int32_t* lds_rows);
 
 void ipcs_run_destroy(ipcs_run r);
+
+/* ---------------------------------------------------------------- steady */
+/* The steady Navier-Stokes equations of Section 2.1 (-nu Lap u + (u.grad)u +
+ * grad p = f, div u = 0, u = g on the boundary) with the P2-P1 pair, solved
+ * by Newton's method: the Newton linearization of Section 2.2.1 without its
+ * time-derivative term, run as in Section 4.2 (steps until the relative
+ * change falls below a tolerance, 1e-10 in at most 10 steps there). Each
+ * step solves the monolithic saddle-point system for the increment,
+ *   [[nu K + C(U) + N(U), G], [D, 0]] (dU, dP) = (F - (nu K + C(U)) U - G P, -D U),
+ * N_ce = (phi_j d_e u_c, phi_i), boundary velocity rows and columns
+ * eliminated (the iterates carry the Dirichlet data), by flexible GMRES with
+ * the block upper-triangular preconditioner [[A, G], [0, -(1/nu) diag(Mp 1)]]:
+ * A, the velocity block, applied by a loose inner Jacobi-BiCGStab solve. The
+ * pressure is fixed by zero integral mean after each step. The start is the
+ * Dirichlet data on the boundary and zero elsewhere, P = 0. All device work
+ * runs in the caller's workspace on the given stream. */
+typedef struct ipcs_steady_s* ipcs_steady;
+typedef struct {
+  double nu;            /* kinematic viscosity                                 */
+  double tol;           /* Newton: stop when ||(dU,dP)||_2 <= tol ||(U,P)||_2  */
+  int32_t maxit;        /* Newton steps                                        */
+  int32_t restart;      /* FGMRES basis length (2..512)                        */
+  double lin_tol;       /* FGMRES relative residual of each Newton system      */
+  int32_t lin_maxit;    /* FGMRES iterations per Newton system                 */
+  int32_t inner_maxit;  /* inner BiCGStab iterations per preconditioner use   */
+  double inner_tol;     /* inner BiCGStab relative tolerance                   */
+} ipcs_steady_params;
+/* nu = 1, tol = 1e-10, maxit = 10 (Section 4.2), restart 60, lin_tol 1e-12,
+ * lin_maxit 3000, inner_maxit 2000, inner_tol 1e-2. */
+void ipcs_steady_params_default(ipcs_steady_params* p);
+typedef struct {
+  int32_t status;       /* IPCS_OK or the failure                              */
+  int32_t newton_steps;
+  int32_t lin_it;       /* FGMRES iterations, summed over the steps            */
+  int32_t inner_it;     /* inner BiCGStab iterations, summed                   */
+  double rel_change;    /* ||(dU,dP)|| / ||(U,P)|| of the last step            */
+  double res0, res;     /* ||residual|| at the first and at the last step      */
+  float ms;             /* device time of the steps (stream events)            */
+  int32_t reserved;
+} ipcs_steady_stats;
+/* Device workspace of a steady solve on this mesh (P2-P1 pair). */
+int ipcs_steady_workspace_bytes(ipcs_mesh m, const ipcs_steady_params* p, int64_t* bytes);
+int ipcs_steady_create(ipcs_mesh m, const ipcs_steady_params* p, void* dev_ws,
+                       int64_t ws_bytes, void* hip_stream, ipcs_steady* out);
+/* Closed-form data on the device (IPCS_SOL_STEADY_PAPER_2D,
+ * IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D): f and g; resets the
+ * iterate to the start above. */
+int ipcs_steady_set_builtin(ipcs_steady s, int32_t kind, const double* prm, int32_t nprm);
+/* Iterate given by the caller: u[dim*N2] (Dirichlet data on the boundary
+ * nodes), p[N1], interface numbering. */
+int ipcs_steady_set_state(ipcs_steady s, const double* u, const double* p);
+/* One Newton step; stats (may be NULL) accumulate. */
+int ipcs_steady_step(ipcs_steady s, ipcs_steady_stats* stats);
+/* Newton steps until the relative change is <= tol (IPCS_E_NOT_CONVERGED
+ * after maxit steps). */
+int ipcs_steady_solve(ipcs_steady s, ipcs_steady_stats* stats);
+int ipcs_steady_get_velocity(ipcs_steady s, double* u, int64_t cap);   /* [dim*N2] */
+int ipcs_steady_get_pressure(ipcs_steady s, double* p, int64_t cap);   /* [N1]     */
+/* The last step's residual (right-hand side) or increment,
+ * [dim*N2 + N1] in the interface numbering. */
+enum { IPCS_STEADY_RESIDUAL = 0, IPCS_STEADY_INCREMENT = 1 };
+int ipcs_steady_get_vector(ipcs_steady s, int32_t which, double* out, int64_t cap);
+void ipcs_steady_destroy(ipcs_steady s);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,7 @@ Here it is solved for the increment (du, dp) = (u^{k+1} - u^k, p^{k+1} - p^k),
 which is the same iterate: J(u^k) (dU, dP) = R(u^k, p^k) with, per velocity
 component c and for velocity rows whose node is not on the boundary,
     R_c = F_c - nu K U_c - C(U) U_c - G_c P          (-(p, div v) = (grad p, v))
-    R_p = - sum_c D_c U_c
+    R_p = - sum_c D_c U_c   (projected to zero sum: the system is singular)
     J = [[nu K + C(U) + N(U), G], [D, 0]],
     N_{ce, ij} = sum_q w |J| phi_i phi_j d_e u_c(x_q)   (the term ((du . grad) u^k, v)),
 C(U) the convection matrix of fem.py, G_c = (phi_i, d_c psi_k),
@@ -78,7 +78,10 @@ class SteadyNewton:
                        for c in range(S.dim)])
         Ru[:, S.bmask_u] = 0.0
         Rp = -sum(self.D[c] @ U[c] for c in range(S.dim))
-        return Ru, Rp
+        # the Newton matrix is singular (constant pressure): its pressure
+        # rows' right-hand side is projected to zero sum, as the Poisson
+        # right-hand side of the IPCS step is
+        return Ru, Rp - Rp.mean()
 
     def jacobian(self):
         """The Newton matrix, boundary velocity rows and columns eliminated,

@@ -18,9 +18,9 @@ OBJ = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libipcs.so")
 
-SOURCES = ["mesh.cpp", "parts.cpp", "run.cpp", "batch.cpp", "capi.cpp", "scratch.hip", "kernels_asm.hip",
-           "kernels_krylov.hip", "kernels_fcg.hip",
-           "kernels_fields.hip"]
+SOURCES = ["mesh.cpp", "parts.cpp", "run.cpp", "batch.cpp", "capi.cpp", "steady.cpp",
+           "scratch.hip", "kernels_asm.hip", "kernels_krylov.hip", "kernels_fcg.hip",
+           "kernels_fields.hip", "kernels_steady.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("IPCS_CXX", "/opt/rocm/llvm/bin/clang++")

@@ -7,6 +7,17 @@
 //   Beltrami 3D     : Ethier & Steinman (1994), parameters a, d; f = 0.
 //   Polynomial      : u = (y^2, x^2), p = x + y - 1 (2D) and
 //                     u = (y^2+z^2, z^2+x^2, x^2+y^2), p = x+y+z-3/2 (3D).
+//   Steady example  : Section 4.2, u = 10 x^2 (x-1)^2 y (y-1)(2y-1),
+//                     v = -10 x (x-1)(2x-1) y^2 (y-1)^2, p = 10 (2x-1)(2y-1),
+//                     f = -nu Lap u + (u.grad)u + grad p (steady).
+// The steady example's velocity is the curl of 5 a(x) a(y) with
+// a(s) = s^2 (s-1)^2: u = 5 a(x) a'(y), v = -5 a'(x) a(y).
+struct SteadyPoly {
+  __host__ __device__ static double a(double s) { return s * s * (s - 1.0) * (s - 1.0); }
+  __host__ __device__ static double a1(double s) { return ((4.0 * s - 6.0) * s + 2.0) * s; }
+  __host__ __device__ static double a2(double s) { return (12.0 * s - 12.0) * s + 2.0; }
+  __host__ __device__ static double a3(double s) { return 24.0 * s - 12.0; }
+};
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -44,6 +55,10 @@ __host__ __device__ inline void builtin_velocity(const Builtin& bi, const double
         u[0] = X * X * X + 2.0 * X * X * Y;
         u[1] = -3.0 * X * X * Y - 2.0 * X * Y * Y;
         return;
+      case IPCS_SOL_STEADY_PAPER_2D:
+        u[0] = 5.0 * SteadyPoly::a(X) * SteadyPoly::a1(Y);
+        u[1] = -5.0 * SteadyPoly::a1(X) * SteadyPoly::a(Y);
+        return;
     }
     u[0] = u[1] = 0.0;
   } else {
@@ -78,6 +93,7 @@ __host__ __device__ inline double builtin_pressure(const Builtin& bi, const doub
       case IPCS_SOL_JOHN_2D: return 20.0 * sin(t) * (X * X * Y - 1.0 / 6.0);
       case IPCS_SOL_POLY_STEADY_2D: return X + Y - 1.0;
       case IPCS_SOL_POLY_CUBIC_2D: return X * X - Y * Y + X * Y - 0.25;
+      case IPCS_SOL_STEADY_PAPER_2D: return 10.0 * (2.0 * X - 1.0) * (2.0 * Y - 1.0);
     }
     return 0.0;
   } else {
@@ -136,6 +152,17 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
       f[1] = u1 * u2x + u2 * u2y - nu * (-4.0 * X - 6.0 * Y) + (X - 2.0 * Y);
       return;
     }
+    if (bi.kind == IPCS_SOL_STEADY_PAPER_2D) {
+      using S = SteadyPoly;
+      const double u1 = 5.0 * S::a(X) * S::a1(Y), u2 = -5.0 * S::a1(X) * S::a(Y);
+      const double u1x = 5.0 * S::a1(X) * S::a1(Y), u1y = 5.0 * S::a(X) * S::a2(Y);
+      const double u2x = -5.0 * S::a2(X) * S::a(Y), u2y = -u1x;
+      const double l1 = 5.0 * (S::a2(X) * S::a1(Y) + S::a(X) * S::a3(Y));
+      const double l2 = -5.0 * (S::a3(X) * S::a(Y) + S::a1(X) * S::a2(Y));
+      f[0] = -nu * l1 + u1 * u1x + u2 * u1y + 20.0 * (2.0 * Y - 1.0);
+      f[1] = -nu * l2 + u1 * u2x + u2 * u2y + 20.0 * (2.0 * X - 1.0);
+      return;
+    }
     f[0] = f[1] = 0.0;
   } else {
     const double X = x[0], Y = x[1], Z = x[2];
@@ -153,7 +180,8 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
 
 inline bool builtin_has_force(int kind) {
   return kind == IPCS_SOL_JOHN_2D || kind == IPCS_SOL_POLY_STEADY_2D ||
-         kind == IPCS_SOL_POLY_STEADY_3D || kind == IPCS_SOL_POLY_CUBIC_2D;
+         kind == IPCS_SOL_POLY_STEADY_3D || kind == IPCS_SOL_POLY_CUBIC_2D ||
+         kind == IPCS_SOL_STEADY_PAPER_2D;
 }
 
 }  // namespace ipcs

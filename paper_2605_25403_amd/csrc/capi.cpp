@@ -13,12 +13,16 @@
 #include "mesh.hpp"
 #include "rules.hpp"
 #include "run.hpp"
+#include "steady.hpp"
 
 struct ipcs_mesh_s {
   std::shared_ptr<ipcs::Mesh> m;
 };
 struct ipcs_run_s {
   ipcs::Run r;
+};
+struct ipcs_steady_s {
+  ipcs::Steady s;
 };
 
 namespace {
@@ -56,6 +60,11 @@ const ipcs::Mesh& M(ipcs_mesh m) {
 ipcs::Run& R(ipcs_run r) {
   need(r != nullptr, "null run handle");
   return r->r;
+}
+
+ipcs::Steady& S(ipcs_steady s) {
+  need(s != nullptr, "null steady handle");
+  return s->s;
 }
 
 int wrap_mesh(ipcs::Mesh* raw, ipcs_mesh* out) {
@@ -581,5 +590,106 @@ int ipcs_poisson_partition(ipcs_run r, int32_t* rows_max, int32_t* nparts, int64
 }
 
 void ipcs_run_destroy(ipcs_run r) { delete r; }
+
+void ipcs_steady_params_default(ipcs_steady_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nu = 1.0;
+  p->tol = 1e-10;
+  p->maxit = 10;
+  p->restart = 60;
+  p->lin_tol = 1e-12;
+  p->lin_maxit = 3000;
+  p->inner_maxit = 2000;
+  p->inner_tol = 1e-2;
+}
+
+int ipcs_steady_workspace_bytes(ipcs_mesh m, const ipcs_steady_params* p, int64_t* bytes) {
+  return guard([&]() -> int {
+    need(p != nullptr && bytes != nullptr, "null argument");
+    (void)M(m);
+    ipcs::Steady tmp;
+    *bytes = tmp.measure(m->m, *p);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_steady_create(ipcs_mesh m, const ipcs_steady_params* p, void* dev_ws, int64_t ws_bytes,
+                       void* hip_stream, ipcs_steady* out) {
+  return guard([&]() -> int {
+    need(p != nullptr && out != nullptr, "null argument");
+    (void)M(m);
+    auto h = std::make_unique<ipcs_steady_s>();
+    h->s.create(m->m, *p, dev_ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+    *out = h.release();
+    return IPCS_OK;
+  });
+}
+
+int ipcs_steady_set_builtin(ipcs_steady s, int32_t kind, const double* prm, int32_t nprm) {
+  return guard([&]() -> int {
+    need(nprm >= 0 && (nprm == 0 || prm != nullptr), "bad parameter array");
+    S(s).set_builtin(kind, prm, nprm);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_steady_set_state(ipcs_steady s, const double* u, const double* p) {
+  return guard([&]() -> int {
+    need(u != nullptr && p != nullptr, "null field");
+    ipcs::Steady& st = S(s);
+    std::vector<double> ui((size_t)st.nu_rows);
+    vel_to_internal(*st.run.mesh, st.dim, u, ui.data());
+    st.set_state(ui.data(), p);
+    return IPCS_OK;
+  });
+}
+
+int ipcs_steady_step(ipcs_steady s, ipcs_steady_stats* stats) {
+  return guard([&]() -> int {
+    ipcs::Steady& st = S(s);
+    st.lin_it = st.inner_it = 0;
+    st.newton_step(stats);
+    if (stats) stats->inner_it += st.inner_it;
+    st.to_run();
+    return IPCS_OK;
+  });
+}
+
+int ipcs_steady_solve(ipcs_steady s, ipcs_steady_stats* stats) {
+  return guard([&]() -> int {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    const int rc = S(s).solve(stats);
+    if (stats) stats->status = rc;
+    return rc;
+  });
+}
+
+int ipcs_steady_get_velocity(ipcs_steady s, double* u, int64_t cap) {
+  return guard([&]() -> int {
+    ipcs::Steady& st = S(s);
+    return copy_out_velocity(st.run, st.x, u, cap);
+  });
+}
+
+int ipcs_steady_get_pressure(ipcs_steady s, double* p, int64_t cap) {
+  return guard([&]() -> int {
+    ipcs::Steady& st = S(s);
+    return copy_out(st.run, st.x + st.nu_rows, st.n1, p, cap);
+  });
+}
+
+int ipcs_steady_get_vector(ipcs_steady s, int32_t which, double* out, int64_t cap) {
+  return guard([&]() -> int {
+    ipcs::Steady& st = S(s);
+    need(which == IPCS_STEADY_RESIDUAL || which == IPCS_STEADY_INCREMENT, "unknown vector id");
+    need(out != nullptr && cap >= st.n, "output buffer too small");
+    const double* src = which == IPCS_STEADY_RESIDUAL ? st.R : st.dx;
+    copy_out_velocity(st.run, src, out, cap);
+    return copy_out(st.run, src + st.nu_rows, st.n1, out + st.nu_rows, cap - st.nu_rows);
+  });
+}
+
+void ipcs_steady_destroy(ipcs_steady s) { delete s; }
 
 }  // extern "C"

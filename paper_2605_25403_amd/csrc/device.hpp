@@ -176,6 +176,9 @@ void asm_conv_cells(int dim, bool fp32, hipStream_t s, const RowAsm& a, int64_t 
 void asm_local_sum(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                    const void* buf);
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
+// a.out[0] <- N_ce(U): sum_q w |J| phi_i phi_j d_e u_c (FP64, P2-P1)
+void asm_newton(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds, const double* U,
+                int64_t n2, int c, int e);
 void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds);
 void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w);

@@ -216,6 +216,45 @@ struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi
     }
   }
 };
+// P2 x P2: N_ce = sum_q w |J| phi_i phi_j d_e u_c(x_q), the matrix of the
+// Newton term ((du . grad) u, v) coupling component e of the increment to
+// component c of the equation (steady solver, Newton linearization of
+// Section 2.2.1)
+template <int D, class R>
+struct OpNewton {
+  using real = R;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = P2<D>::NLOC;
+  const double* U;        // [D][n2]
+  int64_t n2;
+  int c, e;
+  __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
+    R Uc[NCOL];
+#pragma unroll
+    for (int m = 0; m < NCOL; ++m) Uc[m] = (R)U[(size_t)c * n2 + dofs[m]];
+#pragma unroll 1
+    for (int q = 0; q < Rule<D>::NQ; ++q) {
+      R gr[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        R s = 0;
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m) s += Uc[m] * T.dphi[q][m][a];
+        gr[a] = s;
+      }
+      R gp[D];
+      phys<D, R>(g, gr, gp);
+      R due = gp[0];
+#pragma unroll
+      for (int b = 1; b < D; ++b) due = (e == b) ? gp[b] : due;
+      const R ci = T.w[q] * g.det * T.phi[q][li] * due;
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) v[0][j] += ci * T.phi[q][j];
+    }
+  }
+};
+
 template <int D, class R>
 struct OpGrad {   // P2 rows x P1 cols: G_c for one component c
   using real = R;
@@ -575,6 +614,12 @@ void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t
               const double* U, int64_t n2, double inv_dt, double cs) {
   if (a.pair == IPCS_PAIR_P3P2) return rows_p3<Op3Conv>(fp32, s, a, bs, lds, U, n2, inv_dt, cs);
   rows_dr<OpConv>(dim, fp32, s, a, bs, lds, U, n2, inv_dt, cs);
+}
+// a.out[0] <- N_ce(U) (P2-P1, FP64; steady solver)
+void asm_newton(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds, const double* U,
+                int64_t n2, int c, int e) {
+  if (a.pair == IPCS_PAIR_P3P2) fail(IPCS_E_INVALID, "the steady solver uses the P2-P1 pair");
+  rows_dr<OpNewton>(dim, false, s, a, bs, lds, U, n2, c, e);
 }
 // a.out[c] <- G_c (one launch per component)
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {

@@ -34,8 +34,6 @@ const Sell& Mesh::sell(int which) const {
   fail(IPCS_E_INVALID, "unknown pattern id " + std::to_string(which));
 }
 
-namespace {
-
 void build_sell(const Pattern& P, Sell& S) {
   S.nrows = P.nrows;
   S.nslices = (P.nrows + 63) / 64;
@@ -64,6 +62,8 @@ void build_sell(const Pattern& P, Sell& S) {
     }
   }
 }
+
+namespace {
 
 inline int edge_a(int dim, int e) { return dim == 2 ? Edges<2>::a(e) : Edges<3>::a(e); }
 inline int edge_b(int dim, int e) { return dim == 2 ? Edges<2>::b(e) : Edges<3>::b(e); }

@@ -123,6 +123,9 @@ struct Mesh {
   mutable std::vector<std::shared_ptr<const PartSell>> parts_cache;
 };
 
+// SELL-64 layout of a CSR pattern (padding repeats a row's last column)
+void build_sell(const Pattern& P, Sell& S);
+
 std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, const double* X,
                                             int dim, int rows_max);
 

@@ -34,6 +34,8 @@ IPCS_SCHEME_IPCS, IPCS_SCHEME_CHORIN = 0, 1
 IPCS_SOL_TAYLOR_GREEN_2D, IPCS_SOL_JOHN_2D, IPCS_SOL_BELTRAMI_3D = 1, 2, 3
 IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D = 4, 5
 IPCS_SOL_POLY_CUBIC_2D = 6
+IPCS_SOL_STEADY_PAPER_2D = 7
+IPCS_STEADY_RESIDUAL, IPCS_STEADY_INCREMENT = 0, 1
 IPCS_PHASE_ASM, IPCS_PHASE_MOMENTUM, IPCS_PHASE_PRESSURE, IPCS_PHASE_CORRECTION = 0, 1, 2, 3
 IPCS_FIELD_U, IPCS_FIELD_P, IPCS_FIELD_USTAR, IPCS_FIELD_DP = 0, 1, 2, 3
 IPCS_FIELD_RHS_MOM, IPCS_FIELD_RHS_P = 4, 5
@@ -85,6 +87,21 @@ class ipcs_step_stats(C.Structure):
                 "ms": [self.ms_asm, self.ms_mom, self.ms_p, self.ms_corr]}
 
 
+class ipcs_steady_params(C.Structure):
+    _fields_ = [("nu", C.c_double), ("tol", C.c_double), ("maxit", C.c_int32),
+                ("restart", C.c_int32), ("lin_tol", C.c_double), ("lin_maxit", C.c_int32),
+                ("inner_maxit", C.c_int32), ("inner_tol", C.c_double)]
+
+
+class ipcs_steady_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("newton_steps", C.c_int32), ("lin_it", C.c_int32),
+                ("inner_it", C.c_int32), ("rel_change", C.c_double), ("res0", C.c_double),
+                ("res", C.c_double), ("ms", C.c_float), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 ipcs_field_fn = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double),
                             C.c_double, C.POINTER(C.c_double))
 
@@ -130,6 +147,19 @@ _SIGS = {
     "ipcs_poisson_partition": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "ipcs_run_destroy": (None, [_P]),
+    "ipcs_steady_params_default": (None, [C.POINTER(ipcs_steady_params)]),
+    "ipcs_steady_workspace_bytes": (C.c_int, [_P, C.POINTER(ipcs_steady_params),
+                                              C.POINTER(C.c_int64)]),
+    "ipcs_steady_create": (C.c_int, [_P, C.POINTER(ipcs_steady_params), _P, C.c_int64, _P,
+                                     C.POINTER(_P)]),
+    "ipcs_steady_set_builtin": (C.c_int, [_P, C.c_int32, _P, C.c_int32]),
+    "ipcs_steady_set_state": (C.c_int, [_P, _P, _P]),
+    "ipcs_steady_step": (C.c_int, [_P, C.POINTER(ipcs_steady_stats)]),
+    "ipcs_steady_solve": (C.c_int, [_P, C.POINTER(ipcs_steady_stats)]),
+    "ipcs_steady_get_velocity": (C.c_int, [_P, _P, C.c_int64]),
+    "ipcs_steady_get_pressure": (C.c_int, [_P, _P, C.c_int64]),
+    "ipcs_steady_get_vector": (C.c_int, [_P, C.c_int32, _P, C.c_int64]),
+    "ipcs_steady_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -410,6 +440,14 @@ def ipcs_run_destroy(r):
     lib.ipcs_run_destroy(r)
 
 
+def ipcs_steady_params_default(**kw):
+    p = ipcs_steady_params()
+    lib.ipcs_steady_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
 # ---------------------------------------------------------------- convenience
 class Mesh:
     """Owns an ipcs_mesh handle."""
@@ -532,6 +570,71 @@ class Run:
         return sp.csr_matrix((val, col, rp), shape=(rows, cols))
 
     def __del__(self, _destroy=lib.ipcs_run_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+class Steady:
+    """Steady Navier-Stokes by Newton's method (ipcs_steady_*), its workspace
+    held as a torch uint8 tensor on the GPU."""
+
+    def __init__(self, mesh, params=None, stream=None, device="cuda", **kw):
+        import torch
+        self.mesh = mesh
+        self.params = params if params is not None else ipcs_steady_params_default(**kw)
+        b = C.c_int64()
+        _check(lib.ipcs_steady_workspace_bytes(mesh.h, C.byref(self.params), C.byref(b)))
+        self.ws_bytes = b.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = _P()
+        _check(lib.ipcs_steady_create(mesh.h, C.byref(self.params), self.ws.data_ptr(),
+                                      self.ws_bytes, self.stream.cuda_stream, C.byref(h)))
+        self.h = h
+        self.dim, self.n1, self.n2 = mesh.counts.dim, mesh.counts.n1, mesh.counts.n2
+
+    def set_builtin(self, kind, prm=()):
+        a = np.ascontiguousarray(prm, dtype=np.float64)
+        _check(lib.ipcs_steady_set_builtin(self.h, kind, _ptr(a) if a.size else None, a.size))
+
+    def set_state(self, U, P):
+        u = np.ascontiguousarray(U, dtype=np.float64).ravel()
+        p = np.ascontiguousarray(P, dtype=np.float64)
+        _check(lib.ipcs_steady_set_state(self.h, _ptr(u), _ptr(p)))
+
+    def step(self):
+        st = ipcs_steady_stats()
+        _check(lib.ipcs_steady_step(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def solve(self):
+        """Newton steps to the tolerance; returns the stats (raises on failure)."""
+        st = ipcs_steady_stats()
+        rc = lib.ipcs_steady_solve(self.h, C.byref(st))
+        if rc != IPCS_OK:
+            err = IpcsError(rc, lib.ipcs_last_error().decode())
+            err.stats = st.as_dict()
+            raise err
+        return st.as_dict()
+
+    def velocity(self):
+        u = np.empty(self.dim * self.n2)
+        _check(lib.ipcs_steady_get_velocity(self.h, _ptr(u), u.size))
+        return u.reshape(self.dim, self.n2)
+
+    def pressure(self):
+        p = np.empty(self.n1)
+        _check(lib.ipcs_steady_get_pressure(self.h, _ptr(p), p.size))
+        return p
+
+    def vector(self, which):
+        """The last step's residual or increment as (U-part (dim, N2), P-part)."""
+        v = np.empty(self.dim * self.n2 + self.n1)
+        _check(lib.ipcs_steady_get_vector(self.h, which, _ptr(v), v.size))
+        return v[:self.dim * self.n2].reshape(self.dim, self.n2), v[self.dim * self.n2:]
+
+    def __del__(self, _destroy=lib.ipcs_steady_destroy):
         if getattr(self, "h", None):
             _destroy(self.h)
             self.h = None
