@@ -25,6 +25,12 @@ Numbering adopted here (the paper does not fix one):
   the node nearer a, then the node nearer b; the centroid. Basis: vertex
   lam_i (3 lam_i - 1)(3 lam_i - 2) / 2; edge node nearer a
   9/2 lam_a lam_b (3 lam_a - 1); centroid 27 lam_0 lam_1 lam_2.
+* P3 (tetrahedra) nodes: the vertices, two per edge (as for triangles), one
+  per face at its centroid (faces = unique sorted vertex triples of cells,
+  listed lexicographically); a tetrahedron has no interior P3 node. Local
+  order: v0..v3; for each local edge (a, b) of (01, 02, 03, 12, 13, 23) the
+  node nearer a, then the node nearer b; the centroids of the faces opposite
+  v0, v1, v2, v3. Basis as for triangles, face node 27 lam_a lam_b lam_c.
 * The space of the pair is chosen by `order` (2: P2-P1, 3: P3-P2). The
   generic names (Nu, c2du, xu, bmask_u for velocity; Np, c2dp, xp for
   pressure) are what the IPCS step uses; N1/N2, c2d1/c2d2, x2, boundary2
@@ -43,6 +49,7 @@ from . import quadrature
 
 EDGES_2D = [(1, 2), (2, 0), (0, 1)]
 EDGES_3D = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+FACES_3D = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]   # face k: opposite vertex k
 
 
 def local_edges(dim):
@@ -86,29 +93,35 @@ def p2_basis(lam):
 
 
 def p3_basis(lam):
-    """Values (nq, 10) and reference gradients (nq, 10, 2) of P3 on triangles."""
+    """Values (nq, nloc) and reference gradients (nq, nloc, d) of P3: nloc = 10
+    on triangles, 20 on tetrahedra."""
     nq, dp1 = lam.shape
-    if dp1 != 3:
-        raise ValueError("P3 is defined here for triangles only")
-    G = bary_grad(2)
-    phi = np.zeros((nq, 10))
-    dphi = np.zeros((nq, 10, 2))
-    for i in range(3):
+    dim = dp1 - 1
+    G = bary_grad(dim)
+    edges = local_edges(dim)
+    nloc = 10 if dim == 2 else 20
+    phi = np.zeros((nq, nloc))
+    dphi = np.zeros((nq, nloc, dim))
+    for i in range(dp1):
         L = lam[:, i]
         phi[:, i] = 0.5 * L * (3.0 * L - 1.0) * (3.0 * L - 2.0)
         dphi[:, i, :] = (0.5 * (27.0 * L * L - 18.0 * L + 2.0))[:, None] * G[i][None, :]
-    for e, (a, b) in enumerate(EDGES_2D):
+    for e, (a, b) in enumerate(edges):
         for k, (p, q) in enumerate(((a, b), (b, a))):   # node nearer p
             Lp, Lq = lam[:, p], lam[:, q]
-            j = 3 + 2 * e + k
+            j = dp1 + 2 * e + k
             phi[:, j] = 4.5 * Lp * Lq * (3.0 * Lp - 1.0)
             # d/dLp = 4.5 Lq (6 Lp - 1), d/dLq = 4.5 Lp (3 Lp - 1)
             dphi[:, j, :] = ((4.5 * Lq * (6.0 * Lp - 1.0))[:, None] * G[p][None, :]
                              + (4.5 * Lp * (3.0 * Lp - 1.0))[:, None] * G[q][None, :])
-    L0, L1, L2 = lam[:, 0], lam[:, 1], lam[:, 2]
-    phi[:, 9] = 27.0 * L0 * L1 * L2
-    dphi[:, 9, :] = 27.0 * ((L1 * L2)[:, None] * G[0][None, :] + (L0 * L2)[:, None] * G[1][None, :]
-                            + (L0 * L1)[:, None] * G[2][None, :])
+    faces = [(0, 1, 2)] if dim == 2 else FACES_3D
+    for f, (a, b, c) in enumerate(faces):
+        j = dp1 + 2 * len(edges) + f
+        La, Lb, Lc = lam[:, a], lam[:, b], lam[:, c]
+        phi[:, j] = 27.0 * La * Lb * Lc
+        dphi[:, j, :] = 27.0 * ((Lb * Lc)[:, None] * G[a][None, :]
+                                + (La * Lc)[:, None] * G[b][None, :]
+                                + (La * Lb)[:, None] * G[c][None, :])
     return phi, dphi
 
 
@@ -144,8 +157,8 @@ class Space:
         self.absdet = np.abs(self.detJ)
         self.Jinv = np.linalg.inv(self.J)
         self.boundary2 = self._boundary_p2()
-        if order not in (2, 3) or (order == 3 and d != 2):
-            raise ValueError("pairs: P2-P1 (triangles, tetrahedra) or P3-P2 (triangles)")
+        if order not in (2, 3):
+            raise ValueError("pairs: P2-P1 or P3-P2")
         self.order = order
         if order == 2:
             self.Nu, self.c2du, self.xu, self.bmask_u = self.N2, self.c2d2, self.x2, self.boundary2
@@ -157,30 +170,44 @@ class Space:
             self.basis_u, self.basis_p = p3_basis, p2_basis
 
     def _p3_dofs(self, cell_edges):
-        """P3 DOF numbering, node coordinates and boundary mask (triangles)."""
+        """P3 DOF numbering, node coordinates and boundary mask."""
+        d = self.dim
         Nv, Ne, Nc = self.Nv, self.edges.shape[0], self.Nc
-        self.N3 = Nv + 2 * Ne + Nc
-        c2d = np.zeros((Nc, 10), dtype=np.int64)
-        c2d[:, :3] = self.cells
-        for e, (a, b) in enumerate(EDGES_2D):
+        edges = local_edges(d)
+        nloc = 10 if d == 2 else 20
+        c2d = np.zeros((Nc, nloc), dtype=np.int64)
+        c2d[:, :d + 1] = self.cells
+        for e, (a, b) in enumerate(edges):
             k = cell_edges[:, e]
             fwd = self.cells[:, a] < self.cells[:, b]        # a is the edge's lower vertex
-            c2d[:, 3 + 2 * e] = np.where(fwd, Nv + 2 * k, Nv + 2 * k + 1)
-            c2d[:, 4 + 2 * e] = np.where(fwd, Nv + 2 * k + 1, Nv + 2 * k)
-        c2d[:, 9] = Nv + 2 * Ne + np.arange(Nc)
+            c2d[:, d + 1 + 2 * e] = np.where(fwd, Nv + 2 * k, Nv + 2 * k + 1)
+            c2d[:, d + 2 + 2 * e] = np.where(fwd, Nv + 2 * k + 1, Nv + 2 * k)
         lo, hi = self.X[self.edges[:, 0]], self.X[self.edges[:, 1]]
-        ex = np.empty((2 * Ne, 2))
+        ex = np.empty((2 * Ne, d))
         ex[0::2] = (2.0 * lo + hi) / 3.0
         ex[1::2] = (lo + 2.0 * hi) / 3.0
-        cx = self.X[self.cells].mean(axis=1)
-        self.Nu, self.c2du = self.N3, c2d
-        self.xu = np.concatenate([self.X, ex, cx])
-        mask = np.zeros(self.N3, dtype=bool)
+        mask = np.zeros(Nv + 2 * Ne, dtype=bool)
         mask[:Nv] = self.boundary2[:Nv]
         be = self.boundary2[Nv:]                  # boundary edges (P2 mask)
         mask[Nv:Nv + 2 * Ne:2] = be
         mask[Nv + 1:Nv + 2 * Ne:2] = be
-        self.bmask_u = mask
+        if d == 2:
+            c2d[:, 9] = Nv + 2 * Ne + np.arange(Nc)
+            fx = self.X[self.cells].mean(axis=1)
+            fmask = np.zeros(Nc, dtype=bool)
+        else:
+            tri = np.stack([np.sort(self.cells[:, list(f)], axis=1) for f in FACES_3D],
+                           axis=1)                                  # (Nc, 4, 3)
+            faces, finv, fcount = np.unique(tri.reshape(-1, 3), axis=0, return_inverse=True,
+                                            return_counts=True)
+            self.faces = faces
+            c2d[:, 16:20] = Nv + 2 * Ne + finv.reshape(Nc, 4)
+            fx = self.X[faces].mean(axis=1)
+            fmask = fcount == 1                   # faces owned by one cell
+        self.N3 = Nv + 2 * Ne + fx.shape[0]
+        self.Nu, self.c2du = self.N3, c2d
+        self.xu = np.concatenate([self.X, ex, fx])
+        self.bmask_u = np.concatenate([mask, fmask])
 
     def _boundary_p2(self):
         """Topological boundary: facets owned by exactly one cell; their vertices
@@ -214,12 +241,16 @@ class Space:
 
 # ----------------------------------------------------------------- local matrices
 def _rule(space):
-    """Cell rule: degree 5 for P2-P1 (every integrand has degree <= 5);
-    the collapsed 5 x 5 Gauss-Legendre rule, exact to degree 8, for P3-P2
-    (convection P3 (P3 . grad P3) has degree 8)."""
+    """Cell rule: degree 5 for P2-P1 (every integrand has degree <= 5); for
+    P3-P2 (convection P3 (P3 . grad P3) has degree 8) the collapsed 5 x 5
+    Gauss-Legendre rule on triangles (exact to degree 8) and Stroud's conical
+    product of 5-point Gauss-Jacobi rules on tetrahedra (125 points, exact to
+    degree 9)."""
     if space.order == 2:
         return quadrature.cell_rule(space.dim)
-    return quadrature.triangle_collapsed_gl(5)
+    if space.dim == 2:
+        return quadrature.triangle_collapsed_gl(5)
+    return quadrature.tet_collapsed(5)
 
 
 def local_mass_u(space):

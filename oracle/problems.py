@@ -160,6 +160,34 @@ class PolySteady3D:
         return np.stack([f1, f2, f3], axis=-1)
 
 
+class PolySteady3DCubic:
+    """u = (y^3 + z^2, z^3 + x^2, x^3 + y^2) (each component independent of its
+    own coordinate, so div u = 0), p = xy + yz + zx - 3/4 (zero mean on the
+    unit cube), f = (u . grad) u - nu Lap u + grad p with
+    Lap u = (6y + 2, 6z + 2, 6x + 2): every integrand of the P3-P2 step has
+    degree <= 8, so the interpolated state is a fixed point."""
+    dim = 3
+
+    def __init__(self, nu=0.1):
+        self.nu = float(nu)
+
+    def u(self, x, t):
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        return np.stack([Y ** 3 + Z * Z, Z ** 3 + X * X, X ** 3 + Y * Y], axis=-1)
+
+    def p(self, x, t):
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        return X * Y + Y * Z + Z * X - 0.75
+
+    def f(self, x, t):
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        u1, u2, u3 = Y ** 3 + Z * Z, Z ** 3 + X * X, X ** 3 + Y * Y
+        f1 = u2 * 3 * Y * Y + u3 * 2 * Z - self.nu * (6 * Y + 2) + (Y + Z)
+        f2 = u1 * 2 * X + u3 * 3 * Z * Z - self.nu * (6 * Z + 2) + (X + Z)
+        f3 = u1 * 3 * X * X + u2 * 2 * Y - self.nu * (6 * X + 2) + (X + Y)
+        return np.stack([f1, f2, f3], axis=-1)
+
+
 class PolySteady2DCubic:
     """Stream function psi = x^3 y + x^2 y^2, u = (psi_y, -psi_x)
     = (x^3 + 2x^2 y, -3x^2 y - 2x y^2), p = x^2 - y^2 + xy - 1/4 (zero mean on

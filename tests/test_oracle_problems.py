@@ -42,6 +42,9 @@ def sym_fields(name, nu, k=None):
         return ([10 * x ** 2 * (x - 1) ** 2 * y * (y - 1) * (2 * y - 1),
                  -10 * x * (x - 1) * (2 * x - 1) * y ** 2 * (y - 1) ** 2],
                 10 * (2 * x - 1) * (2 * y - 1), [x, y])
+    if name == "poly3c":
+        return ([y ** 3 + z ** 2, z ** 3 + x ** 2, x ** 3 + y ** 2],
+                x * y + y * z + z * x - sp.Rational(3, 4), [x, y, z])
     if name == "poly3":
         return [y ** 2 + z ** 2, z ** 2 + x ** 2, x ** 2 + y ** 2], x + y + z - sp.Rational(3, 2), [x, y, z]
     raise KeyError(name)
@@ -55,6 +58,7 @@ CASES = [
     ("poly2", problems.PolySteady2D(0.3), dict(nu=sp.Rational(3, 10))),
     ("poly3", problems.PolySteady3D(0.3), dict(nu=sp.Rational(3, 10))),
     ("poly2c", problems.PolySteady2DCubic(0.3), dict(nu=sp.Rational(3, 10))),
+    ("poly3c", problems.PolySteady3DCubic(0.3), dict(nu=sp.Rational(3, 10))),
     ("steady_paper", problems.SteadyPaper2D(1.0), dict(nu=1)),
     ("steady_paper", problems.SteadyPaper2D(0.05), dict(nu=sp.Rational(1, 20))),
 ]
