@@ -109,7 +109,9 @@ int ipcs_mesh_unit_square(int32_t nx, int32_t ny, ipcs_mesh* out);
  * midpoints with the edges sorted by (lower, higher) vertex; velocity DOFs
  * (P3-P2) are the vertices, then two nodes per edge in that edge order (the
  * node at (2 x_lo + x_hi)/3, then the one at (x_lo + 2 x_hi)/3), then one node
- * per cell at its centroid, in cell order. Pressure DOFs: P1, the vertices;
+ * per cell at its centroid, in cell order (triangles), or one node per face
+ * at its centroid, the faces sorted by their (ascending) vertex triples
+ * (tetrahedra). Pressure DOFs: P1, the vertices;
  * P2 (P3-P2 pair), the vertices, then the edge midpoints in edge order.
  * Internally the library numbers the non-vertex velocity nodes in
  * lexicographic order of their coordinates (last coordinate most
@@ -119,11 +121,14 @@ int ipcs_mesh_unit_square_pair(int32_t nx, int32_t ny, int32_t pair, ipcs_mesh* 
 /* Unit cube, nx*ny*nz cubes, each split into the 6 Kuhn tetrahedra around its
  * main diagonal; vertex (i,j,k) has index (k(ny+1)+j)(nx+1)+i. */
 int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out);
+/* The same cube with the DOF maps of a Taylor-Hood pair (IPCS_PAIR_*;
+ * numbering as for ipcs_mesh_unit_square_pair). */
+int ipcs_mesh_unit_cube_pair(int32_t nx, int32_t ny, int32_t nz, int32_t pair, ipcs_mesh* out);
 /* Any conforming simplicial mesh: x[nv*dim] coordinates, cells[nc*(dim+1)]
  * vertex indices (0-based). Cells of negative orientation are accepted. */
 int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
                           const int32_t* cells, ipcs_mesh* out);
-/* The same with a Taylor-Hood pair (IPCS_PAIR_P3P2 needs dim = 2). */
+/* The same with a Taylor-Hood pair (IPCS_PAIR_*). */
 int ipcs_mesh_from_arrays_pair(int32_t dim, int64_t nv, const double* x, int64_t nc,
                                const int32_t* cells, int32_t pair, ipcs_mesh* out);
 /* The mesh's Taylor-Hood pair (IPCS_PAIR_*). */
@@ -164,9 +169,17 @@ int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int3
 /* The degree-5 cell quadrature rule the kernels use for the P2-P1 pair, in
  * barycentric coordinates lam[nq*(dim+1)] with weights w[nq] summing to
  * 1/dim!. *nq receives the number of points; pass NULL buffers to query it.
- * (P3-P2 runs integrate with the collapsed product of two 5-point
- * Gauss-Legendre rules, 25 points, exact to degree 8.) */
+ * (P3-P2 runs use the rule of ipcs_quadrature_rule_pair.) */
 int ipcs_quadrature_rule(int32_t dim, int32_t* nq, double* lam, double* w, int64_t cap);
+/* The cell rule of a Taylor-Hood pair, same conventions. IPCS_PAIR_P2P1: the
+ * rule above. IPCS_PAIR_P3P2 (its convection integrand has degree 8):
+ * triangles, the collapsed product of two 5-point Gauss-Legendre rules (25
+ * points, exact to degree 8); tetrahedra, Stroud's conical product of 5-point
+ * Gauss-Jacobi rules (125 points, exact to degree 9), point q = 25 i + 5 j + k
+ * from the i-th, j-th and k-th nodes of the rules in x, y/(1-x) and
+ * z/((1-x)(1-y/(1-x))). */
+int ipcs_quadrature_rule_pair(int32_t dim, int32_t pair, int32_t* nq, double* lam, double* w,
+                              int64_t cap);
 void ipcs_mesh_destroy(ipcs_mesh m);
 
 /* ---------------------------------------------------------------- runs */
@@ -271,11 +284,15 @@ enum {
   IPCS_SOL_POLY_CUBIC_2D = 6,   /* u=(x^3+2x^2y, -3x^2y-2xy^2), p=x^2-y^2+xy-1/4,
                                  * steady, f = (u.grad)u - nu Lap u + grad p: a
                                  * fixed point of the P3-P2 step                 */
-  IPCS_SOL_STEADY_PAPER_2D = 7  /* the steady example of Section 4.2:
+  IPCS_SOL_STEADY_PAPER_2D = 7, /* the steady example of Section 4.2:
                                  * u = 10x^2(x-1)^2 y(y-1)(2y-1),
                                  * v = -10x(x-1)(2x-1) y^2(y-1)^2,
                                  * p = 10(2x-1)(2y-1), f = -nu Lap u + (u.grad)u
                                  * + grad p (steady solver only)                 */
+  IPCS_SOL_POLY_CUBIC_3D = 8    /* u=(y^3+z^2, z^3+x^2, x^3+y^2),
+                                 * p=xy+yz+zx-3/4, steady, f as for
+                                 * IPCS_SOL_POLY_CUBIC_2D: a fixed point of the
+                                 * P3-P2 step on tetrahedra                     */
 };
 /* Closed-form manufactured solution evaluated on the device: Dirichlet data,
  * forcing and the initial state U = I_h u(t), P = I_h p(t) shifted to zero

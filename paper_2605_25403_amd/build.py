@@ -18,7 +18,7 @@ OBJ = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libipcs.so")
 
-SOURCES = ["mesh.cpp", "parts.cpp", "run.cpp", "batch.cpp", "capi.cpp", "steady.cpp",
+SOURCES = ["mesh.cpp", "parts.cpp", "run.cpp", "batch.cpp", "capi.cpp", "steady.cpp", "rules.cpp",
            "scratch.hip", "kernels_asm.hip", "kernels_krylov.hip", "kernels_fcg.hip",
            "kernels_fields.hip", "kernels_steady.hip"]
 

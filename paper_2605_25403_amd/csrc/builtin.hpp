@@ -76,6 +76,11 @@ __host__ __device__ inline void builtin_velocity(const Builtin& bi, const double
         u[1] = Z * Z + X * X;
         u[2] = X * X + Y * Y;
         return;
+      case IPCS_SOL_POLY_CUBIC_3D:
+        u[0] = Y * Y * Y + Z * Z;
+        u[1] = Z * Z * Z + X * X;
+        u[2] = X * X * X + Y * Y;
+        return;
     }
     u[0] = u[1] = u[2] = 0.0;
   }
@@ -108,6 +113,7 @@ __host__ __device__ inline double builtin_pressure(const Builtin& bi, const doub
         return -0.5 * a * a * q * exp(-2.0 * bi.nu * d * d * t);
       }
       case IPCS_SOL_POLY_STEADY_3D: return X + Y + Z - 1.5;
+      case IPCS_SOL_POLY_CUBIC_3D: return X * Y + Y * Z + Z * X - 0.75;
     }
     return 0.0;
   }
@@ -174,6 +180,14 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
       f[2] = c + 2 * X * u1 + 2 * Y * u2;
       return;
     }
+    if (bi.kind == IPCS_SOL_POLY_CUBIC_3D) {
+      // (u.grad)u - nu Lap u + grad p; Lap u = (6y + 2, 6z + 2, 6x + 2)
+      const double u1 = Y * Y * Y + Z * Z, u2 = Z * Z * Z + X * X, u3 = X * X * X + Y * Y;
+      f[0] = u2 * 3.0 * Y * Y + u3 * 2.0 * Z - nu * (6.0 * Y + 2.0) + (Y + Z);
+      f[1] = u1 * 2.0 * X + u3 * 3.0 * Z * Z - nu * (6.0 * Z + 2.0) + (X + Z);
+      f[2] = u1 * 3.0 * X * X + u2 * 2.0 * Y - nu * (6.0 * X + 2.0) + (X + Y);
+      return;
+    }
     f[0] = f[1] = f[2] = 0.0;
   }
 }
@@ -181,7 +195,7 @@ __host__ __device__ inline void builtin_force(const Builtin& bi, const double* x
 inline bool builtin_has_force(int kind) {
   return kind == IPCS_SOL_JOHN_2D || kind == IPCS_SOL_POLY_STEADY_2D ||
          kind == IPCS_SOL_POLY_STEADY_3D || kind == IPCS_SOL_POLY_CUBIC_2D ||
-         kind == IPCS_SOL_STEADY_PAPER_2D;
+         kind == IPCS_SOL_STEADY_PAPER_2D || kind == IPCS_SOL_POLY_CUBIC_3D;
 }
 
 }  // namespace ipcs

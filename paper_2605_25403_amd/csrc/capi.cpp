@@ -163,6 +163,13 @@ int ipcs_mesh_unit_cube(int32_t nx, int32_t ny, int32_t nz, ipcs_mesh* out) {
   });
 }
 
+int ipcs_mesh_unit_cube_pair(int32_t nx, int32_t ny, int32_t nz, int32_t pair, ipcs_mesh* out) {
+  return guard([&]() -> int {
+    need(out != nullptr, "null output handle");
+    return wrap_mesh(ipcs::build_unit_cube(nx, ny, nz, pair), out);
+  });
+}
+
 int ipcs_mesh_from_arrays(int32_t dim, int64_t nv, const double* x, int64_t nc,
                           const int32_t* cells, ipcs_mesh* out) {
   return guard([&]() -> int {
@@ -298,6 +305,28 @@ int ipcs_quadrature_rule(int32_t dim, int32_t* nq, double* lam, double* w, int64
       w[q] = dim == 2 ? ipcs::Rule<2>::w(q) : ipcs::Rule<3>::w(q);
       for (int k = 0; k <= dim; ++k)
         lam[q * (dim + 1) + k] = dim == 2 ? ipcs::Rule<2>::lam(q, k) : ipcs::Rule<3>::lam(q, k);
+    }
+    return IPCS_OK;
+  });
+}
+
+int ipcs_quadrature_rule_pair(int32_t dim, int32_t pair, int32_t* nq, double* lam, double* w,
+                              int64_t cap) {
+  if (pair == IPCS_PAIR_P2P1) return ipcs_quadrature_rule(dim, nq, lam, w, cap);
+  return guard([&]() -> int {
+    need(dim == 2 || dim == 3, "dim must be 2 or 3");
+    need(pair == IPCS_PAIR_P3P2, "unknown Taylor-Hood pair");
+    const int n = dim == 2 ? ipcs::RuleT9::NQ : ipcs::RuleTet9::NQ;
+    if (nq) *nq = n;
+    if (!lam && !w) return IPCS_OK;
+    need(lam && w && cap >= (int64_t)n * (dim + 1), "output buffer too small");
+    if (dim == 3) {
+      ipcs::tet_rule9(lam, w);
+      return IPCS_OK;
+    }
+    for (int q = 0; q < n; ++q) {
+      w[q] = ipcs::RuleT9::w(q);
+      for (int k = 0; k < 3; ++k) lam[q * 3 + k] = ipcs::RuleT9::lam(q, k);
     }
     return IPCS_OK;
   });

@@ -126,7 +126,7 @@ struct RowAsm {
   int32_t nrows;
   const int32_t* sptr;        // SELL-64 slice offsets of the output matrices
   const int32_t* inc_ptr;
-  const int32_t* inc;         // cell << 4 | local row index
+  const int32_t* inc;         // cell << 5 | local row index
   const uint8_t* slot;
   int32_t stride;
   const int32_t* c2d;         // [nc][nloc2] velocity DOFs

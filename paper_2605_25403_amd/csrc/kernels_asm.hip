@@ -17,7 +17,10 @@
 //   Kp_kl = |K| grad psi_k . grad psi_l           w_k = int_K psi_k = |K|/(d+1)
 #include <hip/hip_runtime.h>
 
+#include <memory>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "dev_util.hpp"
@@ -338,10 +341,11 @@ struct OpKp {   // P1 x P1 stiffness
   }
 };
 
-// ------------------------------------------------------------------ P3-P2 (triangles)
-// Tables of the P3-P2 pair at the points of its degree-8 rule: P3 velocity
-// basis phi (10) and P2 pressure basis psi (6), values and reference
-// gradients.
+// ------------------------------------------------------------------ P3-P2 pair
+// Tables of the P3-P2 pair at the points of its cell rule: P3 velocity basis
+// phi and P2 pressure basis psi, values and reference gradients.
+// Triangles: the 25-point degree-8 rule, tables built at compile time and kept
+// in constant memory (10.4 KB in FP64).
 template <class R>
 struct Tab3 {
   static constexpr int NQ = RuleT9::NQ, NL = P3T::NLOC, NP = P2<2>::NLOC;
@@ -369,142 +373,235 @@ struct Tab3 {
   }
 };
 
+// Tetrahedra: the 125-point conical rule (degree 9), whose nodes come from a
+// host-side root finder; 125 KB in FP64, so the tables live in global device
+// memory (filled once per device before the first launch that reads them).
+// Loads at wavefront-uniform indices still go through the scalar cache.
+template <class R>
+struct Tab3Tet {
+  static constexpr int NQ = RuleTet9::NQ, NL = P3Tet::NLOC, NP = P2<3>::NLOC;
+  R w[NQ];
+  R lam[NQ][4];
+  R phi[NQ][NL];
+  R dphi[NQ][NL][3];
+  R psi[NQ][NP];
+  R dpsi[NQ][NP][3];
+};
+
 __constant__ Tab3<double> c_tab3p = Tab3<double>();
 __constant__ Tab3<float> c_tab3pf = Tab3<float>();
+__device__ Tab3Tet<double> g_tab3t;
+__device__ Tab3Tet<float> g_tab3tf;
+
+template <int D>
+struct P3Of;
+template <>
+struct P3Of<2> {
+  using B = P3T;
+  template <class R>
+  using Tab = Tab3<R>;
+};
+template <>
+struct P3Of<3> {
+  using B = P3Tet;
+  template <class R>
+  using Tab = Tab3Tet<R>;
+};
+
+template <int D, class R>
+__device__ __forceinline__ const typename P3Of<D>::template Tab<R>& tab3() {
+  if constexpr (D == 2 && std::is_same_v<R, double>) return c_tab3p;
+  else if constexpr (D == 2) return c_tab3pf;
+  else if constexpr (std::is_same_v<R, double>) return g_tab3t;
+  else return g_tab3tf;
+}
 
 template <class R>
-__device__ __forceinline__ const Tab3<R>& tab3() {
-  if constexpr (std::is_same_v<R, double>) return c_tab3p;
-  else return c_tab3pf;
+static void fill_tet_tables(Tab3Tet<R>& T, const double* lam, const double* w) {
+  constexpr int NQ = Tab3Tet<R>::NQ;
+  for (int q = 0; q < NQ; ++q) {
+    const double* l = lam + 4 * q;
+    T.w[q] = (R)w[q];
+    for (int k = 0; k < 4; ++k) T.lam[q][k] = (R)l[k];
+    for (int j = 0; j < P3Tet::NLOC; ++j) {
+      T.phi[q][j] = (R)P3Tet::phi(j, l);
+      for (int r = 0; r < 3; ++r) T.dphi[q][j][r] = (R)P3Tet::dphi(j, r, l);
+    }
+    for (int j = 0; j < P2<3>::NLOC; ++j) {
+      T.psi[q][j] = (R)P2<3>::phi(j, l);
+      for (int r = 0; r < 3; ++r) T.dpsi[q][j][r] = (R)P2<3>::dphi(j, r, l);
+    }
+  }
+}
+
+// Fill the tetrahedral tables on the current device (once per device).
+static void ensure_tet_tables() {
+  static std::mutex mu;
+  static std::vector<char> done;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, 0);
+  if (done[dev]) return;
+  std::vector<double> lam(4 * RuleTet9::NQ), w(RuleTet9::NQ);
+  tet_rule9(lam.data(), w.data());
+  auto t64 = std::make_unique<Tab3Tet<double>>();
+  auto t32 = std::make_unique<Tab3Tet<float>>();
+  fill_tet_tables(*t64, lam.data(), w.data());
+  fill_tet_tables(*t32, lam.data(), w.data());
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(g_tab3t), t64.get(), sizeof(Tab3Tet<double>)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(g_tab3tf), t32.get(), sizeof(Tab3Tet<float>)));
+  HIP_OK(hipDeviceSynchronize());
+  done[dev] = 1;
+}
+
+static void need_tables(int dim, const RowAsm& a) {
+  if (dim == 3 && a.pair == IPCS_PAIR_P3P2) ensure_tet_tables();
 }
 
 // the c-th physical gradient component of a reference gradient
-template <class R>
-__device__ __forceinline__ R phys_c(const Geo<2, R>& g, const R* gr, int c) {
-  R p[2];
-  phys<2, R>(g, gr, p);
-  return c == 0 ? p[0] : p[1];
+template <int D, class R>
+__device__ __forceinline__ R phys_c(const Geo<D, R>& g, const R* gr, int c) {
+  R p[D];
+  phys<D, R>(g, gr, p);
+  R s = p[0];
+#pragma unroll
+  for (int b = 1; b < D; ++b) s = (c == b) ? p[b] : s;
+  return s;
 }
 
-template <int WHICH, class R>
+template <int D, int WHICH, class R>
 struct Op3MassStiff {   // P3 x P3: M (WHICH 0) or K (WHICH 1)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 0;   // geometry only
-  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+  static constexpr int NOUT = 1, NCOL = P3Of<D>::B::NLOC, NDOF = 0;   // geometry only
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
-    const Tab3<R>& T = tab3<R>();
+    const auto& T = tab3<D, R>();
 #pragma unroll 1
-    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+    for (int q = 0; q < T.NQ; ++q) {
       const R wq = T.w[q] * g.det;
       if (WHICH == 0) {
         const R ci = wq * T.phi[q][li];
 #pragma unroll
         for (int j = 0; j < NCOL; ++j) v[0][j] += ci * T.phi[q][j];
       } else {
-        R gi[2];
-        phys<2, R>(g, T.dphi[q][li], gi);
+        R gi[D];
+        phys<D, R>(g, T.dphi[q][li], gi);
 #pragma unroll
         for (int j = 0; j < NCOL; ++j) {
-          R gj[2];
-          phys<2, R>(g, T.dphi[q][j], gj);
-          v[0][j] += wq * (gi[0] * gj[0] + gi[1] * gj[1]);
+          R gj[D];
+          phys<D, R>(g, T.dphi[q][j], gj);
+          R s = 0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) s += gi[b] * gj[b];
+          v[0][j] += wq * s;
         }
       }
     }
   }
 };
 
-template <class R>
+template <int D, class R>
 struct Op3Conv {   // P3 x P3: E = M/dt + cs C(U)
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = P3T::NLOC;
-  const double* U;        // [2][n2]
+  static constexpr int NOUT = 1, NCOL = P3Of<D>::B::NLOC, NDOF = NCOL;
+  const double* U;        // [D][n2]
   int64_t n2;
   double inv_dt;
   double cs;
-  __device__ void operator()(const Geo<2, R>& g, const int32_t* dofs, int li,
+  __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
                              R (&v)[NOUT][NCOL]) const {
-    const Tab3<R>& T = tab3<R>();
-    R Uc[2][NCOL];
+    const auto& T = tab3<D, R>();
+    R Uc[D][NCOL];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < D; ++c)
 #pragma unroll
       for (int m = 0; m < NCOL; ++m) Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
     const R idt = (R)inv_dt, csr = (R)cs;
 #pragma unroll 1
-    for (int q = 0; q < Tab3<R>::NQ; ++q) {
-      R uq[2];
+    for (int q = 0; q < T.NQ; ++q) {
+      R uq[D];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < D; ++c) {
         R s = 0;
 #pragma unroll
         for (int m = 0; m < NCOL; ++m) s += Uc[c][m] * T.phi[q][m];
         uq[c] = s;
       }
-      R beta[2];   // J^{-1} u_h
+      R beta[D];   // J^{-1} u_h
 #pragma unroll
-      for (int a = 0; a < 2; ++a) beta[a] = g.Ji[a][0] * uq[0] + g.Ji[a][1] * uq[1];
+      for (int a = 0; a < D; ++a) {
+        R s = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) s += g.Ji[a][c] * uq[c];
+        beta[a] = s;
+      }
       const R ci = T.w[q] * g.det * T.phi[q][li];
 #pragma unroll
       for (int j = 0; j < NCOL; ++j) {
-        const R adv = beta[0] * T.dphi[q][j][0] + beta[1] * T.dphi[q][j][1];
+        R adv = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) adv += beta[a] * T.dphi[q][j][a];
         v[0][j] += ci * (T.phi[q][j] * idt + csr * adv);
       }
     }
   }
 };
 
-template <class R>
+template <int D, class R>
 struct Op3Grad {   // P3 rows x P2 cols: (G_c)_ik = sum_q w |J| phi_i d_c psi_k
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 0;
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = 0;
   int c;
-  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
-    const Tab3<R>& T = tab3<R>();
+    const auto& T = tab3<D, R>();
 #pragma unroll 1
-    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+    for (int q = 0; q < T.NQ; ++q) {
       const R ci = T.w[q] * g.det * T.phi[q][li];
 #pragma unroll
-      for (int k = 0; k < NCOL; ++k) v[0][k] += ci * phys_c<R>(g, T.dpsi[q][k], c);
+      for (int k = 0; k < NCOL; ++k) v[0][k] += ci * phys_c<D, R>(g, T.dpsi[q][k], c);
     }
   }
 };
 
-template <class R>
+template <int D, class R>
 struct Op3Div {   // P2 rows x P3 cols: (D_c)_kj = sum_q w |J| psi_k d_c phi_j
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P3T::NLOC, NDOF = 0;
+  static constexpr int NOUT = 1, NCOL = P3Of<D>::B::NLOC, NDOF = 0;
   int c;
-  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
-    const Tab3<R>& T = tab3<R>();
+    const auto& T = tab3<D, R>();
 #pragma unroll 1
-    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+    for (int q = 0; q < T.NQ; ++q) {
       const R ci = T.w[q] * g.det * T.psi[q][li];
 #pragma unroll
-      for (int j = 0; j < NCOL; ++j) v[0][j] += ci * phys_c<R>(g, T.dphi[q][j], c);
+      for (int j = 0; j < NCOL; ++j) v[0][j] += ci * phys_c<D, R>(g, T.dphi[q][j], c);
     }
   }
 };
 
-template <class R>
+template <int D, class R>
 struct Op3Kp {   // P2 x P2 stiffness of the pressure space
   using real = R;
-  static constexpr int NOUT = 1, NCOL = P2<2>::NLOC, NDOF = 0;
-  __device__ void operator()(const Geo<2, R>& g, const int32_t*, int li,
+  static constexpr int NOUT = 1, NCOL = P2<D>::NLOC, NDOF = 0;
+  __device__ void operator()(const Geo<D, R>& g, const int32_t*, int li,
                              R (&v)[NOUT][NCOL]) const {
-    const Tab3<R>& T = tab3<R>();
+    const auto& T = tab3<D, R>();
 #pragma unroll 1
-    for (int q = 0; q < Tab3<R>::NQ; ++q) {
+    for (int q = 0; q < T.NQ; ++q) {
       const R wq = T.w[q] * g.det;
-      R gi[2];
-      phys<2, R>(g, T.dpsi[q][li], gi);
+      R gi[D];
+      phys<D, R>(g, T.dpsi[q][li], gi);
 #pragma unroll
       for (int k = 0; k < NCOL; ++k) {
-        R gk[2];
-        phys<2, R>(g, T.dpsi[q][k], gk);
-        v[0][k] += wq * (gi[0] * gk[0] + gi[1] * gk[1]);
+        R gk[D];
+        phys<D, R>(g, T.dpsi[q][k], gk);
+        R s = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) s += gi[b] * gk[b];
+        v[0][k] += wq * s;
       }
     }
   }
@@ -533,7 +630,7 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
     const int off = a.sptr[row >> 6] - base + (row & 63);
     for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
       const int code = a.inc[p];
-      const int cell = code >> 4, li = code & 15;
+      const int cell = code >> 5, li = code & 31;
       // velocity DOFs only for ops that read U (NDOF > 0)
       int32_t dl[Op::NDOF > 0 ? Op::NDOF : 1];
       if constexpr (Op::NDOF > 0) {
@@ -565,11 +662,57 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
     for (int o = 0; o < NOUT; ++o) static_cast<R*>(a.out[o])[base + k] = lds[o * bent + k];
 }
 
+// The same for row blocks whose slices exceed the LDS of a block (P3 rows on
+// tetrahedra reach 175 entries): each thread clears its own row in the output
+// and accumulates into it there. Rows are still owned by one thread, so there
+// are no atomics and the sums are formed in the same order as above.
+template <int D, class Op>
+__global__ void __launch_bounds__(256) k_asm_rows_g(RowAsm a, Op op) {
+  using R = typename Op::real;
+  constexpr int NOUT = Op::NOUT, NCOL = Op::NCOL;
+  const int row = xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk) * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  const int sl0 = row >> 6;
+  const int w = (a.sptr[sl0 + 1] - a.sptr[sl0]) >> 6;
+  const int off = a.sptr[sl0] + (row & 63);
+  for (int k = 0; k < w; ++k)
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) static_cast<R*>(a.out[o])[off + 64 * k] = R(0);
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int code = a.inc[p];
+    const int cell = code >> 5, li = code & 31;
+    int32_t dl[Op::NDOF > 0 ? Op::NDOF : 1];
+    if constexpr (Op::NDOF > 0) {
+      const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
+#pragma unroll
+      for (int m = 0; m < Op::NDOF; ++m) dl[m] = dofs[m];
+    }
+    int32_t vx[D + 1];
+    cell_vertices<D>(a, cell, vx);
+    const Geo<D, R> g = cell_geo<D, R>(a.X, vx);
+    R v[NOUT][NCOL];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+      for (int j = 0; j < NCOL; ++j) v[o][j] = R(0);
+    op(g, dl, li, v);
+    const uint8_t* slp = a.slot + (size_t)p * a.stride;
+#pragma unroll
+    for (int j = 0; j < NCOL; ++j) {
+      const int e = off + 64 * slp[j];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) static_cast<R*>(a.out[o])[e] += v[o][j];
+    }
+  }
+}
+
+// lds == 0: the block's slices do not fit in LDS (global accumulation)
 template <int D, class Op>
 static void launch_rows(hipStream_t s, const RowAsm& a, const Op& op, int bs, size_t lds) {
   if (a.nrows <= 0) return;
   const int nb = (int)div_up(a.nrows, bs);
-  launch(k_asm_rows<D, Op>, dim3(nb), dim3(bs), (uint32_t)lds, s, a, op);
+  if (lds == 0) launch(k_asm_rows_g<D, Op>, dim3(nb), dim3(bs), 0, s, a, op);
+  else launch(k_asm_rows<D, Op>, dim3(nb), dim3(bs), (uint32_t)lds, s, a, op);
 }
 
 // Dispatch over dimension and working type.
@@ -587,24 +730,19 @@ using OpMass = OpMassStiff<D, 0, R>;
 template <int D, class R>
 using OpStiff = OpMassStiff<D, 1, R>;
 
-// The P3-P2 pair (2D) over its ops, in the working type
-template <template <class> class OpT, class... P>
-static void rows_p3(bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds, P... prm) {
-  if (!fp32) launch_rows<2>(s, a, OpT<double>{prm...}, bs, lds);
-  else launch_rows<2>(s, a, OpT<float>{prm...}, bs, lds);
-}
-template <class R>
-using Op3Mass = Op3MassStiff<0, R>;
-template <class R>
-using Op3Stiff = Op3MassStiff<1, R>;
+template <int D, class R>
+using Op3Mass = Op3MassStiff<D, 0, R>;
+template <int D, class R>
+using Op3Stiff = Op3MassStiff<D, 1, R>;
 
 // a.out[0] <- M, a.out[1] <- K
 void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
   RowAsm am = a, ak = a;
   ak.out[0] = a.out[1];
   if (a.pair == IPCS_PAIR_P3P2) {
-    rows_p3<Op3Mass>(fp32, s, am, bs, lds);
-    rows_p3<Op3Stiff>(fp32, s, ak, bs, lds);
+    need_tables(dim, a);
+    rows_dr<Op3Mass>(dim, fp32, s, am, bs, lds);
+    rows_dr<Op3Stiff>(dim, fp32, s, ak, bs, lds);
     return;
   }
   rows_dr<OpMass>(dim, fp32, s, am, bs, lds);
@@ -612,7 +750,10 @@ void asm_mass_stiff(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, 
 }
 void asm_conv(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
               const double* U, int64_t n2, double inv_dt, double cs) {
-  if (a.pair == IPCS_PAIR_P3P2) return rows_p3<Op3Conv>(fp32, s, a, bs, lds, U, n2, inv_dt, cs);
+  if (a.pair == IPCS_PAIR_P3P2) {
+    need_tables(dim, a);
+    return rows_dr<Op3Conv>(dim, fp32, s, a, bs, lds, U, n2, inv_dt, cs);
+  }
   rows_dr<OpConv>(dim, fp32, s, a, bs, lds, U, n2, inv_dt, cs);
 }
 // a.out[0] <- N_ce(U) (P2-P1, FP64; steady solver)
@@ -623,24 +764,29 @@ void asm_newton(int dim, hipStream_t s, const RowAsm& a, int bs, size_t lds, con
 }
 // a.out[c] <- G_c (one launch per component)
 void asm_grad(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  need_tables(dim, a);
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    if (a.pair == IPCS_PAIR_P3P2) rows_p3<Op3Grad>(fp32, s, ac, bs, lds, c);
+    if (a.pair == IPCS_PAIR_P3P2) rows_dr<Op3Grad>(dim, fp32, s, ac, bs, lds, c);
     else rows_dr<OpGrad>(dim, fp32, s, ac, bs, lds, c);
   }
 }
 // a.out[c] <- D_c
 void asm_div(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
+  need_tables(dim, a);
   for (int c = 0; c < dim; ++c) {
     RowAsm ac = a;
     ac.out[0] = a.out[c];
-    if (a.pair == IPCS_PAIR_P3P2) rows_p3<Op3Div>(fp32, s, ac, bs, lds, c);
+    if (a.pair == IPCS_PAIR_P3P2) rows_dr<Op3Div>(dim, fp32, s, ac, bs, lds, c);
     else rows_dr<OpDiv>(dim, fp32, s, ac, bs, lds, c);
   }
 }
 void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds) {
-  if (a.pair == IPCS_PAIR_P3P2) return rows_p3<Op3Kp>(fp32, s, a, bs, lds);
+  if (a.pair == IPCS_PAIR_P3P2) {
+    need_tables(dim, a);
+    return rows_dr<Op3Kp>(dim, fp32, s, a, bs, lds);
+  }
   rows_dr<OpKp>(dim, fp32, s, a, bs, lds);
 }
 
@@ -753,7 +899,7 @@ __global__ void __launch_bounds__(256) k_asm_local(RowAsm a, const R* loc) {
     const int off = a.sptr[row >> 6] - base + (row & 63);
     for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
       const int code = a.inc[p];
-      const int cell = code >> 4, li = code & 15;
+      const int cell = code >> 5, li = code & 31;
       const R* lr = loc + ((size_t)cell * NL + li) * NL;
       const uint8_t* sl = a.slot + (size_t)p * a.stride;
 #pragma unroll
@@ -782,6 +928,7 @@ static void local_sum(hipStream_t s, const RowAsm& a, int bs, size_t lds, const 
 
 void asm_conv_cells(int dim, bool fp32, hipStream_t s, const RowAsm& a, int64_t nc,
                     const double* U, int64_t n2, double inv_dt, double cs, void* buf) {
+  if (a.pair != IPCS_PAIR_P2P1) fail(IPCS_E_INVALID, "cell-batched convection: P2-P1 pair only");
   if (dim == 2 && !fp32) conv_cells<2, double>(s, a, nc, U, n2, inv_dt, cs, buf);
   else if (dim == 2) conv_cells<2, float>(s, a, nc, U, n2, inv_dt, cs, buf);
   else if (!fp32) conv_cells<3, double>(s, a, nc, U, n2, inv_dt, cs, buf);
@@ -790,6 +937,8 @@ void asm_conv_cells(int dim, bool fp32, hipStream_t s, const RowAsm& a, int64_t 
 
 void asm_local_sum(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                    const void* buf) {
+  if (a.pair != IPCS_PAIR_P2P1 || lds == 0)
+    fail(IPCS_E_INVALID, "local-matrix sum: P2-P1 pair with rows that fit in LDS only");
   if (dim == 2 && !fp32) local_sum<2, double>(s, a, bs, lds, buf);
   else if (dim == 2) local_sum<2, float>(s, a, bs, lds, buf);
   else if (!fp32) local_sum<3, double>(s, a, bs, lds, buf);
@@ -804,7 +953,7 @@ __global__ void __launch_bounds__(256) k_lumped_p1(RowAsm a, double* w) {
   if (row >= a.nrows) return;
   double s = 0.0;
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
-    const int cell = a.inc[p] >> 4;
+    const int cell = a.inc[p] >> 5;
     int32_t dl[D + 1];
     cell_vertices<D>(a, cell, dl);
     s += cell_geo<D>(a.X, dl).det * (ref_measure<D>() / (D + 1));
@@ -813,25 +962,30 @@ __global__ void __launch_bounds__(256) k_lumped_p1(RowAsm a, double* w) {
 }
 
 // P2 pressure (P3-P2 pair): w_k = sum over incident cells of sum_q w_q |J| psi_k(x_q)
+template <int D>
 __global__ void __launch_bounds__(256) k_lumped_p2(RowAsm a, double* w) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= a.nrows) return;
-  const Tab3<double>& T = tab3<double>();
+  const auto& T = tab3<D, double>();
   double s = 0.0;
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
-    const int cell = a.inc[p] >> 4, li = a.inc[p] & 15;
-    int32_t dl[3];
-    cell_vertices<2>(a, cell, dl);
+    const int cell = a.inc[p] >> 5, li = a.inc[p] & 31;
+    int32_t dl[D + 1];
+    cell_vertices<D>(a, cell, dl);
     double iq = 0.0;
-    for (int q = 0; q < Tab3<double>::NQ; ++q) iq += T.w[q] * T.psi[q][li];
-    s += cell_geo<2>(a.X, dl).det * iq;
+    for (int q = 0; q < T.NQ; ++q) iq += T.w[q] * T.psi[q][li];
+    s += cell_geo<D>(a.X, dl).det * iq;
   }
   w[row] = s;
 }
 
 void asm_lumped_p1(int dim, hipStream_t s, const RowAsm& a, double* w) {
   const int nb = (int)div_up(a.nrows, 256);
-  if (a.pair == IPCS_PAIR_P3P2) hipLaunchKernelGGL(k_lumped_p2, dim3(nb), dim3(256), 0, s, a, w);
+  need_tables(dim, a);
+  if (a.pair == IPCS_PAIR_P3P2 && dim == 2)
+    hipLaunchKernelGGL((k_lumped_p2<2>), dim3(nb), dim3(256), 0, s, a, w);
+  else if (a.pair == IPCS_PAIR_P3P2)
+    hipLaunchKernelGGL((k_lumped_p2<3>), dim3(nb), dim3(256), 0, s, a, w);
   else if (dim == 2) hipLaunchKernelGGL((k_lumped_p1<2>), dim3(nb), dim3(256), 0, s, a, w);
   else hipLaunchKernelGGL((k_lumped_p1<3>), dim3(nb), dim3(256), 0, s, a, w);
   HIP_LAUNCH_OK();
@@ -849,7 +1003,7 @@ __global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const dou
   for (int c = 0; c < D; ++c) acc[c] = 0.0;
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
     const int code = a.inc[p];
-    const int cell = code >> 4, li = code & 15;
+    const int cell = code >> 5, li = code & 31;
     int32_t dl[D + 1];
     cell_vertices<D>(a, cell, dl);
     const Geo<D> g = cell_geo<D>(a.X, dl);
@@ -881,48 +1035,57 @@ __global__ void __launch_bounds__(256) k_forcing(RowAsm a, Builtin bi, const dou
   for (int c = 0; c < D; ++c) F[(size_t)c * n2 + row] = acc[c];
 }
 
-// The same for P3 velocity rows (P3-P2 pair) on its degree-8 rule; fq holds
-// f at its RuleT9::NQ points per cell.
+// The same for P3 velocity rows (P3-P2 pair) on its cell rule; fq holds f at
+// the rule's NQ points per cell.
+template <int D>
 __global__ void __launch_bounds__(256) k_forcing_p3(RowAsm a, Builtin bi, const double* fq,
                                                     int64_t nc, double t, double* F, int64_t n2) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= a.nrows) return;
-  const Tab3<double>& T = tab3<double>();
-  double acc[2] = {0.0, 0.0};
+  const auto& T = tab3<D, double>();
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
   for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
     const int code = a.inc[p];
-    const int cell = code >> 4, li = code & 15;
-    int32_t dl[3];
-    cell_vertices<2>(a, cell, dl);
-    const Geo<2> g = cell_geo<2>(a.X, dl);
+    const int cell = code >> 5, li = code & 31;
+    int32_t dl[D + 1];
+    cell_vertices<D>(a, cell, dl);
+    const Geo<D> g = cell_geo<D>(a.X, dl);
 #pragma unroll 1
-    for (int q = 0; q < Tab3<double>::NQ; ++q) {
+    for (int q = 0; q < T.NQ; ++q) {
       const double ci = T.w[q] * g.det * T.phi[q][li];
-      double f[2];
+      double f[D];
       if (fq) {
-        for (int c = 0; c < 2; ++c) f[c] = fq[((size_t)c * nc + cell) * Tab3<double>::NQ + q];
+#pragma unroll
+        for (int c = 0; c < D; ++c) f[c] = fq[((size_t)c * nc + cell) * T.NQ + q];
       } else {
-        double x[2];
-        for (int r = 0; r < 2; ++r) {
+        double x[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
           double sx = 0.0;
-          for (int k = 0; k < 3; ++k) sx += T.lam[q][k] * a.X[(size_t)dl[k] * 2 + r];
+#pragma unroll
+          for (int k = 0; k <= D; ++k) sx += T.lam[q][k] * a.X[(size_t)dl[k] * D + r];
           x[r] = sx;
         }
-        builtin_force<2>(bi, x, t, f);
+        builtin_force<D>(bi, x, t, f);
       }
-      acc[0] += ci * f[0];
-      acc[1] += ci * f[1];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += ci * f[c];
     }
   }
-  F[row] = acc[0];
-  F[(size_t)n2 + row] = acc[1];
+#pragma unroll
+  for (int c = 0; c < D; ++c) F[(size_t)c * n2 + row] = acc[c];
 }
 
 void asm_forcing(int dim, hipStream_t s, const RowAsm& a, const Builtin& bi, const double* fq,
                  int64_t nc, double t, double* F, int64_t n2) {
   const int nb = (int)div_up(a.nrows, 256);
-  if (a.pair == IPCS_PAIR_P3P2)
-    hipLaunchKernelGGL(k_forcing_p3, dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
+  need_tables(dim, a);
+  if (a.pair == IPCS_PAIR_P3P2 && dim == 2)
+    hipLaunchKernelGGL((k_forcing_p3<2>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
+  else if (a.pair == IPCS_PAIR_P3P2)
+    hipLaunchKernelGGL((k_forcing_p3<3>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
   else if (dim == 2)
     hipLaunchKernelGGL((k_forcing<2>), dim3(nb), dim3(256), 0, s, a, bi, fq, nc, t, F, n2);
   else

@@ -85,7 +85,7 @@ void build_pattern(const Incidence& inc, const std::vector<int32_t>& c2d, int nl
     int32_t buf[1024];
     int n = 0;
     for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
-      int64_t c = inc.code[p] >> 4;
+      int64_t c = inc.code[p] >> 5;
       for (int j = 0; j < ncolloc; ++j) {
         if (n < 1024) buf[n++] = c2d[c * nloc + j];
       }
@@ -108,7 +108,7 @@ void build_pattern(const Incidence& inc, const std::vector<int32_t>& c2d, int nl
     int32_t buf[1024];
     int n = 0;
     for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
-      int64_t c = inc.code[p] >> 4;
+      int64_t c = inc.code[p] >> 5;
       for (int j = 0; j < ncolloc; ++j) {
         if (n < 1024) buf[n++] = c2d[c * nloc + j];
       }
@@ -131,7 +131,7 @@ void build_slots(const Incidence& inc, const std::vector<int32_t>& c2d, int nloc
     const int32_t* b = P.col.data() + P.rowptr[i];
     const int32_t* e = P.col.data() + P.rowptr[i + 1];
     for (int32_t p = inc.ptr[i]; p < inc.ptr[i + 1]; ++p) {
-      int64_t c = inc.code[p] >> 4;
+      int64_t c = inc.code[p] >> 5;
       for (int j = 0; j < ncolloc; ++j) {
         const int32_t* f = std::lower_bound(b, e, c2d[c * nloc + j]);
         S.slot[(int64_t)p * S.stride + j] = uint8_t(f - b);
@@ -149,7 +149,7 @@ void build_incidence(const std::vector<int32_t>& c2d, int64_t nc, int nloc, int 
   I.code.resize(I.ptr[nrows]);
   std::vector<int32_t> fill(I.ptr.begin(), I.ptr.end() - 1);
   for (int64_t c = 0; c < nc; ++c)
-    for (int j = 0; j < nrowloc; ++j) I.code[fill[c2d[c * nloc + j]]++] = int32_t((c << 4) | j);
+    for (int j = 0; j < nrowloc; ++j) I.code[fill[c2d[c * nloc + j]]++] = int32_t((c << 5) | j);
 }
 
 // Internal numbering of the velocity DOFs (the interface keeps the listing
@@ -196,11 +196,9 @@ void finalize(Mesh& m) {
   const int ne_loc = d == 2 ? 3 : 6;
   if (m.pair != IPCS_PAIR_P2P1 && m.pair != IPCS_PAIR_P3P2)
     fail(IPCS_E_INVALID, "unknown Taylor-Hood pair " + std::to_string(m.pair));
-  if (m.pair == IPCS_PAIR_P3P2 && d != 2)
-    fail(IPCS_E_INVALID, "the P3-P2 pair is built on triangles only");
   m.nloc1 = d + 1;
   m.nloc2 = d + 1 + ne_loc;
-  if (nc >= (int64_t(1) << 27)) fail(IPCS_E_INVALID, "too many cells");
+  if (nc >= (int64_t(1) << 26)) fail(IPCS_E_INVALID, "too many cells");
   if (nv >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "too many vertices");
   // --- edges: unique vertex pairs, sorted lexicographically
   std::vector<uint64_t> keys(nc * ne_loc);
@@ -287,49 +285,113 @@ void finalize(Mesh& m) {
       for (int k = 0; k <= d; ++k) m.c2dp[c * m.nloc1 + k] = m.c2d[c * m.nloc2 + k];
     m.xp = m.X;
   } else {
-    // pressure P2: the P2 maps built above; velocity P3 (triangles)
+    // pressure P2: the P2 maps built above; velocity P3: vertices, two nodes
+    // per edge, then one node per cell (triangles) or per face (tetrahedra)
     m.c2dp.swap(m.c2d);
     m.nloc1 = m.nloc2;
     m.xp.swap(m.x2);
     std::vector<uint8_t> bm2;
     bm2.swap(m.bmask);
-    m.nloc2 = 10;
+    const int nl3 = d == 2 ? 10 : 20;
+    const int nl2 = m.nloc1;
+    m.nloc2 = nl3;
     m.n1 = m.n2;
-    m.n2 = nv + 2 * m.ne + nc;
+    // faces (tetrahedra): unique sorted vertex triples, the face opposite
+    // local vertex k of each cell; boundary faces are owned by one cell
+    std::vector<uint64_t> fkeys, fu;
+    std::vector<int32_t> fcnt;
+    if (d == 3) {
+      fkeys.resize(nc * 4);
+      auto fkey = [](int32_t a, int32_t b, int32_t c) {
+        int32_t v[3] = {a, b, c};
+        std::sort(v, v + 3);
+        return (uint64_t(uint32_t(v[0])) << 42) | (uint64_t(uint32_t(v[1])) << 21) |
+               uint64_t(uint32_t(v[2]));
+      };
+      if (nv >= (int64_t(1) << 21)) fail(IPCS_E_INVALID, "too many vertices for P3 tetrahedra");
+#pragma omp parallel for
+      for (int64_t c = 0; c < nc; ++c)
+        for (int f = 0; f < 4; ++f) {
+          const int32_t* p = m.c2dp.data() + c * nl2;
+          fkeys[c * 4 + f] = fkey(p[P3Tet::fv(f, 0)], p[P3Tet::fv(f, 1)], p[P3Tet::fv(f, 2)]);
+        }
+      fu = fkeys;
+      std::sort(fu.begin(), fu.end());
+      fcnt.assign(fu.size(), 0);
+      {
+        std::vector<uint64_t> tmp;
+        tmp.reserve(fu.size());
+        for (size_t i = 0; i < fu.size();) {
+          size_t j = i + 1;
+          while (j < fu.size() && fu[j] == fu[i]) ++j;
+          tmp.push_back(fu[i]);
+          i = j;
+        }
+        fcnt.assign(tmp.size(), 0);
+        for (uint64_t k : fkeys) fcnt[std::lower_bound(tmp.begin(), tmp.end(), k) - tmp.begin()]++;
+        fu.swap(tmp);
+      }
+    }
+    const int64_t ncn = d == 2 ? nc : (int64_t)fu.size();   // cell or face nodes
+    m.n2 = nv + 2 * m.ne + ncn;
     if (m.n2 >= (int64_t(1) << 31)) fail(IPCS_E_INVALID, "too many DOFs");
-    m.c2d.resize(nc * 10);
+    m.c2d.resize(nc * nl3);
+    const int ne_l = Edges<3>::NE;
 #pragma omp parallel for
     for (int64_t c = 0; c < nc; ++c) {
-      const int32_t* p = m.c2dp.data() + c * 6;
-      int32_t* o = m.c2d.data() + c * 10;
-      for (int k = 0; k < 3; ++k) o[k] = p[k];
-      for (int e = 0; e < 3; ++e) {
-        const int64_t k = p[3 + e] - nv;               // edge index
-        const bool fwd = p[Edges<2>::a(e)] < p[Edges<2>::b(e)];
-        o[3 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 0 : 1));
-        o[4 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 1 : 0));
+      const int32_t* p = m.c2dp.data() + c * nl2;
+      int32_t* o = m.c2d.data() + c * nl3;
+      for (int k = 0; k <= d; ++k) o[k] = p[k];
+      const int nel = d == 2 ? 3 : ne_l;
+      for (int e = 0; e < nel; ++e) {
+        const int64_t k = p[d + 1 + e] - nv;           // edge index
+        const int ea = d == 2 ? Edges<2>::a(e) : Edges<3>::a(e);
+        const int eb = d == 2 ? Edges<2>::b(e) : Edges<3>::b(e);
+        const bool fwd = p[ea] < p[eb];
+        o[d + 1 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 0 : 1));
+        o[d + 2 + 2 * e] = int32_t(nv + 2 * k + (fwd ? 1 : 0));
       }
-      o[9] = int32_t(nv + 2 * m.ne + c);
+      if (d == 2) {
+        o[9] = int32_t(nv + 2 * m.ne + c);
+      } else {
+        for (int f = 0; f < 4; ++f)
+          o[16 + f] = int32_t(nv + 2 * m.ne +
+                              (std::lower_bound(fu.begin(), fu.end(), fkeys[c * 4 + f]) - fu.begin()));
+      }
     }
-    m.x2.resize(m.n2 * 2);
-    for (int64_t i = 0; i < nv * 2; ++i) m.x2[i] = m.X[i];
+    m.x2.resize(m.n2 * d);
+    for (int64_t i = 0; i < nv * d; ++i) m.x2[i] = m.X[i];
     for (int64_t e = 0; e < m.ne; ++e)
-      for (int r = 0; r < 2; ++r) {
-        const double lo = m.X[(int64_t)m.edges[2 * e] * 2 + r];
-        const double hi = m.X[(int64_t)m.edges[2 * e + 1] * 2 + r];
-        m.x2[(nv + 2 * e) * 2 + r] = (2.0 * lo + hi) / 3.0;
-        m.x2[(nv + 2 * e + 1) * 2 + r] = (lo + 2.0 * hi) / 3.0;
+      for (int r = 0; r < d; ++r) {
+        const double lo = m.X[(int64_t)m.edges[2 * e] * d + r];
+        const double hi = m.X[(int64_t)m.edges[2 * e + 1] * d + r];
+        m.x2[(nv + 2 * e) * d + r] = (2.0 * lo + hi) / 3.0;
+        m.x2[(nv + 2 * e + 1) * d + r] = (lo + 2.0 * hi) / 3.0;
       }
-    for (int64_t c = 0; c < nc; ++c)
-      for (int r = 0; r < 2; ++r)
-        m.x2[(nv + 2 * m.ne + c) * 2 + r] =
-            (m.X[(int64_t)m.c2d[c * 10] * 2 + r] + m.X[(int64_t)m.c2d[c * 10 + 1] * 2 + r] +
-             m.X[(int64_t)m.c2d[c * 10 + 2] * 2 + r]) / 3.0;
-    // boundary: boundary vertices and both nodes of boundary edges
+    if (d == 2) {
+      for (int64_t c = 0; c < nc; ++c)
+        for (int r = 0; r < 2; ++r)
+          m.x2[(nv + 2 * m.ne + c) * 2 + r] =
+              (m.X[(int64_t)m.c2d[c * 10] * 2 + r] + m.X[(int64_t)m.c2d[c * 10 + 1] * 2 + r] +
+               m.X[(int64_t)m.c2d[c * 10 + 2] * 2 + r]) / 3.0;
+    } else {
+      for (int64_t f = 0; f < ncn; ++f) {
+        const int32_t v[3] = {int32_t(fu[f] >> 42), int32_t((fu[f] >> 21) & 0x1fffff),
+                              int32_t(fu[f] & 0x1fffff)};
+        for (int r = 0; r < 3; ++r)
+          m.x2[(nv + 2 * m.ne + f) * 3 + r] =
+              (m.X[(int64_t)v[0] * 3 + r] + m.X[(int64_t)v[1] * 3 + r] + m.X[(int64_t)v[2] * 3 + r]) / 3.0;
+      }
+    }
+    // boundary: boundary vertices, both nodes of boundary edges, the nodes of
+    // boundary faces
     m.bmask.assign(m.n2, 0);
     for (int64_t i = 0; i < nv; ++i) m.bmask[i] = bm2[i];
     for (int64_t e = 0; e < m.ne; ++e)
       if (bm2[nv + e]) m.bmask[nv + 2 * e] = m.bmask[nv + 2 * e + 1] = 1;
+    if (d == 3)
+      for (int64_t f = 0; f < ncn; ++f)
+        if (fcnt[f] == 1) m.bmask[nv + 2 * m.ne + f] = 1;
   }
   renumber_velocity(m);
   m.bidx.clear();
@@ -404,11 +466,12 @@ Mesh* build_unit_square(int nx, int ny, int pair) {
   return m;
 }
 
-Mesh* build_unit_cube(int nx, int ny, int nz) {
+Mesh* build_unit_cube(int nx, int ny, int nz, int pair) {
   if (nx < 1 || ny < 1 || nz < 1) fail(IPCS_E_INVALID, "unit cube needs nx, ny, nz >= 1");
   if (int64_t(nx) * ny * nz > (int64_t(1) << 23)) fail(IPCS_E_INVALID, "mesh too large");
   Mesh* m = new Mesh;
   m->dim = 3;
+  m->pair = pair;
   m->nv = int64_t(nx + 1) * (ny + 1) * (nz + 1);
   m->nc = 6 * int64_t(nx) * ny * nz;
   m->X.resize(m->nv * 3);

@@ -24,7 +24,7 @@ struct Pattern {
 // (row, incident cell) pairs of one row space, sorted by row then cell.
 struct Incidence {
   std::vector<int32_t> ptr;   // [nrows+1]
-  std::vector<int32_t> code;  // cell << 4 | local index of the row's DOF
+  std::vector<int32_t> code;  // cell << 5 | local index of the row's DOF
 };
 
 // SELL-64 layout of a pattern (sliced ELLPACK): rows are grouped in slices of
@@ -131,7 +131,7 @@ std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, con
 
 // Builders. All throw ipcs::Error on invalid input.
 Mesh* build_unit_square(int nx, int ny, int pair = 0);
-Mesh* build_unit_cube(int nx, int ny, int nz);
+Mesh* build_unit_cube(int nx, int ny, int nz, int pair = 0);
 Mesh* build_from_arrays(int dim, int64_t nv, const double* x, int64_t nc, const int32_t* cells,
                         int pair = 0);
 

@@ -172,6 +172,63 @@ struct P3T {
   }
 };
 
+// ------------------------------------------------------------------ P3-P2 (tetrahedra)
+// P3 on tetrahedra: 20 nodes. Local order: v0..v3; for each local edge (a, b)
+// of (01, 02, 03, 12, 13, 23) the node at lam_a = 2/3, then the node at
+// lam_b = 2/3; the centroids of the faces opposite v0, v1, v2, v3. Basis as
+// on triangles; face node 27 lam_a lam_b lam_c.
+struct P3Tet {
+  static constexpr int NV = 4;
+  static constexpr int NLOC = 20;
+  __host__ __device__ static constexpr int ep(int j) {
+    return ((j - 4) & 1) ? Edges<3>::b((j - 4) >> 1) : Edges<3>::a((j - 4) >> 1);
+  }
+  __host__ __device__ static constexpr int eq(int j) {
+    return ((j - 4) & 1) ? Edges<3>::a((j - 4) >> 1) : Edges<3>::b((j - 4) >> 1);
+  }
+  // the m-th vertex (m = 0, 1, 2) of the face opposite vertex f
+  __host__ __device__ static constexpr int fv(int f, int m) { return m < f ? m : m + 1; }
+  template <class T>
+  __host__ __device__ static constexpr T phi(int j, const T* lam) {
+    if (j < 4) return T(0.5) * lam[j] * (T(3) * lam[j] - T(1)) * (T(3) * lam[j] - T(2));
+    if (j < 16) {
+      const T lp = lam[ep(j)], lq = lam[eq(j)];
+      return T(4.5) * lp * lq * (T(3) * lp - T(1));
+    }
+    const int f = j - 16;
+    return T(27) * lam[fv(f, 0)] * lam[fv(f, 1)] * lam[fv(f, 2)];
+  }
+  template <class T>
+  __host__ __device__ static constexpr T dphi(int j, int r, const T* lam) {
+    if (j < 4)
+      return T(0.5) * (T(27) * lam[j] * lam[j] - T(18) * lam[j] + T(2)) * P2<3>::dlam<T>(j, r);
+    if (j < 16) {
+      const int p = ep(j), q = eq(j);
+      const T lp = lam[p], lq = lam[q];
+      return T(4.5) * lq * (T(6) * lp - T(1)) * P2<3>::dlam<T>(p, r) +
+             T(4.5) * lp * (T(3) * lp - T(1)) * P2<3>::dlam<T>(q, r);
+    }
+    const int f = j - 16, a = fv(f, 0), b = fv(f, 1), c = fv(f, 2);
+    return T(27) * (lam[b] * lam[c] * P2<3>::dlam<T>(a, r) + lam[a] * lam[c] * P2<3>::dlam<T>(b, r) +
+                    lam[a] * lam[b] * P2<3>::dlam<T>(c, r));
+  }
+};
+
+// Cell rule of the P3-P2 pair on tetrahedra: Stroud's conical product of
+// 5-point Gauss-Jacobi rules (weights (1-u)^2, (1-v), 1 on [0, 1]), 125 points,
+// exact to degree 9 (the convection integrand has degree 8). With
+// x = u, y = v (1 - u), z = s (1 - u)(1 - v) the Jacobian (1-u)^2 (1-v) is the
+// Jacobi weight. Nodes are the roots of the Jacobi polynomials P_5^(a,0) on
+// [-1, 1] (Newton's method from a sign-change bracket), weights from the
+// Gauss-Jacobi formula 2^(a+1) / ((1 - t^2) P_5'(t)^2) scaled to [0, 1]; built
+// on the host (tet_rule9) and kept with the kernels' tables in device memory.
+struct RuleTet9 {
+  static constexpr int N1 = 5;
+  static constexpr int NQ = N1 * N1 * N1;
+};
+// lam[NQ][4], w[NQ] (weights sum to 1/6)
+void tet_rule9(double* lam, double* w);
+
 // Integral of lam_k over the reference simplex is 1/(d!(d+1)).
 template <int D>
 __host__ __device__ constexpr double ref_measure() {

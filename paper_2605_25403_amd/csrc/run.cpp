@@ -95,7 +95,9 @@ static AsmCfg asm_cfg(const Sell& S, int vbytes) {
     const size_t lds = (size_t)mx * vbytes;
     if (lds <= 65536) return AsmCfg{bs, std::max<size_t>(lds, 8)};
   }
-  fail(IPCS_E_INVALID, "matrix rows too long for the assembly kernel");
+  // the slices of one 64-row block exceed a block's LDS: the row kernels
+  // accumulate in global memory instead (lds 0)
+  return AsmCfg{256, 0};
 }
 
 int status_to_code(int s) {
@@ -467,7 +469,7 @@ void Run::layout(Carver& c) {
   M = vals(ne22);
   K = vals(ne22);
   E = vals(ne22);
-  Eloc = dim == 3 ? c.take<char>(nc * (int64_t)m.nloc2 * m.nloc2 * vsz) : nullptr;
+  Eloc = two_pass_conv() ? c.take<char>(nc * (int64_t)m.nloc2 * m.nloc2 * vsz) : nullptr;
   Ael = vals(ne22);
   Mel = vals(ne22);
   Kp = vals(ne11);
@@ -860,17 +862,21 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   t = prm.t0;
   if (prm.callbacks) {
     const int nq = cell_nq();
+    std::vector<double> lam((size_t)nq * (dim + 1)), wq(nq);
+    if (mm.pair == IPCS_PAIR_P3P2 && dim == 3) tet_rule9(lam.data(), wq.data());
+    else
+      for (int q = 0; q < nq; ++q)
+        for (int k = 0; k <= dim; ++k)
+          lam[(size_t)q * (dim + 1) + k] = mm.pair == IPCS_PAIR_P3P2 ? RuleT9::lam(q, k)
+                                           : dim == 2               ? Rule<2>::lam(q, k)
+                                                                    : Rule<3>::lam(q, k);
     h_xq.resize((size_t)nc * nq * dim);
     for (int64_t cc = 0; cc < nc; ++cc)
       for (int q = 0; q < nq; ++q)
         for (int r = 0; r < dim; ++r) {
           double x = 0.0;
-          for (int k = 0; k <= dim; ++k) {
-            const double l = mm.pair == IPCS_PAIR_P3P2 ? RuleT9::lam(q, k)
-                             : dim == 2               ? Rule<2>::lam(q, k)
-                                                      : Rule<3>::lam(q, k);
-            x += l * mm.X[(size_t)mm.c2dp[cc * mm.nloc1 + k] * dim + r];
-          }
+          for (int k = 0; k <= dim; ++k)
+            x += lam[(size_t)q * (dim + 1) + k] * mm.X[(size_t)mm.c2dp[cc * mm.nloc1 + k] * dim + r];
           h_xq[((size_t)cc * nq + q) * dim + r] = x;
         }
   }
@@ -883,7 +889,8 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
 void Run::set_builtin(int kind, const double* p, int np) {
   const bool ok2 = kind == IPCS_SOL_TAYLOR_GREEN_2D || kind == IPCS_SOL_JOHN_2D ||
                    kind == IPCS_SOL_POLY_STEADY_2D || kind == IPCS_SOL_POLY_CUBIC_2D;
-  const bool ok3 = kind == IPCS_SOL_BELTRAMI_3D || kind == IPCS_SOL_POLY_STEADY_3D;
+  const bool ok3 = kind == IPCS_SOL_BELTRAMI_3D || kind == IPCS_SOL_POLY_STEADY_3D ||
+                   kind == IPCS_SOL_POLY_CUBIC_3D;
   if (!((dim == 2 && ok2) || (dim == 3 && ok3)))
     fail(IPCS_E_INVALID, "built-in solution kind does not match the mesh dimension");
   Builtin b{};
@@ -973,10 +980,11 @@ void Run::asm_phase() {
     asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
     has_F = true;
   }
-  // 3D: cell-batched local matrices, then their row-owner sum; 2D: one
-  // row-owner pass (cheaper where a cell has 6 rows and 7 quadrature points)
+  // P2-P1 in 3D: cell-batched local matrices, then their row-owner sum;
+  // otherwise one row-owner pass (cheaper where a cell has 6 rows and 7
+  // quadrature points; P3-P2 local matrices are too large to store)
   const double cs = semi ? 1.0 : -1.0;
-  if (dim == 3) {
+  if (two_pass_conv()) {
     timer.run(stream, IPCS_KERNEL_ASM_CONV,
               [&] { asm_conv_cells(dim, mixed, stream, a22, nc, U, n2, 1.0 / prm.dt, cs, Eloc); });
     timer.run(stream, IPCS_KERNEL_ASM_SUM,
@@ -1183,12 +1191,14 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       case IPCS_KERNEL_PCG_UPDATE_P: pcg_update_only(stream, set_p.L, 0); break;
       case IPCS_KERNEL_ASM_CONV: {
         const double cs = prm.convection == IPCS_CONV_SEMI_IMPLICIT ? 1.0 : -1.0;
-        if (dim == 3) asm_conv_cells(dim, mixed, stream, a22, nc, U, n2, 1.0 / prm.dt, cs, Eloc);
+        if (two_pass_conv())
+          asm_conv_cells(dim, mixed, stream, a22, nc, U, n2, 1.0 / prm.dt, cs, Eloc);
         else asm_conv(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, U, n2, 1.0 / prm.dt, cs);
         break;
       }
       case IPCS_KERNEL_ASM_SUM:
-        if (dim != 3) fail(IPCS_E_INVALID, "the two-pass convection assembly is used in 3D only");
+        if (!two_pass_conv())
+          fail(IPCS_E_INVALID, "the two-pass convection assembly is used for P2-P1 in 3D only");
         asm_local_sum(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, Eloc);
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;

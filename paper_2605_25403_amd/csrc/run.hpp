@@ -217,9 +217,13 @@ struct Run {
   void sizes_from_mesh();
   void choose_poisson_form();
   void layout(Carver& c);
+  // convection in two passes (cell-batched local matrices, then their
+  // row-owner sum): the P2-P1 pair in 3D
+  bool two_pass_conv() const { return dim == 3 && mesh->pair == IPCS_PAIR_P2P1; }
   // points per cell of the pair's cell rule (the forcing quadrature)
   int cell_nq() const {
-    return mesh->pair == IPCS_PAIR_P3P2 ? RuleT9::NQ : dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
+    if (mesh->pair == IPCS_PAIR_P3P2) return dim == 2 ? RuleT9::NQ : RuleTet9::NQ;
+    return dim == 2 ? Rule<2>::NQ : Rule<3>::NQ;
   }
   void create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, int64_t bytes,
               hipStream_t s);

@@ -35,6 +35,7 @@ IPCS_SOL_TAYLOR_GREEN_2D, IPCS_SOL_JOHN_2D, IPCS_SOL_BELTRAMI_3D = 1, 2, 3
 IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D = 4, 5
 IPCS_SOL_POLY_CUBIC_2D = 6
 IPCS_SOL_STEADY_PAPER_2D = 7
+IPCS_SOL_POLY_CUBIC_3D = 8
 IPCS_STEADY_RESIDUAL, IPCS_STEADY_INCREMENT = 0, 1
 IPCS_PHASE_ASM, IPCS_PHASE_MOMENTUM, IPCS_PHASE_PRESSURE, IPCS_PHASE_CORRECTION = 0, 1, 2, 3
 IPCS_FIELD_U, IPCS_FIELD_P, IPCS_FIELD_USTAR, IPCS_FIELD_DP = 0, 1, 2, 3
@@ -110,6 +111,8 @@ _SIGS = {
     "ipcs_last_error": (C.c_char_p, []),
     "ipcs_mesh_unit_square": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_P)]),
     "ipcs_mesh_unit_cube": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "ipcs_mesh_unit_cube_pair": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                           C.POINTER(_P)]),
     "ipcs_mesh_from_arrays": (C.c_int, [C.c_int32, C.c_int64, _P, C.c_int64, _P, C.POINTER(_P)]),
     "ipcs_mesh_unit_square_pair": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "ipcs_mesh_from_arrays_pair": (C.c_int, [C.c_int32, C.c_int64, _P, C.c_int64, _P, C.c_int32,
@@ -122,6 +125,8 @@ _SIGS = {
     "ipcs_mesh_pattern": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
     "ipcs_mesh_p1_partition": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64)] + [_P] * 8),
     "ipcs_quadrature_rule": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), _P, _P, C.c_int64]),
+    "ipcs_quadrature_rule_pair": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), _P, _P,
+                                            C.c_int64]),
     "ipcs_mesh_destroy": (None, [_P]),
     "ipcs_params_default": (None, [C.POINTER(ipcs_params)]),
     "ipcs_run_workspace_bytes": (C.c_int, [_P, C.POINTER(ipcs_params), C.POINTER(C.c_int64)]),
@@ -202,6 +207,12 @@ def ipcs_mesh_unit_cube(nx, ny, nz):
     return h
 
 
+def ipcs_mesh_unit_cube_pair(nx, ny, nz, pair):
+    h = C.c_void_p()
+    _check(lib.ipcs_mesh_unit_cube_pair(nx, ny, nz, pair, C.byref(h)))
+    return h
+
+
 def ipcs_mesh_from_arrays(x, cells):
     x = np.ascontiguousarray(x, dtype=np.float64)
     cells = np.ascontiguousarray(cells, dtype=np.int32)
@@ -243,7 +254,8 @@ def ipcs_mesh_dof_coords(m, space):
 def ipcs_mesh_cell_dofs(m, space):
     c = ipcs_mesh_counts(m)
     if ipcs_mesh_pair(m) == IPCS_PAIR_P3P2:
-        nl = 6 if space == IPCS_SPACE_P1 else 10
+        p2, p3 = (6, 10) if c.dim == 2 else (10, 20)
+        nl = p2 if space == IPCS_SPACE_P1 else p3
     else:
         nl = c.dim + 1 if space == IPCS_SPACE_P1 else (6 if c.dim == 2 else 10)
     out = np.empty((c.nc, nl), dtype=np.int32)
@@ -294,6 +306,15 @@ def ipcs_quadrature_rule(dim):
     lam = np.empty((nq.value, dim + 1))
     w = np.empty(nq.value)
     _check(lib.ipcs_quadrature_rule(dim, C.byref(nq), _ptr(lam), _ptr(w), lam.size))
+    return lam, w
+
+
+def ipcs_quadrature_rule_pair(dim, pair):
+    nq = C.c_int32()
+    _check(lib.ipcs_quadrature_rule_pair(dim, pair, C.byref(nq), None, None, 0))
+    lam = np.empty((nq.value, dim + 1))
+    w = np.empty(nq.value)
+    _check(lib.ipcs_quadrature_rule_pair(dim, pair, C.byref(nq), _ptr(lam), _ptr(w), lam.size))
     return lam, w
 
 
@@ -463,8 +484,10 @@ class Mesh:
         return cls(ipcs_mesh_unit_square_pair(nx, ny or nx, pair))
 
     @classmethod
-    def unit_cube(cls, nx, ny=None, nz=None):
-        return cls(ipcs_mesh_unit_cube(nx, ny or nx, nz or nx))
+    def unit_cube(cls, nx, ny=None, nz=None, pair=IPCS_PAIR_P2P1):
+        if pair == IPCS_PAIR_P2P1:
+            return cls(ipcs_mesh_unit_cube(nx, ny or nx, nz or nx))
+        return cls(ipcs_mesh_unit_cube_pair(nx, ny or nx, nz or nx, pair))
 
     @classmethod
     def from_arrays(cls, x, cells, pair=IPCS_PAIR_P2P1):

@@ -24,7 +24,7 @@ def oracle_problem(kind, dim, nu, k=np.pi):
     if kind == "poly":
         return problems.PolySteady2D(nu) if dim == 2 else problems.PolySteady3D(nu)
     if kind == "cubic":
-        return problems.PolySteady2DCubic(nu)
+        return problems.PolySteady2DCubic(nu) if dim == 2 else problems.PolySteady3DCubic(nu)
     raise KeyError(kind)
 
 
@@ -32,7 +32,7 @@ def builtin_kind(I, kind, dim):
     return {"tg": I.IPCS_SOL_TAYLOR_GREEN_2D, "john": I.IPCS_SOL_JOHN_2D,
             "beltrami": I.IPCS_SOL_BELTRAMI_3D,
             "poly": I.IPCS_SOL_POLY_STEADY_2D if dim == 2 else I.IPCS_SOL_POLY_STEADY_3D,
-            "cubic": I.IPCS_SOL_POLY_CUBIC_2D}[kind]
+            "cubic": I.IPCS_SOL_POLY_CUBIC_2D if dim == 2 else I.IPCS_SOL_POLY_CUBIC_3D}[kind]
 
 
 def oracle_space(dim, n, order=2):
@@ -46,12 +46,12 @@ def make_pair(I, dim, n, kind, nu, dt, tol=1e-13, k=np.pi, t0=0.0, same_state=Tr
     same_state the library starts from the oracle's initial arrays. arrays =
     (x, cells) replaces the structured n-mesh by that mesh on both sides; semi
     selects the semi-implicit convection form, chorin the Chorin-Temam
-    projection and p3 the P3-P2 pair (triangles) on both sides."""
+    projection and p3 the P3-P2 pair on both sides."""
     order = 3 if p3 else 2
     pair = I.IPCS_PAIR_P3P2 if p3 else I.IPCS_PAIR_P2P1
     if arrays is None:
         S = oracle_space(dim, n, order)
-        m = I.Mesh.unit_square(n, pair=pair) if dim == 2 else I.Mesh.unit_cube(n)
+        m = I.Mesh.unit_square(n, pair=pair) if dim == 2 else I.Mesh.unit_cube(n, pair=pair)
     else:
         S = fem.Space(*arrays, order=order)
         m = I.Mesh.from_arrays(*arrays, pair=pair)

@@ -95,6 +95,31 @@ def test_library_quadrature_rules_are_degree_5_exact():
                 assert abs(got - ex) < 5e-17, (dim, alpha)
 
 
+@pytest.mark.parametrize("dim,nq,deg", [(2, 25, 8), (3, 125, 9)])
+def test_library_p3_p2_rules_are_exact_to_their_degree(dim, nq, deg):
+    """The P3-P2 cell rules (tetrahedra: nodes from the library's own
+    Gauss-Jacobi root finder) integrate every monomial in the barycentric
+    coordinates up to their degree to the closed-form simplex moment
+    prod(a_k!) / (|a| + dim)!, and are the oracle's rules point by point."""
+    from oracle import quadrature
+    lam, w = I.ipcs_quadrature_rule_pair(dim, I.IPCS_PAIR_P3P2)
+    assert lam.shape == (nq, dim + 1)
+    np.testing.assert_allclose(lam.sum(axis=1), 1.0, atol=1e-15)
+    assert np.all(w > 0) and np.all(lam >= 0)
+    for alpha in itertools.product(range(deg + 1), repeat=dim + 1):
+        if sum(alpha) <= deg:
+            ex = np.prod([factorial(a) for a in alpha]) / factorial(sum(alpha) + dim)
+            got = np.sum(w * np.prod(lam ** np.array(alpha), axis=1))
+            assert abs(got - ex) < 5e-17 + 1e-14 * ex, (dim, alpha)
+    lo, wo = quadrature.triangle_collapsed_gl(5) if dim == 2 else quadrature.tet_collapsed(5)
+    np.testing.assert_allclose(lam, lo, rtol=0, atol=2e-15)
+    np.testing.assert_allclose(w, wo, rtol=1e-14, atol=0)
+    l2, w2 = I.ipcs_quadrature_rule_pair(dim, I.IPCS_PAIR_P2P1)
+    l1, w1 = I.ipcs_quadrature_rule(dim)
+    np.testing.assert_array_equal(l2, l1)
+    np.testing.assert_array_equal(w2, w1)
+
+
 def test_invalid_arguments_are_reported():
     with pytest.raises(I.IpcsError) as e:
         I.ipcs_mesh_unit_square(0, 4)
@@ -156,27 +181,47 @@ def test_p3_p2_jittered_meshes_match_oracle(n, seed):
     compare(fem.Space(X, cells, order=3), I.Mesh.from_arrays(X, cells, pair=I.IPCS_PAIR_P3P2))
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_p3_p2_cube_matches_oracle_exactly(n):
+    """P3 on tetrahedra: vertices, two nodes per edge, one node per face (the
+    faces in the order of their sorted vertex triples), boundary faces'
+    nodes on the boundary."""
+    m = I.Mesh.unit_cube(n, pair=I.IPCS_PAIR_P3P2)
+    assert m.pair == I.IPCS_PAIR_P3P2
+    compare(fem.Space(*mesh.unit_cube(n, n, n), order=3), m)
+
+
+def test_p3_p2_jittered_tetrahedra_match_oracle():
+    from paper_2605_25403_amd.workloads import jittered_mesh
+    X, cells = jittered_mesh(3, 3, 1)
+    compare(fem.Space(X, cells, order=3), I.Mesh.from_arrays(X, cells, pair=I.IPCS_PAIR_P3P2))
+
+
 def test_pair_arguments_are_checked():
     with pytest.raises(I.IpcsError):
         I.ipcs_mesh_unit_square_pair(2, 2, 7)
+    with pytest.raises(I.IpcsError):
+        I.ipcs_mesh_unit_cube_pair(2, 2, 2, 7)
+    assert "pair" in I.ipcs_last_error()
     from paper_2605_25403_amd.workloads import jittered_mesh
     X, cells = jittered_mesh(3, 2, 0)
-    with pytest.raises(I.IpcsError) as e:
-        I.ipcs_mesh_from_arrays_pair(X, cells, I.IPCS_PAIR_P3P2)
-    assert "triangles" in I.ipcs_last_error()
+    with pytest.raises(I.IpcsError):
+        I.ipcs_mesh_from_arrays_pair(X, cells, -1)
     assert I.Mesh.unit_square(3).pair == I.IPCS_PAIR_P2P1
+    assert I.Mesh.from_arrays(X, cells, pair=I.IPCS_PAIR_P3P2).pair == I.IPCS_PAIR_P3P2
 
 
-@pytest.mark.parametrize("dim,n,pair", [(2, 3, 0), (3, 2, 0), (2, 3, 1)])
+@pytest.mark.parametrize("dim,n,pair", [(2, 3, 0), (3, 2, 0), (2, 3, 1), (3, 2, 1)])
 def test_interface_velocity_numbering_is_the_listing_order(dim, n, pair):
     """The velocity numbering of the interface, built here by brute force from
     the library's own vertex and cell tables (independently of the oracle): the
     vertices in input order, then the edges' nodes with the edges sorted by
     (lower, higher) vertex (P2: the midpoint; P3: the node at
     (2 x_lo + x_hi)/3, then the one at (x_lo + 2 x_hi)/3), then (P3) the cell
-    centroids in cell order. The library numbers these nodes differently inside
-    and converts at the interface."""
-    m = I.Mesh.unit_square(n, pair=pair) if dim == 2 else I.Mesh.unit_cube(n)
+    centroids in cell order (triangles) or the face centroids with the faces
+    sorted by vertex triple (tetrahedra). The library numbers these nodes
+    differently inside and converts at the interface."""
+    m = I.Mesh.unit_square(n, pair=pair) if dim == 2 else I.Mesh.unit_cube(n, pair=pair)
     c = I.ipcs_mesh_counts(m.h)
     xp = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P1).reshape(-1, dim)
     X = xp[:c.nv]
@@ -189,7 +234,12 @@ def test_interface_velocity_numbering_is_the_listing_order(dim, n, pair):
         nodes = [X]
         for a, b in edges:
             nodes += [(2.0 * X[a] + X[b]) / 3.0, (X[a] + 2.0 * X[b]) / 3.0]
-        nodes += [X[cell].mean(axis=0) for cell in cp]
+        if dim == 2:
+            nodes += [X[cell].mean(axis=0) for cell in cp]
+        else:
+            faces = sorted({tuple(sorted(int(v) for v in f)) for cell in cp
+                            for f in itertools.combinations(cell, 3)})
+            nodes += [(X[a] + X[b] + X[c]) / 3.0 for a, b, c in faces]
         want = np.vstack(nodes)
     x2 = I.ipcs_mesh_dof_coords(m.h, I.IPCS_SPACE_P2).reshape(-1, dim)
     assert x2.shape == want.shape
