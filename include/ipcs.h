@@ -162,7 +162,8 @@ int ipcs_mesh_pattern(ipcs_mesh m, int32_t which, int32_t* rowptr, int64_t cap_r
  * sptr[slice_ptr[p] + j] + 64 k + q), lcol[] (local columns: < own for the
  * part's rows, own + h for halo[halo_ptr[p] + h]) and src[] (entry index in
  * the global SELL-64 layout of the pattern, -1 for padding). The arrays must
- * be all NULL or all non-NULL and as large as sizes[] says. */
+ * be all NULL or all non-NULL (halo may be NULL when sizes[1] is 0) and as
+ * large as sizes[] says; IPCS_E_INVALID otherwise. */
 int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int32_t* perm,
                            int32_t* part_ptr, int32_t* halo_ptr, int32_t* halo,
                            int32_t* slice_ptr, int32_t* sptr, uint16_t* lcol, int32_t* src);
@@ -251,17 +252,28 @@ typedef struct {
  * (tol_ir 1e-10), maxit 20000, check_every 16, callbacks 0. */
 void ipcs_params_default(ipcs_params* p);
 
-/* Device workspace a run of this mesh needs (its whole HBM footprint). */
+/* Device workspace a run of this mesh needs (its whole HBM footprint): the
+ * matrices of eq. (9) (M, K, Kp, D_c, G_c, A, the convection matrix of
+ * Section 2.2.1), the fields U^n, P^n, U*, dP and the Krylov vectors of the
+ * three solves. *bytes receives the size; IPCS_E_INVALID for a bad mesh or
+ * parameters. The caller allocates it (device memory, 256-byte aligned). */
 int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes);
-/* Uploads the mesh data, assembles the constant matrices (M, K, Kp, D_c, G_c,
- * A = M/dt + nu K with Dirichlet rows/columns eliminated) on the device.
+/* Sets up one IPCS run (the time loop of Section 2.2.1 on the spaces of
+ * eqs. (4)-(5)): uploads the mesh data and assembles the constant matrices
+ * of eq. (9) (M, K, Kp, D_c, G_c, A = M/dt + nu K with Dirichlet rows/columns
+ * eliminated) on the device. dev_ws: the caller's device workspace of
+ * ws_bytes bytes (IPCS_E_NOMEM if smaller than ipcs_run_workspace_bytes); it
+ * stays owned by the caller and must outlive the run.
  * The initial state is zero until ipcs_set_state / ipcs_set_builtin_solution.
  * hip_stream is a hipStream_t (NULL = default stream). The mesh may be
  * destroyed afterwards. */
 int ipcs_run_create(ipcs_mesh m, const ipcs_params* p, void* dev_ws, int64_t ws_bytes,
                     void* hip_stream, ipcs_run* out);
-int ipcs_set_viscosity(ipcs_run r, double nu);    /* re-forms A before next step */
-int ipcs_set_time_step(ipcs_run r, double dt);    /* re-forms A before next step */
+/* nu of eq. (1) and dt of eq. (9); A = M/dt + nu K is re-formed (and its
+ * elimination and Jacobi diagonal) before the next step. IPCS_E_INVALID for
+ * nu < 0 or dt <= 0. */
+int ipcs_set_viscosity(ipcs_run r, double nu);
+int ipcs_set_time_step(ipcs_run r, double dt);
 
 /* Host callback evaluating a vector field at npts points x[npts*dim] at time
  * t into out[npts*dim]. */
@@ -330,8 +342,13 @@ enum { IPCS_PHASE_ASM = 0, IPCS_PHASE_MOMENTUM = 1, IPCS_PHASE_PRESSURE = 2,
  * order; ipcs_advance is equivalent to the four in sequence. */
 int ipcs_step_phase(ipcs_run r, int32_t phase, ipcs_step_stats* stats);
 
-int ipcs_get_velocity(ipcs_run r, double* u, int64_t cap);   /* [dim*N2] */
-int ipcs_get_pressure(ipcs_run r, double* p, int64_t cap);   /* [N1]     */
+/* Read-back of the discrete solution of eq. (9) after the last step: the
+ * velocity coefficients u_h in V_h (eq. (4)), [dim][N2] component-major, and
+ * the pressure p_h in Q_h (eq. (5)), [N1], in the interface numbering, into
+ * host memory of cap doubles (IPCS_E_INVALID if smaller); t^n. Synchronizes
+ * the run's stream. */
+int ipcs_get_velocity(ipcs_run r, double* u, int64_t cap);
+int ipcs_get_pressure(ipcs_run r, double* p, int64_t cap);
 int ipcs_get_time(ipcs_run r, double* t);
 
 enum { IPCS_FIELD_U = 0, IPCS_FIELD_P = 1, IPCS_FIELD_USTAR = 2, IPCS_FIELD_DP = 3,
@@ -471,8 +488,15 @@ typedef struct {
   float ms;             /* device time of the steps (stream events)            */
   int32_t reserved;
 } ipcs_steady_stats;
-/* Device workspace of a steady solve on this mesh (P2-P1 pair). */
+/* Device workspace of a steady solve on this mesh (P2-P1 pair; the blocks of
+ * the Newton system above, its monolithic layout, the FGMRES basis and the
+ * inner solver's vectors). IPCS_E_INVALID for another pair or bad
+ * parameters. */
 int ipcs_steady_workspace_bytes(ipcs_mesh m, const ipcs_steady_params* p, int64_t* bytes);
+/* Sets up a steady solve (Section 4.2's workflow) in the caller's workspace
+ * of ws_bytes bytes (IPCS_E_NOMEM if smaller than the size above; it stays
+ * owned by the caller and must outlive the solver): uploads the mesh and
+ * assembles nu K, D_c, G_c and the lumped pressure mass. */
 int ipcs_steady_create(ipcs_mesh m, const ipcs_steady_params* p, void* dev_ws,
                        int64_t ws_bytes, void* hip_stream, ipcs_steady* out);
 /* Closed-form data on the device (IPCS_SOL_STEADY_PAPER_2D,
@@ -487,8 +511,12 @@ int ipcs_steady_step(ipcs_steady s, ipcs_steady_stats* stats);
 /* Newton steps until the relative change is <= tol (IPCS_E_NOT_CONVERGED
  * after maxit steps). */
 int ipcs_steady_solve(ipcs_steady s, ipcs_steady_stats* stats);
-int ipcs_steady_get_velocity(ipcs_steady s, double* u, int64_t cap);   /* [dim*N2] */
-int ipcs_steady_get_pressure(ipcs_steady s, double* p, int64_t cap);   /* [N1]     */
+/* The current iterate, the discrete solution of the steady equations of
+ * Section 2.1 once converged: velocity [dim][N2] and pressure [N1] in the
+ * interface numbering, into host memory of cap doubles (IPCS_E_INVALID if
+ * smaller). */
+int ipcs_steady_get_velocity(ipcs_steady s, double* u, int64_t cap);
+int ipcs_steady_get_pressure(ipcs_steady s, double* p, int64_t cap);
 /* The last step's residual (right-hand side) or increment,
  * [dim*N2 + N1] in the interface numbering. */
 enum { IPCS_STEADY_RESIDUAL = 0, IPCS_STEADY_INCREMENT = 1 };

@@ -277,7 +277,9 @@ int ipcs_mesh_p1_partition(ipcs_mesh m, int32_t rows_max, int64_t sizes[5], int3
     sizes[4] = q->lds_max;
     const bool any = perm || part_ptr || halo_ptr || halo || slice_ptr || sptr || lcol || src;
     if (!any) return IPCS_OK;
-    need(perm && part_ptr && halo_ptr && halo && slice_ptr && sptr && lcol && src,
+    // an empty halo (one part) may come as NULL
+    need(perm && part_ptr && halo_ptr && (halo || q->halo.empty()) && slice_ptr && sptr &&
+             lcol && src,
          "partition arrays must be all NULL or all non-NULL");
     auto cp = [](auto* dst, const auto& v) {
       if (!v.empty()) std::memcpy(dst, v.data(), sizeof(v[0]) * v.size());

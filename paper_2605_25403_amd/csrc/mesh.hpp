@@ -72,17 +72,18 @@ struct PartSell {
 // vocabulary: "2" is the velocity space, "1" the pressure space.
 //   P2-P1 (triangles, tetrahedra): velocity P2 (vertices and edge midpoints),
 //   pressure P1 (vertices).
-//   P3-P2 (triangles): velocity P3 (vertices; two nodes per edge, at
-//   (2 x_lo + x_hi)/3 and (x_lo + 2 x_hi)/3 for sorted vertices lo < hi; one
-//   node per cell at its centroid), pressure P2 (vertices, then the edges
+//   P3-P2: velocity P3 (vertices; two nodes per edge, at (2 x_lo + x_hi)/3
+//   and (x_lo + 2 x_hi)/3 for sorted vertices lo < hi; one node per cell at
+//   its centroid (triangles) or per face at its centroid, the faces sorted by
+//   their vertex triples (tetrahedra)), pressure P2 (vertices, then the edges
 //   sorted by (lo, hi)).
 // Velocity DOFs, internal numbering (every array below): the vertices in input
 // order, then the other velocity nodes in lexicographic order of their
 // coordinates (last coordinate most significant), so that neighbouring nodes
 // have neighbouring indices. The interface numbering differs: the vertices,
 // then the other nodes in listing order (P2: the edge midpoints with the edges
-// sorted by (lo, hi); P3: two nodes per edge in edge order, then the cell
-// centroids). v_out maps internal to interface ids, v_in back.
+// sorted by (lo, hi); P3: two nodes per edge in edge order, then the cell or
+// face centroids). v_out maps internal to interface ids, v_in back.
 // A cell's local velocity DOFs start with its vertices. Kernels take the cell
 // geometry from the pressure cell table, which starts with the vertex ids in
 // both pairs (P1: the vertices; P2: vertices, then edges).
