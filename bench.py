@@ -168,7 +168,18 @@ def cpu_baseline(w, budget_steps=3):
         o.step()
         dt1 = time.perf_counter() - t1
     ndof = dim * S.Nu + S.Np
-    return {"value": ndof * budget_steps / dt, "unit": "DOF-steps/s",
+    # the steady solver's oracle (Newton with sparse direct solves) on the
+    # Section 4.2 example at its largest printed size, 64 x 64 squares
+    from oracle import steady
+    Ss = fem.Space(*mesh.unit_square(64, 64))
+    so = steady.SteadyNewton(Ss, problems.SteadyPaper2D(1.0), 1.0)
+    t2 = time.perf_counter()
+    so.run()
+    dts = time.perf_counter() - t2
+    steady_cpu = {"n": 64, "dofs": 2 * Ss.Nu + Ss.Np, "newton_steps": len(so.history),
+                  "seconds": dts,
+                  "dof_newton_steps_per_s": (2 * Ss.Nu + Ss.Np) * len(so.history) / dts}
+    return {"value": ndof * budget_steps / dt, "unit": "DOF-steps/s", "steady_newton": steady_cpu,
             "cores": int(threads), "kind": "oracle",
             "sample": f"the first {budget_steps} of {w['steps']} IPCS steps of the same workload "
                       f"from the interpolated initial state ({dt:.1f} s; setup not timed; "
@@ -404,22 +415,31 @@ def scheme_forms(w, steps, torch, I):
     return out
 
 
-def pair_forms(w, steps, torch, I):
-    """The P3-P2 pair against P2-P1 on 2D Taylor-Green (the workload's k, nu,
-    dt, tolerance; FP64), with the same pressure system size: P2-P1 on the
-    workload's n x n squares, P3-P2 on n/2 x n/2 (both pressure spaces have
-    (n+1)^2 nodes). Per pair: throughput, iterations, per-launch times of the
-    convection assembly and the Poisson CG, and the nodal relative L2
-    distance to the interpolated exact solution after `steps` steps."""
+def pair_forms(w, steps, torch, I, dim=2, n=None):
+    """The P3-P2 pair against P2-P1 with the same pressure system size: P2-P1
+    on n^d cells, P3-P2 on (n/2)^d (both pressure spaces have (n+1)^d nodes).
+    2D: Taylor-Green with the workload's k, nu, dt and tolerance; 3D: Beltrami
+    (a = pi/4, d = pi/2) with nu = 0.01, dt = 1e-3, tol 1e-12. FP64. Per pair:
+    throughput, iterations, per-launch times of the convection assembly and
+    the Poisson CG, and the nodal relative L2 distance to the interpolated
+    exact solution after `steps` steps."""
     out = {"steps": steps}
-    for name, pair, n in (("p2p1", I.IPCS_PAIR_P2P1, w["n"]),
-                          ("p3p2", I.IPCS_PAIR_P3P2, w["n"] // 2)):
-        m = I.Mesh.unit_square(n, pair=pair)
-        c = m.counts
-        ndof = 2 * c.n2 + c.n1
+    if dim == 2:
+        n = n or w["n"]
+        kind, prm = I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],)
         base = dict(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"], tol_corr=w["tol"])
+        mk = lambda nn, pair: I.Mesh.unit_square(nn, pair=pair)
+    else:
+        kind, prm = I.IPCS_SOL_BELTRAMI_3D, ()
+        base = dict(nu=0.01, dt=1e-3, tol_mom=1e-12, tol_p=1e-12, tol_corr=1e-12)
+        mk = lambda nn, pair: I.Mesh.unit_cube(nn, pair=pair)
+    out["n"] = n
+    for name, pair, nn in (("p2p1", I.IPCS_PAIR_P2P1, n), ("p3p2", I.IPCS_PAIR_P3P2, n // 2)):
+        m = mk(nn, pair)
+        c = m.counts
+        ndof = dim * c.n2 + c.n1
         r = I.Run(m, I.ipcs_params_default(**base), stream=torch.cuda.Stream())
-        r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        r.set_builtin(kind, prm)
         lat, it_p = [], []
         for _ in range(steps):
             t0 = time.perf_counter()
@@ -427,7 +447,7 @@ def pair_forms(w, steps, torch, I):
             lat.append(time.perf_counter() - t0)
             it_p.append(st["it_p"])
         ex = I.Run(m, I.ipcs_params_default(t0=r.time(), **base))
-        ex.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        ex.set_builtin(kind, prm)
         Ue, Pe = ex.velocity(), ex.pressure()
         eu = float(np.linalg.norm(r.velocity() - Ue) / np.linalg.norm(Ue))
         ep = float(np.linalg.norm(r.pressure() - Pe) / np.linalg.norm(Pe))
@@ -441,14 +461,19 @@ def pair_forms(w, steps, torch, I):
         us = lambda k: 1000.0 * kms[k] / kcnt[k] if kcnt[k] else None
         ms = 1000.0 * float(np.median(lat))
         fus = us(I.IPCS_KERNEL_PCG_FUSED_P)
-        fgb = kernel_bytes("pcg_fused_p", c, 2, 8) / (fus * 1e-6) / 1e9 if fus else None
-        out[name] = {"n": n, "dofs": int(ndof), "velocity_dofs_per_component": int(c.n2),
+        fgb = kernel_bytes("pcg_fused_p", c, dim, 8) / (fus * 1e-6) / 1e9 if fus else None
+        asm = us(I.IPCS_KERNEL_ASM_CONV)
+        if dim == 3 and pair == I.IPCS_PAIR_P2P1:
+            asm = (asm or 0.0) + (us(I.IPCS_KERNEL_ASM_SUM) or 0.0)
+        out[name] = {"n": nn, "dofs": int(ndof), "velocity_dofs_per_component": int(c.n2),
                      "pressure_dofs": int(c.n1), "value": ndof / (ms / 1000.0),
                      "p50_step_ms": ms, "pressure_iterations_median": float(np.median(it_p)),
-                     "asm_conv_us": us(I.IPCS_KERNEL_ASM_CONV),
+                     "asm_conv_us": asm,
                      "pcg_fused_p_us": fus, "pcg_fused_p_GBps": fgb,
                      "pcg_fused_p_frac_of_hbm_peak": fgb / PEAK_HBM_GBS if fgb else None,
                      "rel_l2_to_exact_u": eu, "rel_l2_to_exact_p": ep}
+        del r
+        torch.cuda.empty_cache()
     return out
 
 
@@ -590,6 +615,33 @@ def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
                           "n in {32,64,128,256}, 50 steps at dt=1e-3, mixed form, "
                           f"max_slots {max_slots}, lanes {[list(l) for l in lanes]}")
     return report
+
+
+def steady_form(torch, I, sizes=(64, 128)):
+    """Steady Navier-Stokes by Newton's method (the Section 4.2 example,
+    nu = 1, tol 1e-10) on n x n squares: n = 64 is the largest mesh of the
+    paper's table "convergence_data" (33,282 velocity DOFs). Per size: DOFs,
+    Newton steps, FGMRES and inner BiCGStab iterations, wall and device time
+    of the solve, and DOF-Newton-steps/s."""
+    out = {}
+    for n in sizes:
+        m = I.Mesh.unit_square(n)
+        s = I.Steady(m, nu=1.0)
+        s.set_builtin(I.IPCS_SOL_STEADY_PAPER_2D)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.solve()
+        wall = time.perf_counter() - t0
+        c = m.counts
+        ndof = 2 * c.n2 + c.n1
+        out[str(n)] = {"dofs": int(ndof), "newton_steps": st["newton_steps"],
+                       "fgmres_iterations": st["lin_it"], "inner_iterations": st["inner_it"],
+                       "wall_ms": 1000.0 * wall, "device_ms": st["ms"],
+                       "ms_per_fgmres_iteration": 1000.0 * wall / max(1, st["lin_it"]),
+                       "rel_change": st["rel_change"],
+                       "dof_newton_steps_per_s": ndof * st["newton_steps"] / wall}
+        del s
+    return out
 
 
 def c4_form(torch, I, steps=10, warmup=2):
@@ -833,9 +885,11 @@ def main():
                          ("schemes", lambda: scheme_forms(w, args.form_steps, torch, I)),
                          ("serving", lambda: serving_form(torch, I)),
                          ("c4", lambda: c4_form(torch, I)),
+                         ("steady", lambda: steady_form(torch, I)),
                          ("pairs", lambda: pair_forms(w, args.form_steps, torch, I)),
+                         ("pairs_3d", lambda: pair_forms(w, args.form_steps, torch, I, 3, 32)),
                          ("seeds", lambda: seed_forms(w, 20, torch, I))):
-            if name in ("pairs", "seeds") and w["dim"] != 2:
+            if name in ("pairs", "pairs_3d", "seeds") and w["dim"] != 2:
                 continue
             out["forms"][name] = fn()
             torch.cuda.empty_cache()
