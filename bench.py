@@ -726,6 +726,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--poisson-s", type=int, default=0,
+                    help="CG iterations per launch of the one-kernel Poisson CG (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=5,
                     help="steps after the timed region with per-launch kernel timing")
@@ -773,7 +775,8 @@ def main():
     m = I.Mesh.unit_square(n, pair=w.get("pair", 0)) if dim == 2 else I.Mesh.unit_cube(n)
     p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
                               tol_corr=w["tol"],
-                              precision=I.IPCS_MIXED if mixed else I.IPCS_FP64)
+                              precision=I.IPCS_MIXED if mixed else I.IPCS_FP64,
+                              poisson_s=args.poisson_s)
     stream = torch.cuda.Stream()
     r = I.Run(m, p, stream=stream)
     if dim == 2:
@@ -800,6 +803,9 @@ def main():
     it_p = float(np.median([s["it_p"] for s in stats]))
     it_m = float(np.median([max(s["it_mom"][:dim]) for s in stats]))
     it_c = float(np.median([max(s["it_corr"][:dim]) for s in stats]))
+    # CG iterations per launch of the one-kernel Poisson CG (two for s-step
+    # CG): the byte models count that many iterations per launch
+    ipl = 2 if args.poisson_s == 2 else 1
     r.kernel_timing((1 << I.IPCS_NKERNEL) - 1 if args.kernel_steps > 0 else 0)
     kstats = [r.advance(1)[0] for _ in range(args.kernel_steps)]
     torch.cuda.synchronize()
@@ -812,6 +818,8 @@ def main():
             continue
         us = 1000.0 * kms[kid] / kcnt[kid]
         b = kernel_bytes(name, c, dim, 4 if mixed else 8, p3)
+        if name == "pcg_fused_p":
+            b *= ipl
         kern[name] = {"us_per_launch": us, "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
                       "launches_per_step": kcnt[kid] / ksteps,
                       "ms_per_step": kms[kid] / ksteps}
@@ -820,6 +828,8 @@ def main():
         dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
         vb = 4 if mixed else 8
         ub = unit_bytes(dom, c, dim, vb)
+        if ub is not None and dom == "pcg_fused_p":
+            ub *= ipl
         us = kern[dom]["us_per_launch"]
         b = ub if ub is not None else kern[dom]["bytes"]
         ach = b / (us * 1e-6) / 1e9

@@ -245,7 +245,12 @@ typedef struct {
                            * it does not fit); -1 two kernels per iteration
                            * (SpMV, then the vector update)                  */
   int32_t scheme;       /* IPCS_SCHEME_IPCS (default) or IPCS_SCHEME_CHORIN    */
-  int32_t reserved;
+  int32_t poisson_s;    /* CG iterations per launch of the one-kernel Poisson
+                         * CG: 1 (Chronopoulos-Gear CG) or 2 (s-step CG: two
+                         * iterations of the same Jacobi-PCG per launch, from
+                         * a basis of the matrix powers and one reduction of
+                         * its Gram matrix; needs the part's second halo ring
+                         * in LDS); 0 (default) chooses 1                    */
 } ipcs_params;
 
 /* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12

@@ -81,11 +81,12 @@ struct Plan {
 // Plans the shared sets for system set `which` (0 momentum, 1 Poisson,
 // 2 correction) of the given runs; returns the bytes their descriptors take.
 size_t plan_shared(const std::vector<Run*>& runs, int which, std::vector<Plan>& plans) {
-  // fused Poisson sets: (1, rows per thread, value type); others: (0, ns, ept_m, value type)
+  // fused Poisson sets: (1, iterations per launch, rows per thread, value type);
+  // others: (0, ns, ept_m, value type)
   std::map<std::tuple<int, int, int, int>, std::vector<Run*>> cls;
   for (Run* r : runs) {
     const KSet& K = set_of(*r, which);
-    if (K.fused) cls[{1, 1, K.F.ept, K.F.fp32}].push_back(r);
+    if (K.fused) cls[{1, K.F.ipl, K.F.ept, K.F.fp32}].push_back(r);
     else cls[{0, K.L.ns, K.L.ept_m, K.L.fp32}].push_back(r);
   }
   // sizes
@@ -194,6 +195,7 @@ std::vector<Shared> make_shared(const std::vector<Run*>& runs, int which, hipStr
       S.F = FLaunch{reinterpret_cast<const FGroup*>(base + p.o_fgroups), (int)p.rs.size(),
                     F0.ept, F0.fp32, reinterpret_cast<const int2*>(base + p.o_bf),
                     (int)p.bf.size(), lds};
+      S.F.ipl = F0.ipl;
     }
     S.last_iters = last;
     S.us_per_launch = us;

@@ -84,6 +84,7 @@ void check_params(const ipcs_params* p) {
   need(p->convection == IPCS_CONV_EXPLICIT || p->convection == IPCS_CONV_SEMI_IMPLICIT,
        "unknown convection form");
   need(p->precision == IPCS_FP64 || p->tol_ir > 0, "the mixed form needs tol_ir > 0");
+  need(p->poisson_s >= 0 && p->poisson_s <= 2, "poisson_s must be 0, 1 or 2");
   need(p->poisson_part_rows == 0 || p->poisson_part_rows == -1 ||
            (p->poisson_part_rows >= 64 && p->poisson_part_rows <= 2048),
        "poisson_part_rows must be 0, -1 or in [64, 2048]");

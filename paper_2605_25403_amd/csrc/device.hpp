@@ -118,7 +118,19 @@ struct FGroup {
   double* part[2];            // [KP][nparts] SoA partials by parity
   double* part_s;             // start partials [r.r, b.b]
   KState* st;
-  int32_t maxit, pad;
+  int32_t maxit;
+  int32_t ipl;                // CG iterations per launch (1 or 2)
+  // two iterations per launch: the second halo ring, the halo rows' slices
+  // (local columns over own, halo and second ring) and values, and the
+  // basis p, B p, B^2 p, z, B z ([5][n], part order) by launch parity; the
+  // Gram partials take 16 values per part in part[]
+  const int32_t* halo2_ptr;   // [nparts+1]
+  const int32_t* halo2;
+  const int32_t* hslice_ptr;  // [nparts+1]
+  const int32_t* hsptr;
+  const uint16_t* hlcol;
+  const void* hval;
+  double* y[2];
 };
 
 // Row-owner assembly inputs (see mesh.hpp)
@@ -264,6 +276,7 @@ struct FLaunch {
   const FBlk* blk;
   const int32_t* hfirst;
   FGroup one;
+  int ipl = 1;       // CG iterations per launch of every group
 };
 // Mode 0: x and b to part order, r = b - A x, w = A D^{-1} r, status decision.
 // Mode 1 (systems PENDING or RESTART): the same from the current iterate.

@@ -66,6 +66,20 @@ struct PartSell {
   std::vector<int32_t> sptr;        // [nslices+1] entry offsets
   std::vector<uint16_t> lcol;       // [nent]
   std::vector<int32_t> src;         // [nent]
+  // depth 2 (two CG iterations per launch): the second ring halo2 (the
+  // columns the halo rows reference outside the part and its halo, sorted,
+  // local indices own + nhalo + q) and a SELL-64 layout of each part's halo
+  // rows (local row q = the q-th halo row) with local columns over own, halo
+  // and halo2; hsrc as src
+  int depth = 1;
+  int lds2_max = 0;                 // largest own + halo + halo2 count of a part
+  int64_t hnent = 0;
+  std::vector<int32_t> halo2_ptr;   // [nparts+1]
+  std::vector<int32_t> halo2;       // part-order rows
+  std::vector<int32_t> hslice_ptr;  // [nparts+1] first halo-row slice of each part
+  std::vector<int32_t> hsptr;       // [nhslices+1] entry offsets
+  std::vector<uint16_t> hlcol;      // [hnent]
+  std::vector<int32_t> hsrc;        // [hnent]
 };
 
 // The Taylor-Hood pair fixes the two spaces. Names keep the P2-P1 pair's
@@ -117,7 +131,8 @@ struct Mesh {
   const Sell& sell(int which) const;
   // partition of the pressure-pressure pattern by the pressure node
   // coordinates, built on first use for each part size and kept with the mesh
-  std::shared_ptr<const PartSell> parts11(int rows_max) const;
+  // (depth 2: with the second halo ring, for two CG iterations per launch)
+  std::shared_ptr<const PartSell> parts11(int rows_max, int depth = 1) const;
 
  private:
   mutable std::mutex parts_mu;
@@ -128,7 +143,7 @@ struct Mesh {
 void build_sell(const Pattern& P, Sell& S);
 
 std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, const double* X,
-                                            int dim, int rows_max);
+                                            int dim, int rows_max, int depth = 1);
 
 // Builders. All throw ipcs::Error on invalid input.
 Mesh* build_unit_square(int nx, int ny, int pair = 0);

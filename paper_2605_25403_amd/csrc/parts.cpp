@@ -49,11 +49,87 @@ void rcb(std::vector<int32_t>& idx, size_t lo, size_t hi, int64_t k, const doubl
   rcb(idx, lo + n1, hi, k - k1, X, dim, sizes);
 }
 
+// The second halo ring of every part and the SELL-64 slices of its halo rows
+// (two CG iterations per launch: a block forms B p on its own and halo rows,
+// which read p on the second ring too).
+void build_second_ring(const Pattern& P, const Sell& S, const std::vector<int32_t>& iperm,
+                       PartSell& R) {
+  R.halo2_ptr.assign(R.nparts + 1, 0);
+  R.hslice_ptr.assign(R.nparts + 1, 0);
+  R.hsptr.assign(1, 0);
+  R.halo2.clear();
+  R.hlcol.clear();
+  R.hsrc.clear();
+  R.lds2_max = 0;
+  std::vector<int32_t> h2;
+  for (int p = 0; p < R.nparts; ++p) {
+    const int32_t p0 = R.part_ptr[p], p1 = R.part_ptr[p + 1], own = p1 - p0;
+    const int32_t* hb = R.halo.data() + R.halo_ptr[p];
+    const int32_t* he = R.halo.data() + R.halo_ptr[p + 1];
+    const int nh = (int)(he - hb);
+    auto in_halo = [&](int32_t c) { return std::binary_search(hb, he, c); };
+    h2.clear();
+    for (const int32_t* hp = hb; hp != he; ++hp) {
+      const int32_t o = R.perm[*hp];
+      for (int32_t q = P.rowptr[o]; q < P.rowptr[o + 1]; ++q) {
+        const int32_t c = iperm[P.col[q]];
+        if ((c < p0 || c >= p1) && !in_halo(c)) h2.push_back(c);
+      }
+    }
+    std::sort(h2.begin(), h2.end());
+    h2.erase(std::unique(h2.begin(), h2.end()), h2.end());
+    const int64_t local = (int64_t)own + nh + (int64_t)h2.size();
+    if (local > 65535) fail(IPCS_E_CAPACITY, "a part's two halo rings reference too many rows");
+    R.lds2_max = std::max<int>(R.lds2_max, (int)local);
+    R.halo2.insert(R.halo2.end(), h2.begin(), h2.end());
+    R.halo2_ptr[p + 1] = (int32_t)R.halo2.size();
+    auto loc = [&](int32_t c) -> uint16_t {
+      if (c >= p0 && c < p1) return (uint16_t)(c - p0);
+      const int32_t* f = std::lower_bound(hb, he, c);
+      if (f != he && *f == c) return (uint16_t)(own + (f - hb));
+      return (uint16_t)(own + nh + (std::lower_bound(h2.begin(), h2.end(), c) - h2.begin()));
+    };
+    const int nsl = (nh + 63) / 64;
+    for (int sl = 0; sl < nsl; ++sl) {
+      int w = 0;
+      for (int lane = 0; lane < 64; ++lane) {
+        const int q = 64 * sl + lane;
+        if (q < nh) w = std::max(w, P.rowptr[R.perm[hb[q]] + 1] - P.rowptr[R.perm[hb[q]]]);
+      }
+      const int64_t base = R.hsptr.back();
+      if (base + 64ll * w >= (int64_t(1) << 31)) fail(IPCS_E_CAPACITY, "partition too large");
+      R.hlcol.resize(base + 64ll * w);
+      R.hsrc.resize(base + 64ll * w);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int q = 64 * sl + lane;
+        const int32_t o = q < nh ? R.perm[hb[q]] : -1;
+        const int len = o >= 0 ? P.rowptr[o + 1] - P.rowptr[o] : 0;
+        uint16_t last = o >= 0 ? (uint16_t)(own + q) : 0;
+        for (int k = 0; k < w; ++k) {
+          const int64_t e = base + 64ll * k + lane;
+          if (k < len) {
+            last = loc(iperm[P.col[P.rowptr[o] + k]]);
+            R.hlcol[e] = last;
+            R.hsrc[e] = (int32_t)S.index(o, k);
+          } else {
+            R.hlcol[e] = last;
+            R.hsrc[e] = -1;
+          }
+        }
+      }
+      R.hsptr.push_back((int32_t)(base + 64ll * w));
+    }
+    R.hslice_ptr[p + 1] = R.hslice_ptr[p] + nsl;
+  }
+  R.hnent = R.hsptr.back();
+}
+
 }  // namespace
 
 std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, const double* X,
-                                            int dim, int rows_max) {
+                                            int dim, int rows_max, int depth) {
   if (P.nrows != P.ncols) fail(IPCS_E_INVALID, "partition of a non-square pattern");
+  if (depth != 1 && depth != 2) fail(IPCS_E_INVALID, "partition halo depth must be 1 or 2");
   if (rows_max < 64 || rows_max > 4096)
     fail(IPCS_E_INVALID, "rows per part must be in [64, 4096]");
   auto out = std::make_shared<PartSell>();
@@ -140,14 +216,16 @@ std::shared_ptr<const PartSell> build_parts(const Pattern& P, const Sell& S, con
     R.slice_ptr[p + 1] = R.slice_ptr[p] + nsl;
   }
   R.nent = R.sptr.back();
+  R.depth = depth;
+  if (depth == 2) build_second_ring(P, S, iperm, R);
   return out;
 }
 
-std::shared_ptr<const PartSell> Mesh::parts11(int rows_max) const {
+std::shared_ptr<const PartSell> Mesh::parts11(int rows_max, int depth) const {
   std::lock_guard<std::mutex> lk(parts_mu);
   for (auto& q : parts_cache)
-    if (q->rows_max == rows_max) return q;
-  auto q = build_parts(p11, e11, xp.data(), dim, rows_max);
+    if (q->rows_max == rows_max && q->depth == depth) return q;
+  auto q = build_parts(p11, e11, xp.data(), dim, rows_max, depth);
   parts_cache.push_back(q);
   return q;
 }

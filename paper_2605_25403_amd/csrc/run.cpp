@@ -199,6 +199,7 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
       for (int j = 0; j < S.h_groups[g].nsys; ++j) f(hs[g * GMAX + j]);
   };
   const bool fused = m == KMethod::PCG && S.fused;
+  int ipl = fused ? S.F.ipl : 1;   // iterations per launch
   auto iterate = [&](int par) {
     if (fused) {
       T.run(s, S.kid[0], [&] { fcg_iter(s, S.F, par); });
@@ -289,56 +290,89 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
           : every;
   bool restarted = false;
   int tail = 0;   // polls made in the unknown tail of the solve
-  for (;;) {
-    bool run = false;
-    each([&](const KState& k) { run |= (k.status == KS_RUN); });
-    if (!run) break;
-    // groups whose cap is reached stop (on the device too), the others go on
-    bool stopped = false;
-    for (int g = 0; g < S.L.ngroups; ++g) {
-      if (launched < S.h_groups[g].maxit) continue;
-      bool here = false;
-      for (int j = 0; j < S.h_groups[g].nsys; ++j) {
-        KState& k = hs[g * GMAX + j];
-        if (k.status == KS_RUN) {
-          k.status = KS_MAXIT;
-          here = true;
-        }
-      }
-      if (here) stop_group(s, S.L, g);
-      stopped |= here;
-    }
-    if (stopped) continue;
-    const int rem = remaining();
-    // after a restart, or past the previous solve's length, the remaining
-    // iterations are unknown: chunks grow geometrically from the least one
-    int chunk;
-    if (restarted || launched >= S.last_iters) {
-      chunk = least << std::min(tail, 10);
-      ++tail;
-    } else {
-      chunk = std::max(least, (S.last_iters - launched) / 2);
-    }
-    chunk = std::max(1, std::min(chunk, rem));
-    if (burst(true, [&] {
-          for (int k = 0; k < chunk; ++k) {
-            iterate(par);
-            par ^= 1;
+  auto iterations = [&]() {
+    for (;;) {
+      bool run = false;
+      each([&](const KState& k) { run |= (k.status == KS_RUN); });
+      if (!run) break;
+      // groups whose cap is reached stop (on the device too), the others go on
+      bool stopped = false;
+      for (int g = 0; g < S.L.ngroups; ++g) {
+        if (launched < S.h_groups[g].maxit) continue;
+        bool here = false;
+        for (int j = 0; j < S.h_groups[g].nsys; ++j) {
+          KState& k = hs[g * GMAX + j];
+          if (k.status == KS_RUN) {
+            k.status = KS_MAXIT;
+            here = true;
           }
-        }))
-      timed_launches += chunk;
-    launched += chunk;
-    fetch();
-    compact();
-    bool pend = false;
-    each([&](const KState& k) { pend |= (k.status == KS_PENDING || k.status == KS_RESTART); });
-    if (pend) {
+        }
+        if (here) stop_group(s, S.L, g);
+        stopped |= here;
+      }
+      if (stopped) continue;
+      const int rem = remaining();
+      // after a restart, or past the previous solve's length, the remaining
+      // iterations are unknown: chunks (of launches) grow geometrically from
+      // the least one
+      int chunk;
+      if (restarted || launched >= S.last_iters) {
+        chunk = least << std::min(tail, 10);
+        ++tail;
+      } else {
+        chunk = std::max(least, (S.last_iters - launched) / 2 / ipl);
+      }
+      chunk = std::max(1, std::min(chunk, (rem + ipl - 1) / ipl));
+      if (burst(true, [&] {
+            for (int k = 0; k < chunk; ++k) {
+              iterate(par);
+              par ^= 1;
+            }
+          }))
+        timed_launches += chunk;
+      launched += chunk * ipl;
+      fetch();
+      compact();
+      bool pend = false;
+      each([&](const KState& k) { pend |= (k.status == KS_PENDING || k.status == KS_RESTART); });
+      if (pend) {
+        burst(false, [&] { start(1); });
+        fetch();
+        bool again = false;
+        each([&](const KState& k) { again |= k.status == KS_RUN; });
+        if (again && !restarted) tail = 0;
+        restarted |= again;
+      }
+    }
+  };
+  iterations();
+  // Two iterations per launch (s-step CG) reach a less accurate true residual
+  // than one: where its checks stall above the tolerance, the system restarts
+  // from its iterate with one iteration per launch, which takes it the rest
+  // of the way. (A system alone and in a batch stalls at the same point, so
+  // the switch keeps their results equal.)
+  if (fused && ipl == 2) {
+    bool any = false;
+    for (int g = 0; g < S.L.ngroups; ++g)
+      for (int j = 0; j < S.h_groups[g].nsys; ++j) {
+        const int idx = g * GMAX + j;
+        if (hs[idx].status != KS_STALL) continue;
+        KState k = hs[idx];
+        k.status = KS_RESTART;
+        k.nstall = 0;
+        pinned[idx] = k;
+        hs[idx] = k;
+        HIP_OK(hipMemcpyAsync(S.h_groups[g].v[j].st, &pinned[idx], sizeof(KState),
+                              hipMemcpyHostToDevice, s));
+        any = true;
+      }
+    if (any) {
+      S.F.ipl = ipl = 1;
       burst(false, [&] { start(1); });
       fetch();
-      bool again = false;
-      each([&](const KState& k) { again |= k.status == KS_RUN; });
-      if (again && !restarted) tail = 0;
-      restarted |= again;
+      if (!restarted) tail = 0;
+      restarted = true;
+      iterations();
     }
   }
   int iters = 0;
@@ -407,19 +441,26 @@ constexpr int kFcgRows = 384;
 void Run::choose_poisson_form() {
   pp.reset();
   fcg_ept = 0;
+  fcg_s = 1;
   f_blk_ok = false;
   const int req = prm.poisson_part_rows;
   if (req < 0) return;
-  auto q = mesh->parts11(req > 0 ? req : kFcgRows);
+  const int s = prm.poisson_s == 2 ? 2 : 1;
+  auto q = mesh->parts11(req > 0 ? req : kFcgRows, s);
   int biggest = 0;
   for (int p = 0; p < q->nparts; ++p)
     biggest = std::max(biggest, q->part_ptr[p + 1] - q->part_ptr[p]);
-  const bool fits = q->lds_max <= kFcgLocalMax && q->nparts <= KNB_MAX;
+  // LDS of a block (8 bytes per local value): one iteration per launch, u
+  // over own and halo rows; two, p and z over own, halo and second ring and
+  // B p over own and halo rows
+  const int64_t local = s == 2 ? 2 * (int64_t)q->lds2_max + q->lds_max : q->lds_max;
+  const bool fits = local <= kFcgLocalMax && q->nparts <= KNB_MAX;
   if (!fits) {
-    if (req > 0)
+    if (req > 0 || s == 2)
       fail(IPCS_E_CAPACITY, "the Poisson partition's parts reference more rows than fit in LDS");
     return;
   }
+  fcg_s = s;
   pp = q;
   for (int e : {1, 2, 4, 8})
     if (KBS * e >= biggest) {
@@ -528,11 +569,24 @@ void Run::layout(Carver& c) {
     f_xp = c.take<double>(n1);
     f_p = c.take<double>(n1);
     f_vec = c.take<double>(6 * n1);
-    for (int k = 0; k < 2; ++k) f_part[k] = c.take<double>((int64_t)KP * q.nparts);
+    // partials: 3 values per part (one iteration per launch), or the 16 of the
+    // Gram matrix and ||r||^2 (two)
+    const int kp = fcg_s == 2 ? 2 * KP : KP;
+    for (int k = 0; k < 2; ++k) f_part[k] = c.take<double>((int64_t)kp * q.nparts);
     f_part_s = c.take<double>((int64_t)KP * q.nparts);
     f_bmap = c.take<int2>(q.nparts);
     f_blk = c.take<FBlk>(q.nparts);
     f_hfirst = c.take<int32_t>((int64_t)KBS * q.nparts);
+    if (fcg_s == 2) {
+      f_h2ptr = c.take<int32_t>(q.nparts + 1);
+      f_h2 = c.take<int32_t>(std::max<int64_t>((int64_t)q.halo2.size(), 1));
+      f_hsl = c.take<int32_t>(q.nparts + 1);
+      f_hsptr = c.take<int32_t>((int64_t)q.hsptr.size());
+      f_hsrc = c.take<int32_t>(std::max<int64_t>(q.hnent, 1));
+      f_hlcol = c.take<uint16_t>(std::max<int64_t>(q.hnent, 1));
+      f_hval = c.take<char>(std::max<int64_t>(q.hnent, 1) * vsz);
+      f_y = c.take<double>(10 * n1);
+    }
     fgroup = c.take<FGroup>(1);
   }
   spart = c.take<double>(8192 * 2);
@@ -596,6 +650,14 @@ void Run::upload_mesh() {
     up(stream, f_sptr, q.sptr);
     up(stream, f_src, q.src);
     up(stream, f_lcol, q.lcol);
+    if (fcg_s == 2) {
+      up(stream, f_h2ptr, q.halo2_ptr);
+      up(stream, f_h2, q.halo2);
+      up(stream, f_hsl, q.hslice_ptr);
+      up(stream, f_hsptr, q.hsptr);
+      up(stream, f_hsrc, q.hsrc);
+      up(stream, f_hlcol, q.hlcol);
+    }
     std::vector<int2> bm(q.nparts);
     for (int p = 0; p < q.nparts; ++p) bm[p] = make_int2(0, p);
     xcd_order(bm);
@@ -655,6 +717,7 @@ void Run::assemble_constant() {
   inv_diagonal(stream, mixed, n1, sp11, rp11, col11, Kp, dinvKp);
   if (pp) {
     fcg_gather_values(stream, mixed, pp->nent, f_src, Kp, f_val);
+    if (fcg_s == 2 && pp->hnent > 0) fcg_gather_values(stream, mixed, pp->hnent, f_hsrc, Kp, f_hval);
     fcg_gather_dinv(stream, n1, f_perm, dinvKp, f_dinv);
   }
   form_eliminated(stream, mixed, n2, sp22, rp22, col22, bmask, M, nullptr, 1.0, 0.0, Mel, dinvM);
@@ -791,12 +854,27 @@ void Run::setup_solvers() {
     f.part_s = f_part_s;
     f.st = V.st;
     f.maxit = prm.maxit;
+    f.ipl = fcg_s;
+    if (fcg_s == 2) {
+      f.halo2_ptr = f_h2ptr;
+      f.halo2 = f_h2;
+      f.hslice_ptr = f_hsl;
+      f.hsptr = f_hsptr;
+      f.hlcol = f_hlcol;
+      f.hval = f_hval;
+      f.y[0] = f_y;
+      f.y[1] = f_y + 5 * (size_t)n1;
+    }
     set_p.h_fgroups = {f};
     HIP_OK(hipMemcpyAsync(fgroup, set_p.h_fgroups.data(), sizeof(f), hipMemcpyHostToDevice,
                           stream));
     set_p.F = FLaunch{fgroup, 1, fcg_ept, mixed ? 1 : 0, f_bmap, pp->nparts,
                       sizeof(double) * (size_t)pp->lds_max};
-    if (f_blk_ok) {
+    set_p.F.ipl = fcg_s;
+    // two iterations per launch: p and z over own, halo and second ring, B p
+    // over own and halo rows
+    if (fcg_s == 2) set_p.F.lds = sizeof(double) * (size_t)(2 * pp->lds2_max + pp->lds_max);
+    if (f_blk_ok && fcg_s == 1) {
       set_p.F.blk = f_blk;
       set_p.F.hfirst = f_hfirst;
       set_p.F.one = f;

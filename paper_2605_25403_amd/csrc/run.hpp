@@ -188,6 +188,13 @@ struct Run {
   FBlk* f_blk = nullptr;
   int32_t* f_hfirst = nullptr;
   bool f_blk_ok = false;       // every part's slice offsets fit an FBlk
+  int fcg_s = 1;               // CG iterations per launch
+  // two iterations per launch: second ring, halo rows' slices and values, basis
+  int32_t *f_h2ptr = nullptr, *f_h2 = nullptr, *f_hsl = nullptr, *f_hsptr = nullptr,
+          *f_hsrc = nullptr;
+  uint16_t* f_hlcol = nullptr;
+  void* f_hval = nullptr;
+  double* f_y = nullptr;       // [2][5][n1]
   FGroup* fgroup = nullptr;
   double* spart = nullptr;    // scratch partials for one-off reductions [8192*2]
   uint32_t* scnt = nullptr;

@@ -68,7 +68,7 @@ class ipcs_params(C.Structure):
                 ("tol_mom", C.c_double), ("tol_p", C.c_double), ("tol_corr", C.c_double),
                 ("tol_ir", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
                 ("callbacks", C.c_int32), ("poisson_part_rows", C.c_int32),
-                ("scheme", C.c_int32), ("reserved", C.c_int32)]
+                ("scheme", C.c_int32), ("poisson_s", C.c_int32)]
 
 
 class ipcs_step_stats(C.Structure):

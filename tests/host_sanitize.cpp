@@ -74,6 +74,63 @@ static void check_parts(const Mesh& m, int rows_max) {
   for (int64_t e = 0; e < Q.nent; ++e) {
     CHECK(Q.src[e] >= -1 && Q.src[e] < m.e11.nent);
   }
+  // the second ring (two CG iterations per launch): exactly the columns the
+  // halo rows reference outside the part and its halo, and the halo rows'
+  // SELL entries resolve to their CSR entries
+  auto q2 = m.parts11(rows_max, 2);
+  const PartSell& Q2 = *q2;
+  CHECK(Q2.depth == 2 && Q2.nparts == Q.nparts && Q2.perm == Q.perm && Q2.halo == Q.halo);
+  std::vector<int32_t> iperm(Q2.n);
+  for (int64_t i = 0; i < Q2.n; ++i) iperm[Q2.perm[i]] = (int32_t)i;
+  const Pattern& P = m.p11;
+  for (int p = 0; p < Q2.nparts; ++p) {
+    const int p0 = Q2.part_ptr[p], own = Q2.part_ptr[p + 1] - p0;
+    const int h0 = Q2.halo_ptr[p], nh = Q2.halo_ptr[p + 1] - h0;
+    const int g0 = Q2.halo2_ptr[p], nh2 = Q2.halo2_ptr[p + 1] - g0;
+    CHECK(own + nh + nh2 <= Q2.lds2_max);
+    auto inside = [&](int32_t c) {
+      if (c >= p0 && c < p0 + own) return true;
+      return std::binary_search(Q2.halo.begin() + h0, Q2.halo.begin() + h0 + nh, c);
+    };
+    std::vector<int32_t> want;
+    for (int q = 0; q < nh; ++q) {
+      const int32_t o = Q2.perm[Q2.halo[h0 + q]];
+      for (int32_t k = P.rowptr[o]; k < P.rowptr[o + 1]; ++k)
+        if (!inside(iperm[P.col[k]])) want.push_back(iperm[P.col[k]]);
+    }
+    std::sort(want.begin(), want.end());
+    want.erase(std::unique(want.begin(), want.end()), want.end());
+    CHECK((int)want.size() == nh2);
+    for (int q = 0; q < nh2; ++q) CHECK(Q2.halo2[g0 + q] == want[q]);
+    auto resolve = [&](int l) -> int32_t {
+      if (l < own) return p0 + l;
+      if (l < own + nh) return Q2.halo[h0 + l - own];
+      return Q2.halo2[g0 + l - own - nh];
+    };
+    const int s0 = Q2.hslice_ptr[p], s1 = Q2.hslice_ptr[p + 1];
+    CHECK(s1 - s0 == (nh + 63) / 64);
+    for (int sl = s0; sl < s1; ++sl) {
+      const int w = (Q2.hsptr[sl + 1] - Q2.hsptr[sl]) / 64;
+      CHECK((Q2.hsptr[sl + 1] - Q2.hsptr[sl]) % 64 == 0);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int q = 64 * (sl - s0) + lane;
+        const int32_t o = q < nh ? Q2.perm[Q2.halo[h0 + q]] : -1;
+        const int len = o >= 0 ? P.rowptr[o + 1] - P.rowptr[o] : 0;
+        CHECK(len <= w);
+        for (int k = 0; k < w; ++k) {
+          const int64_t e = Q2.hsptr[sl] + 64ll * k + lane;
+          CHECK(Q2.hlcol[e] < own + nh + nh2);
+          if (k < len) {
+            CHECK(resolve(Q2.hlcol[e]) == iperm[P.col[P.rowptr[o] + k]]);
+            CHECK(Q2.hsrc[e] == m.e11.index(o, k));
+          } else {
+            CHECK(Q2.hsrc[e] == -1);
+          }
+        }
+      }
+    }
+  }
+  CHECK(Q2.hnent == Q2.hsptr.back());
 }
 
 static void check_mesh(const Mesh& m) {
