@@ -554,8 +554,9 @@ def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
                  lanes=((32,), (64,), (128,), (256,))):
     """C5: Poisson-arrival stream of 2D TG requests (n in {32,64,128,256},
     seed-drawn k and nu, 50 steps at dt = 1e-3), mixed form, continuous
-    batching in one lane per mesh size (each with its own stream), and the
-    same stream in a single lane for comparison. Beside them, the first
+    batching in one lane per mesh size (each with its own stream), the same
+    lanes with 16 CUs reserved for each of the two small sizes, and the same
+    stream in a single lane for comparison. Beside them, the first
     seq_sample requests run one after the other, each alone, in the mixed form
     (the served form's alone latency per mesh size) and in the plain FP64
     form at tolerance 1e-12 (the baseline): per-step latency p50/p99 and
@@ -568,9 +569,13 @@ def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
     srv = Server(max_slots=max_slots, lanes=lanes)
     report, res = srv.serve(reqs, keep_ids={q.id for q in sample})
     one, _ = Server(max_slots=max_slots).serve(reqs)
-    report["one_lane"] = {k: one[k] for k in ("dof_steps_per_s", "p50_step_ms", "p99_step_ms",
-                                              "step_ms_by_n", "queue_delay_p99_ms",
-                                              "end_to_end_p99_ms", "rounds")}
+    keys = ("dof_steps_per_s", "p50_step_ms", "p99_step_ms", "step_ms_by_n",
+            "queue_delay_p99_ms", "end_to_end_p99_ms", "rounds")
+    report["one_lane"] = {k: one[k] for k in keys}
+    # the same lanes with CUs reserved for the two small sizes (16 each) and
+    # the large lanes on the other CUs
+    rsv, _ = Server(max_slots=max_slots, lanes=lanes, lane_cus=(16, 16, None, None)).serve(reqs)
+    report["reserved_cus"] = dict({k: rsv[k] for k in keys}, lane_cus=rsv["lane_cus"])
 
     def alone(prec):
         base = Server(precision=prec)

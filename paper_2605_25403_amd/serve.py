@@ -21,6 +21,13 @@ all lanes, each lane admitting its own requests in arrival order. A run's
 result does not depend on what it is batched with, or on the stream, so it is
 the same alone and in the mix.
 
+Reserved CUs. Lanes still share the compute units, so a small lane's short
+kernels can wait behind the grids of a large lane. A lane may therefore get a
+set of CUs of its own (`lane_cus`): its stream is created with a CU mask
+(HIP's CU-masked streams), and the lanes without a reservation share the
+remaining CUs on streams masked to those. Masks change where kernels run, not
+what they compute.
+
 Per-step latency of a request is the time between two consecutive completions
 of its steps (the first is counted from its admission); the report gives
 their p50 and p99, overall and per mesh size, beside the aggregate
@@ -31,6 +38,43 @@ import time
 from dataclasses import dataclass, field
 
 import numpy as np
+
+
+def _hip_runtime():
+    """The HIP runtime this process already uses (the one torch loaded; the
+    library links the same one), for the stream calls below."""
+    import ctypes
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1] if line.strip() else ""
+            if "libamdhip64.so" in path:
+                return ctypes.CDLL(path)
+    raise RuntimeError("the HIP runtime is not loaded")
+
+
+def cu_masked_stream(torch, cus):
+    """A stream whose kernels run only on the compute units listed (bit c of
+    the device's CU mask for each c), wrapped for torch; returns (stream,
+    handle) with handle for destroy_stream."""
+    import ctypes
+    hip = _hip_runtime()
+    total = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    words = (total + 31) // 32
+    mask = (ctypes.c_uint32 * words)()
+    for c in cus:
+        if not 0 <= c < total:
+            raise ValueError(f"CU {c} out of range (the device has {total})")
+        mask[c // 32] |= 1 << (c % 32)
+    h = ctypes.c_void_p()
+    rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), ctypes.c_uint32(words), mask)
+    if rc != 0:
+        raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({rc})")
+    return torch.cuda.ExternalStream(h.value), h.value
+
+
+def destroy_stream(handle):
+    import ctypes
+    _hip_runtime().hipStreamDestroy(ctypes.c_void_p(handle))
 
 
 @dataclass
@@ -78,10 +122,12 @@ def admit(queue, now, active_count, active_bytes, footprint_of, max_slots, hbm_b
 
 class Server:
     def __init__(self, dim=2, precision=None, max_slots=64, hbm_budget=200 << 30, tol=1e-12,
-                 tol_ir=1e-10, stream=None, poisson_part_rows=0, lanes=None):
+                 tol_ir=1e-10, stream=None, poisson_part_rows=0, lanes=None, lane_cus=None):
         """lanes: tuple of tuples of mesh sizes, one lane per tuple (each with
         its own stream and host thread); None: one lane for every size (on
-        `stream` if given)."""
+        `stream` if given). lane_cus: per lane, the number of CUs reserved
+        for it (consecutive mask bits, from bit 0 in lane order) or None (the
+        lane shares the CUs no lane reserved); None: no masks."""
         import torch
         from paper_2605_25403_amd import ipcs as I
         if dim != 2:
@@ -92,8 +138,13 @@ class Server:
         self.tol, self.tol_ir = tol, tol_ir
         self.part_rows = poisson_part_rows
         self.lanes = tuple(tuple(l) for l in lanes) if lanes else None
+        self.lane_cus = tuple(lane_cus) if lane_cus else None
+        if self.lane_cus is not None and (self.lanes is None or
+                                          len(self.lane_cus) != len(self.lanes)):
+            raise ValueError("lane_cus needs one entry per lane")
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self._meshes = {}
+        self._owned = []
         self._lock = threading.Lock()
 
     def mesh(self, n):
@@ -128,8 +179,8 @@ class Server:
             missing = sizes - {n for l in self.lanes for n in l}
             if missing:
                 raise ValueError(f"no lane serves mesh sizes {sorted(missing)}")
-            lanes = [(l, [q for q in queue if q.n in l], self.torch.cuda.Stream())
-                     for l in self.lanes]
+            lanes = [(l, [q for q in queue if q.n in l], st)
+                     for l, st in zip(self.lanes, self._lane_streams())]
         keep = (lambda q: True) if keep_fields else (
             (lambda q: q.id in keep_ids) if keep_ids else (lambda q: False))
         shared = {"slots": 0, "bytes": 0, "max_active": 0}
@@ -144,6 +195,10 @@ class Server:
             th.start()
         for th in threads:
             th.join()
+        self.torch.cuda.synchronize()
+        for h in self._owned:
+            destroy_stream(h)
+        self._owned = []
         if errors:
             raise errors[0]
         wall = clock() - t0
@@ -160,6 +215,7 @@ class Server:
         report = {
             "requests": len(requests), "failed": counters["fails"],
             "rounds": counters["rounds"], "lanes": [list(l) for l, _, _ in lanes if l] or None,
+            "lane_cus": list(self.lane_cus) if self.lane_cus else None,
             "max_active": shared["max_active"], "max_slots": self.max_slots,
             "hbm_budget_bytes": self.hbm_budget,
             "dof_steps": counters["dof_steps"], "wall_s": wall,
@@ -237,6 +293,28 @@ class Server:
                 active = stay
         except Exception as e:   # reported by serve() after every lane has ended
             errors.append(e)
+
+    def _lane_streams(self):
+        """One stream per lane: plain, or masked to the lane's reserved CUs
+        (or to the CUs no lane reserved)."""
+        self._owned = []
+        if self.lane_cus is None:
+            return [self.torch.cuda.Stream() for _ in self.lanes]
+        total = self.torch.cuda.get_device_properties(
+            self.torch.cuda.current_device()).multi_processor_count
+        first, ranges = 0, []
+        for c in self.lane_cus:
+            ranges.append(range(first, first + c) if c else None)
+            first += c or 0
+        if first >= total:
+            raise ValueError("the reserved CUs leave none for the other lanes")
+        rest = range(first, total)
+        out = []
+        for r in ranges:
+            st, h = cu_masked_stream(self.torch, r if r is not None else rest)
+            self._owned.append(h)
+            out.append(st)
+        return out
 
     def footprint_nolock(self, req):
         n = req.n

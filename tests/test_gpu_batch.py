@@ -77,16 +77,18 @@ def test_serving_loop_small_stream_equals_alone():
         assert len(res[q.id]["lat"]) == q.steps
 
 
-def test_serving_lanes_by_size_equal_alone():
+@pytest.mark.parametrize("cus", [None, (8, None)])
+def test_serving_lanes_by_size_equal_alone(cus):
     """Lanes by mesh size, each with its own stream and host thread, sharing
-    the slot cap: every result is bitwise the result alone, and the report
-    gives per-size latencies."""
+    the slot cap, without and with CU masks (8 CUs reserved for the first
+    lane, the rest for the second): every result is bitwise the result
+    alone, and the report gives per-size latencies."""
     torch, I = require_gpu()
-    print("serving lanes", flush=True)
+    print(f"serving lanes cus={cus}", flush=True)
     from paper_2605_25403_amd.serve import Request, Server
     reqs = [Request(id=i, t_arrive=0.001 * i, n=n, k=k, nu=nu, steps=2 + (i % 4), dt=dt)
             for i, (n, k, nu, dt) in enumerate(CASES * 3)]
-    srv = Server(max_slots=4, hbm_budget=1 << 34, lanes=((8, 12), (16, 24)))
+    srv = Server(max_slots=4, hbm_budget=1 << 34, lanes=((8, 12), (16, 24)), lane_cus=cus)
     report, res = srv.serve(reqs, keep_fields=True)
     print(report, flush=True)
     assert report["failed"] == 0 and len(res) == len(reqs)
