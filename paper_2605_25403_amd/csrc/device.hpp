@@ -55,6 +55,10 @@ struct KState {
 // Vectors of one system (FP64).
 //   PCG (Chronopoulos-Gear form): r, u = D^{-1} r, p, s = A p, w = A u
 //   BiCGStab: r, u = rhat, p, s, w = v = A phat, t = A shat, phat, shat
+// The vectors the SpMVs gather (u, phat, shat) are interleaved over the
+// group's nsys systems: entry i of system j is at u[i * nsys] with system j's
+// pointer at base + j, so one gathered row serves every system of the group
+// from one cache line. The others are contiguous per system.
 struct KVecs {
   const double* b;
   double* x;

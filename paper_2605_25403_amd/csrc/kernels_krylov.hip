@@ -139,14 +139,14 @@ __global__ void __launch_bounds__(KBS) k_start(const KGroup* groups, const int2*
         V.r[i] = r;
         if (PCG) {
           const double u = di * r;
-          V.u[i] = u;
+          V.u[(size_t)i * NS] = u;
           V.p[i] = 0.0;
           V.s[i] = 0.0;
           acc[j * 3 + 1] += r * u;
         } else {
-          V.u[i] = r;
+          V.u[(size_t)i * NS] = r;
           V.p[i] = r;
-          V.phat[i] = di * r;
+          V.phat[(size_t)i * NS] = di * r;
           acc[j * 3 + 1] += r * r;
         }
         acc[j * 3 + 0] += r * r;
@@ -295,9 +295,9 @@ __global__ void __launch_bounds__(KBS) k_cg_spmv(const KGroup* groups, const int
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int i = row_clamp(row_of<EPT>(lb, e), g.n);
-    sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].u)[c]; }, y[e]);
+    sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].u)[(size_t)c * NS]; }, y[e]);
 #pragma unroll
-    for (int j = 0; j < NS; ++j) ui[e][j] = G(g.v[j].u)[i];
+    for (int j = 0; j < NS; ++j) ui[e][j] = G(g.v[j].u)[(size_t)i * NS];
   }
   if (!any) return;   // uniform: the states were written by an earlier kernel
   double acc[NS] = {};
@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(KBS) k_cg_update(const KGroup* groups, const i
       G(V.r)[i] = r;
       G(V.p)[i] = p;
       G(V.s)[i] = s;
-      G(V.u)[i] = u;
+      G(V.u)[(size_t)i * NS] = u;
       acc[j * 2] += r * u;
       acc[j * 2 + 1] += r * r;
     }
@@ -442,12 +442,12 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
   for (int e = 0; e < EPT; ++e) {
     const int i = row_clamp(row_of<EPT>(lb, e), g.n);
     if (WHICH == 0)
-      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].phat)[c]; }, y[e]);
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].phat)[(size_t)c * NS]; }, y[e]);
     else
-      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].shat)[c]; }, y[e]);
+      sell_row<NS, VT>(g, i, [&](int j, int c) { return G(g.v[j].shat)[(size_t)c * NS]; }, y[e]);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      rh[e][j] = G(g.v[j].u)[i];
+      rh[e][j] = G(g.v[j].u)[(size_t)i * NS];
       si[e][j] = WHICH == 1 ? G(g.v[j].s)[i] : 0.0;
     }
   }
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_3(const KGroup* groups, const int2
       if (!go[j]) continue;
       const double s = ri[e][j] - al[j] * vi[e][j];
       G(g.v[j].s)[i] = s;
-      G(g.v[j].shat)[i] = di[e] * s;
+      G(g.v[j].shat)[(size_t)i * NS] = di[e] * s;
     }
   }
 }
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
       if (full[j]) {
         const double p = r + be[j] * (pi[e][j] - om[j] * vi[e][j]);
         G(V.p)[i] = p;
-        G(V.phat)[i] = di[e] * p;
+        G(V.phat)[(size_t)i * NS] = di[e] * p;
       }
     }
   }

@@ -780,19 +780,22 @@ void Run::setup_solvers() {
     g.col = col22;
     g.val = mom ? Ael : Mel;
     g.dinv = mom ? dinvA : dinvM;
+    // r, p, s, w, t per component; u, phat, shat interleaved over the
+    // components (the vectors the SpMVs gather)
+    double* il = kv2 + (size_t)5 * dim * n2;
     for (int c = 0; c < dim; ++c) {
-      double* base = kv2 + (size_t)c * 8 * n2;
+      double* base = kv2 + (size_t)c * 5 * n2;
       KVecs& V = g.v[c];
       V.b = bU + (size_t)c * n2;
       V.x = (mom ? Ustar : Unew) + (size_t)c * n2;
       V.r = base;
-      V.u = base + n2;
-      V.p = base + 2 * n2;
-      V.s = base + 3 * n2;
-      V.w = base + 4 * n2;
-      V.t = base + 5 * n2;
-      V.phat = base + 6 * n2;
-      V.shat = base + 7 * n2;
+      V.p = base + n2;
+      V.s = base + 2 * n2;
+      V.w = base + 3 * n2;
+      V.t = base + 4 * n2;
+      V.u = il + c;
+      V.phat = il + (size_t)dim * n2 + c;
+      V.shat = il + (size_t)2 * dim * n2 + c;
       const int sidx = mom ? c : dim + 1 + c;
       V.st = kst + sidx;
       st[sidx] = fresh_state(mom ? prm.tol_mom : prm.tol_corr, prm.maxit);
