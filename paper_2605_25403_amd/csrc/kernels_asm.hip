@@ -791,25 +791,44 @@ void asm_kp(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t l
 }
 
 // ------------------------------------------------------------------ cell-batched convection
-// E = M/dt + cs C(U) in two passes (used in 3D). The row-owner kernel above
-// (OpConv) recomputes a cell's geometry and u_h at every quadrature point for
-// each of the cell's rows (n_loc times): 10 times in 3D, with 14 quadrature
-// points, while in 2D (6 rows, 7 points) that recomputation costs less than
-// storing and re-reading the local matrices. Here a block first forms the
-// local matrices of 256 / n_loc cells once, one thread per (cell, local row):
-// the cell's threads share U at its DOFs, its geometry and the reference-frame
-// velocity beta_q = J^{-1} u_h(x_q) at every quadrature point through LDS, and
-// each thread forms its local row: for every quadrature point q,
+// E = M/dt + cs C(U) in two passes (used in 3D, both pairs). The row-owner
+// kernel above (OpConv, Op3Conv) recomputes a cell's geometry and u_h at every
+// quadrature point for each of the cell's rows (n_loc times): 10 times in 3D
+// with P2 and 14 points, 20 times with P3 and 125 points, while in 2D (6 rows,
+// 7 points) that recomputation costs less than storing and re-reading the
+// local matrices; in 3D the rows of a slice also differ widely in their number
+// of incident cells (a P3 vertex row has 24, a face row 2), which leaves lanes
+// idle. Here a block first forms the local matrices of 256 / n_loc cells
+// once, one thread per (cell, local row): the cell's threads share U at its
+// DOFs, its geometry and the reference-frame velocity
+// beta_q = J^{-1} u_h(x_q) at every quadrature point through LDS, and each
+// thread forms its local row: for every quadrature point q,
 //   v_j += w_q |det J| phi_li(x_q) (phi_j(x_q) / dt + cs beta_q . grad_ref phi_j(x_q)),
-// the same operations in the same order as OpConv. The local rows go to a
-// buffer [cell][local row][local column]; k_asm_local then adds them into the
-// matrix rows with the conflict-free row-owner scatter.
+// the same operations in the same order as the row-owner ops. The local rows
+// go to a buffer [cell][local row][local column]; k_asm_local then adds them
+// into the matrix rows with the conflict-free row-owner scatter.
+
+// The velocity element of a pair: local rows, rule points, tables.
+template <int D, int P3, class R>
+struct VelElem;
 template <int D, class R>
+struct VelElem<D, 0, R> {
+  static constexpr int NL = P2<D>::NLOC, NQ = Rule<D>::NQ;
+  __device__ static const Tab<D, R>& table() { return tab<D, R>(); }
+};
+template <int D, class R>
+struct VelElem<D, 1, R> {
+  static constexpr int NL = P3Of<D>::B::NLOC, NQ = P3Of<D>::template Tab<R>::NQ;
+  __device__ static const typename P3Of<D>::template Tab<R>& table() { return tab3<D, R>(); }
+};
+
+template <int D, class R, int P3>
 __global__ void __launch_bounds__(256) k_conv_cells(RowAsm a, int64_t nc, const double* U,
                                                     int64_t n2, double inv_dt, double cs, R* out) {
+  using E = VelElem<D, P3, R>;
   const int32_t* c2d = a.c2d;
   const int nloc2 = a.nloc2;
-  constexpr int NL = P2<D>::NLOC, NQ = Rule<D>::NQ, CPB = 256 / NL;
+  constexpr int NL = E::NL, NQ = E::NQ, CPB = 256 / NL;
   __shared__ R s_u[CPB][D][NL];          // U_c at the cell's DOFs
   __shared__ R s_beta[CPB][NQ][D];       // J^{-1} u_h(x_q)
   __shared__ R s_det[CPB];
@@ -817,7 +836,7 @@ __global__ void __launch_bounds__(256) k_conv_cells(RowAsm a, int64_t nc, const 
   const int cl = threadIdx.x / NL, li = threadIdx.x % NL;
   const int64_t cell = (int64_t)blockIdx.x * CPB + cl;
   const bool act = cl < CPB && cell < nc;
-  const Tab<D, R>& T = tab<D, R>();
+  const auto& T = E::table();
   int32_t dl[NL];
   if (act) {
 #pragma unroll
@@ -882,9 +901,9 @@ __global__ void __launch_bounds__(256) k_conv_cells(RowAsm a, int64_t nc, const 
 
 // Row-owner sum of stored local rows: row r adds local row li of each incident
 // cell into its slots (the scatter of k_asm_rows, without recomputation).
-template <int D, class R>
+template <int D, class R, int P3>
 __global__ void __launch_bounds__(256) k_asm_local(RowAsm a, const R* loc) {
-  constexpr int NL = P2<D>::NLOC;
+  constexpr int NL = VelElem<D, P3, R>::NL;
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   const int r0 = xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk) * blockDim.x;
@@ -910,39 +929,82 @@ __global__ void __launch_bounds__(256) k_asm_local(RowAsm a, const R* loc) {
   for (int k = threadIdx.x; k < bent; k += blockDim.x) static_cast<R*>(a.out[0])[base + k] = lds[k];
 }
 
-template <int D, class R>
+// The same where a block's slices exceed LDS: each thread clears its row in
+// the output and accumulates there (same owner, same order of additions).
+template <int D, class R, int P3>
+__global__ void __launch_bounds__(256) k_asm_local_g(RowAsm a, const R* loc) {
+  constexpr int NL = VelElem<D, P3, R>::NL;
+  const int row = xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk) * blockDim.x + threadIdx.x;
+  if (row >= a.nrows) return;
+  R* out = static_cast<R*>(a.out[0]);
+  const int sl0 = row >> 6;
+  const int w = (a.sptr[sl0 + 1] - a.sptr[sl0]) >> 6;
+  const int off = a.sptr[sl0] + (row & 63);
+  for (int k = 0; k < w; ++k) out[off + 64 * k] = R(0);
+  for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
+    const int code = a.inc[p];
+    const int cell = code >> 5, li = code & 31;
+    const R* lr = loc + ((size_t)cell * NL + li) * NL;
+    const uint8_t* sl = a.slot + (size_t)p * a.stride;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) out[off + 64 * sl[j]] += lr[j];
+  }
+}
+
+template <int D, class R, int P3>
 static void conv_cells(hipStream_t s, const RowAsm& a, int64_t nc, const double* U, int64_t n2,
                        double inv_dt, double cs, void* buf) {
-  constexpr int CPB = 256 / P2<D>::NLOC;
+  constexpr int CPB = 256 / VelElem<D, P3, R>::NL;
   if (nc <= 0) return;
-  launch(k_conv_cells<D, R>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, a, nc, U, n2,
+  launch(k_conv_cells<D, R, P3>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, a, nc, U, n2,
          inv_dt, cs, static_cast<R*>(buf));
 }
 
-template <int D, class R>
+template <int D, class R, int P3>
 static void local_sum(hipStream_t s, const RowAsm& a, int bs, size_t lds, const void* buf) {
   if (a.nrows <= 0) return;
-  launch(k_asm_local<D, R>, dim3((unsigned)div_up(a.nrows, bs)), dim3(bs), (uint32_t)lds, s, a,
-         static_cast<const R*>(buf));
+  const dim3 grid((unsigned)div_up(a.nrows, bs));
+  if (lds == 0)
+    launch(k_asm_local_g<D, R, P3>, grid, dim3(bs), 0, s, a, static_cast<const R*>(buf));
+  else
+    launch(k_asm_local<D, R, P3>, grid, dim3(bs), (uint32_t)lds, s, a,
+           static_cast<const R*>(buf));
+}
+
+// dispatch over dimension, working type and pair
+template <class F>
+static void with_dr_pair(int dim, bool fp32, int pair, F f) {
+  auto d3 = [&](auto R) {
+    if (pair == IPCS_PAIR_P3P2) f(std::integral_constant<int, 3>{}, R, std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 3>{}, R, std::integral_constant<int, 0>{});
+  };
+  auto d2 = [&](auto R) {
+    if (pair == IPCS_PAIR_P3P2) f(std::integral_constant<int, 2>{}, R, std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 2>{}, R, std::integral_constant<int, 0>{});
+  };
+  if (dim == 2) {
+    if (fp32) d2(float{});
+    else d2(double{});
+  } else {
+    if (fp32) d3(float{});
+    else d3(double{});
+  }
 }
 
 void asm_conv_cells(int dim, bool fp32, hipStream_t s, const RowAsm& a, int64_t nc,
                     const double* U, int64_t n2, double inv_dt, double cs, void* buf) {
-  if (a.pair != IPCS_PAIR_P2P1) fail(IPCS_E_INVALID, "cell-batched convection: P2-P1 pair only");
-  if (dim == 2 && !fp32) conv_cells<2, double>(s, a, nc, U, n2, inv_dt, cs, buf);
-  else if (dim == 2) conv_cells<2, float>(s, a, nc, U, n2, inv_dt, cs, buf);
-  else if (!fp32) conv_cells<3, double>(s, a, nc, U, n2, inv_dt, cs, buf);
-  else conv_cells<3, float>(s, a, nc, U, n2, inv_dt, cs, buf);
+  need_tables(dim, a);
+  with_dr_pair(dim, fp32, a.pair, [&](auto D, auto R, auto P) {
+    conv_cells<decltype(D)::value, decltype(R), decltype(P)::value>(s, a, nc, U, n2, inv_dt, cs,
+                                                                     buf);
+  });
 }
 
 void asm_local_sum(int dim, bool fp32, hipStream_t s, const RowAsm& a, int bs, size_t lds,
                    const void* buf) {
-  if (a.pair != IPCS_PAIR_P2P1 || lds == 0)
-    fail(IPCS_E_INVALID, "local-matrix sum: P2-P1 pair with rows that fit in LDS only");
-  if (dim == 2 && !fp32) local_sum<2, double>(s, a, bs, lds, buf);
-  else if (dim == 2) local_sum<2, float>(s, a, bs, lds, buf);
-  else if (!fp32) local_sum<3, double>(s, a, bs, lds, buf);
-  else local_sum<3, float>(s, a, bs, lds, buf);
+  with_dr_pair(dim, fp32, a.pair, [&](auto D, auto R, auto P) {
+    local_sum<decltype(D)::value, decltype(R), decltype(P)::value>(s, a, bs, lds, buf);
+  });
 }
 
 // ------------------------------------------------------------------ vectors
