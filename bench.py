@@ -462,9 +462,8 @@ def pair_forms(w, steps, torch, I, dim=2, n=None):
         ms = 1000.0 * float(np.median(lat))
         fus = us(I.IPCS_KERNEL_PCG_FUSED_P)
         fgb = kernel_bytes("pcg_fused_p", c, dim, 8) / (fus * 1e-6) / 1e9 if fus else None
-        asm = us(I.IPCS_KERNEL_ASM_CONV)
-        if dim == 3 and pair == I.IPCS_PAIR_P2P1:
-            asm = (asm or 0.0) + (us(I.IPCS_KERNEL_ASM_SUM) or 0.0)
+        # the cell pass and the local sum where the convection takes two passes
+        asm = (us(I.IPCS_KERNEL_ASM_CONV) or 0.0) + (us(I.IPCS_KERNEL_ASM_SUM) or 0.0)
         out[name] = {"n": nn, "dofs": int(ndof), "velocity_dofs_per_component": int(c.n2),
                      "pressure_dofs": int(c.n1), "value": ndof / (ms / 1000.0),
                      "p50_step_ms": ms, "pressure_iterations_median": float(np.median(it_p)),

@@ -1061,8 +1061,9 @@ void Run::asm_phase() {
     asm_forcing(dim, stream, a22, bi, nullptr, nc, t1, F, n2);
     has_F = true;
   }
-  // 3D: cell-batched local matrices, then their row-owner sum; 2D: one
-  // row-owner pass (cheaper where a cell has 6 or 10 rows and few points)
+  // 3D and the P3-P2 pair: cell-batched local matrices, then their row-owner
+  // sum; P2-P1 in 2D: one row-owner pass (cheaper where a cell has 6 rows and
+  // 7 quadrature points)
   const double cs = semi ? 1.0 : -1.0;
   if (two_pass_conv()) {
     timer.run(stream, IPCS_KERNEL_ASM_CONV,
@@ -1278,7 +1279,7 @@ double Run::profile_kernel(int kernel, int nlaunch) {
       }
       case IPCS_KERNEL_ASM_SUM:
         if (!two_pass_conv())
-          fail(IPCS_E_INVALID, "the two-pass convection assembly is used in 3D only");
+          fail(IPCS_E_INVALID, "this run's convection assembly takes one pass");
         asm_local_sum(dim, mixed, stream, a22, cfg_e.bs, cfg_e.lds, Eloc);
         break;
       case IPCS_KERNEL_BICG_SPMV: bicg_spmv_only(stream, set_mom.L); break;

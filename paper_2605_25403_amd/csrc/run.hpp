@@ -225,8 +225,8 @@ struct Run {
   void choose_poisson_form();
   void layout(Carver& c);
   // convection in two passes (cell-batched local matrices, then their
-  // row-owner sum): 3D, both pairs
-  bool two_pass_conv() const { return dim == 3; }
+  // row-owner sum): 3D, and the P3-P2 pair in 2D
+  bool two_pass_conv() const { return dim == 3 || mesh->pair == IPCS_PAIR_P3P2; }
   // points per cell of the pair's cell rule (the forcing quadrature)
   int cell_nq() const {
     if (mesh->pair == IPCS_PAIR_P3P2) return dim == 2 ? RuleT9::NQ : RuleTet9::NQ;
