@@ -199,3 +199,27 @@ def test_p3_tet_fused_and_two_kernel_poisson_forms_agree():
     for c in range(3):
         assert rel(a.velocity()[c], b.velocity()[c]) <= FIELD_TOL
     assert rel(a.pressure(), b.pressure()) <= FIELD_TOL
+
+
+@pytest.mark.parametrize("rows", [0, -1])
+@pytest.mark.parametrize("n", [1, 2])
+def test_p3_tet_degenerate_small_meshes(n, rows):
+    """One or two cubes per direction: at n = 1 the only interior velocity
+    nodes are the two nodes of the main diagonal and the six nodes of the
+    interior faces (8 of 64), and the P2 pressure system has 27 rows in one
+    part. Three Beltrami
+    steps against the oracle in both Poisson CG forms (fields that vanish up to
+    rounding are compared with an RMS floor of 0.01, as for the other pairs)."""
+    torch, I = require_gpu()
+    print(f"P3-P2 tetrahedra degenerate n={n} poisson_part_rows={rows}", flush=True)
+    S, o, r = make_pair(I, 3, n, "beltrami", NU, DT, p3=True, poisson_part_rows=rows)
+
+    def err(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-2 * np.sqrt(b.size))
+
+    for step in range(3):
+        st = r.advance(1)[0]
+        o.step()
+        U, P = r.velocity(), r.pressure()
+        errs = [err(U[c], o.U[c]) for c in range(3)] + [err(P, o.P)]
+        assert max(errs) <= FIELD_TOL, (step, errs, st)
