@@ -82,21 +82,36 @@ void xcd_chunks(std::vector<int2>& bmap, int chunk) {
   bmap.swap(out);
 }
 
+// LDS a block may use on the current device (160 KiB on gfx950).
+static size_t lds_limit() {
+  int dev = 0, v = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  return v > 0 ? (size_t)v : 65536;
+}
+
 // LDS needed by the assembly kernel with bs rows per block: the largest
 // number of SELL entries of the bs/64 slices a block owns, times the value size.
+// The largest block that fits in 64 KiB (several blocks per CU); failing that,
+// one 64-row block up to the device's limit (P3 rows on tetrahedra: 175
+// entries, 89.6 KB of FP64 values per slice); failing that, lds 0: the row
+// kernels accumulate in global memory.
 static AsmCfg asm_cfg(const Sell& S, int vbytes) {
-  for (int bs : {256, 128, 64}) {
+  auto need = [&](int bs) {
     int64_t mx = 0;
     const int per = bs / 64;
     for (int64_t s0 = 0; s0 < S.nslices; s0 += per) {
       const int64_t s1 = std::min<int64_t>(s0 + per, S.nslices);
       mx = std::max<int64_t>(mx, S.sptr[s1] - S.sptr[s0]);
     }
-    const size_t lds = (size_t)mx * vbytes;
+    return (size_t)mx * vbytes;
+  };
+  for (int bs : {256, 128, 64}) {
+    const size_t lds = need(bs);
     if (lds <= 65536) return AsmCfg{bs, std::max<size_t>(lds, 8)};
   }
-  // the slices of one 64-row block exceed a block's LDS: the row kernels
-  // accumulate in global memory instead (lds 0)
+  const size_t lds = need(64);
+  if (lds <= lds_limit()) return AsmCfg{64, lds};
   return AsmCfg{256, 0};
 }
 
@@ -711,7 +726,8 @@ void Run::assemble_constant() {
   // pass is limited by the inner tolerance rather than by the operator.
   RowAsm a11{(int32_t)n1, sp11, inc1p, inc1, s11, m.s11.stride, c2d, m.nloc2, X,
              {Kp64, nullptr, nullptr}, m.pair, c2v, m.nloc1};
-  asm_kp(dim, false, stream, a11, cfg_kp.bs, cfg_kp.lds * (8 / vsz));
+  const AsmCfg kp64 = asm_cfg(mesh->e11, 8);   // FP64 values in both forms
+  asm_kp(dim, false, stream, a11, kp64.bs, kp64.lds);
   if (mixed) round_to_f32(stream, ne11, Kp64, static_cast<float*>(Kp));
   asm_lumped_p1(dim, stream, a11, w);
   inv_diagonal(stream, mixed, n1, sp11, rp11, col11, Kp, dinvKp);
