@@ -40,15 +40,14 @@ struct Geo {
   R det;        // |det J|
 };
 
+// From the vertex coordinates xc[k] of the cell's vertices k = 0..D.
 template <int D, class R = double>
-__device__ __forceinline__ Geo<D, R> cell_geo(const double* X, const int32_t* dofs) {
-  double x0[D], J[D][D], Ji[D][D], det;
-#pragma unroll
-  for (int r = 0; r < D; ++r) x0[r] = X[(size_t)dofs[0] * D + r];
+__device__ __forceinline__ Geo<D, R> cell_geo_x(const double (&xc)[D + 1][D]) {
+  double J[D][D], Ji[D][D], det;
 #pragma unroll
   for (int k = 0; k < D; ++k)
 #pragma unroll
-    for (int r = 0; r < D; ++r) J[r][k] = X[(size_t)dofs[k + 1] * D + r] - x0[r];
+    for (int r = 0; r < D; ++r) J[r][k] = xc[k + 1][r] - xc[0][r];
   if constexpr (D == 2) {
     det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double id = 1.0 / det;
@@ -79,6 +78,22 @@ __device__ __forceinline__ Geo<D, R> cell_geo(const double* X, const int32_t* do
     for (int b = 0; b < D; ++b) g.Ji[a][b] = (R)Ji[a][b];
   g.det = (R)fabs(det);
   return g;
+}
+
+template <int D>
+__device__ __forceinline__ void load_coords(const double* X, const int32_t* v,
+                                            double (&xc)[D + 1][D]) {
+#pragma unroll
+  for (int k = 0; k <= D; ++k)
+#pragma unroll
+    for (int r = 0; r < D; ++r) xc[k][r] = X[(size_t)v[k] * D + r];
+}
+
+template <int D, class R = double>
+__device__ __forceinline__ Geo<D, R> cell_geo(const double* X, const int32_t* dofs) {
+  double xc[D + 1][D];
+  load_coords<D>(X, dofs, xc);
+  return cell_geo_x<D, R>(xc);
 }
 
 // The vertex ids of a cell (for its geometry), from the cell-vertex table.
@@ -181,14 +196,27 @@ struct OpConv {   // P2 x P2: E = M/dt + cs C(U), cs = -1 (explicit) or +1 (semi
   int64_t n2;
   double inv_dt;
   double cs;
-  __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
-                             R (&v)[NOUT][NCOL]) const {
-    const Tab<D, R>& T = tab<D, R>();
+  // the cell's nodal velocities, loaded apart from the evaluation so that a
+  // row can fetch its next cell's while it evaluates this one
+  struct Nodal {
     R Uc[D][NCOL];
+  };
+  __device__ void load(const int32_t* dofs, Nodal& nd) const {
 #pragma unroll
     for (int c = 0; c < D; ++c)
 #pragma unroll
-      for (int m = 0; m < NCOL; ++m) Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
+      for (int m = 0; m < NCOL; ++m) nd.Uc[c][m] = (R)U[(size_t)c * n2 + dofs[m]];
+  }
+  __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    Nodal nd;
+    load(dofs, nd);
+    (*this)(g, nd, li, v);
+  }
+  __device__ void operator()(const Geo<D, R>& g, const Nodal& nd, int li,
+                             R (&v)[NOUT][NCOL]) const {
+    const Tab<D, R>& T = tab<D, R>();
+    const auto& Uc = nd.Uc;
     const R idt = (R)inv_dt, csr = (R)cs;
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
@@ -230,12 +258,23 @@ struct OpNewton {
   const double* U;        // [D][n2]
   int64_t n2;
   int c, e;
+  struct Nodal {   // component c of the cell's nodal velocities
+    R Uc[NCOL];
+  };
+  __device__ void load(const int32_t* dofs, Nodal& nd) const {
+#pragma unroll
+    for (int m = 0; m < NCOL; ++m) nd.Uc[m] = (R)U[(size_t)c * n2 + dofs[m]];
+  }
   __device__ void operator()(const Geo<D, R>& g, const int32_t* dofs, int li,
                              R (&v)[NOUT][NCOL]) const {
+    Nodal nd;
+    load(dofs, nd);
+    (*this)(g, nd, li, v);
+  }
+  __device__ void operator()(const Geo<D, R>& g, const Nodal& nd, int li,
+                             R (&v)[NOUT][NCOL]) const {
     const Tab<D, R>& T = tab<D, R>();
-    R Uc[NCOL];
-#pragma unroll
-    for (int m = 0; m < NCOL; ++m) Uc[m] = (R)U[(size_t)c * n2 + dofs[m]];
+    const auto& Uc = nd.Uc;
 #pragma unroll 1
     for (int q = 0; q < Rule<D>::NQ; ++q) {
       R gr[D];
@@ -608,10 +647,63 @@ struct Op3Kp {   // P2 x P2 stiffness of the pressure space
 };
 
 // ------------------------------------------------------------------ kernel
+// What a row's walk over its incident cells loads per cell, in dependency
+// order: the incidence code; the cell's vertex ids and (ops that read U) its
+// velocity DOFs; the vertex coordinates and the op's nodal values (ops with a
+// Nodal type load them apart from the evaluation).
+template <class Op, class = void>
+struct NodalOf {
+  static constexpr bool on = false;
+  struct type {};
+};
+template <class Op>
+struct NodalOf<Op, std::void_t<typename Op::Nodal>> {
+  static constexpr bool on = true;
+  using type = typename Op::Nodal;
+};
+
+template <int D, class Op>
+struct CellIdx {
+  int32_t dl[Op::NDOF > 0 ? Op::NDOF : 1];
+  int32_t vx[D + 1];
+};
+
+template <int D, class Op>
+struct CellVals {
+  double xc[D + 1][D];
+  typename NodalOf<Op>::type nd;
+};
+
+template <int D, class Op>
+__device__ __forceinline__ void load_idx(const RowAsm& a, int code, CellIdx<D, Op>& ix) {
+  const int cell = code >> 5;
+  if constexpr (Op::NDOF > 0) {
+    const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
+#pragma unroll
+    for (int m = 0; m < Op::NDOF; ++m) ix.dl[m] = dofs[m];
+  }
+  cell_vertices<D>(a, cell, ix.vx);
+}
+
+template <int D, class Op>
+__device__ __forceinline__ void load_vals(const RowAsm& a, const Op& op, const CellIdx<D, Op>& ix,
+                                          CellVals<D, Op>& cv) {
+  load_coords<D>(a.X, ix.vx, cv.xc);
+  if constexpr (NodalOf<Op>::on) op.load(ix.dl, cv.nd);
+}
+
 // One thread per output row; the block owns whole SELL-64 slices (blockDim a
 // multiple of 64), accumulates their values in LDS in the SELL layout and
 // writes them back as one contiguous, coalesced range. Values are of the op's
 // working type (double, or float in the mixed form).
+//
+// The walk over a row's incident cells is software-pipelined: while cell p is
+// evaluated, the coordinates and nodal values of cell p+1, the indices of cell
+// p+2 and the incidence code of cell p+3 are in flight, so each cell costs
+// about one memory latency overlapped with the previous cell's arithmetic
+// instead of three in a row. Prefetches past the row's last cell re-read its
+// last incidence entry and are discarded. The cells are evaluated and added in
+// incidence order, as without the pipeline.
 template <int D, class Op>
 __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
   using R = typename Op::real;
@@ -628,31 +720,52 @@ __global__ void __launch_bounds__(256) k_asm_rows(RowAsm a, Op op) {
   const int row = r0 + threadIdx.x;
   if (row < a.nrows) {
     const int off = a.sptr[row >> 6] - base + (row & 63);
-    for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
-      const int code = a.inc[p];
-      const int cell = code >> 5, li = code & 31;
-      // velocity DOFs only for ops that read U (NDOF > 0)
-      int32_t dl[Op::NDOF > 0 ? Op::NDOF : 1];
-      if constexpr (Op::NDOF > 0) {
-        const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
+    const int pb = a.inc_ptr[row], pe = a.inc_ptr[row + 1];
+    if (pb < pe) {
+      const int last = pe - 1;
+      // prologue: codes of cells pb, pb+1, pb+2; indices of pb, pb+1; values of pb
+      int code = a.inc[pb];
+      int code1 = a.inc[min(pb + 1, last)];
+      int code2 = a.inc[min(pb + 2, last)];
+      CellIdx<D, Op> ix;
+      load_idx<D, Op>(a, code, ix);
+      CellIdx<D, Op> ix1;
+      load_idx<D, Op>(a, code1, ix1);
+      CellVals<D, Op> cv;
+      load_vals<D, Op>(a, op, ix, cv);
+      for (int p = pb; p < pe; ++p) {
+        // in flight during this cell's evaluation
+        CellVals<D, Op> cv1;
+        load_vals<D, Op>(a, op, ix1, cv1);
+        CellIdx<D, Op> ix2;
+        load_idx<D, Op>(a, code2, ix2);
+        const int code3 = a.inc[min(p + 3, last)];
+        const uint8_t* sl = a.slot + (size_t)p * a.stride;
+        int sj[NCOL];
 #pragma unroll
-        for (int m = 0; m < Op::NDOF; ++m) dl[m] = dofs[m];
-      }
-      int32_t vx[D + 1];
-      cell_vertices<D>(a, cell, vx);
-      const Geo<D, R> g = cell_geo<D, R>(a.X, vx);
-      R v[NOUT][NCOL];
+        for (int j = 0; j < NCOL; ++j) sj[j] = sl[j];
+        // keep the loads above ahead of this cell's arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+        const Geo<D, R> g = cell_geo_x<D, R>(cv.xc);
+        R v[NOUT][NCOL];
 #pragma unroll
-      for (int o = 0; o < NOUT; ++o)
+        for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-        for (int j = 0; j < NCOL; ++j) v[o][j] = R(0);
-      op(g, dl, li, v);
-      const uint8_t* sl = a.slot + (size_t)p * a.stride;
+          for (int j = 0; j < NCOL; ++j) v[o][j] = R(0);
+        if constexpr (NodalOf<Op>::on) op(g, cv.nd, code & 31, v);
+        else op(g, ix.dl, code & 31, v);
 #pragma unroll
-      for (int j = 0; j < NCOL; ++j) {
-        const int s = off + 64 * sl[j];
+        for (int j = 0; j < NCOL; ++j) {
+          const int s = off + 64 * sj[j];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) lds[o * bent + s] += v[o][j];
+          for (int o = 0; o < NOUT; ++o) lds[o * bent + s] += v[o][j];
+        }
+        code = code1;
+        code1 = code2;
+        code2 = code3;
+        ix = ix1;
+        ix1 = ix2;
+        cv = cv1;
       }
     }
   }
@@ -916,13 +1029,36 @@ __global__ void __launch_bounds__(256) k_asm_local(RowAsm a, const R* loc) {
   const int row = r0 + threadIdx.x;
   if (row < a.nrows) {
     const int off = a.sptr[row >> 6] - base + (row & 63);
-    for (int p = a.inc_ptr[row]; p < a.inc_ptr[row + 1]; ++p) {
-      const int code = a.inc[p];
-      const int cell = code >> 5, li = code & 31;
-      const R* lr = loc + ((size_t)cell * NL + li) * NL;
-      const uint8_t* sl = a.slot + (size_t)p * a.stride;
+    const int pb = a.inc_ptr[row], pe = a.inc_ptr[row + 1];
+    // incident cells in batches of NB: the batch's codes, then its local rows
+    // and slot indices, then the additions in incidence order (entries past
+    // the row's last cell re-read it and are not added)
+    constexpr int NB = NL <= 10 ? 4 : 2;
+    for (int p = pb; p < pe; p += NB) {
+      int code[NB];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) lds[off + 64 * sl[j]] += lr[j];
+      for (int k = 0; k < NB; ++k) code[k] = a.inc[min(p + k, pe - 1)];
+      R v[NB][NL];
+      int sj[NB][NL];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int cell = code[k] >> 5, li = code[k] & 31;
+        const R* lr = loc + ((size_t)cell * NL + li) * NL;
+        const uint8_t* sl = a.slot + (size_t)min(p + k, pe - 1) * a.stride;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          v[k][j] = lr[j];
+          sj[k][j] = sl[j];
+        }
+      }
+      // all of the batch's loads in flight before the first addition
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (p + k >= pe) break;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) lds[off + 64 * sj[k][j]] += v[k][j];
+      }
     }
   }
   __syncthreads();
