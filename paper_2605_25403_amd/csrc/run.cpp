@@ -127,12 +127,15 @@ int status_to_code(int s) {
 
 // Host side of a solve: start, then launch iterations in chunks and poll the
 // status words between chunks. Chunks are sized from the previous solve of the
-// same set: half of the expected remaining iterations, but at least as many
+// same set: the first one all of its length but a margin (a sixteenth, and at
+// least the least chunk below), then half of the expected remaining
+// iterations, but at least as many
 // launches as take the device time one poll leaves idle (both measured with
 // events in the previous solve; check_every before the first one, and never
 // more than check_every). A solve
-// that takes as long as the last one polls about log2 of its length times, and
-// overshoots its convergence by about the cost of one poll. Past the expected
+// that takes as long as the last one polls about 1 + log2 of the margin (in
+// least chunks) times, and overshoots its convergence by about the cost of one
+// poll. Past the expected
 // length, or after a restart, chunks double from the least one. Launches past
 // convergence are not free: kernels issue their loads before they read the
 // status. Parity par alternates with every iteration launch.
@@ -334,6 +337,8 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
       if (restarted || launched >= S.last_iters) {
         chunk = least << std::min(tail, 10);
         ++tail;
+      } else if (launched == 0) {
+        chunk = std::max(least, (S.last_iters - std::max(least * ipl, S.last_iters / 16)) / ipl);
       } else {
         chunk = std::max(least, (S.last_iters - launched) / 2 / ipl);
       }
