@@ -1087,13 +1087,208 @@ __global__ void __launch_bounds__(256) k_asm_local_g(RowAsm a, const R* loc) {
   }
 }
 
+// ------------------------------------------------------------------ cell pass on matrix cores
+// For the velocity elements with ten local rows (P2 on tetrahedra, P3 on
+// triangles) the local matrices of a batch of cells are one dense product.
+// With b_q = J^{-1} u_h(x_q) the reference-frame velocity (as above),
+//   E_ij = (|J| / dt) Mref_ij + sum_{q, a} (cs |J| b_q[a]) (w_q phi_i(x_q) dref_a phi_j(x_q)),
+// Mref_ij = sum_q w_q phi_i(x_q) phi_j(x_q): the row of a cell's K = D NQ + 1
+// coefficients [cs |J| b_q[a] for every (q, a), |J| / dt] times the fixed
+// table T[k][i NL + j] (K padded to a multiple of 4, the 100 columns to 112).
+// A wavefront takes 16 cells as the M dimension of the 16x16x4 MFMA (FP32
+// in the mixed form, FP64 otherwise), the table in 7 column tiles of 16 from
+// LDS (each block builds it once from the FP64 reference tables), and writes
+// the cells' local matrices to the buffer the local-sum pass reads. Lane l
+// feeds row l mod 16 (its cell) and K slot l / 16 of each group of four; the
+// slots are dealt to the four lane groups so that a lane forms b_q at as few
+// quadrature points as possible.
+template <int D, int NQ>
+struct MfmaSlots {
+  static constexpr int MASS = -1, PAD = -2;
+  static constexpr int K = (D * NQ + 1 + 3) / 4 * 4, S = K / 4;
+  // slot 4 s + g: q * 4 + a, MASS or PAD; point q's D items go to group
+  // q mod 4 while it has room, else to the next group with room
+  int item[K];
+  constexpr MfmaSlots() : item() {
+    int fill[4] = {0, 0, 0, 0};
+    for (int k = 0; k < K; ++k) item[k] = PAD;
+    for (int v = 0; v <= D * NQ; ++v) {
+      const int q = v / D;
+      int g = v < D * NQ ? q & 3 : 0;
+      while (fill[g] >= S) g = (g + 1) & 3;
+      item[4 * fill[g] + g] = v < D * NQ ? q * 4 + v % D : MASS;
+      fill[g] += 1;
+    }
+  }
+};
+// the tables of the two elements the matrix-core pass serves, built at compile time
+__constant__ MfmaSlots<3, Rule<3>::NQ> c_slots_tet_p2 = MfmaSlots<3, Rule<3>::NQ>();
+__constant__ MfmaSlots<2, RuleT9::NQ> c_slots_tri_p3 = MfmaSlots<2, RuleT9::NQ>();
+
+template <int D, int NQ>
+__device__ __forceinline__ const MfmaSlots<D, NQ>& mfma_slots() {
+  if constexpr (D == 3) return c_slots_tet_p2;
+  else return c_slots_tri_p3;
+}
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+__device__ __forceinline__ auto mfma16(R a, R b, typename std::conditional<std::is_same_v<R, float>, mf4, md4>::type c) {
+  if constexpr (std::is_same_v<R, float>) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int D, class R, int P3>
+__global__ void __launch_bounds__(256, 3) k_conv_cells_mfma(RowAsm a, int64_t nc, const double* U,
+                                                         int64_t n2, double inv_dt, double cs,
+                                                         R* out) {
+  using E = VelElem<D, P3, double>;
+  constexpr int NL = E::NL, NQ = E::NQ, NN = NL * NL, NT = (NN + 15) / 16, NC = 16 * NT;
+  static_assert(NL == 10, "matrix-core cell pass: elements with ten local rows");
+  using SL = MfmaSlots<D, NQ>;
+  constexpr int K = SL::K, S = SL::S;
+  using acc_t = typename std::conditional<std::is_same_v<R, float>, mf4, md4>::type;
+  __shared__ R sT[K][NC];
+  __shared__ R sPhi[NQ][NL];
+  __shared__ int sItem[K];
+  const auto& T = E::table();
+  {
+    static_assert(std::is_same_v<SL, std::remove_cv_t<std::remove_reference_t<decltype(mfma_slots<D, NQ>())>>>,
+                  "slot table of this element");
+    for (int k = threadIdx.x; k < K; k += blockDim.x) sItem[k] = mfma_slots<D, NQ>().item[k];
+    for (int e = threadIdx.x; e < NQ * NL; e += blockDim.x)
+      sPhi[e / NL][e % NL] = (R)T.phi[e / NL][e % NL];
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * NC; e += blockDim.x) {
+      const int k = e / NC, n = e % NC, it = sItem[k];
+      double v = 0.0;
+      if (n < NN && it != SL::PAD) {
+        const int i = n / NL, j = n % NL;
+        if (it == SL::MASS) {
+          for (int q = 0; q < NQ; ++q) v += T.w[q] * T.phi[q][i] * T.phi[q][j];
+        } else {
+          const int q = it >> 2, c = it & 3;
+          v = T.w[q] * T.phi[q][i] * T.dphi[q][j][c];
+        }
+      }
+      sT[k][n] = (R)v;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+  const int64_t ntile = (nc + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile;
+       tile += (int64_t)gridDim.x * 4) {
+    const int64_t c0 = tile * 16;
+    const int64_t cell = c0 + m < nc ? c0 + m : nc - 1;
+    int32_t vx[D + 1];
+    cell_vertices<D>(a, cell, vx);
+    const Geo<D, R> geo = cell_geo<D, R>(a.X, vx);
+    const int32_t* dofs = a.c2d + (size_t)cell * a.nloc2;
+    R u[D][NL];
+#pragma unroll
+    for (int mm = 0; mm < NL; ++mm) {
+      const int32_t dm = dofs[mm];
+#pragma unroll
+      for (int c = 0; c < D; ++c) u[c][mm] = (R)U[(size_t)c * n2 + dm];
+    }
+    const R idt = (R)inv_dt, csd = (R)cs * geo.det;
+    R av[S];
+    int qprev = -1;
+    R uh[D] = {};
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      const int it = sItem[4 * sl + g];
+      R v = R(0);
+      if (it == SL::MASS) {
+        v = geo.det * idt;
+      } else if (it >= 0) {
+        const int q = it >> 2, c = it & 3;
+        if (q != qprev) {
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) {
+            R sum = R(0);
+#pragma unroll
+            for (int mm = 0; mm < NL; ++mm) sum += u[cc][mm] * sPhi[q][mm];
+            uh[cc] = sum;
+          }
+          qprev = q;
+        }
+        R b = R(0);   // (J^{-1} u_h)[c], the row chosen without an indexed array
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          R br = R(0);
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) br += geo.Ji[r][cc] * uh[cc];
+          b = c == r ? br : b;
+        }
+        v = csd * b;
+      }
+      av[sl] = v;
+    }
+    acc_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    // each slot's column tiles are read from LDS one slot ahead of its MFMAs
+    R bt[2][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bt[0][t] = sT[g][16 * t + m];
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      if (sl + 1 < S) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bt[(sl + 1) & 1][t] = sT[4 * (sl + 1) + g][16 * t + m];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        // FP32: the transposed product (table as the first operand), so that a
+        // lane ends with four consecutive entries of one cell
+        if constexpr (std::is_same_v<R, float>) acc[t] = mfma16<R>(bt[sl & 1][t], av[sl], acc[t]);
+        else acc[t] = mfma16<R>(av[sl], bt[sl & 1][t], acc[t]);
+      }
+    }
+    if constexpr (std::is_same_v<R, float>) {
+      // lane l: entries 16 t + 4 (l / 16) + r, r = 0..3, of cell c0 + l mod 16
+      // (NN = 100 is a multiple of 4: a group of four is in range or not at all)
+      const int64_t oc = c0 + m;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = 16 * t + 4 * g;
+        if (n < NN && oc < nc) *reinterpret_cast<mf4*>(out + (size_t)oc * NN + n) = acc[t];
+      }
+    } else {
+      // lane l: rows l / 16 + 4 r (cells) of column l mod 16 (entries)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = 16 * t + m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t oc = c0 + g + 4 * r;
+          if (n < NN && oc < nc) out[(size_t)oc * NN + n] = acc[t][r];
+        }
+      }
+    }
+  }
+}
+
 template <int D, class R, int P3>
 static void conv_cells(hipStream_t s, const RowAsm& a, int64_t nc, const double* U, int64_t n2,
                        double inv_dt, double cs, void* buf) {
-  constexpr int CPB = 256 / VelElem<D, P3, R>::NL;
+  constexpr int NL = VelElem<D, P3, R>::NL, CPB = 256 / NL;
   if (nc <= 0) return;
-  launch(k_conv_cells<D, R, P3>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, a, nc, U, n2,
-         inv_dt, cs, static_cast<R*>(buf));
+  if constexpr (NL == 10) {
+    // matrix cores: one tile of 16 cells per wavefront, at most 8 blocks per CU
+    const int64_t tiles = div_up(nc, 16);
+    const unsigned nb = (unsigned)std::min<int64_t>(div_up(tiles, 4), 2048);
+    launch(k_conv_cells_mfma<D, R, P3>, dim3(nb), dim3(256), 0, s, a, nc, U, n2, inv_dt, cs,
+           static_cast<R*>(buf));
+  } else {
+    launch(k_conv_cells<D, R, P3>, dim3((unsigned)div_up(nc, CPB)), dim3(256), 0, s, a, nc, U, n2,
+           inv_dt, cs, static_cast<R*>(buf));
+  }
 }
 
 template <int D, class R, int P3>
