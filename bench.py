@@ -211,7 +211,7 @@ def pmc_summary(fetch_dir, write_dir, kernel, workload, calib_mib, command):
     sym = {"pcg_update_p": r"k_cg_update<1>", "pcg_spmv_p": r"k_cg_spmv<1,",
            "pcg_fused_p": r"k_fcg_iter1?<",
            "bicg_update_x": r"k_bicg_5<", "bicg_spmv": r"k_bicg_spmv<0,",
-           "asm_conv": r"OpConv<|k_conv_cells<", "asm_sum": r"k_asm_local<"}[kernel]
+           "asm_conv": r"OpConv<|k_conv_cells(_mfma)?<", "asm_sum": r"k_asm_local<"}[kernel]
     # the calibration copy is a device-to-device hipMemcpy (torch's copy_ of
     # contiguous tensors); fills (torch's elementwise FillFunctor) are not
     copy_re = re.compile(r"copyBuffer")
@@ -293,6 +293,10 @@ def counters_summary(run_dirs, kernel_regex, name, workload, command, clock_ghz=
             if "SQ_ACTIVE_INST_VALU" in med:
                 o.write(f"VALU busy 4*SQ_ACTIVE_INST_VALU/(1024*cycles): "
                         f"{4 * med['SQ_ACTIVE_INST_VALU'] / (1024 * cyc):.3f}\n")
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in med:
+                # summed over the SIMDs, as SQ_BUSY_CYCLES is summed over the SEs
+                o.write(f"MFMA busy SQ_VALU_MFMA_BUSY_CYCLES/(1024*cycles): "
+                        f"{med['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024 * cyc):.3f}\n")
         if "GRBM_GUI_ACTIVE" in med and "SQ_ACTIVE_INST_VALU" in med:
             # GRBM_GUI_ACTIVE reads the busy cycles of the 8 XCDs summed
             o.write(f"VALU busy 4*SQ_ACTIVE_INST_VALU/(1024*GRBM_GUI_ACTIVE/8): "
