@@ -127,8 +127,8 @@ int status_to_code(int s) {
 
 // Host side of a solve: start, then launch iterations in chunks and poll the
 // status words between chunks. Chunks are sized from the previous solve of the
-// same set: the first one all of its length but a margin (a sixteenth, and at
-// least the least chunk below), then half of the expected remaining
+// same set: for one run the first one all of its length but a margin (a
+// sixteenth, and at least the least chunk below), then half of the expected remaining
 // iterations, but at least as many
 // launches as take the device time one poll leaves idle (both measured with
 // events in the previous solve; check_every before the first one, and never
@@ -337,7 +337,9 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
       if (restarted || launched >= S.last_iters) {
         chunk = least << std::min(tail, 10);
         ++tail;
-      } else if (launched == 0) {
+      } else if (launched == 0 && S.L.ngroups == 1) {
+        // (sets of several runs halve from the start: their runs end at
+        // different counts, and a poll is where finished ones leave the launches)
         chunk = std::max(least, (S.last_iters - std::max(least * ipl, S.last_iters / 16)) / ipl);
       } else {
         chunk = std::max(least, (S.last_iters - launched) / 2 / ipl);
