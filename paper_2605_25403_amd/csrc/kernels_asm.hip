@@ -988,25 +988,41 @@ __global__ void __launch_bounds__(256) k_conv_cells(RowAsm a, int64_t nc, const 
     }
   }
   __syncthreads();
-  if (!act) return;
-  const R idt = (R)inv_dt, csr = (R)cs, det = s_det[cl];
+  const R idt = (R)inv_dt, csr = (R)cs, det = act ? s_det[cl] : R(0);
   R v[NL];
 #pragma unroll
   for (int j = 0; j < NL; ++j) v[j] = R(0);
-#pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    R beta[D];
+  // the factor d_qj = phi_j(x_q) / dt + cs beta_q . grad_ref phi_j(x_q) is the
+  // same for every row of a cell: the cell's threads form it for a chunk of QC
+  // points in LDS, then each row adds w_q |J| phi_li(x_q) d_qj over the chunk
+  constexpr int QC = 5;
+  __shared__ R s_d[CPB][QC][NL];
+  for (int q0 = 0; q0 < NQ; q0 += QC) {
+    if (act) {
+      for (int e = li; e < QC * NL; e += NL) {
+        const int q = q0 + e / NL, j = e % NL;
+        if (q < NQ) {
+          R adv = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) beta[a] = s_beta[cl][q][a];
-    const R ci = T.w[q] * det * T.phi[q][li];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      R adv = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) adv += beta[a] * T.dphi[q][j][a];
-      v[j] += ci * (T.phi[q][j] * idt + csr * adv);
+          for (int a = 0; a < D; ++a) adv += s_beta[cl][q][a] * T.dphi[q][j][a];
+          s_d[cl][e / NL][j] = T.phi[q][j] * idt + csr * adv;
+        }
+      }
     }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int qq = 0; qq < QC; ++qq) {
+        const int q = q0 + qq;
+        if (q >= NQ) break;
+        const R ci = T.w[q] * det * T.phi[q][li];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) v[j] += ci * s_d[cl][qq][j];
+      }
+    }
+    __syncthreads();
   }
+  if (!act) return;
   R* o = out + ((size_t)cell * NL + li) * NL;
 #pragma unroll
   for (int j = 0; j < NL; ++j) o[j] = v[j];
