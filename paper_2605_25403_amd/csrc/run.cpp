@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "builtin.hpp"
@@ -139,6 +140,29 @@ int status_to_code(int s) {
 // length, or after a restart, chunks double from the least one. Launches past
 // convergence are not free: kernels issue their loads before they read the
 // status. Parity par alternates with every iteration launch.
+static std::mutex g_pinned_mu;
+static std::vector<KState*> g_pinned_free;
+
+KState* pinned_take() {
+  {
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      KState* p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  KState* p = nullptr;
+  HIP_OK(hipHostMalloc((void**)&p, sizeof(KState) * kPinnedStates, hipHostMallocDefault));
+  return p;
+}
+
+void pinned_give(KState* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_pinned_mu);
+  g_pinned_free.push_back(p);
+}
+
 LaunchEvents*& launch_events() {
   thread_local LaunchEvents* slot = nullptr;
   return slot;
@@ -621,7 +645,7 @@ void Run::layout(Carver& c) {
 Run::~Run() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
-  if (pinned) (void)hipHostFree(pinned);
+  pinned_give(pinned);
 }
 
 template <class T>
@@ -938,7 +962,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   c.base = static_cast<char*>(ws);
   layout(c);
   ws_bytes = bytes;
-  HIP_OK(hipHostMalloc((void**)&pinned, sizeof(KState) * 3 * GMAX, hipHostMallocDefault));
+  pinned = pinned_take();
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   upload_mesh();
   // value arrays: SELL padding entries must read as zero

@@ -98,6 +98,15 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every,
                  bool time_bursts = true);
 int status_to_code(int kstatus);
 
+// Pinned host staging for status polls (kPinnedStates states each), from a
+// process-wide pool: freeing pinned memory waits for every stream of the
+// device, so a run that ends (a served request) would otherwise stall the
+// other runs' streams until the device drains. Buffers taken are given back
+// when their run ends and are reused; the pool is freed with the process.
+constexpr int kPinnedStates = 3 * GMAX;
+KState* pinned_take();
+void pinned_give(KState* p);
+
 // Rows per thread of matrix kernels for a group of n rows, and the block
 // counts of matrix / vector kernels (each at most KNB_MAX).
 int kept_m_for(int64_t n, int ns);

@@ -99,7 +99,7 @@ void up(hipStream_t s, T* dst, const std::vector<T>& src) {
 }  // namespace
 
 Steady::~Steady() {
-  if (pinned) (void)hipHostFree(pinned);
+  pinned_give(pinned);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -241,7 +241,7 @@ void Steady::create(std::shared_ptr<const Mesh> msh, const ipcs_steady_params& p
   setA.L = KLaunch{kgroup, 1, 1, kept_m_for(nu_rows, 1), 0, bm, (int)mm.size(), bv,
                    (int)mv.size(), fold_for(nu_rows, 1)};
   setA.d_poll = poll;
-  HIP_OK(hipHostMalloc((void**)&pinned, sizeof(KState) * GMAX, hipHostMallocDefault));
+  pinned = pinned_take();
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   // the host copies above are stack or member vectors: finish the transfers
   HIP_OK(hipStreamSynchronize(st));
