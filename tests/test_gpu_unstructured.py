@@ -2,6 +2,10 @@
 vertices relabelled, cells reordered and half of them of opposite orientation.
 Geometry then differs from cell to cell, matrix rows have irregular lengths and
 column indices are scattered, which the structured meshes do not exercise.
+Both Taylor-Hood pairs: with P3-P2 the convection assembly takes its two-pass
+form (the matrix-core cell pass on triangles, the per-thread one on
+tetrahedra), whose cell batches then hold cells of every shape and orientation
+and end in a ragged last batch.
 Bars as for the structured meshes: matrices max|dA|/max|A| <= 1e-12, fields
 ||dx||/||x|| <= 1e-10 per component and for the pressure, per step."""
 import numpy as np
@@ -15,19 +19,21 @@ pytestmark = pytest.mark.gpu
 
 MAT_TOL = 1e-12
 FIELD_TOL = 1e-10
-CASES = [(2, 9, 0), (2, 21, 4), (3, 3, 1)]
+# (dim, n, seed, P3-P2 pair)
+CASES = [(2, 9, 0, False), (2, 21, 4, False), (3, 3, 1, False), (2, 7, 2, True),
+         (3, 2, 3, True)]
 
 
-def pair(I, dim, n, seed, nu, dt, **kw):
+def pair(I, dim, n, seed, nu, dt, p3=False, **kw):
     kind = "tg" if dim == 2 else "beltrami"
-    return make_pair(I, dim, n, kind, nu, dt, arrays=jittered_mesh(dim, n, seed), **kw)
+    return make_pair(I, dim, n, kind, nu, dt, arrays=jittered_mesh(dim, n, seed), p3=p3, **kw)
 
 
-@pytest.mark.parametrize("dim,n,seed", CASES)
-def test_unstructured_matrices(dim, n, seed):
+@pytest.mark.parametrize("dim,n,seed,p3", CASES)
+def test_unstructured_matrices(dim, n, seed, p3):
     torch, I = require_gpu()
-    print(f"unstructured matrices dim={dim} n={n} seed={seed}", flush=True)
-    S, o, r = pair(I, dim, n, seed, 0.013, 0.007)
+    print(f"unstructured matrices dim={dim} n={n} seed={seed} p3={p3}", flush=True)
+    S, o, r = pair(I, dim, n, seed, 0.013, 0.007, p3=p3)
     errs = {"M": mat_rel(r.matrix(I.IPCS_MAT_M), o.M),
             "K": mat_rel(r.matrix(I.IPCS_MAT_K), o.K),
             "Kp": mat_rel(r.matrix(I.IPCS_MAT_KP), o.Kp),
@@ -43,12 +49,12 @@ def test_unstructured_matrices(dim, n, seed):
     assert max(errs.values()) <= MAT_TOL, errs
 
 
-@pytest.mark.parametrize("dim,n,seed", CASES)
-def test_unstructured_substeps_and_steps(dim, n, seed):
+@pytest.mark.parametrize("dim,n,seed,p3", CASES)
+def test_unstructured_substeps_and_steps(dim, n, seed, p3):
     torch, I = require_gpu()
-    print(f"unstructured steps dim={dim} n={n} seed={seed}", flush=True)
+    print(f"unstructured steps dim={dim} n={n} seed={seed} p3={p3}", flush=True)
     dt = 0.01
-    S, o, r = pair(I, dim, n, seed, 0.01, dt)
+    S, o, r = pair(I, dim, n, seed, 0.01, dt, p3=p3)
     t1 = o.t + dt
     g = o.dirichlet(t1)
     r.phase(I.IPCS_PHASE_ASM)
