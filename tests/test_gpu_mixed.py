@@ -15,6 +15,7 @@ and the bars are the stated error bounds of the form:
 import numpy as np
 import pytest
 
+from oracle import fem
 from tests.gpu_common import field_errors, make_pair, mat_rel, rel, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -28,12 +29,15 @@ def mixed_pair(I, dim, n, kind, nu, dt, **kw):
     return make_pair(I, dim, n, kind, nu, dt, precision=I.IPCS_MIXED, tol_ir=TOL_IR, **kw)
 
 
-@pytest.mark.parametrize("dim,n", [(2, 16), (3, 3)])
-def test_mixed_matrices_within_fp32_bound(dim, n):
+@pytest.mark.parametrize("dim,n,p3", [(2, 16, False), (3, 3, False), (2, 8, True), (3, 2, True)])
+def test_mixed_matrices_within_fp32_bound(dim, n, p3):
+    """The constant matrices and the convection matrix E = M/dt - C(U) of the
+    first step (in 3D and for P3-P2 formed by the two-pass assembly: FP32
+    matrix cores for P2 tetrahedra and P3 triangles) within the FP32 bound."""
     torch, I = require_gpu()
-    print(f"mixed matrices dim={dim} n={n}", flush=True)
+    print(f"mixed matrices dim={dim} n={n} p3={p3}", flush=True)
     kind = "tg" if dim == 2 else "beltrami"
-    S, o, r = mixed_pair(I, dim, n, kind, 0.013, 0.007)
+    S, o, r = mixed_pair(I, dim, n, kind, 0.013, 0.007, p3=p3)
     errs = {"M": mat_rel(r.matrix(I.IPCS_MAT_M), o.M),
             "K": mat_rel(r.matrix(I.IPCS_MAT_K), o.K),
             "Kp": mat_rel(r.matrix(I.IPCS_MAT_KP), o.Kp),
@@ -41,6 +45,10 @@ def test_mixed_matrices_within_fp32_bound(dim, n):
     for c in range(dim):
         errs[f"D{c}"] = mat_rel(r.matrix(I.IPCS_MAT_D0 + c), o.D[c])
         errs[f"G{c}"] = mat_rel(r.matrix(I.IPCS_MAT_G0 + c), o.G[c])
+    r.phase(I.IPCS_PHASE_ASM)
+    E = (o.M / o.prm.dt - fem.convection(S, o.U)).tocsr()
+    E.sort_indices()
+    errs["E"] = mat_rel(r.matrix(I.IPCS_MAT_E), E)
     print(errs, flush=True)
     assert max(errs.values()) <= MIX_MAT_TOL, errs
     # the values really are FP32: exactly representable in single precision
