@@ -361,6 +361,7 @@ int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes) 
     ipcs::Run tmp;
     tmp.mesh = m->m;
     tmp.prm = *p;
+    tmp.set_precision();   // the layout of the run's own form
     tmp.sizes_from_mesh();
     ipcs::Carver c;
     tmp.layout(c);

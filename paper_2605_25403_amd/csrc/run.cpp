@@ -453,6 +453,11 @@ int krylov_solve(hipStream_t s, KSet& S, KMethod m, int check_every, std::vector
 }
 
 // ------------------------------------------------------------------ layout
+void Run::set_precision() {
+  mixed = prm.precision == IPCS_MIXED;
+  vsz = mixed ? 4 : 8;
+}
+
 void Run::sizes_from_mesh() {
   const Mesh& m = *mesh;
   dim = m.dim;
@@ -945,8 +950,7 @@ void Run::create(std::shared_ptr<const Mesh> m, const ipcs_params& p, void* ws, 
   mesh = std::move(m);
   prm = p;
   stream = s;
-  mixed = prm.precision == IPCS_MIXED;
-  vsz = mixed ? 4 : 8;
+  set_precision();
   sizes_from_mesh();
   const Mesh& mm = *mesh;
   cfg_mk = asm_cfg(mm.e22, vsz);

@@ -230,6 +230,7 @@ struct Run {
   hipEvent_t ev[5] = {};
 
   ~Run();
+  void set_precision();   // mixed and vsz from prm.precision
   void sizes_from_mesh();
   void choose_poisson_form();
   void layout(Carver& c);

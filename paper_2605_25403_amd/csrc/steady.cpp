@@ -164,6 +164,7 @@ int64_t Steady::measure(std::shared_ptr<const Mesh> msh, const ipcs_steady_param
   Run probe;
   probe.mesh = msh;
   probe.prm = run_params(p);
+  probe.set_precision();
   probe.sizes_from_mesh();
   Carver cm;
   probe.layout(cm);
