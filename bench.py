@@ -368,6 +368,56 @@ def mixed_form(w, steps, torch, I):
     return out
 
 
+def start_form(w, steps, torch, I):
+    """The pressure Poisson solve started from the previous step's increment
+    against the zero start, on the same problem and start (FP64, and the
+    mixed form with the previous start): throughput, Poisson iterations, and
+    the per-step relative L2 difference of u and p from the zero start's
+    fields (both meet the same stopping test, eq. (9), second line)."""
+    from paper_2605_25403_amd.workloads import dofs
+    m = I.Mesh.unit_square(w["n"]) if w["dim"] == 2 else I.Mesh.unit_cube(w["n"])
+    variants = {"fp64_zero": (I.IPCS_FP64, I.IPCS_START_ZERO),
+                "fp64_previous": (I.IPCS_FP64, I.IPCS_START_PREVIOUS),
+                "mixed_previous": (I.IPCS_MIXED, I.IPCS_START_PREVIOUS)}
+    runs = {}
+    for name, (prec, start) in variants.items():
+        p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
+                                  tol_corr=w["tol"], tol_ir=1e-10, precision=prec,
+                                  poisson_start=start)
+        r = I.Run(m, p, stream=torch.cuda.Stream())
+        if w["dim"] == 2:
+            r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        else:
+            r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+        runs[name] = r
+    lat = {k: [] for k in runs}
+    it = {k: [] for k in runs}
+    diff = {k: {"u": [], "p": []} for k in runs if k != "fp64_zero"}
+    for _ in range(steps):
+        for name, r in runs.items():
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat[name].append(time.perf_counter() - t0)
+            it[name].append(st["it_p"])
+        U0, P0 = runs["fp64_zero"].velocity(), runs["fp64_zero"].pressure()
+        for name, d in diff.items():
+            d["u"].append(float(np.linalg.norm(runs[name].velocity() - U0) / np.linalg.norm(U0)))
+            d["p"].append(float(np.linalg.norm(runs[name].pressure() - P0) / np.linalg.norm(P0)))
+    nd = dofs(w["dim"], w["n"])
+    out = {"steps": steps}
+    for name in runs:
+        # the first step starts from zero in every variant: medians over the rest
+        ms = 1000.0 * float(np.median(lat[name][1:]))
+        out[name] = {"value": nd / (ms / 1000.0), "p50_step_ms": ms,
+                     "pressure_iterations_median": float(np.median(it[name][1:])),
+                     "pressure_iterations": it[name]}
+        if name in diff:
+            out[name]["rel_l2_diff_vs_zero_start_u"] = diff[name]["u"]
+            out[name]["rel_l2_diff_vs_zero_start_p"] = diff[name]["p"]
+            out[name]["speedup_vs_zero_start"] = out[name]["value"] / out["fp64_zero"]["value"]
+    return out
+
+
 def scheme_forms(w, steps, torch, I):
     """IPCS with explicit convection (eq. (9) as printed), IPCS with
     semi-implicit convection, and the Chorin-Temam projection, on the same
@@ -900,6 +950,7 @@ def main():
     if not args.no_forms and not mixed and not p3:
         out["forms"] = {}
         for name, fn in (("mixed", lambda: mixed_form(w, args.form_steps, torch, I)),
+                         ("poisson_start", lambda: start_form(w, args.form_steps, torch, I)),
                          ("schemes", lambda: scheme_forms(w, args.form_steps, torch, I)),
                          ("serving", lambda: serving_form(torch, I)),
                          ("c4", lambda: c4_form(torch, I)),

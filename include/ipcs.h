@@ -220,6 +220,19 @@ enum { IPCS_CONV_EXPLICIT = 0, IPCS_CONV_SEMI_IMPLICIT = 1 };
  * zero integral mean) and the correction uses it; the right-hand-side sign
  * is read as for IPCS. */
 enum { IPCS_SCHEME_IPCS = 0, IPCS_SCHEME_CHORIN = 1 };
+/* Start of the pressure Poisson solve (eq. (9), second line; Section 2.2.1
+ * fixes the system, not the Krylov start). IPCS_START_ZERO: dP = 0 at every
+ * step. IPCS_START_PREVIOUS: the previous step's dP (IPCS: the last
+ * increment; Chorin-Temam: the last pressure), which the stopping test
+ * ||r - Kp dP|| <= tol_p ||r|| judges the same way, so the result meets the
+ * same tolerance (with a few percent fewer iterations on the Taylor-Green
+ * and Beltrami problems, where dP changes by ~1e-3 of itself per step). In
+ * the mixed form the first refinement pass's inner solve starts there (the
+ * refinement itself still starts from dP = 0). The first step after
+ * ipcs_run_create, ipcs_set_builtin_solution or ipcs_set_state starts from
+ * 0, so a run resumed from a saved state differs from the uninterrupted one
+ * within the tolerance (not bit for bit, as it does with IPCS_START_ZERO). */
+enum { IPCS_START_ZERO = 0, IPCS_START_PREVIOUS = 1 };
 
 typedef struct {
   double nu;            /* kinematic viscosity                                 */
@@ -251,6 +264,7 @@ typedef struct {
                          * a basis of the matrix powers and one reduction of
                          * its Gram matrix; needs the part's second halo ring
                          * in LDS); 0 (default) chooses 1                    */
+  int32_t poisson_start; /* IPCS_START_ZERO (default) or IPCS_START_PREVIOUS  */
 } ipcs_params;
 
 /* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12

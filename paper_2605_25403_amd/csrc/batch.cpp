@@ -308,7 +308,8 @@ static void refine_shared(const std::vector<Run*>& runs, hipStream_t s, std::map
           std::min(0.5, std::max({need, 0.5 * q.contraction, q.floor_in, r->prm.tol_p}));
       q.last_tol = tol_in;
       set_tolerance(s, r->set_p.L, tol_in * tol_in);
-      HIP_OK(hipMemsetAsync(r->dIR, 0, sizeof(double) * r->n1, s));
+      if (q.outer > 0 || !r->warm_p())   // as in Run::pressure_solve
+        HIP_OK(hipMemsetAsync(r->dIR, 0, sizeof(double) * r->n1, s));
       q.outer += 1;
       inner.push_back(r);
     }

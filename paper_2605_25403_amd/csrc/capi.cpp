@@ -89,6 +89,8 @@ void check_params(const ipcs_params* p) {
            (p->poisson_part_rows >= 64 && p->poisson_part_rows <= 2048),
        "poisson_part_rows must be 0, -1 or in [64, 2048]");
   need(p->scheme == IPCS_SCHEME_IPCS || p->scheme == IPCS_SCHEME_CHORIN, "unknown scheme");
+  need(p->poisson_start == IPCS_START_ZERO || p->poisson_start == IPCS_START_PREVIOUS,
+       "unknown Poisson start");
 }
 
 // The interface numbers velocity DOFs in listing order, the library

@@ -1039,6 +1039,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
   eval_velocity(stream, dim, bi, x2, n2, t, U, n2);
   eval_pressure(stream, dim, bi, xp, n1, t, P);
   sub_weighted_mean(stream, n1, w, P, spart, scal + 2);
+  clear_pressure_start();
   phase_next = IPCS_PHASE_ASM;
   HIP_OK(hipStreamSynchronize(stream));
 }
@@ -1046,6 +1047,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
 void Run::set_state(const double* u, const double* p, double tt) {
   HIP_OK(hipMemcpyAsync(U, u, sizeof(double) * dim * n2, hipMemcpyHostToDevice, stream));
   HIP_OK(hipMemcpyAsync(P, p, sizeof(double) * n1, hipMemcpyHostToDevice, stream));
+  clear_pressure_start();
   HIP_OK(hipStreamSynchronize(stream));
   t = tt;
   phase_next = IPCS_PHASE_ASM;
@@ -1139,7 +1141,9 @@ void Run::asm_phase() {
   HIP_OK(hipEventRecord(ev[1], stream));
 }
 
-// r = -(rho/dt) sum_c D_c U*_c projected to zero sum; dP = 0.
+// r = -(rho/dt) sum_c D_c U*_c projected to zero sum; the start of the
+// solve: dP = 0, or the previous step's dP (FP64 form: dP keeps it; mixed
+// form: the first refinement pass's correction d starts there, dP = 0).
 void Run::pressure_rhs() {
   // r is a difference of terms that cancel exactly at a discrete steady
   // state; an r no larger than a bound on its own rounding error is treated
@@ -1147,6 +1151,13 @@ void Run::pressure_rhs() {
   // refinement test (scal[6]) in the mixed form
   rhs_pressure(stream, dim, false, n1, sp12, col12, Dc, Ustar, n2, -prm.rho / prm.dt, rP, spart,
                scal + 0, mixed ? nullptr : &(kst + dim)->zero2, scal + 6);
+  if (warm_p() && mixed)
+    HIP_OK(hipMemcpyAsync(dIR, dP, sizeof(double) * n1, hipMemcpyDeviceToDevice, stream));
+  if (!warm_p() || mixed) HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
+}
+
+// The next solve starts from dP = 0 (a new state or trajectory).
+void Run::clear_pressure_start() {
   HIP_OK(hipMemsetAsync(dP, 0, sizeof(double) * n1, stream));
 }
 
@@ -1445,7 +1456,7 @@ int Run::pressure_solve(std::vector<KState>& hs, ipcs_step_stats* st) {
         std::min(0.5, std::max({need, 0.5 * contraction, floor_in, prm.tol_p}));
     last_tol = tol_in;
     set_tolerance(stream, set_p.L, tol_in * tol_in);
-    HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
+    if (outer > 0 || !warm_p()) HIP_OK(hipMemsetAsync(dIR, 0, sizeof(double) * n1, stream));
     set_p.last_iters = outer < kIrHist ? ir_last[outer] : 0;
     rc = krylov_solve(stream, set_p, KMethod::PCG, prm.check_every, hs, pinned, timer);
     if (outer < kIrHist) ir_last[outer] = set_p.last_iters;

@@ -254,6 +254,8 @@ struct Run {
   void asm_phase();
   void pressure_rhs();
   void pressure_end();
+  void clear_pressure_start();
+  bool warm_p() const { return prm.poisson_start == IPCS_START_PREVIOUS; }
   void correction_rhs();
   void correction_commit();
   void finish_step(ipcs_step_stats* st);

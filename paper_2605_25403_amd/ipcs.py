@@ -31,6 +31,7 @@ IPCS_PATTERN_P2P2, IPCS_PATTERN_P1P1, IPCS_PATTERN_P1P2, IPCS_PATTERN_P2P1 = 0, 
 IPCS_FP64, IPCS_MIXED = 0, 1
 IPCS_CONV_EXPLICIT, IPCS_CONV_SEMI_IMPLICIT = 0, 1
 IPCS_SCHEME_IPCS, IPCS_SCHEME_CHORIN = 0, 1
+IPCS_START_ZERO, IPCS_START_PREVIOUS = 0, 1
 IPCS_SOL_TAYLOR_GREEN_2D, IPCS_SOL_JOHN_2D, IPCS_SOL_BELTRAMI_3D = 1, 2, 3
 IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D = 4, 5
 IPCS_SOL_POLY_CUBIC_2D = 6
@@ -68,7 +69,8 @@ class ipcs_params(C.Structure):
                 ("tol_mom", C.c_double), ("tol_p", C.c_double), ("tol_corr", C.c_double),
                 ("tol_ir", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
                 ("callbacks", C.c_int32), ("poisson_part_rows", C.c_int32),
-                ("scheme", C.c_int32), ("poisson_s", C.c_int32)]
+                ("scheme", C.c_int32), ("poisson_s", C.c_int32),
+                ("poisson_start", C.c_int32)]
 
 
 class ipcs_step_stats(C.Structure):

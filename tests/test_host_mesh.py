@@ -139,6 +139,11 @@ def test_invalid_arguments_are_reported():
         I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(convection=5))
     with pytest.raises(I.IpcsError):
         I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(scheme=2))
+    with pytest.raises(I.IpcsError):
+        I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(poisson_start=2))
+    warm = I.ipcs_params_default(poisson_start=I.IPCS_START_PREVIOUS)
+    assert I.ipcs_run_workspace_bytes(m.h, warm) == I.ipcs_run_workspace_bytes(
+        m.h, I.ipcs_params_default())
     semi = I.ipcs_params_default(convection=I.IPCS_CONV_SEMI_IMPLICIT)
     assert I.ipcs_run_workspace_bytes(m.h, semi) == I.ipcs_run_workspace_bytes(
         m.h, I.ipcs_params_default())
