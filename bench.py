@@ -418,6 +418,53 @@ def start_form(w, steps, torch, I):
     return out
 
 
+def momentum_start_form(w, steps, torch, I):
+    """The momentum solve from U^n against the default extrapolated start
+    2 U*^n - U*^(n-1), same problem and start (FP64): throughput, BiCGStab
+    iterations per component, and the per-step relative L2 difference of the
+    two runs' u and p (both meet the same stopping test, eq. (9), first
+    line)."""
+    from paper_2605_25403_amd.workloads import dofs
+    m = I.Mesh.unit_square(w["n"]) if w["dim"] == 2 else I.Mesh.unit_cube(w["n"])
+    runs = {}
+    for name, ms in (("from_state", I.IPCS_MSTART_STATE),
+                     ("extrapolated", I.IPCS_MSTART_EXTRAPOLATED)):
+        p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
+                                  tol_corr=w["tol"], momentum_start=ms)
+        r = I.Run(m, p, stream=torch.cuda.Stream())
+        if w["dim"] == 2:
+            r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        else:
+            r.set_builtin(I.IPCS_SOL_BELTRAMI_3D, ())
+        runs[name] = r
+    lat = {k: [] for k in runs}
+    it = {k: [] for k in runs}
+    mom = {k: [] for k in runs}
+    du, dp = [], []
+    for _ in range(steps):
+        for name, r in runs.items():
+            t0 = time.perf_counter()
+            st = r.advance(1)[0]
+            lat[name].append(time.perf_counter() - t0)
+            it[name].append(max(st["it_mom"][:w["dim"]]))
+            mom[name].append(st["ms"][1])
+        a, b = runs["from_state"], runs["extrapolated"]
+        du.append(float(np.linalg.norm(b.velocity() - a.velocity()) / np.linalg.norm(a.velocity())))
+        dp.append(float(np.linalg.norm(b.pressure() - a.pressure()) / np.linalg.norm(a.pressure())))
+    nd = dofs(w["dim"], w["n"])
+    out = {"steps": steps}
+    for name in runs:
+        # the first two steps start from U^n in both: medians over the rest
+        ms = 1000.0 * float(np.median(lat[name][2:]))
+        out[name] = {"value": nd / (ms / 1000.0), "p50_step_ms": ms,
+                     "momentum_ms_median": float(np.median(mom[name][2:])),
+                     "momentum_iterations": it[name]}
+    out["rel_l2_diff_u"] = du
+    out["rel_l2_diff_p"] = dp
+    out["speedup"] = out["extrapolated"]["value"] / out["from_state"]["value"]
+    return out
+
+
 def scheme_forms(w, steps, torch, I):
     """IPCS with explicit convection (eq. (9) as printed), IPCS with
     semi-implicit convection, and the Chorin-Temam projection, on the same
@@ -951,6 +998,8 @@ def main():
         out["forms"] = {}
         for name, fn in (("mixed", lambda: mixed_form(w, args.form_steps, torch, I)),
                          ("poisson_start", lambda: start_form(w, args.form_steps, torch, I)),
+                         ("momentum_start",
+                          lambda: momentum_start_form(w, args.form_steps, torch, I)),
                          ("schemes", lambda: scheme_forms(w, args.form_steps, torch, I)),
                          ("serving", lambda: serving_form(torch, I)),
                          ("c4", lambda: c4_form(torch, I)),

@@ -91,6 +91,8 @@ void check_params(const ipcs_params* p) {
   need(p->scheme == IPCS_SCHEME_IPCS || p->scheme == IPCS_SCHEME_CHORIN, "unknown scheme");
   need(p->poisson_start == IPCS_START_ZERO || p->poisson_start == IPCS_START_PREVIOUS,
        "unknown Poisson start");
+  need(p->momentum_start == IPCS_MSTART_EXTRAPOLATED || p->momentum_start == IPCS_MSTART_STATE,
+       "unknown momentum start");
 }
 
 // The interface numbers velocity DOFs in listing order, the library
@@ -390,6 +392,7 @@ int ipcs_set_viscosity(ipcs_run r, double nu) {
     need(nu >= 0, "nu must be >= 0");
     R(r).prm.nu = nu;
     R(r).A_dirty = true;
+    R(r).clear_history();
     return IPCS_OK;
   });
 }
@@ -399,6 +402,7 @@ int ipcs_set_time_step(ipcs_run r, double dt) {
     need(dt > 0, "dt must be > 0");
     R(r).prm.dt = dt;
     R(r).A_dirty = true;
+    R(r).clear_history();
     return IPCS_OK;
   });
 }
@@ -410,6 +414,7 @@ int ipcs_set_forcing(ipcs_run r, ipcs_field_fn f, void* ctx) {
       ipcs::fail(IPCS_E_STATE, "forcing callbacks need a run created with params.callbacks = 1");
     rr.f_cb = f;
     rr.f_ctx = ctx;
+    rr.clear_history();
     return IPCS_OK;
   });
 }
@@ -418,6 +423,7 @@ int ipcs_set_dirichlet(ipcs_run r, ipcs_field_fn g, void* ctx) {
   return guard([&]() -> int {
     R(r).g_cb = g;
     R(r).g_ctx = ctx;
+    R(r).clear_history();
     return IPCS_OK;
   });
 }

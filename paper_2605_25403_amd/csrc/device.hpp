@@ -305,6 +305,9 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
+// out = 2 A - B on interior rows, the Dirichlet data on boundary rows
+void extrapolate_with_bc(hipStream_t s, int dim, const double* A, const double* B,
+                         const uint8_t* bmask, const double* gfull, double* out, int64_t n2);
 // b_c = sa E U_c - sg G_c P + F_c with Dirichlet lifting (explicit: E = M/dt -
 // C(U^n), sa = 1; semi-implicit: E = M, sa = 1/dt; sg = 1 for IPCS, 0 for the
 // Chorin projection, whose momentum step has no pressure term)

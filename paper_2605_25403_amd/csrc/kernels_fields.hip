@@ -114,6 +114,26 @@ void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
   HIP_LAUNCH_OK();
 }
 
+// out = 2 A - B (the linear extrapolation of two consecutive values in time)
+// on interior rows, the Dirichlet data on boundary rows.
+__global__ void k_extrap_bc(int dim, const double* A, const double* B, const uint8_t* bmask,
+                            const double* g, double* out, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  const bool b = bmask[i];
+  for (int c = 0; c < dim; ++c) {
+    const int64_t k = c * n2 + i;
+    out[k] = b ? g[k] : 2.0 * A[k] - B[k];
+  }
+}
+
+void extrapolate_with_bc(hipStream_t s, int dim, const double* A, const double* B,
+                         const uint8_t* bmask, const double* gfull, double* out, int64_t n2) {
+  hipLaunchKernelGGL(k_extrap_bc, dim3((unsigned)div_up(n2, 256)), dim3(256), 0, s, dim, A, B,
+                     bmask, gfull, out, n2);
+  HIP_LAUNCH_OK();
+}
+
 // ---------------------------------------------------------------- right-hand sides
 // Matrices are FP64, or FP32 in the mixed form (VT); vectors and sums are FP64.
 template <class VT>

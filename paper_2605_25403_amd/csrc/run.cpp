@@ -583,6 +583,8 @@ void Run::layout(Carver& c) {
   bU = c.take<double>(dim * n2);
   F = c.take<double>(dim * n2);
   gfull = c.take<double>(dim * n2);
+  Us1 = extrap_m() ? c.take<double>(dim * n2) : nullptr;
+  Us2 = extrap_m() ? c.take<double>(dim * n2) : nullptr;
   P = c.take<double>(n1);
   dP = c.take<double>(n1);
   rP = c.take<double>(n1);
@@ -1039,7 +1041,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
   eval_velocity(stream, dim, bi, x2, n2, t, U, n2);
   eval_pressure(stream, dim, bi, xp, n1, t, P);
   sub_weighted_mean(stream, n1, w, P, spart, scal + 2);
-  clear_pressure_start();
+  clear_history();
   phase_next = IPCS_PHASE_ASM;
   HIP_OK(hipStreamSynchronize(stream));
 }
@@ -1047,7 +1049,7 @@ void Run::set_builtin(int kind, const double* p, int np) {
 void Run::set_state(const double* u, const double* p, double tt) {
   HIP_OK(hipMemcpyAsync(U, u, sizeof(double) * dim * n2, hipMemcpyHostToDevice, stream));
   HIP_OK(hipMemcpyAsync(P, p, sizeof(double) * n1, hipMemcpyHostToDevice, stream));
-  clear_pressure_start();
+  clear_history();
   HIP_OK(hipStreamSynchronize(stream));
   t = tt;
   phase_next = IPCS_PHASE_ASM;
@@ -1137,7 +1139,11 @@ void Run::asm_phase() {
   rhs_momentum(stream, dim, mixed, n2, sp22, col22, semi ? M : E, semi ? 1.0 / prm.dt : 1.0, sg,
                U, sp21, col21, Gc, P, has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask,
                gfull, bU);
-  copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
+  // the momentum solve's start: 2 U*^n - U*^(n-1), or U^n
+  if (extrap_m() && mhist >= 2)
+    extrapolate_with_bc(stream, dim, Us1, Us2, bmask, gfull, Ustar, n2);
+  else
+    copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
   HIP_OK(hipEventRecord(ev[1], stream));
 }
 
@@ -1182,6 +1188,12 @@ void Run::correction_commit() {
   else
     axpy_inplace(stream, n1, 1.0, dP, P);
   HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
+  if (extrap_m()) {   // U*^(n+1) becomes the newest of the two kept
+    HIP_OK(hipMemcpyAsync(Us2, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
+                          stream));
+    std::swap(Us1, Us2);
+    mhist = std::min(mhist + 1, 2);
+  }
   HIP_OK(hipEventRecord(ev[4], stream));
 }
 

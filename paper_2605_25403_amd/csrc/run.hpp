@@ -172,6 +172,10 @@ struct Run {
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
          *gfull = nullptr;
   double *P = nullptr, *dP = nullptr, *rP = nullptr;
+  // the two previous steps' tentative velocities (newest first), kept for the
+  // extrapolated momentum start; mhist of them are valid (0, 1 or 2)
+  double *Us1 = nullptr, *Us2 = nullptr;
+  int mhist = 0;
   double* kv2 = nullptr;      // Krylov work of the velocity systems [dim][8][n2]
   double* kv1 = nullptr;      // Krylov work of the Poisson system [5][n1]
   KState* kst = nullptr;      // [2*dim+1]
@@ -256,6 +260,12 @@ struct Run {
   void pressure_end();
   void clear_pressure_start();
   bool warm_p() const { return prm.poisson_start == IPCS_START_PREVIOUS; }
+  bool extrap_m() const { return prm.momentum_start == IPCS_MSTART_EXTRAPOLATED; }
+  // the next steps start their solves as the first after a new state would
+  void clear_history() {
+    mhist = 0;
+    clear_pressure_start();
+  }
   void correction_rhs();
   void correction_commit();
   void finish_step(ipcs_step_stats* st);

@@ -32,6 +32,7 @@ IPCS_FP64, IPCS_MIXED = 0, 1
 IPCS_CONV_EXPLICIT, IPCS_CONV_SEMI_IMPLICIT = 0, 1
 IPCS_SCHEME_IPCS, IPCS_SCHEME_CHORIN = 0, 1
 IPCS_START_ZERO, IPCS_START_PREVIOUS = 0, 1
+IPCS_MSTART_EXTRAPOLATED, IPCS_MSTART_STATE = 0, 1
 IPCS_SOL_TAYLOR_GREEN_2D, IPCS_SOL_JOHN_2D, IPCS_SOL_BELTRAMI_3D = 1, 2, 3
 IPCS_SOL_POLY_STEADY_2D, IPCS_SOL_POLY_STEADY_3D = 4, 5
 IPCS_SOL_POLY_CUBIC_2D = 6
@@ -70,7 +71,7 @@ class ipcs_params(C.Structure):
                 ("tol_ir", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
                 ("callbacks", C.c_int32), ("poisson_part_rows", C.c_int32),
                 ("scheme", C.c_int32), ("poisson_s", C.c_int32),
-                ("poisson_start", C.c_int32)]
+                ("poisson_start", C.c_int32), ("momentum_start", C.c_int32)]
 
 
 class ipcs_step_stats(C.Structure):
