@@ -286,13 +286,15 @@ typedef struct {
 } ipcs_params;
 
 /* nu=0.01, rho=1, dt=1e-3, t0=0, FP64, explicit, tolerances 1e-12
- * (tol_ir 1e-10), maxit 20000, check_every 16, callbacks 0. */
+ * (tol_ir 1e-10), maxit 20000, check_every 16, callbacks 0, the
+ * extrapolated momentum start and the zero Poisson start. */
 void ipcs_params_default(ipcs_params* p);
 
 /* Device workspace a run of this mesh needs (its whole HBM footprint): the
  * matrices of eq. (9) (M, K, Kp, D_c, G_c, A, the convection matrix of
- * Section 2.2.1), the fields U^n, P^n, U*, dP and the Krylov vectors of the
- * three solves. *bytes receives the size; IPCS_E_INVALID for a bad mesh or
+ * Section 2.2.1), the fields U^n, P^n, U*, dP (with the extrapolated
+ * momentum start, also the two previous steps' U*) and the Krylov vectors of
+ * the three solves. *bytes receives the size; IPCS_E_INVALID for a bad mesh or
  * parameters. The caller allocates it (device memory, 256-byte aligned). */
 int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes);
 /* Sets up one IPCS run (the time loop of Section 2.2.1 on the spaces of
