@@ -236,14 +236,17 @@ enum { IPCS_START_ZERO = 0, IPCS_START_PREVIOUS = 1 };
 /* Start of the momentum solve (eq. (9), first line; Section 2.2.1 fixes the
  * system, not the Krylov start), both judged by the same stopping test
  * ||b - A U*|| <= tol_mom ||b||. IPCS_MSTART_EXTRAPOLATED (default): the
- * linear extrapolation 2 U*^n - U*^(n-1) of the two previous steps' tentative
- * velocities, whose residual is O(dt^2) where U^n's is O(dt) (at 512^2,
- * dt = 1e-3: 2e-8 against 2e-5 of ||b||, 22 BiCGStab iterations against 39);
- * U^n until two steps have completed since ipcs_run_create,
- * ipcs_set_builtin_solution, ipcs_set_state, ipcs_set_viscosity,
- * ipcs_set_time_step or a new forcing or Dirichlet callback (each of which
- * clears that history; a failed step keeps it). A step then depends on the
- * previous tentative velocities as well as on (U^n, P^n): a run resumed
+ * extrapolation of the previous steps' tentative velocities to t^(n+1),
+ * quadratic (3 U*^n - 3 U*^(n-1) + U*^(n-2)) once four steps have completed,
+ * linear (2 U*^n - U*^(n-1)) after two or three, U^n before, counted since
+ * ipcs_run_create, ipcs_set_builtin_solution, ipcs_set_state,
+ * ipcs_set_viscosity, ipcs_set_time_step or a new forcing or Dirichlet
+ * callback (each of which clears the history; a failed step keeps it). The
+ * quadratic start leaves out the first step after a clear, whose tentative
+ * velocity carries the scheme's initial layer. Its residual is O(dt^3) where
+ * U^n's is O(dt) (at 512^2, dt = 1e-3: 4e-10 against 2e-5 of ||b||, 13
+ * BiCGStab iterations against 39; linear: 2e-8, 22). A step then depends
+ * on the previous tentative velocities as well as on (U^n, P^n): a run resumed
  * through ipcs_set_state differs from the uninterrupted one within the
  * tolerance, not bit for bit. IPCS_MSTART_STATE: U^n at every step, a step
  * is a function of (U^n, P^n, t) alone. Dirichlet rows start at their data
@@ -293,7 +296,7 @@ void ipcs_params_default(ipcs_params* p);
 /* Device workspace a run of this mesh needs (its whole HBM footprint): the
  * matrices of eq. (9) (M, K, Kp, D_c, G_c, A, the convection matrix of
  * Section 2.2.1), the fields U^n, P^n, U*, dP (with the extrapolated
- * momentum start, also the two previous steps' U*) and the Krylov vectors of
+ * momentum start, also the three previous steps' U*) and the Krylov vectors of
  * the three solves. *bytes receives the size; IPCS_E_INVALID for a bad mesh or
  * parameters. The caller allocates it (device memory, 256-byte aligned). */
 int ipcs_run_workspace_bytes(ipcs_mesh m, const ipcs_params* p, int64_t* bytes);

@@ -305,9 +305,12 @@ void dirichlet_scatter(hipStream_t s, int dim, const double* gb, const int32_t* 
                        int64_t nb, double* gfull, int64_t n2);
 void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
                   const double* gfull, double* out, int64_t n2);
-// out = 2 A - B on interior rows, the Dirichlet data on boundary rows
-void extrapolate_with_bc(hipStream_t s, int dim, const double* A, const double* B,
-                         const uint8_t* bmask, const double* gfull, double* out, int64_t n2);
+// out = the extrapolation to the next time level of the newest nh (2 or 3)
+// values h0, h1, h2 at equal steps on interior rows, the Dirichlet data on
+// boundary rows
+void extrapolate_with_bc(hipStream_t s, int dim, int nh, const double* h0, const double* h1,
+                         const double* h2, const uint8_t* bmask, const double* gfull,
+                         double* out, int64_t n2);
 // b_c = sa E U_c - sg G_c P + F_c with Dirichlet lifting (explicit: E = M/dt -
 // C(U^n), sa = 1; semi-implicit: E = M, sa = 1/dt; sg = 1 for IPCS, 0 for the
 // Chorin projection, whose momentum step has no pressure term)

@@ -114,23 +114,36 @@ void copy_with_bc(hipStream_t s, int dim, const double* U, const uint8_t* bmask,
   HIP_LAUNCH_OK();
 }
 
-// out = 2 A - B (the linear extrapolation of two consecutive values in time)
-// on interior rows, the Dirichlet data on boundary rows.
-__global__ void k_extrap_bc(int dim, const double* A, const double* B, const uint8_t* bmask,
-                            const double* g, double* out, int64_t n2) {
+// out = the polynomial extrapolation to the next time level of the last NH
+// values at equal steps (NH = 2: 2 h0 - h1; NH = 3: 3 h0 - 3 h1 + h2; h0 the
+// newest) on interior rows, the Dirichlet data on boundary rows.
+template <int NH>
+__global__ void k_extrap_bc(int dim, const double* h0, const double* h1, const double* h2,
+                            const uint8_t* bmask, const double* g, double* out, int64_t n2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n2) return;
   const bool b = bmask[i];
   for (int c = 0; c < dim; ++c) {
     const int64_t k = c * n2 + i;
-    out[k] = b ? g[k] : 2.0 * A[k] - B[k];
+    double v;
+    if constexpr (NH == 2) v = 2.0 * h0[k] - h1[k];
+    else v = 3.0 * (h0[k] - h1[k]) + h2[k];
+    out[k] = b ? g[k] : v;
   }
 }
 
-void extrapolate_with_bc(hipStream_t s, int dim, const double* A, const double* B,
-                         const uint8_t* bmask, const double* gfull, double* out, int64_t n2) {
-  hipLaunchKernelGGL(k_extrap_bc, dim3((unsigned)div_up(n2, 256)), dim3(256), 0, s, dim, A, B,
-                     bmask, gfull, out, n2);
+void extrapolate_with_bc(hipStream_t s, int dim, int nh, const double* h0, const double* h1,
+                         const double* h2, const uint8_t* bmask, const double* gfull,
+                         double* out, int64_t n2) {
+  const dim3 grid((unsigned)div_up(n2, 256));
+  if (nh == 2)
+    hipLaunchKernelGGL(k_extrap_bc<2>, grid, dim3(256), 0, s, dim, h0, h1, h2, bmask, gfull, out,
+                       n2);
+  else if (nh == 3)
+    hipLaunchKernelGGL(k_extrap_bc<3>, grid, dim3(256), 0, s, dim, h0, h1, h2, bmask, gfull, out,
+                       n2);
+  else
+    fail(IPCS_E_INVALID, "extrapolation takes 2 or 3 values");
   HIP_LAUNCH_OK();
 }
 

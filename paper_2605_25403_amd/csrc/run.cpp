@@ -583,8 +583,7 @@ void Run::layout(Carver& c) {
   bU = c.take<double>(dim * n2);
   F = c.take<double>(dim * n2);
   gfull = c.take<double>(dim * n2);
-  Us1 = extrap_m() ? c.take<double>(dim * n2) : nullptr;
-  Us2 = extrap_m() ? c.take<double>(dim * n2) : nullptr;
+  for (auto& h : Ush) h = extrap_m() ? c.take<double>(dim * n2) : nullptr;
   P = c.take<double>(n1);
   dP = c.take<double>(n1);
   rP = c.take<double>(n1);
@@ -1139,9 +1138,13 @@ void Run::asm_phase() {
   rhs_momentum(stream, dim, mixed, n2, sp22, col22, semi ? M : E, semi ? 1.0 / prm.dt : 1.0, sg,
                U, sp21, col21, Gc, P, has_F ? F : nullptr, lift_ptr, lift_col, liftA, bmask,
                gfull, bU);
-  // the momentum solve's start: 2 U*^n - U*^(n-1), or U^n
+  // the momentum solve's start: the extrapolation of the last tentative
+  // velocities, quadratic once its three values leave out the first step of
+  // the history (the scheme's initial layer makes that one rough in time),
+  // linear from two; U^n before
   if (extrap_m() && mhist >= 2)
-    extrapolate_with_bc(stream, dim, Us1, Us2, bmask, gfull, Ustar, n2);
+    extrapolate_with_bc(stream, dim, mhist >= kMhistFull ? 3 : 2, Ush[0], Ush[1], Ush[2], bmask,
+                        gfull, Ustar, n2);
   else
     copy_with_bc(stream, dim, U, bmask, gfull, Ustar, n2);
   HIP_OK(hipEventRecord(ev[1], stream));
@@ -1188,11 +1191,11 @@ void Run::correction_commit() {
   else
     axpy_inplace(stream, n1, 1.0, dP, P);
   HIP_OK(hipMemcpyAsync(U, Unew, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice, stream));
-  if (extrap_m()) {   // U*^(n+1) becomes the newest of the two kept
-    HIP_OK(hipMemcpyAsync(Us2, Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
+  if (extrap_m()) {   // U*^(n+1) becomes the newest of the three kept
+    HIP_OK(hipMemcpyAsync(Ush[2], Ustar, sizeof(double) * dim * n2, hipMemcpyDeviceToDevice,
                           stream));
-    std::swap(Us1, Us2);
-    mhist = std::min(mhist + 1, 2);
+    std::rotate(Ush, Ush + 2, Ush + 3);
+    mhist = std::min(mhist + 1, kMhistFull);
   }
   HIP_OK(hipEventRecord(ev[4], stream));
 }

@@ -172,9 +172,11 @@ struct Run {
   double *U = nullptr, *Unew = nullptr, *Ustar = nullptr, *bU = nullptr, *F = nullptr,
          *gfull = nullptr;
   double *P = nullptr, *dP = nullptr, *rP = nullptr;
-  // the two previous steps' tentative velocities (newest first), kept for the
-  // extrapolated momentum start; mhist of them are valid (0, 1 or 2)
-  double *Us1 = nullptr, *Us2 = nullptr;
+  // the three previous steps' tentative velocities (newest first), kept for
+  // the extrapolated momentum start; mhist counts the steps completed since
+  // the history was last cleared (kept up to kMhistFull)
+  static constexpr int kMhistFull = 4;
+  double* Ush[3] = {};
   int mhist = 0;
   double* kv2 = nullptr;      // Krylov work of the velocity systems [dim][8][n2]
   double* kv1 = nullptr;      // Krylov work of the Poisson system [5][n1]

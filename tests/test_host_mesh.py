@@ -146,12 +146,12 @@ def test_invalid_arguments_are_reported():
         m.h, I.ipcs_params_default())
     with pytest.raises(I.IpcsError):
         I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default(momentum_start=2))
-    # the extrapolated momentum start keeps two tentative velocities (dim x N2 doubles each)
+    # the extrapolated momentum start keeps three tentative velocities (dim x N2 doubles each)
     c = I.ipcs_mesh_counts(m.h)
     pure = I.ipcs_params_default(momentum_start=I.IPCS_MSTART_STATE)
     extra = I.ipcs_run_workspace_bytes(m.h, I.ipcs_params_default()) - \
         I.ipcs_run_workspace_bytes(m.h, pure)
-    assert 2 * 8 * c.dim * c.n2 <= extra <= 2 * 8 * c.dim * c.n2 + 2 * 256
+    assert 3 * 8 * c.dim * c.n2 <= extra <= 3 * 8 * c.dim * c.n2 + 3 * 256
     semi = I.ipcs_params_default(convection=I.IPCS_CONV_SEMI_IMPLICIT)
     assert I.ipcs_run_workspace_bytes(m.h, semi) == I.ipcs_run_workspace_bytes(
         m.h, I.ipcs_params_default())
