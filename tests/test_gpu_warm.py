@@ -96,17 +96,19 @@ def test_warm_start_multipart_against_zero_start():
 
 
 def test_warm_start_batch_and_reset():
-    """Warm runs in a batch (FP64 and mixed, two sizes) equal the same runs
-    alone bitwise over three steps; a state set anew starts the next solve
-    from zero again (that step is bitwise the zero start's from the same
-    state)."""
+    """Runs with both history starts (the previous dP for the pressure, the
+    linear and then quadratic extrapolation for the momentum) in a batch
+    (FP64 and mixed, two sizes) equal the same runs alone bitwise over six
+    steps; a state set anew starts the next solves from zero and U^n again
+    (that step is bitwise the plain starts' from the same state)."""
     torch, I = require_gpu()
     print("warm start batch and reset", flush=True)
     cases = [(12, I.IPCS_FP64), (16, I.IPCS_FP64), (16, I.IPCS_MIXED)]
 
     def mk(n, prec, start, stream=None):
+        ms = I.IPCS_MSTART_STATE if start == I.IPCS_START_ZERO else I.IPCS_MSTART_EXTRAPOLATED
         p = I.ipcs_params_default(nu=0.01, dt=0.005, precision=prec, tol_ir=1e-10,
-                                  poisson_start=start)
+                                  poisson_start=start, momentum_start=ms)
         r = I.Run(I.Mesh.unit_square(n), p, stream=stream)
         r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (np.pi,))
         return r
@@ -114,11 +116,11 @@ def test_warm_start_batch_and_reset():
     alone = []
     for c in cases:
         r = mk(*c, I.IPCS_START_PREVIOUS)
-        r.advance(3)
+        r.advance(6)
         alone.append((r.velocity(), r.pressure()))
     s = torch.cuda.Stream()
     runs = [mk(*c, I.IPCS_START_PREVIOUS, stream=s) for c in cases]
-    for _ in range(3):
+    for _ in range(6):
         rc, st = I.ipcs_batch_step([r.h for r in runs], s.cuda_stream)
         assert rc == I.IPCS_OK, st
     for (U, P), r in zip(alone, runs):
