@@ -655,8 +655,9 @@ def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
     """C5: Poisson-arrival stream of 2D TG requests (n in {32,64,128,256},
     seed-drawn k and nu, 50 steps at dt = 1e-3), mixed form, continuous
     batching in one lane per mesh size (each with its own stream), the same
-    lanes with 16 CUs reserved for each of the two small sizes, and the same
-    stream in a single lane for comparison. Beside them, the first
+    lanes with 16 CUs reserved for each of the two small sizes, the same
+    lanes serving the plain FP64 form, and the same stream in a single lane
+    for comparison. Beside them, the first
     seq_sample requests run one after the other, each alone, in the mixed form
     (the served form's alone latency per mesh size) and in the plain FP64
     form at tolerance 1e-12 (the baseline): per-step latency p50/p99 and
@@ -676,6 +677,10 @@ def serving_form(torch, I, count=256, rate=20.0, max_slots=64, seq_sample=16,
     # the large lanes on the other CUs
     rsv, _ = Server(max_slots=max_slots, lanes=lanes, lane_cus=(16, 16, None, None)).serve(reqs)
     report["reserved_cus"] = dict({k: rsv[k] for k in keys}, lane_cus=rsv["lane_cus"])
+    # the same lanes serving the plain FP64 form (each result bitwise the run
+    # alone in FP64, so at the baseline's accuracy)
+    f64s, _ = Server(max_slots=max_slots, lanes=lanes, precision=I.IPCS_FP64).serve(reqs)
+    report["fp64_served"] = {k: f64s[k] for k in keys}
 
     def alone(prec):
         base = Server(precision=prec)
