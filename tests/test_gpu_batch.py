@@ -58,19 +58,21 @@ def test_batch_mixes_forms_and_matches_oracle():
         assert max(errs) <= 1e-10, (step, errs)
 
 
-def test_serving_loop_small_stream_equals_alone():
+@pytest.mark.parametrize("fp64", [False, True])
+def test_serving_loop_small_stream_equals_alone(fp64):
     torch, I = require_gpu()
-    print("serving loop", flush=True)
+    print(f"serving loop fp64={fp64}", flush=True)
     from paper_2605_25403_amd.serve import Request, Server
-    reqs = [Request(id=i, t_arrive=0.002 * i, n=n, k=k, nu=nu, steps=3 + (i % 3), dt=dt)
+    prec = I.IPCS_FP64 if fp64 else I.IPCS_MIXED
+    reqs = [Request(id=i, t_arrive=0.002 * i, n=n, k=k, nu=nu, steps=3 + (i % 4), dt=dt)
             for i, (n, k, nu, dt) in enumerate(CASES * 2)]
-    srv = Server(max_slots=3, hbm_budget=1 << 34)
+    srv = Server(max_slots=3, hbm_budget=1 << 34, precision=prec)
     report, res = srv.serve(reqs, keep_fields=True)
     print(report, flush=True)
     assert report["failed"] == 0 and len(res) == len(reqs)
     assert report["max_active"] <= 3
     for q in reqs:
-        r = new_run(I, q.n, q.k, q.nu, q.dt, I.IPCS_MIXED)
+        r = new_run(I, q.n, q.k, q.nu, q.dt, prec)
         r.advance(q.steps)
         np.testing.assert_array_equal(res[q.id]["U"], r.velocity())
         np.testing.assert_array_equal(res[q.id]["P"], r.pressure())
