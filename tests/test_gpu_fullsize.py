@@ -17,13 +17,16 @@ output at these sizes, so the checks are:
   by up to kappa * tol (kappa(Kp) ~ 1e5 at n = 512), but the measured
   differences are far smaller, and the field bars are set at five times them;
 * the mixed form of the 512^2 workload over three steps against the FP64
-  oracle (its stated bound, 1e-5 per field per step).
+  oracle (its stated bound, 1e-5 per field per step);
+* a step of the 512^2 workload with the momentum solve started from the
+  quadratic extrapolation, as in the timed steps: its three solve outputs
+  in the oracle's systems built from the library's state.
 """
 import numpy as np
 import pytest
 
 from oracle import fem, mesh
-from tests.gpu_common import make_pair, rel, require_gpu, step_residuals
+from tests.gpu_common import make_pair, rel, require_gpu, residual, step_residuals
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -185,6 +188,49 @@ def test_full_size_2d_mixed_prefix_against_fp64_oracle(c2_pair):
             assert max(errs[:2]) <= MIXED_U and errs[2] <= MIXED_P, (step, errs)
     finally:
         o.prm.tol_mom = o.prm.tol_p = o.prm.tol_corr = 1e-13
+
+
+def test_full_size_2d_extrapolated_start_step_residuals(c2_pair):
+    """The 512^2 workload as bench.py times it: tolerance 1e-12 and the
+    default momentum start, whose fifth step starts BiCGStab from the
+    quadratic extrapolation of the previous tentative velocities. That step,
+    phase by phase: each of the three solve outputs put into the oracle's own
+    system built from the library's state (relative residual <= 2e-12, the
+    tolerance plus the rounding of evaluating b - A x), and the momentum solve
+    shorter than from U^n (39 iterations)."""
+    torch, I = require_gpu()
+    print("full-size 2D step with the extrapolated momentum start", flush=True)
+    w, S, o, _, (U0, P0, t0) = c2_pair
+    try:
+        m = I.Mesh.unit_square(512)
+        p = I.ipcs_params_default(nu=w["nu"], dt=w["dt"], tol_mom=w["tol"], tol_p=w["tol"],
+                                  tol_corr=w["tol"])
+        r = I.Run(m, p)
+        r.set_builtin(I.IPCS_SOL_TAYLOR_GREEN_2D, (w["k"],))
+        r.advance(4)
+        o.set_state(r.velocity(), r.pressure(), r.time())
+        t1 = o.t + w["dt"]
+        g = o.dirichlet(t1)
+        A_el, bs, _, _, _ = o.momentum_system(t1, g)
+        r.phase(I.IPCS_PHASE_ASM)
+        st = r.phase(I.IPCS_PHASE_MOMENTUM)
+        Us = r.field(I.IPCS_FIELD_USTAR)
+        res = {f"momentum{c}": residual(A_el, Us[c], bs[c]) for c in range(2)}
+        r.phase(I.IPCS_PHASE_PRESSURE)
+        dP, rp = r.field(I.IPCS_FIELD_DP), r.field(I.IPCS_FIELD_RHS_P)
+        res["pressure"] = residual(o.Kp, dP, rp)
+        r.phase(I.IPCS_PHASE_CORRECTION)
+        U = r.velocity()
+        M_el, bc = o.correction_system(Us, dP, g)
+        for c in range(2):
+            res[f"correction{c}"] = residual(M_el, U[c], bc[c])
+        print("BiCGStab iterations", st["it_mom"][:2], "residuals",
+              {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
+        for k, v in res.items():
+            assert v <= 2 * RES_TOL, (k, v)
+        assert max(st["it_mom"][:2]) < 39, st["it_mom"]
+    finally:
+        o.set_state(U0, P0, t0)
 
 
 @pytest.mark.parametrize("dim,n,bar_u,bar_p", [(2, 512, 5.5e-6, 3e-3), (3, 64, 2e-6, 4e-4)])
