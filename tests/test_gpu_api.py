@@ -116,6 +116,27 @@ def test_runs_are_deterministic_and_resumable(mstart):
         assert eu <= 1e-10 and ep <= 1e-10, (eu, ep)
 
 
+def test_set_time_step_matches_a_fresh_run():
+    """A new time step re-forms A = M/dt + nu K and clears the solve-start
+    history (an extrapolation needs equal steps): after five steps at
+    dt = 0.003 (the quadratic momentum start in use) and a change to 0.002,
+    the run is bitwise a fresh run at 0.002 started from the same state,
+    with both history starts on."""
+    torch, I = require_gpu()
+    print("set_time_step", flush=True)
+    kw = dict(n=16, k=2 * np.pi, nu=0.004, poisson_start=I.IPCS_START_PREVIOUS)
+    a = tg_run(I, dt=0.003, **kw)
+    a.advance(5)
+    I.ipcs_set_time_step(a.h, 0.002)
+    b = tg_run(I, dt=0.002, **kw)
+    b.set_state(a.velocity(), a.pressure(), a.time())
+    sa, sb = a.advance(4), b.advance(4)
+    np.testing.assert_array_equal(a.velocity(), b.velocity())
+    np.testing.assert_array_equal(a.pressure(), b.pressure())
+    assert [s["it_mom"] for s in sa] == [s["it_mom"] for s in sb]
+    assert a.time() == b.time()
+
+
 def test_set_viscosity_matches_a_fresh_run():
     torch, I = require_gpu()
     print("set_viscosity", flush=True)
