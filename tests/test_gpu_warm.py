@@ -140,7 +140,7 @@ def test_warm_start_batch_and_reset():
 @pytest.mark.parametrize("dim,n,kind,form", [
     (2, 16, "tg", "explicit"), (2, 12, "tg", "semi"), (2, 12, "tg", "chorin"),
     (2, 8, "tg", "p3"), (2, 16, "tg", "mixed"), (2, 9, "john", "explicit"),
-    (3, 3, "beltrami", "explicit")])
+    (3, 3, "beltrami", "explicit"), (3, 3, "beltrami", "semi"), (3, 2, "beltrami", "p3")])
 def test_extrapolated_momentum_start(dim, n, kind, form):
     """The default momentum start against the oracle over nine steps (linear
     extrapolation at the third and fourth, quadratic from the fifth): U* from
