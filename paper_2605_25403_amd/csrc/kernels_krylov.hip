@@ -437,6 +437,12 @@ __global__ void __launch_bounds__(KBS) k_bicg_spmv(const KGroup* groups, const i
     run[j] = G(g.v[j].st)->status == KS_RUN;
     any |= run[j];
   }
+  // b4 follows the s-update of the same iteration, which has already ended
+  // the systems whose residual met the tolerance: when none is left the
+  // block skips its loads (the iteration launched past convergence would
+  // otherwise read the whole matrix); b2 issues its loads first, as the
+  // systems' status is decided after it
+  if (WHICH == 1 && !any) return;
   double y[EPT][NS], rh[EPT][NS], si[EPT][NS];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -569,13 +575,16 @@ __global__ void __launch_bounds__(KBS) k_bicg_5(const KGroup* groups, const int2
   __shared__ double sh[(KBS / 64) * NS * 4];
   int status[NS];
   double rho[NS], alpha[NS];
+  bool live = false;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     const gptr<const KState> st = G((const KState*)g.v[j].st);
     status[j] = st->status;
     rho[j] = st->sc[par];
     alpha[j] = st->alpha[0];
+    live |= status[j] == KS_RUN;
   }
+  if (!live) return;   // as in b4: nothing to update, skip the loads
   double di[EV], xi[EV][NS], si[EV][NS], ti[EV][NS], pi[EV][NS], vi[EV][NS];
 #pragma unroll
   for (int e = 0; e < EV; ++e) {
